@@ -1,0 +1,320 @@
+"""Seeded synthetic inputs for the GRFFE DG-FD hot path.
+
+This module is shared by the CPU oracle tests, the GPU parity tests, the
+smoke entry point and the benchmark.  It only *samples* analytic data:
+element boxes, point coordinates, initial fields, Gaussian noise and the
+Kerr-Schild background metric with its first derivatives.  It contains none
+of the scheme's arithmetic (no collocation points, no derivative or
+interpolation operators, no fluxes, no time stepping).  Callers that need
+values at DG collocation points pass in their own 1D reference points.
+
+Array conventions
+-----------------
+* Elements are numbered e = ex + nx*(ey + ny*ez).
+* Point arrays have shape (E, n, n, n) with axes (z, y, x): the x (xi^1)
+  index runs fastest in memory, matching the library's node ordering.
+* Field arrays have a leading component axis: (ncomp, E, n, n, n).
+
+Physical content
+----------------
+* Evolved variables U = sqrt(gamma) (E^i, B^i, psi, phi, q) (Sec. II A, the
+  conservative-form variables).
+* The Kerr-Schild line element in Cartesian form (Appendix B): g = eta +
+  2 H l l with H = M r^3 / (r^4 + a^2 z^2) and the quartic relation for r.
+* Background field order (26 fields): alpha; beta^x, beta^y, beta^z;
+  gamma_xx, gamma_xy, gamma_xz, gamma_yy, gamma_yz, gamma_zz; d_x alpha,
+  d_y alpha, d_z alpha; d_j beta^i for j = x,y,z (outer) and i = x,y,z
+  (inner); K (trace of the extrinsic curvature, sign convention
+  d_t gamma_ij = -2 alpha K_ij + L_beta gamma_ij); Gamma^i = gamma^jk
+  Gamma^i_jk for i = x,y,z.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_BG = 26
+
+# ----------------------------------------------------------------------------
+# element geometry and point sets
+
+
+def element_boxes(n_elem, lower, upper):
+    """Lower corners (E,3) and widths (3,) of an affine Cartesian element grid."""
+    n_elem = np.asarray(n_elem, dtype=np.int64)
+    lower = np.asarray(lower, dtype=np.float64)
+    upper = np.asarray(upper, dtype=np.float64)
+    h = (upper - lower) / n_elem
+    E = int(np.prod(n_elem))
+    e = np.arange(E)
+    ex = e % n_elem[0]
+    ey = (e // n_elem[0]) % n_elem[1]
+    ez = e // (n_elem[0] * n_elem[1])
+    corner = np.stack([lower[0] + ex * h[0], lower[1] + ey * h[1], lower[2] + ez * h[2]], axis=1)
+    return corner, h
+
+
+def points(n_elem, lower, upper, ref_1d):
+    """Physical coordinates of a tensor-product point set in every element.
+
+    ``ref_1d`` holds reference coordinates in [-1, 1] (used for all three
+    axes).  Returns x, y, z each of shape (E, n, n, n) with axes (z, y, x).
+    """
+    ref_1d = np.asarray(ref_1d, dtype=np.float64)
+    corner, h = element_boxes(n_elem, lower, upper)
+    t = 0.5 * (ref_1d + 1.0)
+    n = ref_1d.size
+    E = corner.shape[0]
+    x = corner[:, 0, None, None, None] + h[0] * t[None, None, None, :]
+    y = corner[:, 1, None, None, None] + h[1] * t[None, None, :, None]
+    z = corner[:, 2, None, None, None] + h[2] * t[None, :, None, None]
+    shape = (E, n, n, n)
+    return np.broadcast_to(x, shape).copy(), np.broadcast_to(y, shape).copy(), np.broadcast_to(z, shape).copy()
+
+
+def fd_cell_centres_1d(degree):
+    """Reference centres of the 2N+1 uniform subcells of [-1, 1]."""
+    m = 2 * degree + 1
+    return -1.0 + (2.0 * np.arange(m) + 1.0) / m
+
+
+def fd_points(n_elem, lower, upper, degree):
+    return points(n_elem, lower, upper, fd_cell_centres_1d(degree))
+
+
+# ----------------------------------------------------------------------------
+# Kerr-Schild background (Appendix B, Cartesian Kerr-Schild line element)
+
+
+def _ks_radius(x, y, z, a):
+    rho2 = x * x + y * y + z * z
+    t = rho2 - a * a
+    r2 = 0.5 * (t + np.sqrt(t * t + 4.0 * a * a * z * z))
+    return np.sqrt(r2)
+
+
+def ks_radius(x, y, z, a):
+    """Kerr-Schild radial coordinate r(x, y, z) from the quartic relation."""
+    return _ks_radius(np.asarray(x, np.float64), np.asarray(y, np.float64), np.asarray(z, np.float64), a)
+
+
+def _ks_3p1(x, y, z, M, a):
+    """alpha, beta^i (3), gamma_ij (3,3), gamma^ij (3,3), sqrt(gamma) (complex-safe)."""
+    r = _ks_radius(x, y, z, a)
+    H = M * r ** 3 / (r ** 4 + a * a * z * z)
+    ra = r * r + a * a
+    l = [(r * x + a * y) / ra, (r * y - a * x) / ra, z / r]  # spatial part of the null covector, l_t = 1
+    ll = sum(li * li for li in l)  # equals 1 for the Kerr-Schild null vector
+    g = [[(1.0 if i == j else 0.0) + 2.0 * H * l[i] * l[j] for j in range(3)] for i in range(3)]
+    ginv = [[(1.0 if i == j else 0.0) - 2.0 * H * l[i] * l[j] / (1.0 + 2.0 * H * ll) for j in range(3)]
+            for i in range(3)]
+    beta_lo = [2.0 * H * l[i] for i in range(3)]
+    beta = [sum(ginv[i][j] * beta_lo[j] for j in range(3)) for i in range(3)]
+    g00 = -1.0 + 2.0 * H
+    alpha = np.sqrt(sum(beta_lo[i] * beta[i] for i in range(3)) - g00)
+    sqrtg = np.sqrt(1.0 + 2.0 * H * ll)
+    return alpha, beta, g, ginv, sqrtg
+
+
+def _cstep(fun, x, y, z, h=1e-30):
+    """Complex-step partial derivatives of ``fun`` (which returns a list of arrays)."""
+    out = []
+    for d in range(3):
+        xs = [x.astype(np.complex128), y.astype(np.complex128), z.astype(np.complex128)]
+        xs[d] = xs[d] + 1j * h
+        vals = fun(*xs)
+        out.append([np.imag(v) / h for v in vals])
+    return out  # out[d][k] = d_d of value k
+
+
+def kerr_schild_background(x, y, z, M=1.0, a=0.0):
+    """The 26 background fields at the given points (see module docstring)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    z = np.asarray(z, np.float64)
+    alpha, beta, g, ginv, sqrtg = _ks_3p1(x, y, z, M, a)
+
+    def flat_vals(x_, y_, z_):
+        al, be, gg, _, sg = _ks_3p1(x_, y_, z_, M, a)
+        vals = [al] + list(be) + [gg[i][j] for i in range(3) for j in range(3)] + [sg * be[i] for i in range(3)]
+        return vals
+
+    der = _cstep(flat_vals, x, y, z)
+    # unpack: index 0 alpha, 1..3 beta, 4..12 gamma_ij (row-major), 13..15 sqrtg*beta^i
+    dalpha = [der[d][0] for d in range(3)]
+    dbeta = [[der[j][1 + i] for i in range(3)] for j in range(3)]  # [j][i] = d_j beta^i
+    dg = [[[der[k][4 + 3 * i + j] for j in range(3)] for i in range(3)] for k in range(3)]  # dg[k][i][j]
+    div_sgb = sum(der[i][13 + i] for i in range(3))
+    K = div_sgb / (sqrtg * alpha)  # K = D_i beta^i / alpha for a stationary slice
+    # Gamma^i = gamma^jk Gamma^i_jk, Gamma^i_jk = 1/2 gamma^il (d_j g_lk + d_k g_lj - d_l g_jk)
+    Gam = []
+    for i in range(3):
+        acc = 0.0
+        for j in range(3):
+            for k in range(3):
+                for l_ in range(3):
+                    acc = acc + 0.5 * ginv[j][k] * ginv[i][l_] * (dg[j][l_][k] + dg[k][l_][j] - dg[l_][j][k])
+        Gam.append(acc)
+    fields = [alpha, beta[0], beta[1], beta[2],
+              g[0][0], g[0][1], g[0][2], g[1][1], g[1][2], g[2][2],
+              dalpha[0], dalpha[1], dalpha[2]]
+    for j in range(3):
+        for i in range(3):
+            fields.append(dbeta[j][i])
+    fields.append(K)
+    fields.extend(Gam)
+    out = np.stack([np.broadcast_to(np.real(f), x.shape) for f in fields], axis=0).astype(np.float64)
+    return out
+
+
+def flat_background(shape):
+    """The 26 background fields of flat space in Cartesian coordinates."""
+    bg = np.zeros((N_BG,) + tuple(shape))
+    bg[0] = 1.0
+    bg[4] = bg[7] = bg[9] = 1.0
+    return bg
+
+
+# ----------------------------------------------------------------------------
+# initial data (all returned as densitized evolved variables, shape (9, ...))
+
+
+def noise(seed, shape, sigma=1e-3):
+    """Seeded N(0, sigma^2) samples (PCG64)."""
+    rng = np.random.default_rng(seed)
+    return sigma * rng.standard_normal(shape)
+
+
+def fast_wave_sine(x, amplitude=0.1, k=np.pi):
+    """Flat-space fast wave moving in +x: B = (1, -A sin kx, 0), E = (0, 0, A sin kx)."""
+    U = np.zeros((9,) + x.shape)
+    s = amplitude * np.sin(k * x)
+    U[3] = 1.0
+    U[4] = -s
+    U[2] = s
+    return U
+
+
+def current_sheet(x, width=0.05, half_length=1.0):
+    """Flat-space current sheet across x = 0: B = (1, tanh(x/w) - x tanh(L/w)/L, 0), E = 0.
+
+    The linear term makes B_y (and its first derivative) continuous across
+    the periodic wrap at x = +-L, so the box holds a single sheet.
+    """
+    U = np.zeros((9,) + x.shape)
+    U[3] = 1.0
+    U[4] = np.tanh(x / width) - x * np.tanh(half_length / width) / half_length
+    return U
+
+
+def add_noise_by_and_ez(U, seed, sigma=1e-3):
+    """Independent noise on B_y and E_z at every point (drawn B_y first, then E_z)."""
+    U = U.copy()
+    nz = noise(seed, (2,) + U.shape[1:], sigma)
+    U[4] += nz[0]
+    U[2] += nz[1]
+    return U
+
+
+def wald_a0(x, y, z, M=1.0, B0=1.0):
+    """Exact Wald field for a = 0 in Kerr-Schild coordinates (densitized; Sec. IV B)."""
+    r2 = x * x + y * y + z * z
+    U = np.zeros((9,) + np.shape(x))
+    U[5] = B0
+    U[0] = -2.0 * M * B0 * y / r2
+    U[1] = 2.0 * M * B0 * x / r2
+    return U
+
+
+def _ideal_e_tilde(x, y, z, M, a, Bt):
+    """E~^i from E_i = -[ijk] v^j B~^k with v = beta/alpha (plasma at rest in KS coordinates)."""
+    alpha, beta, g, ginv, sqrtg = _ks_3p1(x, y, z, M, a)
+    v = [beta[i] / alpha for i in range(3)]
+    E_lo = [-(v[1] * Bt[2] - v[2] * Bt[1]), -(v[2] * Bt[0] - v[0] * Bt[2]), -(v[0] * Bt[1] - v[1] * Bt[0])]
+    return [sqrtg * sum(ginv[i][j] * E_lo[j] for j in range(3)) for i in range(3)]
+
+
+def kerr_schild_uniform_field(x, y, z, M=1.0, a=0.0, B0=1.0):
+    """Wald-like data: B~ = (0, 0, B0), E~ from the ideal condition, q~ = d_i E~^i."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    z = np.asarray(z, np.float64)
+    Bt = [0.0 * x, 0.0 * x, B0 + 0.0 * x]
+
+    def et(x_, y_, z_):
+        return _ideal_e_tilde(x_, y_, z_, M, a, [0.0, 0.0, B0])
+
+    Et = et(x, y, z)
+    der = _cstep(et, x, y, z)
+    q = der[0][0] + der[1][1] + der[2][2]
+    U = np.zeros((9,) + x.shape)
+    for i in range(3):
+        U[i] = np.real(Et[i])
+        U[3 + i] = Bt[i]
+    U[8] = q
+    return U
+
+
+# ----------------------------------------------------------------------------
+# named workloads (shapes of the paper's flat-space wave tests and
+# black-hole magnetospheres)
+
+BC_PERIODIC = 0
+BC_NO_INCOMING_POYNTING = 1
+
+
+def workload(name, **over):
+    """Grid and parameter description of a named synthetic workload."""
+    if name == "wave":  # 2^3 elements, periodic [-1,1]^3, smooth sine + noise
+        w = dict(n_elem=(2, 2, 2), lower=(-1.0, -1.0, -1.0), upper=(1.0, 1.0, 1.0), degree=5,
+                 bc=(BC_PERIODIC,) * 6, eta=1e6, cfl=0.25, steps=10, seed=1001, curved=False,
+                 amplitude=0.1, kind="wave")
+    elif name == "sheet":  # 8^3 elements, tanh current sheet, mixed DG/FD
+        w = dict(n_elem=(8, 8, 8), lower=(-1.0, -1.0, -1.0), upper=(1.0, 1.0, 1.0), degree=5,
+                 bc=(BC_PERIODIC,) * 6, eta=1e6, cfl=0.25, steps=200, seed=1002, curved=False,
+                 width=0.05, kind="sheet")
+    elif name == "kerr_schild":  # black hole a=0.9, 16^3 elements on [-40,40]^3
+        w = dict(n_elem=(16, 16, 16), lower=(-40.0,) * 3, upper=(40.0,) * 3, degree=5,
+                 bc=(BC_NO_INCOMING_POYNTING,) * 6, eta=1e5, cfl=0.25, steps=1000, seed=1003,
+                 curved=True, M=1.0, spin=0.9, B0=1.0, r_excise=1.8, kind="kerr_schild")
+    else:
+        raise ValueError(f"unknown workload {name!r}")
+    w.update(over)
+    return w
+
+
+def excision_mask(w):
+    """Elements whose box intersects the Euclidean ball of radius r_excise (uint8, E)."""
+    E = int(np.prod(w["n_elem"]))
+    if not w.get("curved") or not w.get("r_excise"):
+        return np.zeros(E, np.uint8)
+    corner, h = element_boxes(w["n_elem"], w["lower"], w["upper"])
+    lo = corner
+    hi = corner + h[None, :]
+    closest = np.clip(0.0, lo, hi)
+    d = np.sqrt((closest ** 2).sum(axis=1))
+    return (d < w["r_excise"]).astype(np.uint8)
+
+
+def initial_data(w, x, y, z, with_noise=True):
+    """Densitized initial U (9, ...) of workload ``w`` at the given points."""
+    kind = w["kind"]
+    if kind == "wave":
+        U = fast_wave_sine(x, w.get("amplitude", 0.1))
+    elif kind == "sheet":
+        U = current_sheet(x, w.get("width", 0.05), 0.5 * (w["upper"][0] - w["lower"][0]))
+    elif kind == "kerr_schild":
+        U = kerr_schild_uniform_field(x, y, z, w.get("M", 1.0), w.get("spin", 0.0), w.get("B0", 1.0))
+    elif kind == "wald_a0":
+        U = wald_a0(x, y, z, w.get("M", 1.0), w.get("B0", 1.0))
+    else:
+        raise ValueError(kind)
+    if with_noise and kind in ("wave", "sheet"):
+        U = add_noise_by_and_ez(U, w["seed"], w.get("noise", 1e-3))
+    return U
+
+
+def background(w, x, y, z):
+    """Background fields (26, ...) of workload ``w`` at given points (None when flat)."""
+    if not w.get("curved"):
+        return None
+    return kerr_schild_background(x, y, z, w.get("M", 1.0), w.get("spin", 0.0))
