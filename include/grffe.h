@@ -1,0 +1,174 @@
+/* C ABI of the GRFFE DG-FD hot path on MI355X (gfx950).
+ *
+ * Method: Kim, Most, Throwe, Teukolsky, Deppe, "General relativistic
+ * force-free electrodynamics with a discontinuous Galerkin-finite difference
+ * hybrid method" (arXiv:2404.01531).  The library evaluates the semi-discrete
+ * right-hand side of the augmented GRFFE system (Sec. II, Eqs. (evolved
+ * variables), (fluxes), (sources), (electric current density)) on a grid of
+ * affine Cartesian elements, each held either as a nodal DG-P_N element on
+ * Legendre-Gauss-Lobatto points (Sec. III A) or as (2N+1)^3 finite-difference
+ * subcells (Sec. III C 2), and advances it with the IMEX-SSP3(4,3,3) step and
+ * the troubled-cell-indicator driven DG<->FD switching (Sec. III B, III C 1,
+ * III C 3).
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ *  - Evolved variables are the densitized U = sqrt(gamma) (E^i, B^i, psi, phi, q),
+ *    component order (Ex, Ey, Ez, Bx, By, Bz, psi, phi, q).
+ *  - Elements are numbered e = ex + nx*(ey + ny*ez).  Within an element the DG
+ *    node (i, j, k) is stored at i + n*(j + n*k), n = N+1 (xi^1 fastest); the FD
+ *    cell (i, j, k) at i + m*(j + m*k), m = 2N+1.
+ *  - DG arrays are [9][E][n^3] FP64, FD arrays [9][E][m^3] FP64, structure of
+ *    arrays (component-major), all in device memory.  rep arrays are int32 [E]
+ *    with 0 = DG, 1 = FD (excised elements are ignored and read as DG).
+ *  - Every pointer argument marked "device" must point to device memory of the
+ *    current HIP device; work is enqueued on `stream` (a hipStream_t, may be
+ *    NULL for the default stream).  The library never retains or frees caller
+ *    pointers.  Host pointers are only read during the call.
+ *  - Return value: GRFFE_OK (0) or a negative status; the message of the last
+ *    failure on the calling thread is returned by grffe_last_error().  No
+ *    implicit device synchronisation happens except where a host value is
+ *    returned (grffe_get_dt, grffe_get_counts).
+ *  - A domain is not thread-safe; separate domains are independent.
+ */
+#ifndef GRFFE_H
+#define GRFFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRFFE_OK 0
+#define GRFFE_EINVAL (-1)      /* bad shape, degree, parameter or pointer */
+#define GRFFE_ENOMEM (-2)      /* device allocation failed */
+#define GRFFE_EHIP (-3)        /* HIP runtime error */
+#define GRFFE_EUNSUPPORTED (-5)
+
+#define GRFFE_BC_PERIODIC 0
+#define GRFFE_BC_NO_INCOMING_POYNTING 1 /* Sec. III D */
+
+#define GRFFE_PART_EXPLICIT 1 /* fluxes + non-stiff sources */
+#define GRFFE_PART_STIFF 2    /* driver current + kappa damping (treated implicitly) */
+#define GRFFE_PART_ALL 3
+
+#define GRFFE_HYBRID_DG_ONLY 0  /* no indicator, every element stays DG */
+#define GRFFE_HYBRID_ADAPTIVE 1 /* Sec. III C 1: indicator decides */
+#define GRFFE_HYBRID_FORCED 2   /* representation fixed by a mask (Sec. IV D 2 style) */
+
+/* Element grid (Sec. III A): an axis-aligned box [lower, upper] cut into
+ * n_elem[0] x n_elem[1] x n_elem[2] equal elements of degree N (3 <= N <= 7).
+ * bc[2d + s] is the boundary kind of the lower (s = 0) / upper (s = 1) face
+ * along direction d; periodic faces must come in pairs.  excised (host, E
+ * bytes, nullable) removes elements: their faces towards live elements take the
+ * no-incoming-Poynting state with the normal pointing into the hole. */
+typedef struct grffe_grid {
+  int32_t n_elem[3];
+  double lower[3];
+  double upper[3];
+  int32_t degree;
+  int32_t bc[6];
+  const uint8_t* excised;
+} grffe_grid;
+
+/* Scheme parameters.  Zero-initialise and call grffe_default_params() first. */
+typedef struct grffe_params {
+  double eta;           /* driver relaxation rate, Eq. (electric current density) */
+  double kappa_psi;     /* divergence-cleaning damping rates */
+  double kappa_phi;
+  double cfl;           /* CFL factor f of Eq. (spectre DG CFL condition) */
+  double stab_c;        /* stepper constant c; 0 selects SSP-RK3's 1.2563726633 */
+  int32_t tci_M;        /* modes removed by the indicator; 0 selects max(2, min(3, (N+1)/2)) */
+  int32_t tci_mode;     /* 2: u - low-pass(u) (default); 1: only modes with all indices >= M */
+  double tci_alpha;     /* exponent on DG (4) */
+  double tci_alpha_fd;  /* exponent on FD (5) */
+  double filter_a;      /* exponential filter, Eq. (exponential filter): a = 36, b = 50 */
+  double filter_b;
+  int32_t filter_on;
+  int32_t fd_order;     /* 4: with the fourth-order flux corrector, 2: Rusanov flux only */
+  double weno_eps;      /* WENO5-Z epsilon (1e-40) */
+  int32_t ff_clamp;     /* 1: algebraic E.B = 0, E < B fix after every substep */
+  double ff_margin;     /* E^2 <= (1 - margin) B^2 in the clamp */
+  int32_t hybrid;       /* GRFFE_HYBRID_* */
+  int32_t precision;    /* 0: FP64 (the only mode built) */
+} grffe_params;
+
+typedef struct grffe_domain grffe_domain;
+
+/* Fill *p with the paper's parameter values (eta = 1e6, kappa = 1, cfl = 0.25,
+ * M auto, alpha = 4 / 5, a = 36, b = 50, WENO5-Z eps 1e-40, FD4 corrector,
+ * clamp off, adaptive hybrid control). */
+void grffe_default_params(grffe_params* p);
+
+/* Create a domain.  bg (device, nullable) is the background metric at the DG
+ * nodes, [26][E][n^3]: alpha; beta^x,y,z; gamma_xx,xy,xz,yy,yz,zz; d_x,y,z alpha;
+ * d_j beta^i (j outer, i inner); K; Gamma^i = gamma^jk Gamma^i_jk (Sec. II A and
+ * Appendix B).  NULL means flat space.  The library copies bg and derives the
+ * metric at FD cell centres and faces by evaluating the nodal polynomial.
+ * The state is zero and every element is DG until set.  Returns the domain in *out. */
+int grffe_init_domain(const grffe_grid* grid, const grffe_params* params, const double* bg, void* stream,
+                      grffe_domain** out);
+int grffe_destroy(grffe_domain* dom);
+
+/* Set the state from FD subcell data u_fd (device, [9][E][m^3]), as at
+ * start-up (Sec. III C 1): every element is reconstructed to DG and the
+ * indicator with alpha_fd decides which stay FD (adaptive mode); in forced mode
+ * `forced` (device uint8 [E], nullable) marks the FD elements; in DG-only mode
+ * all go DG. */
+int grffe_init_from_fd(grffe_domain* dom, const double* u_fd, const uint8_t* forced, void* stream);
+
+/* Copy the state in / out.  dg [9][E][n^3], fd [9][E][m^3] and rep [E] are device
+ * pointers; on set, only the representation named by rep is read per element. */
+int grffe_set_state(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep, void* stream);
+int grffe_get_state(grffe_domain* dom, double* dg, double* fd, int32_t* rep, void* stream);
+
+/* Semi-discrete right-hand side dU/dt of every live element in its
+ * representation given by rep (a pure function of the arguments; the domain's
+ * own state is not touched).  parts = GRFFE_PART_*.  Outputs have the layouts of
+ * the inputs; entries of the other representation are left unchanged. */
+int grffe_rhs(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep, double* ddg, double* dfd,
+              int parts, void* stream);
+
+/* Advance the domain's state by n_steps IMEX-SSP3(4,3,3) steps of size dt
+ * (dt <= 0 selects the CFL step of Eq. (spectre DG CFL condition)), with the
+ * hybrid control of Sec. III C 1 inside every step. */
+int grffe_step(grffe_domain* dom, int n_steps, double dt, void* stream);
+
+/* Troubled-cell indicator, Eq. (persson tci), on |B~| = sqrt(gamma_ij B~^i B~^j):
+ * DG elements (rep 0) are checked on dg with alpha, FD elements (rep 1) on the
+ * sixth-order reconstruction of fd with alpha_fd.  troubled (device uint8 [E]);
+ * ratio (device double [E], nullable) receives sqrt(sum u_hat^2 / sum u^2). */
+int grffe_tci(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep, uint8_t* troubled,
+              double* ratio, void* stream);
+
+/* DG -> FD projection (evaluation of the nodal polynomial at the subcell
+ * centres, Sec. III C 2) and FD -> DG sixth-order least-squares reconstruction
+ * (Sec. III C 1) of the n listed elements.  Compact layouts: u_dg [9][n][n^3],
+ * u_fd [9][n][m^3]; elems (device int32 [n]) only selects the element degree and
+ * must hold valid element ids. */
+int grffe_project_dg_to_fd(grffe_domain* dom, const double* u_dg, double* u_fd, const int32_t* elems, int32_t n,
+                           void* stream);
+int grffe_reconstruct_fd_to_dg(grffe_domain* dom, const double* u_fd, double* u_dg, const int32_t* elems,
+                               int32_t n, void* stream);
+
+/* Time step of Eq. (spectre DG CFL condition) (host value; synchronises). */
+int grffe_get_dt(grffe_domain* dom, double* dt);
+
+/* Number of live elements on DG and on FD (host values; synchronises). */
+int grffe_get_counts(grffe_domain* dom, int32_t* n_dg, int32_t* n_fd);
+
+/* Host copies of the library's 1D operators for degree N, row-major:
+ * which = 0 GLL nodes (n), 1 GLL weights (n), 2 derivative matrix (n x n),
+ * 3 filter (n x n), 4 low-pass (n x n), 5 projection P (m x n),
+ * 6 reconstruction R (n x m), 7 face evaluation (m+1 x n).  Returns the number
+ * of doubles written (out may be NULL to query). */
+int grffe_operator(int degree, int which, double* out, int capacity);
+
+const char* grffe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRFFE_H */

@@ -1,0 +1,148 @@
+// Device helpers shared by the kernel translation units.
+#pragma once
+#include "grffe_internal.h"
+#include "physics.h"
+
+namespace grffe {
+
+template <int N>
+struct Dims {
+  static constexpr int n = N + 1;
+  static constexpr int m = 2 * N + 1;
+  static constexpr int nn = n * n * n;
+  static constexpr int mm = m * m * m;
+  static constexpr int tpb = ((nn + 63) / 64) * 64;  // threads of a per-element DG block
+};
+
+// Block-wide sum of two doubles (all threads of the block must call it).
+template <int TPB>
+__device__ inline void block_sum2(double& a, double& b, double* sred) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  constexpr int NWAVE = TPB / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sred[2 * wave] = a;
+    sred[2 * wave + 1] = b;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  for (int w = 0; w < NWAVE; ++w) {
+    a += sred[2 * w];
+    b += sred[2 * w + 1];
+  }
+  __syncthreads();
+}
+
+// Metric (10 leading fields) of point `p` of element `e` from a [F][E][P] array.
+template <bool CURVED>
+__device__ inline void load_metric(const double* bg, int E, int P, int e, int p, Metric& M) {
+  if (!CURVED) {
+    metric_flat(M);
+    return;
+  }
+  double f[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) f[k] = bg[((size_t)k * E + e) * P + p];
+  metric_from10(f, M);
+}
+
+template <bool CURVED>
+__device__ inline void load_deriv(const double* bg, int E, int P, int e, int p, MetricDeriv& Dv) {
+  if (!CURVED) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Dv.da[k] = bg[((size_t)(10 + k) * E + e) * P + p];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Dv.db[k] = bg[((size_t)(13 + k) * E + e) * P + p];
+  Dv.K = bg[((size_t)22 * E + e) * P + p];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Dv.Gam[k] = bg[((size_t)(23 + k) * E + e) * P + p];
+}
+
+__device__ inline void load9(const double* base, int E, int P, int e, int p, double* U) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) U[v] = base[((size_t)v * E + e) * P + p];
+}
+
+__device__ inline void store9(double* base, int E, int P, int e, int p, const double* U) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) base[((size_t)v * E + e) * P + p] = U[v];
+}
+
+// U_1, U_2 and their stiff sources from U^n (the implicit pre-stages of IMEX-SSP3(4,3,3)).
+__device__ inline void derived_stages(const double* Un, const Metric& M, const KArgs& a, double* U2, double* S1,
+                                      double* S2) {
+  double U1[NV];
+  const double h = a.dt * IMEX_A;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) U1[v] = Un[v];
+  implicit_solve(U1, M, a.eta, a.kpsi, a.kphi, h);
+  source_stiff(U1, M, a.eta, a.kpsi, a.kphi, S1);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) U2[v] = Un[v] - a.dt * IMEX_A * S1[v];
+  implicit_solve(U2, M, a.eta, a.kpsi, a.kphi, h);
+  source_stiff(U2, M, a.eta, a.kpsi, a.kphi, S2);
+}
+
+// Stage value that is the input of substep MODE, at point p of element e of a register set.
+template <int MODE>
+__device__ inline void stage_input(const Regs& r, int E, int P, int e, int p, const Metric& M, const KArgs& a,
+                                   double* X) {
+  if (MODE == MODE_RHS) {
+    load9(r.Un, E, P, e, p, X);
+  } else if (MODE == MODE_SUB1) {
+    double Un[NV], S1[NV], S2[NV];
+    load9(r.Un, E, P, e, p, Un);
+    derived_stages(Un, M, a, X, S1, S2);
+  } else if (MODE == MODE_SUB2) {
+    load9(r.X0, E, P, e, p, X);
+  } else {
+    load9(r.X1, E, P, e, p, X);
+  }
+}
+
+// Explicit update Y of substep MODE (before the filter and the implicit solve) and the new
+// accumulator.  L is the explicit operator at the stage input X.
+template <int MODE>
+__device__ inline void stage_update(const Regs& r, int E, int P, int e, int p, const Metric& M, const KArgs& a,
+                                    const double* X, const double* L, double* Y, double* Anew) {
+  double Un[NV], S1[NV], S2[NV], U2[NV];
+  load9(r.Un, E, P, e, p, Un);
+  const double dt = a.dt;
+  if (MODE == MODE_SUB1) {
+    derived_stages(Un, M, a, U2, S1, S2);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      Y[v] = Un[v] + dt * L[v] + dt * (1.0 - IMEX_A) * S2[v];
+      Anew[v] = dt * L[v];
+    }
+  } else if (MODE == MODE_SUB2) {
+    double A[NV], S3[NV];
+    load9(r.A, E, P, e, p, A);
+    derived_stages(Un, M, a, U2, S1, S2);
+    source_stiff(X, M, a.eta, a.kpsi, a.kphi, S3);
+    const double c3 = 0.5 - IMEX_B - IMEX_E - IMEX_A;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double inc = A[v] + dt * L[v];
+      Y[v] = Un[v] + 0.25 * inc + dt * (IMEX_B * S1[v] + IMEX_E * S2[v] + c3 * S3[v]);
+      Anew[v] = inc / 6.0 + dt * S3[v] / 6.0;
+    }
+  } else {
+    double A[NV], S4[NV];
+    load9(r.A, E, P, e, p, A);
+    derived_stages(Un, M, a, U2, S1, S2);
+    source_stiff(X, M, a.eta, a.kpsi, a.kphi, S4);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      Y[v] = Un[v] + A[v] + dt * S2[v] / 6.0 + (2.0 / 3.0) * dt * (L[v] + S4[v]);
+      Anew[v] = 0.0;
+    }
+  }
+}
+
+}  // namespace grffe

@@ -1,0 +1,139 @@
+// Internal declarations of the GRFFE library: domain layout in HBM, kernel
+// argument blocks and launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/grffe.h"
+
+namespace grffe {
+
+constexpr int NV = 9;      // evolved components
+constexpr int NW = 12;     // evolved components + densitized current J~
+constexpr int NBG = 26;    // background fields at DG nodes / FD cells
+constexpr int NBGF = 10;   // background fields at FD faces (alpha, beta, gamma)
+constexpr int MAX_DEG = 7; // largest degree with a fused DG kernel
+
+// IMEX-SSP3(4,3,3) (Pareschi & Russo 2005): implicit diagonal a, and b, e of the last row.
+constexpr double IMEX_A = 0.24169426078821;
+constexpr double IMEX_B = 0.06042356519705;
+constexpr double IMEX_E = 0.12915286960590;
+
+struct Ops1D {
+  int N = 0;
+  std::vector<double> x, w, D, F, L, P, Q, R;
+};
+
+Ops1D build_ops(int N, double filter_a, double filter_b, int tci_M, int tci_mode);
+void gll_nodes_weights(int N, std::vector<double>& x, std::vector<double>& w);
+int default_tci_M(int N);
+
+// Operators in device memory (row-major), sized for MAX_DEG.
+struct DevOps {
+  double w[MAX_DEG + 1];
+  double D[(MAX_DEG + 1) * (MAX_DEG + 1)];
+  double F[(MAX_DEG + 1) * (MAX_DEG + 1)];
+  double L[(MAX_DEG + 1) * (MAX_DEG + 1)];
+  double P[(2 * MAX_DEG + 1) * (MAX_DEG + 1)];
+  double R[(MAX_DEG + 1) * (2 * MAX_DEG + 1)];
+};
+
+enum Mode { MODE_RHS = 0, MODE_SUB1 = 1, MODE_SUB2 = 2, MODE_SUB3 = 3 };
+
+// Register set of one representation: U^n, the two stage values, the accumulator.
+struct Regs {
+  double* Un;
+  double* X0;  // U_3 (written in substep 1)
+  double* X1;  // U_4 (written in substep 2)
+  double* A;   // accumulated increments
+};
+
+// Everything a kernel needs; passed by value.
+struct KArgs {
+  int E, nx, ny, nz;
+  double h[3];
+  const int32_t* nbr;      // [E][6], -1 at a boundary
+  const uint8_t* live;     // [E]
+  const double* bg_dg;     // [26][E][n^3] or null
+  const double* bg_fd;     // [26][E][m^3] or null
+  const double* bg_face;   // [3][10][E][(m+1) m^2] or null
+  const DevOps* ops;
+  // state
+  Regs dg, fd;
+  int32_t* rep0;           // representation at the start of the substep
+  int32_t* rep;            // representation being built
+  uint8_t* troubled;       // [E] flags of the current substep
+  double* ratio;           // [E] indicator ratios (diagnostic)
+  // scratch
+  double* w_fd;            // [12][E][m^3]  FD stage values + J~
+  double* trace;           // [12][E][6][n^2]  R-traces of FD elements at their faces
+  double* slab;            // [12][E][6][3 m^2]  P-projection of DG stage values next to each face
+  double* fhat;            // [3][9][E][(m+1) m^2] FD numerical fluxes
+  // RHS mode outputs
+  double* out_dg;
+  double* out_fd;
+  int parts;
+  // scheme parameters
+  double dt, eta, kpsi, kphi;
+  double tci_thr, tci_thr_fd;
+  int tci_mode, filter_on, fd_order, ff_clamp, hybrid;
+  double weno_eps, ff_margin;
+};
+
+}  // namespace grffe
+
+struct grffe_domain {
+  int N, n, m, nn, mm;
+  int E, nx, ny, nz;
+  double lower[3], upper[3], h[3];
+  int bc[6];
+  grffe_params par;
+  bool curved;
+  std::vector<int32_t> nbr_h;
+  std::vector<uint8_t> live_h;
+  int32_t* nbr = nullptr;
+  uint8_t* live = nullptr;
+  double* bg_dg = nullptr;
+  double* bg_fd = nullptr;
+  double* bg_face = nullptr;
+  grffe::DevOps* ops = nullptr;
+  grffe::Ops1D ops_h;
+  grffe::Regs dg{}, fd{};
+  int32_t* rep = nullptr;
+  int32_t* rep0 = nullptr;
+  uint8_t* troubled = nullptr;
+  double* ratio = nullptr;
+  double* w_fd = nullptr;
+  double* trace = nullptr;
+  double* slab = nullptr;
+  double* fhat = nullptr;
+  double dt_cfl = 0.0;
+  double lambda_max = 0.0;
+  std::vector<void*> allocs;
+};
+
+namespace grffe {
+
+KArgs make_args(grffe_domain* d);
+
+// launchers (kernels_dg.hip)
+void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
+void launch_dg_slab(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
+// launchers (kernels_fd.hip)
+void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, bool troubled_only, hipStream_t s);
+void launch_fd_trace(const KArgs& a, int N, hipStream_t s);
+void launch_project_troubled(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
+void launch_fd_flux(const KArgs& a, int N, bool curved, hipStream_t s);
+void launch_fd_update(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
+void launch_fd_to_dg(const KArgs& a, int N, bool curved, int init, hipStream_t s);
+void launch_begin_substep(const KArgs& a, hipStream_t s);
+void launch_tci(const KArgs& a, int N, bool curved, const double* dg, const double* fd, const int32_t* rep,
+                uint8_t* troubled, double* ratio, hipStream_t s);
+void launch_transfer(const KArgs& a, int N, int to_fd, const double* in, double* out, int count, hipStream_t s);
+void launch_bg_derive(const KArgs& a, int N, hipStream_t s);
+void launch_lambda_max(const KArgs& a, int N, double* out, hipStream_t s);
+
+}  // namespace grffe

@@ -1,0 +1,326 @@
+// DG kernels: the fused per-element DG substep and the DG -> FD ghost slabs.
+//
+// One workgroup per element, one thread per GLL node (Sec. III A).  The
+// strong-form DG-SEM operator with a lumped GLL mass matrix is
+//   dU/dt = -sum_d (2/h_d) [ D_d F^d + W^-1 (e_N (F*_+ - F_N) - e_0 (F*_- - F_0)) ] + S,
+// the face flux F* is Rusanov with speed max(lambda_int, lambda_ext),
+// lambda = alpha sqrt(gamma^dd) + |beta^d|.  The whole substep -- stage input,
+// fluxes, derivative and lift, sources, IMEX stage update, exponential filter
+// (Eq. exponential filter) on the explicit update, pointwise implicit solve,
+// optional algebraic clamp and the troubled-cell indicator (Eq. persson tci) --
+// runs in one launch; the candidate is written only when it is admissible, so a
+// troubled element keeps its substep-start registers for the FD redo.
+#include "common.h"
+
+namespace grffe {
+
+// External (neighbour or boundary) state W = (U, J~) and metric for the face node
+// (i, j, k) of element e on face f = 2 d + s.
+template <int N, bool CURVED, int MODE>
+__device__ inline void external_state(const KArgs& a, int e, int f, int i, int j, int k, const double* Ui,
+                                      const Metric& Mi, double* Wx, Metric& Mx) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, nn = Dm::nn;
+  const int d = f >> 1, s = f & 1;
+  const int o = a.nbr[e * 6 + f];
+  if (o < 0) {
+    boundary_state(d, s ? 1.0 : -1.0, Ui, Mi, Wx);
+    current_total(Wx, Mi, a.eta, Wx + 9);
+    Mx = Mi;
+    return;
+  }
+  int ii = i, jj = j, kk = k;
+  if (d == 0) ii = s ? 0 : N;
+  else if (d == 1) jj = s ? 0 : N;
+  else kk = s ? 0 : N;
+  const int pn = ii + n * (jj + n * kk);
+  load_metric<CURVED>(a.bg_dg, a.E, nn, o, pn, Mx);
+  if (a.rep0[o] == 0) {
+    stage_input<MODE>(a.dg, a.E, nn, o, pn, Mx, a, Wx);
+    current_total(Wx, Mx, a.eta, Wx + 9);
+  } else {
+    // FD neighbour: R-trace on its face facing us (face 2d + 1 - s)
+    const int fo = 2 * d + (1 - s);
+    int t1, t2;
+    if (d == 0) { t1 = j; t2 = k; }
+    else if (d == 1) { t1 = i; t2 = k; }
+    else { t1 = i; t2 = j; }
+    const size_t base = ((size_t)o * 6 + fo) * (n * n) + t1 + n * t2;
+    const size_t stride = (size_t)a.E * 6 * n * n;
+#pragma unroll
+    for (int c = 0; c < NW; ++c) Wx[c] = a.trace[base + c * stride];
+  }
+}
+
+template <int N, bool CURVED, int MODE>
+__global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, nn = Dm::nn, TPB = Dm::tpb;
+  __shared__ double sF[NV * nn];
+  __shared__ double sred[2 * (TPB / 64)];
+  __shared__ double sop[3 * n * n];  // D, filter, indicator operator
+  const int e = blockIdx.x;
+  if (!a.live[e] || a.rep0[e] != 0) return;
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int p = act ? t : 0;
+  const int i = p % n, j = (p / n) % n, k = p / (n * n);
+  for (int q = t; q < n * n; q += TPB) {
+    sop[q] = a.ops->D[q];
+    sop[n * n + q] = a.ops->F[q];
+    sop[2 * n * n + q] = a.ops->L[q];
+  }
+  Metric M;
+  load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
+  double X[NV], J[3], Jd[3], Je[3], dU[NV];
+  stage_input<MODE>(a.dg, a.E, nn, e, p, M, a, X);
+  current(X, M, a.eta, Jd, Je);
+  for (int c = 0; c < 3; ++c) J[c] = Jd[c] + Je[c];
+  {
+    MetricDeriv Dv;
+    load_deriv<CURVED>(a.bg_dg, a.E, nn, e, p, Dv);
+    source_explicit<CURVED>(X, M, Dv, Jd, dU);
+  }
+  const int idx[3] = {i, j, k};
+  const int strideN[3] = {1, n, n * n};
+  for (int d = 0; d < 3; ++d) {
+    double F[NV];
+    flux_any(d, X, J, M, F);
+    __syncthreads();
+    if (act)
+      for (int v = 0; v < NV; ++v) sF[v * nn + p] = F[v];
+    __syncthreads();
+    const double sc = 2.0 / a.h[d];
+    const int id = idx[d];
+    const int p0 = p - id * strideN[d];
+    const double* Drow = sop + id * n;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < n; ++q) acc += Drow[q] * sF[v * nn + p0 + q * strideN[d]];
+      dU[v] -= sc * acc;
+    }
+    if (act && (id == 0 || id == N)) {
+      const int s = (id == N) ? 1 : 0;
+      double Wx[NW], Fx[NV], Fs[NV];
+      Metric Mx;
+      external_state<N, CURVED, MODE>(a, e, 2 * d + s, i, j, k, X, M, Wx, Mx);
+      flux_any(d, Wx, Wx + 9, Mx, Fx);
+      const double lam = CURVED ? fmax(char_speed(d, M), char_speed(d, Mx)) : 1.0;
+      if (s == 0) {
+        const double wl = sc / a.ops->w[0];
+        for (int v = 0; v < NV; ++v) {
+          Fs[v] = 0.5 * (Fx[v] + F[v]) - 0.5 * lam * (X[v] - Wx[v]);
+          dU[v] += wl * (Fs[v] - F[v]);
+        }
+      } else {
+        const double wr = sc / a.ops->w[N];
+        for (int v = 0; v < NV; ++v) {
+          Fs[v] = 0.5 * (F[v] + Fx[v]) - 0.5 * lam * (Wx[v] - X[v]);
+          dU[v] -= wr * (Fs[v] - F[v]);
+        }
+      }
+    }
+  }
+  if (MODE == MODE_RHS) {
+    if (!act) return;
+    double St[NV];
+    source_stiff(X, M, a.eta, a.kpsi, a.kphi, St);
+    double out[NV];
+    for (int v = 0; v < NV; ++v) out[v] = ((a.parts & 1) ? dU[v] : 0.0) + ((a.parts & 2) ? St[v] : 0.0);
+    store9(a.out_dg, a.E, nn, e, p, out);
+    return;
+  }
+  // IMEX stage update, filter on the explicit update, implicit solve
+  double Y[NV], Anew[NV];
+  stage_update<MODE>(a.dg, a.E, nn, e, p, M, a, X, dU, Y, Anew);
+  if (a.filter_on) {
+    for (int d = 0; d < 3; ++d) {
+      __syncthreads();
+      if (act)
+        for (int v = 0; v < NV; ++v) sF[v * nn + p] = Y[v];
+      __syncthreads();
+      const int id = idx[d];
+      const int p0 = p - id * strideN[d];
+      const double* Frow = sop + n * n + id * n;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < n; ++q) acc += Frow[q] * sF[v * nn + p0 + q * strideN[d]];
+        Y[v] = acc;
+      }
+    }
+  }
+  if (MODE != MODE_SUB3) implicit_solve(Y, M, a.eta, a.kpsi, a.kphi, a.dt * IMEX_A);
+  if (a.ff_clamp) constraint_clamp(Y, M, a.ff_margin);
+  // troubled-cell indicator on u = |B~|
+  bool bad = false;
+  if (a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
+    const double u = act ? sqrt(dot3(M, Y + 3, Y + 3)) : 0.0;
+    double uh = u;
+    for (int d = 0; d < 3; ++d) {
+      __syncthreads();
+      if (act) sF[p] = uh;
+      __syncthreads();
+      const int id = idx[d];
+      const int p0 = p - id * strideN[d];
+      const double* Lrow = sop + 2 * n * n + id * n;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < n; ++q) acc += Lrow[q] * sF[p0 + q * strideN[d]];
+      uh = acc;
+    }
+    double num = act ? (a.tci_mode == 1 ? uh * uh : (u - uh) * (u - uh)) : 0.0;
+    double den = act ? u * u : 0.0;
+    block_sum2<TPB>(num, den, sred);
+    const double ratio = den > 0.0 ? sqrt(num / den) : 0.0;
+    bad = ratio > a.tci_thr;
+    if (t == 0) {
+      a.ratio[e] = ratio;
+      if (bad) a.troubled[e] = 1;
+    }
+  }
+  if (bad || !act) return;
+  if (MODE == MODE_SUB1) {
+    store9(a.dg.X0, a.E, nn, e, p, Y);
+    store9(a.dg.A, a.E, nn, e, p, Anew);
+  } else if (MODE == MODE_SUB2) {
+    store9(a.dg.X1, a.E, nn, e, p, Y);
+    store9(a.dg.A, a.E, nn, e, p, Anew);
+  } else {
+    store9(a.dg.Un, a.E, nn, e, p, Y);
+  }
+}
+
+// P-projection (3 subcell layers next to each face) of the DG stage input of
+// elements whose neighbour across that face is on FD or has just been flagged.
+template <int N, bool CURVED, int MODE>
+__global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, TPB = Dm::tpb;
+  const int e = blockIdx.x;
+  if (!a.live[e] || a.rep0[e] != 0) return;
+  int need = 0;
+  for (int f = 0; f < 6; ++f) {
+    const int o = a.nbr[e * 6 + f];
+    if (o >= 0 && (a.rep0[o] == 1 || a.troubled[o])) need |= 1 << f;
+  }
+  if (!need) return;
+  __shared__ double sW[NW * nn];
+  __shared__ double sA[3 * m * n * n];
+  __shared__ double sB[3 * m * m * n];
+  __shared__ double sP[m * n];
+  const int t = threadIdx.x;
+  for (int q = t; q < m * n; q += TPB) sP[q] = a.ops->P[q];
+  if (t < nn) {
+    Metric M;
+    load_metric<CURVED>(a.bg_dg, a.E, nn, e, t, M);
+    double X[NV];
+    stage_input<MODE>(a.dg, a.E, nn, e, t, M, a, X);
+    double J[3];
+    current_total(X, M, a.eta, J);
+    for (int v = 0; v < NV; ++v) sW[v * nn + t] = X[v];
+    for (int c = 0; c < 3; ++c) sW[(9 + c) * nn + t] = J[c];
+  }
+  __syncthreads();
+  const size_t stride = (size_t)a.E * 6 * 3 * m * m;
+  for (int f = 0; f < 6; ++f) {
+    if (!(need & (1 << f))) continue;
+    const int d = f >> 1, s = f & 1;
+    // axes: normal d, tangential t1 < t2
+    const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+    const int str[3] = {1, n, n * n};
+    for (int c = 0; c < NW; ++c) {
+      const double* W = sW + c * nn;
+      // 1) normal direction: layers l = 0..2, cell index m-1-l (upper face) or l (lower face)
+      for (int q = t; q < 3 * n * n; q += TPB) {
+        const int l = q / (n * n), r = q % (n * n);
+        const int a1 = r % n, a2 = r / n;
+        const int cell = s ? (m - 1 - l) : l;
+        double acc = 0.0;
+        for (int z = 0; z < n; ++z) acc += sP[cell * n + z] * W[z * str[d] + a1 * str[t1ax] + a2 * str[t2ax]];
+        sA[q] = acc;  // [l][a2][a1]
+      }
+      __syncthreads();
+      // 2) first tangential axis: a1 (n) -> c1 (m)
+      for (int q = t; q < 3 * m * n; q += TPB) {
+        const int l = q / (m * n), r = q % (m * n);
+        const int c1 = r % m, a2 = r / m;
+        double acc = 0.0;
+        for (int z = 0; z < n; ++z) acc += sP[c1 * n + z] * sA[(l * n + a2) * n + z];
+        sB[q] = acc;  // [l][a2][c1]
+      }
+      __syncthreads();
+      // 3) second tangential axis: a2 (n) -> c2 (m), write [l][c2][c1]
+      double* out = a.slab + ((size_t)c * a.E * 6 + (size_t)e * 6 + f) * (3 * m * m);
+      for (int q = t; q < 3 * m * m; q += TPB) {
+        const int l = q / (m * m), r = q % (m * m);
+        const int c1 = r % m, c2 = r / m;
+        double acc = 0.0;
+        for (int z = 0; z < n; ++z) acc += sP[c2 * n + z] * sB[(l * n + z) * m + c1];
+        out[q] = acc;
+      }
+      __syncthreads();
+    }
+  }
+  (void)stride;
+}
+
+template <int N, bool CURVED>
+static void launch_dg_substep_t(const KArgs& a, int mode, hipStream_t s) {
+  dim3 grid(a.E), block(Dims<N>::tpb);
+  switch (mode) {
+    case MODE_RHS: hipLaunchKernelGGL((k_dg_substep<N, CURVED, MODE_RHS>), grid, block, 0, s, a); break;
+    case MODE_SUB1: hipLaunchKernelGGL((k_dg_substep<N, CURVED, MODE_SUB1>), grid, block, 0, s, a); break;
+    case MODE_SUB2: hipLaunchKernelGGL((k_dg_substep<N, CURVED, MODE_SUB2>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_dg_substep<N, CURVED, MODE_SUB3>), grid, block, 0, s, a); break;
+  }
+}
+
+template <int N, bool CURVED>
+static void launch_dg_slab_t(const KArgs& a, int mode, hipStream_t s) {
+  dim3 grid(a.E), block(Dims<N>::tpb);
+  switch (mode) {
+    case MODE_RHS: hipLaunchKernelGGL((k_dg_slab<N, CURVED, MODE_RHS>), grid, block, 0, s, a); break;
+    case MODE_SUB1: hipLaunchKernelGGL((k_dg_slab<N, CURVED, MODE_SUB1>), grid, block, 0, s, a); break;
+    case MODE_SUB2: hipLaunchKernelGGL((k_dg_slab<N, CURVED, MODE_SUB2>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_dg_slab<N, CURVED, MODE_SUB3>), grid, block, 0, s, a); break;
+  }
+}
+
+#define GRFFE_DISPATCH_N(FN, ...)                 \
+  switch (N) {                                    \
+    case 3: FN<3, CURVED_T>(__VA_ARGS__); break;  \
+    case 4: FN<4, CURVED_T>(__VA_ARGS__); break;  \
+    case 5: FN<5, CURVED_T>(__VA_ARGS__); break;  \
+    case 6: FN<6, CURVED_T>(__VA_ARGS__); break;  \
+    default: FN<7, CURVED_T>(__VA_ARGS__); break; \
+  }
+
+void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t s) {
+  if (curved) {
+#define CURVED_T true
+    GRFFE_DISPATCH_N(launch_dg_substep_t, a, mode, s)
+#undef CURVED_T
+  } else {
+#define CURVED_T false
+    GRFFE_DISPATCH_N(launch_dg_substep_t, a, mode, s)
+#undef CURVED_T
+  }
+}
+
+void launch_dg_slab(const KArgs& a, int N, bool curved, int mode, hipStream_t s) {
+  if (curved) {
+#define CURVED_T true
+    GRFFE_DISPATCH_N(launch_dg_slab_t, a, mode, s)
+#undef CURVED_T
+  } else {
+#define CURVED_T false
+    GRFFE_DISPATCH_N(launch_dg_slab_t, a, mode, s)
+#undef CURVED_T
+  }
+}
+
+}  // namespace grffe

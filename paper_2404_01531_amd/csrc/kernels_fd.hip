@@ -1,0 +1,749 @@
+// FD subcell kernels and the DG <-> FD transfers.
+//
+// Sec. III C 2, Eq. (fd time derivative): conservative finite differences on
+// (2N+1)^3 uniform subcells.  Dimension by dimension, the point values of U and
+// of J~ are reconstructed to the subcell faces with WENO5-Z (exponent q = 2),
+// the Rusanov flux F* is formed with the metric at the face, and the
+// fourth-order corrector of Eq. (higher order flux correction), built from the
+// cell-centred fluxes,
+//   Fhat_{i+1/2} = F*_{i+1/2} - (F_i - 2 F*_{i+1/2} + F_{i+1}) / 6,
+// gives dU_i/dt = -sum_d (2N+1)/h_d (Fhat_{i+1/2} - Fhat_{i-1/2}) + S(U_i).
+// Three ghost layers per face come from the neighbour's subcells, from the
+// P-projection of a DG neighbour (slab buffer), or from the no-incoming-Poynting
+// state of the outermost own cell (Sec. III D).
+#include "common.h"
+
+namespace grffe {
+
+__device__ inline bool fd_active(const KArgs& a, int e) {
+  return a.live[e] && (a.rep0[e] == 1 || a.troubled[e]);
+}
+
+// ---------------------------------------------------------------- FD stage values + J~
+template <int N, bool CURVED, int MODE>
+__global__ __launch_bounds__(256) void k_fd_stage(KArgs a, int troubled_only) {
+  using Dm = Dims<N>;
+  constexpr int mm = Dm::mm;
+  const int e = blockIdx.y;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= mm || !a.live[e]) return;
+  if (troubled_only ? !a.troubled[e] : (a.rep0[e] != 1)) return;
+  Metric M;
+  load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
+  double X[NV], J[3];
+  stage_input<MODE>(a.fd, a.E, mm, e, p, M, a, X);
+  current_total(X, M, a.eta, J);
+  const size_t st = (size_t)a.E * mm;
+  double* w = a.w_fd + (size_t)e * mm + p;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) w[v * st] = X[v];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w[(9 + c) * st] = J[c];
+}
+
+// ---------------------------------------------------------------- R-traces of FD elements
+template <int N>
+__global__ __launch_bounds__(256) void k_fd_trace(KArgs a) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m, mm = Dm::mm;
+  const int e = blockIdx.x;
+  if (!a.live[e] || a.rep0[e] != 1) return;
+  __shared__ double sW[mm];
+  __shared__ double s1[m * m];
+  __shared__ double s2[n * m];
+  __shared__ double sR[n * m];
+  const int t = threadIdx.x;
+  for (int q = t; q < n * m; q += 256) sR[q] = a.ops->R[q];
+  const int str[3] = {1, m, m * m};
+  for (int c = 0; c < NW; ++c) {
+    __syncthreads();
+    for (int q = t; q < mm; q += 256) sW[q] = a.w_fd[((size_t)c * a.E + e) * mm + q];
+    __syncthreads();
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1, s = f & 1;
+      const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+      const int row = s ? N : 0;
+      for (int q = t; q < m * m; q += 256) {
+        const int c1 = q % m, c2 = q / m;
+        double acc = 0.0;
+        for (int z = 0; z < m; ++z) acc += sR[row * m + z] * sW[z * str[d] + c1 * str[t1ax] + c2 * str[t2ax]];
+        s1[q] = acc;  // [c2][c1]
+      }
+      __syncthreads();
+      for (int q = t; q < n * m; q += 256) {
+        const int a1 = q % n, c2 = q / n;
+        double acc = 0.0;
+        for (int z = 0; z < m; ++z) acc += sR[a1 * m + z] * s1[c2 * m + z];
+        s2[q] = acc;  // [c2][a1]
+      }
+      __syncthreads();
+      double* out = a.trace + ((size_t)c * a.E * 6 + (size_t)e * 6 + f) * (n * n);
+      for (int q = t; q < n * n; q += 256) {
+        const int a1 = q % n, a2 = q / n;
+        double acc = 0.0;
+        for (int z = 0; z < m; ++z) acc += sR[a2 * m + z] * s2[z * n + a1];
+        out[q] = acc;  // [a2][a1]
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- DG -> FD of flagged elements
+// P (x) P (x) P of the live registers of every element flagged in this substep.
+template <int N>
+__global__ __launch_bounds__(256) void k_project_troubled(KArgs a, int mode) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, mm = Dm::mm;
+  const int e = blockIdx.x;
+  if (!a.live[e] || !a.troubled[e]) return;
+  __shared__ double s0[nn];
+  __shared__ double s1[m * n * n];
+  __shared__ double s2[m * m * n];
+  __shared__ double sP[m * n];
+  const int t = threadIdx.x;
+  for (int q = t; q < m * n; q += 256) sP[q] = a.ops->P[q];
+  const double* src[3];
+  double* dst[3];
+  int nreg = 0;
+  src[nreg] = a.dg.Un;
+  dst[nreg++] = a.fd.Un;
+  if (mode == MODE_SUB2) {
+    src[nreg] = a.dg.X0;
+    dst[nreg++] = a.fd.X0;
+  }
+  if (mode == MODE_SUB3) {
+    src[nreg] = a.dg.X1;
+    dst[nreg++] = a.fd.X1;
+  }
+  if (mode == MODE_SUB2 || mode == MODE_SUB3) {
+    src[nreg] = a.dg.A;
+    dst[nreg++] = a.fd.A;
+  }
+  for (int r = 0; r < nreg; ++r)
+    for (int v = 0; v < NV; ++v) {
+      __syncthreads();
+      for (int q = t; q < nn; q += 256) s0[q] = src[r][((size_t)v * a.E + e) * nn + q];
+      __syncthreads();
+      for (int q = t; q < m * n * n; q += 256) {  // x: [z][y][cx]
+        const int cx = q % m, yz = q / m;
+        double acc = 0.0;
+        for (int z = 0; z < n; ++z) acc += sP[cx * n + z] * s0[yz * n + z];
+        s1[q] = acc;
+      }
+      __syncthreads();
+      for (int q = t; q < m * m * n; q += 256) {  // y: [z][cy][cx]
+        const int cx = q % m, cy = (q / m) % m, z0 = q / (m * m);
+        double acc = 0.0;
+        for (int z = 0; z < n; ++z) acc += sP[cy * n + z] * s1[(z0 * n + z) * m + cx];
+        s2[q] = acc;
+      }
+      __syncthreads();
+      double* out = dst[r] + ((size_t)v * a.E + e) * mm;
+      for (int q = t; q < mm; q += 256) {  // z: [cz][cy][cx]
+        const int cxy = q % (m * m), cz = q / (m * m);
+        double acc = 0.0;
+        for (int z = 0; z < n; ++z) acc += sP[cz * n + z] * s2[z * m * m + cxy];
+        out[q] = acc;
+      }
+    }
+}
+
+// ---------------------------------------------------------------- WENO5-Z on point values
+// Candidates are the quadratic Lagrange interpolants of the point values at the
+// face; optimal weights (1, 10, 5)/16; Z weights with tau5 = |b0 - b2|, q = 2.
+__device__ inline double weno5z(double vm2, double vm1, double v0, double vp1, double vp2, double eps) {
+  const double q0 = (3.0 * vm2 - 10.0 * vm1 + 15.0 * v0) * 0.125;
+  const double q1 = (-vm1 + 6.0 * v0 + 3.0 * vp1) * 0.125;
+  const double q2 = (3.0 * v0 + 6.0 * vp1 - vp2) * 0.125;
+  const double d0 = vm2 - 2.0 * vm1 + v0, e0 = vm2 - 4.0 * vm1 + 3.0 * v0;
+  const double d1 = vm1 - 2.0 * v0 + vp1, e1 = vm1 - vp1;
+  const double d2 = v0 - 2.0 * vp1 + vp2, e2 = 3.0 * v0 - 4.0 * vp1 + vp2;
+  const double b0 = (13.0 / 12.0) * d0 * d0 + 0.25 * e0 * e0;
+  const double b1 = (13.0 / 12.0) * d1 * d1 + 0.25 * e1 * e1;
+  const double b2 = (13.0 / 12.0) * d2 * d2 + 0.25 * e2 * e2;
+  const double tau = fabs(b0 - b2);
+  const double r0 = tau / (b0 + eps), r1 = tau / (b1 + eps), r2 = tau / (b2 + eps);
+  const double a0 = (1.0 / 16.0) * (1.0 + r0 * r0);
+  const double a1 = (10.0 / 16.0) * (1.0 + r1 * r1);
+  const double a2 = (5.0 / 16.0) * (1.0 + r2 * r2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// Where the (U, J~) of cell c (-3 <= c <= m+2 along d) of element e lives.
+struct CellSrc {
+  const double* ptr;  // component 0; null for the computed boundary state
+  size_t stride;      // between components
+  int elem, cell;     // element / cell index used for the cell metric
+};
+
+template <int N>
+__device__ inline CellSrc cell_source(const KArgs& a, int e, int d, int c, int t1, int t2) {
+  using Dm = Dims<N>;
+  constexpr int m = Dm::m, mm = Dm::mm;
+  const int str[3] = {1, m, m * m};
+  const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+  CellSrc cs;
+  if (c >= 0 && c < m) {
+    cs.cell = c * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
+    cs.elem = e;
+    cs.ptr = a.w_fd + (size_t)e * mm + cs.cell;
+    cs.stride = (size_t)a.E * mm;
+    return cs;
+  }
+  const int s = (c >= m) ? 1 : 0;
+  const int o = a.nbr[e * 6 + 2 * d + s];
+  if (o < 0) {
+    const int cb = s ? m - 1 : 0;
+    cs.cell = cb * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
+    cs.elem = e;
+    cs.ptr = nullptr;
+    cs.stride = 0;
+    return cs;
+  }
+  const int cn = s ? c - m : c + m;  // cell index inside the neighbour
+  cs.cell = cn * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
+  cs.elem = o;
+  if (a.rep0[o] == 1) {
+    cs.ptr = a.w_fd + (size_t)o * mm + cs.cell;
+    cs.stride = (size_t)a.E * mm;
+  } else {
+    // DG neighbour: its slab on the face facing us, layer = distance from the face
+    const int fo = 2 * d + (1 - s);
+    const int l = s ? (c - m) : (-1 - c);
+    cs.ptr = a.slab + ((size_t)o * 6 + fo) * (3 * m * m) + l * m * m + t1 + m * t2;
+    cs.stride = (size_t)a.E * 6 * 3 * m * m;
+  }
+  return cs;
+}
+
+template <int N, bool CURVED>
+__global__ __launch_bounds__(128) void k_fd_flux(KArgs a) {
+  using Dm = Dims<N>;
+  constexpr int m = Dm::m, mm = Dm::mm;
+  constexpr int nf = (m + 1) * m * m;
+  const int e = blockIdx.z;
+  const int d = blockIdx.y;
+  const int tix = blockIdx.x * 128 + threadIdx.x;
+  if (tix >= nf || !fd_active(a, e)) return;
+  int f, t1, t2;
+  if (d == 0) {
+    f = tix % (m + 1);
+    t1 = (tix / (m + 1)) % m;
+    t2 = tix / ((m + 1) * m);
+  } else if (d == 1) {
+    t1 = tix % m;
+    f = (tix / m) % (m + 1);
+    t2 = tix / (m * (m + 1));
+  } else {
+    t1 = tix % m;
+    t2 = (tix / m) % m;
+    f = tix / (m * m);
+  }
+  // cells f-3 .. f+2 along d; face f sits between cells f-1 and f
+  CellSrc cs[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) cs[q] = cell_source<N>(a, e, d, f - 3 + q, t1, t2);
+  // boundary state of the outermost own cell, if any of the six cells is a ghost of a domain face
+  double Wb[NW];
+  Metric Mb;
+  bool has_b = false;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) has_b |= (cs[q].ptr == nullptr);
+  if (has_b) {
+    int qb = 0;
+    for (int q = 0; q < 6; ++q)
+      if (cs[q].ptr == nullptr) qb = q;
+    const int side = (f - 3 + qb) >= m ? 1 : 0;
+    double Ui[NV];
+    load_metric<CURVED>(a.bg_fd, a.E, mm, e, cs[qb].cell, Mb);
+    load9(a.w_fd, a.E, mm, e, cs[qb].cell, Ui);
+    boundary_state(d, side ? 1.0 : -1.0, Ui, Mb, Wb);
+    current_total(Wb, Mb, a.eta, Wb + 9);
+  }
+  double WL[NW], WR[NW], W0[NW], W1[NW];
+  const double eps = a.weno_eps;
+#pragma unroll
+  for (int c = 0; c < NW; ++c) {
+    double v[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[q] = cs[q].ptr ? cs[q].ptr[c * cs[q].stride] : Wb[c];
+    WL[c] = weno5z(v[0], v[1], v[2], v[3], v[4], eps);
+    WR[c] = weno5z(v[5], v[4], v[3], v[2], v[1], eps);
+    W0[c] = v[2];
+    W1[c] = v[3];
+  }
+  Metric Mf;
+  load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nf, a.E, nf, e, tix, Mf);
+  double FL[NV], FR[NV];
+  flux_any(d, WL, WL + 9, Mf, FL);
+  flux_any(d, WR, WR + 9, Mf, FR);
+  const double lam = CURVED ? char_speed(d, Mf) : 1.0;
+  double Fh[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Fh[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (WR[v] - WL[v]);
+  if (a.fd_order == 4) {
+    Metric M0, M1;
+    if (cs[2].ptr) load_metric<CURVED>(a.bg_fd, a.E, mm, cs[2].elem, cs[2].cell, M0);
+    else M0 = Mb;
+    if (cs[3].ptr) load_metric<CURVED>(a.bg_fd, a.E, mm, cs[3].elem, cs[3].cell, M1);
+    else M1 = Mb;
+    double F0[NV], F1[NV];
+    flux_any(d, W0, W0 + 9, M0, F0);
+    flux_any(d, W1, W1 + 9, M1, F1);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fh[v] = Fh[v] - (F0[v] - 2.0 * Fh[v] + F1[v]) / 6.0;
+  }
+  double* out = a.fhat + ((size_t)d * NV * a.E + e) * nf + tix;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[(size_t)v * a.E * nf] = Fh[v];
+}
+
+template <int N, bool CURVED, int MODE>
+__global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
+  using Dm = Dims<N>;
+  constexpr int m = Dm::m, mm = Dm::mm;
+  constexpr int nf = (m + 1) * m * m;
+  const int e = blockIdx.y;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= mm || !fd_active(a, e)) return;
+  const int i = p % m, j = (p / m) % m, k = p / (m * m);
+  Metric M;
+  load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
+  double X[NV];
+  load9(a.w_fd, a.E, mm, e, p, X);
+  double Jd[3], Je[3], dU[NV];
+  current(X, M, a.eta, Jd, Je);
+  {
+    MetricDeriv Dv;
+    load_deriv<CURVED>(a.bg_fd, a.E, mm, e, p, Dv);
+    source_explicit<CURVED>(X, M, Dv, Jd, dU);
+  }
+  const int lo[3] = {i + (m + 1) * (j + m * k), i + m * (j + (m + 1) * k), i + m * (j + m * k)};
+  const int step[3] = {1, m, m * m};
+  for (int d = 0; d < 3; ++d) {
+    const double sc = (double)m / a.h[d];
+    const double* fh = a.fhat + ((size_t)d * NV * a.E + e) * nf + lo[d];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double* q = fh + (size_t)v * a.E * nf;
+      dU[v] -= sc * (q[step[d]] - q[0]);
+    }
+  }
+  if (MODE == MODE_RHS) {
+    double St[NV], out[NV];
+    source_stiff(X, M, a.eta, a.kpsi, a.kphi, St);
+    for (int v = 0; v < NV; ++v) out[v] = ((a.parts & 1) ? dU[v] : 0.0) + ((a.parts & 2) ? St[v] : 0.0);
+    store9(a.out_fd, a.E, mm, e, p, out);
+    return;
+  }
+  double Y[NV], Anew[NV];
+  stage_update<MODE>(a.fd, a.E, mm, e, p, M, a, X, dU, Y, Anew);
+  if (MODE != MODE_SUB3) implicit_solve(Y, M, a.eta, a.kpsi, a.kphi, a.dt * IMEX_A);
+  if (a.ff_clamp) constraint_clamp(Y, M, a.ff_margin);
+  if (MODE == MODE_SUB1) {
+    store9(a.fd.X0, a.E, mm, e, p, Y);
+    store9(a.fd.A, a.E, mm, e, p, Anew);
+  } else if (MODE == MODE_SUB2) {
+    store9(a.fd.X1, a.E, mm, e, p, Y);
+    store9(a.fd.A, a.E, mm, e, p, Anew);
+  } else {
+    store9(a.fd.Un, a.E, mm, e, p, Y);
+  }
+  if (p == 0 && a.troubled[e]) a.rep[e] = 1;
+}
+
+// ---------------------------------------------------------------- indicator helpers
+// u = |B~| at the DG nodes of R (x) R (x) R applied to the FD B~ of element e (from `fd`),
+// or taken directly from `dg`; returns the indicator ratio (block-wide).
+template <int N, bool CURVED>
+__device__ inline double block_ratio(const KArgs& a, int e, const double* Bn /* [3][nn] in LDS */,
+                                     double* su, double* sred, const double* sL) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, nn = Dm::nn, TPB = 256;
+  const int t = threadIdx.x;
+  double num = 0.0, den = 0.0;
+  // up to two nodes per thread for N <= 7 (nn <= 512)
+  double u[2], uh[2];
+  for (int r = 0; r < 2; ++r) {
+    const int p = t + r * TPB;
+    u[r] = 0.0;
+    if (p < nn) {
+      Metric M;
+      load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
+      double B[3] = {Bn[p], Bn[nn + p], Bn[2 * nn + p]};
+      u[r] = sqrt(dot3(M, B, B));
+    }
+    uh[r] = u[r];
+  }
+  const int str[3] = {1, n, n * n};
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();
+    for (int r = 0; r < 2; ++r)
+      if (t + r * TPB < nn) su[t + r * TPB] = uh[r];
+    __syncthreads();
+    for (int r = 0; r < 2; ++r) {
+      const int p = t + r * TPB;
+      if (p >= nn) continue;
+      const int id = (p / str[d]) % n;
+      const int p0 = p - id * str[d];
+      double acc = 0.0;
+      for (int q = 0; q < n; ++q) acc += sL[id * n + q] * su[p0 + q * str[d]];
+      uh[r] = acc;
+    }
+  }
+  for (int r = 0; r < 2; ++r) {
+    if (t + r * TPB >= nn) continue;
+    const double hp = (a.tci_mode == 1) ? uh[r] : (u[r] - uh[r]);
+    num += hp * hp;
+    den += u[r] * u[r];
+  }
+  block_sum2<TPB>(num, den, sred);
+  return den > 0.0 ? sqrt(num / den) : 0.0;
+}
+
+// R (x) R (x) R of one component (m^3 values in s_in) into s_out (n^3), using two scratch arrays.
+template <int N>
+__device__ inline void recon3(const double* sR, const double* s_in, double* s1, double* s2, double* s_out) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m;
+  const int t = threadIdx.x;
+  for (int q = t; q < n * m * m; q += 256) {  // x: [cz][cy][a]
+    const int ax = q % n, yz = q / n;
+    double acc = 0.0;
+    for (int z = 0; z < m; ++z) acc += sR[ax * m + z] * s_in[yz * m + z];
+    s1[q] = acc;
+  }
+  __syncthreads();
+  for (int q = t; q < n * n * m; q += 256) {  // y: [cz][b][a]
+    const int ax = q % n, by = (q / n) % n, cz = q / (n * n);
+    double acc = 0.0;
+    for (int z = 0; z < m; ++z) acc += sR[by * m + z] * s1[(cz * m + z) * n + ax];
+    s2[q] = acc;
+  }
+  __syncthreads();
+  for (int q = t; q < n * n * n; q += 256) {  // z: [c][b][a]
+    const int ab = q % (n * n), cz = q / (n * n);
+    double acc = 0.0;
+    for (int z = 0; z < m; ++z) acc += sR[cz * m + z] * s2[z * n * n + ab];
+    s_out[q] = acc;
+  }
+  __syncthreads();
+}
+
+// End of step (and start-up): FD elements whose reconstruction passes the indicator with
+// alpha_fd go back to DG.  policy: 0 indicator decides, 1 all go DG, 2 forced mask decides.
+template <int N, bool CURVED>
+__global__ __launch_bounds__(256) void k_fd_to_dg(KArgs a, int policy, const uint8_t* forced) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, mm = Dm::mm;
+  const int e = blockIdx.x;
+  if (!a.live[e] || a.rep[e] != 1) return;
+  __shared__ double sin_[mm];
+  __shared__ double s1[n * m * m];
+  __shared__ double s2[n * n * m];
+  __shared__ double sB[3 * nn];
+  __shared__ double su[nn];
+  __shared__ double sR[n * m];
+  __shared__ double sL[n * n];
+  __shared__ double sred[8];
+  const int t = threadIdx.x;
+  for (int q = t; q < n * m; q += 256) sR[q] = a.ops->R[q];
+  for (int q = t; q < n * n; q += 256) sL[q] = a.ops->L[q];
+  bool go;
+  if (policy == 1) {
+    go = true;
+  } else if (policy == 2) {
+    go = !(forced && forced[e]);
+  } else {
+    for (int c = 0; c < 3; ++c) {
+      __syncthreads();
+      for (int q = t; q < mm; q += 256) sin_[q] = a.fd.Un[((size_t)(3 + c) * a.E + e) * mm + q];
+      __syncthreads();
+      recon3<N>(sR, sin_, s1, s2, sB + c * nn);
+    }
+    const double ratio = block_ratio<N, CURVED>(a, e, sB, su, sred, sL);
+    if (t == 0) a.ratio[e] = ratio;
+    go = !(ratio > a.tci_thr_fd);
+  }
+  if (!go) return;
+  for (int v = 0; v < NV; ++v) {
+    __syncthreads();
+    for (int q = t; q < mm; q += 256) sin_[q] = a.fd.Un[((size_t)v * a.E + e) * mm + q];
+    __syncthreads();
+    recon3<N>(sR, sin_, s1, s2, su);
+    for (int q = t; q < nn; q += 256) a.dg.Un[((size_t)v * a.E + e) * nn + q] = su[q];
+  }
+  if (t == 0) a.rep[e] = 0;
+}
+
+// Stand-alone indicator: DG elements on dg (alpha), FD elements on R(fd) (alpha_fd).
+template <int N, bool CURVED>
+__global__ __launch_bounds__(256) void k_tci(KArgs a, const double* dg, const double* fd, const int32_t* rep,
+                                             uint8_t* troubled, double* ratio) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, mm = Dm::mm;
+  const int e = blockIdx.x;
+  if (!a.live[e]) {
+    if (threadIdx.x == 0) {
+      troubled[e] = 0;
+      if (ratio) ratio[e] = 0.0;
+    }
+    return;
+  }
+  __shared__ double sin_[mm];
+  __shared__ double s1[n * m * m];
+  __shared__ double s2[n * n * m];
+  __shared__ double sB[3 * nn];
+  __shared__ double su[nn];
+  __shared__ double sR[n * m];
+  __shared__ double sL[n * n];
+  __shared__ double sred[8];
+  const int t = threadIdx.x;
+  for (int q = t; q < n * m; q += 256) sR[q] = a.ops->R[q];
+  for (int q = t; q < n * n; q += 256) sL[q] = a.ops->L[q];
+  const bool isfd = rep[e] == 1;
+  for (int c = 0; c < 3; ++c) {
+    __syncthreads();
+    if (isfd) {
+      for (int q = t; q < mm; q += 256) sin_[q] = fd[((size_t)(3 + c) * a.E + e) * mm + q];
+      __syncthreads();
+      recon3<N>(sR, sin_, s1, s2, sB + c * nn);
+    } else {
+      for (int q = t; q < nn; q += 256) sB[c * nn + q] = dg[((size_t)(3 + c) * a.E + e) * nn + q];
+    }
+  }
+  __syncthreads();
+  const double r = block_ratio<N, CURVED>(a, e, sB, su, sred, sL);
+  if (t == 0) {
+    troubled[e] = r > (isfd ? a.tci_thr_fd : a.tci_thr) ? 1 : 0;
+    if (ratio) ratio[e] = r;
+  }
+}
+
+// Compact-layout transfers: to_fd = 1: P (x) P (x) P of [9][count][n^3] into [9][count][m^3];
+// to_fd = 0: R (x) R (x) R the other way.
+template <int N>
+__global__ __launch_bounds__(256) void k_transfer(KArgs a, int to_fd, const double* in, double* out, int count) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, mm = Dm::mm;
+  const int e = blockIdx.x;
+  const int v = blockIdx.y;
+  __shared__ double sin_[mm];
+  __shared__ double s1[m * m * m];
+  __shared__ double s2[m * m * m];
+  __shared__ double sO[n * m];
+  const int t = threadIdx.x;
+  if (to_fd) {
+    for (int q = t; q < m * n; q += 256) sO[q] = a.ops->P[q];
+    for (int q = t; q < nn; q += 256) sin_[q] = in[((size_t)v * count + e) * nn + q];
+    __syncthreads();
+    for (int q = t; q < m * n * n; q += 256) {
+      const int cx = q % m, yz = q / m;
+      double acc = 0.0;
+      for (int z = 0; z < n; ++z) acc += sO[cx * n + z] * sin_[yz * n + z];
+      s1[q] = acc;
+    }
+    __syncthreads();
+    for (int q = t; q < m * m * n; q += 256) {
+      const int cx = q % m, cy = (q / m) % m, z0 = q / (m * m);
+      double acc = 0.0;
+      for (int z = 0; z < n; ++z) acc += sO[cy * n + z] * s1[(z0 * n + z) * m + cx];
+      s2[q] = acc;
+    }
+    __syncthreads();
+    for (int q = t; q < mm; q += 256) {
+      const int cxy = q % (m * m), cz = q / (m * m);
+      double acc = 0.0;
+      for (int z = 0; z < n; ++z) acc += sO[cz * n + z] * s2[z * m * m + cxy];
+      out[((size_t)v * count + e) * mm + q] = acc;
+    }
+  } else {
+    for (int q = t; q < n * m; q += 256) sO[q] = a.ops->R[q];
+    for (int q = t; q < mm; q += 256) sin_[q] = in[((size_t)v * count + e) * mm + q];
+    __syncthreads();
+    recon3<N>(sO, sin_, s1, s2, s1 + n * m * m);
+    for (int q = t; q < nn; q += 256) out[((size_t)v * count + e) * nn + q] = s1[n * m * m + q];
+  }
+}
+
+// Background at FD cells ([26][E][m^3], P along every axis) and at FD faces
+// ([3][10][E][(m+1) m^2], face evaluation along d, P along the others).
+template <int N>
+__global__ __launch_bounds__(256) void k_bg_derive(KArgs a, double* bg_fd, double* bg_face, const double* Q) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, mm = Dm::mm;
+  constexpr int nf = (m + 1) * m * m;
+  const int e = blockIdx.x;
+  const int fld = blockIdx.y;  // 0..25
+  __shared__ double s0[nn];
+  __shared__ double s1[(m + 1) * n * n];
+  __shared__ double s2[(m + 1) * (m + 1) * n];
+  __shared__ double sP[m * n];
+  __shared__ double sQ[(m + 1) * n];
+  const int t = threadIdx.x;
+  for (int q = t; q < m * n; q += 256) sP[q] = a.ops->P[q];
+  for (int q = t; q < (m + 1) * n; q += 256) sQ[q] = Q[q];
+  for (int q = t; q < nn; q += 256) s0[q] = a.bg_dg[((size_t)fld * a.E + e) * nn + q];
+  __syncthreads();
+  const int ndir = (fld < NBGF) ? 4 : 1;  // cells, then faces along x, y, z
+  for (int dir = 0; dir < ndir; ++dir) {
+    // along each axis: Q if the axis is the face direction, else P
+    const int lx = (dir == 1) ? m + 1 : m, ly = (dir == 2) ? m + 1 : m, lz = (dir == 3) ? m + 1 : m;
+    const double* Ox = (dir == 1) ? sQ : sP;
+    const double* Oy = (dir == 2) ? sQ : sP;
+    const double* Oz = (dir == 3) ? sQ : sP;
+    for (int q = t; q < lx * n * n; q += 256) {
+      const int cx = q % lx, yz = q / lx;
+      double acc = 0.0;
+      for (int z = 0; z < n; ++z) acc += Ox[cx * n + z] * s0[yz * n + z];
+      s1[q] = acc;  // [z][y][cx]
+    }
+    __syncthreads();
+    for (int q = t; q < lx * ly * n; q += 256) {
+      const int cx = q % lx, cy = (q / lx) % ly, z0 = q / (lx * ly);
+      double acc = 0.0;
+      for (int z = 0; z < n; ++z) acc += Oy[cy * n + z] * s1[(z0 * n + z) * lx + cx];
+      s2[q] = acc;  // [z][cy][cx]
+    }
+    __syncthreads();
+    const int tot = lx * ly * lz;
+    for (int q = t; q < tot; q += 256) {
+      const int cxy = q % (lx * ly), cz = q / (lx * ly);
+      double acc = 0.0;
+      for (int z = 0; z < n; ++z) acc += Oz[cz * n + z] * s2[z * lx * ly + cxy];
+      if (dir == 0) {
+        bg_fd[((size_t)fld * a.E + e) * mm + q] = acc;
+      } else {
+        // q = cx + lx (cy + ly cz) is exactly the face ordering of direction dir-1
+        bg_face[(((size_t)(dir - 1) * NBGF + fld) * a.E + e) * nf + q] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Per-block maximum of the coordinate light speed over the live DG nodes.
+template <int N>
+__global__ __launch_bounds__(256) void k_lambda_max(KArgs a, double* out) {
+  using Dm = Dims<N>;
+  constexpr int nn = Dm::nn;
+  const int e = blockIdx.x;
+  __shared__ double sm[4];
+  double v = 0.0;
+  if (a.live[e]) {
+    for (int p = threadIdx.x; p < nn; p += 256) {
+      Metric M;
+      load_metric<true>(a.bg_dg, a.E, nn, e, p, M);
+      for (int d = 0; d < 3; ++d) v = fmax(v, char_speed(d, M));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[e] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+}
+
+__global__ void k_begin_substep(KArgs a) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.E) return;
+  a.rep0[e] = a.rep[e];
+  a.troubled[e] = 0;
+}
+
+// ------------------------------------------------------------------ launchers
+#define GRFFE_SWITCH_N(CALL)      \
+  switch (N) {                    \
+    case 3: { constexpr int NN = 3; CALL; } break; \
+    case 4: { constexpr int NN = 4; CALL; } break; \
+    case 5: { constexpr int NN = 5; CALL; } break; \
+    case 6: { constexpr int NN = 6; CALL; } break; \
+    default: { constexpr int NN = 7; CALL; } break; \
+  }
+
+template <int N, bool CURVED>
+static void fd_stage_t(const KArgs& a, int mode, int tro, hipStream_t s) {
+  dim3 grid((Dims<N>::mm + 255) / 256, a.E), block(256);
+  switch (mode) {
+    case MODE_RHS: hipLaunchKernelGGL((k_fd_stage<N, CURVED, MODE_RHS>), grid, block, 0, s, a, tro); break;
+    case MODE_SUB1: hipLaunchKernelGGL((k_fd_stage<N, CURVED, MODE_SUB1>), grid, block, 0, s, a, tro); break;
+    case MODE_SUB2: hipLaunchKernelGGL((k_fd_stage<N, CURVED, MODE_SUB2>), grid, block, 0, s, a, tro); break;
+    default: hipLaunchKernelGGL((k_fd_stage<N, CURVED, MODE_SUB3>), grid, block, 0, s, a, tro); break;
+  }
+}
+
+void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, bool troubled_only, hipStream_t s) {
+  if (curved) GRFFE_SWITCH_N((fd_stage_t<NN, true>(a, mode, troubled_only, s)))
+  else GRFFE_SWITCH_N((fd_stage_t<NN, false>(a, mode, troubled_only, s)))
+}
+
+void launch_fd_trace(const KArgs& a, int N, hipStream_t s) {
+  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_fd_trace<NN>), dim3(a.E), dim3(256), 0, s, a))
+}
+
+void launch_project_troubled(const KArgs& a, int N, bool, int mode, hipStream_t s) {
+  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_project_troubled<NN>), dim3(a.E), dim3(256), 0, s, a, mode))
+}
+
+template <int N, bool CURVED>
+static void fd_flux_t(const KArgs& a, hipStream_t s) {
+  constexpr int m = Dims<N>::m;
+  dim3 grid(((m + 1) * m * m + 127) / 128, 3, a.E), block(128);
+  hipLaunchKernelGGL((k_fd_flux<N, CURVED>), grid, block, 0, s, a);
+}
+
+void launch_fd_flux(const KArgs& a, int N, bool curved, hipStream_t s) {
+  if (curved) GRFFE_SWITCH_N((fd_flux_t<NN, true>(a, s)))
+  else GRFFE_SWITCH_N((fd_flux_t<NN, false>(a, s)))
+}
+
+template <int N, bool CURVED>
+static void fd_update_t(const KArgs& a, int mode, hipStream_t s) {
+  dim3 grid((Dims<N>::mm + 255) / 256, a.E), block(256);
+  switch (mode) {
+    case MODE_RHS: hipLaunchKernelGGL((k_fd_update<N, CURVED, MODE_RHS>), grid, block, 0, s, a); break;
+    case MODE_SUB1: hipLaunchKernelGGL((k_fd_update<N, CURVED, MODE_SUB1>), grid, block, 0, s, a); break;
+    case MODE_SUB2: hipLaunchKernelGGL((k_fd_update<N, CURVED, MODE_SUB2>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_fd_update<N, CURVED, MODE_SUB3>), grid, block, 0, s, a); break;
+  }
+}
+
+void launch_fd_update(const KArgs& a, int N, bool curved, int mode, hipStream_t s) {
+  if (curved) GRFFE_SWITCH_N((fd_update_t<NN, true>(a, mode, s)))
+  else GRFFE_SWITCH_N((fd_update_t<NN, false>(a, mode, s)))
+}
+
+void launch_fd_to_dg_policy(const KArgs& a, int N, bool curved, int policy, const uint8_t* forced, hipStream_t s) {
+  if (curved) GRFFE_SWITCH_N(hipLaunchKernelGGL((k_fd_to_dg<NN, true>), dim3(a.E), dim3(256), 0, s, a, policy, forced))
+  else GRFFE_SWITCH_N(hipLaunchKernelGGL((k_fd_to_dg<NN, false>), dim3(a.E), dim3(256), 0, s, a, policy, forced))
+}
+
+void launch_fd_to_dg(const KArgs& a, int N, bool curved, int init, hipStream_t s) {
+  launch_fd_to_dg_policy(a, N, curved, init, nullptr, s);
+}
+
+void launch_begin_substep(const KArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin_substep, dim3((a.E + 255) / 256), dim3(256), 0, s, a);
+}
+
+void launch_tci(const KArgs& a, int N, bool curved, const double* dg, const double* fd, const int32_t* rep,
+                uint8_t* troubled, double* ratio, hipStream_t s) {
+  if (curved)
+    GRFFE_SWITCH_N(hipLaunchKernelGGL((k_tci<NN, true>), dim3(a.E), dim3(256), 0, s, a, dg, fd, rep, troubled, ratio))
+  else
+    GRFFE_SWITCH_N(hipLaunchKernelGGL((k_tci<NN, false>), dim3(a.E), dim3(256), 0, s, a, dg, fd, rep, troubled, ratio))
+}
+
+void launch_transfer(const KArgs& a, int N, int to_fd, const double* in, double* out, int count, hipStream_t s) {
+  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_transfer<NN>), dim3(count, NV), dim3(256), 0, s, a, to_fd, in, out, count))
+}
+
+void launch_bg_derive_q(const KArgs& a, int N, double* bg_fd, double* bg_face, const double* Q, hipStream_t s) {
+  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_bg_derive<NN>), dim3(a.E, NBG), dim3(256), 0, s, a, bg_fd, bg_face, Q))
+}
+
+void launch_lambda_max(const KArgs& a, int N, double* out, hipStream_t s) {
+  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_lambda_max<NN>), dim3(a.E), dim3(256), 0, s, a, out))
+}
+
+}  // namespace grffe

@@ -1,0 +1,263 @@
+"""Python binding of libgrffe (ctypes, argument marshalling only).
+
+Every computation runs in the HIP library; this module only turns torch
+tensors into device pointers and the current torch stream into a hipStream_t.
+If the library has not been built the import of a domain fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libgrffe.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "grffe.h")
+
+BC_PERIODIC = 0
+BC_NO_INCOMING_POYNTING = 1
+PART_EXPLICIT, PART_STIFF, PART_ALL = 1, 2, 3
+HYBRID_DG_ONLY, HYBRID_ADAPTIVE, HYBRID_FORCED = 0, 1, 2
+
+
+class GrffeError(RuntimeError):
+    pass
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [
+        ("n_elem", ctypes.c_int32 * 3),
+        ("lower", ctypes.c_double * 3),
+        ("upper", ctypes.c_double * 3),
+        ("degree", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 6),
+        ("excised", ctypes.POINTER(ctypes.c_uint8)),
+    ]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("eta", ctypes.c_double),
+        ("kappa_psi", ctypes.c_double),
+        ("kappa_phi", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("stab_c", ctypes.c_double),
+        ("tci_M", ctypes.c_int32),
+        ("tci_mode", ctypes.c_int32),
+        ("tci_alpha", ctypes.c_double),
+        ("tci_alpha_fd", ctypes.c_double),
+        ("filter_a", ctypes.c_double),
+        ("filter_b", ctypes.c_double),
+        ("filter_on", ctypes.c_int32),
+        ("fd_order", ctypes.c_int32),
+        ("weno_eps", ctypes.c_double),
+        ("ff_clamp", ctypes.c_int32),
+        ("ff_margin", ctypes.c_double),
+        ("hybrid", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgrffe.so (raises GrffeError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GrffeError(f"{LIB_PATH} not found: build it with paper_2404_01531_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.grffe_default_params.argtypes = [ctypes.POINTER(Params)]
+    L.grffe_default_params.restype = None
+    L.grffe_init_domain.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
+    L.grffe_destroy.argtypes = [vp]
+    L.grffe_init_from_fd.argtypes = [vp, vp, vp, vp]
+    L.grffe_set_state.argtypes = [vp, vp, vp, vp, vp]
+    L.grffe_get_state.argtypes = [vp, vp, vp, vp, vp]
+    L.grffe_rhs.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
+    L.grffe_step.argtypes = [vp, ctypes.c_int, dbl, vp]
+    L.grffe_tci.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.grffe_project_dg_to_fd.argtypes = [vp, vp, vp, vp, i32, vp]
+    L.grffe_reconstruct_fd_to_dg.argtypes = [vp, vp, vp, vp, i32, vp]
+    L.grffe_get_dt.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.grffe_get_counts.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.grffe_operator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(dbl), ctypes.c_int]
+    L.grffe_last_error.restype = ctypes.c_char_p
+    for name in ("grffe_init_domain", "grffe_destroy", "grffe_init_from_fd", "grffe_set_state", "grffe_get_state",
+                 "grffe_rhs", "grffe_step", "grffe_tci", "grffe_project_dg_to_fd", "grffe_reconstruct_fd_to_dg",
+                 "grffe_get_dt", "grffe_get_counts", "grffe_operator"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def declared_symbols():
+    """Function names declared in include/grffe.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(grffe_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(rc):
+    if rc < 0:
+        raise GrffeError(f"libgrffe error {rc}: {lib().grffe_last_error().decode()}")
+    return rc
+
+
+def default_params(**over):
+    p = Params()
+    lib().grffe_default_params(ctypes.byref(p))
+    for k, v in over.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def operator(degree, which):
+    """Host copy of one of the library's 1D operators (see grffe_operator)."""
+    n = _check(lib().grffe_operator(degree, which, None, 0))
+    buf = (ctypes.c_double * n)()
+    _check(lib().grffe_operator(degree, which, buf, n))
+    return np.frombuffer(buf, dtype=np.float64).copy()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise GrffeError("device tensors are required")
+    if not t.is_contiguous():
+        raise GrffeError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Domain:
+    """A GRFFE domain living on the current HIP device."""
+
+    def __init__(self, n_elem, lower, upper, degree, bc, params=None, bg=None, excised=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise GrffeError("no HIP device available")
+        L = lib()
+        g = Grid()
+        for k in range(3):
+            g.n_elem[k] = int(n_elem[k])
+            g.lower[k] = float(lower[k])
+            g.upper[k] = float(upper[k])
+        g.degree = int(degree)
+        for k in range(6):
+            g.bc[k] = int(bc[k])
+        self._exc = None
+        if excised is not None:
+            self._exc = np.ascontiguousarray(np.asarray(excised, np.uint8))
+            g.excised = self._exc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        p = params if isinstance(params, Params) else default_params(**(params or {}))
+        self.params = p
+        self.N = int(degree)
+        self.n = self.N + 1
+        self.m = 2 * self.N + 1
+        self.E = int(np.prod(n_elem))
+        if bg is not None:
+            bg = bg.contiguous()
+            if tuple(bg.shape) != (26, self.E, self.n ** 3) or bg.dtype != torch.float64:
+                raise GrffeError("bg must be float64 of shape (26, E, (N+1)^3)")
+        h = ctypes.c_void_p()
+        _check(L.grffe_init_domain(ctypes.byref(g), ctypes.byref(p), _ptr(bg), _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().grffe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- shapes
+    def dg_shape(self):
+        return (9, self.E, self.n ** 3)
+
+    def fd_shape(self):
+        return (9, self.E, self.m ** 3)
+
+    def _check_state(self, dg, fd, rep):
+        if dg is not None and tuple(dg.shape) != self.dg_shape():
+            raise GrffeError(f"dg must have shape {self.dg_shape()}")
+        if fd is not None and tuple(fd.shape) != self.fd_shape():
+            raise GrffeError(f"fd must have shape {self.fd_shape()}")
+        if rep is not None and tuple(rep.shape) != (self.E,):
+            raise GrffeError("rep must have shape (E,)")
+
+    # ------------------------------------------------------------------ calls
+    def init_from_fd(self, u_fd, forced=None):
+        self._check_state(None, u_fd, None)
+        _check(lib().grffe_init_from_fd(self._h, _ptr(u_fd), _ptr(forced), _stream()))
+
+    def set_state(self, dg, fd, rep):
+        self._check_state(dg, fd, rep)
+        _check(lib().grffe_set_state(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _stream()))
+
+    def get_state(self):
+        import torch
+        dg = torch.empty(self.dg_shape(), dtype=torch.float64, device="cuda")
+        fd = torch.empty(self.fd_shape(), dtype=torch.float64, device="cuda")
+        rep = torch.empty((self.E,), dtype=torch.int32, device="cuda")
+        _check(lib().grffe_get_state(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _stream()))
+        return dg, fd, rep
+
+    def rhs(self, dg, fd, rep, parts=PART_ALL):
+        import torch
+        self._check_state(dg, fd, rep)
+        ddg = torch.zeros_like(dg)
+        dfd = torch.zeros_like(fd)
+        _check(lib().grffe_rhs(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _ptr(ddg), _ptr(dfd), int(parts), _stream()))
+        return ddg, dfd
+
+    def step(self, n_steps=1, dt=0.0):
+        _check(lib().grffe_step(self._h, int(n_steps), float(dt), _stream()))
+
+    def tci(self, dg, fd, rep):
+        import torch
+        self._check_state(dg, fd, rep)
+        tr = torch.zeros((self.E,), dtype=torch.uint8, device="cuda")
+        ratio = torch.zeros((self.E,), dtype=torch.float64, device="cuda")
+        _check(lib().grffe_tci(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _ptr(tr), _ptr(ratio), _stream()))
+        return tr, ratio
+
+    def project_dg_to_fd(self, u_dg, elems):
+        import torch
+        n = int(elems.numel())
+        out = torch.zeros((9, n, self.m ** 3), dtype=torch.float64, device="cuda")
+        _check(lib().grffe_project_dg_to_fd(self._h, _ptr(u_dg), _ptr(out), _ptr(elems), n, _stream()))
+        return out
+
+    def reconstruct_fd_to_dg(self, u_fd, elems):
+        import torch
+        n = int(elems.numel())
+        out = torch.zeros((9, n, self.n ** 3), dtype=torch.float64, device="cuda")
+        _check(lib().grffe_reconstruct_fd_to_dg(self._h, _ptr(u_fd), _ptr(out), _ptr(elems), n, _stream()))
+        return out
+
+    def dt(self):
+        v = ctypes.c_double()
+        _check(lib().grffe_get_dt(self._h, ctypes.byref(v)))
+        return v.value
+
+    def counts(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().grffe_get_counts(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value

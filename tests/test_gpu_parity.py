@@ -1,0 +1,240 @@
+"""GPU parity: every C-ABI entry point against the FP64 CPU oracle, element by element.
+
+Tolerance (FP64 path): per evolved component v, max |gpu - oracle| <=
+RTOL * max |oracle_v| with RTOL = 1e-12 (the bar the scheme is held to), or
+the stated looser bound where a test names one.  Both sides take every
+discrete decision (indicator flags, implicit-solve branch) in FP64; the
+representation flags must match exactly.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from oracle import rhs as OR
+from oracle import step as OS
+from oracle import tci as OT
+from oracle.domain import DG, FD
+from paper_2404_01531_amd import inputs as I
+
+from helpers import from_dev, group_err, make_pair, node_coords, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _state_arrays(odom, rng, rep, smooth_kind="wave", amp=0.1, noise=1e-3):
+    """Smooth fields plus noise on both grids (DG nodes and FD cells)."""
+    w = dict(n_elem=odom.n_elem, lower=odom.lower, upper=odom.upper, degree=odom.N)
+    x, y, z = node_coords(w)
+    xf, yf, zf = I.fd_points(odom.n_elem, odom.lower, odom.upper, odom.N)
+    out = []
+    for (a, b, c) in ((x, y, z), (xf, yf, zf)):
+        U = I.fast_wave_sine(a, amp) if smooth_kind == "wave" else I.current_sheet(a, 0.2)
+        U[0] += 0.05 * np.sin(1.3 * b + 0.7 * c)
+        U[8] += 0.02 * np.cos(0.9 * a + 1.1 * c)
+        U[6] += 0.01 * np.sin(a + b)
+        U[7] += 0.01 * np.cos(b - c)
+        U += noise * rng.standard_normal(U.shape)
+        out.append(U)
+    dg, fd = out
+    return dg, fd
+
+
+def _curved_state(odom, w, rng):
+    x, y, z = node_coords(w)
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    dg = I.kerr_schild_uniform_field(x, y, z, w["M"], w["spin"], w["B0"])
+    fd = I.kerr_schild_uniform_field(xf, yf, zf, w["M"], w["spin"], w["B0"])
+    dg[6:8] += 1e-3 * rng.standard_normal(dg[6:8].shape)
+    fd[6:8] += 1e-3 * rng.standard_normal(fd[6:8].shape)
+    dg[0:3] += 1e-4 * rng.standard_normal(dg[0:3].shape)
+    fd[0:3] += 1e-4 * rng.standard_normal(fd[0:3].shape)
+    return dg, fd
+
+
+def _compare_rhs(odom, ldom, dg, fd, rep, parts, rtol=RTOL, label=""):
+    torch = _torch()
+    Ldg, Lfd = OR.rhs(odom, dg, fd, rep, parts=parts)
+    rep_t = torch.from_numpy(rep.astype(np.int32)).cuda()
+    gdg, gfd = ldom.rhs(to_dev(dg), to_dev(fd), rep_t, parts=parts)
+    gdg = from_dev(gdg, dg.shape)
+    gfd = from_dev(gfd, fd.shape)
+    act = odom.active
+    dge = np.nonzero(act & (rep == DG))[0]
+    fde = np.nonzero(act & (rep == FD))[0]
+    worst = 0.0
+    for el, G, R in ((dge, gdg, Ldg), (fde, gfd, Lfd)):
+        if el.size == 0:
+            continue
+        e = rel_err(G[:, el], R[:, el])
+        worst = max(worst, float(e.max()))
+        assert np.all(e <= rtol), (label, e)
+    _say(f"rhs parity {label}: worst rel err {worst:.2e}")
+    return worst
+
+
+# ------------------------------------------------------------------ right-hand side
+
+
+@pytest.mark.parametrize("parts", [1, 2, 3])
+def test_rhs_flat_all_dg(parts):
+    _torch()
+    w = I.workload("wave")
+    odom, ldom, _ = make_pair(w)
+    rng = np.random.default_rng(11)
+    rep = np.zeros(odom.E, np.int64)
+    dg, fd = _state_arrays(odom, rng, rep)
+    _compare_rhs(odom, ldom, dg, fd, rep, parts, label=f"wave parts={parts}")
+
+
+@pytest.mark.parametrize("N", [3, 4, 6, 7])
+def test_rhs_flat_ragged_degrees(N):
+    _torch()
+    w = dict(n_elem=(3, 2, 1), lower=(-1.0, -0.5, -0.25), upper=(1.0, 0.75, 0.5), degree=N,
+             bc=(0,) * 6, curved=False)
+    odom, ldom, _ = make_pair(w)
+    rng = np.random.default_rng(20 + N)
+    rep = np.zeros(odom.E, np.int64)
+    rep[[1, 4]] = FD
+    dg, fd = _state_arrays(odom, rng, rep)
+    _compare_rhs(odom, ldom, dg, fd, rep, 3, label=f"ragged N={N}")
+
+
+def test_rhs_flat_mixed_dg_fd():
+    _torch()
+    w = I.workload("sheet", n_elem=(3, 3, 3))
+    odom, ldom, _ = make_pair(w)
+    rng = np.random.default_rng(12)
+    rep = (rng.random(odom.E) < 0.4).astype(np.int64)
+    dg, fd = _state_arrays(odom, rng, rep, smooth_kind="sheet")
+    _compare_rhs(odom, ldom, dg, fd, rep, 3, label="sheet mixed")
+
+
+def test_rhs_fd2_and_no_filter_params():
+    _torch()
+    w = I.workload("sheet", n_elem=(2, 2, 3))
+    odom, ldom, _ = make_pair(w, dict(fd_order=2, eta=10.0))
+    rng = np.random.default_rng(13)
+    rep = np.array([1, 0, 0, 1, 1, 0, 1, 0, 0, 1, 1, 1], np.int64)
+    dg, fd = _state_arrays(odom, rng, rep, smooth_kind="sheet")
+    _compare_rhs(odom, ldom, dg, fd, rep, 3, label="fd2")
+
+
+@pytest.mark.parametrize("N", [5, 3])
+def test_rhs_kerr_schild_excision_boundaries(N):
+    _torch()
+    w = I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3, degree=N)
+    odom, ldom, _ = make_pair(w)
+    assert (~odom.active).sum() == 8
+    rng = np.random.default_rng(14)
+    rep = (rng.random(odom.E) < 0.3).astype(np.int64)
+    rep[~odom.active] = DG
+    dg, fd = _curved_state(odom, w, rng)
+    _compare_rhs(odom, ldom, dg, fd, rep, 3, label=f"kerr-schild N={N}")
+
+
+# ------------------------------------------------------------- indicator / transfers
+
+
+def test_tci_project_reconstruct():
+    torch = _torch()
+    w = I.workload("sheet", n_elem=(4, 3, 2))
+    odom, ldom, _ = make_pair(w)
+    rng = np.random.default_rng(15)
+    rep = (rng.random(odom.E) < 0.5).astype(np.int64)
+    dg, fd = _state_arrays(odom, rng, rep, smooth_kind="sheet", noise=3e-3)
+    tr, ratio = ldom.tci(to_dev(dg), to_dev(fd), torch.from_numpy(rep.astype(np.int32)).cuda())
+    tr, ratio = tr.cpu().numpy(), ratio.cpu().numpy()
+    N, M = odom.N, ops.tci_M(odom.N)
+    r_dg = OT.tci_ratio(dg, odom.geo_dg, N, M)
+    r_fd = OT.tci_ratio(OT.reconstruct_fd_to_dg(fd, N), odom.geo_dg, N, M)
+    ref = np.where(rep == FD, r_fd, r_dg)
+    thr = np.where(rep == FD, OT.tci_threshold(N, M, 5.0), OT.tci_threshold(N, M, 4.0))
+    assert np.abs(ratio - ref).max() <= 1e-12 * max(1e-3, ref.max())
+    assert np.array_equal(tr.astype(bool), ref > thr)
+    elems = torch.arange(odom.E, dtype=torch.int32, device="cuda")
+    pf = from_dev(ldom.project_dg_to_fd(to_dev(dg), elems), fd.shape)
+    assert rel_err(pf, OT.project_dg_to_fd(dg, N)).max() <= RTOL
+    rd = from_dev(ldom.reconstruct_fd_to_dg(to_dev(fd), elems), dg.shape)
+    assert rel_err(rd, OT.reconstruct_fd_to_dg(fd, N)).max() <= RTOL
+
+
+# ------------------------------------------------------------------------ steps
+
+
+def _run_steps(w, nsteps, params=None, forced=None, rtol=1e-12, label=""):
+    torch = _torch()
+    odom, ldom, _ = make_pair(w, params)
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    u_fd = I.initial_data(w, xf, yf, zf)
+    st = OS.initial_state(odom, u_fd, forced)
+    ldom.init_from_fd(to_dev(u_fd), None if forced is None else torch.from_numpy(forced.astype(np.uint8)).cuda())
+    dt = ldom.dt()
+    assert abs(dt - odom.dt()) <= 1e-14 * dt
+    gdg, gfd, grep = ldom.get_state()
+    assert np.array_equal(grep.cpu().numpy(), st.rep), "initial representation differs"
+    worst = 0.0
+    for k in range(nsteps):
+        log = []
+        st = OS.step(odom, st, dt, log)
+        ldom.step(1, dt)
+        gdg, gfd, grep = ldom.get_state()
+        grep = grep.cpu().numpy()
+        assert np.array_equal(grep, st.rep), f"{label}: representation differs after step {k + 1}"
+        gdg = from_dev(gdg, st.dg.shape)
+        gfd = from_dev(gfd, st.fd.shape)
+        act = odom.active
+        for r, G, R in ((DG, gdg, st.dg), (FD, gfd, st.fd)):
+            el = np.nonzero(act & (st.rep == r))[0]
+            if el.size:
+                e = group_err(G[:, el], R[:, el])
+                worst = max(worst, float(e.max()))
+                ec = rel_err(G[:, el], R[:, el])
+                _say(f"  step {k + 1} rep {r}: group err {np.array2string(e, precision=2)} "
+                     f"component err {np.array2string(ec, precision=2)}")
+                assert np.all(e <= rtol), (label, k, r, e.tolist())
+    _say(f"step parity {label}: {nsteps} steps, fd elements {int((st.rep == FD).sum())}, worst rel err {worst:.2e}")
+    return st, ldom
+
+
+def test_step_wave_config_10_steps():
+    w = I.workload("wave")
+    st, _ = _run_steps(w, 10, dict(eta=w["eta"], cfl=w["cfl"]), label="wave 2^3 P5, 10 steps")
+    assert (st.rep == DG).all()
+
+
+def test_step_sheet_adaptive_reduced():
+    w = I.workload("sheet", n_elem=(4, 2, 2))
+    _run_steps(w, 4, dict(eta=w["eta"], cfl=w["cfl"]), label="sheet 4x2x2 adaptive")
+
+
+def test_step_forced_partition_and_clamp():
+    w = I.workload("sheet", n_elem=(3, 2, 2))
+    forced = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 1, 0, 0], bool)
+    _run_steps(w, 3, dict(eta=1e6, hybrid=2, ff_clamp=1), forced=forced, label="forced + clamp")
+
+
+def test_step_dg_only_degree3():
+    w = I.workload("wave", n_elem=(3, 2, 2), degree=3)
+    _run_steps(w, 3, dict(eta=1e6, hybrid=0), label="dg-only P3")
+
+
+def test_step_kerr_schild_small():
+    w = I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3)
+    _run_steps(w, 2, dict(eta=w["eta"], cfl=w["cfl"]), label="kerr-schild 4^3 P5")

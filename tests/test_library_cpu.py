@@ -1,0 +1,50 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load, export every function that include/grffe.h declares,
+and its host-built 1D operators must agree with the oracle's independent ones.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from paper_2404_01531_amd import grffe
+
+pytestmark = pytest.mark.skipif(not os.path.exists(grffe.LIB_PATH), reason="libgrffe.so not built")
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(grffe.LIB_PATH)
+    names = grffe.declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_default_params_match_paper_values():
+    p = grffe.default_params()
+    assert p.eta == 1e6 and p.tci_alpha == 4.0 and p.tci_alpha_fd == 5.0
+    assert p.filter_a == 36.0 and p.filter_b == 50.0 and p.fd_order == 4 and p.weno_eps == 1e-40
+
+
+@pytest.mark.parametrize("N", [3, 4, 5, 6, 7])
+def test_host_operators_match_oracle(N):
+    n, m = N + 1, 2 * N + 1
+    x, w = ops.gll(N)
+    M = ops.tci_M(N)
+    pairs = [
+        (0, x), (1, w), (2, ops.diff_matrix(N).ravel()), (3, ops.filter_matrix(N).ravel()),
+        (4, ops.mode_mask_matrix(N, M, True).ravel()), (5, ops.projection_matrix(N).ravel()),
+        (6, ops.reconstruction_matrix(N).ravel()), (7, ops.face_eval_matrix(N).ravel()),
+    ]
+    for which, ref in pairs:
+        got = grffe.operator(N, which)
+        assert got.shape == ref.shape, which
+        assert np.abs(got - ref).max() < 2e-13 * max(1.0, np.abs(ref).max()), (which, np.abs(got - ref).max())
+
+
+def test_invalid_degree_is_rejected():
+    with pytest.raises(grffe.GrffeError):
+        grffe.operator(2, 0)
