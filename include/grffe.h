@@ -165,6 +165,15 @@ int grffe_get_counts(grffe_domain* dom, int32_t* n_dg, int32_t* n_fd);
  * of doubles written (out may be NULL to query). */
 int grffe_operator(int degree, int which, double* out, int capacity);
 
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * launch of one kernel family: 0 off, 1 fused DG substep, 2 FD face fluxes,
+ * 3 FD update, 4 FD stage values, 5 FD traces, 6 DG ghost slabs,
+ * 7 DG->FD projection of flagged elements, 8 FD->DG check.  grffe_timing_read
+ * synchronises the stream of the last timed launch, returns the summed
+ * duration (ms) and the number of timed launches, and resets the counters. */
+int grffe_timing_enable(grffe_domain* dom, int family);
+int grffe_timing_read(grffe_domain* dom, double* total_ms, int64_t* launches);
+
 const char* grffe_last_error(void);
 
 #ifdef __cplusplus

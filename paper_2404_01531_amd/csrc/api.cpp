@@ -32,6 +32,11 @@ static int fail(int code, const std::string& msg) {
 
 static hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+static int check_dom(grffe_domain* d) {
+  if (!d) return fail(GRFFE_EINVAL, "domain is NULL");
+  return GRFFE_OK;
+}
+
 extern "C" const char* grffe_last_error(void) { return g_err.c_str(); }
 
 extern "C" void grffe_default_params(grffe_params* p) {
@@ -119,6 +124,8 @@ static void free_all(grffe_domain* d) {
 
 extern "C" int grffe_destroy(grffe_domain* d) {
   if (!d) return GRFFE_OK;
+  for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
+  d->ev.clear();
   free_all(d);
   delete d;
   return GRFFE_OK;
@@ -310,11 +317,6 @@ extern "C" int grffe_init_domain(const grffe_grid* g, const grffe_params* p, con
   return GRFFE_OK;
 }
 
-static int check_dom(grffe_domain* d) {
-  if (!d) return fail(GRFFE_EINVAL, "domain is NULL");
-  return GRFFE_OK;
-}
-
 extern "C" int grffe_set_state(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep, void* stream) {
   if (int rc = check_dom(d)) return rc;
   if (!dg || !fd || !rep) return fail(GRFFE_EINVAL, "state pointers must not be NULL");
@@ -352,21 +354,72 @@ extern "C" int grffe_init_from_fd(grffe_domain* d, const double* u_fd, const uin
   return GRFFE_OK;
 }
 
+// Event pair around one launch of the timed kernel family (no-op otherwise).
+struct TimedLaunch {
+  grffe_domain* d;
+  bool on;
+  hipStream_t st;
+  TimedLaunch(grffe_domain* dd, int family, hipStream_t s) : d(dd), on(dd->timed_family == family), st(s) {
+    if (!on) return;
+    if (d->ev_used + 2 > d->ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        on = false;
+        return;
+      }
+      d->ev.push_back(a);
+      d->ev.push_back(b);
+    }
+    (void)hipEventRecord(d->ev[d->ev_used], st);
+  }
+  ~TimedLaunch() {
+    if (!on) return;
+    (void)hipEventRecord(d->ev[d->ev_used + 1], st);
+    d->ev_used += 2;
+    d->ev_stream = st;
+  }
+};
+
 // One substep (or a pure right-hand side evaluation when mode == MODE_RHS).
 static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   const int N = d->N;
   const bool cv = d->curved;
   if (mode != MODE_RHS) launch_begin_substep(a, st);
-  launch_fd_stage(a, N, cv, mode, false, st);
-  launch_fd_trace(a, N, st);
-  launch_dg_substep(a, N, cv, mode, st);
-  launch_dg_slab(a, N, cv, mode, st);
+  { TimedLaunch t(d, 4, st); launch_fd_stage(a, N, cv, mode, false, st); }
+  { TimedLaunch t(d, 5, st); launch_fd_trace(a, N, st); }
+  { TimedLaunch t(d, 1, st); launch_dg_substep(a, N, cv, mode, st); }
+  { TimedLaunch t(d, 6, st); launch_dg_slab(a, N, cv, mode, st); }
   if (mode != MODE_RHS && a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
-    launch_project_troubled(a, N, cv, mode, st);
-    launch_fd_stage(a, N, cv, mode, true, st);
+    { TimedLaunch t(d, 7, st); launch_project_troubled(a, N, cv, mode, st); }
+    { TimedLaunch t(d, 4, st); launch_fd_stage(a, N, cv, mode, true, st); }
   }
-  launch_fd_flux(a, N, cv, st);
-  launch_fd_update(a, N, cv, mode, st);
+  { TimedLaunch t(d, 2, st); launch_fd_flux(a, N, cv, st); }
+  { TimedLaunch t(d, 3, st); launch_fd_update(a, N, cv, mode, st); }
+}
+
+extern "C" int grffe_timing_enable(grffe_domain* d, int family) {
+  if (int rc = check_dom(d)) return rc;
+  if (family < 0 || family > 8) return fail(GRFFE_EINVAL, "unknown kernel family");
+  d->timed_family = family;
+  d->ev_used = 0;
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_timing_read(grffe_domain* d, double* total_ms, int64_t* launches) {
+  if (int rc = check_dom(d)) return rc;
+  double tot = 0.0;
+  if (d->ev_used) {
+    HIPCHK(hipStreamSynchronize(d->ev_stream));
+    for (size_t k = 0; k < d->ev_used; k += 2) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, d->ev[k], d->ev[k + 1]));
+      tot += ms;
+    }
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)(d->ev_used / 2);
+  d->ev_used = 0;
+  return GRFFE_OK;
 }
 
 extern "C" int grffe_rhs(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep, double* ddg,
@@ -398,7 +451,10 @@ extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream)
     run_substep(d, a, MODE_SUB1, st);
     run_substep(d, a, MODE_SUB2, st);
     run_substep(d, a, MODE_SUB3, st);
-    if (a.hybrid == GRFFE_HYBRID_ADAPTIVE) launch_fd_to_dg(a, d->N, d->curved, 0, st);
+    if (a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
+      TimedLaunch t(d, 8, st);
+      launch_fd_to_dg(a, d->N, d->curved, 0, st);
+    }
   }
   HIPCHK(hipGetLastError());
   return GRFFE_OK;
@@ -484,3 +540,4 @@ extern "C" int grffe_operator(int degree, int which, double* out, int capacity) 
   }
   return cnt;
 }
+

@@ -113,6 +113,11 @@ struct grffe_domain {
   double dt_cfl = 0.0;
   double lambda_max = 0.0;
   std::vector<void*> allocs;
+  // kernel timing (one family at a time)
+  int timed_family = 0;
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  size_t ev_used = 0;
+  hipStream_t ev_stream = nullptr;
 };
 
 namespace grffe {

@@ -14,18 +14,18 @@
 
 namespace grffe {
 
-// External (neighbour or boundary) state W = (U, J~) and metric for the face node
+// External (neighbour or boundary) state (Ux, Jx) and metric for the face node
 // (i, j, k) of element e on face f = 2 d + s.
 template <int N, bool CURVED, int MODE>
 __device__ inline void external_state(const KArgs& a, int e, int f, int i, int j, int k, const double* Ui,
-                                      const Metric& Mi, double* Wx, Metric& Mx) {
+                                      const Metric& Mi, double* Ux, double* Jx, Metric& Mx) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn;
   const int d = f >> 1, s = f & 1;
   const int o = a.nbr[e * 6 + f];
   if (o < 0) {
-    boundary_state(d, s ? 1.0 : -1.0, Ui, Mi, Wx);
-    current_total(Wx, Mi, a.eta, Wx + 9);
+    boundary_state(d, s ? 1.0 : -1.0, Ui, Mi, Ux);
+    current_total(Ux, Mi, a.eta, Jx);
     Mx = Mi;
     return;
   }
@@ -36,8 +36,8 @@ __device__ inline void external_state(const KArgs& a, int e, int f, int i, int j
   const int pn = ii + n * (jj + n * kk);
   load_metric<CURVED>(a.bg_dg, a.E, nn, o, pn, Mx);
   if (a.rep0[o] == 0) {
-    stage_input<MODE>(a.dg, a.E, nn, o, pn, Mx, a, Wx);
-    current_total(Wx, Mx, a.eta, Wx + 9);
+    stage_input<MODE>(a.dg, a.E, nn, o, pn, Mx, a, Ux);
+    current_total(Ux, Mx, a.eta, Jx);
   } else {
     // FD neighbour: R-trace on its face facing us (face 2d + 1 - s)
     const int fo = 2 * d + (1 - s);
@@ -48,7 +48,9 @@ __device__ inline void external_state(const KArgs& a, int e, int f, int i, int j
     const size_t base = ((size_t)o * 6 + fo) * (n * n) + t1 + n * t2;
     const size_t stride = (size_t)a.E * 6 * n * n;
 #pragma unroll
-    for (int c = 0; c < NW; ++c) Wx[c] = a.trace[base + c * stride];
+    for (int c = 0; c < NV; ++c) Ux[c] = a.trace[base + c * stride];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Jx[c] = a.trace[base + (NV + c) * stride];
   }
 }
 
@@ -103,10 +105,10 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
     }
     if (act && (id == 0 || id == N)) {
       const int s = (id == N) ? 1 : 0;
-      double Wx[NW], Fx[NV], Fs[NV];
+      double Wx[NV], Jx[3], Fx[NV], Fs[NV];
       Metric Mx;
-      external_state<N, CURVED, MODE>(a, e, 2 * d + s, i, j, k, X, M, Wx, Mx);
-      flux_any(d, Wx, Wx + 9, Mx, Fx);
+      external_state<N, CURVED, MODE>(a, e, 2 * d + s, i, j, k, X, M, Wx, Jx, Mx);
+      flux_any(d, Wx, Jx, Mx, Fx);
       const double lam = CURVED ? fmax(char_speed(d, M), char_speed(d, Mx)) : 1.0;
       if (s == 0) {
         const double wl = sc / a.ops->w[0];

@@ -42,50 +42,51 @@ __global__ __launch_bounds__(256) void k_fd_stage(KArgs a, int troubled_only) {
 }
 
 // ---------------------------------------------------------------- R-traces of FD elements
+// One workgroup per (FD element, transported component): the six face traces of
+// R (x) R (x) R applied to that component.
 template <int N>
 __global__ __launch_bounds__(256) void k_fd_trace(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, m = Dm::m, mm = Dm::mm;
   const int e = blockIdx.x;
+  const int c = blockIdx.y;
   if (!a.live[e] || a.rep0[e] != 1) return;
   __shared__ double sW[mm];
-  __shared__ double s1[m * m];
-  __shared__ double s2[n * m];
+  __shared__ double s1[6 * m * m];
+  __shared__ double s2[6 * n * m];
   __shared__ double sR[n * m];
   const int t = threadIdx.x;
   for (int q = t; q < n * m; q += 256) sR[q] = a.ops->R[q];
+  for (int q = t; q < mm; q += 256) sW[q] = a.w_fd[((size_t)c * a.E + e) * mm + q];
+  __syncthreads();
   const int str[3] = {1, m, m * m};
-  for (int c = 0; c < NW; ++c) {
-    __syncthreads();
-    for (int q = t; q < mm; q += 256) sW[q] = a.w_fd[((size_t)c * a.E + e) * mm + q];
-    __syncthreads();
-    for (int f = 0; f < 6; ++f) {
-      const int d = f >> 1, s = f & 1;
-      const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
-      const int row = s ? N : 0;
-      for (int q = t; q < m * m; q += 256) {
-        const int c1 = q % m, c2 = q / m;
-        double acc = 0.0;
-        for (int z = 0; z < m; ++z) acc += sR[row * m + z] * sW[z * str[d] + c1 * str[t1ax] + c2 * str[t2ax]];
-        s1[q] = acc;  // [c2][c1]
-      }
-      __syncthreads();
-      for (int q = t; q < n * m; q += 256) {
-        const int a1 = q % n, c2 = q / n;
-        double acc = 0.0;
-        for (int z = 0; z < m; ++z) acc += sR[a1 * m + z] * s1[c2 * m + z];
-        s2[q] = acc;  // [c2][a1]
-      }
-      __syncthreads();
-      double* out = a.trace + ((size_t)c * a.E * 6 + (size_t)e * 6 + f) * (n * n);
-      for (int q = t; q < n * n; q += 256) {
-        const int a1 = q % n, a2 = q / n;
-        double acc = 0.0;
-        for (int z = 0; z < m; ++z) acc += sR[a2 * m + z] * s2[z * n + a1];
-        out[q] = acc;  // [a2][a1]
-      }
-      __syncthreads();
-    }
+  // 1) normal direction of every face: R row 0 (lower face) or N (upper face)
+  for (int q = t; q < 6 * m * m; q += 256) {
+    const int f = q / (m * m), r = q % (m * m);
+    const int d = f >> 1, row = (f & 1) ? N : 0;
+    const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+    const int c1 = r % m, c2 = r / m;
+    double acc = 0.0;
+    for (int z = 0; z < m; ++z) acc += sR[row * m + z] * sW[z * str[d] + c1 * str[t1ax] + c2 * str[t2ax]];
+    s1[q] = acc;  // [f][c2][c1]
+  }
+  __syncthreads();
+  // 2) first tangential axis
+  for (int q = t; q < 6 * n * m; q += 256) {
+    const int f = q / (n * m), r = q % (n * m);
+    const int a1 = r % n, c2 = r / n;
+    double acc = 0.0;
+    for (int z = 0; z < m; ++z) acc += sR[a1 * m + z] * s1[(f * m + c2) * m + z];
+    s2[q] = acc;  // [f][c2][a1]
+  }
+  __syncthreads();
+  // 3) second tangential axis, written as [f][a2][a1]
+  for (int q = t; q < 6 * n * n; q += 256) {
+    const int f = q / (n * n), r = q % (n * n);
+    const int a1 = r % n, a2 = r / n;
+    double acc = 0.0;
+    for (int z = 0; z < m; ++z) acc += sR[a2 * m + z] * s2[(f * m + z) * n + a1];
+    a.trace[((size_t)c * a.E * 6 + (size_t)e * 6 + f) * (n * n) + r] = acc;
   }
 }
 
@@ -217,86 +218,147 @@ __device__ inline CellSrc cell_source(const KArgs& a, int e, int d, int c, int t
   return cs;
 }
 
+// One workgroup per (FD element, direction d, row t2 of pencils along d): the
+// m pencils of the row, with three ghost cells at each end, are staged in LDS
+// once; then every (component, face, pencil) is reconstructed, the cell-centred
+// fluxes of the corrector are formed once per cell, and finally every (face,
+// pencil) forms the Rusanov flux and the fourth-order corrected flux.  Only
+// J~^d enters F^d, so ten components (U and J~^d) are reconstructed.
 template <int N, bool CURVED>
-__global__ __launch_bounds__(128) void k_fd_flux(KArgs a) {
+__global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   using Dm = Dims<N>;
   constexpr int m = Dm::m, mm = Dm::mm;
   constexpr int nf = (m + 1) * m * m;
+  constexpr int L = m;      // pencils per workgroup
+  constexpr int C = m + 6;  // cells per pencil including ghosts
+  constexpr int F = m + 1;  // faces per pencil
+  constexpr int NR = NV + 1;  // reconstructed components: U and J~^d
   const int e = blockIdx.z;
   const int d = blockIdx.y;
-  const int tix = blockIdx.x * 128 + threadIdx.x;
-  if (tix >= nf || !fd_active(a, e)) return;
-  int f, t1, t2;
-  if (d == 0) {
-    f = tix % (m + 1);
-    t1 = (tix / (m + 1)) % m;
-    t2 = tix / ((m + 1) * m);
-  } else if (d == 1) {
-    t1 = tix % m;
-    f = (tix / m) % (m + 1);
-    t2 = tix / (m * (m + 1));
-  } else {
-    t1 = tix % m;
-    t2 = (tix / m) % m;
-    f = tix / (m * m);
-  }
-  // cells f-3 .. f+2 along d; face f sits between cells f-1 and f
-  CellSrc cs[6];
+  const int t2 = blockIdx.x;
+  if (!fd_active(a, e)) return;
+  __shared__ double sW[NR * L * C];
+  __shared__ double sLf[NR * L * F];
+  __shared__ double sRf[NR * L * F];
+  __shared__ double sFc[NV * L * (m + 2)];
+  __shared__ double sM[CURVED ? NBGF * L * (m + 2) : 1];
+  const int t = threadIdx.x;
+  // phase 1: stage cells -3 .. m+2 of every pencil (and the metric of cells -1 .. m)
+  for (int q = t; q < L * C; q += 256) {
+    int c, t1;
+    if (d == 0) {
+      c = q % C;
+      t1 = q / C;
+    } else {
+      t1 = q % L;
+      c = q / L;
+    }
+    const CellSrc cs = cell_source<N>(a, e, d, c - 3, t1, t2);
+    double W[NR];
+    Metric Mc;
+    if (cs.ptr) {
 #pragma unroll
-  for (int q = 0; q < 6; ++q) cs[q] = cell_source<N>(a, e, d, f - 3 + q, t1, t2);
-  // boundary state of the outermost own cell, if any of the six cells is a ghost of a domain face
-  double Wb[NW];
-  Metric Mb;
-  bool has_b = false;
+      for (int k = 0; k < NV; ++k) W[k] = cs.ptr[k * cs.stride];
+      W[NV] = cs.ptr[(NV + d) * cs.stride];
+      if (CURVED && c >= 2 && c <= m + 3) load_metric<CURVED>(a.bg_fd, a.E, mm, cs.elem, cs.cell, Mc);
+    } else {
+      double Ui[NV], Ub[NV], J[3];
+      load_metric<CURVED>(a.bg_fd, a.E, mm, e, cs.cell, Mc);
+      load9(a.w_fd, a.E, mm, e, cs.cell, Ui);
+      boundary_state(d, (c >= m + 3) ? 1.0 : -1.0, Ui, Mc, Ub);
+      current_total(Ub, Mc, a.eta, J);
 #pragma unroll
-  for (int q = 0; q < 6; ++q) has_b |= (cs[q].ptr == nullptr);
-  if (has_b) {
-    int qb = 0;
-    for (int q = 0; q < 6; ++q)
-      if (cs[q].ptr == nullptr) qb = q;
-    const int side = (f - 3 + qb) >= m ? 1 : 0;
-    double Ui[NV];
-    load_metric<CURVED>(a.bg_fd, a.E, mm, e, cs[qb].cell, Mb);
-    load9(a.w_fd, a.E, mm, e, cs[qb].cell, Ui);
-    boundary_state(d, side ? 1.0 : -1.0, Ui, Mb, Wb);
-    current_total(Wb, Mb, a.eta, Wb + 9);
+      for (int k = 0; k < NV; ++k) W[k] = Ub[k];
+      W[NV] = (d == 0) ? J[0] : (d == 1 ? J[1] : J[2]);
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) sW[(k * L + t1) * C + c] = W[k];
+    if (CURVED && c >= 2 && c <= m + 3) {
+      const int cm = c - 2;
+      double* o = sM + t1 * (m + 2) + cm;
+      o[0] = Mc.alpha;
+      o[1 * L * (m + 2)] = Mc.beta[0];
+      o[2 * L * (m + 2)] = Mc.beta[1];
+      o[3 * L * (m + 2)] = Mc.beta[2];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) o[(4 + k) * L * (m + 2)] = Mc.g[k];
+    }
   }
-  double WL[NW], WR[NW], W0[NW], W1[NW];
+  __syncthreads();
+  // phase 2: WENO5-Z of every component at every face of every pencil, and the
+  // cell-centred fluxes of cells -1 .. m used by the corrector
   const double eps = a.weno_eps;
-#pragma unroll
-  for (int c = 0; c < NW; ++c) {
-    double v[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) v[q] = cs[q].ptr ? cs[q].ptr[c * cs[q].stride] : Wb[c];
-    WL[c] = weno5z(v[0], v[1], v[2], v[3], v[4], eps);
-    WR[c] = weno5z(v[5], v[4], v[3], v[2], v[1], eps);
-    W0[c] = v[2];
-    W1[c] = v[3];
-  }
-  Metric Mf;
-  load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nf, a.E, nf, e, tix, Mf);
-  double FL[NV], FR[NV];
-  flux_any(d, WL, WL + 9, Mf, FL);
-  flux_any(d, WR, WR + 9, Mf, FR);
-  const double lam = CURVED ? char_speed(d, Mf) : 1.0;
-  double Fh[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) Fh[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (WR[v] - WL[v]);
   if (a.fd_order == 4) {
-    Metric M0, M1;
-    if (cs[2].ptr) load_metric<CURVED>(a.bg_fd, a.E, mm, cs[2].elem, cs[2].cell, M0);
-    else M0 = Mb;
-    if (cs[3].ptr) load_metric<CURVED>(a.bg_fd, a.E, mm, cs[3].elem, cs[3].cell, M1);
-    else M1 = Mb;
-    double F0[NV], F1[NV];
-    flux_any(d, W0, W0 + 9, M0, F0);
-    flux_any(d, W1, W1 + 9, M1, F1);
+    for (int q = t; q < L * (m + 2); q += 256) {
+      const int cm = q % (m + 2), t1 = q / (m + 2);  // cell cm - 1
+      double W[NR];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fh[v] = Fh[v] - (F0[v] - 2.0 * Fh[v] + F1[v]) / 6.0;
+      for (int k = 0; k < NR; ++k) W[k] = sW[(k * L + t1) * C + cm + 2];
+      Metric Mc;
+      if (CURVED) {
+        double fm[10];
+        const double* o = sM + t1 * (m + 2) + cm;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) fm[k] = o[k * L * (m + 2)];
+        metric_from10(fm, Mc);
+      } else {
+        metric_flat(Mc);
+      }
+      double Fc[NV];
+      flux_any_jd(d, W, W[NV], Mc, Fc);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sFc[(v * L + t1) * (m + 2) + cm] = Fc[v];
+    }
   }
-  double* out = a.fhat + ((size_t)d * NV * a.E + e) * nf + tix;
+  for (int q = t; q < NR * L * F; q += 256) {
+    const int f = q % F;
+    const int t1 = (q / F) % L;
+    const int k = q / (F * L);
+    const double* v = sW + (k * L + t1) * C + f;  // cells f-3 .. f+2
+    sLf[q] = weno5z(v[0], v[1], v[2], v[3], v[4], eps);
+    sRf[q] = weno5z(v[5], v[4], v[3], v[2], v[1], eps);
+  }
+  __syncthreads();
+  // phase 3: fluxes
+  for (int q = t; q < L * F; q += 256) {
+    int f, t1;
+    if (d == 0) {
+      f = q % F;
+      t1 = q / F;
+    } else {
+      t1 = q % L;
+      f = q / L;
+    }
+    int tix;
+    if (d == 0) tix = f + (m + 1) * (t1 + m * t2);
+    else if (d == 1) tix = t1 + m * (f + (m + 1) * t2);
+    else tix = t1 + m * (t2 + m * f);
+    double WL[NR], WR[NR];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) out[(size_t)v * a.E * nf] = Fh[v];
+    for (int k = 0; k < NR; ++k) {
+      WL[k] = sLf[(k * L + t1) * F + f];
+      WR[k] = sRf[(k * L + t1) * F + f];
+    }
+    Metric Mf;
+    load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nf, a.E, nf, e, tix, Mf);
+    double Fh[NV], Ft[NV];
+    flux_any_jd(d, WL, WL[NV], Mf, Fh);
+    flux_any_jd(d, WR, WR[NV], Mf, Ft);
+    const double lam = CURVED ? char_speed(d, Mf) : 1.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fh[v] = 0.5 * (Fh[v] + Ft[v]) - 0.5 * lam * (WR[v] - WL[v]);
+    if (a.fd_order == 4) {
+      // cell-centred fluxes of cells f-1 and f
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double* fc = sFc + (v * L + t1) * (m + 2) + f;
+        Fh[v] = Fh[v] - (fc[0] - 2.0 * Fh[v] + fc[1]) / 6.0;
+      }
+    }
+    double* out = a.fhat + ((size_t)d * NV * a.E + e) * nf + tix;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[(size_t)v * a.E * nf] = Fh[v];
+  }
 }
 
 template <int N, bool CURVED, int MODE>
@@ -678,7 +740,7 @@ void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, bool troubled
 }
 
 void launch_fd_trace(const KArgs& a, int N, hipStream_t s) {
-  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_fd_trace<NN>), dim3(a.E), dim3(256), 0, s, a))
+  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_fd_trace<NN>), dim3(a.E, NW), dim3(256), 0, s, a))
 }
 
 void launch_project_troubled(const KArgs& a, int N, bool, int mode, hipStream_t s) {
@@ -688,7 +750,7 @@ void launch_project_troubled(const KArgs& a, int N, bool, int mode, hipStream_t 
 template <int N, bool CURVED>
 static void fd_flux_t(const KArgs& a, hipStream_t s) {
   constexpr int m = Dims<N>::m;
-  dim3 grid(((m + 1) * m * m + 127) / 128, 3, a.E), block(128);
+  dim3 grid(m, 3, a.E), block(256);
   hipLaunchKernelGGL((k_fd_flux<N, CURVED>), grid, block, 0, s, a);
 }
 

@@ -104,9 +104,10 @@ __device__ inline void current_total(const double* U, const Metric& M, double et
   J[2] = Jd[2] + Je[2];
 }
 
-// F^d(U) with a given total densitized current J (Eq. fluxes).
+// F^d(U) with jd = J~^d, the component along d of the total densitized current
+// (Eq. fluxes); only that component enters F^d.
 template <int D>
-__device__ inline void flux_dir(const double* U, const double* J, const Metric& M, double* F) {
+__device__ inline void flux_dir(const double* U, double jd, const Metric& M, double* F) {
   const double* E = U;
   const double* B = U + 3;
   double El[3], Bl[3];
@@ -133,13 +134,21 @@ __device__ inline void flux_dir(const double* U, const double* J, const Metric& 
   }
   F[6] = -bd * psi + a * E[D];
   F[7] = -bd * phi + a * B[D];
-  F[8] = J[D] - bd * U[8];
+  F[8] = jd - bd * U[8];
 }
 
+// F^d with the whole current vector J (its component d is used).
 __device__ inline void flux_any(int d, const double* U, const double* J, const Metric& M, double* F) {
-  if (d == 0) flux_dir<0>(U, J, M, F);
-  else if (d == 1) flux_dir<1>(U, J, M, F);
-  else flux_dir<2>(U, J, M, F);
+  if (d == 0) flux_dir<0>(U, J[0], M, F);
+  else if (d == 1) flux_dir<1>(U, J[1], M, F);
+  else flux_dir<2>(U, J[2], M, F);
+}
+
+// F^d with the scalar jd = J~^d.
+__device__ inline void flux_any_jd(int d, const double* U, double jd, const Metric& M, double* F) {
+  if (d == 0) flux_dir<0>(U, jd, M, F);
+  else if (d == 1) flux_dir<1>(U, jd, M, F);
+  else flux_dir<2>(U, jd, M, F);
 }
 
 // Background derivative fields at a point (curved only).

@@ -20,6 +20,8 @@ BC_PERIODIC = 0
 BC_NO_INCOMING_POYNTING = 1
 PART_EXPLICIT, PART_STIFF, PART_ALL = 1, 2, 3
 HYBRID_DG_ONLY, HYBRID_ADAPTIVE, HYBRID_FORCED = 0, 1, 2
+KERNEL_FAMILIES = {"dg_substep": 1, "fd_flux": 2, "fd_update": 3, "fd_stage": 4, "fd_trace": 5,
+                   "dg_slab": 6, "project": 7, "fd_to_dg": 8}
 
 
 class GrffeError(RuntimeError):
@@ -87,10 +89,13 @@ def lib():
     L.grffe_get_dt.argtypes = [vp, ctypes.POINTER(dbl)]
     L.grffe_get_counts.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.grffe_operator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(dbl), ctypes.c_int]
+    L.grffe_timing_enable.argtypes = [vp, ctypes.c_int]
+    L.grffe_timing_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
     L.grffe_last_error.restype = ctypes.c_char_p
     for name in ("grffe_init_domain", "grffe_destroy", "grffe_init_from_fd", "grffe_set_state", "grffe_get_state",
                  "grffe_rhs", "grffe_step", "grffe_tci", "grffe_project_dg_to_fd", "grffe_reconstruct_fd_to_dg",
-                 "grffe_get_dt", "grffe_get_counts", "grffe_operator"):
+                 "grffe_get_dt", "grffe_get_counts", "grffe_operator", "grffe_timing_enable",
+                 "grffe_timing_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -256,6 +261,15 @@ class Domain:
         v = ctypes.c_double()
         _check(lib().grffe_get_dt(self._h, ctypes.byref(v)))
         return v.value
+
+    def timing_enable(self, family):
+        """Time every launch of one kernel family with HIP events (see grffe_timing_enable)."""
+        _check(lib().grffe_timing_enable(self._h, int(family)))
+
+    def timing_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().grffe_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def counts(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()
