@@ -27,7 +27,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_VALU_PEAK_TFLOPS = 78.6
+# FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP64_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+# Algorithmic FP64 flops per subcell face per direction of the FD flux kernel:
+# WENO5-Z of ten components (U and J~^d) on both sides, 20 x 78 = 1560; the two
+# face fluxes F(U_L), F(U_R), 2 x 75 = 150; Rusanov 36; one cell-centred flux
+# and the fourth-order corrector 75 + 36 = 111; flux difference 18.
+FD_FLOP_PER_FACE = 1560 + 150 + 36 + 111 + 18
 
 # Algorithmic bytes per DG node per substep moved by the register scheme:
 # substep 1 reads U^n, writes U_3 and the accumulator (216 B); substep 2 reads
@@ -43,12 +50,29 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sheet")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample-steps", type=int, default=5)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy (counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain copy kernel of known size: 512 MiB read, 512 MiB written."""
+    import torch
+    n = 512 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8}))
 
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
                                    "rerun with --gpus 1"}))
@@ -78,8 +102,9 @@ def main():
     n_dg0, n_fd0 = dom.counts()
     print(f"# warm: {n_dg0} DG + {n_fd0} FD elements, dt {dt:.6e}", file=sys.stderr, flush=True)
 
-    # timed region: the whole step; the dominant kernel is timed with HIP events
-    dom.timing_enable(grffe.KERNEL_FAMILIES["dg_substep"])
+    # timed region: the whole step; the dominant kernel (FD face fluxes) is timed
+    # with HIP events recorded on its launch stream around every launch
+    dom.timing_enable(grffe.KERNEL_FAMILIES["fd_flux"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dom.step(args.steps, dt)
@@ -92,13 +117,21 @@ def main():
     pts = 0.5 * ((n_dg0 + n_dg1) * n3 + (n_fd0 + n_fd1) * m3)
     updates = pts * 3 * args.steps
     value = updates / secs
-    # roofline: fused DG substep kernel, HBM bound; algorithmic bytes per launch
-    n_dg = 0.5 * (n_dg0 + n_dg1)
-    bytes_per_launch = n_dg * n3 * (sum(DG_BYTES_PER_NODE.values()) / 3.0)
+    m = 2 * N + 1
+    n_fd = 0.5 * (n_fd0 + n_fd1)
+    flop_per_launch = n_fd * 3 * (m + 1) * m * m * FD_FLOP_PER_FACE
     avg_s = (k_ms / 1e3) / max(k_launches, 1)
-    achieved = bytes_per_launch / avg_s / 1e9
-    print(f"# {args.steps} steps in {secs:.4f} s; dg_substep {k_launches} launches, mean {avg_s * 1e6:.2f} us",
+    achieved = flop_per_launch / avg_s / 1e12
+    print(f"# {args.steps} steps in {secs:.4f} s; fd_flux {k_launches} launches, mean {avg_s * 1e6:.2f} us",
           file=sys.stderr, flush=True)
+    # secondary: the fused DG substep kernel (HBM bound) timed over a short extra run
+    dom.timing_enable(grffe.KERNEL_FAMILIES["dg_substep"])
+    dom.step(max(1, args.steps // 10), dt)
+    dg_ms, dg_launches = dom.timing_read()
+    dom.timing_enable(0)
+    n_dg = 0.5 * (n_dg0 + n_dg1)
+    dg_bytes = n_dg * n3 * (sum(DG_BYTES_PER_NODE.values()) / 3.0)
+    dg_avg = (dg_ms / 1e3) / max(dg_launches, 1)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -121,10 +154,15 @@ def main():
                                "eta 1e6, CFL 0.25, adaptive DG-FD, seed 1002",
                    "elements": int(dom.E), "fd_elements": [int(n_fd0), int(n_fd1)],
                    "points_per_substep": pts, "dt": dt},
-        "roofline": {"kernel": "k_dg_substep (fused DG substep)", "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "mean_launch_us": avg_s * 1e6, "launches": int(k_launches)},
+        "roofline": {"kernel": "k_fd_flux (FD subcell WENO5-Z face fluxes)", "bound": "alu",
+                     "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "mean_launch_us": avg_s * 1e6, "launches": int(k_launches),
+                     "flop_per_launch": flop_per_launch},
+        "roofline_dg": {"kernel": "k_dg_substep (fused DG substep)", "bound": "hbm",
+                        "achieved": dg_bytes / dg_avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": dg_bytes / dg_avg / 1e9 / HBM_PEAK_GBS, "mean_launch_us": dg_avg * 1e6,
+                        "bytes_per_launch": dg_bytes},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -260,7 +260,7 @@ extern "C" int grffe_init_domain(const grffe_grid* g, const grffe_params* p, con
   ALLOC(w_fd, sizeof(double) * NW * E * mm);
   ALLOC(trace, sizeof(double) * NW * E * 6 * n * n);
   ALLOC(slab, sizeof(double) * NW * E * 6 * 3 * m * m);
-  ALLOC(fhat, sizeof(double) * 3 * NV * E * nf);
+  ALLOC(fhat, sizeof(double) * 3 * NV * E * mm);
   double* qdev = nullptr;
   if (d->curved) {
     ALLOC(bg_dg, sizeof(double) * NBG * E * nn);
@@ -354,7 +354,15 @@ extern "C" int grffe_init_from_fd(grffe_domain* d, const double* u_fd, const uin
   return GRFFE_OK;
 }
 
-// Event pair around one launch of the timed kernel family (no-op otherwise).
+namespace grffe {
+LaunchEvents& armed_launch_events() {
+  static thread_local LaunchEvents le;
+  return le;
+}
+}  // namespace grffe
+
+// Arms an event pair for the one kernel launched in its scope when its family is
+// the timed one; the launch attaches the events to the kernel's own dispatch.
 struct TimedLaunch {
   grffe_domain* d;
   bool on;
@@ -370,11 +378,13 @@ struct TimedLaunch {
       d->ev.push_back(a);
       d->ev.push_back(b);
     }
-    (void)hipEventRecord(d->ev[d->ev_used], st);
+    armed_launch_events().start = d->ev[d->ev_used];
+    armed_launch_events().stop = d->ev[d->ev_used + 1];
   }
   ~TimedLaunch() {
     if (!on) return;
-    (void)hipEventRecord(d->ev[d->ev_used + 1], st);
+    armed_launch_events().start = nullptr;
+    armed_launch_events().stop = nullptr;
     d->ev_used += 2;
     d->ev_stream = st;
   }
@@ -384,14 +394,12 @@ struct TimedLaunch {
 static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   const int N = d->N;
   const bool cv = d->curved;
-  if (mode != MODE_RHS) launch_begin_substep(a, st);
-  { TimedLaunch t(d, 4, st); launch_fd_stage(a, N, cv, mode, false, st); }
+  { TimedLaunch t(d, 4, st); launch_fd_stage(a, N, cv, mode, mode != MODE_RHS, st); }
   { TimedLaunch t(d, 5, st); launch_fd_trace(a, N, st); }
   { TimedLaunch t(d, 1, st); launch_dg_substep(a, N, cv, mode, st); }
   { TimedLaunch t(d, 6, st); launch_dg_slab(a, N, cv, mode, st); }
   if (mode != MODE_RHS && a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
     { TimedLaunch t(d, 7, st); launch_project_troubled(a, N, cv, mode, st); }
-    { TimedLaunch t(d, 4, st); launch_fd_stage(a, N, cv, mode, true, st); }
   }
   { TimedLaunch t(d, 2, st); launch_fd_flux(a, N, cv, st); }
   { TimedLaunch t(d, 3, st); launch_fd_update(a, N, cv, mode, st); }

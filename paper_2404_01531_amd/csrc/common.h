@@ -1,9 +1,25 @@
 // Device helpers shared by the kernel translation units.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "grffe_internal.h"
 #include "physics.h"
 
 namespace grffe {
+
+// Launch a kernel; if timing events are armed, they are attached to the kernel's own
+// dispatch (hipExtLaunchKernelGGL), so they bracket exactly that kernel.
+template <typename... P, typename... A>
+inline void launch_kernel(void (*kernel)(P...), dim3 grid, dim3 block, hipStream_t s, A... args) {
+  LaunchEvents& le = armed_launch_events();
+  if (le.start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, le.start, le.stop, 0, args...);
+    le.start = nullptr;
+    le.stop = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+  }
+}
 
 template <int N>
 struct Dims {
@@ -114,7 +130,8 @@ __device__ inline void stage_update(const Regs& r, int E, int P, int e, int p, c
   load9(r.Un, E, P, e, p, Un);
   const double dt = a.dt;
   if (MODE == MODE_SUB1) {
-    derived_stages(Un, M, a, U2, S1, S2);
+    // the substep input X is U_2 itself
+    source_stiff(X, M, a.eta, a.kpsi, a.kphi, S2);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       Y[v] = Un[v] + dt * L[v] + dt * (1.0 - IMEX_A) * S2[v];

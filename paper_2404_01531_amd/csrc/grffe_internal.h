@@ -71,7 +71,7 @@ struct KArgs {
   double* w_fd;            // [12][E][m^3]  FD stage values + J~
   double* trace;           // [12][E][6][n^2]  R-traces of FD elements at their faces
   double* slab;            // [12][E][6][3 m^2]  P-projection of DG stage values next to each face
-  double* fhat;            // [3][9][E][(m+1) m^2] FD numerical fluxes
+  double* fhat;            // [3][9][E][m^3] FD flux differences per direction
   // RHS mode outputs
   double* out_dg;
   double* out_fd;
@@ -124,11 +124,18 @@ namespace grffe {
 
 KArgs make_args(grffe_domain* d);
 
+// Event pair armed for the next kernel launch on this host thread (kernel timing).
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+LaunchEvents& armed_launch_events();
+
 // launchers (kernels_dg.hip)
 void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_dg_slab(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 // launchers (kernels_fd.hip)
-void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, bool troubled_only, hipStream_t s);
+void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, bool begin, hipStream_t s);
 void launch_fd_trace(const KArgs& a, int N, hipStream_t s);
 void launch_project_troubled(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_fd_flux(const KArgs& a, int N, bool curved, hipStream_t s);

@@ -198,6 +198,8 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
 
 // P-projection (3 subcell layers next to each face) of the DG stage input of
 // elements whose neighbour across that face is on FD or has just been flagged.
+// The twelve transported components (U, J~) are projected together, one face at
+// a time, in three separable stages.
 template <int N, bool CURVED, int MODE>
 __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
   using Dm = Dims<N>;
@@ -211,8 +213,8 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
   }
   if (!need) return;
   __shared__ double sW[NW * nn];
-  __shared__ double sA[3 * m * n * n];
-  __shared__ double sB[3 * m * m * n];
+  __shared__ double sA[NW * 3 * n * n];
+  __shared__ double sB[NW * 3 * m * n];
   __shared__ double sP[m * n];
   const int t = threadIdx.x;
   for (int q = t; q < m * n; q += TPB) sP[q] = a.ops->P[q];
@@ -227,57 +229,52 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
     for (int c = 0; c < 3; ++c) sW[(9 + c) * nn + t] = J[c];
   }
   __syncthreads();
-  const size_t stride = (size_t)a.E * 6 * 3 * m * m;
+  const int str[3] = {1, n, n * n};
   for (int f = 0; f < 6; ++f) {
     if (!(need & (1 << f))) continue;
     const int d = f >> 1, s = f & 1;
     // axes: normal d, tangential t1 < t2
     const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
-    const int str[3] = {1, n, n * n};
-    for (int c = 0; c < NW; ++c) {
+    // 1) normal direction: layers l = 0..2, cell index m-1-l (upper face) or l (lower face)
+    for (int q = t; q < NW * 3 * n * n; q += TPB) {
+      const int c = q / (3 * n * n), r0 = q % (3 * n * n);
+      const int l = r0 / (n * n), r = r0 % (n * n);
+      const int a1 = r % n, a2 = r / n;
+      const int cell = s ? (m - 1 - l) : l;
       const double* W = sW + c * nn;
-      // 1) normal direction: layers l = 0..2, cell index m-1-l (upper face) or l (lower face)
-      for (int q = t; q < 3 * n * n; q += TPB) {
-        const int l = q / (n * n), r = q % (n * n);
-        const int a1 = r % n, a2 = r / n;
-        const int cell = s ? (m - 1 - l) : l;
-        double acc = 0.0;
-        for (int z = 0; z < n; ++z) acc += sP[cell * n + z] * W[z * str[d] + a1 * str[t1ax] + a2 * str[t2ax]];
-        sA[q] = acc;  // [l][a2][a1]
-      }
-      __syncthreads();
-      // 2) first tangential axis: a1 (n) -> c1 (m)
-      for (int q = t; q < 3 * m * n; q += TPB) {
-        const int l = q / (m * n), r = q % (m * n);
-        const int c1 = r % m, a2 = r / m;
-        double acc = 0.0;
-        for (int z = 0; z < n; ++z) acc += sP[c1 * n + z] * sA[(l * n + a2) * n + z];
-        sB[q] = acc;  // [l][a2][c1]
-      }
-      __syncthreads();
-      // 3) second tangential axis: a2 (n) -> c2 (m), write [l][c2][c1]
-      double* out = a.slab + ((size_t)c * a.E * 6 + (size_t)e * 6 + f) * (3 * m * m);
-      for (int q = t; q < 3 * m * m; q += TPB) {
-        const int l = q / (m * m), r = q % (m * m);
-        const int c1 = r % m, c2 = r / m;
-        double acc = 0.0;
-        for (int z = 0; z < n; ++z) acc += sP[c2 * n + z] * sB[(l * n + z) * m + c1];
-        out[q] = acc;
-      }
-      __syncthreads();
+      double acc = 0.0;
+      for (int z = 0; z < n; ++z) acc += sP[cell * n + z] * W[z * str[d] + a1 * str[t1ax] + a2 * str[t2ax]];
+      sA[q] = acc;  // [c][l][a2][a1]
     }
+    __syncthreads();
+    // 2) first tangential axis: a1 (n) -> c1 (m)
+    for (int q = t; q < NW * 3 * m * n; q += TPB) {
+      const int c1 = q % m, rest = q / m;  // rest = (c*3 + l)*n + a2
+      double acc = 0.0;
+      for (int z = 0; z < n; ++z) acc += sP[c1 * n + z] * sA[rest * n + z];
+      sB[q] = acc;  // [c][l][a2][c1]
+    }
+    __syncthreads();
+    // 3) second tangential axis: a2 (n) -> c2 (m), written as [c][l][c2][c1]
+    for (int q = t; q < NW * 3 * m * m; q += TPB) {
+      const int c1 = q % m, c2 = (q / m) % m, cl = q / (m * m);  // cl = c*3 + l
+      const int c = cl / 3, l = cl % 3;
+      double acc = 0.0;
+      for (int z = 0; z < n; ++z) acc += sP[c2 * n + z] * sB[(cl * n + z) * m + c1];
+      a.slab[((size_t)c * a.E * 6 + (size_t)e * 6 + f) * (3 * m * m) + (l * m + c2) * m + c1] = acc;
+    }
+    __syncthreads();
   }
-  (void)stride;
 }
 
 template <int N, bool CURVED>
 static void launch_dg_substep_t(const KArgs& a, int mode, hipStream_t s) {
   dim3 grid(a.E), block(Dims<N>::tpb);
   switch (mode) {
-    case MODE_RHS: hipLaunchKernelGGL((k_dg_substep<N, CURVED, MODE_RHS>), grid, block, 0, s, a); break;
-    case MODE_SUB1: hipLaunchKernelGGL((k_dg_substep<N, CURVED, MODE_SUB1>), grid, block, 0, s, a); break;
-    case MODE_SUB2: hipLaunchKernelGGL((k_dg_substep<N, CURVED, MODE_SUB2>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_dg_substep<N, CURVED, MODE_SUB3>), grid, block, 0, s, a); break;
+    case MODE_RHS: launch_kernel(k_dg_substep<N, CURVED, MODE_RHS>, grid, block, s, a); break;
+    case MODE_SUB1: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB1>, grid, block, s, a); break;
+    case MODE_SUB2: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB2>, grid, block, s, a); break;
+    default: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB3>, grid, block, s, a); break;
   }
 }
 
@@ -285,10 +282,10 @@ template <int N, bool CURVED>
 static void launch_dg_slab_t(const KArgs& a, int mode, hipStream_t s) {
   dim3 grid(a.E), block(Dims<N>::tpb);
   switch (mode) {
-    case MODE_RHS: hipLaunchKernelGGL((k_dg_slab<N, CURVED, MODE_RHS>), grid, block, 0, s, a); break;
-    case MODE_SUB1: hipLaunchKernelGGL((k_dg_slab<N, CURVED, MODE_SUB1>), grid, block, 0, s, a); break;
-    case MODE_SUB2: hipLaunchKernelGGL((k_dg_slab<N, CURVED, MODE_SUB2>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_dg_slab<N, CURVED, MODE_SUB3>), grid, block, 0, s, a); break;
+    case MODE_RHS: launch_kernel(k_dg_slab<N, CURVED, MODE_RHS>, grid, block, s, a); break;
+    case MODE_SUB1: launch_kernel(k_dg_slab<N, CURVED, MODE_SUB1>, grid, block, s, a); break;
+    case MODE_SUB2: launch_kernel(k_dg_slab<N, CURVED, MODE_SUB2>, grid, block, s, a); break;
+    default: launch_kernel(k_dg_slab<N, CURVED, MODE_SUB3>, grid, block, s, a); break;
   }
 }
 

@@ -20,14 +20,22 @@ __device__ inline bool fd_active(const KArgs& a, int e) {
 }
 
 // ---------------------------------------------------------------- FD stage values + J~
+// With `begin` set this launch also opens the substep: the representation at
+// the substep start (rep0) is taken from rep and the flags are cleared.  Only the
+// element's own entries are touched, and no other element's rep0 is read here.
 template <int N, bool CURVED, int MODE>
-__global__ __launch_bounds__(256) void k_fd_stage(KArgs a, int troubled_only) {
+__global__ __launch_bounds__(256) void k_fd_stage(KArgs a, int begin) {
   using Dm = Dims<N>;
   constexpr int mm = Dm::mm;
   const int e = blockIdx.y;
   const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= mm || !a.live[e]) return;
-  if (troubled_only ? !a.troubled[e] : (a.rep0[e] != 1)) return;
+  if (!a.live[e]) return;
+  const int r = begin ? a.rep[e] : a.rep0[e];
+  if (begin && blockIdx.x == 0 && threadIdx.x == 0) {
+    a.rep0[e] = r;
+    a.troubled[e] = 0;
+  }
+  if (p >= mm || r != 1) return;
   Metric M;
   load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
   double X[NV], J[3];
@@ -51,6 +59,12 @@ __global__ __launch_bounds__(256) void k_fd_trace(KArgs a) {
   const int e = blockIdx.x;
   const int c = blockIdx.y;
   if (!a.live[e] || a.rep0[e] != 1) return;
+  int need = 0;
+  for (int f = 0; f < 6; ++f) {
+    const int o = a.nbr[e * 6 + f];
+    if (o >= 0 && a.rep0[o] == 0) need |= 1 << f;
+  }
+  if (!need) return;
   __shared__ double sW[mm];
   __shared__ double s1[6 * m * m];
   __shared__ double s2[6 * n * m];
@@ -63,6 +77,7 @@ __global__ __launch_bounds__(256) void k_fd_trace(KArgs a) {
   // 1) normal direction of every face: R row 0 (lower face) or N (upper face)
   for (int q = t; q < 6 * m * m; q += 256) {
     const int f = q / (m * m), r = q % (m * m);
+    if (!(need & (1 << f))) continue;
     const int d = f >> 1, row = (f & 1) ? N : 0;
     const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
     const int c1 = r % m, c2 = r / m;
@@ -74,6 +89,7 @@ __global__ __launch_bounds__(256) void k_fd_trace(KArgs a) {
   // 2) first tangential axis
   for (int q = t; q < 6 * n * m; q += 256) {
     const int f = q / (n * m), r = q % (n * m);
+    if (!(need & (1 << f))) continue;
     const int a1 = r % n, c2 = r / n;
     double acc = 0.0;
     for (int z = 0; z < m; ++z) acc += sR[a1 * m + z] * s1[(f * m + c2) * m + z];
@@ -83,6 +99,7 @@ __global__ __launch_bounds__(256) void k_fd_trace(KArgs a) {
   // 3) second tangential axis, written as [f][a2][a1]
   for (int q = t; q < 6 * n * n; q += 256) {
     const int f = q / (n * n), r = q % (n * n);
+    if (!(need & (1 << f))) continue;
     const int a1 = r % n, a2 = r / n;
     double acc = 0.0;
     for (int z = 0; z < m; ++z) acc += sR[a2 * m + z] * s2[(f * m + z) * n + a1];
@@ -91,9 +108,10 @@ __global__ __launch_bounds__(256) void k_fd_trace(KArgs a) {
 }
 
 // ---------------------------------------------------------------- DG -> FD of flagged elements
-// P (x) P (x) P of the live registers of every element flagged in this substep.
-template <int N>
-__global__ __launch_bounds__(256) void k_project_troubled(KArgs a, int mode) {
+// P (x) P (x) P of the live registers of every element flagged in this substep,
+// followed by the FD stage values (U and J~) of its subcells.
+template <int N, bool CURVED, int MODE>
+__global__ __launch_bounds__(256) void k_project_troubled(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, mm = Dm::mm;
   const int e = blockIdx.x;
@@ -109,15 +127,15 @@ __global__ __launch_bounds__(256) void k_project_troubled(KArgs a, int mode) {
   int nreg = 0;
   src[nreg] = a.dg.Un;
   dst[nreg++] = a.fd.Un;
-  if (mode == MODE_SUB2) {
+  if (MODE == MODE_SUB2) {
     src[nreg] = a.dg.X0;
     dst[nreg++] = a.fd.X0;
   }
-  if (mode == MODE_SUB3) {
+  if (MODE == MODE_SUB3) {
     src[nreg] = a.dg.X1;
     dst[nreg++] = a.fd.X1;
   }
-  if (mode == MODE_SUB2 || mode == MODE_SUB3) {
+  if (MODE == MODE_SUB2 || MODE == MODE_SUB3) {
     src[nreg] = a.dg.A;
     dst[nreg++] = a.fd.A;
   }
@@ -148,11 +166,30 @@ __global__ __launch_bounds__(256) void k_project_troubled(KArgs a, int mode) {
         out[q] = acc;
       }
     }
+  // the block's own global writes are visible to it after the barrier
+  __syncthreads();
+  for (int p = t; p < mm; p += 256) {
+    Metric M;
+    load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
+    double X[NV], J[3];
+    stage_input<MODE>(a.fd, a.E, mm, e, p, M, a, X);
+    current_total(X, M, a.eta, J);
+    const size_t st = (size_t)a.E * mm;
+    double* w = a.w_fd + (size_t)e * mm + p;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v * st] = X[v];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[(9 + c) * st] = J[c];
+  }
 }
 
 // ---------------------------------------------------------------- WENO5-Z on point values
 // Candidates are the quadratic Lagrange interpolants of the point values at the
-// face; optimal weights (1, 10, 5)/16; Z weights with tau5 = |b0 - b2|, q = 2.
+// face; optimal weights (1, 10, 5)/16; Z weights alpha_k = d_k (1 + (tau5 /
+// (beta_k + eps))^2) with tau5 = |beta_0 - beta_2| (exponent q = 2).  With
+// b_k = beta_k + eps the normalised combination sum alpha_k q_k / sum alpha_k is
+// evaluated after multiplying numerator and denominator by b_0^2 b_1^2 b_2^2,
+// which leaves a single division.
 __device__ inline double weno5z(double vm2, double vm1, double v0, double vp1, double vp2, double eps) {
   const double q0 = (3.0 * vm2 - 10.0 * vm1 + 15.0 * v0) * 0.125;
   const double q1 = (-vm1 + 6.0 * v0 + 3.0 * vp1) * 0.125;
@@ -160,15 +197,56 @@ __device__ inline double weno5z(double vm2, double vm1, double v0, double vp1, d
   const double d0 = vm2 - 2.0 * vm1 + v0, e0 = vm2 - 4.0 * vm1 + 3.0 * v0;
   const double d1 = vm1 - 2.0 * v0 + vp1, e1 = vm1 - vp1;
   const double d2 = v0 - 2.0 * vp1 + vp2, e2 = 3.0 * v0 - 4.0 * vp1 + vp2;
-  const double b0 = (13.0 / 12.0) * d0 * d0 + 0.25 * e0 * e0;
-  const double b1 = (13.0 / 12.0) * d1 * d1 + 0.25 * e1 * e1;
-  const double b2 = (13.0 / 12.0) * d2 * d2 + 0.25 * e2 * e2;
+  const double b0 = (13.0 / 12.0) * d0 * d0 + 0.25 * e0 * e0 + eps;
+  const double b1 = (13.0 / 12.0) * d1 * d1 + 0.25 * e1 * e1 + eps;
+  const double b2 = (13.0 / 12.0) * d2 * d2 + 0.25 * e2 * e2 + eps;
   const double tau = fabs(b0 - b2);
-  const double r0 = tau / (b0 + eps), r1 = tau / (b1 + eps), r2 = tau / (b2 + eps);
-  const double a0 = (1.0 / 16.0) * (1.0 + r0 * r0);
-  const double a1 = (10.0 / 16.0) * (1.0 + r1 * r1);
-  const double a2 = (5.0 / 16.0) * (1.0 + r2 * r2);
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+  const double t2 = tau * tau;
+  const double s0 = b0 * b0, s1 = b1 * b1, s2 = b2 * b2;
+  const double w0 = (1.0 / 16.0) * (s0 + t2) * (s1 * s2);
+  const double w1 = (10.0 / 16.0) * (s1 + t2) * (s0 * s2);
+  const double w2 = (5.0 / 16.0) * (s2 + t2) * (s0 * s1);
+  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+// Both WENO5-Z reconstructions whose target cell is c, from the five point
+// values v[0..4] = cells c-2 .. c+2: `left` is the state on the left of face
+// c+1/2, `right` the state on the right of face c-1/2.  The two share the
+// smoothness indicators of the target cell (the mirrored reconstruction sees
+// beta_0 and beta_2 swapped) and tau5 = |beta_0 - beta_2|.  Z weights with
+// exponent 2, optimal weights (1, 10, 5)/16, candidates are quadratic Lagrange
+// interpolants of point values; the normalisation is done with one division
+// per state after multiplying by b_0^2 b_1^2 b_2^2, b_k = beta_k + eps.
+__device__ inline void weno5z_cell(const double* v, double eps, double& left, double& right) {
+  const double d0 = v[0] - 2.0 * v[1] + v[2], e0 = v[0] - 4.0 * v[1] + 3.0 * v[2];
+  const double d1 = v[1] - 2.0 * v[2] + v[3], e1 = v[1] - v[3];
+  const double d2 = v[2] - 2.0 * v[3] + v[4], e2 = 3.0 * v[2] - 4.0 * v[3] + v[4];
+  const double b0 = (13.0 / 12.0) * d0 * d0 + 0.25 * e0 * e0 + eps;
+  const double b1 = (13.0 / 12.0) * d1 * d1 + 0.25 * e1 * e1 + eps;
+  const double b2 = (13.0 / 12.0) * d2 * d2 + 0.25 * e2 * e2 + eps;
+  const double tau = fabs(b0 - b2);
+  const double t2 = tau * tau;
+  const double s0 = b0 * b0, s1 = b1 * b1, s2 = b2 * b2;
+  const double p01 = s0 * s1, p02 = s0 * s2, p12 = s1 * s2;
+  const double a0 = (s0 + t2), a1 = (s1 + t2), a2 = (s2 + t2);
+  {
+    const double w0 = (1.0 / 16.0) * a0 * p12;
+    const double w1 = (10.0 / 16.0) * a1 * p02;
+    const double w2 = (5.0 / 16.0) * a2 * p01;
+    const double q0 = (3.0 * v[0] - 10.0 * v[1] + 15.0 * v[2]) * 0.125;
+    const double q1 = (-v[1] + 6.0 * v[2] + 3.0 * v[3]) * 0.125;
+    const double q2 = (3.0 * v[2] + 6.0 * v[3] - v[4]) * 0.125;
+    left = (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+  }
+  {
+    const double w0 = (1.0 / 16.0) * a2 * p01;
+    const double w1 = (10.0 / 16.0) * a1 * p02;
+    const double w2 = (5.0 / 16.0) * a0 * p12;
+    const double q0 = (3.0 * v[4] - 10.0 * v[3] + 15.0 * v[2]) * 0.125;
+    const double q1 = (-v[3] + 6.0 * v[2] + 3.0 * v[1]) * 0.125;
+    const double q2 = (3.0 * v[2] + 6.0 * v[1] - v[0]) * 0.125;
+    right = (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+  }
 }
 
 // Where the (U, J~) of cell c (-3 <= c <= m+2 along d) of element e lives.
@@ -232,14 +310,15 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   constexpr int L = m;      // pencils per workgroup
   constexpr int C = m + 6;  // cells per pencil including ghosts
   constexpr int F = m + 1;  // faces per pencil
+  constexpr int FP = F + 1;  // padded (odd) LDS row length of face arrays
   constexpr int NR = NV + 1;  // reconstructed components: U and J~^d
   const int e = blockIdx.z;
   const int d = blockIdx.y;
   const int t2 = blockIdx.x;
   if (!fd_active(a, e)) return;
   __shared__ double sW[NR * L * C];
-  __shared__ double sLf[NR * L * F];
-  __shared__ double sRf[NR * L * F];
+  __shared__ double sLf[NR * L * FP];
+  __shared__ double sRf[NR * L * FP];
   __shared__ double sFc[NV * L * (m + 2)];
   __shared__ double sM[CURVED ? NBGF * L * (m + 2) : 1];
   const int t = threadIdx.x;
@@ -310,38 +389,46 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
       for (int v = 0; v < NV; ++v) sFc[(v * L + t1) * (m + 2) + cm] = Fc[v];
     }
   }
-  for (int q = t; q < NR * L * F; q += 256) {
-    const int f = q % F;
-    const int t1 = (q / F) % L;
-    const int k = q / (F * L);
-    const double* v = sW + (k * L + t1) * C + f;  // cells f-3 .. f+2
-    sLf[q] = weno5z(v[0], v[1], v[2], v[3], v[4], eps);
-    sRf[q] = weno5z(v[5], v[4], v[3], v[2], v[1], eps);
+  // target cells c = -1 .. m: left state of face c+1 and right state of face c
+  for (int q = t; q < NR * L * (m + 2); q += 256) {
+    const int c = q % (m + 2) - 1;
+    const int kt = q / (m + 2);  // k * L + t1
+    const double* v = sW + kt * C + c + 1;  // cells c-2 .. c+2 (extended index c+1 .. c+5)
+    double vl[5];
+#pragma unroll
+    for (int z = 0; z < 5; ++z) vl[z] = v[z];
+    double lft, rgt;
+    weno5z_cell(vl, eps, lft, rgt);
+    if (c < m) sLf[kt * FP + c + 1] = lft;
+    if (c >= 0) sRf[kt * FP + c] = rgt;
   }
   __syncthreads();
-  // phase 3: fluxes
-  for (int q = t; q < L * F; q += 256) {
-    int f, t1;
+  // phase 3: fluxes at every face of every pencil
+  double Fh[NV];
+  static_assert(L * F <= 256, "one face per thread in phase 3");
+  const int q3 = t;
+  int f3 = 0, t13 = 0;
+  if (q3 < L * F) {
     if (d == 0) {
-      f = q % F;
-      t1 = q / F;
+      f3 = q3 % F;
+      t13 = q3 / F;
     } else {
-      t1 = q % L;
-      f = q / L;
+      t13 = q3 % L;
+      f3 = q3 / L;
     }
     int tix;
-    if (d == 0) tix = f + (m + 1) * (t1 + m * t2);
-    else if (d == 1) tix = t1 + m * (f + (m + 1) * t2);
-    else tix = t1 + m * (t2 + m * f);
+    if (d == 0) tix = f3 + (m + 1) * (t13 + m * t2);
+    else if (d == 1) tix = t13 + m * (f3 + (m + 1) * t2);
+    else tix = t13 + m * (t2 + m * f3);
     double WL[NR], WR[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      WL[k] = sLf[(k * L + t1) * F + f];
-      WR[k] = sRf[(k * L + t1) * F + f];
+      WL[k] = sLf[(k * L + t13) * FP + f3];
+      WR[k] = sRf[(k * L + t13) * FP + f3];
     }
     Metric Mf;
     load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nf, a.E, nf, e, tix, Mf);
-    double Fh[NV], Ft[NV];
+    double Ft[NV];
     flux_any_jd(d, WL, WL[NV], Mf, Fh);
     flux_any_jd(d, WR, WR[NV], Mf, Ft);
     const double lam = CURVED ? char_speed(d, Mf) : 1.0;
@@ -351,25 +438,48 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
       // cell-centred fluxes of cells f-1 and f
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double* fc = sFc + (v * L + t1) * (m + 2) + f;
+        const double* fc = sFc + (v * L + t13) * (m + 2) + f3;
         Fh[v] = Fh[v] - (fc[0] - 2.0 * Fh[v] + fc[1]) / 6.0;
       }
     }
-    double* out = a.fhat + ((size_t)d * NV * a.E + e) * nf + tix;
+  }
+  __syncthreads();
+  double* sFh = sLf;  // the reconstructed states are no longer needed
+  if (q3 < L * F) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out[(size_t)v * a.E * nf] = Fh[v];
+    for (int v = 0; v < NV; ++v) sFh[(v * L + t13) * FP + f3] = Fh[v];
+  }
+  __syncthreads();
+  // phase 4: flux difference of every cell of the row, -(2N+1)/h_d (Fhat_{i+1/2} - Fhat_{i-1/2})
+  const double sc = (double)m / a.h[d];
+  const int str[3] = {1, m, m * m};
+  const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+  for (int q = t; q < L * m; q += 256) {
+    int c, t1;
+    if (d == 0) {
+      c = q % m;
+      t1 = q / m;
+    } else {
+      t1 = q % L;
+      c = q / L;
+    }
+    const int cell = c * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
+    double* out = a.fhat + ((size_t)d * NV * a.E + e) * mm + cell;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double* fh = sFh + (v * L + t1) * FP + c;
+      out[(size_t)v * a.E * mm] = -sc * (fh[1] - fh[0]);
+    }
   }
 }
 
 template <int N, bool CURVED, int MODE>
 __global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
   using Dm = Dims<N>;
-  constexpr int m = Dm::m, mm = Dm::mm;
-  constexpr int nf = (m + 1) * m * m;
+  constexpr int mm = Dm::mm;
   const int e = blockIdx.y;
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= mm || !fd_active(a, e)) return;
-  const int i = p % m, j = (p / m) % m, k = p / (m * m);
   Metric M;
   load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
   double X[NV];
@@ -381,16 +491,10 @@ __global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
     load_deriv<CURVED>(a.bg_fd, a.E, mm, e, p, Dv);
     source_explicit<CURVED>(X, M, Dv, Jd, dU);
   }
-  const int lo[3] = {i + (m + 1) * (j + m * k), i + m * (j + (m + 1) * k), i + m * (j + m * k)};
-  const int step[3] = {1, m, m * m};
   for (int d = 0; d < 3; ++d) {
-    const double sc = (double)m / a.h[d];
-    const double* fh = a.fhat + ((size_t)d * NV * a.E + e) * nf + lo[d];
+    const double* fd_ = a.fhat + ((size_t)d * NV * a.E + e) * mm + p;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double* q = fh + (size_t)v * a.E * nf;
-      dU[v] -= sc * (q[step[d]] - q[0]);
-    }
+    for (int v = 0; v < NV; ++v) dU[v] += fd_[(size_t)v * a.E * mm];
   }
   if (MODE == MODE_RHS) {
     double St[NV], out[NV];
@@ -727,10 +831,10 @@ template <int N, bool CURVED>
 static void fd_stage_t(const KArgs& a, int mode, int tro, hipStream_t s) {
   dim3 grid((Dims<N>::mm + 255) / 256, a.E), block(256);
   switch (mode) {
-    case MODE_RHS: hipLaunchKernelGGL((k_fd_stage<N, CURVED, MODE_RHS>), grid, block, 0, s, a, tro); break;
-    case MODE_SUB1: hipLaunchKernelGGL((k_fd_stage<N, CURVED, MODE_SUB1>), grid, block, 0, s, a, tro); break;
-    case MODE_SUB2: hipLaunchKernelGGL((k_fd_stage<N, CURVED, MODE_SUB2>), grid, block, 0, s, a, tro); break;
-    default: hipLaunchKernelGGL((k_fd_stage<N, CURVED, MODE_SUB3>), grid, block, 0, s, a, tro); break;
+    case MODE_RHS: launch_kernel(k_fd_stage<N, CURVED, MODE_RHS>, grid, block, s, a, tro); break;
+    case MODE_SUB1: launch_kernel(k_fd_stage<N, CURVED, MODE_SUB1>, grid, block, s, a, tro); break;
+    case MODE_SUB2: launch_kernel(k_fd_stage<N, CURVED, MODE_SUB2>, grid, block, s, a, tro); break;
+    default: launch_kernel(k_fd_stage<N, CURVED, MODE_SUB3>, grid, block, s, a, tro); break;
   }
 }
 
@@ -740,18 +844,28 @@ void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, bool troubled
 }
 
 void launch_fd_trace(const KArgs& a, int N, hipStream_t s) {
-  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_fd_trace<NN>), dim3(a.E, NW), dim3(256), 0, s, a))
+  GRFFE_SWITCH_N(launch_kernel(k_fd_trace<NN>, dim3(a.E, NW), dim3(256), s, a))
 }
 
-void launch_project_troubled(const KArgs& a, int N, bool, int mode, hipStream_t s) {
-  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_project_troubled<NN>), dim3(a.E), dim3(256), 0, s, a, mode))
+template <int N, bool CURVED>
+static void project_t(const KArgs& a, int mode, hipStream_t s) {
+  switch (mode) {
+    case MODE_SUB1: launch_kernel(k_project_troubled<N, CURVED, MODE_SUB1>, dim3(a.E), dim3(256), s, a); break;
+    case MODE_SUB2: launch_kernel(k_project_troubled<N, CURVED, MODE_SUB2>, dim3(a.E), dim3(256), s, a); break;
+    default: launch_kernel(k_project_troubled<N, CURVED, MODE_SUB3>, dim3(a.E), dim3(256), s, a); break;
+  }
+}
+
+void launch_project_troubled(const KArgs& a, int N, bool curved, int mode, hipStream_t s) {
+  if (curved) GRFFE_SWITCH_N((project_t<NN, true>(a, mode, s)))
+  else GRFFE_SWITCH_N((project_t<NN, false>(a, mode, s)))
 }
 
 template <int N, bool CURVED>
 static void fd_flux_t(const KArgs& a, hipStream_t s) {
   constexpr int m = Dims<N>::m;
   dim3 grid(m, 3, a.E), block(256);
-  hipLaunchKernelGGL((k_fd_flux<N, CURVED>), grid, block, 0, s, a);
+  launch_kernel(k_fd_flux<N, CURVED>, grid, block, s, a);
 }
 
 void launch_fd_flux(const KArgs& a, int N, bool curved, hipStream_t s) {
@@ -763,10 +877,10 @@ template <int N, bool CURVED>
 static void fd_update_t(const KArgs& a, int mode, hipStream_t s) {
   dim3 grid((Dims<N>::mm + 255) / 256, a.E), block(256);
   switch (mode) {
-    case MODE_RHS: hipLaunchKernelGGL((k_fd_update<N, CURVED, MODE_RHS>), grid, block, 0, s, a); break;
-    case MODE_SUB1: hipLaunchKernelGGL((k_fd_update<N, CURVED, MODE_SUB1>), grid, block, 0, s, a); break;
-    case MODE_SUB2: hipLaunchKernelGGL((k_fd_update<N, CURVED, MODE_SUB2>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_fd_update<N, CURVED, MODE_SUB3>), grid, block, 0, s, a); break;
+    case MODE_RHS: launch_kernel(k_fd_update<N, CURVED, MODE_RHS>, grid, block, s, a); break;
+    case MODE_SUB1: launch_kernel(k_fd_update<N, CURVED, MODE_SUB1>, grid, block, s, a); break;
+    case MODE_SUB2: launch_kernel(k_fd_update<N, CURVED, MODE_SUB2>, grid, block, s, a); break;
+    default: launch_kernel(k_fd_update<N, CURVED, MODE_SUB3>, grid, block, s, a); break;
   }
 }
 
@@ -776,8 +890,8 @@ void launch_fd_update(const KArgs& a, int N, bool curved, int mode, hipStream_t 
 }
 
 void launch_fd_to_dg_policy(const KArgs& a, int N, bool curved, int policy, const uint8_t* forced, hipStream_t s) {
-  if (curved) GRFFE_SWITCH_N(hipLaunchKernelGGL((k_fd_to_dg<NN, true>), dim3(a.E), dim3(256), 0, s, a, policy, forced))
-  else GRFFE_SWITCH_N(hipLaunchKernelGGL((k_fd_to_dg<NN, false>), dim3(a.E), dim3(256), 0, s, a, policy, forced))
+  if (curved) GRFFE_SWITCH_N(launch_kernel(k_fd_to_dg<NN, true>, dim3(a.E), dim3(256), s, a, policy, forced))
+  else GRFFE_SWITCH_N(launch_kernel(k_fd_to_dg<NN, false>, dim3(a.E), dim3(256), s, a, policy, forced))
 }
 
 void launch_fd_to_dg(const KArgs& a, int N, bool curved, int init, hipStream_t s) {
@@ -785,27 +899,27 @@ void launch_fd_to_dg(const KArgs& a, int N, bool curved, int init, hipStream_t s
 }
 
 void launch_begin_substep(const KArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_begin_substep, dim3((a.E + 255) / 256), dim3(256), 0, s, a);
+  launch_kernel(k_begin_substep, dim3((a.E + 255) / 256), dim3(256), s, a);
 }
 
 void launch_tci(const KArgs& a, int N, bool curved, const double* dg, const double* fd, const int32_t* rep,
                 uint8_t* troubled, double* ratio, hipStream_t s) {
   if (curved)
-    GRFFE_SWITCH_N(hipLaunchKernelGGL((k_tci<NN, true>), dim3(a.E), dim3(256), 0, s, a, dg, fd, rep, troubled, ratio))
+    GRFFE_SWITCH_N(launch_kernel(k_tci<NN, true>, dim3(a.E), dim3(256), s, a, dg, fd, rep, troubled, ratio))
   else
-    GRFFE_SWITCH_N(hipLaunchKernelGGL((k_tci<NN, false>), dim3(a.E), dim3(256), 0, s, a, dg, fd, rep, troubled, ratio))
+    GRFFE_SWITCH_N(launch_kernel(k_tci<NN, false>, dim3(a.E), dim3(256), s, a, dg, fd, rep, troubled, ratio))
 }
 
 void launch_transfer(const KArgs& a, int N, int to_fd, const double* in, double* out, int count, hipStream_t s) {
-  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_transfer<NN>), dim3(count, NV), dim3(256), 0, s, a, to_fd, in, out, count))
+  GRFFE_SWITCH_N(launch_kernel(k_transfer<NN>, dim3(count, NV), dim3(256), s, a, to_fd, in, out, count))
 }
 
 void launch_bg_derive_q(const KArgs& a, int N, double* bg_fd, double* bg_face, const double* Q, hipStream_t s) {
-  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_bg_derive<NN>), dim3(a.E, NBG), dim3(256), 0, s, a, bg_fd, bg_face, Q))
+  GRFFE_SWITCH_N(launch_kernel(k_bg_derive<NN>, dim3(a.E, NBG), dim3(256), s, a, bg_fd, bg_face, Q))
 }
 
 void launch_lambda_max(const KArgs& a, int N, double* out, hipStream_t s) {
-  GRFFE_SWITCH_N(hipLaunchKernelGGL((k_lambda_max<NN>), dim3(a.E), dim3(256), 0, s, a, out))
+  GRFFE_SWITCH_N(launch_kernel(k_lambda_max<NN>, dim3(a.E), dim3(256), s, a, out))
 }
 
 }  // namespace grffe
