@@ -174,6 +174,39 @@ int grffe_operator(int degree, int which, double* out, int capacity);
 int grffe_timing_enable(grffe_domain* dom, int family);
 int grffe_timing_read(grffe_domain* dom, double* total_ms, int64_t* launches);
 
+/* Batches: many independent domains advanced together, each with its own grid,
+ * degree (3..7) and CFL time step (Eq. (spectre DG CFL condition) per domain).
+ * Domains of one degree are concatenated into one pool, so every kernel of a step
+ * is one launch over the elements of all of them; pools of different degrees run
+ * on concurrent branches of a HIP graph that holds one step of the whole batch.
+ * All grids share `params`; bgs (host array of `count` device pointers, each
+ * [26][E_k][n_k^3] as for grffe_init_domain) is NULL for flat space, otherwise
+ * every entry is non-NULL.  Domain k is addressed by its index in `grids`. */
+typedef struct grffe_batch grffe_batch;
+int grffe_batch_create(const grffe_grid* grids, int32_t count, const grffe_params* params,
+                       const double* const* bgs, void* stream, grffe_batch** out);
+int grffe_batch_destroy(grffe_batch* batch);
+/* Number of domains and of degree pools (host values). */
+int grffe_batch_size(grffe_batch* batch, int32_t* n_domains, int32_t* n_pools);
+/* Start-up of every domain from FD data, as grffe_init_from_fd: u_fd is a host
+ * array of `count` device pointers ([9][E_k][m_k^3]); forced (host array,
+ * nullable, entries nullable) holds device uint8 [E_k] masks in forced mode. */
+int grffe_batch_init_from_fd(grffe_batch* batch, const double* const* u_fd, const uint8_t* const* forced,
+                             void* stream);
+/* State of domain k in the layouts of grffe_get_state / grffe_set_state. */
+int grffe_batch_get_state(grffe_batch* batch, int32_t k, double* dg, double* fd, int32_t* rep, void* stream);
+int grffe_batch_set_state(grffe_batch* batch, int32_t k, const double* dg, const double* fd, const int32_t* rep,
+                          void* stream);
+/* CFL time step of domain k (host value, no synchronisation). */
+int grffe_batch_get_dt(grffe_batch* batch, int32_t k, double* dt);
+/* Live elements of domain k on DG and on FD (host values; synchronises the device). */
+int grffe_batch_get_counts(grffe_batch* batch, int32_t k, int32_t* n_dg, int32_t* n_fd);
+/* Advance every domain by n_steps steps of its own CFL time step.  use_graph = 1
+ * replays the captured one-step graph (captured at the first such call on a
+ * library-owned stream, launched on `stream`); 0 enqueues the same kernels
+ * directly.  The two give identical results. */
+int grffe_batch_step(grffe_batch* batch, int32_t n_steps, int32_t use_graph, void* stream);
+
 const char* grffe_last_error(void);
 
 #ifdef __cplusplus

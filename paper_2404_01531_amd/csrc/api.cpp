@@ -66,10 +66,8 @@ namespace grffe {
 KArgs make_args(grffe_domain* d) {
   KArgs a{};
   a.E = d->E;
-  a.nx = d->nx;
-  a.ny = d->ny;
-  a.nz = d->nz;
-  for (int k = 0; k < 3; ++k) a.h[k] = d->h[k];
+  a.eh = d->eh;
+  a.edt = d->edt;
   a.nbr = d->nbr;
   a.live = d->live;
   a.bg_dg = d->bg_dg;
@@ -86,7 +84,7 @@ KArgs make_args(grffe_domain* d) {
   a.trace = d->trace;
   a.slab = d->slab;
   a.fhat = d->fhat;
-  a.dt = d->dt_cfl;
+  a.dt = 0.0;
   a.eta = d->par.eta;
   a.kpsi = d->par.kappa_psi;
   a.kphi = d->par.kappa_phi;
@@ -169,53 +167,80 @@ static int validate(const grffe_grid* g, const grffe_params* p) {
   return GRFFE_OK;
 }
 
-extern "C" int grffe_init_domain(const grffe_grid* g, const grffe_params* p, const double* bg, void* stream,
-                                 grffe_domain** out) {
-  if (!out) return fail(GRFFE_EINVAL, "out must not be NULL");
+// Build a domain over one or more grids of the same degree: the elements of the
+// grids are concatenated (grid k occupies elements off_k .. off_k + E_k - 1) and
+// every grid keeps its own neighbour table, element widths and time step.
+static int build_pool(const grffe_grid* const* grids, int count, const grffe_params* p, const double* const* bgs,
+                      hipStream_t st, grffe_domain** out) {
   *out = nullptr;
-  int rc = validate(g, p);
-  if (rc) return rc;
+  if (count < 1) return fail(GRFFE_EINVAL, "no grid");
+  for (int k = 0; k < count; ++k)
+    if (int rc = validate(grids[k], p)) return rc;
+  const bool curved = bgs && bgs[0] != nullptr;
+  for (int k = 0; k < count; ++k) {
+    if (grids[k]->degree != grids[0]->degree) return fail(GRFFE_EINVAL, "a pool holds one degree");
+    if ((bgs && bgs[k] != nullptr) != curved) return fail(GRFFE_EINVAL, "a pool is all flat or all curved");
+  }
+  int rc = 0;
   grffe_domain* d = new grffe_domain();
-  d->N = g->degree;
+  const grffe_grid* g0 = grids[0];
+  d->N = g0->degree;
   d->n = d->N + 1;
   d->m = 2 * d->N + 1;
   d->nn = d->n * d->n * d->n;
   d->mm = d->m * d->m * d->m;
-  d->nx = g->n_elem[0];
-  d->ny = g->n_elem[1];
-  d->nz = g->n_elem[2];
-  d->E = d->nx * d->ny * d->nz;
+  d->nx = g0->n_elem[0];
+  d->ny = g0->n_elem[1];
+  d->nz = g0->n_elem[2];
   for (int k = 0; k < 3; ++k) {
-    d->lower[k] = g->lower[k];
-    d->upper[k] = g->upper[k];
-    d->h[k] = (g->upper[k] - g->lower[k]) / g->n_elem[k];
+    d->lower[k] = g0->lower[k];
+    d->upper[k] = g0->upper[k];
+    d->h[k] = (g0->upper[k] - g0->lower[k]) / g0->n_elem[k];
   }
-  for (int k = 0; k < 6; ++k) d->bc[k] = g->bc[k];
+  for (int k = 0; k < 6; ++k) d->bc[k] = g0->bc[k];
   d->par = *p;
-  d->curved = bg != nullptr;
-  const int E = d->E;
-  // neighbour table (host)
-  d->live_h.assign(E, 1);
-  if (g->excised)
-    for (int e = 0; e < E; ++e) d->live_h[e] = g->excised[e] ? 0 : 1;
-  d->nbr_h.assign((size_t)E * 6, -1);
-  const int ne[3] = {d->nx, d->ny, d->nz};
-  for (int e = 0; e < E; ++e) {
-    const int c[3] = {e % d->nx, (e / d->nx) % d->ny, e / (d->nx * d->ny)};
-    for (int dd = 0; dd < 3; ++dd)
-      for (int s = 0; s < 2; ++s) {
-        int cc[3] = {c[0], c[1], c[2]};
-        cc[dd] += s ? 1 : -1;
-        if (cc[dd] < 0 || cc[dd] >= ne[dd]) {
-          if (d->bc[2 * dd + s] != GRFFE_BC_PERIODIC) continue;
-          cc[dd] = (cc[dd] + ne[dd]) % ne[dd];
-        }
-        const int o = cc[0] + d->nx * (cc[1] + d->ny * cc[2]);
-        if (!d->live_h[o]) continue;
-        d->nbr_h[(size_t)e * 6 + 2 * dd + s] = o;
-      }
+  d->curved = curved;
+  int E = 0;
+  for (int k = 0; k < count; ++k) {
+    const grffe_grid* g = grids[k];
+    grffe_part pt{};
+    pt.off = E;
+    pt.nx = g->n_elem[0];
+    pt.ny = g->n_elem[1];
+    pt.nz = g->n_elem[2];
+    pt.E = pt.nx * pt.ny * pt.nz;
+    for (int q = 0; q < 3; ++q) pt.h[q] = (g->upper[q] - g->lower[q]) / g->n_elem[q];
+    d->parts.push_back(pt);
+    E += pt.E;
   }
-  hipStream_t st = S(stream);
+  d->E = E;
+  // neighbour tables (host), element widths
+  d->live_h.assign(E, 1);
+  d->nbr_h.assign((size_t)E * 6, -1);
+  d->eh_h.assign((size_t)E * 3, 0.0);
+  for (int k = 0; k < count; ++k) {
+    const grffe_grid* g = grids[k];
+    const grffe_part& pt = d->parts[k];
+    if (g->excised)
+      for (int e = 0; e < pt.E; ++e) d->live_h[pt.off + e] = g->excised[e] ? 0 : 1;
+    const int ne[3] = {pt.nx, pt.ny, pt.nz};
+    for (int e = 0; e < pt.E; ++e) {
+      for (int q = 0; q < 3; ++q) d->eh_h[3 * (pt.off + e) + q] = pt.h[q];
+      const int c[3] = {e % pt.nx, (e / pt.nx) % pt.ny, e / (pt.nx * pt.ny)};
+      for (int dd = 0; dd < 3; ++dd)
+        for (int sd = 0; sd < 2; ++sd) {
+          int cc[3] = {c[0], c[1], c[2]};
+          cc[dd] += sd ? 1 : -1;
+          if (cc[dd] < 0 || cc[dd] >= ne[dd]) {
+            if (g->bc[2 * dd + sd] != GRFFE_BC_PERIODIC) continue;
+            cc[dd] = (cc[dd] + ne[dd]) % ne[dd];
+          }
+          const int o = cc[0] + pt.nx * (cc[1] + pt.ny * cc[2]);
+          if (!d->live_h[pt.off + o]) continue;
+          d->nbr_h[(size_t)(pt.off + e) * 6 + 2 * dd + sd] = pt.off + o;
+        }
+    }
+  }
   const int M = p->tci_M > 0 ? p->tci_M : default_tci_M(d->N);
   d->ops_h = build_ops(d->N, p->filter_a, p->filter_b, M, p->tci_mode);
   DevOps ho{};
@@ -244,6 +269,8 @@ extern "C" int grffe_init_domain(const grffe_grid* g, const grffe_params* p, con
   } while (0)
   ALLOC(nbr, sizeof(int32_t) * E * 6);
   ALLOC(live, E);
+  ALLOC(eh, sizeof(double) * E * 3);
+  ALLOC(edt, sizeof(double) * E);
   ALLOC(ops, sizeof(DevOps));
   ALLOC(dg.Un, regdg);
   ALLOC(dg.X0, regdg);
@@ -273,27 +300,40 @@ extern "C" int grffe_init_domain(const grffe_grid* g, const grffe_params* p, con
     qdev = reinterpret_cast<double*>(ptr);
   }
 #undef ALLOC
-  HIPCHK(hipMemcpyAsync(d->nbr, d->nbr_h.data(), sizeof(int32_t) * E * 6, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d->live, d->live_h.data(), E, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d->ops, &ho, sizeof(DevOps), hipMemcpyHostToDevice, st));
+#define CHK(expr)                                                                            \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) {                                                                  \
+      grffe_destroy(d);                                                                      \
+      return fail(GRFFE_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));            \
+    }                                                                                        \
+  } while (0)
+  CHK(hipMemcpyAsync(d->nbr, d->nbr_h.data(), sizeof(int32_t) * E * 6, hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(d->live, d->live_h.data(), E, hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(d->eh, d->eh_h.data(), sizeof(double) * E * 3, hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(d->ops, &ho, sizeof(DevOps), hipMemcpyHostToDevice, st));
   for (void* r : {(void*)d->dg.Un, (void*)d->dg.X0, (void*)d->dg.X1, (void*)d->dg.A})
-    HIPCHK(hipMemsetAsync(r, 0, regdg, st));
+    CHK(hipMemsetAsync(r, 0, regdg, st));
   for (void* r : {(void*)d->fd.Un, (void*)d->fd.X0, (void*)d->fd.X1, (void*)d->fd.A})
-    HIPCHK(hipMemsetAsync(r, 0, regfd, st));
-  HIPCHK(hipMemsetAsync(d->rep, 0, sizeof(int32_t) * E, st));
-  HIPCHK(hipMemsetAsync(d->rep0, 0, sizeof(int32_t) * E, st));
-  HIPCHK(hipMemsetAsync(d->troubled, 0, E, st));
-  HIPCHK(hipMemsetAsync(d->ratio, 0, sizeof(double) * E, st));
-  // time step: lambda_max from the background (1 in flat space)
-  double lam = 1.0;
+    CHK(hipMemsetAsync(r, 0, regfd, st));
+  CHK(hipMemsetAsync(d->rep, 0, sizeof(int32_t) * E, st));
+  CHK(hipMemsetAsync(d->rep0, 0, sizeof(int32_t) * E, st));
+  CHK(hipMemsetAsync(d->troubled, 0, E, st));
+  CHK(hipMemsetAsync(d->ratio, 0, sizeof(double) * E, st));
+  // time step per grid: lambda_max from the background (1 in flat space)
+  for (auto& pt : d->parts) pt.lambda_max = 1.0;
   if (d->curved) {
-    HIPCHK(hipMemcpyAsync(d->bg_dg, bg, sizeof(double) * NBG * E * nn, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(qdev, d->ops_h.Q.data(), sizeof(double) * (m + 1) * n, hipMemcpyHostToDevice, st));
+    for (int k = 0; k < count; ++k) {
+      const grffe_part& pt = d->parts[k];
+      CHK(hipMemcpy2DAsync(d->bg_dg + (size_t)pt.off * nn, sizeof(double) * E * nn, bgs[k],
+                           sizeof(double) * pt.E * nn, sizeof(double) * pt.E * nn, NBG, hipMemcpyDeviceToDevice, st));
+    }
+    CHK(hipMemcpyAsync(qdev, d->ops_h.Q.data(), sizeof(double) * (m + 1) * n, hipMemcpyHostToDevice, st));
     KArgs a = make_args(d);
     launch_bg_derive_q(a, d->N, d->bg_fd, d->bg_face, qdev, st);
-    HIPCHK(hipGetLastError());
+    CHK(hipGetLastError());
     double* lmax = nullptr;
-    HIPCHK(hipMalloc((void**)&lmax, sizeof(double) * E));
+    CHK(hipMalloc((void**)&lmax, sizeof(double) * E));
     launch_lambda_max(a, d->N, lmax, st);
     std::vector<double> hl(E);
     hipError_t e1 = hipMemcpyAsync(hl.data(), lmax, sizeof(double) * E, hipMemcpyDeviceToHost, st);
@@ -303,18 +343,36 @@ extern "C" int grffe_init_domain(const grffe_grid* g, const grffe_params* p, con
       grffe_destroy(d);
       return fail(GRFFE_EHIP, "lambda_max reduction failed");
     }
-    lam = 0.0;
-    for (int e = 0; e < E; ++e) lam = std::fmax(lam, hl[e]);
+    for (auto& pt : d->parts) {
+      pt.lambda_max = 0.0;
+      for (int e = pt.off; e < pt.off + pt.E; ++e) pt.lambda_max = std::fmax(pt.lambda_max, hl[e]);
+    }
   }
-  d->lambda_max = lam;
   double gap = 1e300;
   for (int k = 0; k < d->N; ++k) gap = std::fmin(gap, d->ops_h.x[k + 1] - d->ops_h.x[k]);
-  const double hmin = std::fmin(d->h[0], std::fmin(d->h[1], d->h[2]));
   const double c = p->stab_c > 0.0 ? p->stab_c : ssp_rk3_stability_c();
-  d->dt_cfl = p->cfl * gap * hmin / 2.0 / lam * c / 3.0;
-  HIPCHK(hipGetLastError());
+  d->edt_h.assign(E, 0.0);
+  for (auto& pt : d->parts) {
+    const double hmin = std::fmin(pt.h[0], std::fmin(pt.h[1], pt.h[2]));
+    pt.dt = p->cfl * gap * hmin / 2.0 / pt.lambda_max * c / 3.0;
+    for (int e = pt.off; e < pt.off + pt.E; ++e) d->edt_h[e] = pt.dt;
+  }
+  d->dt_cfl = d->parts[0].dt;
+  d->lambda_max = d->parts[0].lambda_max;
+  CHK(hipMemcpyAsync(d->edt, d->edt_h.data(), sizeof(double) * E, hipMemcpyHostToDevice, st));
+  CHK(hipStreamSynchronize(st));
+  CHK(hipGetLastError());
+#undef CHK
   *out = d;
   return GRFFE_OK;
+}
+
+extern "C" int grffe_init_domain(const grffe_grid* g, const grffe_params* p, const double* bg, void* stream,
+                                 grffe_domain** out) {
+  if (!out) return fail(GRFFE_EINVAL, "out must not be NULL");
+  const grffe_grid* gs[1] = {g};
+  const double* bs[1] = {bg};
+  return build_pool(gs, 1, p, bs, S(stream), out);
 }
 
 extern "C" int grffe_set_state(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep, void* stream) {
@@ -336,11 +394,9 @@ extern "C" int grffe_get_state(grffe_domain* d, double* dg, double* fd, int32_t*
   return GRFFE_OK;
 }
 
-extern "C" int grffe_init_from_fd(grffe_domain* d, const double* u_fd, const uint8_t* forced, void* stream) {
-  if (int rc = check_dom(d)) return rc;
-  if (!u_fd) return fail(GRFFE_EINVAL, "u_fd must not be NULL");
-  hipStream_t st = S(stream);
-  HIPCHK(hipMemcpyAsync(d->fd.Un, u_fd, sizeof(double) * NV * d->E * d->mm, hipMemcpyDeviceToDevice, st));
+// Start-up from the FD data already in d->fd.Un: every live element is reconstructed
+// to DG and the hybrid policy decides which stay FD.
+static int init_pool_from_fd(grffe_domain* d, const uint8_t* forced, hipStream_t st) {
   HIPCHK(hipMemsetAsync(d->dg.Un, 0, sizeof(double) * NV * d->E * d->nn, st));
   std::vector<int32_t> ones(d->E);
   for (int e = 0; e < d->E; ++e) ones[e] = d->live_h[e] ? 1 : 0;
@@ -352,6 +408,14 @@ extern "C" int grffe_init_from_fd(grffe_domain* d, const double* u_fd, const uin
   // the pageable host copy above must finish before `ones` leaves scope
   HIPCHK(hipStreamSynchronize(st));
   return GRFFE_OK;
+}
+
+extern "C" int grffe_init_from_fd(grffe_domain* d, const double* u_fd, const uint8_t* forced, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (!u_fd) return fail(GRFFE_EINVAL, "u_fd must not be NULL");
+  hipStream_t st = S(stream);
+  HIPCHK(hipMemcpyAsync(d->fd.Un, u_fd, sizeof(double) * NV * d->E * d->mm, hipMemcpyDeviceToDevice, st));
+  return init_pool_from_fd(d, forced, st);
 }
 
 namespace grffe {
@@ -449,21 +513,24 @@ extern "C" int grffe_rhs(grffe_domain* d, const double* dg, const double* fd, co
   return GRFFE_OK;
 }
 
+// One IMEX-SSP3(4,3,3) step of every element of the domain (or pool).
+static void step_once(grffe_domain* d, KArgs& a, hipStream_t st) {
+  run_substep(d, a, MODE_SUB1, st);
+  run_substep(d, a, MODE_SUB2, st);
+  run_substep(d, a, MODE_SUB3, st);
+  if (a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
+    TimedLaunch t(d, 8, st);
+    launch_fd_to_dg(a, d->N, d->curved, 0, st);
+  }
+}
+
 extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream) {
   if (int rc = check_dom(d)) return rc;
   if (n_steps < 0) return fail(GRFFE_EINVAL, "n_steps must be >= 0");
   hipStream_t st = S(stream);
   KArgs a = make_args(d);
   if (dt > 0.0) a.dt = dt;
-  for (int it = 0; it < n_steps; ++it) {
-    run_substep(d, a, MODE_SUB1, st);
-    run_substep(d, a, MODE_SUB2, st);
-    run_substep(d, a, MODE_SUB3, st);
-    if (a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
-      TimedLaunch t(d, 8, st);
-      launch_fd_to_dg(a, d->N, d->curved, 0, st);
-    }
-  }
+  for (int it = 0; it < n_steps; ++it) step_once(d, a, st);
   HIPCHK(hipGetLastError());
   return GRFFE_OK;
 }
@@ -549,3 +616,267 @@ extern "C" int grffe_operator(int degree, int which, double* out, int capacity) 
   return cnt;
 }
 
+
+// ------------------------------------------------------------------ batches
+// A batch holds many independent domains.  Domains of one degree share a pool: their
+// elements are concatenated, so every kernel of a step is one launch over all of
+// them, with per-element widths and time steps.  One step of all pools is captured
+// once into a HIP graph, the pools on forked branches that can run concurrently.
+struct grffe_batch {
+  std::vector<grffe_domain*> pools;
+  std::vector<int> pool_of, part_of;  // domain k -> pool, part within the pool
+  std::vector<uint8_t*> forced;       // per pool [E] (forced hybrid mode)
+  hipStream_t cap = nullptr;          // capture stream (library owned)
+  std::vector<hipStream_t> side;      // one branch stream per extra pool
+  std::vector<hipEvent_t> ev;         // fork + joins
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static int check_batch(grffe_batch* b) {
+  if (!b || b->pools.empty()) return fail(GRFFE_EINVAL, "batch is NULL");
+  return GRFFE_OK;
+}
+
+static int check_member(grffe_batch* b, int k) {
+  if (int rc = check_batch(b)) return rc;
+  if (k < 0 || k >= (int)b->pool_of.size()) return fail(GRFFE_EINVAL, "domain index out of range");
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_destroy(grffe_batch* b) {
+  if (!b) return GRFFE_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (grffe_domain* d : b->pools) grffe_destroy(d);
+  delete b;
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_create(const grffe_grid* grids, int32_t count, const grffe_params* params,
+                                  const double* const* bgs, void* stream, grffe_batch** out) {
+  if (!out) return fail(GRFFE_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (!grids || !params || count < 1) return fail(GRFFE_EINVAL, "a batch needs at least one grid");
+  for (int k = 0; k < count; ++k)
+    if (grids[k].degree < 3 || grids[k].degree > MAX_DEG) return fail(GRFFE_EINVAL, "degree must be in 3..7");
+  const bool curved = bgs && bgs[0];
+  for (int k = 0; k < count; ++k)
+    if ((bgs && bgs[k]) != curved) return fail(GRFFE_EINVAL, "a batch is all flat or all curved");
+  hipStream_t st = S(stream);
+  grffe_batch* b = new grffe_batch();
+  b->pool_of.assign(count, -1);
+  b->part_of.assign(count, -1);
+  for (int N = 3; N <= MAX_DEG; ++N) {
+    std::vector<const grffe_grid*> gs;
+    std::vector<const double*> bs;
+    std::vector<int> ids;
+    for (int k = 0; k < count; ++k)
+      if (grids[k].degree == N) {
+        gs.push_back(&grids[k]);
+        bs.push_back(curved ? bgs[k] : nullptr);
+        ids.push_back(k);
+      }
+    if (gs.empty()) continue;
+    grffe_domain* d = nullptr;
+    if (int rc = build_pool(gs.data(), (int)gs.size(), params, bs.data(), st, &d)) {
+      grffe_batch_destroy(b);
+      return rc;
+    }
+    const int pi = (int)b->pools.size();
+    b->pools.push_back(d);
+    for (size_t q = 0; q < ids.size(); ++q) {
+      b->pool_of[ids[q]] = pi;
+      b->part_of[ids[q]] = (int)q;
+    }
+    void* ptr = nullptr;
+    if (int rc = dalloc(d, &ptr, d->E)) {
+      grffe_batch_destroy(b);
+      return rc;
+    }
+    b->forced.push_back(reinterpret_cast<uint8_t*>(ptr));
+    if (hipMemsetAsync(ptr, 0, d->E, st) != hipSuccess) {
+      grffe_batch_destroy(b);
+      return fail(GRFFE_EHIP, "hipMemsetAsync failed");
+    }
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    grffe_batch_destroy(b);
+    return fail(GRFFE_EHIP, "hipStreamSynchronize failed");
+  }
+  *out = b;
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_size(grffe_batch* b, int32_t* n_domains, int32_t* n_pools) {
+  if (int rc = check_batch(b)) return rc;
+  if (n_domains) *n_domains = (int32_t)b->pool_of.size();
+  if (n_pools) *n_pools = (int32_t)b->pools.size();
+  return GRFFE_OK;
+}
+
+// Copy between a domain's compact [9][E_k][P] array and its rows in a pool [9][E][P].
+static int copy_rows(double* dst, size_t dpitch, const double* src, size_t spitch, size_t width, int rows,
+                     hipStream_t st) {
+  if (width == 0) return GRFFE_OK;
+  HIPCHK(hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, hipMemcpyDeviceToDevice, st));
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_init_from_fd(grffe_batch* b, const double* const* u_fd, const uint8_t* const* forced,
+                                        void* stream) {
+  if (int rc = check_batch(b)) return rc;
+  if (!u_fd) return fail(GRFFE_EINVAL, "u_fd must not be NULL");
+  hipStream_t st = S(stream);
+  for (size_t k = 0; k < b->pool_of.size(); ++k) {
+    if (!u_fd[k]) return fail(GRFFE_EINVAL, "every domain needs FD data");
+    grffe_domain* d = b->pools[b->pool_of[k]];
+    const grffe_part& pt = d->parts[b->part_of[k]];
+    const size_t row = sizeof(double) * pt.E * d->mm;
+    if (int rc = copy_rows(d->fd.Un + (size_t)pt.off * d->mm, sizeof(double) * d->E * d->mm, u_fd[k], row, row, NV,
+                           st))
+      return rc;
+    uint8_t* f = b->forced[b->pool_of[k]] + pt.off;
+    if (forced && forced[k]) {
+      HIPCHK(hipMemcpyAsync(f, forced[k], pt.E, hipMemcpyDeviceToDevice, st));
+    } else {
+      HIPCHK(hipMemsetAsync(f, 0, pt.E, st));
+    }
+  }
+  for (size_t pi = 0; pi < b->pools.size(); ++pi)
+    if (int rc = init_pool_from_fd(b->pools[pi], b->forced[pi], st)) return rc;
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_get_state(grffe_batch* b, int32_t k, double* dg, double* fd, int32_t* rep, void* stream) {
+  if (int rc = check_member(b, k)) return rc;
+  hipStream_t st = S(stream);
+  grffe_domain* d = b->pools[b->pool_of[k]];
+  const grffe_part& pt = d->parts[b->part_of[k]];
+  if (dg) {
+    const size_t row = sizeof(double) * pt.E * d->nn;
+    if (int rc = copy_rows(dg, row, d->dg.Un + (size_t)pt.off * d->nn, sizeof(double) * d->E * d->nn, row, NV, st))
+      return rc;
+  }
+  if (fd) {
+    const size_t row = sizeof(double) * pt.E * d->mm;
+    if (int rc = copy_rows(fd, row, d->fd.Un + (size_t)pt.off * d->mm, sizeof(double) * d->E * d->mm, row, NV, st))
+      return rc;
+  }
+  if (rep) HIPCHK(hipMemcpyAsync(rep, d->rep + pt.off, sizeof(int32_t) * pt.E, hipMemcpyDeviceToDevice, st));
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_set_state(grffe_batch* b, int32_t k, const double* dg, const double* fd,
+                                     const int32_t* rep, void* stream) {
+  if (int rc = check_member(b, k)) return rc;
+  if (!dg || !fd || !rep) return fail(GRFFE_EINVAL, "state pointers must not be NULL");
+  hipStream_t st = S(stream);
+  grffe_domain* d = b->pools[b->pool_of[k]];
+  const grffe_part& pt = d->parts[b->part_of[k]];
+  size_t row = sizeof(double) * pt.E * d->nn;
+  if (int rc = copy_rows(d->dg.Un + (size_t)pt.off * d->nn, sizeof(double) * d->E * d->nn, dg, row, row, NV, st))
+    return rc;
+  row = sizeof(double) * pt.E * d->mm;
+  if (int rc = copy_rows(d->fd.Un + (size_t)pt.off * d->mm, sizeof(double) * d->E * d->mm, fd, row, row, NV, st))
+    return rc;
+  HIPCHK(hipMemcpyAsync(d->rep + pt.off, rep, sizeof(int32_t) * pt.E, hipMemcpyDeviceToDevice, st));
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_get_dt(grffe_batch* b, int32_t k, double* dt) {
+  if (int rc = check_member(b, k)) return rc;
+  if (!dt) return fail(GRFFE_EINVAL, "dt must not be NULL");
+  *dt = b->pools[b->pool_of[k]]->parts[b->part_of[k]].dt;
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_get_counts(grffe_batch* b, int32_t k, int32_t* n_dg, int32_t* n_fd) {
+  if (int rc = check_member(b, k)) return rc;
+  grffe_domain* d = b->pools[b->pool_of[k]];
+  const grffe_part& pt = d->parts[b->part_of[k]];
+  std::vector<int32_t> rep(pt.E);
+  HIPCHK(hipMemcpy(rep.data(), d->rep + pt.off, sizeof(int32_t) * pt.E, hipMemcpyDeviceToHost));
+  int32_t a = 0, f = 0;
+  for (int e = 0; e < pt.E; ++e) {
+    if (!d->live_h[pt.off + e]) continue;
+    if (rep[e]) ++f; else ++a;
+  }
+  if (n_dg) *n_dg = a;
+  if (n_fd) *n_fd = f;
+  return GRFFE_OK;
+}
+
+// One step of every pool: pool 0 on `st`, every other pool on its own branch stream
+// forked from and joined back to `st`.
+static int batch_step_once(grffe_batch* b, hipStream_t st) {
+  const size_t np = b->pools.size();
+  if (np > 1) {
+    HIPCHK(hipEventRecord(b->ev[0], st));
+    for (size_t pi = 1; pi < np; ++pi) HIPCHK(hipStreamWaitEvent(b->side[pi - 1], b->ev[0], 0));
+  }
+  for (size_t pi = 0; pi < np; ++pi) {
+    grffe_domain* d = b->pools[pi];
+    hipStream_t s = pi == 0 ? st : b->side[pi - 1];
+    KArgs a = make_args(d);
+    step_once(d, a, s);
+    HIPCHK(hipGetLastError());
+  }
+  if (np > 1)
+    for (size_t pi = 1; pi < np; ++pi) {
+      HIPCHK(hipEventRecord(b->ev[pi], b->side[pi - 1]));
+      HIPCHK(hipStreamWaitEvent(st, b->ev[pi], 0));
+    }
+  return GRFFE_OK;
+}
+
+static int batch_streams(grffe_batch* b) {
+  const size_t np = b->pools.size();
+  while (b->side.size() + 1 < np) {
+    hipStream_t s;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    b->side.push_back(s);
+  }
+  while (b->ev.size() < np) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b->ev.push_back(e);
+  }
+  return GRFFE_OK;
+}
+
+static int batch_capture(grffe_batch* b) {
+  if (b->exec) return GRFFE_OK;
+  if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  const int rc = batch_step_once(b, b->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(GRFFE_EHIP, std::string("stream capture failed: ") + hipGetErrorString(e));
+  b->graph = g;
+  HIPCHK(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_step(grffe_batch* b, int32_t n_steps, int32_t use_graph, void* stream) {
+  if (int rc = check_batch(b)) return rc;
+  if (n_steps < 0) return fail(GRFFE_EINVAL, "n_steps must be >= 0");
+  hipStream_t st = S(stream);
+  if (int rc = batch_streams(b)) return rc;
+  if (use_graph) {
+    if (int rc = batch_capture(b)) return rc;
+    for (int it = 0; it < n_steps; ++it) HIPCHK(hipGraphLaunch(b->exec, st));
+  } else {
+    for (int it = 0; it < n_steps; ++it)
+      if (int rc = batch_step_once(b, st)) return rc;
+  }
+  HIPCHK(hipGetLastError());
+  return GRFFE_OK;
+}

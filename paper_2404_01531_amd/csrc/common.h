@@ -89,17 +89,20 @@ __device__ inline void store9(double* base, int E, int P, int e, int p, const do
   for (int v = 0; v < NV; ++v) base[((size_t)v * E + e) * P + p] = U[v];
 }
 
+__device__ inline double dt_of(const KArgs& a, int e) { return a.dt > 0.0 ? a.dt : a.edt[e]; }
+__device__ inline double h_of(const KArgs& a, int e, int d) { return a.eh[3 * e + d]; }
+
 // U_1, U_2 and their stiff sources from U^n (the implicit pre-stages of IMEX-SSP3(4,3,3)).
-__device__ inline void derived_stages(const double* Un, const Metric& M, const KArgs& a, double* U2, double* S1,
-                                      double* S2) {
+__device__ inline void derived_stages(const double* Un, const Metric& M, const KArgs& a, double dt, double* U2,
+                                      double* S1, double* S2) {
   double U1[NV];
-  const double h = a.dt * IMEX_A;
+  const double h = dt * IMEX_A;
 #pragma unroll
   for (int v = 0; v < NV; ++v) U1[v] = Un[v];
   implicit_solve(U1, M, a.eta, a.kpsi, a.kphi, h);
   source_stiff(U1, M, a.eta, a.kpsi, a.kphi, S1);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) U2[v] = Un[v] - a.dt * IMEX_A * S1[v];
+  for (int v = 0; v < NV; ++v) U2[v] = Un[v] - dt * IMEX_A * S1[v];
   implicit_solve(U2, M, a.eta, a.kpsi, a.kphi, h);
   source_stiff(U2, M, a.eta, a.kpsi, a.kphi, S2);
 }
@@ -113,7 +116,7 @@ __device__ inline void stage_input(const Regs& r, int E, int P, int e, int p, co
   } else if (MODE == MODE_SUB1) {
     double Un[NV], S1[NV], S2[NV];
     load9(r.Un, E, P, e, p, Un);
-    derived_stages(Un, M, a, X, S1, S2);
+    derived_stages(Un, M, a, dt_of(a, e), X, S1, S2);
   } else if (MODE == MODE_SUB2) {
     load9(r.X0, E, P, e, p, X);
   } else {
@@ -128,7 +131,7 @@ __device__ inline void stage_update(const Regs& r, int E, int P, int e, int p, c
                                     const double* X, const double* L, double* Y, double* Anew) {
   double Un[NV], S1[NV], S2[NV], U2[NV];
   load9(r.Un, E, P, e, p, Un);
-  const double dt = a.dt;
+  const double dt = dt_of(a, e);
   if (MODE == MODE_SUB1) {
     // the substep input X is U_2 itself
     source_stiff(X, M, a.eta, a.kpsi, a.kphi, S2);
@@ -140,7 +143,7 @@ __device__ inline void stage_update(const Regs& r, int E, int P, int e, int p, c
   } else if (MODE == MODE_SUB2) {
     double A[NV], S3[NV];
     load9(r.A, E, P, e, p, A);
-    derived_stages(Un, M, a, U2, S1, S2);
+    derived_stages(Un, M, a, dt, U2, S1, S2);
     source_stiff(X, M, a.eta, a.kpsi, a.kphi, S3);
     const double c3 = 0.5 - IMEX_B - IMEX_E - IMEX_A;
 #pragma unroll
@@ -152,7 +155,7 @@ __device__ inline void stage_update(const Regs& r, int E, int P, int e, int p, c
   } else {
     double A[NV], S4[NV];
     load9(r.A, E, P, e, p, A);
-    derived_stages(Un, M, a, U2, S1, S2);
+    derived_stages(Un, M, a, dt, U2, S1, S2);
     source_stiff(X, M, a.eta, a.kpsi, a.kphi, S4);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

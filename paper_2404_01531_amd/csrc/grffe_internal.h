@@ -53,8 +53,9 @@ struct Regs {
 
 // Everything a kernel needs; passed by value.
 struct KArgs {
-  int E, nx, ny, nz;
-  double h[3];
+  int E;
+  const double* eh;        // [E][3] element widths
+  const double* edt;       // [E] time step of the element's domain
   const int32_t* nbr;      // [E][6], -1 at a boundary
   const uint8_t* live;     // [E]
   const double* bg_dg;     // [26][E][n^3] or null
@@ -76,7 +77,7 @@ struct KArgs {
   double* out_dg;
   double* out_fd;
   int parts;
-  // scheme parameters
+  // scheme parameters; dt > 0 overrides the per-element time steps
   double dt, eta, kpsi, kphi;
   double tci_thr, tci_thr_fd;
   int tci_mode, filter_on, fd_order, ff_clamp, hybrid;
@@ -85,9 +86,18 @@ struct KArgs {
 
 }  // namespace grffe
 
+// One grid of a pool (a batch concatenates several grids of one degree).
+struct grffe_part {
+  int off, E, nx, ny, nz;
+  double h[3];
+  double dt;
+  double lambda_max;
+};
+
 struct grffe_domain {
   int N, n, m, nn, mm;
   int E, nx, ny, nz;
+  std::vector<grffe_part> parts;
   double lower[3], upper[3], h[3];
   int bc[6];
   grffe_params par;
@@ -96,6 +106,9 @@ struct grffe_domain {
   std::vector<uint8_t> live_h;
   int32_t* nbr = nullptr;
   uint8_t* live = nullptr;
+  double* eh = nullptr;   // [E][3]
+  double* edt = nullptr;  // [E]
+  std::vector<double> eh_h, edt_h;
   double* bg_dg = nullptr;
   double* bg_fd = nullptr;
   double* bg_face = nullptr;

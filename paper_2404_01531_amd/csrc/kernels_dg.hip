@@ -92,7 +92,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
     if (act)
       for (int v = 0; v < NV; ++v) sF[v * nn + p] = F[v];
     __syncthreads();
-    const double sc = 2.0 / a.h[d];
+    const double sc = 2.0 / h_of(a, e, d);
     const int id = idx[d];
     const int p0 = p - id * strideN[d];
     const double* Drow = sop + id * n;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
       }
     }
   }
-  if (MODE != MODE_SUB3) implicit_solve(Y, M, a.eta, a.kpsi, a.kphi, a.dt * IMEX_A);
+  if (MODE != MODE_SUB3) implicit_solve(Y, M, a.eta, a.kpsi, a.kphi, dt_of(a, e) * IMEX_A);
   if (a.ff_clamp) constraint_clamp(Y, M, a.ff_margin);
   // troubled-cell indicator on u = |B~|
   bool bad = false;

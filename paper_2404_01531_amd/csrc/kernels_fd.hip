@@ -319,7 +319,6 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   __shared__ double sW[NR * L * C];
   __shared__ double sLf[NR * L * FP];
   __shared__ double sRf[NR * L * FP];
-  __shared__ double sFc[NV * L * (m + 2)];
   __shared__ double sM[CURVED ? NBGF * L * (m + 2) : 1];
   const int t = threadIdx.x;
   // phase 1: stage cells -3 .. m+2 of every pencil (and the metric of cells -1 .. m)
@@ -367,28 +366,6 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   // phase 2: WENO5-Z of every component at every face of every pencil, and the
   // cell-centred fluxes of cells -1 .. m used by the corrector
   const double eps = a.weno_eps;
-  if (a.fd_order == 4) {
-    for (int q = t; q < L * (m + 2); q += 256) {
-      const int cm = q % (m + 2), t1 = q / (m + 2);  // cell cm - 1
-      double W[NR];
-#pragma unroll
-      for (int k = 0; k < NR; ++k) W[k] = sW[(k * L + t1) * C + cm + 2];
-      Metric Mc;
-      if (CURVED) {
-        double fm[10];
-        const double* o = sM + t1 * (m + 2) + cm;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) fm[k] = o[k * L * (m + 2)];
-        metric_from10(fm, Mc);
-      } else {
-        metric_flat(Mc);
-      }
-      double Fc[NV];
-      flux_any_jd(d, W, W[NV], Mc, Fc);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sFc[(v * L + t1) * (m + 2) + cm] = Fc[v];
-    }
-  }
   // target cells c = -1 .. m: left state of face c+1 and right state of face c
   for (int q = t; q < NR * L * (m + 2); q += 256) {
     const int c = q % (m + 2) - 1;
@@ -435,12 +412,28 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fh[v] = 0.5 * (Fh[v] + Ft[v]) - 0.5 * lam * (WR[v] - WL[v]);
     if (a.fd_order == 4) {
-      // cell-centred fluxes of cells f-1 and f
+      // cell-centred fluxes of cells f-1 and f (extended indices f+2 and f+3)
+      for (int side = 0; side < 2; ++side) {
+        double W[NR];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double* fc = sFc + (v * L + t13) * (m + 2) + f3;
-        Fh[v] = Fh[v] - (fc[0] - 2.0 * Fh[v] + fc[1]) / 6.0;
+        for (int k = 0; k < NR; ++k) W[k] = sW[(k * L + t13) * C + f3 + 2 + side];
+        Metric Mc;
+        if (CURVED) {
+          double fm[10];
+          const double* o = sM + t13 * (m + 2) + f3 + side;
+#pragma unroll
+          for (int k = 0; k < 10; ++k) fm[k] = o[k * L * (m + 2)];
+          metric_from10(fm, Mc);
+        } else {
+          metric_flat(Mc);
+        }
+        double Fc[NV];
+        flux_any_jd(d, W, W[NV], Mc, Fc);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Ft[v] = side ? Ft[v] + Fc[v] : Fc[v];
       }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fh[v] = Fh[v] - (Ft[v] - 2.0 * Fh[v]) / 6.0;
     }
   }
   __syncthreads();
@@ -451,7 +444,7 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   }
   __syncthreads();
   // phase 4: flux difference of every cell of the row, -(2N+1)/h_d (Fhat_{i+1/2} - Fhat_{i-1/2})
-  const double sc = (double)m / a.h[d];
+  const double sc = (double)m / h_of(a, e, d);
   const int str[3] = {1, m, m * m};
   const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
   for (int q = t; q < L * m; q += 256) {
@@ -505,7 +498,7 @@ __global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
   }
   double Y[NV], Anew[NV];
   stage_update<MODE>(a.fd, a.E, mm, e, p, M, a, X, dU, Y, Anew);
-  if (MODE != MODE_SUB3) implicit_solve(Y, M, a.eta, a.kpsi, a.kphi, a.dt * IMEX_A);
+  if (MODE != MODE_SUB3) implicit_solve(Y, M, a.eta, a.kpsi, a.kphi, dt_of(a, e) * IMEX_A);
   if (a.ff_clamp) constraint_clamp(Y, M, a.ff_margin);
   if (MODE == MODE_SUB1) {
     store9(a.fd.X0, a.E, mm, e, p, Y);

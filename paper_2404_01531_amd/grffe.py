@@ -91,11 +91,23 @@ def lib():
     L.grffe_operator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(dbl), ctypes.c_int]
     L.grffe_timing_enable.argtypes = [vp, ctypes.c_int]
     L.grffe_timing_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
+    pvp = ctypes.POINTER(vp)
+    L.grffe_batch_create.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(Params), pvp, vp, pvp]
+    L.grffe_batch_destroy.argtypes = [vp]
+    L.grffe_batch_size.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.grffe_batch_init_from_fd.argtypes = [vp, pvp, pvp, vp]
+    L.grffe_batch_get_state.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.grffe_batch_set_state.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.grffe_batch_get_dt.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+    L.grffe_batch_get_counts.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.grffe_batch_step.argtypes = [vp, i32, i32, vp]
     L.grffe_last_error.restype = ctypes.c_char_p
     for name in ("grffe_init_domain", "grffe_destroy", "grffe_init_from_fd", "grffe_set_state", "grffe_get_state",
                  "grffe_rhs", "grffe_step", "grffe_tci", "grffe_project_dg_to_fd", "grffe_reconstruct_fd_to_dg",
                  "grffe_get_dt", "grffe_get_counts", "grffe_operator", "grffe_timing_enable",
-                 "grffe_timing_read"):
+                 "grffe_timing_read", "grffe_batch_create", "grffe_batch_destroy", "grffe_batch_size",
+                 "grffe_batch_init_from_fd", "grffe_batch_get_state", "grffe_batch_set_state",
+                 "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -147,6 +159,22 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _fill_grid(g, n_elem, lower, upper, degree, bc, excised):
+    """Fill a Grid; returns the host excision array that must outlive the call."""
+    for k in range(3):
+        g.n_elem[k] = int(n_elem[k])
+        g.lower[k] = float(lower[k])
+        g.upper[k] = float(upper[k])
+    g.degree = int(degree)
+    for k in range(6):
+        g.bc[k] = int(bc[k])
+    exc = None
+    if excised is not None:
+        exc = np.ascontiguousarray(np.asarray(excised, np.uint8))
+        g.excised = exc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    return exc
+
+
 class Domain:
     """A GRFFE domain living on the current HIP device."""
 
@@ -156,17 +184,7 @@ class Domain:
             raise GrffeError("no HIP device available")
         L = lib()
         g = Grid()
-        for k in range(3):
-            g.n_elem[k] = int(n_elem[k])
-            g.lower[k] = float(lower[k])
-            g.upper[k] = float(upper[k])
-        g.degree = int(degree)
-        for k in range(6):
-            g.bc[k] = int(bc[k])
-        self._exc = None
-        if excised is not None:
-            self._exc = np.ascontiguousarray(np.asarray(excised, np.uint8))
-            g.excised = self._exc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        self._exc = _fill_grid(g, n_elem, lower, upper, degree, bc, excised)
         p = params if isinstance(params, Params) else default_params(**(params or {}))
         self.params = p
         self.N = int(degree)
@@ -275,3 +293,104 @@ class Domain:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().grffe_get_counts(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+
+class Batch:
+    """Many independent domains stepped together (see grffe_batch_create).
+
+    `grids` is a list of dicts with keys n_elem, lower, upper, degree, bc and
+    optionally excised; `bgs` is None (flat) or one (26, E_k, n_k^3) float64
+    device tensor per grid."""
+
+    def __init__(self, grids, params=None, bgs=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise GrffeError("no HIP device available")
+        L = lib()
+        cnt = len(grids)
+        if cnt < 1:
+            raise GrffeError("a batch needs at least one grid")
+        arr = (Grid * cnt)()
+        self._keep = []
+        self.shapes = []
+        for k, gd in enumerate(grids):
+            self._keep.append(_fill_grid(arr[k], gd["n_elem"], gd["lower"], gd["upper"], gd["degree"], gd["bc"],
+                                         gd.get("excised")))
+            N = int(gd["degree"])
+            self.shapes.append((int(np.prod(gd["n_elem"])), N))
+        p = params if isinstance(params, Params) else default_params(**(params or {}))
+        self.params = p
+        bg_arr = None
+        if bgs is not None:
+            if len(bgs) != cnt:
+                raise GrffeError("one background per grid")
+            for (E, N), b in zip(self.shapes, bgs):
+                if tuple(b.shape) != (26, E, (N + 1) ** 3) or b.dtype != torch.float64:
+                    raise GrffeError("bg must be float64 of shape (26, E, (N+1)^3)")
+            bg_arr = (ctypes.c_void_p * cnt)(*[b.data_ptr() for b in bgs])
+        h = ctypes.c_void_p()
+        _check(L.grffe_batch_create(arr, cnt, ctypes.byref(p), bg_arr, _stream(), ctypes.byref(h)))
+        self._h = h
+        self.count = cnt
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().grffe_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def size(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().grffe_batch_size(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def _dims(self, k):
+        E, N = self.shapes[k]
+        return E, (N + 1) ** 3, (2 * N + 1) ** 3
+
+    def init_from_fd(self, u_fds, forced=None):
+        if len(u_fds) != self.count:
+            raise GrffeError("one FD array per domain")
+        for k, u in enumerate(u_fds):
+            E, _, mm = self._dims(k)
+            if tuple(u.shape) != (9, E, mm):
+                raise GrffeError(f"u_fd[{k}] must have shape {(9, E, mm)}")
+            _ptr(u)
+        ua = (ctypes.c_void_p * self.count)(*[u.data_ptr() for u in u_fds])
+        fa = None
+        if forced is not None:
+            fa = (ctypes.c_void_p * self.count)(*[(f.data_ptr() if f is not None else None) for f in forced])
+        _check(lib().grffe_batch_init_from_fd(self._h, ua, fa, _stream()))
+
+    def get_state(self, k):
+        import torch
+        E, nn, mm = self._dims(k)
+        dg = torch.empty((9, E, nn), dtype=torch.float64, device="cuda")
+        fd = torch.empty((9, E, mm), dtype=torch.float64, device="cuda")
+        rep = torch.empty((E,), dtype=torch.int32, device="cuda")
+        _check(lib().grffe_batch_get_state(self._h, int(k), _ptr(dg), _ptr(fd), _ptr(rep), _stream()))
+        return dg, fd, rep
+
+    def set_state(self, k, dg, fd, rep):
+        E, nn, mm = self._dims(k)
+        if tuple(dg.shape) != (9, E, nn) or tuple(fd.shape) != (9, E, mm) or tuple(rep.shape) != (E,):
+            raise GrffeError("state shapes do not match domain")
+        _check(lib().grffe_batch_set_state(self._h, int(k), _ptr(dg), _ptr(fd), _ptr(rep), _stream()))
+
+    def dt(self, k):
+        v = ctypes.c_double()
+        _check(lib().grffe_batch_get_dt(self._h, int(k), ctypes.byref(v)))
+        return v.value
+
+    def counts(self, k):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().grffe_batch_get_counts(self._h, int(k), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def step(self, n_steps=1, use_graph=True):
+        _check(lib().grffe_batch_step(self._h, int(n_steps), int(bool(use_graph)), _stream()))

@@ -1,0 +1,147 @@
+"""GPU parity of batched stepping: many domains of several degrees advanced by one
+call (degree pools with per-element widths and time steps, one-step HIP graph).
+
+Each member of the batch must match the oracle run on that domain alone (group
+error <= 1e-12, identical representation flags), and the graph replay must give
+bit-for-bit the same state as the same kernels enqueued directly and as the
+member stepped as a stand-alone domain.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import step as OS
+from oracle.domain import DG, FD
+from oracle.domain import Domain as ODomain
+from paper_2404_01531_amd import inputs as I
+
+from helpers import from_dev, group_err, oracle_params, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# Members: degrees 3, 4, 5 (two of degree 5 share a pool) with different element
+# counts and widths, so every domain has its own time step.
+MEMBERS = [
+    I.workload("sheet", n_elem=(4, 2, 2)),
+    I.workload("wave", n_elem=(2, 2, 2), degree=3),
+    I.workload("sheet", n_elem=(3, 2, 1), degree=4, lower=(-1.0, -0.5, -0.25), upper=(1.0, 0.5, 0.25)),
+    I.workload("wave", n_elem=(2, 1, 2), lower=(-1.0, -0.5, -1.0), upper=(1.0, 0.5, 1.0)),
+]
+PARAMS = dict(eta=1e6, cfl=0.25)
+
+
+def _grid(w):
+    return dict(n_elem=w["n_elem"], lower=w["lower"], upper=w["upper"], degree=w["degree"], bc=w["bc"])
+
+
+def _u_fd(w):
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    return I.initial_data(w, xf, yf, zf)
+
+
+def _make_batch(members=MEMBERS, params=PARAMS):
+    from paper_2404_01531_amd import grffe
+    b = grffe.Batch([_grid(w) for w in members], params=params)
+    b.init_from_fd([to_dev(_u_fd(w)) for w in members])
+    return b
+
+
+def test_batch_layout_and_dt():
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    b = _make_batch()
+    assert b.size() == (4, 3)
+    p = grffe.default_params(**PARAMS)
+    for k, w in enumerate(MEMBERS):
+        odom = ODomain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], params=oracle_params(p))
+        assert abs(b.dt(k) - odom.dt()) <= 1e-14 * odom.dt(), k
+    dts = [b.dt(k) for k in range(4)]
+    assert len(set(dts)) == 4, dts
+    torch.cuda.synchronize()
+
+
+def test_batch_matches_oracle_per_domain():
+    _torch()
+    from paper_2404_01531_amd import grffe
+    p = grffe.default_params(**PARAMS)
+    b = _make_batch()
+    nsteps = 3
+    ref = []
+    for k, w in enumerate(MEMBERS):
+        odom = ODomain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], params=oracle_params(p))
+        st = OS.initial_state(odom, _u_fd(w))
+        _, _, grep = b.get_state(k)
+        assert np.array_equal(grep.cpu().numpy(), st.rep), f"member {k}: initial representation differs"
+        for _ in range(nsteps):
+            st = OS.step(odom, st, odom.dt())
+        ref.append(st)
+    b.step(nsteps, use_graph=True)
+    for k, w in enumerate(MEMBERS):
+        st = ref[k]
+        gdg, gfd, grep = b.get_state(k)
+        assert np.array_equal(grep.cpu().numpy(), st.rep), f"member {k}: representation differs"
+        for r, G, R in ((DG, from_dev(gdg, st.dg.shape), st.dg), (FD, from_dev(gfd, st.fd.shape), st.fd)):
+            el = np.nonzero(st.rep == r)[0]
+            if el.size:
+                e = group_err(G[:, el], R[:, el])
+                _say(f"batch member {k} (P{w['degree']}, {w['kind']}) rep {r}: group err "
+                     f"{np.array2string(e, precision=2)}")
+                assert np.all(e <= 1e-12), (k, r, e.tolist())
+        n_dg, n_fd = b.counts(k)
+        assert n_fd == int((st.rep == FD).sum()) and n_dg == int((st.rep == DG).sum())
+
+
+def test_batch_graph_replays_equal_eager_and_standalone():
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    bg = _make_batch()
+    be = _make_batch()
+    solo = grffe.Domain(MEMBERS[3]["n_elem"], MEMBERS[3]["lower"], MEMBERS[3]["upper"], MEMBERS[3]["degree"],
+                        MEMBERS[3]["bc"], params=grffe.default_params(**PARAMS))
+    solo.init_from_fd(to_dev(_u_fd(MEMBERS[3])))
+    junk = torch.zeros(1 << 20, dtype=torch.float64, device="cuda")
+    for it in range(4):
+        bg.step(1, use_graph=True)
+        # eager work of the program between replays
+        junk.add_(1.0)
+        torch.cuda.synchronize()
+        be.step(1, use_graph=False)
+        solo.step(1, solo.dt())
+        for k in range(len(MEMBERS)):
+            a = bg.get_state(k)
+            c = be.get_state(k)
+            for x, y in zip(a, c):
+                assert torch.equal(x, y), f"replay {it + 1}, member {k}: graph and eager differ"
+        s = solo.get_state()
+        for x, y in zip(bg.get_state(3), s):
+            assert torch.equal(x, y), f"replay {it + 1}: batch member and stand-alone domain differ"
+    assert float(junk[0]) == 4.0
+    _say("graph replays: 4 steps bit-identical to eager and stand-alone runs")
+
+
+def test_batch_rejects_bad_input():
+    _torch()
+    from paper_2404_01531_amd import grffe
+    with pytest.raises(grffe.GrffeError):
+        grffe.Batch([], params=PARAMS)
+    bad = _grid(MEMBERS[0])
+    bad["degree"] = 9
+    with pytest.raises(grffe.GrffeError):
+        grffe.Batch([bad], params=PARAMS)
+    b = _make_batch(MEMBERS[:1])
+    with pytest.raises(grffe.GrffeError):
+        b.dt(5)
