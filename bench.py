@@ -42,6 +42,12 @@ FD_FLOP_PER_FACE = 1560 + 150 + 36 + 111 + 18
 # U^{n+1} (288 B).  Mean 288 B; the flat metric adds nothing.
 DG_BYTES_PER_NODE = {1: 216.0, 2: 360.0, 3: 288.0}
 
+# HBM bytes per launch of k_fd_flux (FP64) from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs scaled by a plain copy kernel's reading, valid for the kernel source whose
+# hash is FD_FLUX_TRAFFIC_SRC; reported as null for any other source.
+FD_FLUX_TRAFFIC = None
+FD_FLUX_TRAFFIC_SRC = ""
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -68,6 +74,79 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": n * 8}))
 
 
+def run_workload(w, precision, steps, warmup, families):
+    """Start-up, warm-up and `steps` timed steps of workload w at one precision.
+    Returns the timing record and the final state (device tensors)."""
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+
+    N = w["degree"]
+    n3, m3 = (N + 1) ** 3, (2 * N + 1) ** 3
+    p = grffe.default_params(eta=w["eta"], cfl=w["cfl"], precision=precision)
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p)
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], N)
+    u_fd = I.initial_data(w, xf, yf, zf)
+    dom.init_from_fd(torch.from_numpy(u_fd.reshape(9, dom.E, -1)).cuda())
+    dt = dom.dt()
+    dom.step(warmup, dt)
+    torch.cuda.synchronize()
+    n_dg0, n_fd0 = dom.counts()
+    # timed region: the whole step; the listed kernel families are timed with HIP
+    # events attached to their own dispatches on the launch stream
+    dom.timing_enable(*families)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dom.step(steps, dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {f: dom.timing_read(f) for f in families}
+    dom.timing_enable()
+    n_dg1, n_fd1 = dom.counts()
+    secs = t1 - t0
+    pts = 0.5 * ((n_dg0 + n_dg1) * n3 + (n_fd0 + n_fd1) * m3)
+    rec = dict(secs=secs, value=pts * 3 * steps / secs, pts=pts, dt=dt, E=dom.E, n_dg=(n_dg0, n_dg1),
+               n_fd=(n_fd0, n_fd1), kern=kern)
+    return rec, dom.get_state()
+
+
+def state_diff(a, b):
+    """Max and RMS difference per variable group (E~, B~, psi~, phi~, q~) of two
+    states, each relative to the group's scale in `b` (floored at 1e-3 of the whole
+    state's), over the elements held in the same representation by both."""
+    import numpy as np
+    dga, fda, repa = (x.cpu().numpy() for x in a)
+    dgb, fdb, repb = (x.cpu().numpy() for x in b)
+    same = repa == repb
+    groups = ((0, 3), (3, 6), (6, 7), (7, 8), (8, 9))
+    mx = np.zeros(5)
+    sq = np.zeros(5)
+    ref_sq = np.zeros(5)
+    cnt = np.zeros(5)
+    ref_max = np.zeros(5)
+    for r, A, B in ((0, dga, dgb), (1, fda, fdb)):
+        el = np.nonzero(same & (repb == r))[0]
+        if el.size == 0:
+            continue
+        A, B = A[:, el], B[:, el]
+        for g, (lo, hi) in enumerate(groups):
+            d = A[lo:hi] - B[lo:hi]
+            mx[g] = max(mx[g], np.abs(d).max())
+            sq[g] += (d ** 2).sum()
+            ref_sq[g] += (B[lo:hi] ** 2).sum()
+            cnt[g] += d.size
+            ref_max[g] = max(ref_max[g], np.abs(B[lo:hi]).max())
+    rms_ref = np.sqrt(ref_sq / np.maximum(cnt, 1))
+    rms_all = np.sqrt(ref_sq.sum() / max(cnt.sum(), 1))
+    max_all = ref_max.max()
+    rel_max = mx / np.maximum(ref_max, 1e-3 * max_all)
+    rel_l2 = np.sqrt(sq / np.maximum(cnt, 1)) / np.maximum(rms_ref, 1e-3 * rms_all)
+    names = ["E", "B", "psi", "phi", "q"]
+    return {"max": dict(zip(names, rel_max.tolist())), "l2": dict(zip(names, rel_l2.tolist())),
+            "elements_compared": int(same.sum()), "elements_rep_differs": int((~same).sum())}
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -77,7 +156,6 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
                                    "rerun with --gpus 1"}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2404_01531_amd import grffe
@@ -85,66 +163,54 @@ def main():
 
     torch.cuda.set_device(0)
     w = I.workload(args.workload)
-    N = w["degree"]
-    n3, m3 = (N + 1) ** 3, (2 * N + 1) ** 3
-    p = grffe.default_params(eta=w["eta"], cfl=w["cfl"])
-    exc = I.excision_mask(w) if w.get("curved") else None
-    bg = None
     if w.get("curved"):
         raise SystemExit("the benchmark workload is flat; curved workloads are parity cases")
-    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p, bg=bg, excised=exc)
-    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], N)
-    u_fd = I.initial_data(w, xf, yf, zf)
-    dom.init_from_fd(torch.from_numpy(u_fd.reshape(9, dom.E, -1)).cuda())
-    dt = dom.dt()
-    dom.step(args.warmup, dt)
-    torch.cuda.synchronize()
-    n_dg0, n_fd0 = dom.counts()
-    print(f"# warm: {n_dg0} DG + {n_fd0} FD elements, dt {dt:.6e}", file=sys.stderr, flush=True)
-
-    # timed region: the whole step; the dominant kernel (FD face fluxes) is timed
-    # with HIP events recorded on its launch stream around every launch
-    dom.timing_enable(grffe.KERNEL_FAMILIES["fd_flux"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dom.step(args.steps, dt)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    k_ms, k_launches = dom.timing_read()
-    dom.timing_enable(0)
-    n_dg1, n_fd1 = dom.counts()
-    secs = t1 - t0
-    pts = 0.5 * ((n_dg0 + n_dg1) * n3 + (n_fd0 + n_fd1) * m3)
-    updates = pts * 3 * args.steps
-    value = updates / secs
+    N = w["degree"]
     m = 2 * N + 1
-    n_fd = 0.5 * (n_fd0 + n_fd1)
-    flop_per_launch = n_fd * 3 * (m + 1) * m * m * FD_FLOP_PER_FACE
-    avg_s = (k_ms / 1e3) / max(k_launches, 1)
-    achieved = flop_per_launch / avg_s / 1e12
-    print(f"# {args.steps} steps in {secs:.4f} s; fd_flux {k_launches} launches, mean {avg_s * 1e6:.2f} us",
-          file=sys.stderr, flush=True)
-    # secondary: the fused DG substep kernel (HBM bound) timed over a short extra run
-    dom.timing_enable(grffe.KERNEL_FAMILIES["dg_substep"])
-    dom.step(max(1, args.steps // 10), dt)
-    dg_ms, dg_launches = dom.timing_read()
-    dom.timing_enable(0)
-    n_dg = 0.5 * (n_dg0 + n_dg1)
-    dg_bytes = n_dg * n3 * (sum(DG_BYTES_PER_NODE.values()) / 3.0)
-    dg_avg = (dg_ms / 1e3) / max(dg_launches, 1)
+    n3 = (N + 1) ** 3
+    fam_fd, fam_dg = grffe.KERNEL_FAMILIES["fd_flux"], grffe.KERNEL_FAMILIES["dg_substep"]
+    res = {}
+    states = {}
+    for prec, name in ((0, "fp64"), (1, "mixed")):
+        rec, st = run_workload(w, prec, args.steps, args.warmup, (fam_fd, fam_dg))
+        res[name] = rec
+        states[name] = st
+        k_ms, k_n = rec["kern"][fam_fd]
+        print(f"# {name}: {args.steps} steps in {rec['secs']:.4f} s, {rec['n_dg']} DG / {rec['n_fd']} FD elements; "
+              f"fd_flux {k_n} launches, mean {k_ms / max(k_n, 1) * 1e3:.2f} us", file=sys.stderr, flush=True)
 
+    def roofline_fd(rec):
+        k_ms, k_n = rec["kern"][fam_fd]
+        n_fd = 0.5 * sum(rec["n_fd"])
+        flop = n_fd * 3 * (m + 1) * m * m * FD_FLOP_PER_FACE
+        avg = (k_ms / 1e3) / max(k_n, 1)
+        ach = flop / avg / 1e12
+        return {"kernel": "k_fd_flux (FD subcell WENO5-Z face fluxes)", "bound": "alu", "achieved": ach,
+                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK_TFLOPS,
+                "traffic": FD_FLUX_TRAFFIC if kernel_source_hash() == FD_FLUX_TRAFFIC_SRC else None,
+                "mean_launch_us": avg * 1e6, "launches": int(k_n), "flop_per_launch": flop}
+
+    def roofline_dg(rec):
+        k_ms, k_n = rec["kern"][fam_dg]
+        n_dg = 0.5 * sum(rec["n_dg"])
+        byt = n_dg * n3 * (sum(DG_BYTES_PER_NODE.values()) / 3.0)
+        avg = (k_ms / 1e3) / max(k_n, 1)
+        return {"kernel": "k_dg_substep (fused DG substep)", "bound": "hbm", "achieved": byt / avg / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": byt / avg / 1e9 / HBM_PEAK_GBS,
+                "mean_launch_us": avg * 1e6, "launches": int(k_n), "bytes_per_launch": byt}
+
+    f64, mix = res["fp64"], res["mixed"]
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_sample_steps)
-
     out = {
         "metric": "grid-point updates/s per RK substep, FP64 vs mixed, at stated L2 error",
-        "value": value,
+        "value": f64["value"],
         "unit": "grid-point updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": secs * 1e3 / args.steps,
+        "ms_per_step": f64["secs"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -152,20 +218,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": "flat current sheet, periodic [-1,1]^3, 8^3 elements DG-P5 / FD 11^3, "
                                "eta 1e6, CFL 0.25, adaptive DG-FD, seed 1002",
-                   "elements": int(dom.E), "fd_elements": [int(n_fd0), int(n_fd1)],
-                   "points_per_substep": pts, "dt": dt},
-        "roofline": {"kernel": "k_fd_flux (FD subcell WENO5-Z face fluxes)", "bound": "alu",
-                     "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
-                     "mean_launch_us": avg_s * 1e6, "launches": int(k_launches),
-                     "flop_per_launch": flop_per_launch},
-        "roofline_dg": {"kernel": "k_dg_substep (fused DG substep)", "bound": "hbm",
-                        "achieved": dg_bytes / dg_avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": dg_bytes / dg_avg / 1e9 / HBM_PEAK_GBS, "mean_launch_us": dg_avg * 1e6,
-                        "bytes_per_launch": dg_bytes},
+                   "elements": int(f64["E"]), "fd_elements": [int(x) for x in f64["n_fd"]],
+                   "points_per_substep": f64["pts"], "dt": f64["dt"]},
+        "roofline": roofline_fd(f64),
+        "roofline_dg": roofline_dg(f64),
+        "mixed": {"value": mix["value"], "ms_per_step": mix["secs"] * 1e3 / args.steps,
+                  "dtype": "f64 state, f32 fluxes and DG contractions",
+                  "fd_elements": [int(x) for x in mix["n_fd"]],
+                  "error_vs_fp64_run": state_diff(states["mixed"], states["fp64"]),
+                  "roofline": roofline_fd(mix), "roofline_dg": roofline_dg(mix)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def kernel_source_hash():
+    """SHA-256 (first 16 hex digits) of the FD kernel source and the headers it includes."""
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(ROOT, "paper_2404_01531_amd", "csrc")
+    for f in ("kernels_fd.hip", "common.h", "physics.h", "grffe_internal.h"):
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(w, steps):

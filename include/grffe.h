@@ -57,6 +57,14 @@ extern "C" {
 #define GRFFE_HYBRID_ADAPTIVE 1 /* Sec. III C 1: indicator decides */
 #define GRFFE_HYBRID_FORCED 2   /* representation fixed by a mask (Sec. IV D 2 style) */
 
+/* Arithmetic of the right-hand side.  FP64 throughout, or mixed: the pointwise
+ * fluxes, the DG derivative and lift contractions (accumulated in FP32) and the
+ * FD face fluxes, Rusanov and corrector in FP32; the state and its stage
+ * combinations, the sources, the implicit solve, the clamp, the filter, the
+ * WENO5-Z reconstruction, the indicator and every DG<->FD transfer stay FP64. */
+#define GRFFE_PRECISION_FP64 0
+#define GRFFE_PRECISION_MIXED 1
+
 /* Element grid (Sec. III A): an axis-aligned box [lower, upper] cut into
  * n_elem[0] x n_elem[1] x n_elem[2] equal elements of degree N (3 <= N <= 7).
  * bc[2d + s] is the boundary kind of the lower (s = 0) / upper (s = 1) face
@@ -91,7 +99,7 @@ typedef struct grffe_params {
   int32_t ff_clamp;     /* 1: algebraic E.B = 0, E < B fix after every substep */
   double ff_margin;     /* E^2 <= (1 - margin) B^2 in the clamp */
   int32_t hybrid;       /* GRFFE_HYBRID_* */
-  int32_t precision;    /* 0: FP64 (the only mode built) */
+  int32_t precision;    /* GRFFE_PRECISION_* */
 } grffe_params;
 
 typedef struct grffe_domain grffe_domain;
@@ -165,14 +173,16 @@ int grffe_get_counts(grffe_domain* dom, int32_t* n_dg, int32_t* n_fd);
  * of doubles written (out may be NULL to query). */
 int grffe_operator(int degree, int which, double* out, int capacity);
 
-/* Kernel timing with HIP events recorded on the launch stream around every
- * launch of one kernel family: 0 off, 1 fused DG substep, 2 FD face fluxes,
- * 3 FD update, 4 FD stage values, 5 FD traces, 6 DG ghost slabs,
- * 7 DG->FD projection of flagged elements, 8 FD->DG check.  grffe_timing_read
- * synchronises the stream of the last timed launch, returns the summed
- * duration (ms) and the number of timed launches, and resets the counters. */
-int grffe_timing_enable(grffe_domain* dom, int family);
-int grffe_timing_read(grffe_domain* dom, double* total_ms, int64_t* launches);
+/* Kernel timing with HIP events attached to every launch of the selected kernel
+ * families (the events bracket the kernel's own dispatch on its launch stream).
+ * Families: 1 fused DG substep, 2 FD face fluxes, 3 FD update, 4 FD stage
+ * values, 5 FD traces, 6 DG ghost slabs, 7 DG->FD projection of flagged
+ * elements, 8 FD->DG check.  mask = OR of (1 << family), 0 = off; enabling
+ * resets every counter.  grffe_timing_read synchronises the stream of the last
+ * timed launch, returns the summed duration (ms) and the number of timed launches
+ * of one family, and resets that family's counters. */
+int grffe_timing_enable(grffe_domain* dom, int mask);
+int grffe_timing_read(grffe_domain* dom, int family, double* total_ms, int64_t* launches);
 
 /* Batches: many independent domains advanced together, each with its own grid,
  * degree (3..7) and CFL time step (Eq. (spectre DG CFL condition) per domain).

@@ -96,6 +96,7 @@ KArgs make_args(grffe_domain* d) {
   a.fd_order = d->par.fd_order;
   a.ff_clamp = d->par.ff_clamp;
   a.hybrid = d->par.hybrid;
+  a.precision = d->par.precision;
   a.weno_eps = d->par.weno_eps;
   a.ff_margin = d->par.ff_margin;
   a.parts = GRFFE_PART_ALL;
@@ -122,8 +123,10 @@ static void free_all(grffe_domain* d) {
 
 extern "C" int grffe_destroy(grffe_domain* d) {
   if (!d) return GRFFE_OK;
-  for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
-  d->ev.clear();
+  for (auto& v : d->ev) {
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    v.clear();
+  }
   free_all(d);
   delete d;
   return GRFFE_OK;
@@ -156,7 +159,8 @@ static int validate(const grffe_grid* g, const grffe_params* p) {
   for (int d = 0; d < 3; ++d)
     if ((g->bc[2 * d] == GRFFE_BC_PERIODIC) != (g->bc[2 * d + 1] == GRFFE_BC_PERIODIC))
       return fail(GRFFE_EINVAL, "periodic faces must come in pairs");
-  if (p->precision != 0) return fail(GRFFE_EUNSUPPORTED, "only FP64 is built");
+  if (p->precision != GRFFE_PRECISION_FP64 && p->precision != GRFFE_PRECISION_MIXED)
+    return fail(GRFFE_EUNSUPPORTED, "precision must be GRFFE_PRECISION_FP64 or GRFFE_PRECISION_MIXED");
   if (p->hybrid < 0 || p->hybrid > 2) return fail(GRFFE_EINVAL, "hybrid must be 0, 1 or 2");
   if (p->fd_order != 2 && p->fd_order != 4) return fail(GRFFE_EINVAL, "fd_order must be 2 or 4");
   if (p->tci_mode != 1 && p->tci_mode != 2) return fail(GRFFE_EINVAL, "tci_mode must be 1 or 2");
@@ -429,27 +433,30 @@ LaunchEvents& armed_launch_events() {
 // the timed one; the launch attaches the events to the kernel's own dispatch.
 struct TimedLaunch {
   grffe_domain* d;
+  int fam;
   bool on;
   hipStream_t st;
-  TimedLaunch(grffe_domain* dd, int family, hipStream_t s) : d(dd), on(dd->timed_family == family), st(s) {
+  TimedLaunch(grffe_domain* dd, int family, hipStream_t s)
+      : d(dd), fam(family), on(((dd->timed_mask >> family) & 1) != 0), st(s) {
     if (!on) return;
-    if (d->ev_used + 2 > d->ev.size()) {
+    auto& ev = d->ev[fam];
+    if (d->ev_used[fam] + 2 > ev.size()) {
       hipEvent_t a, b;
       if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
         on = false;
         return;
       }
-      d->ev.push_back(a);
-      d->ev.push_back(b);
+      ev.push_back(a);
+      ev.push_back(b);
     }
-    armed_launch_events().start = d->ev[d->ev_used];
-    armed_launch_events().stop = d->ev[d->ev_used + 1];
+    armed_launch_events().start = ev[d->ev_used[fam]];
+    armed_launch_events().stop = ev[d->ev_used[fam] + 1];
   }
   ~TimedLaunch() {
     if (!on) return;
     armed_launch_events().start = nullptr;
     armed_launch_events().stop = nullptr;
-    d->ev_used += 2;
+    d->ev_used[fam] += 2;
     d->ev_stream = st;
   }
 };
@@ -469,28 +476,31 @@ static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   { TimedLaunch t(d, 3, st); launch_fd_update(a, N, cv, mode, st); }
 }
 
-extern "C" int grffe_timing_enable(grffe_domain* d, int family) {
+extern "C" int grffe_timing_enable(grffe_domain* d, int mask) {
   if (int rc = check_dom(d)) return rc;
-  if (family < 0 || family > 8) return fail(GRFFE_EINVAL, "unknown kernel family");
-  d->timed_family = family;
-  d->ev_used = 0;
+  if (mask < 0 || mask >= (1 << grffe_domain::NFAM) || (mask & 1))
+    return fail(GRFFE_EINVAL, "timing mask holds bits 1..8 only");
+  d->timed_mask = mask;
+  for (size_t& u : d->ev_used) u = 0;
   return GRFFE_OK;
 }
 
-extern "C" int grffe_timing_read(grffe_domain* d, double* total_ms, int64_t* launches) {
+extern "C" int grffe_timing_read(grffe_domain* d, int family, double* total_ms, int64_t* launches) {
   if (int rc = check_dom(d)) return rc;
+  if (family < 1 || family >= grffe_domain::NFAM) return fail(GRFFE_EINVAL, "unknown kernel family");
   double tot = 0.0;
-  if (d->ev_used) {
+  const size_t used = d->ev_used[family];
+  if (used) {
     HIPCHK(hipStreamSynchronize(d->ev_stream));
-    for (size_t k = 0; k < d->ev_used; k += 2) {
+    for (size_t k = 0; k < used; k += 2) {
       float ms = 0.0f;
-      HIPCHK(hipEventElapsedTime(&ms, d->ev[k], d->ev[k + 1]));
+      HIPCHK(hipEventElapsedTime(&ms, d->ev[family][k], d->ev[family][k + 1]));
       tot += ms;
     }
   }
   if (total_ms) *total_ms = tot;
-  if (launches) *launches = (int64_t)(d->ev_used / 2);
-  d->ev_used = 0;
+  if (launches) *launches = (int64_t)(used / 2);
+  d->ev_used[family] = 0;
   return GRFFE_OK;
 }
 

@@ -80,7 +80,7 @@ struct KArgs {
   // scheme parameters; dt > 0 overrides the per-element time steps
   double dt, eta, kpsi, kphi;
   double tci_thr, tci_thr_fd;
-  int tci_mode, filter_on, fd_order, ff_clamp, hybrid;
+  int tci_mode, filter_on, fd_order, ff_clamp, hybrid, precision;
   double weno_eps, ff_margin;
 };
 
@@ -127,9 +127,11 @@ struct grffe_domain {
   double lambda_max = 0.0;
   std::vector<void*> allocs;
   // kernel timing (one family at a time)
-  int timed_family = 0;
-  std::vector<hipEvent_t> ev;  // start/stop pairs
-  size_t ev_used = 0;
+  // kernel timing: bit f of timed_mask times family f (1..8)
+  static constexpr int NFAM = 9;
+  int timed_mask = 0;
+  std::vector<hipEvent_t> ev[NFAM];  // start/stop pairs per family
+  size_t ev_used[NFAM] = {};
   hipStream_t ev_stream = nullptr;
 };
 

@@ -54,13 +54,14 @@ __device__ inline void external_state(const KArgs& a, int e, int f, int i, int j
   }
 }
 
-template <int N, bool CURVED, int MODE>
+template <int N, bool CURVED, int MODE, typename R>
 __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn, TPB = Dm::tpb;
   __shared__ double sF[NV * nn];
   __shared__ double sred[2 * (TPB / 64)];
-  __shared__ double sop[3 * n * n];  // D, filter, indicator operator
+  __shared__ double sop[2 * n * n];  // filter, indicator operator
+  __shared__ R sD[n * n];            // derivative matrix in the flux arithmetic type
   const int e = blockIdx.x;
   if (!a.live[e] || a.rep0[e] != 0) return;
   const int t = threadIdx.x;
@@ -68,63 +69,84 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
   const int p = act ? t : 0;
   const int i = p % n, j = (p / n) % n, k = p / (n * n);
   for (int q = t; q < n * n; q += TPB) {
-    sop[q] = a.ops->D[q];
-    sop[n * n + q] = a.ops->F[q];
-    sop[2 * n * n + q] = a.ops->L[q];
+    sD[q] = (R)a.ops->D[q];
+    sop[q] = a.ops->F[q];
+    sop[n * n + q] = a.ops->L[q];
   }
   Metric M;
   load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
-  double X[NV], J[3], Jd[3], Je[3], dU[NV];
+  double X[NV], Jd[3], Je[3], dU[NV];
   stage_input<MODE>(a.dg, a.E, nn, e, p, M, a, X);
   current(X, M, a.eta, Jd, Je);
-  for (int c = 0; c < 3; ++c) J[c] = Jd[c] + Je[c];
   {
     MetricDeriv Dv;
     load_deriv<CURVED>(a.bg_dg, a.E, nn, e, p, Dv);
     source_explicit<CURVED>(X, M, Dv, Jd, dU);
   }
+  // fluxes, derivative and lift in R (FP64, or FP32 in the mixed-precision mode),
+  // accumulated in R and added to the FP64 sources
+  MetricT<R> Mr;
+  metric_cast(M, Mr);
+  R Xr[NV], Jr[3], dUr[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    Xr[v] = (R)X[v];
+    dUr[v] = 0;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) Jr[c] = (R)(Jd[c] + Je[c]);
+  R* sFr = reinterpret_cast<R*>(sF);
   const int idx[3] = {i, j, k};
   const int strideN[3] = {1, n, n * n};
   for (int d = 0; d < 3; ++d) {
-    double F[NV];
-    flux_any(d, X, J, M, F);
+    R F[NV];
+    flux_any(d, Xr, Jr, Mr, F);
     __syncthreads();
     if (act)
-      for (int v = 0; v < NV; ++v) sF[v * nn + p] = F[v];
+      for (int v = 0; v < NV; ++v) sFr[v * nn + p] = F[v];
     __syncthreads();
     const double sc = 2.0 / h_of(a, e, d);
     const int id = idx[d];
     const int p0 = p - id * strideN[d];
-    const double* Drow = sop + id * n;
+    const R* Drow = sD + id * n;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double acc = 0.0;
+      R acc = 0;
 #pragma unroll
-      for (int q = 0; q < n; ++q) acc += Drow[q] * sF[v * nn + p0 + q * strideN[d]];
-      dU[v] -= sc * acc;
+      for (int q = 0; q < n; ++q) acc += Drow[q] * sFr[v * nn + p0 + q * strideN[d]];
+      dUr[v] -= (R)sc * acc;
     }
     if (act && (id == 0 || id == N)) {
       const int s = (id == N) ? 1 : 0;
-      double Wx[NV], Jx[3], Fx[NV], Fs[NV];
+      double Wx[NV], Jx[3];
       Metric Mx;
       external_state<N, CURVED, MODE>(a, e, 2 * d + s, i, j, k, X, M, Wx, Jx, Mx);
-      flux_any(d, Wx, Jx, Mx, Fx);
-      const double lam = CURVED ? fmax(char_speed(d, M), char_speed(d, Mx)) : 1.0;
+      MetricT<R> Mxr;
+      metric_cast(Mx, Mxr);
+      R Wr[NV], Jxr[3], Fx[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Wr[v] = (R)Wx[v];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Jxr[c] = (R)Jx[c];
+      flux_any(d, Wr, Jxr, Mxr, Fx);
+      const R lam = CURVED ? (R)fmax(char_speed(d, M), char_speed(d, Mx)) : R(1);
       if (s == 0) {
-        const double wl = sc / a.ops->w[0];
+        const R wl = (R)(sc / a.ops->w[0]);
         for (int v = 0; v < NV; ++v) {
-          Fs[v] = 0.5 * (Fx[v] + F[v]) - 0.5 * lam * (X[v] - Wx[v]);
-          dU[v] += wl * (Fs[v] - F[v]);
+          const R Fs = R(0.5) * (Fx[v] + F[v]) - R(0.5) * lam * (Xr[v] - Wr[v]);
+          dUr[v] += wl * (Fs - F[v]);
         }
       } else {
-        const double wr = sc / a.ops->w[N];
+        const R wr = (R)(sc / a.ops->w[N]);
         for (int v = 0; v < NV; ++v) {
-          Fs[v] = 0.5 * (F[v] + Fx[v]) - 0.5 * lam * (Wx[v] - X[v]);
-          dU[v] -= wr * (Fs[v] - F[v]);
+          const R Fs = R(0.5) * (F[v] + Fx[v]) - R(0.5) * lam * (Wr[v] - Xr[v]);
+          dUr[v] -= wr * (Fs - F[v]);
         }
       }
     }
   }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dU[v] += (double)dUr[v];
   if (MODE == MODE_RHS) {
     if (!act) return;
     double St[NV];
@@ -145,7 +167,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
       __syncthreads();
       const int id = idx[d];
       const int p0 = p - id * strideN[d];
-      const double* Frow = sop + n * n + id * n;
+      const double* Frow = sop + id * n;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double acc = 0.0;
@@ -168,7 +190,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
       __syncthreads();
       const int id = idx[d];
       const int p0 = p - id * strideN[d];
-      const double* Lrow = sop + 2 * n * n + id * n;
+      const double* Lrow = sop + n * n + id * n;
       double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < n; ++q) acc += Lrow[q] * sF[p0 + q * strideN[d]];
@@ -267,15 +289,21 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
   }
 }
 
-template <int N, bool CURVED>
-static void launch_dg_substep_t(const KArgs& a, int mode, hipStream_t s) {
+template <int N, bool CURVED, typename R>
+static void launch_dg_substep_r(const KArgs& a, int mode, hipStream_t s) {
   dim3 grid(a.E), block(Dims<N>::tpb);
   switch (mode) {
-    case MODE_RHS: launch_kernel(k_dg_substep<N, CURVED, MODE_RHS>, grid, block, s, a); break;
-    case MODE_SUB1: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB1>, grid, block, s, a); break;
-    case MODE_SUB2: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB2>, grid, block, s, a); break;
-    default: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB3>, grid, block, s, a); break;
+    case MODE_RHS: launch_kernel(k_dg_substep<N, CURVED, MODE_RHS, R>, grid, block, s, a); break;
+    case MODE_SUB1: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB1, R>, grid, block, s, a); break;
+    case MODE_SUB2: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB2, R>, grid, block, s, a); break;
+    default: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB3, R>, grid, block, s, a); break;
   }
+}
+
+template <int N, bool CURVED>
+static void launch_dg_substep_t(const KArgs& a, int mode, hipStream_t s) {
+  if (a.precision == GRFFE_PRECISION_MIXED) launch_dg_substep_r<N, CURVED, float>(a, mode, s);
+  else launch_dg_substep_r<N, CURVED, double>(a, mode, s);
 }
 
 template <int N, bool CURVED>

@@ -302,7 +302,7 @@ __device__ inline CellSrc cell_source(const KArgs& a, int e, int d, int c, int t
 // fluxes of the corrector are formed once per cell, and finally every (face,
 // pencil) forms the Rusanov flux and the fourth-order corrected flux.  Only
 // J~^d enters F^d, so ten components (U and J~^d) are reconstructed.
-template <int N, bool CURVED>
+template <int N, bool CURVED, typename R>
 __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   using Dm = Dims<N>;
   constexpr int m = Dm::m, mm = Dm::mm;
@@ -397,26 +397,30 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
     if (d == 0) tix = f3 + (m + 1) * (t13 + m * t2);
     else if (d == 1) tix = t13 + m * (f3 + (m + 1) * t2);
     else tix = t13 + m * (t2 + m * f3);
-    double WL[NR], WR[NR];
+    // face fluxes, Rusanov and the corrector in R (FP64, or FP32 in the
+    // mixed-precision mode; the reconstruction above is always FP64)
+    R WL[NR], WR[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      WL[k] = sLf[(k * L + t13) * FP + f3];
-      WR[k] = sRf[(k * L + t13) * FP + f3];
+      WL[k] = (R)sLf[(k * L + t13) * FP + f3];
+      WR[k] = (R)sRf[(k * L + t13) * FP + f3];
     }
     Metric Mf;
     load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nf, a.E, nf, e, tix, Mf);
-    double Ft[NV];
-    flux_any_jd(d, WL, WL[NV], Mf, Fh);
-    flux_any_jd(d, WR, WR[NV], Mf, Ft);
-    const double lam = CURVED ? char_speed(d, Mf) : 1.0;
+    MetricT<R> Mfr;
+    metric_cast(Mf, Mfr);
+    R Fr[NV], Ft[NV];
+    flux_any_jd(d, WL, WL[NV], Mfr, Fr);
+    flux_any_jd(d, WR, WR[NV], Mfr, Ft);
+    const R lam = CURVED ? (R)char_speed(d, Mf) : R(1);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fh[v] = 0.5 * (Fh[v] + Ft[v]) - 0.5 * lam * (WR[v] - WL[v]);
+    for (int v = 0; v < NV; ++v) Fr[v] = R(0.5) * (Fr[v] + Ft[v]) - R(0.5) * lam * (WR[v] - WL[v]);
     if (a.fd_order == 4) {
       // cell-centred fluxes of cells f-1 and f (extended indices f+2 and f+3)
       for (int side = 0; side < 2; ++side) {
-        double W[NR];
+        R W[NR];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) W[k] = sW[(k * L + t13) * C + f3 + 2 + side];
+        for (int k = 0; k < NR; ++k) W[k] = (R)sW[(k * L + t13) * C + f3 + 2 + side];
         Metric Mc;
         if (CURVED) {
           double fm[10];
@@ -427,14 +431,18 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
         } else {
           metric_flat(Mc);
         }
-        double Fc[NV];
-        flux_any_jd(d, W, W[NV], Mc, Fc);
+        MetricT<R> Mcr;
+        metric_cast(Mc, Mcr);
+        R Fc[NV];
+        flux_any_jd(d, W, W[NV], Mcr, Fc);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ft[v] = side ? Ft[v] + Fc[v] : Fc[v];
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Fh[v] = Fh[v] - (Ft[v] - 2.0 * Fh[v]) / 6.0;
+      for (int v = 0; v < NV; ++v) Fr[v] = Fr[v] - (Ft[v] - R(2) * Fr[v]) / R(6);
     }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fh[v] = (double)Fr[v];
   }
   __syncthreads();
   double* sFh = sLf;  // the reconstructed states are no longer needed
@@ -858,7 +866,8 @@ template <int N, bool CURVED>
 static void fd_flux_t(const KArgs& a, hipStream_t s) {
   constexpr int m = Dims<N>::m;
   dim3 grid(m, 3, a.E), block(256);
-  launch_kernel(k_fd_flux<N, CURVED>, grid, block, s, a);
+  if (a.precision == GRFFE_PRECISION_MIXED) launch_kernel(k_fd_flux<N, CURVED, float>, grid, block, s, a);
+  else launch_kernel(k_fd_flux<N, CURVED, double>, grid, block, s, a);
 }
 
 void launch_fd_flux(const KArgs& a, int N, bool curved, hipStream_t s) {

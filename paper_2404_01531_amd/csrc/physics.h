@@ -16,9 +16,24 @@
 namespace grffe {
 
 // Metric at one point.  g and gi are symmetric, stored xx, xy, xz, yy, yz, zz.
-struct Metric {
-  double alpha, beta[3], g[6], gi[6], sqrtg;
+template <typename T>
+struct MetricT {
+  T alpha, beta[3], g[6], gi[6], sqrtg;
 };
+using Metric = MetricT<double>;
+
+// The metric rounded to another arithmetic type (the FP32 flux evaluation of the
+// mixed-precision mode).
+template <typename T>
+__device__ inline void metric_cast(const Metric& M, MetricT<T>& o) {
+  o.alpha = (T)M.alpha;
+  o.sqrtg = (T)M.sqrtg;
+  for (int k = 0; k < 3; ++k) o.beta[k] = (T)M.beta[k];
+  for (int k = 0; k < 6; ++k) {
+    o.g[k] = (T)M.g[k];
+    o.gi[k] = (T)M.gi[k];
+  }
+}
 
 __host__ __device__ inline int sym(int i, int j) {
   // index of (i, j) in the packed symmetric storage
@@ -59,7 +74,8 @@ __device__ inline void metric_from10(const double f[10], Metric& M) {
   M.sqrtg = sqrt(det);
 }
 
-__device__ inline void lower3(const Metric& M, const double* v, double* o) {
+template <typename T>
+__device__ inline void lower3(const MetricT<T>& M, const T* v, T* o) {
   o[0] = M.g[0] * v[0] + M.g[1] * v[1] + M.g[2] * v[2];
   o[1] = M.g[1] * v[0] + M.g[3] * v[1] + M.g[4] * v[2];
   o[2] = M.g[2] * v[0] + M.g[4] * v[1] + M.g[5] * v[2];
@@ -105,30 +121,31 @@ __device__ inline void current_total(const double* U, const Metric& M, double et
 }
 
 // F^d(U) with jd = J~^d, the component along d of the total densitized current
-// (Eq. fluxes); only that component enters F^d.
-template <int D>
-__device__ inline void flux_dir(const double* U, double jd, const Metric& M, double* F) {
-  const double* E = U;
-  const double* B = U + 3;
-  double El[3], Bl[3];
+// (Eq. fluxes); only that component enters F^d.  T is the arithmetic type (FP64,
+// or FP32 for the flux evaluation of the mixed-precision mode).
+template <int D, typename T>
+__device__ inline void flux_dir(const T* U, T jd, const MetricT<T>& M, T* F) {
+  const T* E = U;
+  const T* B = U + 3;
+  T El[3], Bl[3];
   lower3(M, E, El);
   lower3(M, B, Bl);
-  const double a = M.alpha, bd = M.beta[D], isg = 1.0 / M.sqrtg;
-  const double psi = U[6], phi = U[7];
+  const T a = M.alpha, bd = M.beta[D], isg = T(1) / M.sqrtg;
+  const T psi = U[6], phi = U[7];
   // [i D k] X_k for i = 0..2
-  double eB[3], eE[3];
+  T eB[3], eE[3];
   if (D == 0) {
-    eB[0] = 0.0; eB[1] = -Bl[2]; eB[2] = Bl[1];
-    eE[0] = 0.0; eE[1] = -El[2]; eE[2] = El[1];
+    eB[0] = 0; eB[1] = -Bl[2]; eB[2] = Bl[1];
+    eE[0] = 0; eE[1] = -El[2]; eE[2] = El[1];
   } else if (D == 1) {
-    eB[0] = Bl[2]; eB[1] = 0.0; eB[2] = -Bl[0];
-    eE[0] = El[2]; eE[1] = 0.0; eE[2] = -El[0];
+    eB[0] = Bl[2]; eB[1] = 0; eB[2] = -Bl[0];
+    eE[0] = El[2]; eE[1] = 0; eE[2] = -El[0];
   } else {
-    eB[0] = -Bl[1]; eB[1] = Bl[0]; eB[2] = 0.0;
-    eE[0] = -El[1]; eE[1] = El[0]; eE[2] = 0.0;
+    eB[0] = -Bl[1]; eB[1] = Bl[0]; eB[2] = 0;
+    eE[0] = -El[1]; eE[1] = El[0]; eE[2] = 0;
   }
   for (int i = 0; i < 3; ++i) {
-    const double gid = M.gi[sym(i, D)];
+    const T gid = M.gi[sym(i, D)];
     F[i] = -bd * E[i] + a * (gid * psi - eB[i] * isg);
     F[3 + i] = -bd * B[i] + a * (gid * phi + eE[i] * isg);
   }
@@ -138,14 +155,16 @@ __device__ inline void flux_dir(const double* U, double jd, const Metric& M, dou
 }
 
 // F^d with the whole current vector J (its component d is used).
-__device__ inline void flux_any(int d, const double* U, const double* J, const Metric& M, double* F) {
+template <typename T>
+__device__ inline void flux_any(int d, const T* U, const T* J, const MetricT<T>& M, T* F) {
   if (d == 0) flux_dir<0>(U, J[0], M, F);
   else if (d == 1) flux_dir<1>(U, J[1], M, F);
   else flux_dir<2>(U, J[2], M, F);
 }
 
 // F^d with the scalar jd = J~^d.
-__device__ inline void flux_any_jd(int d, const double* U, double jd, const Metric& M, double* F) {
+template <typename T>
+__device__ inline void flux_any_jd(int d, const T* U, T jd, const MetricT<T>& M, T* F) {
   if (d == 0) flux_dir<0>(U, jd, M, F);
   else if (d == 1) flux_dir<1>(U, jd, M, F);
   else flux_dir<2>(U, jd, M, F);

@@ -90,7 +90,7 @@ def lib():
     L.grffe_get_counts.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.grffe_operator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(dbl), ctypes.c_int]
     L.grffe_timing_enable.argtypes = [vp, ctypes.c_int]
-    L.grffe_timing_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
+    L.grffe_timing_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
     pvp = ctypes.POINTER(vp)
     L.grffe_batch_create.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(Params), pvp, vp, pvp]
     L.grffe_batch_destroy.argtypes = [vp]
@@ -280,13 +280,18 @@ class Domain:
         _check(lib().grffe_get_dt(self._h, ctypes.byref(v)))
         return v.value
 
-    def timing_enable(self, family):
-        """Time every launch of one kernel family with HIP events (see grffe_timing_enable)."""
-        _check(lib().grffe_timing_enable(self._h, int(family)))
+    def timing_enable(self, *families):
+        """Time every launch of the given kernel families with HIP events (see
+        grffe_timing_enable); no argument switches timing off."""
+        mask = 0
+        for f in families:
+            mask |= 1 << int(f)
+        _check(lib().grffe_timing_enable(self._h, mask))
 
-    def timing_read(self):
+    def timing_read(self, family):
+        """(summed ms, launches) of one family since timing was enabled or last read."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
-        _check(lib().grffe_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        _check(lib().grffe_timing_read(self._h, int(family), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
     def counts(self):

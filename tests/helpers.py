@@ -60,14 +60,58 @@ def rel_err(got, ref, axis_groups=None):
 GROUPS = ((0, 3), (3, 6), (6, 7), (7, 8), (8, 9))  # E~, B~, psi~, phi~, q~
 
 
-def group_err(got, ref):
+def group_err(got, ref, floor=1.0):
     """Per variable group (E~, B~, psi~, phi~, q~): max |got - ref| over the group divided by
-    max(max |ref| over the group, max |ref| over all nine components)."""
+    max(max |ref| over the group, floor * max |ref| over all nine components)."""
     got = np.asarray(got).reshape(ref.shape[0], -1)
     ref = np.asarray(ref).reshape(ref.shape[0], -1)
     overall = max(np.abs(ref).max(), 1e-300)
     out = []
     for a, b in GROUPS:
-        sc = max(np.abs(ref[a:b]).max(), overall)
+        sc = max(np.abs(ref[a:b]).max(), floor * overall)
         out.append(np.abs(got[a:b] - ref[a:b]).max() / sc)
+    return np.array(out)
+
+
+def state_arrays(odom, rng, rep, smooth_kind="wave", amp=0.1, noise=1e-3):
+    """Smooth fields plus noise on both grids (DG nodes and FD cells)."""
+    w = dict(n_elem=odom.n_elem, lower=odom.lower, upper=odom.upper, degree=odom.N)
+    x, y, z = node_coords(w)
+    xf, yf, zf = I.fd_points(odom.n_elem, odom.lower, odom.upper, odom.N)
+    out = []
+    for (a, b, c) in ((x, y, z), (xf, yf, zf)):
+        U = I.fast_wave_sine(a, amp) if smooth_kind == "wave" else I.current_sheet(a, 0.2)
+        U[0] += 0.05 * np.sin(1.3 * b + 0.7 * c)
+        U[8] += 0.02 * np.cos(0.9 * a + 1.1 * c)
+        U[6] += 0.01 * np.sin(a + b)
+        U[7] += 0.01 * np.cos(b - c)
+        U += noise * rng.standard_normal(U.shape)
+        out.append(U)
+    dg, fd = out
+    return dg, fd
+
+
+def curved_state(odom, w, rng):
+    x, y, z = node_coords(w)
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    dg = I.kerr_schild_uniform_field(x, y, z, w["M"], w["spin"], w["B0"])
+    fd = I.kerr_schild_uniform_field(xf, yf, zf, w["M"], w["spin"], w["B0"])
+    dg[6:8] += 1e-3 * rng.standard_normal(dg[6:8].shape)
+    fd[6:8] += 1e-3 * rng.standard_normal(fd[6:8].shape)
+    dg[0:3] += 1e-4 * rng.standard_normal(dg[0:3].shape)
+    fd[0:3] += 1e-4 * rng.standard_normal(fd[0:3].shape)
+    return dg, fd
+
+
+def group_l2(got, ref, floor=1.0):
+    """Per variable group: RMS(got - ref) / max(RMS(ref) over the group, floor * RMS(ref)
+    over all nine components), the relative L2 error with a floor for nearly vanishing
+    groups as in group_err."""
+    got = np.asarray(got).reshape(ref.shape[0], -1)
+    ref = np.asarray(ref).reshape(ref.shape[0], -1)
+    rms_all = max(np.sqrt(np.mean(ref ** 2)), 1e-300)
+    out = []
+    for a, b in GROUPS:
+        rms = max(np.sqrt(np.mean(ref[a:b] ** 2)), floor * rms_all)
+        out.append(np.sqrt(np.mean((got[a:b] - ref[a:b]) ** 2)) / rms)
     return np.array(out)

@@ -19,7 +19,9 @@ from oracle import tci as OT
 from oracle.domain import DG, FD
 from paper_2404_01531_amd import inputs as I
 
+from helpers import curved_state as _curved_state
 from helpers import from_dev, group_err, make_pair, node_coords, rel_err, to_dev
+from helpers import state_arrays as _state_arrays
 
 pytestmark = pytest.mark.gpu
 
@@ -36,36 +38,6 @@ def _torch():
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def _state_arrays(odom, rng, rep, smooth_kind="wave", amp=0.1, noise=1e-3):
-    """Smooth fields plus noise on both grids (DG nodes and FD cells)."""
-    w = dict(n_elem=odom.n_elem, lower=odom.lower, upper=odom.upper, degree=odom.N)
-    x, y, z = node_coords(w)
-    xf, yf, zf = I.fd_points(odom.n_elem, odom.lower, odom.upper, odom.N)
-    out = []
-    for (a, b, c) in ((x, y, z), (xf, yf, zf)):
-        U = I.fast_wave_sine(a, amp) if smooth_kind == "wave" else I.current_sheet(a, 0.2)
-        U[0] += 0.05 * np.sin(1.3 * b + 0.7 * c)
-        U[8] += 0.02 * np.cos(0.9 * a + 1.1 * c)
-        U[6] += 0.01 * np.sin(a + b)
-        U[7] += 0.01 * np.cos(b - c)
-        U += noise * rng.standard_normal(U.shape)
-        out.append(U)
-    dg, fd = out
-    return dg, fd
-
-
-def _curved_state(odom, w, rng):
-    x, y, z = node_coords(w)
-    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
-    dg = I.kerr_schild_uniform_field(x, y, z, w["M"], w["spin"], w["B0"])
-    fd = I.kerr_schild_uniform_field(xf, yf, zf, w["M"], w["spin"], w["B0"])
-    dg[6:8] += 1e-3 * rng.standard_normal(dg[6:8].shape)
-    fd[6:8] += 1e-3 * rng.standard_normal(fd[6:8].shape)
-    dg[0:3] += 1e-4 * rng.standard_normal(dg[0:3].shape)
-    fd[0:3] += 1e-4 * rng.standard_normal(fd[0:3].shape)
-    return dg, fd
 
 
 def _compare_rhs(odom, ldom, dg, fd, rep, parts, rtol=RTOL, label=""):
