@@ -184,6 +184,30 @@ int grffe_operator(int degree, int which, double* out, int capacity);
 int grffe_timing_enable(grffe_domain* dom, int mask);
 int grffe_timing_read(grffe_domain* dom, int family, double* total_ms, int64_t* launches);
 
+/* Adjoint of the right-hand side (a vector-Jacobian product) for a state whose
+ * live elements are all on DG:  ubar += (d RHS_parts / d dg)^T lam, where
+ * RHS_parts is the semi-discrete right-hand side of grffe_rhs restricted to
+ * `parts` (fluxes, derivative and lift with the Rusanov faces and the
+ * no-incoming-Poynting boundary state, non-stiff and stiff sources of Sec. II and
+ * III A).  dg, lam, ubar: device [9][E][n^3]; rep: device int32 [E], read on the
+ * host (the call synchronises the stream).  EUNSUPPORTED if a live element is on
+ * FD, in mixed precision or with the clamp on (no derivative is defined there). */
+int grffe_rhs_adjoint(grffe_domain* dom, const double* dg, const int32_t* rep, const double* lam, double* ubar,
+                      int parts, void* stream);
+
+/* Adjoint of one IMEX-SSP3(4,3,3) step (Sec. III B) taken with every element on
+ * DG and no switching (the hybrid decisions frozen to DG):
+ *   lam = (d U^{n+1} / d U^n)^T lam_next,
+ * through the explicit operator, the implicit solves (by the implicit function
+ * theorem), the stiff sources and the filter.  u_dg (device [9][E][n^3]) is U^n;
+ * the domain re-runs the forward step from it, so its state is left at U^{n+1}
+ * with every element on DG.  dt <= 0 selects the CFL step.  lam may be the same
+ * buffer as lam_next; neither may overlap u_dg.  Same restrictions as
+ * grffe_rhs_adjoint; the first call allocates the adjoint's work space
+ * (7 arrays of the DG state's size). */
+int grffe_step_adjoint(grffe_domain* dom, const double* u_dg, const double* lam_next, double* lam, double dt,
+                       void* stream);
+
 /* Batches: many independent domains advanced together, each with its own grid,
  * degree (3..7) and CFL time step (Eq. (spectre DG CFL condition) per domain).
  * Domains of one degree are concatenated into one pool, so every kernel of a step

@@ -545,6 +545,69 @@ extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream)
   return GRFFE_OK;
 }
 
+// Representation check of the adjoint entry points: every live element on DG.
+static int require_all_dg(grffe_domain* d, const int32_t* rep, hipStream_t st) {
+  std::vector<int32_t> h(d->E);
+  HIPCHK(hipMemcpyAsync(h.data(), rep, sizeof(int32_t) * d->E, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int e = 0; e < d->E; ++e)
+    if (d->live_h[e] && h[e] != 0) return fail(GRFFE_EUNSUPPORTED, "the adjoint is built for all-DG states only");
+  return GRFFE_OK;
+}
+
+static int adjoint_supported(grffe_domain* d) {
+  if (d->par.precision != GRFFE_PRECISION_FP64) return fail(GRFFE_EUNSUPPORTED, "the adjoint runs in FP64 only");
+  if (d->par.ff_clamp) return fail(GRFFE_EUNSUPPORTED, "the adjoint does not differentiate the clamp");
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_rhs_adjoint(grffe_domain* d, const double* dg, const int32_t* rep, const double* lam,
+                                 double* ubar, int parts, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (!dg || !rep || !lam || !ubar) return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
+  if (parts < 1 || parts > 3) return fail(GRFFE_EINVAL, "parts must be 1, 2 or 3");
+  if (int rc = adjoint_supported(d)) return rc;
+  hipStream_t st = S(stream);
+  if (int rc = require_all_dg(d, rep, st)) return rc;
+  KArgs a = make_args(d);
+  a.dg.Un = const_cast<double*>(dg);
+  launch_rhs_adjoint(a, d->N, d->curved, lam, ubar, parts, st);
+  HIPCHK(hipGetLastError());
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_step_adjoint(grffe_domain* d, const double* u_dg, const double* lam_next, double* lam,
+                                  double dt, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (!u_dg || !lam_next || !lam) return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
+  if (int rc = adjoint_supported(d)) return rc;
+  hipStream_t st = S(stream);
+  const size_t reg = (size_t)NV * d->E * d->nn;
+  if (!d->adj_ws) {
+    void* p1 = nullptr;
+    void* p2 = nullptr;
+    if (int rc = dalloc(d, &p1, sizeof(double) * 6 * reg)) return rc;
+    d->adj_ws = reinterpret_cast<double*>(p1);
+    if (int rc = dalloc(d, &p2, sizeof(double) * reg)) return rc;
+    d->adj_u0 = reinterpret_cast<double*>(p2);
+  }
+  // forward step from u_dg with every element on DG, keeping U_3, U_4 in the registers
+  HIPCHK(hipMemcpyAsync(d->adj_u0, u_dg, sizeof(double) * reg, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d->dg.Un, u_dg, sizeof(double) * reg, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemsetAsync(d->rep, 0, sizeof(int32_t) * d->E, st));
+  KArgs a = make_args(d);
+  a.hybrid = GRFFE_HYBRID_DG_ONLY;
+  if (dt > 0.0) a.dt = dt;
+  step_once(d, a, st);
+  HIPCHK(hipGetLastError());
+  // backward sweep over the stages
+  KArgs b = a;
+  b.dg.Un = d->adj_u0;
+  launch_step_adjoint(b, d->N, d->curved, lam_next, lam, d->adj_ws, st);
+  HIPCHK(hipGetLastError());
+  return GRFFE_OK;
+}
+
 extern "C" int grffe_tci(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep, uint8_t* troubled,
                          double* ratio, void* stream) {
   if (int rc = check_dom(d)) return rc;

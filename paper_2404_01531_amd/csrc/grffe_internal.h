@@ -123,6 +123,8 @@ struct grffe_domain {
   double* trace = nullptr;
   double* slab = nullptr;
   double* fhat = nullptr;
+  double* adj_ws = nullptr;  // step adjoint: 6 DG-sized arrays, allocated at first use
+  double* adj_u0 = nullptr;  // step adjoint: copy of U^n
   double dt_cfl = 0.0;
   double lambda_max = 0.0;
   std::vector<void*> allocs;
@@ -162,5 +164,10 @@ void launch_tci(const KArgs& a, int N, bool curved, const double* dg, const doub
 void launch_transfer(const KArgs& a, int N, int to_fd, const double* in, double* out, int count, hipStream_t s);
 void launch_bg_derive(const KArgs& a, int N, hipStream_t s);
 void launch_lambda_max(const KArgs& a, int N, double* out, hipStream_t s);
+// launchers (kernels_adj.hip)
+void launch_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar, int parts,
+                        hipStream_t s);
+void launch_step_adjoint(const KArgs& a, int N, bool curved, const double* mu, double* lam, double* ws,
+                         hipStream_t s);
 
 }  // namespace grffe

@@ -1,0 +1,456 @@
+// Adjoint (vector-Jacobian products) of the DG right-hand side and of the
+// IMEX-SSP3(4,3,3) step, with every element held on DG (the representation is
+// frozen; the indicator is not differentiated).
+//
+// The explicit DG operator at a node p of element e is (Sec. III A, strong form)
+//   L(X)_p = -sum_d s_d [ sum_q D[i_d(p)][q] F^d(X_q) ] + lift terms + S_ex(X_p),
+// with s_d = 2/h_d and the Rusanov face terms of the lower (s = 0) and upper
+// (s = 1) faces.  Its transpose applied to V gathers, at every node r:
+//   - the transposed derivative g_d(r) = -s_d sum_p D[i_d(p)][i_d(r)] V(p) along
+//     the three lines through r, multiplied by (dF^d/dX)^T at r;
+//   - the node's own face terms and the terms of the neighbouring element's faces
+//     whose exterior state is X_r (no scatter: every element gathers from its
+//     neighbours' V at the mirror nodes);
+//   - (dS_ex/dX)^T V(r), and at physical boundaries the derivative through the
+//     no-incoming-Poynting state.
+// All products with pointwise Jacobians are formed as the gradient of one scalar
+// functional of X_r, evaluated with forward-mode dual numbers (one pass per
+// component), so they are exact up to rounding.
+//
+// The step adjoint runs the step's stages backwards (substep 3, 2, 1, then the two
+// implicit pre-stages); the implicit solve U = Y + h S_stiff(U) has the adjoint
+//   Y_bar = (I - h dS_stiff/dU)^-T U_bar
+// (a 9x9 solve per node), the filter the transposed tensor-product filter.
+#include "common.h"
+#include "dual.h"
+
+namespace grffe {
+
+enum AdjStage { ADJ_A3 = 0, ADJ_B1 = 1, ADJ_B2 = 2, ADJ_B3 = 3, ADJ_RHS = 4 };
+
+// Columns of dS_stiff/dU at U (Jm[v][k] = dS_v/dU_k).
+__device__ inline void stiff_jacobian(const double* U, const Metric& M, const KArgs& a, double Jm[NV][NV]) {
+  MetricT<Dual> Md;
+  metric_cast(M, Md);
+  for (int k = 0; k < NV; ++k) {
+    Dual Ud[NV], S[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ud[v] = Dual(U[v], v == k ? 1.0 : 0.0);
+    source_stiff(Ud, Md, a.eta, a.kpsi, a.kphi, S);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Jm[v][k] = S[v].d;
+  }
+}
+
+// out += (dS_stiff/dU)^T w at U.
+__device__ inline void stiff_vjp(const double* U, const Metric& M, const KArgs& a, const double* w, double* out) {
+  double Jm[NV][NV];
+  stiff_jacobian(U, M, a, Jm);
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s += Jm[v][k] * w[v];
+    out[k] += s;
+  }
+}
+
+// y = (I - h dS_stiff/dU)^-T ub at the solution U of the implicit solve with step h
+// (Gaussian elimination with partial pivoting).
+__device__ inline void solve_vjp(const double* U, const Metric& M, const KArgs& a, double h, const double* ub,
+                                 double* y) {
+  double Jm[NV][NV];
+  stiff_jacobian(U, M, a, Jm);
+  double A[NV][NV + 1];
+  for (int r = 0; r < NV; ++r) {
+    for (int c = 0; c < NV; ++c) A[r][c] = (r == c ? 1.0 : 0.0) - h * Jm[c][r];  // transposed
+    A[r][NV] = ub[r];
+  }
+  for (int c = 0; c < NV; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < NV; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    if (piv != c)
+      for (int k = c; k <= NV; ++k) {
+        const double t = A[c][k];
+        A[c][k] = A[piv][k];
+        A[piv][k] = t;
+      }
+    const double inv = 1.0 / A[c][c];
+    for (int r = c + 1; r < NV; ++r) {
+      const double f = A[r][c] * inv;
+      if (f != 0.0)
+        for (int k = c; k <= NV; ++k) A[r][k] -= f * A[c][k];
+    }
+  }
+  for (int r = NV - 1; r >= 0; --r) {
+    double s = A[r][NV];
+    for (int k = r + 1; k < NV; ++k) s -= A[r][k] * y[k];
+    y[r] = s / A[r][r];
+  }
+}
+
+// U_1, U_2 of the implicit pre-stages from U^n (as in the forward step).
+__device__ inline void pre_stages(const double* Un, const Metric& M, const KArgs& a, double dt, double* U1,
+                                  double* U2, double* S1) {
+  const double h = dt * IMEX_A;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) U1[v] = Un[v];
+  implicit_solve(U1, M, a.eta, a.kpsi, a.kphi, h);
+  source_stiff(U1, M, a.eta, a.kpsi, a.kphi, S1);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) U2[v] = Un[v] - dt * IMEX_A * S1[v];
+  implicit_solve(U2, M, a.eta, a.kpsi, a.kphi, h);
+}
+
+// Adjoint buffers ([9][E][n^3] each).
+struct AdjBufs {
+  const double* mu;  // adjoint of U^{n+1} (input of the step adjoint), or lambda of the RHS adjoint
+  double* un_bar;    // adjoint of U^n (output)
+  double* a_bar;     // adjoint of the accumulator
+  double* s1_bar;    // adjoint of S_stiff(U_1)
+  double* s2_bar;    // adjoint of S_stiff(U_2)
+  double* v_in;      // vector the transposed explicit operator is applied to (read by neighbours)
+  double* v_out;     // the next stage's vector
+  double* w;         // vector the transposed stiff source is applied to (pointwise)
+  int parts;         // RHS adjoint: GRFFE_PART_* of lambda
+};
+
+// Element-wise transposed filter of the nine fields held in sZ (LDS, [9][nn]) at
+// node p: returns (F^T x F^T x F^T) Z at p.  All threads of the block must call it.
+template <int N>
+__device__ inline void filter_transpose(const double* sF, double* sZ, int p, bool act, double* Z) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, nn = Dm::nn;
+  const int idx[3] = {p % n, (p / n) % n, p / (n * n)};
+  const int str[3] = {1, n, n * n};
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();
+    if (act)
+      for (int v = 0; v < NV; ++v) sZ[v * nn + p] = Z[v];
+    __syncthreads();
+    const int id = idx[d];
+    const int p0 = p - id * str[d];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < n; ++q) acc += sF[q * n + id] * sZ[v * nn + p0 + q * str[d]];
+      Z[v] = acc;
+    }
+  }
+}
+
+// ub = (dL_ex/dX)^T V + (dS_stiff/dX)^T W at node p of element e, where L_ex is the
+// explicit DG operator evaluated on the stage field X (own value X, metric M).
+// V is read from b.v_in for this element and its neighbours, W is given.
+// use_v / use_w switch the two parts off.  All threads of the block must call it.
+template <int N, bool CURVED>
+__device__ void operator_vjp(const KArgs& a, const AdjBufs& b, int e, int p, bool act, const double* X,
+                             const Metric& M, const double* Wst, bool use_v, bool use_w, double* sV, const double* sD,
+                             double* ub) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, nn = Dm::nn;
+  const int idx[3] = {p % n, (p / n) % n, p / (n * n)};
+  const int str[3] = {1, n, n * n};
+  double Vp[NV];
+  __syncthreads();
+  if (use_v) {
+    if (act) load9(b.v_in, a.E, nn, e, p, Vp);
+    if (act)
+      for (int v = 0; v < NV; ++v) sV[v * nn + p] = Vp[v];
+  } else {
+    for (int v = 0; v < NV; ++v) Vp[v] = 0.0;
+  }
+  __syncthreads();
+  for (int v = 0; v < NV; ++v) ub[v] = 0.0;
+  double G[3][NV];
+  // boundary faces of this node: coefficient of V.F^d(B(X)) and of V.B(X)
+  double bA[3] = {0.0, 0.0, 0.0}, bI[3] = {0.0, 0.0, 0.0};
+  int bside[3] = {0, 0, 0};
+  if (use_v) {
+    for (int d = 0; d < 3; ++d) {
+      const double sc = 2.0 / h_of(a, e, d);
+      const int id = idx[d];
+      const int p0 = p - id * str[d];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < n; ++q) acc += sD[q * n + id] * sV[v * nn + p0 + q * str[d]];
+        G[d][v] = -sc * acc;
+      }
+      if (!act || (id != 0 && id != N)) continue;
+      const int s = (id == N) ? 1 : 0;
+      const double wl = sc / a.ops->w[0], wr = sc / a.ops->w[N];
+      // the node's own face term (interior dependence)
+      const int o = a.nbr[e * 6 + 2 * d + s];
+      Metric Mo;
+      int pn = 0;
+      if (o >= 0) {
+        int ii = idx[0], jj = idx[1], kk = idx[2];
+        if (d == 0) ii = s ? 0 : N;
+        else if (d == 1) jj = s ? 0 : N;
+        else kk = s ? 0 : N;
+        pn = ii + n * (jj + n * kk);
+        load_metric<CURVED>(a.bg_dg, a.E, nn, o, pn, Mo);
+      }
+      const double lam = CURVED ? (o >= 0 ? fmax(char_speed(d, M), char_speed(d, Mo)) : char_speed(d, M)) : 1.0;
+      if (s == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          G[d][v] += -0.5 * wl * Vp[v];
+          ub[v] += -0.5 * wl * lam * Vp[v];
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          G[d][v] += 0.5 * wr * Vp[v];
+          ub[v] += -0.5 * wr * lam * Vp[v];
+        }
+      }
+      if (o < 0) {
+        // exterior state = no-incoming-Poynting state of X itself
+        bside[d] = s ? 1 : -1;
+        bA[d] = s ? -0.5 * wr : 0.5 * wl;
+        bI[d] = s ? 0.5 * wr * lam : 0.5 * wl * lam;
+      } else {
+        // the neighbour's face term on its opposite face uses X as exterior state
+        const double sco = 2.0 / h_of(a, o, d);
+        double Vo[NV];
+        load9(b.v_in, a.E, nn, o, pn, Vo);
+        if (s == 1) {  // neighbour's lower face
+          const double wlo = sco / a.ops->w[0];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            G[d][v] += 0.5 * wlo * Vo[v];
+            ub[v] += 0.5 * wlo * lam * Vo[v];
+          }
+        } else {  // neighbour's upper face
+          const double wro = sco / a.ops->w[N];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            G[d][v] += -0.5 * wro * Vo[v];
+            ub[v] += 0.5 * wro * lam * Vo[v];
+          }
+        }
+      }
+    }
+  }
+  if (!act) return;
+  MetricDeriv Dv;
+  load_deriv<CURVED>(a.bg_dg, a.E, nn, e, p, Dv);
+  MetricT<Dual> Md;
+  metric_cast(M, Md);
+  // gradient of  sum_d G_d.F^d(X) + V.S_ex(X) + W.S_stiff(X) + boundary terms
+  for (int k = 0; k < NV; ++k) {
+    Dual Xd[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Xd[v] = Dual(X[v], v == k ? 1.0 : 0.0);
+    Dual tot(0.0);
+    if (use_v) {
+      Dual Jd[3], Je[3], J[3], F[NV], S[NV];
+      current(Xd, Md, a.eta, Jd, Je);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) J[c] = Jd[c] + Je[c];
+      for (int d = 0; d < 3; ++d) {
+        flux_any(d, Xd, J, Md, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tot += G[d][v] * F[v];
+        if (bside[d]) {
+          Dual Ub[NV], Jb[3], Fb[NV];
+          boundary_state(d, (double)bside[d], Xd, Md, Ub);
+          current_total(Ub, Md, a.eta, Jb);
+          flux_any(d, Ub, Jb, Md, Fb);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) tot += Vp[v] * (bA[d] * Fb[v] + bI[d] * Ub[v]);
+        }
+      }
+      source_explicit<CURVED>(Xd, Md, Dv, Jd, S);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) tot += Vp[v] * S[v];
+    }
+    if (use_w) {
+      Dual S[NV];
+      source_stiff(Xd, Md, a.eta, a.kpsi, a.kphi, S);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) tot += Wst[v] * S[v];
+    }
+    ub[k] += tot.d;
+  }
+}
+
+template <int N, bool CURVED, int STAGE>
+__global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adjoint(KArgs a, AdjBufs b) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, nn = Dm::nn, TPB = Dm::tpb;
+  __shared__ double sV[NV * nn];
+  __shared__ double sD[n * n];
+  __shared__ double sF[n * n];
+  const int e = blockIdx.x;
+  if (!a.live[e]) return;
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int p = act ? t : 0;
+  for (int q = t; q < n * n; q += TPB) {
+    sD[q] = a.ops->D[q];
+    sF[q] = a.ops->F[q];
+  }
+  Metric M;
+  load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
+  const double dt = dt_of(a, e);
+  const double h = dt * IMEX_A;
+  double Un[NV];
+  load9(a.dg.Un, a.E, nn, e, p, Un);
+  if (STAGE == ADJ_RHS) {
+    double lam[NV], ub[NV];
+    load9(b.mu, a.E, nn, e, p, lam);
+    operator_vjp<N, CURVED>(a, b, e, p, act, Un, M, lam, (b.parts & 1) != 0, (b.parts & 2) != 0, sV, sD, ub);
+    if (!act) return;
+    double o[NV];
+    load9(b.un_bar, a.E, nn, e, p, o);
+    for (int v = 0; v < NV; ++v) o[v] += ub[v];
+    store9(b.un_bar, a.E, nn, e, p, o);
+    return;
+  }
+  if (STAGE == ADJ_A3) {
+    // U^{n+1} = Phi(Y3),  Y3 = U^n + A' + dt S2/6 + (2/3) dt (L(U4) + S(U4))
+    double Z[NV];
+    load9(b.mu, a.E, nn, e, p, Z);
+    if (a.filter_on) filter_transpose<N>(sF, sV, p, act, Z);
+    if (!act) return;
+    double V[NV], S2b[NV];
+    for (int v = 0; v < NV; ++v) {
+      V[v] = (2.0 / 3.0) * dt * Z[v];
+      S2b[v] = dt / 6.0 * Z[v];
+    }
+    store9(b.un_bar, a.E, nn, e, p, Z);
+    store9(b.a_bar, a.E, nn, e, p, Z);
+    store9(b.s2_bar, a.E, nn, e, p, S2b);
+    store9(b.v_out, a.E, nn, e, p, V);
+    store9(b.w, a.E, nn, e, p, V);
+    return;
+  }
+  // stage value the transposed operator is taken at
+  double X[NV], U1[NV], S1[NV];
+  if (STAGE == ADJ_B3) load9(a.dg.X1, a.E, nn, e, p, X);       // U_4
+  else if (STAGE == ADJ_B2) load9(a.dg.X0, a.E, nn, e, p, X);  // U_3
+  else pre_stages(Un, M, a, dt, U1, X, S1);                    // U_2
+  double W[NV], ub[NV];
+  load9(b.w, a.E, nn, e, p, W);
+  operator_vjp<N, CURVED>(a, b, e, p, act, X, M, W, true, true, sV, sD, ub);
+  double unb[NV];
+  load9(b.un_bar, a.E, nn, e, p, unb);
+  if (STAGE == ADJ_B3 || STAGE == ADJ_B2) {
+    // X = solve(Phi(Y)): Y_bar = Phi^T (I - h S'(X))^-T X_bar
+    double Z[NV];
+    if (act) solve_vjp(X, M, a, h, ub, Z);
+    if (a.filter_on) filter_transpose<N>(sF, sV, p, act, Z);
+    if (!act) return;
+    double Ab[NV];
+    load9(b.a_bar, a.E, nn, e, p, Ab);
+    for (int v = 0; v < NV; ++v) unb[v] += Z[v];
+    store9(b.un_bar, a.E, nn, e, p, unb);
+    double V[NV], Wn[NV];
+    if (STAGE == ADJ_B3) {
+      // Y2 = U^n + (A + dt L(U3))/4 + dt (b S1 + e S2 + c3 S(U3)),  A' = (A + dt L(U3))/6 + dt S(U3)/6
+      const double c3 = 0.5 - IMEX_B - IMEX_E - IMEX_A;
+      double S1b[NV], S2b[NV];
+      load9(b.s2_bar, a.E, nn, e, p, S2b);
+      for (int v = 0; v < NV; ++v) {
+        const double inc = 0.25 * Z[v] + Ab[v] / 6.0;
+        Wn[v] = c3 * dt * Z[v] + dt / 6.0 * Ab[v];
+        V[v] = dt * inc;
+        Ab[v] = inc;
+        S1b[v] = IMEX_B * dt * Z[v];
+        S2b[v] += IMEX_E * dt * Z[v];
+      }
+      store9(b.a_bar, a.E, nn, e, p, Ab);
+      store9(b.s1_bar, a.E, nn, e, p, S1b);
+      store9(b.s2_bar, a.E, nn, e, p, S2b);
+    } else {
+      // Y1 = U^n + dt L(U2) + dt (1 - a) S(U2),  A = dt L(U2);  S2 = S(U2)
+      double S2b[NV];
+      load9(b.s2_bar, a.E, nn, e, p, S2b);
+      for (int v = 0; v < NV; ++v) {
+        V[v] = dt * (Z[v] + Ab[v]);
+        Wn[v] = (1.0 - IMEX_A) * dt * Z[v] + S2b[v];
+      }
+    }
+    store9(b.v_out, a.E, nn, e, p, V);
+    store9(b.w, a.E, nn, e, p, Wn);
+    return;
+  }
+  // ADJ_B1: U2 = solve(U^n - a dt S1), S1 = S(U1), U1 = solve(U^n)
+  if (!act) return;
+  double Y[NV], S1b[NV], U1b[NV], Yn[NV];
+  solve_vjp(X, M, a, h, ub, Y);
+  load9(b.s1_bar, a.E, nn, e, p, S1b);
+  for (int v = 0; v < NV; ++v) {
+    unb[v] += Y[v];
+    S1b[v] -= IMEX_A * dt * Y[v];
+    U1b[v] = 0.0;
+  }
+  stiff_vjp(U1, M, a, S1b, U1b);
+  solve_vjp(U1, M, a, h, U1b, Yn);
+  for (int v = 0; v < NV; ++v) unb[v] += Yn[v];
+  store9(b.un_bar, a.E, nn, e, p, unb);
+}
+
+template <int N, bool CURVED>
+static void launch_adj_t(const KArgs& a, const AdjBufs& b, int stage, hipStream_t s) {
+  dim3 grid(a.E), block(Dims<N>::tpb);
+  switch (stage) {
+    case ADJ_A3: launch_kernel(k_dg_adjoint<N, CURVED, ADJ_A3>, grid, block, s, a, b); break;
+    case ADJ_B3: launch_kernel(k_dg_adjoint<N, CURVED, ADJ_B3>, grid, block, s, a, b); break;
+    case ADJ_B2: launch_kernel(k_dg_adjoint<N, CURVED, ADJ_B2>, grid, block, s, a, b); break;
+    case ADJ_B1: launch_kernel(k_dg_adjoint<N, CURVED, ADJ_B1>, grid, block, s, a, b); break;
+    default: launch_kernel(k_dg_adjoint<N, CURVED, ADJ_RHS>, grid, block, s, a, b); break;
+  }
+}
+
+template <bool CURVED>
+static void launch_adj_c(const KArgs& a, const AdjBufs& b, int N, int stage, hipStream_t s) {
+  switch (N) {
+    case 3: launch_adj_t<3, CURVED>(a, b, stage, s); break;
+    case 4: launch_adj_t<4, CURVED>(a, b, stage, s); break;
+    case 5: launch_adj_t<5, CURVED>(a, b, stage, s); break;
+    case 6: launch_adj_t<6, CURVED>(a, b, stage, s); break;
+    default: launch_adj_t<7, CURVED>(a, b, stage, s); break;
+  }
+}
+
+void launch_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar, int parts,
+                        hipStream_t s) {
+  AdjBufs b{};
+  b.mu = lam;
+  b.un_bar = ubar;
+  b.v_in = const_cast<double*>(lam);
+  b.parts = parts;
+  if (curved) launch_adj_c<true>(a, b, N, ADJ_RHS, s);
+  else launch_adj_c<false>(a, b, N, ADJ_RHS, s);
+}
+
+// ws: six [9][E][n^3] arrays (accumulator adjoints, stiff vector, two explicit vectors).
+void launch_step_adjoint(const KArgs& a, int N, bool curved, const double* mu, double* lam, double* ws,
+                         hipStream_t s) {
+  const size_t n3 = (size_t)(N + 1) * (N + 1) * (N + 1);
+  const size_t reg = (size_t)NV * a.E * n3;
+  AdjBufs b{};
+  b.mu = mu;
+  b.un_bar = lam;
+  b.a_bar = ws;
+  b.s1_bar = ws + reg;
+  b.s2_bar = ws + 2 * reg;
+  b.w = ws + 3 * reg;
+  double* va = ws + 4 * reg;
+  double* vb = ws + 5 * reg;
+  const int order[4] = {ADJ_A3, ADJ_B3, ADJ_B2, ADJ_B1};
+  for (int k = 0; k < 4; ++k) {
+    b.v_in = (k % 2 == 0) ? vb : va;
+    b.v_out = (k % 2 == 0) ? va : vb;
+    if (curved) launch_adj_c<true>(a, b, N, order[k], s);
+    else launch_adj_c<false>(a, b, N, order[k], s);
+  }
+}
+
+}  // namespace grffe

@@ -87,33 +87,36 @@ __device__ inline double dot3(const Metric& M, const double* u, const double* v)
   return u[0] * l[0] + u[1] * l[1] + u[2] * l[2];
 }
 
-// Densitized current split into drift (Jd) and driver (Je) parts.
-__device__ inline void current(const double* U, const Metric& M, double eta, double* Jd, double* Je) {
-  const double* E = U;
-  const double* B = U + 3;
-  double El[3], Bl[3];
+// Densitized current split into drift (Jd) and driver (Je) parts.  T is the
+// arithmetic type of the state (FP64, or a dual number for derivatives).
+template <typename T>
+__device__ inline void current(const T* U, const MetricT<T>& M, double eta, T* Jd, T* Je) {
+  const T* E = U;
+  const T* B = U + 3;
+  T El[3], Bl[3];
   lower3(M, E, El);
   lower3(M, B, Bl);
-  const double B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
+  const T B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
   if (!(B2 > 0.0)) {
-    Jd[0] = Jd[1] = Jd[2] = Je[0] = Je[1] = Je[2] = 0.0;
+    for (int i = 0; i < 3; ++i) Jd[i] = Je[i] = T(0.0);
     return;
   }
-  const double E2 = E[0] * El[0] + E[1] * El[1] + E[2] * El[2];
-  const double EB = E[0] * Bl[0] + E[1] * Bl[1] + E[2] * Bl[2];
-  const double iB2 = 1.0 / B2;
-  const double cd = M.alpha * U[8] * iB2 / M.sqrtg;
+  const T E2 = E[0] * El[0] + E[1] * El[1] + E[2] * El[2];
+  const T EB = E[0] * Bl[0] + E[1] * Bl[1] + E[2] * Bl[2];
+  const T iB2 = T(1.0) / B2;
+  const T cd = M.alpha * U[8] * iB2 / M.sqrtg;
   Jd[0] = cd * (El[1] * Bl[2] - El[2] * Bl[1]);
   Jd[1] = cd * (El[2] * Bl[0] - El[0] * Bl[2]);
   Jd[2] = cd * (El[0] * Bl[1] - El[1] * Bl[0]);
-  const double ce = M.alpha * eta;
-  const double par = EB * iB2;
-  const double rec = fmax(E2 - B2, 0.0) * iB2;
+  const T ce = M.alpha * eta;
+  const T par = EB * iB2;
+  const T rec = fmax(E2 - B2, T(0.0)) * iB2;
   for (int i = 0; i < 3; ++i) Je[i] = ce * (par * B[i] + rec * E[i]);
 }
 
-__device__ inline void current_total(const double* U, const Metric& M, double eta, double* J) {
-  double Jd[3], Je[3];
+template <typename T>
+__device__ inline void current_total(const T* U, const MetricT<T>& M, double eta, T* J) {
+  T Jd[3], Je[3];
   current(U, M, eta, Jd, Je);
   J[0] = Jd[0] + Je[0];
   J[1] = Jd[1] + Je[1];
@@ -176,18 +179,18 @@ struct MetricDeriv {
 };
 
 // Explicit (non-stiff) sources: everything but the driver current and kappa damping.
-template <bool CURVED>
-__device__ inline void source_explicit(const double* U, const Metric& M, const MetricDeriv& Dv, const double* Jd,
-                                       double* S) {
+// The background (metric and its derivatives) is FP64; T is the state's type.
+template <bool CURVED, typename T>
+__device__ inline void source_explicit(const T* U, const MetricT<T>& M, const MetricDeriv& Dv, const T* Jd, T* S) {
   for (int i = 0; i < 3; ++i) S[i] = -Jd[i];
-  S[3] = S[4] = S[5] = S[6] = S[7] = S[8] = 0.0;
+  S[3] = S[4] = S[5] = S[6] = S[7] = S[8] = T(0.0);
   if (CURVED) {
-    const double a = M.alpha;
-    double ga[3];
+    const T a = M.alpha;
+    T ga[3];
     for (int i = 0; i < 3; ++i)
       ga[i] = M.gi[sym(i, 0)] * Dv.da[0] + M.gi[sym(i, 1)] * Dv.da[1] + M.gi[sym(i, 2)] * Dv.da[2];
     for (int i = 0; i < 3; ++i) {
-      double se = 0.0, sb = 0.0;
+      T se = T(0.0), sb = T(0.0);
       for (int j = 0; j < 3; ++j) {
         se += U[j] * Dv.db[3 * j + i];
         sb += U[3 + j] * Dv.db[3 * j + i];
@@ -203,17 +206,17 @@ __device__ inline void source_explicit(const double* U, const Metric& M, const M
 }
 
 // Stiff sources: -J~_eta for E~, -alpha kappa for psi~, phi~.
-__device__ inline void source_stiff(const double* U, const Metric& M, double eta, double kpsi, double kphi,
-                                    double* S) {
-  double Jd[3], Je[3];
+template <typename T>
+__device__ inline void source_stiff(const T* U, const MetricT<T>& M, double eta, double kpsi, double kphi, T* S) {
+  T Jd[3], Je[3];
   current(U, M, eta, Jd, Je);
   S[0] = -Je[0];
   S[1] = -Je[1];
   S[2] = -Je[2];
-  S[3] = S[4] = S[5] = 0.0;
+  S[3] = S[4] = S[5] = T(0.0);
   S[6] = -M.alpha * kpsi * U[6];
   S[7] = -M.alpha * kphi * U[7];
-  S[8] = 0.0;
+  S[8] = T(0.0);
 }
 
 // Solve U = Y + h S_stiff(U) in place (Sec. III B).  B~ and q~ are unchanged;
@@ -285,19 +288,20 @@ __device__ inline void constraint_clamp(double* U, const Metric& M, double margi
 }
 
 // No-incoming-Poynting external state (Sec. III D); side = sign of the outward normal along x^d.
-__device__ inline void boundary_state(int d, double side, const double* Ui, const Metric& M, double* Ub) {
-  double El[3], Bl[3];
+template <typename T>
+__device__ inline void boundary_state(int d, double side, const T* Ui, const MetricT<T>& M, T* Ub) {
+  T El[3], Bl[3];
   lower3(M, Ui, El);
   lower3(M, Ui + 3, Bl);
   const int j = (d + 1) % 3, k = (d + 2) % 3;
-  const double Sd = El[j] * Bl[k] - El[k] * Bl[j];  // [d j k] E_j B_k
+  const T Sd = El[j] * Bl[k] - El[k] * Bl[j];  // [d j k] E_j B_k
   const bool inward = side * Sd < 0.0;
   for (int i = 0; i < 3; ++i) {
-    Ub[i] = inward ? 0.0 : Ui[i];
+    Ub[i] = inward ? T(0.0) : Ui[i];
     Ub[3 + i] = Ui[3 + i];
   }
-  Ub[6] = 0.0;
-  Ub[7] = 0.0;
+  Ub[6] = T(0.0);
+  Ub[7] = T(0.0);
   Ub[8] = Ui[8];
 }
 

@@ -91,6 +91,8 @@ def lib():
     L.grffe_operator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(dbl), ctypes.c_int]
     L.grffe_timing_enable.argtypes = [vp, ctypes.c_int]
     L.grffe_timing_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
+    L.grffe_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp]
+    L.grffe_step_adjoint.argtypes = [vp, vp, vp, vp, dbl, vp]
     pvp = ctypes.POINTER(vp)
     L.grffe_batch_create.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(Params), pvp, vp, pvp]
     L.grffe_batch_destroy.argtypes = [vp]
@@ -107,7 +109,8 @@ def lib():
                  "grffe_get_dt", "grffe_get_counts", "grffe_operator", "grffe_timing_enable",
                  "grffe_timing_read", "grffe_batch_create", "grffe_batch_destroy", "grffe_batch_size",
                  "grffe_batch_init_from_fd", "grffe_batch_get_state", "grffe_batch_set_state",
-                 "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step"):
+                 "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step", "grffe_rhs_adjoint",
+                 "grffe_step_adjoint"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -252,6 +255,25 @@ class Domain:
 
     def step(self, n_steps=1, dt=0.0):
         _check(lib().grffe_step(self._h, int(n_steps), float(dt), _stream()))
+
+    def rhs_adjoint(self, dg, rep, lam, parts=PART_ALL, ubar=None):
+        """ubar + (dRHS/d dg)^T lam for an all-DG state (see grffe_rhs_adjoint)."""
+        import torch
+        self._check_state(dg, None, rep)
+        self._check_state(lam, None, None)
+        if ubar is None:
+            ubar = torch.zeros_like(dg)
+        _check(lib().grffe_rhs_adjoint(self._h, _ptr(dg), _ptr(rep), _ptr(lam), _ptr(ubar), int(parts), _stream()))
+        return ubar
+
+    def step_adjoint(self, u_dg, lam_next, dt=0.0):
+        """(dU^{n+1}/dU^n)^T lam_next for one all-DG step from u_dg (see grffe_step_adjoint)."""
+        import torch
+        self._check_state(u_dg, None, None)
+        self._check_state(lam_next, None, None)
+        lam = torch.empty_like(lam_next)
+        _check(lib().grffe_step_adjoint(self._h, _ptr(u_dg), _ptr(lam_next), _ptr(lam), float(dt), _stream()))
+        return lam
 
     def tci(self, dg, fd, rep):
         import torch
