@@ -41,6 +41,8 @@ FD_FLOP_PER_FACE = 1560 + 150 + 36 + 111 + 18
 # U^n, U_3, A and writes U_4, A (360 B); substep 3 reads U^n, U_4, A and writes
 # U^{n+1} (288 B).  Mean 288 B; the flat metric adds nothing.
 DG_BYTES_PER_NODE = {1: 216.0, 2: 360.0, 3: 288.0}
+# The curved background adds its 26 FP64 fields per node, read once per substep.
+DG_BG_BYTES_PER_NODE = 26 * 8.0
 
 # HBM bytes per launch of k_fd_flux (FP64) from rocprofv3 FETCH_SIZE and WRITE_SIZE
 # runs scaled by a plain copy kernel's reading, valid for the kernel source whose
@@ -57,6 +59,9 @@ def parse():
     ap.add_argument("--workload", default="sheet")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=5)
+    ap.add_argument("--extras", choices=("all", "none"), default="all",
+                    help="also measure the black-hole, batch and adjoint workloads (nested in the JSON line)")
+    ap.add_argument("--extra-steps", type=int, default=30)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -147,6 +152,188 @@ def state_diff(a, b):
             "elements_compared": int(same.sum()), "elements_rep_differs": int((~same).sum())}
 
 
+def _dg_nodes(w):
+    """DG node coordinates of workload w from the library's own GLL nodes."""
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    return I.points(w["n_elem"], w["lower"], w["upper"], grffe.operator(w["degree"], 0))
+
+
+def _time_steps(step, steps, warmup):
+    import torch
+    step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_kerr_schild(steps, warmup, precision, n_elem=16):
+    """Kerr-Schild black hole (M = 1, a = 0.9, B0 = 1, Wald-like data with the ideal
+    E), [-40,40]^3 with n_elem^3 DG-P5 elements, elements meeting r < 1.8 excised."""
+    import numpy as np
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    w = I.workload("kerr_schild", n_elem=(n_elem,) * 3)
+    N = w["degree"]
+    x, y, z = _dg_nodes(w)
+    with np.errstate(all="ignore"):
+        bg = I.background(w, x, y, z)
+        u = I.initial_data(w, x, y, z)
+    exc = I.excision_mask(w)
+    E, n3 = int(np.prod(w["n_elem"])), (N + 1) ** 3
+    bg = bg.reshape(26, E, n3)
+    u = u.reshape(9, E, n3)
+    bg[:, exc.astype(bool)] = 0.0
+    bg[0, exc.astype(bool)] = 1.0
+    bg[4, exc.astype(bool)] = bg[7, exc.astype(bool)] = bg[9, exc.astype(bool)] = 1.0
+    u[:, exc.astype(bool)] = 0.0
+    p = grffe.default_params(eta=w["eta"], cfl=w["cfl"], precision=precision)
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p,
+                       bg=torch.from_numpy(np.ascontiguousarray(bg)).cuda(), excised=exc)
+    m3 = (2 * N + 1) ** 3
+    dom.set_state(torch.from_numpy(np.ascontiguousarray(u)).cuda(),
+                  torch.zeros((9, E, m3), dtype=torch.float64, device="cuda"),
+                  torch.zeros(E, dtype=torch.int32, device="cuda"))
+    dt = dom.dt()
+    fam = grffe.KERNEL_FAMILIES["dg_substep"]
+    dom.step(warmup, dt)
+    torch.cuda.synchronize()
+    n_dg0, n_fd0 = dom.counts()
+    dom.timing_enable(fam)
+    secs = _time_steps(lambda k: dom.step(k, dt), steps, 0)
+    k_ms, k_n = dom.timing_read(fam)
+    dom.timing_enable()
+    n_dg1, n_fd1 = dom.counts()
+    pts = 0.5 * ((n_dg0 + n_dg1) * n3 + (n_fd0 + n_fd1) * m3)
+    n_dg = 0.5 * (n_dg0 + n_dg1)
+    byt = n_dg * n3 * (sum(DG_BYTES_PER_NODE.values()) / 3.0 + DG_BG_BYTES_PER_NODE)
+    avg = (k_ms / 1e3) / max(k_n, 1)
+    return {"workload": f"Kerr-Schild a=0.9 B0=1, [-40,40]^3, {n_elem}^3 elements DG-P5, eta 1e5, CFL 0.25, "
+                        f"{int(exc.sum())} excised", "dtype": "f64" if precision == 0 else "mixed",
+            "value": pts * 3 * steps / secs, "unit": "grid-point updates/s", "steps": steps,
+            "ms_per_step": secs * 1e3 / steps, "dt": dt, "elements_dg_fd": [[int(n_dg0), int(n_fd0)],
+                                                                            [int(n_dg1), int(n_fd1)]],
+            "roofline_dg": {"kernel": "k_dg_substep (fused DG substep, curved)", "bound": "hbm",
+                            "achieved": byt / avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": byt / avg / 1e9 / HBM_PEAK_GBS, "mean_launch_us": avg * 1e6,
+                            "launches": int(k_n), "bytes_per_launch": byt}}
+
+
+def run_batch(steps, warmup, precision, use_graph=True):
+    """64 independent flat periodic domains (n^3 elements, n ~ U{4..12}, degree
+    N ~ U{3..7}, wave or sheet), each advanced by its own CFL step, one call per step."""
+    import numpy as np
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    ws = I.batch_workloads()
+    b = grffe.Batch([dict(n_elem=w["n_elem"], lower=w["lower"], upper=w["upper"], degree=w["degree"],
+                          bc=w["bc"]) for w in ws], params=dict(eta=1e6, cfl=0.25, precision=precision))
+    nodes = 0
+    for k, w in enumerate(ws):
+        N = w["degree"]
+        E, n3, m3 = int(np.prod(w["n_elem"])), (N + 1) ** 3, (2 * N + 1) ** 3
+        x, y, z = _dg_nodes(w)
+        u = I.initial_data(w, x, y, z).reshape(9, E, n3)
+        b.set_state(k, torch.from_numpy(np.ascontiguousarray(u)).cuda(),
+                    torch.zeros((9, E, m3), dtype=torch.float64, device="cuda"),
+                    torch.zeros(E, dtype=torch.int32, device="cuda"))
+        nodes += E * n3
+    torch.cuda.synchronize()
+    b.step(warmup, use_graph=use_graph)
+    torch.cuda.synchronize()
+
+    def points():
+        tot = fd = 0
+        for k, w in enumerate(ws):
+            N = w["degree"]
+            a, f = b.counts(k)
+            tot += a * (N + 1) ** 3 + f * (2 * N + 1) ** 3
+            fd += f
+        return tot, fd
+
+    p0, f0 = points()
+    secs = _time_steps(lambda k: b.step(k, use_graph=use_graph), steps, 0)
+    p1, f1 = points()
+    pts = 0.5 * (p0 + p1)
+    return {"workload": "64 flat periodic domains on [-1,1]^3, n^3 elements n~U{4..12}, DG degree ~U{3..7}, "
+                        "wave or sheet, eta 1e6, CFL 0.25, adaptive DG-FD, one HIP-graph launch per step",
+            "dtype": "f64" if precision == 0 else "mixed", "domains": len(ws), "dg_nodes": nodes,
+            "degrees": sorted({w["degree"] for w in ws}), "value": pts * 3 * steps / secs,
+            "unit": "grid-point updates/s", "steps": steps, "ms_per_step": secs * 1e3 / steps,
+            "fd_elements": [int(f0), int(f1)],
+            "hbm_GBps_dg_state": (nodes * sum(DG_BYTES_PER_NODE.values())) * steps / secs / 1e9}
+
+
+def run_adjoint(steps=200, every=20):
+    """All-DG Kerr-Schild black hole, 8^3 P5 elements on [-40,40]^3: forward steps,
+    one-step adjoints and the checkpointed gradient of a linear functional of the end
+    state, timed against the forward run."""
+    import numpy as np
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    from paper_2404_01531_amd.autograd import GRFFEStep
+    w = I.workload("kerr_schild", n_elem=(8, 8, 8))
+    N = w["degree"]
+    x, y, z = _dg_nodes(w)
+    with np.errstate(all="ignore"):
+        bg = I.background(w, x, y, z)
+        u = I.initial_data(w, x, y, z)
+    exc = I.excision_mask(w).astype(bool)
+    E, n3 = int(np.prod(w["n_elem"])), (N + 1) ** 3
+    bg = bg.reshape(26, E, n3)
+    u = u.reshape(9, E, n3)
+    bg[:, exc] = 0.0
+    bg[0, exc] = bg[4, exc] = bg[7, exc] = bg[9, exc] = 1.0
+    u[:, exc] = 0.0
+    p = grffe.default_params(eta=w["eta"], cfl=w["cfl"], hybrid=grffe.HYBRID_DG_ONLY)
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p,
+                       bg=torch.from_numpy(np.ascontiguousarray(bg)).cuda(), excised=exc.astype(np.uint8))
+    dt = dom.dt()
+    u0 = torch.from_numpy(np.ascontiguousarray(u)).cuda()
+    wt = torch.from_numpy(np.random.default_rng(1005).standard_normal(u.shape)).cuda()
+    wt[:, torch.from_numpy(exc).cuda()] = 0.0
+    # forward only
+    GRFFEStep.apply(u0, dom, 2, dt, every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        GRFFEStep.apply(u0, dom, steps, dt, every)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    # one-step adjoints
+    lam = wt.clone()
+    dom.step_adjoint(u0, lam, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        lam = dom.step_adjoint(u0, lam, dt)
+    torch.cuda.synchronize()
+    t_adj1 = (time.perf_counter() - t0) / 20
+    # checkpointed gradient of J = <wt, U_N>
+    uu = u0.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    J = (wt * GRFFEStep.apply(uu, dom, steps, dt, every)).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    return {"workload": f"Kerr-Schild a=0.9, [-40,40]^3, 8^3 elements DG-P5 (all DG), {int(exc.sum())} excised, "
+                        f"J = <w, U_N> after {steps} steps, checkpoints every {every}",
+            "dtype": "f64", "forward_ms_per_step": t_fwd * 1e3 / steps,
+            "step_adjoint_ms": t_adj1 * 1e3,
+            "step_adjoint_over_forward": t_adj1 / (t_fwd / steps),
+            "gradient_ms_total": t_grad * 1e3,
+            "gradient_over_forward": t_grad / t_fwd,
+            "grad_norm": float(uu.grad.norm())}
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -229,6 +416,19 @@ def main():
                   "roofline": roofline_fd(mix), "roofline_dg": roofline_dg(mix)},
         "cpu_baseline": cpu,
     }
+    if args.extras == "all":
+        ex = {}
+        for name, fn in (("kerr_schild_16^3_fp64", lambda: run_kerr_schild(args.extra_steps, 2, 0)),
+                         ("kerr_schild_16^3_mixed", lambda: run_kerr_schild(args.extra_steps, 2, 1)),
+                         ("batch_64_fp64", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0)),
+                         ("batch_64_mixed", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 1)),
+                         ("adjoint_kerr_schild_8^3", lambda: run_adjoint())):
+            print(f"# extra workload {name}", file=sys.stderr, flush=True)
+            ex[name] = fn()
+            print(f"#   {json.dumps(ex[name])[:300]}", file=sys.stderr, flush=True)
+            import torch
+            torch.cuda.empty_cache()
+        out["extras"] = ex
     print(json.dumps(out))
 
 

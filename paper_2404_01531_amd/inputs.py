@@ -282,6 +282,20 @@ def workload(name, **over):
     return w
 
 
+def batch_workloads(count=64, seed=4, n_range=(4, 12), degree_range=(3, 7)):
+    """Descriptions of `count` independent flat periodic domains on [-1,1]^3:
+    n^3 elements with n ~ U{n_range}, degree N ~ U{degree_range}, kind wave or sheet
+    with equal probability; domain j draws its noise from seed 4000 + j."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        N = int(rng.integers(degree_range[0], degree_range[1] + 1))
+        kind = "wave" if rng.random() < 0.5 else "sheet"
+        out.append(workload(kind, n_elem=(n, n, n), degree=N, seed=4000 + j))
+    return out
+
+
 def excision_mask(w):
     """Elements whose box intersects the Euclidean ball of radius r_excise (uint8, E)."""
     E = int(np.prod(w["n_elem"]))
