@@ -177,10 +177,10 @@ int grffe_operator(int degree, int which, double* out, int capacity);
  * families (the events bracket the kernel's own dispatch on its launch stream).
  * Families: 1 fused DG substep, 2 FD face fluxes, 3 FD update, 4 FD stage
  * values, 5 FD traces, 6 DG ghost slabs, 7 DG->FD projection of flagged
- * elements, 8 FD->DG check.  mask = OR of (1 << family), 0 = off; enabling
- * resets every counter.  grffe_timing_read synchronises the stream of the last
- * timed launch, returns the summed duration (ms) and the number of timed launches
- * of one family, and resets that family's counters. */
+ * elements, 8 FD->DG check, 9 DG pre-stage pass.  mask = OR of (1 << family),
+ * 0 = off; enabling resets every counter.  grffe_timing_read synchronises the
+ * stream of the last timed launch, returns the summed duration (ms) and the
+ * number of timed launches of one family, and resets that family's counters. */
 int grffe_timing_enable(grffe_domain* dom, int mask);
 int grffe_timing_read(grffe_domain* dom, int family, double* total_ms, int64_t* launches);
 

@@ -108,15 +108,20 @@ __device__ inline void derived_stages(const double* Un, const Metric& M, const K
 }
 
 // Stage value that is the input of substep MODE, at point p of element e of a register set.
-template <int MODE>
+// PRE: the register set holds the pre-stage pass's U_2 (in X1) and stiff terms (in K).
+template <int MODE, bool PRE = false>
 __device__ inline void stage_input(const Regs& r, int E, int P, int e, int p, const Metric& M, const KArgs& a,
                                    double* X) {
   if (MODE == MODE_RHS) {
     load9(r.Un, E, P, e, p, X);
   } else if (MODE == MODE_SUB1) {
-    double Un[NV], S1[NV], S2[NV];
-    load9(r.Un, E, P, e, p, Un);
-    derived_stages(Un, M, a, dt_of(a, e), X, S1, S2);
+    if (PRE) {
+      load9(r.X1, E, P, e, p, X);
+    } else {
+      double Un[NV], S1[NV], S2[NV];
+      load9(r.Un, E, P, e, p, Un);
+      derived_stages(Un, M, a, dt_of(a, e), X, S1, S2);
+    }
   } else if (MODE == MODE_SUB2) {
     load9(r.X0, E, P, e, p, X);
   } else {
@@ -124,16 +129,26 @@ __device__ inline void stage_input(const Regs& r, int E, int P, int e, int p, co
   }
 }
 
+// Stiff-source term of substep 2 (half = 0: dt (b S_1 + e S_2)) or substep 3
+// (half = 1: dt S_2 / 6) as a nine-component vector, from the pre-stage pass.
+__device__ inline void load_stiff_terms(const Regs& r, int E, int P, int e, int p, int half, double* T) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) T[v] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) T[stiff_comp(k)] = r.K[((size_t)(half * NK + k) * E + e) * P + p];
+}
+
 // Explicit update Y of substep MODE (before the filter and the implicit solve) and the new
 // accumulator.  L is the explicit operator at the stage input X.
-template <int MODE>
+template <int MODE, bool PRE = false>
 __device__ inline void stage_update(const Regs& r, int E, int P, int e, int p, const Metric& M, const KArgs& a,
                                     const double* X, const double* L, double* Y, double* Anew) {
-  double Un[NV], S1[NV], S2[NV], U2[NV];
+  double Un[NV];
   load9(r.Un, E, P, e, p, Un);
   const double dt = dt_of(a, e);
   if (MODE == MODE_SUB1) {
     // the substep input X is U_2 itself
+    double S2[NV];
     source_stiff(X, M, a.eta, a.kpsi, a.kphi, S2);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -141,25 +156,39 @@ __device__ inline void stage_update(const Regs& r, int E, int P, int e, int p, c
       Anew[v] = dt * L[v];
     }
   } else if (MODE == MODE_SUB2) {
-    double A[NV], S3[NV];
+    double A[NV], S3[NV], T[NV];
     load9(r.A, E, P, e, p, A);
-    derived_stages(Un, M, a, dt, U2, S1, S2);
+    if (PRE) {
+      load_stiff_terms(r, E, P, e, p, 0, T);
+    } else {
+      double S1[NV], S2[NV], U2[NV];
+      derived_stages(Un, M, a, dt, U2, S1, S2);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) T[v] = dt * (IMEX_B * S1[v] + IMEX_E * S2[v]);
+    }
     source_stiff(X, M, a.eta, a.kpsi, a.kphi, S3);
     const double c3 = 0.5 - IMEX_B - IMEX_E - IMEX_A;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const double inc = A[v] + dt * L[v];
-      Y[v] = Un[v] + 0.25 * inc + dt * (IMEX_B * S1[v] + IMEX_E * S2[v] + c3 * S3[v]);
+      Y[v] = Un[v] + 0.25 * inc + T[v] + dt * c3 * S3[v];
       Anew[v] = inc / 6.0 + dt * S3[v] / 6.0;
     }
   } else {
-    double A[NV], S4[NV];
+    double A[NV], S4[NV], T[NV];
     load9(r.A, E, P, e, p, A);
-    derived_stages(Un, M, a, dt, U2, S1, S2);
+    if (PRE) {
+      load_stiff_terms(r, E, P, e, p, 1, T);
+    } else {
+      double S1[NV], S2[NV], U2[NV];
+      derived_stages(Un, M, a, dt, U2, S1, S2);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) T[v] = dt * S2[v] / 6.0;
+    }
     source_stiff(X, M, a.eta, a.kpsi, a.kphi, S4);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      Y[v] = Un[v] + A[v] + dt * S2[v] / 6.0 + (2.0 / 3.0) * dt * (L[v] + S4[v]);
+      Y[v] = Un[v] + A[v] + T[v] + (2.0 / 3.0) * dt * (L[v] + S4[v]);
       Anew[v] = 0.0;
     }
   }

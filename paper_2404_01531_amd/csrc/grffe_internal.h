@@ -47,9 +47,14 @@ enum Mode { MODE_RHS = 0, MODE_SUB1 = 1, MODE_SUB2 = 2, MODE_SUB3 = 3 };
 struct Regs {
   double* Un;
   double* X0;  // U_3 (written in substep 1)
-  double* X1;  // U_4 (written in substep 2)
+  double* X1;  // U_2 (written by the pre-stage pass), then U_4 (written in substep 2)
   double* A;   // accumulated increments
+  double* K;   // [10][E][P] stiff-source terms of substeps 2 and 3 (pre-stage pass), or null
 };
+
+// Components of the stiff source that can be non-zero (E~ and psi~, phi~).
+constexpr int NK = 5;
+__host__ __device__ constexpr int stiff_comp(int k) { return k < 3 ? k : k + 3; }
 
 // Everything a kernel needs; passed by value.
 struct KArgs {
@@ -129,8 +134,8 @@ struct grffe_domain {
   double lambda_max = 0.0;
   std::vector<void*> allocs;
   // kernel timing (one family at a time)
-  // kernel timing: bit f of timed_mask times family f (1..8)
-  static constexpr int NFAM = 9;
+  // kernel timing: bit f of timed_mask times family f (1..9)
+  static constexpr int NFAM = 10;
   int timed_mask = 0;
   std::vector<hipEvent_t> ev[NFAM];  // start/stop pairs per family
   size_t ev_used[NFAM] = {};
@@ -151,6 +156,7 @@ LaunchEvents& armed_launch_events();
 // launchers (kernels_dg.hip)
 void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_dg_slab(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
+void launch_dg_prestage(const KArgs& a, int N, bool curved, hipStream_t s);
 // launchers (kernels_fd.hip)
 void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, bool begin, hipStream_t s);
 void launch_fd_trace(const KArgs& a, int N, hipStream_t s);

@@ -36,7 +36,7 @@ __device__ inline void external_state(const KArgs& a, int e, int f, int i, int j
   const int pn = ii + n * (jj + n * kk);
   load_metric<CURVED>(a.bg_dg, a.E, nn, o, pn, Mx);
   if (a.rep0[o] == 0) {
-    stage_input<MODE>(a.dg, a.E, nn, o, pn, Mx, a, Ux);
+    stage_input<MODE, true>(a.dg, a.E, nn, o, pn, Mx, a, Ux);
     current_total(Ux, Mx, a.eta, Jx);
   } else {
     // FD neighbour: R-trace on its face facing us (face 2d + 1 - s)
@@ -54,8 +54,18 @@ __device__ inline void external_state(const KArgs& a, int e, int f, int i, int j
   }
 }
 
+// Workgroups per CU the substep kernel is compiled for: two resident wavefronts per
+// SIMD when curved (about 256 VGPRs per lane hold the metric next to the state),
+// three when flat.
+template <int N, bool CURVED>
+constexpr int dg_min_blocks() {
+  constexpr int waves = Dims<N>::tpb / 64;
+  constexpr int want = (CURVED ? 2 : 3) * 4 / waves;
+  return want > 1 ? want : 1;
+}
+
 template <int N, bool CURVED, int MODE, typename R>
-__global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
+__global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_dg_substep(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn, TPB = Dm::tpb;
   __shared__ double sF[NV * nn];
@@ -76,7 +86,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
   Metric M;
   load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
   double X[NV], Jd[3], Je[3], dU[NV];
-  stage_input<MODE>(a.dg, a.E, nn, e, p, M, a, X);
+  stage_input<MODE, true>(a.dg, a.E, nn, e, p, M, a, X);
   current(X, M, a.eta, Jd, Je);
   {
     MetricDeriv Dv;
@@ -98,6 +108,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
   R* sFr = reinterpret_cast<R*>(sF);
   const int idx[3] = {i, j, k};
   const int strideN[3] = {1, n, n * n};
+  #pragma unroll
   for (int d = 0; d < 3; ++d) {
     R F[NV];
     flux_any(d, Xr, Jr, Mr, F);
@@ -158,8 +169,9 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
   }
   // IMEX stage update, filter on the explicit update, implicit solve
   double Y[NV], Anew[NV];
-  stage_update<MODE>(a.dg, a.E, nn, e, p, M, a, X, dU, Y, Anew);
+  stage_update<MODE, true>(a.dg, a.E, nn, e, p, M, a, X, dU, Y, Anew);
   if (a.filter_on) {
+    #pragma unroll
     for (int d = 0; d < 3; ++d) {
       __syncthreads();
       if (act)
@@ -184,6 +196,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
   if (a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
     const double u = act ? sqrt(dot3(M, Y + 3, Y + 3)) : 0.0;
     double uh = u;
+    #pragma unroll
     for (int d = 0; d < 3; ++d) {
       __syncthreads();
       if (act) sF[p] = uh;
@@ -218,6 +231,33 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_substep(KArgs a) {
   }
 }
 
+// Pre-stage pass at the start of a step, pointwise on every DG node: the implicit
+// stages U_1 = solve(U^n), U_2 = solve(U^n - a dt S(U_1)) of IMEX-SSP3(4,3,3) depend
+// on U^n alone, so they are computed once per step: U_2 (the input of substep 1)
+// goes to X1, and the stiff-source terms that substeps 2 and 3 add,
+// dt (b S(U_1) + e S(U_2)) and dt S(U_2) / 6, go to K (their five non-zero
+// components).  Neighbours read U_2 from X1 for their face states.
+template <int N, bool CURVED>
+__global__ __launch_bounds__(256) void k_dg_prestage(KArgs a) {
+  constexpr int nn = Dims<N>::nn;
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int e = gid / nn, p = gid % nn;
+  if (e >= a.E || !a.live[e] || a.rep[e] != 0) return;
+  Metric M;
+  load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
+  double Un[NV], U2[NV], S1[NV], S2[NV];
+  load9(a.dg.Un, a.E, nn, e, p, Un);
+  const double dt = dt_of(a, e);
+  derived_stages(Un, M, a, dt, U2, S1, S2);
+  store9(a.dg.X1, a.E, nn, e, p, U2);
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int v = stiff_comp(k);
+    a.dg.K[((size_t)k * a.E + e) * nn + p] = dt * (IMEX_B * S1[v] + IMEX_E * S2[v]);
+    a.dg.K[((size_t)(NK + k) * a.E + e) * nn + p] = dt * S2[v] / 6.0;
+  }
+}
+
 // P-projection (3 subcell layers next to each face) of the DG stage input of
 // elements whose neighbour across that face is on FD or has just been flagged.
 // The twelve transported components (U, J~) are projected together, one face at
@@ -244,7 +284,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
     Metric M;
     load_metric<CURVED>(a.bg_dg, a.E, nn, e, t, M);
     double X[NV];
-    stage_input<MODE>(a.dg, a.E, nn, e, t, M, a, X);
+    stage_input<MODE, true>(a.dg, a.E, nn, e, t, M, a, X);
     double J[3];
     current_total(X, M, a.eta, J);
     for (int v = 0; v < NV; ++v) sW[v * nn + t] = X[v];
@@ -334,6 +374,24 @@ void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t
   } else {
 #define CURVED_T false
     GRFFE_DISPATCH_N(launch_dg_substep_t, a, mode, s)
+#undef CURVED_T
+  }
+}
+
+template <int N, bool CURVED>
+static void launch_dg_prestage_t(const KArgs& a, hipStream_t s) {
+  const int blocks = (int)(((size_t)a.E * Dims<N>::nn + 255) / 256);
+  launch_kernel(k_dg_prestage<N, CURVED>, dim3(blocks), dim3(256), s, a);
+}
+
+void launch_dg_prestage(const KArgs& a, int N, bool curved, hipStream_t s) {
+  if (curved) {
+#define CURVED_T true
+    GRFFE_DISPATCH_N(launch_dg_prestage_t, a, s)
+#undef CURVED_T
+  } else {
+#define CURVED_T false
+    GRFFE_DISPATCH_N(launch_dg_prestage_t, a, s)
 #undef CURVED_T
   }
 }

@@ -97,13 +97,11 @@ __device__ inline void current(const T* U, const MetricT<T>& M, double eta, T* J
   lower3(M, E, El);
   lower3(M, B, Bl);
   const T B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
-  if (!(B2 > 0.0)) {
-    for (int i = 0; i < 3; ++i) Jd[i] = Je[i] = T(0.0);
-    return;
-  }
   const T E2 = E[0] * El[0] + E[1] * El[1] + E[2] * El[2];
   const T EB = E[0] * Bl[0] + E[1] * Bl[1] + E[2] * Bl[2];
-  const T iB2 = T(1.0) / B2;
+  // B^2 = 0: both parts vanish (1/B^2 is replaced by 0; no branch, so the
+  // outputs stay in registers)
+  const T iB2 = (B2 > 0.0) ? T(1.0) / B2 : T(0.0);
   const T cd = M.alpha * U[8] * iB2 / M.sqrtg;
   Jd[0] = cd * (El[1] * Bl[2] - El[2] * Bl[1]);
   Jd[1] = cd * (El[2] * Bl[0] - El[0] * Bl[2]);

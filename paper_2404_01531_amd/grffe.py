@@ -21,7 +21,7 @@ BC_NO_INCOMING_POYNTING = 1
 PART_EXPLICIT, PART_STIFF, PART_ALL = 1, 2, 3
 HYBRID_DG_ONLY, HYBRID_ADAPTIVE, HYBRID_FORCED = 0, 1, 2
 KERNEL_FAMILIES = {"dg_substep": 1, "fd_flux": 2, "fd_update": 3, "fd_stage": 4, "fd_trace": 5,
-                   "dg_slab": 6, "project": 7, "fd_to_dg": 8}
+                   "dg_slab": 6, "project": 7, "fd_to_dg": 8, "dg_prestage": 9}
 
 
 class GrffeError(RuntimeError):
