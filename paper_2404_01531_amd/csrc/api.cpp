@@ -285,6 +285,7 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   ALLOC(fd.X0, regfd);
   ALLOC(fd.X1, regfd);
   ALLOC(fd.A, regfd);
+  ALLOC(fd.K, (size_t)2 * NK * E * mm * sizeof(double));
   ALLOC(rep, sizeof(int32_t) * E);
   ALLOC(rep0, sizeof(int32_t) * E);
   ALLOC(troubled, E);
@@ -322,6 +323,7 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   CHK(hipMemsetAsync(d->dg.K, 0, (size_t)2 * NK * E * nn * sizeof(double), st));
   for (void* r : {(void*)d->fd.Un, (void*)d->fd.X0, (void*)d->fd.X1, (void*)d->fd.A})
     CHK(hipMemsetAsync(r, 0, regfd, st));
+  CHK(hipMemsetAsync(d->fd.K, 0, (size_t)2 * NK * E * mm * sizeof(double), st));
   CHK(hipMemsetAsync(d->rep, 0, sizeof(int32_t) * E, st));
   CHK(hipMemsetAsync(d->rep0, 0, sizeof(int32_t) * E, st));
   CHK(hipMemsetAsync(d->troubled, 0, E, st));

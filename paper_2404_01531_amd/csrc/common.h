@@ -129,6 +129,18 @@ __device__ inline void stage_input(const Regs& r, int E, int P, int e, int p, co
   }
 }
 
+// Store the stiff-source terms of substeps 2 and 3 (the five non-zero components of
+// dt (b S_1 + e S_2) and of dt S_2 / 6) computed from the pre-stages.
+__device__ inline void store_stiff_terms(const Regs& r, int E, int P, int e, int p, double dt, const double* S1,
+                                         const double* S2) {
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int v = stiff_comp(k);
+    r.K[((size_t)k * E + e) * P + p] = dt * (IMEX_B * S1[v] + IMEX_E * S2[v]);
+    r.K[((size_t)(NK + k) * E + e) * P + p] = dt * S2[v] / 6.0;
+  }
+}
+
 // Stiff-source term of substep 2 (half = 0: dt (b S_1 + e S_2)) or substep 3
 // (half = 1: dt S_2 / 6) as a nine-component vector, from the pre-stage pass.
 __device__ inline void load_stiff_terms(const Regs& r, int E, int P, int e, int p, int half, double* T) {

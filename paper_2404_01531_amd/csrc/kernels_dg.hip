@@ -250,12 +250,7 @@ __global__ __launch_bounds__(256) void k_dg_prestage(KArgs a) {
   const double dt = dt_of(a, e);
   derived_stages(Un, M, a, dt, U2, S1, S2);
   store9(a.dg.X1, a.E, nn, e, p, U2);
-#pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    const int v = stiff_comp(k);
-    a.dg.K[((size_t)k * a.E + e) * nn + p] = dt * (IMEX_B * S1[v] + IMEX_E * S2[v]);
-    a.dg.K[((size_t)(NK + k) * a.E + e) * nn + p] = dt * S2[v] / 6.0;
-  }
+  store_stiff_terms(a.dg, a.E, nn, e, p, dt, S1, S2);
 }
 
 // P-projection (3 subcell layers next to each face) of the DG stage input of

@@ -39,7 +39,17 @@ __global__ __launch_bounds__(256) void k_fd_stage(KArgs a, int begin) {
   Metric M;
   load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
   double X[NV], J[3];
-  stage_input<MODE>(a.fd, a.E, mm, e, p, M, a, X);
+  if (MODE == MODE_SUB1) {
+    // the implicit pre-stages of the step: U_2 is this substep's input, the
+    // stiff-source terms of substeps 2 and 3 are kept for the updates
+    double Un[NV], S1[NV], S2[NV];
+    load9(a.fd.Un, a.E, mm, e, p, Un);
+    const double dt = dt_of(a, e);
+    derived_stages(Un, M, a, dt, X, S1, S2);
+    store_stiff_terms(a.fd, a.E, mm, e, p, dt, S1, S2);
+  } else {
+    stage_input<MODE>(a.fd, a.E, mm, e, p, M, a, X);
+  }
   current_total(X, M, a.eta, J);
   const size_t st = (size_t)a.E * mm;
   double* w = a.w_fd + (size_t)e * mm + p;
@@ -172,7 +182,17 @@ __global__ __launch_bounds__(256) void k_project_troubled(KArgs a) {
     Metric M;
     load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
     double X[NV], J[3];
-    stage_input<MODE>(a.fd, a.E, mm, e, p, M, a, X);
+    {
+      // pre-stages re-derived from the projected U^n
+      double Un[NV], U2[NV], S1[NV], S2[NV];
+      load9(a.fd.Un, a.E, mm, e, p, Un);
+      const double dt = dt_of(a, e);
+      derived_stages(Un, M, a, dt, U2, S1, S2);
+      store_stiff_terms(a.fd, a.E, mm, e, p, dt, S1, S2);
+      if (MODE == MODE_SUB1)
+        for (int v = 0; v < NV; ++v) X[v] = U2[v];
+    }
+    if (MODE != MODE_SUB1) stage_input<MODE>(a.fd, a.E, mm, e, p, M, a, X);
     current_total(X, M, a.eta, J);
     const size_t st = (size_t)a.E * mm;
     double* w = a.w_fd + (size_t)e * mm + p;
@@ -505,7 +525,7 @@ __global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
     return;
   }
   double Y[NV], Anew[NV];
-  stage_update<MODE>(a.fd, a.E, mm, e, p, M, a, X, dU, Y, Anew);
+  stage_update<MODE, true>(a.fd, a.E, mm, e, p, M, a, X, dU, Y, Anew);
   if (MODE != MODE_SUB3) implicit_solve(Y, M, a.eta, a.kpsi, a.kphi, dt_of(a, e) * IMEX_A);
   if (a.ff_clamp) constraint_clamp(Y, M, a.ff_margin);
   if (MODE == MODE_SUB1) {
