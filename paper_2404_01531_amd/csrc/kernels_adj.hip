@@ -184,7 +184,6 @@ __device__ void operator_vjp(const KArgs& a, const AdjBufs& b, int e, int p, boo
       const double wl = sc / a.ops->w[0], wr = sc / a.ops->w[N];
       // the node's own face term (interior dependence)
       const int o = a.nbr[e * 6 + 2 * d + s];
-      Metric Mo;
       int pn = 0;
       if (o >= 0) {
         int ii = idx[0], jj = idx[1], kk = idx[2];
@@ -192,9 +191,10 @@ __device__ void operator_vjp(const KArgs& a, const AdjBufs& b, int e, int p, boo
         else if (d == 1) jj = s ? 0 : N;
         else kk = s ? 0 : N;
         pn = ii + n * (jj + n * kk);
-        load_metric<CURVED>(a.bg_dg, a.E, nn, o, pn, Mo);
       }
-      const double lam = CURVED ? (o >= 0 ? fmax(char_speed(d, M), char_speed(d, Mo)) : char_speed(d, M)) : 1.0;
+      // both sides of a face node use the element's own nodal metric (one point of
+      // a continuous background), so the Rusanov speed is that of X's node
+      const double lam = CURVED ? char_speed(d, M) : 1.0;
       if (s == 0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {

@@ -34,7 +34,9 @@ __device__ inline void external_state(const KArgs& a, int e, int f, int i, int j
   else if (d == 1) jj = s ? 0 : N;
   else kk = s ? 0 : N;
   const int pn = ii + n * (jj + n * kk);
-  load_metric<CURVED>(a.bg_dg, a.E, nn, o, pn, Mx);
+  // the face node is one point of a continuous background: the element's own nodal
+  // metric there is the neighbour's as well
+  Mx = Mi;
   if (a.rep0[o] == 0) {
     stage_input<MODE, true>(a.dg, a.E, nn, o, pn, Mx, a, Ux);
     current_total(Ux, Mx, a.eta, Jx);

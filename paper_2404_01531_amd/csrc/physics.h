@@ -18,7 +18,7 @@ namespace grffe {
 // Metric at one point.  g and gi are symmetric, stored xx, xy, xz, yy, yz, zz.
 template <typename T>
 struct MetricT {
-  T alpha, beta[3], g[6], gi[6], sqrtg;
+  T alpha, beta[3], g[6], gi[6], sqrtg, isqrtg;  // isqrtg = 1 / sqrt(gamma)
 };
 using Metric = MetricT<double>;
 
@@ -28,6 +28,7 @@ template <typename T>
 __device__ inline void metric_cast(const Metric& M, MetricT<T>& o) {
   o.alpha = (T)M.alpha;
   o.sqrtg = (T)M.sqrtg;
+  o.isqrtg = (T)M.isqrtg;
   for (int k = 0; k < 3; ++k) o.beta[k] = (T)M.beta[k];
   for (int k = 0; k < 6; ++k) {
     o.g[k] = (T)M.g[k];
@@ -47,6 +48,7 @@ __device__ inline void metric_flat(Metric& M) {
   M.g[0] = M.g[3] = M.g[5] = 1.0;
   M.gi[0] = M.gi[3] = M.gi[5] = 1.0;
   M.sqrtg = 1.0;
+  M.isqrtg = 1.0;
 }
 
 // From the 10 leading background fields (alpha, beta^i, gamma_ij packed).
@@ -72,6 +74,7 @@ __device__ inline void metric_from10(const double f[10], Metric& M) {
   M.gi[4] = c_yz * inv;
   M.gi[5] = c_zz * inv;
   M.sqrtg = sqrt(det);
+  M.isqrtg = M.sqrtg * inv;
 }
 
 template <typename T>
@@ -102,7 +105,7 @@ __device__ inline void current(const T* U, const MetricT<T>& M, double eta, T* J
   // B^2 = 0: both parts vanish (1/B^2 is replaced by 0; no branch, so the
   // outputs stay in registers)
   const T iB2 = (B2 > 0.0) ? T(1.0) / B2 : T(0.0);
-  const T cd = M.alpha * U[8] * iB2 / M.sqrtg;
+  const T cd = M.alpha * U[8] * iB2 * M.isqrtg;
   Jd[0] = cd * (El[1] * Bl[2] - El[2] * Bl[1]);
   Jd[1] = cd * (El[2] * Bl[0] - El[0] * Bl[2]);
   Jd[2] = cd * (El[0] * Bl[1] - El[1] * Bl[0]);
@@ -131,7 +134,7 @@ __device__ inline void flux_dir(const T* U, T jd, const MetricT<T>& M, T* F) {
   T El[3], Bl[3];
   lower3(M, E, El);
   lower3(M, B, Bl);
-  const T a = M.alpha, bd = M.beta[D], isg = T(1) / M.sqrtg;
+  const T a = M.alpha, bd = M.beta[D], isg = M.isqrtg;
   const T psi = U[6], phi = U[7];
   // [i D k] X_k for i = 0..2
   T eB[3], eE[3];
