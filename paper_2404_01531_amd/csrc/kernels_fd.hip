@@ -400,9 +400,55 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
     if (c >= 0) sRf[kt * FP + c] = rgt;
   }
   __syncthreads();
-  // phase 3: fluxes at every face of every pencil
+  // phase 3a: cell-centred fluxes of cells -1 .. m of every pencil (the corrector's
+  // F_i), each computed once; they replace the staged cells in LDS
+  static_assert(L * (m + 2) <= 256 && L * F <= 256, "one cell / one face per thread in phase 3");
+  constexpr int CF = m + 2;  // cells -1 .. m
+  R Fcell[NV];
+  const bool corr = a.fd_order == 4;
+  if (corr && t < L * CF) {
+    int c, t1;
+    if (d == 0) {
+      c = t % CF;
+      t1 = t / CF;
+    } else {
+      t1 = t % L;
+      c = t / L;
+    }
+    R W[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) W[k] = (R)sW[(k * L + t1) * C + c + 2];
+    Metric Mc;
+    if (CURVED) {
+      double fm[10];
+      const double* o = sM + t1 * (m + 2) + c;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) fm[k] = o[k * L * (m + 2)];
+      metric_from10(fm, Mc);
+    } else {
+      metric_flat(Mc);
+    }
+    MetricT<R> Mcr;
+    metric_cast(Mc, Mcr);
+    flux_any_jd(d, W, W[NV], Mcr, Fcell);
+  }
+  __syncthreads();
+  double* sFc = sW;  // [9][L][m+2], cell -1 at index 0
+  if (corr && t < L * CF) {
+    int c, t1;
+    if (d == 0) {
+      c = t % CF;
+      t1 = t / CF;
+    } else {
+      t1 = t % L;
+      c = t / L;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sFc[(v * L + t1) * CF + c] = (double)Fcell[v];
+  }
+  __syncthreads();
+  // phase 3b: fluxes at every face of every pencil
   double Fh[NV];
-  static_assert(L * F <= 256, "one face per thread in phase 3");
   const int q3 = t;
   int f3 = 0, t13 = 0;
   if (q3 < L * F) {
@@ -435,31 +481,14 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
     const R lam = CURVED ? (R)char_speed(d, Mf) : R(1);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fr[v] = R(0.5) * (Fr[v] + Ft[v]) - R(0.5) * lam * (WR[v] - WL[v]);
-    if (a.fd_order == 4) {
-      // cell-centred fluxes of cells f-1 and f (extended indices f+2 and f+3)
-      for (int side = 0; side < 2; ++side) {
-        R W[NR];
+    if (corr) {
+      // F* - (F_{f-1} - 2 F* + F_f) / 6 with the cell fluxes of cells f-1 and f
 #pragma unroll
-        for (int k = 0; k < NR; ++k) W[k] = (R)sW[(k * L + t13) * C + f3 + 2 + side];
-        Metric Mc;
-        if (CURVED) {
-          double fm[10];
-          const double* o = sM + t13 * (m + 2) + f3 + side;
-#pragma unroll
-          for (int k = 0; k < 10; ++k) fm[k] = o[k * L * (m + 2)];
-          metric_from10(fm, Mc);
-        } else {
-          metric_flat(Mc);
-        }
-        MetricT<R> Mcr;
-        metric_cast(Mc, Mcr);
-        R Fc[NV];
-        flux_any_jd(d, W, W[NV], Mcr, Fc);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Ft[v] = side ? Ft[v] + Fc[v] : Fc[v];
+      for (int v = 0; v < NV; ++v) {
+        const double* fc = sFc + (v * L + t13) * CF + f3;
+        const R G = ((R)fc[0] - R(2) * Fr[v] + (R)fc[1]) * R(1.0 / 6.0);
+        Fr[v] = Fr[v] - G;
       }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Fr[v] = Fr[v] - (Ft[v] - R(2) * Fr[v]) / R(6);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fh[v] = (double)Fr[v];
