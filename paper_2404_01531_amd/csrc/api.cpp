@@ -99,6 +99,9 @@ KArgs make_args(grffe_domain* d) {
   a.precision = d->par.precision;
   a.weno_eps = d->par.weno_eps;
   a.ff_margin = d->par.ff_margin;
+  a.fd_list = d->fd_list;
+  a.fd_count = d->fd_count;
+  a.sub = 0;
   a.parts = GRFFE_PART_ALL;
   return a;
 }
@@ -294,6 +297,8 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   ALLOC(trace, sizeof(double) * NW * E * 6 * n * n);
   ALLOC(slab, sizeof(double) * NW * E * 6 * 3 * m * m);
   ALLOC(fhat, sizeof(double) * 3 * NV * E * mm);
+  ALLOC(fd_list, sizeof(int32_t) * E);
+  ALLOC(fd_count, sizeof(int32_t) * 4);
   double* qdev = nullptr;
   if (d->curved) {
     ALLOC(bg_dg, sizeof(double) * NBG * E * nn);
@@ -328,6 +333,7 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   CHK(hipMemsetAsync(d->rep0, 0, sizeof(int32_t) * E, st));
   CHK(hipMemsetAsync(d->troubled, 0, E, st));
   CHK(hipMemsetAsync(d->ratio, 0, sizeof(double) * E, st));
+  CHK(hipMemsetAsync(d->fd_count, 0, sizeof(int32_t) * 4, st));
   // time step per grid: lambda_max from the background (1 in flat space)
   for (auto& pt : d->parts) pt.lambda_max = 1.0;
   if (d->curved) {
@@ -469,7 +475,9 @@ struct TimedLaunch {
 static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   const int N = d->N;
   const bool cv = d->curved;
-  { TimedLaunch t(d, 4, st); launch_fd_stage(a, N, cv, mode, mode != MODE_RHS, st); }
+  a.sub = mode == MODE_RHS ? 3 : mode - 1;
+  launch_begin_substep(a, mode != MODE_RHS, st);
+  { TimedLaunch t(d, 4, st); launch_fd_stage(a, N, cv, mode, st); }
   { TimedLaunch t(d, 5, st); launch_fd_trace(a, N, st); }
   { TimedLaunch t(d, 1, st); launch_dg_substep(a, N, cv, mode, st); }
   { TimedLaunch t(d, 6, st); launch_dg_slab(a, N, cv, mode, st); }
@@ -522,6 +530,7 @@ extern "C" int grffe_rhs(grffe_domain* d, const double* dg, const double* fd, co
   a.out_fd = dfd;
   a.parts = parts;
   HIPCHK(hipMemsetAsync(d->troubled, 0, d->E, st));
+  HIPCHK(hipMemsetAsync(d->fd_count + 3, 0, sizeof(int32_t), st));
   run_substep(d, a, MODE_RHS, st);
   HIPCHK(hipGetLastError());
   return GRFFE_OK;

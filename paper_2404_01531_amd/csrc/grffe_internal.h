@@ -87,6 +87,11 @@ struct KArgs {
   double tci_thr, tci_thr_fd;
   int tci_mode, filter_on, fd_order, ff_clamp, hybrid, precision;
   double weno_eps, ff_margin;
+  // work list of the FD kernels: element ids fd_list[0 .. fd_count[sub]), where sub
+  // is the substep (0, 1, 2) or 3 for a right-hand side evaluation
+  int32_t* fd_list;
+  int32_t* fd_count;
+  int sub;
 };
 
 }  // namespace grffe
@@ -128,6 +133,8 @@ struct grffe_domain {
   double* trace = nullptr;
   double* slab = nullptr;
   double* fhat = nullptr;
+  int32_t* fd_list = nullptr;   // [E] work list of the FD kernels
+  int32_t* fd_count = nullptr;  // [4] list lengths (three substeps, right-hand side)
   double* adj_ws = nullptr;  // step adjoint: 6 DG-sized arrays, allocated at first use
   double* adj_u0 = nullptr;  // step adjoint: copy of U^n
   double dt_cfl = 0.0;
@@ -158,13 +165,13 @@ void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t
 void launch_dg_slab(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_dg_prestage(const KArgs& a, int N, bool curved, hipStream_t s);
 // launchers (kernels_fd.hip)
-void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, bool begin, hipStream_t s);
+void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_fd_trace(const KArgs& a, int N, hipStream_t s);
 void launch_project_troubled(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_fd_flux(const KArgs& a, int N, bool curved, hipStream_t s);
 void launch_fd_update(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_fd_to_dg(const KArgs& a, int N, bool curved, int init, hipStream_t s);
-void launch_begin_substep(const KArgs& a, hipStream_t s);
+void launch_begin_substep(const KArgs& a, bool copy, hipStream_t s);
 void launch_tci(const KArgs& a, int N, bool curved, const double* dg, const double* fd, const int32_t* rep,
                 uint8_t* troubled, double* ratio, hipStream_t s);
 void launch_transfer(const KArgs& a, int N, int to_fd, const double* in, double* out, int count, hipStream_t s);

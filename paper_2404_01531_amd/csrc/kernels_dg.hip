@@ -218,7 +218,10 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
     bad = ratio > a.tci_thr;
     if (t == 0) {
       a.ratio[e] = ratio;
-      if (bad) a.troubled[e] = 1;
+      if (bad) {
+        a.troubled[e] = 1;
+        a.fd_list[atomicAdd(a.fd_count + a.sub, 1)] = e;  // redone on FD in this substep
+      }
     }
   }
   if (bad || !act) return;

@@ -15,48 +15,62 @@
 
 namespace grffe {
 
-__device__ inline bool fd_active(const KArgs& a, int e) {
-  return a.live[e] && (a.rep0[e] == 1 || a.troubled[e]);
+// ---------------------------------------------------------------- substep start
+// Opens a substep: with `copy` the representation at the substep start (rep0) is
+// taken from rep and the flags are cleared; every live FD element is appended to
+// the substep's work list fd_list (count fd_count[sub]).  The list of the next
+// substep is emptied here: its previous users ran in the previous step.  The
+// DG substep kernel appends the elements it flags, so the FD flux and update
+// launches see both.  List order does not affect any result.
+__global__ __launch_bounds__(256) void k_begin_substep(KArgs a, int copy) {
+  if (a.sub < 3 && blockIdx.x == 0 && threadIdx.x == 0) a.fd_count[(a.sub + 1) % 3] = 0;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.E) return;
+  int r;
+  if (copy) {
+    r = a.rep[e];
+    a.rep0[e] = r;
+    a.troubled[e] = 0;
+  } else {
+    r = a.rep0[e];
+  }
+  if (a.live[e] && r == 1) a.fd_list[atomicAdd(a.fd_count + a.sub, 1)] = e;
 }
 
 // ---------------------------------------------------------------- FD stage values + J~
-// With `begin` set this launch also opens the substep: the representation at
-// the substep start (rep0) is taken from rep and the flags are cleared.  Only the
-// element's own entries are touched, and no other element's rep0 is read here.
+// Work items: (listed FD element, block of 256 cells).
 template <int N, bool CURVED, int MODE>
-__global__ __launch_bounds__(256) void k_fd_stage(KArgs a, int begin) {
+__global__ __launch_bounds__(256) void k_fd_stage(KArgs a) {
   using Dm = Dims<N>;
   constexpr int mm = Dm::mm;
-  const int e = blockIdx.y;
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (!a.live[e]) return;
-  const int r = begin ? a.rep[e] : a.rep0[e];
-  if (begin && blockIdx.x == 0 && threadIdx.x == 0) {
-    a.rep0[e] = r;
-    a.troubled[e] = 0;
-  }
-  if (p >= mm || r != 1) return;
-  Metric M;
-  load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
-  double X[NV], J[3];
-  if (MODE == MODE_SUB1) {
-    // the implicit pre-stages of the step: U_2 is this substep's input, the
-    // stiff-source terms of substeps 2 and 3 are kept for the updates
-    double Un[NV], S1[NV], S2[NV];
-    load9(a.fd.Un, a.E, mm, e, p, Un);
-    const double dt = dt_of(a, e);
-    derived_stages(Un, M, a, dt, X, S1, S2);
-    store_stiff_terms(a.fd, a.E, mm, e, p, dt, S1, S2);
-  } else {
-    stage_input<MODE>(a.fd, a.E, mm, e, p, M, a, X);
-  }
-  current_total(X, M, a.eta, J);
-  const size_t st = (size_t)a.E * mm;
-  double* w = a.w_fd + (size_t)e * mm + p;
+  constexpr int BPE = (mm + 255) / 256;
+  const int items = a.fd_count[a.sub] * BPE;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int e = a.fd_list[item / BPE];
+    const int p = (item % BPE) * 256 + threadIdx.x;
+    if (p >= mm) continue;
+    Metric M;
+    load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
+    double X[NV], J[3];
+    if (MODE == MODE_SUB1) {
+      // the implicit pre-stages of the step: U_2 is this substep's input, the
+      // stiff-source terms of substeps 2 and 3 are kept for the updates
+      double Un[NV], S1[NV], S2[NV];
+      load9(a.fd.Un, a.E, mm, e, p, Un);
+      const double dt = dt_of(a, e);
+      derived_stages(Un, M, a, dt, X, S1, S2);
+      store_stiff_terms(a.fd, a.E, mm, e, p, dt, S1, S2);
+    } else {
+      stage_input<MODE>(a.fd, a.E, mm, e, p, M, a, X);
+    }
+    current_total(X, M, a.eta, J);
+    const size_t st = (size_t)a.E * mm;
+    double* w = a.w_fd + (size_t)e * mm + p;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) w[v * st] = X[v];
+    for (int v = 0; v < NV; ++v) w[v * st] = X[v];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) w[(9 + c) * st] = J[c];
+    for (int c = 0; c < 3; ++c) w[(9 + c) * st] = J[c];
+  }
 }
 
 // ---------------------------------------------------------------- R-traces of FD elements
@@ -66,21 +80,25 @@ template <int N>
 __global__ __launch_bounds__(256) void k_fd_trace(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, m = Dm::m, mm = Dm::mm;
-  const int e = blockIdx.x;
-  const int c = blockIdx.y;
-  if (!a.live[e] || a.rep0[e] != 1) return;
-  int need = 0;
-  for (int f = 0; f < 6; ++f) {
-    const int o = a.nbr[e * 6 + f];
-    if (o >= 0 && a.rep0[o] == 0) need |= 1 << f;
-  }
-  if (!need) return;
   __shared__ double sW[mm];
   __shared__ double s1[6 * m * m];
   __shared__ double s2[6 * n * m];
   __shared__ double sR[n * m];
   const int t = threadIdx.x;
   for (int q = t; q < n * m; q += 256) sR[q] = a.ops->R[q];
+  // work items: (listed FD element, transported component); the list holds the
+  // elements on FD at the substep start only at this point
+  const int items = a.fd_count[a.sub] * NW;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+  const int e = a.fd_list[item / NW];
+  const int c = item % NW;
+  int need = 0;
+  for (int f = 0; f < 6; ++f) {
+    const int o = a.nbr[e * 6 + f];
+    if (o >= 0 && a.rep0[o] == 0) need |= 1 << f;
+  }
+  if (!need) continue;
+  __syncthreads();
   for (int q = t; q < mm; q += 256) sW[q] = a.w_fd[((size_t)c * a.E + e) * mm + q];
   __syncthreads();
   const int str[3] = {1, m, m * m};
@@ -114,6 +132,7 @@ __global__ __launch_bounds__(256) void k_fd_trace(KArgs a) {
     double acc = 0.0;
     for (int z = 0; z < m; ++z) acc += sR[a2 * m + z] * s2[(f * m + z) * n + a1];
     a.trace[((size_t)c * a.E * 6 + (size_t)e * 6 + f) * (n * n) + r] = acc;
+  }
   }
 }
 
@@ -332,15 +351,17 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   constexpr int F = m + 1;  // faces per pencil
   constexpr int FP = F + 1;  // padded (odd) LDS row length of face arrays
   constexpr int NR = NV + 1;  // reconstructed components: U and J~^d
-  const int e = blockIdx.z;
-  const int d = blockIdx.y;
-  const int t2 = blockIdx.x;
-  if (!fd_active(a, e)) return;
   __shared__ double sW[NR * L * C];
   __shared__ double sLf[NR * L * FP];
   __shared__ double sRf[NR * L * FP];
   __shared__ double sM[CURVED ? NBGF * L * (m + 2) : 1];
   const int t = threadIdx.x;
+  // work items: (listed FD element, direction, row of pencils)
+  const int items = a.fd_count[a.sub] * 3 * m;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+  const int e = a.fd_list[item / (3 * m)];
+  const int d = (item / m) % 3;
+  const int t2 = item % m;
   // phase 1: stage cells -3 .. m+2 of every pencil (and the metric of cells -1 .. m)
   for (int q = t; q < L * C; q += 256) {
     int c, t1;
@@ -521,15 +542,22 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
       out[(size_t)v * a.E * mm] = -sc * (fh[1] - fh[0]);
     }
   }
+  __syncthreads();  // the next item restages sW
+  }
 }
 
 template <int N, bool CURVED, int MODE>
 __global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
   using Dm = Dims<N>;
   constexpr int mm = Dm::mm;
-  const int e = blockIdx.y;
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= mm || !fd_active(a, e)) return;
+  constexpr int BPE = (mm + 255) / 256;
+  // work items: (listed FD element, block of 256 cells); the list holds the
+  // substep's FD elements and the elements flagged in it
+  const int items = a.fd_count[a.sub] * BPE;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+  const int e = a.fd_list[item / BPE];
+  const int p = (item % BPE) * 256 + threadIdx.x;
+  if (p >= mm) continue;
   Metric M;
   load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
   double X[NV];
@@ -551,7 +579,7 @@ __global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
     source_stiff(X, M, a.eta, a.kpsi, a.kphi, St);
     for (int v = 0; v < NV; ++v) out[v] = ((a.parts & 1) ? dU[v] : 0.0) + ((a.parts & 2) ? St[v] : 0.0);
     store9(a.out_fd, a.E, mm, e, p, out);
-    return;
+    continue;
   }
   double Y[NV], Anew[NV];
   stage_update<MODE, true>(a.fd, a.E, mm, e, p, M, a, X, dU, Y, Anew);
@@ -567,6 +595,7 @@ __global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
     store9(a.fd.Un, a.E, mm, e, p, Y);
   }
   if (p == 0 && a.troubled[e]) a.rep[e] = 1;
+  }
 }
 
 // ---------------------------------------------------------------- indicator helpers
@@ -860,12 +889,6 @@ __global__ __launch_bounds__(256) void k_lambda_max(KArgs a, double* out) {
   if (threadIdx.x == 0) out[e] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
 }
 
-__global__ void k_begin_substep(KArgs a) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= a.E) return;
-  a.rep0[e] = a.rep[e];
-  a.troubled[e] = 0;
-}
 
 // ------------------------------------------------------------------ launchers
 #define GRFFE_SWITCH_N(CALL)      \
@@ -877,24 +900,30 @@ __global__ void k_begin_substep(KArgs a) {
     default: { constexpr int NN = 7; CALL; } break; \
   }
 
+// Persistent grids of the list-driven kernels: enough workgroups to fill the chip,
+// never more than the largest possible number of work items.
+static dim3 list_grid(size_t max_items, int cap) {
+  return dim3((unsigned)(max_items < (size_t)cap ? (max_items > 0 ? max_items : 1) : cap));
+}
+
 template <int N, bool CURVED>
-static void fd_stage_t(const KArgs& a, int mode, int tro, hipStream_t s) {
-  dim3 grid((Dims<N>::mm + 255) / 256, a.E), block(256);
+static void fd_stage_t(const KArgs& a, int mode, hipStream_t s) {
+  const dim3 grid = list_grid((size_t)a.E * ((Dims<N>::mm + 255) / 256), 2048), block(256);
   switch (mode) {
-    case MODE_RHS: launch_kernel(k_fd_stage<N, CURVED, MODE_RHS>, grid, block, s, a, tro); break;
-    case MODE_SUB1: launch_kernel(k_fd_stage<N, CURVED, MODE_SUB1>, grid, block, s, a, tro); break;
-    case MODE_SUB2: launch_kernel(k_fd_stage<N, CURVED, MODE_SUB2>, grid, block, s, a, tro); break;
-    default: launch_kernel(k_fd_stage<N, CURVED, MODE_SUB3>, grid, block, s, a, tro); break;
+    case MODE_RHS: launch_kernel(k_fd_stage<N, CURVED, MODE_RHS>, grid, block, s, a); break;
+    case MODE_SUB1: launch_kernel(k_fd_stage<N, CURVED, MODE_SUB1>, grid, block, s, a); break;
+    case MODE_SUB2: launch_kernel(k_fd_stage<N, CURVED, MODE_SUB2>, grid, block, s, a); break;
+    default: launch_kernel(k_fd_stage<N, CURVED, MODE_SUB3>, grid, block, s, a); break;
   }
 }
 
-void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, bool troubled_only, hipStream_t s) {
-  if (curved) GRFFE_SWITCH_N((fd_stage_t<NN, true>(a, mode, troubled_only, s)))
-  else GRFFE_SWITCH_N((fd_stage_t<NN, false>(a, mode, troubled_only, s)))
+void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, hipStream_t s) {
+  if (curved) GRFFE_SWITCH_N((fd_stage_t<NN, true>(a, mode, s)))
+  else GRFFE_SWITCH_N((fd_stage_t<NN, false>(a, mode, s)))
 }
 
 void launch_fd_trace(const KArgs& a, int N, hipStream_t s) {
-  GRFFE_SWITCH_N(launch_kernel(k_fd_trace<NN>, dim3(a.E, NW), dim3(256), s, a))
+  GRFFE_SWITCH_N(launch_kernel(k_fd_trace<NN>, list_grid((size_t)a.E * NW, 1024), dim3(256), s, a))
 }
 
 template <int N, bool CURVED>
@@ -914,7 +943,7 @@ void launch_project_troubled(const KArgs& a, int N, bool curved, int mode, hipSt
 template <int N, bool CURVED>
 static void fd_flux_t(const KArgs& a, hipStream_t s) {
   constexpr int m = Dims<N>::m;
-  dim3 grid(m, 3, a.E), block(256);
+  const dim3 grid = list_grid((size_t)a.E * 3 * m, 2048), block(256);
   if (a.precision == GRFFE_PRECISION_MIXED) launch_kernel(k_fd_flux<N, CURVED, float>, grid, block, s, a);
   else launch_kernel(k_fd_flux<N, CURVED, double>, grid, block, s, a);
 }
@@ -926,7 +955,7 @@ void launch_fd_flux(const KArgs& a, int N, bool curved, hipStream_t s) {
 
 template <int N, bool CURVED>
 static void fd_update_t(const KArgs& a, int mode, hipStream_t s) {
-  dim3 grid((Dims<N>::mm + 255) / 256, a.E), block(256);
+  const dim3 grid = list_grid((size_t)a.E * ((Dims<N>::mm + 255) / 256), 2048), block(256);
   switch (mode) {
     case MODE_RHS: launch_kernel(k_fd_update<N, CURVED, MODE_RHS>, grid, block, s, a); break;
     case MODE_SUB1: launch_kernel(k_fd_update<N, CURVED, MODE_SUB1>, grid, block, s, a); break;
@@ -949,8 +978,8 @@ void launch_fd_to_dg(const KArgs& a, int N, bool curved, int init, hipStream_t s
   launch_fd_to_dg_policy(a, N, curved, init, nullptr, s);
 }
 
-void launch_begin_substep(const KArgs& a, hipStream_t s) {
-  launch_kernel(k_begin_substep, dim3((a.E + 255) / 256), dim3(256), s, a);
+void launch_begin_substep(const KArgs& a, bool copy, hipStream_t s) {
+  launch_kernel(k_begin_substep, dim3((a.E + 255) / 256), dim3(256), s, a, copy ? 1 : 0);
 }
 
 void launch_tci(const KArgs& a, int N, bool curved, const double* dg, const double* fd, const int32_t* rep,
