@@ -28,65 +28,153 @@ namespace grffe {
 
 enum AdjStage { ADJ_A3 = 0, ADJ_B1 = 1, ADJ_B2 = 2, ADJ_B3 = 3, ADJ_RHS = 4 };
 
-// Columns of dS_stiff/dU at U (Jm[v][k] = dS_v/dU_k).
-__device__ inline void stiff_jacobian(const double* U, const Metric& M, const KArgs& a, double Jm[NV][NV]) {
+// Levi-Civita symbol [i d k] for i, d, k in {0, 1, 2}.
+__device__ constexpr int levi(int i, int d, int k) { return (i - d) * (d - k) * (k - i) / 2; }
+
+// out += d(G . F^d_lin)/dX, the transpose of the part of the flux F^d that is linear
+// in the state at a fixed metric (every component but the current J~^d of the q~
+// flux):  F_E = -beta^d E + alpha (gamma^{id} psi - [i d k] B_k / sqrt(gamma)),
+// F_B = -beta^d B + alpha (gamma^{id} phi + [i d k] E_k / sqrt(gamma)),
+// F_psi = -beta^d psi + alpha E^d, F_phi = -beta^d phi + alpha B^d, F_q = -beta^d q.
+template <int D>
+__device__ inline void flux_lin_vjp(const Metric& M, const double* G, double* out) {
+  double c[3] = {0.0, 0.0, 0.0}, cp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int lv = levi(i, D, k);
+      if (lv) {
+        c[k] += lv * G[3 + i];
+        cp[k] += lv * G[i];
+      }
+    }
+  double gc[3], gcp[3];
+  lower3(M, c, gc);
+  lower3(M, cp, gcp);
+  const double al = M.alpha, bd = M.beta[D], isg = M.isqrtg;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    out[j] += -bd * G[j] + al * isg * gc[j] + (j == D ? al * G[6] : 0.0);
+    out[3 + j] += -bd * G[3 + j] - al * isg * gcp[j] + (j == D ? al * G[7] : 0.0);
+  }
+  double s6 = 0.0, s7 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    s6 += G[i] * M.gi[sym(i, D)];
+    s7 += G[3 + i] * M.gi[sym(i, D)];
+  }
+  out[6] += al * s6 - bd * G[6];
+  out[7] += al * s7 - bd * G[7];
+  out[8] += -bd * G[8];
+}
+
+// out += gradient of  wa . J_drift(X) + wb . J_driver(X)  (the densitized current's two
+// parts), by forward-mode dual numbers; psi~ and phi~ do not enter the current.
+__device__ inline void current_vjp(const double* X, const Metric& M, double eta, const double* wa, const double* wb,
+                                   double* out) {
   MetricT<Dual> Md;
   metric_cast(M, Md);
+#pragma unroll
   for (int k = 0; k < NV; ++k) {
-    Dual Ud[NV], S[NV];
+    if (k == 6 || k == 7) continue;
+    Dual Xd[NV], Jd[3], Je[3];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Ud[v] = Dual(U[v], v == k ? 1.0 : 0.0);
-    source_stiff(Ud, Md, a.eta, a.kpsi, a.kphi, S);
+    for (int v = 0; v < NV; ++v) Xd[v] = Dual(X[v], v == k ? 1.0 : 0.0);
+    current(Xd, Md, eta, Jd, Je);
+    Dual tot(0.0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Jm[v][k] = S[v].d;
+    for (int i = 0; i < 3; ++i) tot += wa[i] * Jd[i] + wb[i] * Je[i];
+    out[k] += tot.d;
   }
 }
 
-// out += (dS_stiff/dU)^T w at U.
+// out += (dS_ex/dX)^T V for the parts of the explicit source that are linear in X
+// (the drift current's part is taken by current_vjp).
+template <bool CURVED>
+__device__ inline void source_lin_vjp(const Metric& M, const MetricDeriv& Dv, const double* V, double* out) {
+  if (!CURVED) {
+    out[8] += V[6];  // S_psi = q
+    return;
+  }
+  const double al = M.alpha;
+  double ga[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    ga[i] = M.gi[sym(i, 0)] * Dv.da[0] + M.gi[sym(i, 1)] * Dv.da[1] + M.gi[sym(i, 2)] * Dv.da[2];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    double se = 0.0, sb = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      se += V[i] * Dv.db[3 * j + i];
+      sb += V[3 + i] * Dv.db[3 * j + i];
+    }
+    out[j] += -se + V[6] * Dv.da[j];
+    out[3 + j] += -sb + V[7] * Dv.da[j];
+  }
+  double pe = 0.0, pb = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    pe += V[i] * (ga[i] - al * Dv.Gam[i]);
+    pb += V[3 + i] * (ga[i] - al * Dv.Gam[i]);
+  }
+  out[6] += pe - al * Dv.K * V[6];
+  out[7] += pb - al * Dv.K * V[7];
+  out[8] += al * V[6];
+}
+
+// out += (dS_stiff/dU)^T w at U:  S_E = -J_driver, S_psi = -alpha kappa_psi psi,
+// S_phi = -alpha kappa_phi phi.
 __device__ inline void stiff_vjp(const double* U, const Metric& M, const KArgs& a, const double* w, double* out) {
-  double Jm[NV][NV];
-  stiff_jacobian(U, M, a, Jm);
-  for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) s += Jm[v][k] * w[v];
-    out[k] += s;
-  }
+  const double wa[3] = {0.0, 0.0, 0.0}, wb[3] = {-w[0], -w[1], -w[2]};
+  current_vjp(U, M, a.eta, wa, wb, out);
+  out[6] += -M.alpha * a.kpsi * w[6];
+  out[7] += -M.alpha * a.kphi * w[7];
 }
 
-// y = (I - h dS_stiff/dU)^-T ub at the solution U of the implicit solve with step h
-// (Gaussian elimination with partial pivoting).
+// y = (I - h dS_stiff/dU)^-T ub at the solution U of the implicit solve with step h.
+// Only the driver current couples components: with JE = dJe/dE, JB = dJe/dB,
+//   (I + h JE^T) y_E = ub_E,  y_B = ub_B - h JB^T y_E,
+//   y_psi = ub_psi / (1 + h alpha kappa_psi),  y_phi likewise,  y_q = ub_q.
 __device__ inline void solve_vjp(const double* U, const Metric& M, const KArgs& a, double h, const double* ub,
                                  double* y) {
-  double Jm[NV][NV];
-  stiff_jacobian(U, M, a, Jm);
-  double A[NV][NV + 1];
-  for (int r = 0; r < NV; ++r) {
-    for (int c = 0; c < NV; ++c) A[r][c] = (r == c ? 1.0 : 0.0) - h * Jm[c][r];  // transposed
-    A[r][NV] = ub[r];
-  }
-  for (int c = 0; c < NV; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < NV; ++r)
-      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-    if (piv != c)
-      for (int k = c; k <= NV; ++k) {
-        const double t = A[c][k];
-        A[c][k] = A[piv][k];
-        A[piv][k] = t;
-      }
-    const double inv = 1.0 / A[c][c];
-    for (int r = c + 1; r < NV; ++r) {
-      const double f = A[r][c] * inv;
-      if (f != 0.0)
-        for (int k = c; k <= NV; ++k) A[r][k] -= f * A[c][k];
+  double JE[3][3], JB[3][3];  // [i][k] = dJe_i / dE_k (dB_k)
+  MetricT<Dual> Md;
+  metric_cast(M, Md);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    Dual Xd[NV], Jd[3], Je[3];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Xd[v] = Dual(U[v], v == k ? 1.0 : 0.0);
+    current(Xd, Md, a.eta, Jd, Je);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (k < 3) JE[i][k] = Je[i].d;
+      else JB[i][k - 3] = Je[i].d;
     }
   }
-  for (int r = NV - 1; r >= 0; --r) {
-    double s = A[r][NV];
-    for (int k = r + 1; k < NV; ++k) s -= A[r][k] * y[k];
-    y[r] = s / A[r][r];
-  }
+  // A = I + h JE^T, A[r][c] = delta + h JE[c][r]; solve A y_E = ub_E (Cramer's rule)
+  double A[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) A[r][c] = (r == c ? 1.0 : 0.0) + h * JE[c][r];
+  const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+  const double idet = 1.0 / det;
+  const double b0 = ub[0], b1 = ub[1], b2 = ub[2];
+  // inverse via the adjugate
+  y[0] = idet * (c00 * b0 + (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * b1 + (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * b2);
+  y[1] = idet * (c01 * b0 + (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * b1 + (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * b2);
+  y[2] = idet * (c02 * b0 + (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * b1 + (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * b2);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) y[3 + k] = ub[3 + k] - h * (JB[0][k] * y[0] + JB[1][k] * y[1] + JB[2][k] * y[2]);
+  y[6] = ub[6] / (1.0 + h * M.alpha * a.kpsi);
+  y[7] = ub[7] / (1.0 + h * M.alpha * a.kphi);
+  y[8] = ub[8];
 }
 
 // U_1, U_2 of the implicit pre-stages from U^n (as in the forward step).
@@ -237,46 +325,64 @@ __device__ void operator_vjp(const KArgs& a, const AdjBufs& b, int e, int p, boo
     }
   }
   if (!act) return;
-  MetricDeriv Dv;
-  load_deriv<CURVED>(a.bg_dg, a.E, nn, e, p, Dv);
-  MetricT<Dual> Md;
-  metric_cast(M, Md);
-  // gradient of  sum_d G_d.F^d(X) + V.S_ex(X) + W.S_stiff(X) + boundary terms
-  for (int k = 0; k < NV; ++k) {
-    Dual Xd[NV];
+  // gradient of  sum_d G_d.F^d(X) + V.S_ex(X) + W.S_stiff(X) + boundary terms: the
+  // parts linear in X transposed by hand, the current's part by dual numbers
+  double acc[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Xd[v] = Dual(X[v], v == k ? 1.0 : 0.0);
-    Dual tot(0.0);
-    if (use_v) {
-      Dual Jd[3], Je[3], J[3], F[NV], S[NV];
-      current(Xd, Md, a.eta, Jd, Je);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) J[c] = Jd[c] + Je[c];
-      for (int d = 0; d < 3; ++d) {
-        flux_any(d, Xd, J, Md, F);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) tot += G[d][v] * F[v];
-        if (bside[d]) {
-          Dual Ub[NV], Jb[3], Fb[NV];
-          boundary_state(d, (double)bside[d], Xd, Md, Ub);
-          current_total(Ub, Md, a.eta, Jb);
-          flux_any(d, Ub, Jb, Md, Fb);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) tot += Vp[v] * (bA[d] * Fb[v] + bI[d] * Ub[v]);
-        }
-      }
-      source_explicit<CURVED>(Xd, Md, Dv, Jd, S);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) tot += Vp[v] * S[v];
-    }
-    if (use_w) {
-      Dual S[NV];
-      source_stiff(Xd, Md, a.eta, a.kpsi, a.kphi, S);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) tot += Wst[v] * S[v];
-    }
-    ub[k] += tot.d;
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  if (use_v) {
+    MetricDeriv Dv;
+    load_deriv<CURVED>(a.bg_dg, a.E, nn, e, p, Dv);
+    flux_lin_vjp<0>(M, G[0], acc);
+    flux_lin_vjp<1>(M, G[1], acc);
+    flux_lin_vjp<2>(M, G[2], acc);
+    source_lin_vjp<CURVED>(M, Dv, Vp, acc);
   }
+  if (use_w) {
+    acc[6] += -M.alpha * a.kpsi * Wst[6];
+    acc[7] += -M.alpha * a.kphi * Wst[7];
+  }
+  {
+    // J~^d enters F^d_q with weight G_d[8]; S_ex,E = -J_drift; S_stiff,E = -J_driver
+    double wa[3], wb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      wa[i] = use_v ? G[i][8] - Vp[i] : 0.0;
+      wb[i] = (use_v ? G[i][8] : 0.0) - (use_w ? Wst[i] : 0.0);
+    }
+    current_vjp(X, M, a.eta, wa, wb, acc);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!bside[d]) continue;
+    // exterior state Y = B(X) (the no-incoming-Poynting state, linear in X on the
+    // branch the forward evaluation took): d/dX = P^T d/dY with P the branch's mask
+    double Y[NV], gY[NV], bv[NV];
+    boundary_state(d, (double)bside[d], X, M, Y);
+    double El[3], Bl[3];
+    lower3(M, X, El);
+    lower3(M, X + 3, Bl);
+    const int j1 = (d + 1) % 3, k1 = (d + 2) % 3;
+    const bool inward = (double)bside[d] * (El[j1] * Bl[k1] - El[k1] * Bl[j1]) < 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      bv[v] = bA[d] * Vp[v];
+      gY[v] = bI[d] * Vp[v];
+    }
+    if (d == 0) flux_lin_vjp<0>(M, bv, gY);
+    else if (d == 1) flux_lin_vjp<1>(M, bv, gY);
+    else flux_lin_vjp<2>(M, bv, gY);
+    double cj[3] = {0.0, 0.0, 0.0};
+    cj[d] = bv[8];
+    current_vjp(Y, M, a.eta, cj, cj, gY);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const bool keep = (v < 3) ? !inward : (v != 6 && v != 7);
+      if (keep) acc[v] += gY[v];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ub[v] += acc[v];
 }
 
 template <int N, bool CURVED, int STAGE>
