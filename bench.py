@@ -44,11 +44,13 @@ DG_BYTES_PER_NODE = {1: 216.0, 2: 360.0, 3: 288.0}
 # The curved background adds its 26 FP64 fields per node, read once per substep.
 DG_BG_BYTES_PER_NODE = 26 * 8.0
 
-# HBM bytes per launch of k_fd_flux (FP64) from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# runs scaled by a plain copy kernel's reading, valid for the kernel source whose
-# hash is FD_FLUX_TRAFFIC_SRC; reported as null for any other source.
-FD_FLUX_TRAFFIC = None
-FD_FLUX_TRAFFIC_SRC = ""
+# HBM bytes per FD element per launch of k_fd_flux (FP64): rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs (KiB per dispatch, 12 dispatches with 128 FD elements: fetch
+# 44316.7, write 39781.0), scaled by what the same counters read for a plain
+# 512 MiB device copy (fetch x 2.0, write x 1.0).  Valid for the kernel source
+# whose hash is FD_FLUX_TRAFFIC_SRC; reported as null for any other source.
+FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 44316.7 + 1.0 * 39781.0) * 1024.0 / 128.0
+FD_FLUX_TRAFFIC_SRC = "683fefc9ee09d748"
 
 
 def parse():
@@ -366,7 +368,7 @@ def main():
         print(f"# {name}: {args.steps} steps in {rec['secs']:.4f} s, {rec['n_dg']} DG / {rec['n_fd']} FD elements; "
               f"fd_flux {k_n} launches, mean {k_ms / max(k_n, 1) * 1e3:.2f} us", file=sys.stderr, flush=True)
 
-    def roofline_fd(rec):
+    def roofline_fd(rec, counted=True):
         k_ms, k_n = rec["kern"][fam_fd]
         n_fd = 0.5 * sum(rec["n_fd"])
         flop = n_fd * 3 * (m + 1) * m * m * FD_FLOP_PER_FACE
@@ -374,7 +376,8 @@ def main():
         ach = flop / avg / 1e12
         return {"kernel": "k_fd_flux (FD subcell WENO5-Z face fluxes)", "bound": "alu", "achieved": ach,
                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK_TFLOPS,
-                "traffic": FD_FLUX_TRAFFIC if kernel_source_hash() == FD_FLUX_TRAFFIC_SRC else None,
+                "traffic": (FD_FLUX_TRAFFIC_PER_FD_ELEMENT * n_fd
+                            if counted and kernel_source_hash() == FD_FLUX_TRAFFIC_SRC else None),
                 "mean_launch_us": avg * 1e6, "launches": int(k_n), "flop_per_launch": flop}
 
     def roofline_dg(rec):
@@ -413,7 +416,7 @@ def main():
                   "dtype": "f64 state, f32 fluxes and DG contractions",
                   "fd_elements": [int(x) for x in mix["n_fd"]],
                   "error_vs_fp64_run": state_diff(states["mixed"], states["fp64"]),
-                  "roofline": roofline_fd(mix), "roofline_dg": roofline_dg(mix)},
+                  "roofline": roofline_fd(mix, counted=False), "roofline_dg": roofline_dg(mix)},
         "cpu_baseline": cpu,
     }
     if args.extras == "all":
