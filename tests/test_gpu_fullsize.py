@@ -1,0 +1,142 @@
+"""GPU parity at the benchmark's full sizes.
+
+- Current sheet, 8^3 elements of P5, adaptive DG-FD (the benchmark workload, in
+  the launch configuration the benchmark times): two full steps against the
+  oracle, every element (group error <= 1e-12, identical representation flags).
+- Kerr-Schild black hole, 16^3 P5 elements with excision: the right-hand side of
+  the whole domain on the GPU, compared on sampled elements (DG and FD, next to
+  the excised hole, at the outer boundary and in the bulk) with the oracle's
+  right-hand side of those elements (1e-12 per component).
+- The 64-domain batch of mixed degree: one graph step of the whole batch,
+  compared member by member for the smallest members with the oracle's step of
+  that domain alone.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rhs as OR
+from oracle import step as OS
+from oracle.domain import DG, FD
+from oracle.domain import Domain as ODomain
+from paper_2404_01531_amd import inputs as I
+
+from helpers import curved_state, from_dev, group_err, make_pair, node_coords, oracle_params, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_sheet_full_size_two_steps():
+    torch = _torch()
+    w = I.workload("sheet")
+    odom, ldom, _ = make_pair(w, dict(eta=w["eta"], cfl=w["cfl"]))
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    u_fd = I.initial_data(w, xf, yf, zf)
+    st = OS.initial_state(odom, u_fd)
+    ldom.init_from_fd(to_dev(u_fd))
+    dt = ldom.dt()
+    _say(f"sheet 8^3: start-up with {int((st.rep == FD).sum())} FD elements")
+    for k in range(2):
+        st = OS.step(odom, st, dt)
+        ldom.step(1, dt)
+        gdg, gfd, grep = ldom.get_state()
+        assert np.array_equal(grep.cpu().numpy(), st.rep), f"representation differs after step {k + 1}"
+        for r, G, R in ((DG, from_dev(gdg, st.dg.shape), st.dg), (FD, from_dev(gfd, st.fd.shape), st.fd)):
+            el = np.nonzero(st.rep == r)[0]
+            e = group_err(G[:, el], R[:, el])
+            _say(f"  step {k + 1} rep {r} ({el.size} elements): group err {np.array2string(e, precision=2)}")
+            assert np.all(e <= 1e-12), (k, r, e.tolist())
+    torch.cuda.synchronize()
+
+
+def test_kerr_schild_full_size_rhs_sampled():
+    torch = _torch()
+    w = I.workload("kerr_schild")
+    with np.errstate(all="ignore"):
+        odom, ldom, _ = make_pair(w)
+    act = odom.active
+    rng = np.random.default_rng(61)
+    E = odom.E
+    rep = (rng.random(E) < 0.1).astype(np.int64)
+    rep[~act] = DG
+    with np.errstate(all="ignore"):
+        dg, fd = curved_state(odom, w, rng)
+    dg[:, ~act] = 0.0
+    fd[:, ~act] = 0.0
+    gdg, gfd = ldom.rhs(to_dev(dg), to_dev(fd), torch.from_numpy(rep.astype(np.int32)).cuda(), parts=3)
+    gdg = from_dev(gdg, dg.shape)
+    gfd = from_dev(gfd, fd.shape)
+    # samples: neighbours of the hole, outer-boundary elements, and random bulk elements
+    n = w["n_elem"][0]
+    coords = np.array([(e % n, (e // n) % n, e // (n * n)) for e in range(E)])
+    near_hole = [e for e in range(E) if act[e] and np.all(np.abs(coords[e] - (n / 2 - 0.5)) <= 1.5)]
+    outer = [e for e in range(E) if np.any(coords[e] == 0) or np.any(coords[e] == n - 1)]
+    bulk = list(rng.choice(np.nonzero(act)[0], 24, replace=False))
+    sample = sorted(set(near_hole + list(rng.choice(outer, 12, replace=False)) + bulk))
+    sample = np.array(sample, np.int64)
+    W_dg = OR.with_current(odom, dg, odom.geo_dg)
+    W_fd = OR.with_current(odom, fd, odom.geo_fd)
+    for r, G in ((DG, gdg), (FD, gfd)):
+        el = sample[rep[sample] == r]
+        if el.size == 0:
+            continue
+        if r == DG:
+            ref = OR.dg_rhs(odom, el, W_dg, W_fd, rep, 3)
+        else:
+            ref = OR.fd_rhs(odom, el, W_fd[:, el], W_dg, W_fd, rep, 3)
+        e = rel_err(G[:, el], ref)
+        _say(f"kerr-schild 16^3 rhs, rep {r}, {el.size} sampled elements: worst rel err {e.max():.2e}")
+        assert np.all(e <= 1e-12), (r, e.tolist())
+
+
+def test_batch_full_size_sampled_members():
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    ws = I.batch_workloads()
+    params = dict(eta=1e6, cfl=0.25)
+    b = grffe.Batch([dict(n_elem=w["n_elem"], lower=w["lower"], upper=w["upper"], degree=w["degree"],
+                          bc=w["bc"]) for w in ws], params=params)
+    assert b.size()[0] == 64
+    states = []
+    for k, w in enumerate(ws):
+        N = w["degree"]
+        E = int(np.prod(w["n_elem"]))
+        x, y, z = node_coords(w)
+        u = I.initial_data(w, x, y, z)
+        states.append(u)
+        b.set_state(k, to_dev(u), torch.zeros((9, E, (2 * N + 1) ** 3), dtype=torch.float64, device="cuda"),
+                    torch.zeros(E, dtype=torch.int32, device="cuda"))
+    b.step(1, use_graph=True)
+    sizes = [int(np.prod(w["n_elem"])) * (w["degree"] + 1) ** 3 for w in ws]
+    picks = list(np.argsort(sizes)[:3])
+    p = grffe.default_params(**params)
+    for k in picks:
+        w = ws[k]
+        odom = ODomain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], params=oracle_params(p))
+        fd0 = np.zeros((9, odom.E, odom.m, odom.m, odom.m))
+        st = OS.step(odom, OS.State(states[k], fd0, np.zeros(odom.E, np.int64)), odom.dt())
+        gdg, gfd, grep = b.get_state(k)
+        assert np.array_equal(grep.cpu().numpy(), st.rep), f"member {k}: representation differs"
+        for r, G, R in ((DG, from_dev(gdg, st.dg.shape), st.dg), (FD, from_dev(gfd, st.fd.shape), st.fd)):
+            el = np.nonzero(st.rep == r)[0]
+            if el.size == 0:
+                continue
+            e = group_err(G[:, el], R[:, el])
+            _say(f"batch member {k} ({w['kind']} {w['n_elem'][0]}^3 P{w['degree']}) rep {r}: "
+                 f"group err {np.array2string(e, precision=2)}")
+            assert np.all(e <= 1e-12), (k, r, e.tolist())
+    b.close()
+    torch.cuda.empty_cache()

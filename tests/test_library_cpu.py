@@ -48,3 +48,57 @@ def test_host_operators_match_oracle(N):
 def test_invalid_degree_is_rejected():
     with pytest.raises(grffe.GrffeError):
         grffe.operator(2, 0)
+
+
+def _grid(**over):
+    g = grffe.Grid()
+    vals = dict(n_elem=(2, 2, 2), lower=(-1.0,) * 3, upper=(1.0,) * 3, degree=5, bc=(0,) * 6)
+    vals.update(over)
+    grffe._fill_grid(g, vals["n_elem"], vals["lower"], vals["upper"], vals["degree"], vals["bc"], None)
+    return g
+
+
+@pytest.mark.parametrize("bad, code", [
+    (dict(degree=2), -1), (dict(degree=8), -1), (dict(n_elem=(0, 2, 2)), -1),
+    (dict(upper=(1.0, -1.0, 1.0)), -1), (dict(bc=(0, 1, 0, 0, 0, 0)), -1), (dict(bc=(0, 0, 7, 7, 0, 0)), -1),
+])
+def test_init_domain_rejects_bad_grids(bad, code):
+    """Validation happens before any device call, so it runs without a GPU."""
+    L = grffe.lib()
+    g = _grid(**bad)
+    p = grffe.default_params()
+    h = ctypes.c_void_p()
+    rc = L.grffe_init_domain(ctypes.byref(g), ctypes.byref(p), None, None, ctypes.byref(h))
+    assert rc == code and not h.value
+    assert L.grffe_last_error().decode()
+
+
+@pytest.mark.parametrize("over, code", [
+    (dict(precision=2), -5), (dict(hybrid=3), -1), (dict(fd_order=3), -1), (dict(tci_mode=0), -1),
+    (dict(cfl=0.0), -1), (dict(eta=-1.0), -1), (dict(tci_M=6), -1),
+])
+def test_init_domain_rejects_bad_params(over, code):
+    L = grffe.lib()
+    g = _grid()
+    p = grffe.default_params(**over)
+    h = ctypes.c_void_p()
+    assert L.grffe_init_domain(ctypes.byref(g), ctypes.byref(p), None, None, ctypes.byref(h)) == code
+
+
+def test_null_handles_are_rejected():
+    L = grffe.lib()
+    g = _grid()
+    p = grffe.default_params()
+    assert L.grffe_init_domain(ctypes.byref(g), ctypes.byref(p), None, None, None) == -1
+    assert L.grffe_step(None, 1, 0.0, None) == -1
+    assert L.grffe_rhs(None, None, None, None, None, None, 3, None) == -1
+    assert L.grffe_destroy(None) == 0
+    assert L.grffe_batch_destroy(None) == 0
+    h = ctypes.c_void_p()
+    arr = (grffe.Grid * 1)(g)
+    assert L.grffe_batch_create(arr, 0, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+    bad = (grffe.Grid * 1)(_grid(degree=9))
+    assert L.grffe_batch_create(bad, 1, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+    assert L.grffe_batch_step(None, 1, 1, None) == -1
+    d = ctypes.c_double()
+    assert L.grffe_batch_get_dt(None, 0, ctypes.byref(d)) == -1
