@@ -335,25 +335,31 @@ __device__ inline CellSrc cell_source(const KArgs& a, int e, int d, int c, int t
   return cs;
 }
 
+// Threads of an FD flux workgroup.
+constexpr int FLUX_TPB = 256;
+
 // One workgroup per (FD element, direction d, row t2 of pencils along d): the
 // m pencils of the row, with three ghost cells at each end, are staged in LDS
 // once; then every (component, face, pencil) is reconstructed, the cell-centred
 // fluxes of the corrector are formed once per cell, and finally every (face,
 // pencil) forms the Rusanov flux and the fourth-order corrected flux.  Only
-// J~^d enters F^d, so ten components (U and J~^d) are reconstructed.
+// J~^d enters F^d, so ten components (U and J~^d) are reconstructed.  LDS tiles are
+// [component][cell or face][pencil] with the pencil index fastest: the row length
+// m = 2N+1 is odd, so both the pencil-contiguous and the cell-contiguous thread
+// mappings touch 16 distinct bank pairs per 16 lanes (no bank conflicts).
 template <int N, bool CURVED, typename R>
-__global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
+__global__ __launch_bounds__(FLUX_TPB) void k_fd_flux(KArgs a) {
   using Dm = Dims<N>;
   constexpr int m = Dm::m, mm = Dm::mm;
   constexpr int nf = (m + 1) * m * m;
   constexpr int L = m;      // pencils per workgroup
   constexpr int C = m + 6;  // cells per pencil including ghosts
   constexpr int F = m + 1;  // faces per pencil
-  constexpr int FP = F + 1;  // padded (odd) LDS row length of face arrays
   constexpr int NR = NV + 1;  // reconstructed components: U and J~^d
-  __shared__ double sW[NR * L * C];
-  __shared__ double sLf[NR * L * FP];
-  __shared__ double sRf[NR * L * FP];
+  static_assert(L % 2 == 1, "odd pencil count keeps the LDS tiles free of bank conflicts");
+  __shared__ double sW[NR * C * L];   // [k][extended cell][pencil]
+  __shared__ double sLf[NR * F * L];  // [k][face][pencil]
+  __shared__ double sRf[NR * F * L];
   __shared__ double sM[CURVED ? NBGF * L * (m + 2) : 1];
   const int t = threadIdx.x;
   // work items: (listed FD element, direction, row of pencils)
@@ -363,7 +369,7 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   const int d = (item / m) % 3;
   const int t2 = item % m;
   // phase 1: stage cells -3 .. m+2 of every pencil (and the metric of cells -1 .. m)
-  for (int q = t; q < L * C; q += 256) {
+  for (int q = t; q < L * C; q += FLUX_TPB) {
     int c, t1;
     if (d == 0) {
       c = q % C;
@@ -391,10 +397,10 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
       W[NV] = (d == 0) ? J[0] : (d == 1 ? J[1] : J[2]);
     }
 #pragma unroll
-    for (int k = 0; k < NR; ++k) sW[(k * L + t1) * C + c] = W[k];
+    for (int k = 0; k < NR; ++k) sW[(k * C + c) * L + t1] = W[k];
     if (CURVED && c >= 2 && c <= m + 3) {
       const int cm = c - 2;
-      double* o = sM + t1 * (m + 2) + cm;
+      double* o = sM + cm * L + t1;  // [field][cell -1 .. m][pencil]
       o[0] = Mc.alpha;
       o[1 * L * (m + 2)] = Mc.beta[0];
       o[2 * L * (m + 2)] = Mc.beta[1];
@@ -408,41 +414,35 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   // cell-centred fluxes of cells -1 .. m used by the corrector
   const double eps = a.weno_eps;
   // target cells c = -1 .. m: left state of face c+1 and right state of face c
-  for (int q = t; q < NR * L * (m + 2); q += 256) {
-    const int c = q % (m + 2) - 1;
-    const int kt = q / (m + 2);  // k * L + t1
-    const double* v = sW + kt * C + c + 1;  // cells c-2 .. c+2 (extended index c+1 .. c+5)
+  for (int q = t; q < NR * L * (m + 2); q += FLUX_TPB) {
+    const int t1 = q % L;
+    const int c = (q / L) % (m + 2) - 1;
+    const int k = q / (L * (m + 2));
+    const double* v = sW + (k * C + c + 1) * L + t1;  // cells c-2 .. c+2 (extended index c+1 .. c+5)
     double vl[5];
 #pragma unroll
-    for (int z = 0; z < 5; ++z) vl[z] = v[z];
+    for (int z = 0; z < 5; ++z) vl[z] = v[z * L];
     double lft, rgt;
     weno5z_cell(vl, eps, lft, rgt);
-    if (c < m) sLf[kt * FP + c + 1] = lft;
-    if (c >= 0) sRf[kt * FP + c] = rgt;
+    if (c < m) sLf[(k * F + c + 1) * L + t1] = lft;
+    if (c >= 0) sRf[(k * F + c) * L + t1] = rgt;
   }
   __syncthreads();
   // phase 3a: cell-centred fluxes of cells -1 .. m of every pencil (the corrector's
   // F_i), each computed once; they replace the staged cells in LDS
-  static_assert(L * (m + 2) <= 256 && L * F <= 256, "one cell / one face per thread in phase 3");
+  static_assert(L * (m + 2) <= FLUX_TPB && L * F <= FLUX_TPB, "one cell / one face per thread in phase 3");
   constexpr int CF = m + 2;  // cells -1 .. m
   R Fcell[NV];
   const bool corr = a.fd_order == 4;
   if (corr && t < L * CF) {
-    int c, t1;
-    if (d == 0) {
-      c = t % CF;
-      t1 = t / CF;
-    } else {
-      t1 = t % L;
-      c = t / L;
-    }
+    const int t1 = t % L, c = t / L;
     R W[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) W[k] = (R)sW[(k * L + t1) * C + c + 2];
+    for (int k = 0; k < NR; ++k) W[k] = (R)sW[(k * C + c + 2) * L + t1];
     Metric Mc;
     if (CURVED) {
       double fm[10];
-      const double* o = sM + t1 * (m + 2) + c;
+      const double* o = sM + c * L + t1;
 #pragma unroll
       for (int k = 0; k < 10; ++k) fm[k] = o[k * L * (m + 2)];
       metric_from10(fm, Mc);
@@ -454,18 +454,11 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
     flux_any_jd(d, W, W[NV], Mcr, Fcell);
   }
   __syncthreads();
-  double* sFc = sW;  // [9][L][m+2], cell -1 at index 0
+  double* sFc = sW;  // [9][cell -1 .. m][pencil]
   if (corr && t < L * CF) {
-    int c, t1;
-    if (d == 0) {
-      c = t % CF;
-      t1 = t / CF;
-    } else {
-      t1 = t % L;
-      c = t / L;
-    }
+    const int t1 = t % L, c = t / L;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sFc[(v * L + t1) * CF + c] = (double)Fcell[v];
+    for (int v = 0; v < NV; ++v) sFc[(v * CF + c) * L + t1] = (double)Fcell[v];
   }
   __syncthreads();
   // phase 3b: fluxes at every face of every pencil
@@ -489,8 +482,8 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
     R WL[NR], WR[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      WL[k] = (R)sLf[(k * L + t13) * FP + f3];
-      WR[k] = (R)sRf[(k * L + t13) * FP + f3];
+      WL[k] = (R)sLf[(k * F + f3) * L + t13];
+      WR[k] = (R)sRf[(k * F + f3) * L + t13];
     }
     Metric Mf;
     load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nf, a.E, nf, e, tix, Mf);
@@ -506,8 +499,8 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
       // F* - (F_{f-1} - 2 F* + F_f) / 6 with the cell fluxes of cells f-1 and f
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double* fc = sFc + (v * L + t13) * CF + f3;
-        const R G = ((R)fc[0] - R(2) * Fr[v] + (R)fc[1]) * R(1.0 / 6.0);
+        const double* fc = sFc + (v * CF + f3) * L + t13;
+        const R G = ((R)fc[0] - R(2) * Fr[v] + (R)fc[L]) * R(1.0 / 6.0);
         Fr[v] = Fr[v] - G;
       }
     }
@@ -518,14 +511,14 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
   double* sFh = sLf;  // the reconstructed states are no longer needed
   if (q3 < L * F) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sFh[(v * L + t13) * FP + f3] = Fh[v];
+    for (int v = 0; v < NV; ++v) sFh[(v * F + f3) * L + t13] = Fh[v];
   }
   __syncthreads();
   // phase 4: flux difference of every cell of the row, -(2N+1)/h_d (Fhat_{i+1/2} - Fhat_{i-1/2})
   const double sc = (double)m / h_of(a, e, d);
   const int str[3] = {1, m, m * m};
   const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
-  for (int q = t; q < L * m; q += 256) {
+  for (int q = t; q < L * m; q += FLUX_TPB) {
     int c, t1;
     if (d == 0) {
       c = q % m;
@@ -538,8 +531,8 @@ __global__ __launch_bounds__(256) void k_fd_flux(KArgs a) {
     double* out = a.fhat + ((size_t)d * NV * a.E + e) * mm + cell;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double* fh = sFh + (v * L + t1) * FP + c;
-      out[(size_t)v * a.E * mm] = -sc * (fh[1] - fh[0]);
+      const double* fh = sFh + (v * F + c) * L + t1;
+      out[(size_t)v * a.E * mm] = -sc * (fh[L] - fh[0]);
     }
   }
   __syncthreads();  // the next item restages sW
@@ -943,7 +936,7 @@ void launch_project_troubled(const KArgs& a, int N, bool curved, int mode, hipSt
 template <int N, bool CURVED>
 static void fd_flux_t(const KArgs& a, hipStream_t s) {
   constexpr int m = Dims<N>::m;
-  const dim3 grid = list_grid((size_t)a.E * 3 * m, 2048), block(256);
+  const dim3 grid = list_grid((size_t)a.E * 3 * m, 2048), block(FLUX_TPB);
   if (a.precision == GRFFE_PRECISION_MIXED) launch_kernel(k_fd_flux<N, CURVED, float>, grid, block, s, a);
   else launch_kernel(k_fd_flux<N, CURVED, double>, grid, block, s, a);
 }
