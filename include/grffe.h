@@ -184,16 +184,18 @@ int grffe_operator(int degree, int which, double* out, int capacity);
 int grffe_timing_enable(grffe_domain* dom, int mask);
 int grffe_timing_read(grffe_domain* dom, int family, double* total_ms, int64_t* launches);
 
-/* Adjoint of the right-hand side (a vector-Jacobian product) for a state whose
- * live elements are all on DG:  ubar += (d RHS_parts / d dg)^T lam, where
- * RHS_parts is the semi-discrete right-hand side of grffe_rhs restricted to
- * `parts` (fluxes, derivative and lift with the Rusanov faces and the
- * no-incoming-Poynting boundary state, non-stiff and stiff sources of Sec. II and
- * III A).  dg, lam, ubar: device [9][E][n^3]; rep: device int32 [E], read on the
- * host (the call synchronises the stream).  EUNSUPPORTED if a live element is on
- * FD, in mixed precision or with the clamp on (no derivative is defined there). */
-int grffe_rhs_adjoint(grffe_domain* dom, const double* dg, const int32_t* rep, const double* lam, double* ubar,
-                      int parts, void* stream);
+/* Adjoint of the right-hand side (a vector-Jacobian product), with the
+ * representation frozen:  ubar += (d RHS_parts / d u)^T lam, where RHS_parts is
+ * the semi-discrete right-hand side of grffe_rhs restricted to `parts` (fluxes,
+ * DG derivative and lift or FD WENO5-Z reconstruction, Rusanov faces and the
+ * corrector, the no-incoming-Poynting boundary state, non-stiff and stiff sources
+ * of Sec. II and III).  States whose live elements are all on DG (dg, lam_dg,
+ * ubar_dg used) or all on FD (fd, lam_fd, ubar_fd used) are supported; layouts as
+ * grffe_rhs, all device pointers non-NULL.  rep is read on the host (the call
+ * synchronises the stream).  EUNSUPPORTED for states with elements on both, in
+ * mixed precision or with the clamp on. */
+int grffe_rhs_adjoint(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep, const double* lam_dg,
+                      const double* lam_fd, double* ubar_dg, double* ubar_fd, int parts, void* stream);
 
 /* Adjoint of one IMEX-SSP3(4,3,3) step (Sec. III B) taken with every element on
  * DG and no switching (the hybrid decisions frozen to DG):

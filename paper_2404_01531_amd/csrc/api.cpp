@@ -563,12 +563,19 @@ extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream)
 }
 
 // Representation check of the adjoint entry points: every live element on DG.
-static int require_all_dg(grffe_domain* d, const int32_t* rep, hipStream_t st) {
+// Representation of the live elements of `rep` (device): 0 all DG, 1 all FD,
+// 2 both (read on the host; synchronises the stream).
+static int rep_kind(grffe_domain* d, const int32_t* rep, hipStream_t st, int* kind) {
   std::vector<int32_t> h(d->E);
   HIPCHK(hipMemcpyAsync(h.data(), rep, sizeof(int32_t) * d->E, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  for (int e = 0; e < d->E; ++e)
-    if (d->live_h[e] && h[e] != 0) return fail(GRFFE_EUNSUPPORTED, "the adjoint is built for all-DG states only");
+  bool dg = false, fd = false;
+  for (int e = 0; e < d->E; ++e) {
+    if (!d->live_h[e]) continue;
+    if (h[e]) fd = true;
+    else dg = true;
+  }
+  *kind = (dg && fd) ? 2 : (fd ? 1 : 0);
   return GRFFE_OK;
 }
 
@@ -578,17 +585,46 @@ static int adjoint_supported(grffe_domain* d) {
   return GRFFE_OK;
 }
 
-extern "C" int grffe_rhs_adjoint(grffe_domain* d, const double* dg, const int32_t* rep, const double* lam,
-                                 double* ubar, int parts, void* stream) {
+// Work space of the FD adjoint: per-direction adjoints of the transported cell
+// values [3][10][E][m^3] and ghost-cell adjoints [10][E][6][3][m^2].
+static int fd_adjoint_space(grffe_domain* d) {
+  if (d->adj_fd_wbar) return GRFFE_OK;
+  void* p1 = nullptr;
+  void* p2 = nullptr;
+  if (int rc = dalloc(d, &p1, sizeof(double) * 3 * (NV + 1) * (size_t)d->E * d->mm)) return rc;
+  if (int rc = dalloc(d, &p2, sizeof(double) * (NV + 1) * (size_t)d->E * 6 * 3 * d->m * d->m)) return rc;
+  d->adj_fd_wbar = reinterpret_cast<double*>(p1);
+  d->adj_fd_gbar = reinterpret_cast<double*>(p2);
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_rhs_adjoint(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep,
+                                 const double* lam_dg, const double* lam_fd, double* ubar_dg, double* ubar_fd,
+                                 int parts, void* stream) {
   if (int rc = check_dom(d)) return rc;
-  if (!dg || !rep || !lam || !ubar) return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
+  if (!dg || !fd || !rep || !lam_dg || !lam_fd || !ubar_dg || !ubar_fd)
+    return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
   if (parts < 1 || parts > 3) return fail(GRFFE_EINVAL, "parts must be 1, 2 or 3");
   if (int rc = adjoint_supported(d)) return rc;
   hipStream_t st = S(stream);
-  if (int rc = require_all_dg(d, rep, st)) return rc;
+  int kind = 0;
+  if (int rc = rep_kind(d, rep, st, &kind)) return rc;
+  if (kind == 2) return fail(GRFFE_EUNSUPPORTED, "the adjoint is built for states with every element on DG or every "
+                                                 "element on FD");
   KArgs a = make_args(d);
-  a.dg.Un = const_cast<double*>(dg);
-  launch_rhs_adjoint(a, d->N, d->curved, lam, ubar, parts, st);
+  if (kind == 0) {
+    a.dg.Un = const_cast<double*>(dg);
+    launch_rhs_adjoint(a, d->N, d->curved, lam_dg, ubar_dg, parts, st);
+  } else {
+    if (int rc = fd_adjoint_space(d)) return rc;
+    a.fd.Un = const_cast<double*>(fd);
+    a.rep0 = const_cast<int32_t*>(rep);
+    a.sub = 3;
+    HIPCHK(hipMemsetAsync(d->fd_count + 3, 0, sizeof(int32_t), st));
+    launch_begin_substep(a, false, st);
+    launch_fd_stage(a, d->N, d->curved, MODE_RHS, st);  // transported values (U, J~) of the state
+    launch_fd_rhs_adjoint(a, d->N, d->curved, lam_fd, ubar_fd, parts, d->adj_fd_wbar, d->adj_fd_gbar, st);
+  }
   HIPCHK(hipGetLastError());
   return GRFFE_OK;
 }

@@ -137,6 +137,8 @@ struct grffe_domain {
   int32_t* fd_count = nullptr;  // [4] list lengths (three substeps, right-hand side)
   double* adj_ws = nullptr;  // step adjoint: 6 DG-sized arrays, allocated at first use
   double* adj_u0 = nullptr;  // step adjoint: copy of U^n
+  double* adj_fd_wbar = nullptr;  // FD adjoint: [3][10][E][m^3]
+  double* adj_fd_gbar = nullptr;  // FD adjoint: [10][E][6][3][m^2]
   double dt_cfl = 0.0;
   double lambda_max = 0.0;
   std::vector<void*> allocs;
@@ -182,5 +184,8 @@ void launch_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, d
                         hipStream_t s);
 void launch_step_adjoint(const KArgs& a, int N, bool curved, const double* mu, double* lam, double* ws,
                          hipStream_t s);
+// launchers (kernels_fd_adj.hip)
+void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar, int parts,
+                           double* wbar, double* gbar, hipStream_t s);
 
 }  // namespace grffe

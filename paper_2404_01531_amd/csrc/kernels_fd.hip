@@ -12,6 +12,7 @@
 // P-projection of a DG neighbour (slab buffer), or from the no-incoming-Poynting
 // state of the outermost own cell (Sec. III D).
 #include "common.h"
+#include "fd_common.h"
 
 namespace grffe {
 
@@ -286,53 +287,6 @@ __device__ inline void weno5z_cell(const double* v, double eps, double& left, do
     const double q2 = (3.0 * v[2] + 6.0 * v[1] - v[0]) * 0.125;
     right = (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
   }
-}
-
-// Where the (U, J~) of cell c (-3 <= c <= m+2 along d) of element e lives.
-struct CellSrc {
-  const double* ptr;  // component 0; null for the computed boundary state
-  size_t stride;      // between components
-  int elem, cell;     // element / cell index used for the cell metric
-};
-
-template <int N>
-__device__ inline CellSrc cell_source(const KArgs& a, int e, int d, int c, int t1, int t2) {
-  using Dm = Dims<N>;
-  constexpr int m = Dm::m, mm = Dm::mm;
-  const int str[3] = {1, m, m * m};
-  const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
-  CellSrc cs;
-  if (c >= 0 && c < m) {
-    cs.cell = c * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
-    cs.elem = e;
-    cs.ptr = a.w_fd + (size_t)e * mm + cs.cell;
-    cs.stride = (size_t)a.E * mm;
-    return cs;
-  }
-  const int s = (c >= m) ? 1 : 0;
-  const int o = a.nbr[e * 6 + 2 * d + s];
-  if (o < 0) {
-    const int cb = s ? m - 1 : 0;
-    cs.cell = cb * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
-    cs.elem = e;
-    cs.ptr = nullptr;
-    cs.stride = 0;
-    return cs;
-  }
-  const int cn = s ? c - m : c + m;  // cell index inside the neighbour
-  cs.cell = cn * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
-  cs.elem = o;
-  if (a.rep0[o] == 1) {
-    cs.ptr = a.w_fd + (size_t)o * mm + cs.cell;
-    cs.stride = (size_t)a.E * mm;
-  } else {
-    // DG neighbour: its slab on the face facing us, layer = distance from the face
-    const int fo = 2 * d + (1 - s);
-    const int l = s ? (c - m) : (-1 - c);
-    cs.ptr = a.slab + ((size_t)o * 6 + fo) * (3 * m * m) + l * m * m + t1 + m * t2;
-    cs.stride = (size_t)a.E * 6 * 3 * m * m;
-  }
-  return cs;
 }
 
 // Threads of an FD flux workgroup.

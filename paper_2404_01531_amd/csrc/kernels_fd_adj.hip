@@ -1,0 +1,437 @@
+// Adjoint of the FD subcell right-hand side (Sec. III C 2) for states whose live
+// elements are all on FD.
+//
+// Along each pencil of direction d the right-hand side of cell c is
+//   L_c = -(m/h) (Fhat_{c+1/2} - Fhat_{c-1/2}) + S(U_c),
+//   Fhat = (4/3) F* - (F_{c-1} + F_c) / 6    (fourth-order corrector; Fhat = F* for FD2),
+//   F* = (F(W_L) + F(W_R)) / 2 - lambda (U_R - U_L) / 2,
+// with W_L, W_R the WENO5-Z reconstructions of the ten transported components
+// (U and J~^d) and F_c the flux of the cell values.  Every flux is linear in the
+// transported components, so the transposes are the hand-written linear ones;
+// the reconstruction is differentiated in reverse mode (weno5z_cell_vjp).  The
+// adjoint of the transported J~^d is carried back to U through the current's
+// gradient at the cell.  Each element computes its own faces, so the face fluxes
+// of cells next to a face carry adjoints into the neighbour's cells (ghost
+// cells): they are written per face and layer and gathered by the element that
+// owns the cells, so no atomics are needed and the result is deterministic.
+#include "adjoint.h"
+#include "fd_common.h"
+
+namespace grffe {
+
+// Reverse-mode derivative of weno5z_cell (same formulas, same order): given the
+// adjoints gL of `left` and gR of `right`, vb[z] = gL dleft/dv_z + gR dright/dv_z.
+// tau5^2 = (beta_0 - beta_2)^2 is smooth, so no branch is differentiated.
+__device__ inline void weno5z_cell_vjp(const double* v, double eps, double gL, double gR, double* vb) {
+  const double c13 = 13.0 / 12.0;
+  const double d0 = v[0] - 2.0 * v[1] + v[2], e0 = v[0] - 4.0 * v[1] + 3.0 * v[2];
+  const double d1 = v[1] - 2.0 * v[2] + v[3], e1 = v[1] - v[3];
+  const double d2 = v[2] - 2.0 * v[3] + v[4], e2 = 3.0 * v[2] - 4.0 * v[3] + v[4];
+  const double b0 = c13 * d0 * d0 + 0.25 * e0 * e0 + eps;
+  const double b1 = c13 * d1 * d1 + 0.25 * e1 * e1 + eps;
+  const double b2 = c13 * d2 * d2 + 0.25 * e2 * e2 + eps;
+  const double td = b0 - b2;
+  const double t2 = td * td;
+  const double s0 = b0 * b0, s1 = b1 * b1, s2 = b2 * b2;
+  const double p01 = s0 * s1, p02 = s0 * s2, p12 = s1 * s2;
+  const double a0 = s0 + t2, a1 = s1 + t2, a2 = s2 + t2;
+  const double wl0 = (1.0 / 16.0) * a0 * p12, wl1 = (10.0 / 16.0) * a1 * p02, wl2 = (5.0 / 16.0) * a2 * p01;
+  const double ql0 = (3.0 * v[0] - 10.0 * v[1] + 15.0 * v[2]) * 0.125;
+  const double ql1 = (-v[1] + 6.0 * v[2] + 3.0 * v[3]) * 0.125;
+  const double ql2 = (3.0 * v[2] + 6.0 * v[3] - v[4]) * 0.125;
+  const double DL = wl0 + wl1 + wl2;
+  const double left = (wl0 * ql0 + wl1 * ql1 + wl2 * ql2) / DL;
+  const double wr0 = (1.0 / 16.0) * a2 * p01, wr1 = (10.0 / 16.0) * a1 * p02, wr2 = (5.0 / 16.0) * a0 * p12;
+  const double qr0 = (3.0 * v[4] - 10.0 * v[3] + 15.0 * v[2]) * 0.125;
+  const double qr1 = (-v[3] + 6.0 * v[2] + 3.0 * v[1]) * 0.125;
+  const double qr2 = (3.0 * v[2] + 6.0 * v[1] - v[0]) * 0.125;
+  const double DR = wr0 + wr1 + wr2;
+  const double right = (wr0 * qr0 + wr1 * qr1 + wr2 * qr2) / DR;
+  // normalised sums: d(N/D)/dw_k = (q_k - N/D)/D, d(N/D)/dq_k = w_k/D
+  const double iL = gL / DL, iR = gR / DR;
+  const double bql0 = iL * wl0, bql1 = iL * wl1, bql2 = iL * wl2;
+  const double bqr0 = iR * wr0, bqr1 = iR * wr1, bqr2 = iR * wr2;
+  // weights: a0 p12 enters wl0 (1/16) and wr2 (5/16); a1 p02 enters wl1, wr1 (10/16);
+  // a2 p01 enters wl2 (5/16) and wr0 (1/16)
+  const double k0 = (1.0 / 16.0) * iL * (ql0 - left) + (5.0 / 16.0) * iR * (qr2 - right);
+  const double k1 = (10.0 / 16.0) * (iL * (ql1 - left) + iR * (qr1 - right));
+  const double k2 = (5.0 / 16.0) * iL * (ql2 - left) + (1.0 / 16.0) * iR * (qr0 - right);
+  const double bp12 = k0 * a0, bp02 = k1 * a1, bp01 = k2 * a2;
+  const double ba0 = k0 * p12, ba1 = k1 * p02, ba2 = k2 * p01;
+  const double bt2 = ba0 + ba1 + ba2;
+  const double bs0 = ba0 + bp01 * s1 + bp02 * s2;
+  const double bs1 = ba1 + bp01 * s0 + bp12 * s2;
+  const double bs2 = ba2 + bp02 * s0 + bp12 * s1;
+  const double bb0 = 2.0 * b0 * bs0 + 2.0 * td * bt2;
+  const double bb1 = 2.0 * b1 * bs1;
+  const double bb2 = 2.0 * b2 * bs2 - 2.0 * td * bt2;
+  const double bd0 = 2.0 * c13 * d0 * bb0, be0 = 0.5 * e0 * bb0;
+  const double bd1 = 2.0 * c13 * d1 * bb1, be1 = 0.5 * e1 * bb1;
+  const double bd2 = 2.0 * c13 * d2 * bb2, be2 = 0.5 * e2 * bb2;
+  vb[0] = bd0 + be0 + 0.125 * (3.0 * bql0 - bqr2);
+  vb[1] = -2.0 * bd0 - 4.0 * be0 + bd1 + be1 + 0.125 * (-10.0 * bql0 - bql1 + 3.0 * bqr1 + 6.0 * bqr2);
+  vb[2] = bd0 + 3.0 * be0 - 2.0 * bd1 + bd2 + 3.0 * be2 +
+          0.125 * (15.0 * bql0 + 6.0 * bql1 + 3.0 * bql2 + 15.0 * bqr0 + 6.0 * bqr1 + 3.0 * bqr2);
+  vb[3] = bd1 - be1 - 2.0 * bd2 - 4.0 * be2 + 0.125 * (3.0 * bql1 + 6.0 * bql2 - 10.0 * bqr0 - bqr1);
+  vb[4] = bd2 + be2 + 0.125 * (-bql2 + 3.0 * bqr0);
+}
+
+// out += d(G . F^d_lin)/dW for a run-time direction.
+__device__ inline void flux_lin_vjp_d(int d, const Metric& M, const double* G, double* out) {
+  if (d == 0) flux_lin_vjp<0>(M, G, out);
+  else if (d == 1) flux_lin_vjp<1>(M, G, out);
+  else flux_lin_vjp<2>(M, G, out);
+}
+
+struct FdAdj {
+  const double* lam;  // [9][E][m^3] adjoint input (lambda)
+  double* ubar;       // [9][E][m^3] output (accumulated)
+  double* wbar;       // [3][10][E][m^3] per-direction adjoints of the transported cell values
+  double* gbar;       // [10][E][6][3][m^2] adjoints of ghost cells, per face and layer
+  int parts;
+};
+
+// One workgroup per (listed FD element, direction, row of pencils), as the forward
+// flux kernel: adjoints of the transported components (U, J~^d) of the row's cells
+// and of its ghost cells.
+template <int N, bool CURVED>
+__global__ __launch_bounds__(256) void k_fd_adj_flux(KArgs a, FdAdj b) {
+  using Dm = Dims<N>;
+  constexpr int m = Dm::m, mm = Dm::mm;
+  constexpr int nf = (m + 1) * m * m;
+  constexpr int L = m, C = m + 6, F = m + 1, CF = m + 2, NR = NV + 1;
+  constexpr int TPB = 256;
+  __shared__ double sW[NR * C * L];   // staged cells [k][ext cell][pencil]
+  __shared__ double sWb[NR * C * L];  // their adjoints
+  __shared__ double sLb[NR * F * L];  // adjoints of the left states [k][face][pencil]
+  __shared__ double sRb[NR * F * L];  // adjoints of the right states
+  __shared__ double sG[NV * F * L];   // adjoints of the face fluxes
+  __shared__ double sM[CURVED ? NBGF * CF * L : 1];
+  const int t = threadIdx.x;
+  const int items = a.fd_count[a.sub] * 3 * m;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int e = a.fd_list[item / (3 * m)];
+    const int d = (item / m) % 3;
+    const int t2 = item % m;
+    const int str[3] = {1, m, m * m};
+    const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+    // stage the cells -3 .. m+2 (as the forward kernel) and clear their adjoints
+    for (int q = t; q < L * C; q += TPB) {
+      int c, t1;
+      if (d == 0) {
+        c = q % C;
+        t1 = q / C;
+      } else {
+        t1 = q % L;
+        c = q / L;
+      }
+      const CellSrc cs = cell_source<N>(a, e, d, c - 3, t1, t2);
+      double W[NR];
+      Metric Mc;
+      if (cs.ptr) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) W[k] = cs.ptr[k * cs.stride];
+        W[NV] = cs.ptr[(NV + d) * cs.stride];
+        if (CURVED && c >= 2 && c <= m + 3) load_metric<CURVED>(a.bg_fd, a.E, mm, cs.elem, cs.cell, Mc);
+      } else {
+        double Ui[NV], Ub[NV], J[3];
+        load_metric<CURVED>(a.bg_fd, a.E, mm, e, cs.cell, Mc);
+        load9(a.w_fd, a.E, mm, e, cs.cell, Ui);
+        boundary_state(d, (c >= m + 3) ? 1.0 : -1.0, Ui, Mc, Ub);
+        current_total(Ub, Mc, a.eta, J);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) W[k] = Ub[k];
+        W[NV] = (d == 0) ? J[0] : (d == 1 ? J[1] : J[2]);
+      }
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        sW[(k * C + c) * L + t1] = W[k];
+        sWb[(k * C + c) * L + t1] = 0.0;
+      }
+      if (CURVED && c >= 2 && c <= m + 3) {
+        double* o = sM + (c - 2) * L + t1;
+        o[0] = Mc.alpha;
+        o[1 * CF * L] = Mc.beta[0];
+        o[2 * CF * L] = Mc.beta[1];
+        o[3 * CF * L] = Mc.beta[2];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o[(4 + k) * CF * L] = Mc.g[k];
+      }
+    }
+    // adjoints of the face fluxes: L_c = -(m/h)(Fhat_{c+1/2} - Fhat_{c-1/2}) gives
+    // Fhat_f the adjoint (m/h)(lambda_f - lambda_{f-1}) (cells of this element only)
+    const double sc = (double)m / h_of(a, e, d);
+    for (int q = t; q < F * L; q += TPB) {
+      const int t1 = q % L, f = q / L;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const size_t base = ((size_t)v * a.E + e) * mm + t1 * str[t1ax] + t2 * str[t2ax];
+        const double lr = (f < m) ? b.lam[base + (size_t)f * str[d]] : 0.0;
+        const double ll = (f > 0) ? b.lam[base + (size_t)(f - 1) * str[d]] : 0.0;
+        sG[(v * F + f) * L + t1] = sc * (lr - ll);
+      }
+    }
+    __syncthreads();
+    const bool corr = a.fd_order == 4;
+    const double cs_ = corr ? 4.0 / 3.0 : 1.0;
+    // adjoints of the reconstructed states at every face (Rusanov, linear fluxes)
+    for (int q = t; q < F * L; q += TPB) {
+      const int t1 = q % L, f = q / L;
+      int tix;
+      if (d == 0) tix = f + (m + 1) * (t1 + m * t2);
+      else if (d == 1) tix = t1 + m * (f + (m + 1) * t2);
+      else tix = t1 + m * (t2 + m * f);
+      Metric Mf;
+      load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nf, a.E, nf, e, tix, Mf);
+      const double lam = CURVED ? char_speed(d, Mf) : 1.0;
+      double Gh[NV], bl[NR], br[NR];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Gh[v] = 0.5 * cs_ * sG[(v * F + f) * L + t1];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) bl[k] = 0.0;
+      flux_lin_vjp_d(d, Mf, Gh, bl);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) br[k] = bl[k];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        bl[v] += lam * Gh[v];
+        br[v] -= lam * Gh[v];
+      }
+      bl[NV] += Gh[8];  // the q~ flux carries J~^d
+      br[NV] += Gh[8];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        sLb[(k * F + f) * L + t1] = bl[k];
+        sRb[(k * F + f) * L + t1] = br[k];
+      }
+    }
+    // adjoints of the corrector's cell fluxes F_c = F(w_c), cells -1 .. m
+    if (corr) {
+      for (int q = t; q < CF * L; q += TPB) {
+        const int t1 = q % L, c = q / L - 1;
+        Metric Mc;
+        if (CURVED) {
+          double fm[10];
+          const double* o = sM + (c + 1) * L + t1;
+#pragma unroll
+          for (int k = 0; k < 10; ++k) fm[k] = o[k * CF * L];
+          metric_from10(fm, Mc);
+        } else {
+          metric_flat(Mc);
+        }
+        double Gc[NV], wb[NR];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double gf0 = (c >= 0) ? sG[(v * F + c) * L + t1] : 0.0;
+          const double gf1 = (c + 1 <= m) ? sG[(v * F + c + 1) * L + t1] : 0.0;
+          Gc[v] = -(gf0 + gf1) / 6.0;
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) wb[k] = 0.0;
+        flux_lin_vjp_d(d, Mc, Gc, wb);
+        wb[NV] += Gc[8];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) sWb[(k * C + c + 3) * L + t1] = wb[k];
+      }
+    }
+    __syncthreads();
+    // reconstruction: target cell c gives the left state of face c+1 and the right
+    // state of face c from cells c-2 .. c+2; the five contributions of a target go to
+    // five different cells, added one offset at a time (no two targets collide)
+    const double eps = a.weno_eps;
+    constexpr int NT = NR * CF * L;
+    for (int base = 0; base < NT; base += TPB) {
+      const int q = base + t;
+      const bool ok = q < NT;
+      int t1 = 0, c = 0, k = 0;
+      double vb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      if (ok) {
+        t1 = q % L;
+        c = (q / L) % CF - 1;
+        k = q / (CF * L);
+        double vl[5];
+#pragma unroll
+        for (int z = 0; z < 5; ++z) vl[z] = sW[(k * C + c + 1 + z) * L + t1];
+        const double gL = (c < m) ? sLb[(k * F + c + 1) * L + t1] : 0.0;
+        const double gR = (c >= 0) ? sRb[(k * F + c) * L + t1] : 0.0;
+        weno5z_cell_vjp(vl, eps, gL, gR, vb);
+      }
+#pragma unroll
+      for (int z = 0; z < 5; ++z) {
+        __syncthreads();
+        if (ok) sWb[(k * C + c + 1 + z) * L + t1] += vb[z];
+      }
+    }
+    __syncthreads();
+    // own cells -> per-direction adjoints; ghost cells -> per face and layer
+    for (int q = t; q < C * L; q += TPB) {
+      int x, t1;
+      if (d == 0) {
+        x = q % C;
+        t1 = q / C;
+      } else {
+        t1 = q % L;
+        x = q / L;
+      }
+      const int c = x - 3;
+      if (c >= 0 && c < m) {
+        const int cell = c * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          b.wbar[(((size_t)d * NR + k) * a.E + e) * mm + cell] = sWb[(k * C + x) * L + t1];
+      } else {
+        const int s = (c >= m) ? 1 : 0;
+        const int l = s ? (c - m) : (-1 - c);
+        const int f = 2 * d + s;
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          b.gbar[((((size_t)k * a.E + e) * 6 + f) * 3 + l) * (m * m) + t1 + m * t2] = sWb[(k * C + x) * L + t1];
+      }
+    }
+    __syncthreads();  // the next item restages the tiles
+  }
+}
+
+// Per FD cell: the adjoint with respect to U of the cell, from the three directions'
+// transported-component adjoints, the ghost adjoints the neighbours wrote for this
+// cell (or, at a physical boundary, this element's own ghosts through the
+// no-incoming-Poynting state), the current's gradient and the sources.
+template <int N, bool CURVED>
+__global__ __launch_bounds__(256) void k_fd_adj_gather(KArgs a, FdAdj b) {
+  using Dm = Dims<N>;
+  constexpr int m = Dm::m, mm = Dm::mm;
+  constexpr int NR = NV + 1;
+  constexpr int BPE = (mm + 255) / 256;
+  const int items = a.fd_count[a.sub] * BPE;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int e = a.fd_list[item / BPE];
+    const int p = (item % BPE) * 256 + threadIdx.x;
+    if (p >= mm) continue;
+    const int ci[3] = {p % m, (p / m) % m, p / (m * m)};
+    Metric M;
+    load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
+    double U[NV], lam[NV], ub[NV];
+    load9(a.fd.Un, a.E, mm, e, p, U);
+    load9(b.lam, a.E, mm, e, p, lam);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] = 0.0;
+    double wJ[3] = {0.0, 0.0, 0.0};
+    if (b.parts & 1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ub[v] += b.wbar[(((size_t)d * NR + v) * a.E + e) * mm + p];
+        wJ[d] += b.wbar[(((size_t)d * NR + NV) * a.E + e) * mm + p];
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+        const int tt = ci[t1ax] + m * ci[t2ax];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int l = s ? (m - 1 - ci[d]) : ci[d];
+          if (l > 2) continue;
+          const int f = 2 * d + s;
+          const int o = a.nbr[e * 6 + f];
+          if (o >= 0) {
+            // the neighbour's ghost layer l on its face towards us is this cell
+            const int fo = f ^ 1;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+              const double g = b.gbar[((((size_t)k * a.E + o) * 6 + fo) * 3 + l) * (m * m) + tt];
+              if (k < NV) ub[k] += g;
+              else wJ[d] += g;
+            }
+          } else if (l == 0) {
+            // own ghosts: the no-incoming-Poynting state of this cell in all three layers
+            double G10[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+              G10[k] = 0.0;
+#pragma unroll
+              for (int ll = 0; ll < 3; ++ll)
+                G10[k] += b.gbar[((((size_t)k * a.E + e) * 6 + f) * 3 + ll) * (m * m) + tt];
+            }
+            double Y[NV], gY[NV];
+            const double side = s ? 1.0 : -1.0;
+            boundary_state(d, side, U, M, Y);
+            double El[3], Bl[3];
+            lower3(M, U, El);
+            lower3(M, U + 3, Bl);
+            const int j1 = (d + 1) % 3, k1 = (d + 2) % 3;
+            const bool inward = side * (El[j1] * Bl[k1] - El[k1] * Bl[j1]) < 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) gY[v] = G10[v];
+            double cj[3] = {0.0, 0.0, 0.0};
+            cj[d] = G10[NV];
+            current_vjp(Y, M, a.eta, cj, cj, gY);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const bool keep = (v < 3) ? !inward : (v != 6 && v != 7);
+              if (keep) ub[v] += gY[v];
+            }
+          }
+        }
+      }
+    }
+    // the transported current J~^d of the cell, the explicit and the stiff sources
+    double wa[3], wb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      wa[i] = wJ[i] - ((b.parts & 1) ? lam[i] : 0.0);
+      wb[i] = wJ[i] - ((b.parts & 2) ? lam[i] : 0.0);
+    }
+    current_vjp(U, M, a.eta, wa, wb, ub);
+    if (b.parts & 1) {
+      MetricDeriv Dv;
+      load_deriv<CURVED>(a.bg_fd, a.E, mm, e, p, Dv);
+      source_lin_vjp<CURVED>(M, Dv, lam, ub);
+    }
+    if (b.parts & 2) {
+      ub[6] += -M.alpha * a.kpsi * lam[6];
+      ub[7] += -M.alpha * a.kphi * lam[7];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) b.ubar[((size_t)v * a.E + e) * mm + p] += ub[v];
+  }
+}
+
+template <int N, bool CURVED>
+static void fd_rhs_adjoint_t(const KArgs& a, const FdAdj& b, hipStream_t s) {
+  constexpr int m = Dims<N>::m, mm = Dims<N>::mm;
+  const size_t flux_items = (size_t)a.E * 3 * m, cell_items = (size_t)a.E * ((mm + 255) / 256);
+  if (b.parts & 1)
+    launch_kernel(k_fd_adj_flux<N, CURVED>, dim3((unsigned)(flux_items < 2048 ? flux_items : 2048)), dim3(256), s,
+                  a, b);
+  launch_kernel(k_fd_adj_gather<N, CURVED>, dim3((unsigned)(cell_items < 2048 ? cell_items : 2048)), dim3(256), s,
+                a, b);
+}
+
+void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar, int parts,
+                           double* wbar, double* gbar, hipStream_t s) {
+  FdAdj b{};
+  b.lam = lam;
+  b.ubar = ubar;
+  b.wbar = wbar;
+  b.gbar = gbar;
+  b.parts = parts;
+  if (curved) {
+    switch (N) {
+      case 3: fd_rhs_adjoint_t<3, true>(a, b, s); break;
+      case 4: fd_rhs_adjoint_t<4, true>(a, b, s); break;
+      case 5: fd_rhs_adjoint_t<5, true>(a, b, s); break;
+      case 6: fd_rhs_adjoint_t<6, true>(a, b, s); break;
+      default: fd_rhs_adjoint_t<7, true>(a, b, s); break;
+    }
+  } else {
+    switch (N) {
+      case 3: fd_rhs_adjoint_t<3, false>(a, b, s); break;
+      case 4: fd_rhs_adjoint_t<4, false>(a, b, s); break;
+      case 5: fd_rhs_adjoint_t<5, false>(a, b, s); break;
+      case 6: fd_rhs_adjoint_t<6, false>(a, b, s); break;
+      default: fd_rhs_adjoint_t<7, false>(a, b, s); break;
+    }
+  }
+}
+
+}  // namespace grffe

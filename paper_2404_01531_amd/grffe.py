@@ -91,7 +91,7 @@ def lib():
     L.grffe_operator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(dbl), ctypes.c_int]
     L.grffe_timing_enable.argtypes = [vp, ctypes.c_int]
     L.grffe_timing_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
-    L.grffe_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp]
+    L.grffe_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
     L.grffe_step_adjoint.argtypes = [vp, vp, vp, vp, dbl, vp]
     pvp = ctypes.POINTER(vp)
     L.grffe_batch_create.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(Params), pvp, vp, pvp]
@@ -256,15 +256,17 @@ class Domain:
     def step(self, n_steps=1, dt=0.0):
         _check(lib().grffe_step(self._h, int(n_steps), float(dt), _stream()))
 
-    def rhs_adjoint(self, dg, rep, lam, parts=PART_ALL, ubar=None):
-        """ubar + (dRHS/d dg)^T lam for an all-DG state (see grffe_rhs_adjoint)."""
+    def rhs_adjoint(self, dg, fd, rep, lam_dg, lam_fd, parts=PART_ALL):
+        """(ubar_dg, ubar_fd) = (dRHS/du)^T (lam_dg, lam_fd) for a state with every
+        live element on DG or every live element on FD (see grffe_rhs_adjoint)."""
         import torch
-        self._check_state(dg, None, rep)
-        self._check_state(lam, None, None)
-        if ubar is None:
-            ubar = torch.zeros_like(dg)
-        _check(lib().grffe_rhs_adjoint(self._h, _ptr(dg), _ptr(rep), _ptr(lam), _ptr(ubar), int(parts), _stream()))
-        return ubar
+        self._check_state(dg, fd, rep)
+        self._check_state(lam_dg, lam_fd, None)
+        ub_dg = torch.zeros_like(dg)
+        ub_fd = torch.zeros_like(fd)
+        _check(lib().grffe_rhs_adjoint(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _ptr(lam_dg), _ptr(lam_fd),
+                                       _ptr(ub_dg), _ptr(ub_fd), int(parts), _stream()))
+        return ub_dg, ub_fd
 
     def step_adjoint(self, u_dg, lam_next, dt=0.0):
         """(dU^{n+1}/dU^n)^T lam_next for one all-DG step from u_dg (see grffe_step_adjoint)."""
