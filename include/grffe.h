@@ -189,11 +189,14 @@ int grffe_timing_read(grffe_domain* dom, int family, double* total_ms, int64_t* 
  * the semi-discrete right-hand side of grffe_rhs restricted to `parts` (fluxes,
  * DG derivative and lift or FD WENO5-Z reconstruction, Rusanov faces and the
  * corrector, the no-incoming-Poynting boundary state, non-stiff and stiff sources
- * of Sec. II and III).  States whose live elements are all on DG (dg, lam_dg,
- * ubar_dg used) or all on FD (fd, lam_fd, ubar_fd used) are supported; layouts as
- * grffe_rhs, all device pointers non-NULL.  rep is read on the host (the call
- * synchronises the stream).  EUNSUPPORTED for states with elements on both, in
- * mixed precision or with the clamp on. */
+ * of Sec. II and III) and u is the pair (DG nodal values of the elements on DG, FD
+ * cell values of the elements on FD) chosen by rep, any mix of the two: the
+ * DG-FD coupling (P-projected ghost slabs, R-traces; Sec. III C) is transposed
+ * too.  Layouts as grffe_rhs; lam_dg / ubar_dg are read / accumulated on the DG
+ * elements and lam_fd / ubar_fd on the FD elements, the other entries are left
+ * untouched.  All device pointers non-NULL.  The first call allocates the work
+ * space (about 40 doubles per FD cell of the domain).  EUNSUPPORTED in mixed
+ * precision or with the clamp on. */
 int grffe_rhs_adjoint(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep, const double* lam_dg,
                       const double* lam_fd, double* ubar_dg, double* ubar_fd, int parts, void* stream);
 

@@ -565,20 +565,6 @@ extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream)
 // Representation check of the adjoint entry points: every live element on DG.
 // Representation of the live elements of `rep` (device): 0 all DG, 1 all FD,
 // 2 both (read on the host; synchronises the stream).
-static int rep_kind(grffe_domain* d, const int32_t* rep, hipStream_t st, int* kind) {
-  std::vector<int32_t> h(d->E);
-  HIPCHK(hipMemcpyAsync(h.data(), rep, sizeof(int32_t) * d->E, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  bool dg = false, fd = false;
-  for (int e = 0; e < d->E; ++e) {
-    if (!d->live_h[e]) continue;
-    if (h[e]) fd = true;
-    else dg = true;
-  }
-  *kind = (dg && fd) ? 2 : (fd ? 1 : 0);
-  return GRFFE_OK;
-}
-
 static int adjoint_supported(grffe_domain* d) {
   if (d->par.precision != GRFFE_PRECISION_FP64) return fail(GRFFE_EUNSUPPORTED, "the adjoint runs in FP64 only");
   if (d->par.ff_clamp) return fail(GRFFE_EUNSUPPORTED, "the adjoint does not differentiate the clamp");
@@ -607,24 +593,23 @@ extern "C" int grffe_rhs_adjoint(grffe_domain* d, const double* dg, const double
   if (parts < 1 || parts > 3) return fail(GRFFE_EINVAL, "parts must be 1, 2 or 3");
   if (int rc = adjoint_supported(d)) return rc;
   hipStream_t st = S(stream);
-  int kind = 0;
-  if (int rc = rep_kind(d, rep, st, &kind)) return rc;
-  if (kind == 2) return fail(GRFFE_EUNSUPPORTED, "the adjoint is built for states with every element on DG or every "
-                                                 "element on FD");
+  if (int rc = fd_adjoint_space(d)) return rc;
+  // the forward values the transposes are taken at: the FD elements' transported
+  // (U, J~) and the ghost slabs of their DG neighbours (as in grffe_rhs)
   KArgs a = make_args(d);
-  if (kind == 0) {
-    a.dg.Un = const_cast<double*>(dg);
-    launch_rhs_adjoint(a, d->N, d->curved, lam_dg, ubar_dg, parts, st);
-  } else {
-    if (int rc = fd_adjoint_space(d)) return rc;
-    a.fd.Un = const_cast<double*>(fd);
-    a.rep0 = const_cast<int32_t*>(rep);
-    a.sub = 3;
-    HIPCHK(hipMemsetAsync(d->fd_count + 3, 0, sizeof(int32_t), st));
-    launch_begin_substep(a, false, st);
-    launch_fd_stage(a, d->N, d->curved, MODE_RHS, st);  // transported values (U, J~) of the state
-    launch_fd_rhs_adjoint(a, d->N, d->curved, lam_fd, ubar_fd, parts, d->adj_fd_wbar, d->adj_fd_gbar, st);
-  }
+  a.dg.Un = const_cast<double*>(dg);
+  a.fd.Un = const_cast<double*>(fd);
+  a.rep0 = const_cast<int32_t*>(rep);
+  a.sub = 3;
+  HIPCHK(hipMemsetAsync(d->troubled, 0, d->E, st));
+  HIPCHK(hipMemsetAsync(d->fd_count + 3, 0, sizeof(int32_t), st));
+  launch_begin_substep(a, false, st);
+  launch_fd_stage(a, d->N, d->curved, MODE_RHS, st);
+  launch_dg_slab(a, d->N, d->curved, MODE_RHS, st);
+  // DG elements, then FD elements and the two couplings
+  launch_rhs_adjoint(a, d->N, d->curved, lam_dg, ubar_dg, parts, st);
+  launch_fd_rhs_adjoint(a, d->N, d->curved, lam_fd, ubar_fd, lam_dg, ubar_dg, parts, d->adj_fd_wbar,
+                        d->adj_fd_gbar, st);
   HIPCHK(hipGetLastError());
   return GRFFE_OK;
 }

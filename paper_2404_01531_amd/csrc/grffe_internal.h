@@ -185,7 +185,8 @@ void launch_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, d
 void launch_step_adjoint(const KArgs& a, int N, bool curved, const double* mu, double* lam, double* ws,
                          hipStream_t s);
 // launchers (kernels_fd_adj.hip)
-void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar, int parts,
-                           double* wbar, double* gbar, hipStream_t s);
+void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar,
+                           const double* lam_dg, double* ubar_dg, int parts, double* wbar, double* gbar,
+                           hipStream_t s);
 
 }  // namespace grffe

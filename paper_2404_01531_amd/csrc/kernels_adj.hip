@@ -1,6 +1,8 @@
 // Adjoint (vector-Jacobian products) of the DG right-hand side and of the
-// IMEX-SSP3(4,3,3) step, with every element held on DG (the representation is
-// frozen; the indicator is not differentiated).
+// IMEX-SSP3(4,3,3) step.  The representation is frozen (the indicator is not
+// differentiated); the step adjoint holds every element on DG, the right-hand side
+// adjoint takes any mix of DG and FD elements (this file covers the DG elements;
+// the FD elements and the two couplings are in the FD adjoint).
 //
 // The explicit DG operator at a node p of element e is (Sec. III A, strong form)
 //   L(X)_p = -sum_d s_d [ sum_q D[i_d(p)][q] F^d(X_q) ] + lift terms + S_ex(X_p),
@@ -8,9 +10,10 @@
 // (s = 1) faces.  Its transpose applied to V gathers, at every node r:
 //   - the transposed derivative g_d(r) = -s_d sum_p D[i_d(p)][i_d(r)] V(p) along
 //     the three lines through r, multiplied by (dF^d/dX)^T at r;
-//   - the node's own face terms and the terms of the neighbouring element's faces
-//     whose exterior state is X_r (no scatter: every element gathers from its
-//     neighbours' V at the mirror nodes);
+//   - the node's own face terms and the terms of the neighbouring DG element's
+//     faces whose exterior state is X_r (no scatter: every element gathers from its
+//     neighbours' V at the mirror nodes; an FD neighbour sees X only through the
+//     projected ghost slab, whose transpose is applied separately);
 //   - (dS_ex/dX)^T V(r), and at physical boundaries the derivative through the
 //     no-incoming-Poynting state.
 // All products with pointwise Jacobians are formed as the gradient of one scalar
@@ -151,8 +154,8 @@ __device__ void operator_vjp(const KArgs& a, const AdjBufs& b, int e, int p, boo
         bside[d] = s ? 1 : -1;
         bA[d] = s ? -0.5 * wr : 0.5 * wl;
         bI[d] = s ? 0.5 * wr * lam : 0.5 * wl * lam;
-      } else {
-        // the neighbour's face term on its opposite face uses X as exterior state
+      } else if (a.rep0[o] == 0) {
+        // the DG neighbour's face term on its opposite face uses X as exterior state
         const double sco = 2.0 / h_of(a, o, d);
         double Vo[NV];
         load9(b.v_in, a.E, nn, o, pn, Vo);
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adjoint(KArgs a, AdjBufs b)
   __shared__ double sD[n * n];
   __shared__ double sF[n * n];
   const int e = blockIdx.x;
-  if (!a.live[e]) return;
+  if (!a.live[e] || a.rep0[e] != 0) return;
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int p = act ? t : 0;

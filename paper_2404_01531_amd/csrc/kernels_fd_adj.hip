@@ -1,5 +1,5 @@
-// Adjoint of the FD subcell right-hand side (Sec. III C 2) for states whose live
-// elements are all on FD.
+// Adjoint of the FD subcell right-hand side (Sec. III C 2) and of the DG-FD
+// coupling (Sec. III C 3) for any mix of DG and FD elements.
 //
 // Along each pencil of direction d the right-hand side of cell c is
 //   L_c = -(m/h) (Fhat_{c+1/2} - Fhat_{c-1/2}) + S(U_c),
@@ -14,6 +14,14 @@
 // of cells next to a face carry adjoints into the neighbour's cells (ghost
 // cells): they are written per face and layer and gathered by the element that
 // owns the cells, so no atomics are needed and the result is deterministic.
+//
+// Coupling.  An FD element's ghost cells next to a DG neighbour are the
+// P-projection of the neighbour's (U, J~) (the ghost slab), so their adjoints go
+// back through P^T to the DG nodes and through the current's gradient to U there.
+// A DG element's exterior state next to an FD neighbour is the R-trace of the FD
+// element's (U, J~), and the DG face flux is linear in it (the Rusanov speed is
+// the DG node's), so the adjoint of the trace is formed at the DG face nodes and
+// taken back through R^T to the FD cells.
 #include "adjoint.h"
 #include "fd_common.h"
 
@@ -84,10 +92,12 @@ __device__ inline void flux_lin_vjp_d(int d, const Metric& M, const double* G, d
 }
 
 struct FdAdj {
-  const double* lam;  // [9][E][m^3] adjoint input (lambda)
-  double* ubar;       // [9][E][m^3] output (accumulated)
-  double* wbar;       // [3][10][E][m^3] per-direction adjoints of the transported cell values
-  double* gbar;       // [10][E][6][3][m^2] adjoints of ghost cells, per face and layer
+  const double* lam;     // [9][E][m^3] adjoint input (lambda) of the FD elements
+  double* ubar;          // [9][E][m^3] output (accumulated)
+  const double* lam_dg;  // [9][E][n^3] adjoint input of the DG elements
+  double* ubar_dg;       // [9][E][n^3] output of the DG elements (accumulated)
+  double* wbar;          // [3][10][E][m^3] per-direction adjoints of the transported cell values
+  double* gbar;          // [10][E][6][3][m^2] adjoints of ghost cells, per face and layer
   int parts;
 };
 
@@ -333,8 +343,9 @@ __global__ __launch_bounds__(256) void k_fd_adj_gather(KArgs a, FdAdj b) {
           if (l > 2) continue;
           const int f = 2 * d + s;
           const int o = a.nbr[e * 6 + f];
+          if (o >= 0 && a.rep0[o] == 0) continue;  // a DG neighbour reads the R-trace
           if (o >= 0) {
-            // the neighbour's ghost layer l on its face towards us is this cell
+            // the FD neighbour's ghost layer l on its face towards us is this cell
             const int fo = f ^ 1;
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
@@ -396,22 +407,191 @@ __global__ __launch_bounds__(256) void k_fd_adj_gather(KArgs a, FdAdj b) {
   }
 }
 
+// Adjoint of the R-traces the DG neighbours of an FD element read: one workgroup
+// per listed FD element, its faces with a DG neighbour one after the other.  At the
+// DG face node the exterior state enters the lower-face lift as
+// +(2/h)/w_0 (F(Ux)/2 + lambda Ux/2) and the upper-face lift as
+// -(2/h)/w_N (F(Ux)/2 - lambda Ux/2); the adjoint of (Ux, J~x^d) is taken through
+// R (x) R (x) R restricted to the face (row 0 or N along the normal) transposed and
+// added to the element's per-direction adjoints wbar (after the flux adjoint).
+template <int N, bool CURVED>
+__global__ __launch_bounds__(256) void k_fd_adj_trace(KArgs a, FdAdj b) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, mm = Dm::mm;
+  constexpr int NR = NV + 1;
+  __shared__ double sR[n * m];
+  __shared__ double sT[NR * n * n];  // trace adjoint [k][a2][a1]
+  __shared__ double s1[NR * n * m];  // [k][a2][c1]
+  __shared__ double s2[NR * m * m];  // [k][c2][c1]
+  const int t = threadIdx.x;
+  for (int q = t; q < n * m; q += 256) sR[q] = a.ops->R[q];
+  const int items = a.fd_count[a.sub];
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int e = a.fd_list[item];
+    for (int f = 0; f < 6; ++f) {
+      const int g = a.nbr[e * 6 + f];
+      if (g < 0 || a.rep0[g] != 0) continue;
+      const int d = f >> 1;
+      const int fg = f ^ 1, sg = fg & 1;  // the DG element's face and side
+      const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+      const int strn[3] = {1, n, n * n};
+      __syncthreads();
+      for (int q = t; q < n * n; q += 256) {
+        const int a1 = q % n, a2 = q / n;
+        const int pn = (sg ? N : 0) * strn[d] + a1 * strn[t1ax] + a2 * strn[t2ax];
+        Metric M;
+        load_metric<CURVED>(a.bg_dg, a.E, nn, g, pn, M);
+        double V[NV];
+        load9(b.lam_dg, a.E, nn, g, pn, V);
+        const double sc = 2.0 / h_of(a, g, d);
+        const double lam = CURVED ? char_speed(d, M) : 1.0;
+        const double wgt = sg ? sc / a.ops->w[N] : sc / a.ops->w[0];
+        const double cG = sg ? -0.5 * wgt : 0.5 * wgt, cU = 0.5 * wgt * lam;
+        double Gb[NV], Tb[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          Gb[v] = cG * V[v];
+          Tb[v] = cU * V[v];
+        }
+        flux_lin_vjp_d(d, M, Gb, Tb);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sT[v * n * n + q] = Tb[v];
+        sT[NV * n * n + q] = Gb[8];  // the q~ flux carries J~^d
+      }
+      __syncthreads();
+      // first tangential axis: a1 (n) -> c1 (m)
+      for (int q = t; q < NR * n * m; q += 256) {
+        const int c1 = q % m, rest = q / m;  // rest = k n + a2
+        double acc = 0.0;
+#pragma unroll
+        for (int z = 0; z < n; ++z) acc += sR[z * m + c1] * sT[rest * n + z];
+        s1[q] = acc;
+      }
+      __syncthreads();
+      // second tangential axis: a2 (n) -> c2 (m)
+      for (int q = t; q < NR * m * m; q += 256) {
+        const int c1 = q % m, c2 = (q / m) % m, k = q / (m * m);
+        double acc = 0.0;
+#pragma unroll
+        for (int z = 0; z < n; ++z) acc += sR[z * m + c2] * s1[(k * n + z) * m + c1];
+        s2[q] = acc;
+      }
+      __syncthreads();
+      // normal axis: row 0 (lower face) or N (upper face) of R, spread over the line
+      const int row = (f & 1) ? N : 0;
+      for (int q = t; q < mm; q += 256) {
+        const int ci[3] = {q % m, (q / m) % m, q / (m * m)};
+        const double r = sR[row * m + ci[d]];
+        const int tt = ci[t1ax] + m * ci[t2ax];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          b.wbar[(((size_t)d * NR + k) * a.E + e) * mm + q] += r * s2[k * m * m + tt];
+      }
+    }
+  }
+}
+
+// Adjoint of the ghost slabs a DG element hands to its FD neighbours: for each face
+// with an FD neighbour, the neighbour's ghost adjoints (three layers, U and J~^d)
+// taken back through P (x) P (x) P transposed to the element's nodes, then through
+// the current's gradient to U.  One workgroup per DG element.
+template <int N, bool CURVED>
+__global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adj_slab(KArgs a, FdAdj b) {
+  using Dm = Dims<N>;
+  constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, TPB = Dm::tpb;
+  constexpr int NR = NV + 1;
+  const int g = blockIdx.x;
+  if (!a.live[g] || a.rep0[g] != 0) return;
+  int need = 0;
+  for (int f = 0; f < 6; ++f) {
+    const int o = a.nbr[g * 6 + f];
+    if (o >= 0 && a.rep0[o] == 1) need |= 1 << f;
+  }
+  if (!need) return;
+  __shared__ double sP[m * n];
+  __shared__ double sG[3 * m * m];  // [l][c2][c1]
+  __shared__ double sB[3 * n * m];  // [l][a2][c1]
+  __shared__ double sA[3 * n * n];  // [l][a2][a1]
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int p = act ? t : 0;
+  for (int q = t; q < m * n; q += TPB) sP[q] = a.ops->P[q];
+  const int idx[3] = {p % n, (p / n) % n, p / (n * n)};
+  double Wb[NV], Jb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Wb[v] = 0.0;
+  for (int f = 0; f < 6; ++f) {
+    if (!(need & (1 << f))) continue;
+    const int e = a.nbr[g * 6 + f];
+    const int d = f >> 1, s = f & 1, fe = f ^ 1;
+    const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+    for (int k = 0; k < NR; ++k) {
+      __syncthreads();
+      for (int q = t; q < 3 * m * m; q += TPB)
+        sG[q] = b.gbar[(((size_t)k * a.E + e) * 6 + fe) * (3 * m * m) + q];
+      __syncthreads();
+      // second tangential axis back: c2 (m) -> a2 (n)
+      for (int q = t; q < 3 * n * m; q += TPB) {
+        const int c1 = q % m, a2 = (q / m) % n, l = q / (n * m);
+        double acc = 0.0;
+        for (int z = 0; z < m; ++z) acc += sP[z * n + a2] * sG[(l * m + z) * m + c1];
+        sB[q] = acc;
+      }
+      __syncthreads();
+      // first tangential axis back: c1 (m) -> a1 (n)
+      for (int q = t; q < 3 * n * n; q += TPB) {
+        const int a1 = q % n, rest = q / n;  // rest = l n + a2
+        double acc = 0.0;
+        for (int z = 0; z < m; ++z) acc += sP[z * n + a1] * sB[rest * m + z];
+        sA[q] = acc;
+      }
+      __syncthreads();
+      // normal axis back: layers l (cells l or m-1-l) -> node index along d
+      if (act) {
+        const int zi = idx[d], a1 = idx[t1ax], a2 = idx[t2ax];
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          const int cell = s ? (m - 1 - l) : l;
+          acc += sP[cell * n + zi] * sA[(l * n + a2) * n + a1];
+        }
+        if (k < NV) Wb[k] += acc;
+        else Jb[d] += acc;
+      }
+    }
+  }
+  if (!act) return;
+  Metric M;
+  load_metric<CURVED>(a.bg_dg, a.E, nn, g, p, M);
+  double X[NV];
+  load9(a.dg.Un, a.E, nn, g, p, X);
+  current_vjp(X, M, a.eta, Jb, Jb, Wb);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) b.ubar_dg[((size_t)v * a.E + g) * nn + p] += Wb[v];
+}
+
 template <int N, bool CURVED>
 static void fd_rhs_adjoint_t(const KArgs& a, const FdAdj& b, hipStream_t s) {
   constexpr int m = Dims<N>::m, mm = Dims<N>::mm;
   const size_t flux_items = (size_t)a.E * 3 * m, cell_items = (size_t)a.E * ((mm + 255) / 256);
-  if (b.parts & 1)
+  if (b.parts & 1) {
     launch_kernel(k_fd_adj_flux<N, CURVED>, dim3((unsigned)(flux_items < 2048 ? flux_items : 2048)), dim3(256), s,
                   a, b);
+    launch_kernel(k_fd_adj_trace<N, CURVED>, dim3((unsigned)(a.E < 2048 ? a.E : 2048)), dim3(256), s, a, b);
+  }
   launch_kernel(k_fd_adj_gather<N, CURVED>, dim3((unsigned)(cell_items < 2048 ? cell_items : 2048)), dim3(256), s,
                 a, b);
+  if (b.parts & 1) launch_kernel(k_dg_adj_slab<N, CURVED>, dim3(a.E), dim3(Dims<N>::tpb), s, a, b);
 }
 
-void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar, int parts,
-                           double* wbar, double* gbar, hipStream_t s) {
+void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar,
+                           const double* lam_dg, double* ubar_dg, int parts, double* wbar, double* gbar,
+                           hipStream_t s) {
   FdAdj b{};
   b.lam = lam;
   b.ubar = ubar;
+  b.lam_dg = lam_dg;
+  b.ubar_dg = ubar_dg;
   b.wbar = wbar;
   b.gbar = gbar;
   b.parts = parts;

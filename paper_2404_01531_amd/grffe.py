@@ -257,8 +257,9 @@ class Domain:
         _check(lib().grffe_step(self._h, int(n_steps), float(dt), _stream()))
 
     def rhs_adjoint(self, dg, fd, rep, lam_dg, lam_fd, parts=PART_ALL):
-        """(ubar_dg, ubar_fd) = (dRHS/du)^T (lam_dg, lam_fd) for a state with every
-        live element on DG or every live element on FD (see grffe_rhs_adjoint)."""
+        """(ubar_dg, ubar_fd) = (dRHS/du)^T (lam_dg, lam_fd) for a state of DG and FD
+        elements chosen by rep (see grffe_rhs_adjoint); the entries of elements in
+        the other representation are zero."""
         import torch
         self._check_state(dg, fd, rep)
         self._check_state(lam_dg, lam_fd, None)

@@ -190,6 +190,108 @@ def test_fd_rhs_adjoint_kerr_schild():
     _rhs_case(w, dict(eta=w["eta"]), fd, "all-FD kerr-schild 4^3 P5", rng, on_fd=True, tol=TOL_FD)
 
 
+def _mixed_case(w, params, dg, fd, label, rng, tol=TOL_FD):
+    """Dot-product check of grffe_rhs_adjoint for a state with DG and FD elements side
+    by side (about half of each, random), so that the P-projected ghost slabs and the
+    R-traces between them are transposed too."""
+    torch = _torch()
+    odom, ldom, _ = make_pair(w, params)
+    E = odom.E
+    act = odom.active
+    rep = (rng.random(E) < 0.5).astype(np.int64)
+    rep[np.nonzero(act)[0][:2]] = (DG, FD)
+    rep[~act] = DG
+    on_dg = act & (rep == DG)
+    on_fd = act & (rep == FD)
+    dg = dg.copy()
+    fd = fd.copy()
+    dg[:, ~on_dg] = 0.0
+    fd[:, ~on_fd] = 0.0
+    lam_d = rng.standard_normal(dg.shape)
+    lam_f = rng.standard_normal(fd.shape)
+    lam_d[:, ~on_dg] = 0.0
+    lam_f[:, ~on_fd] = 0.0
+    scale = np.maximum(np.abs(dg).max(axis=(1, 2, 3, 4)), np.abs(fd).max(axis=(1, 2, 3, 4)))[:, None, None, None, None]
+    del_d = rng.standard_normal(dg.shape) * scale
+    del_f = rng.standard_normal(fd.shape) * scale
+    del_d[:, ~on_dg] = 0.0
+    del_f[:, ~on_fd] = 0.0
+    rep_t = torch.from_numpy(rep.astype(np.int32)).cuda()
+
+    def ddir(L):
+        def D(eps):
+            pd, pf = L(dg + eps * del_d, fd + eps * del_f)
+            md, mf = L(dg - eps * del_d, fd - eps * del_f)
+            return float(((lam_d * (pd - md)).sum() + (lam_f * (pf - mf)).sum()) / (2 * eps))
+        return (4.0 * D(2e-9) - D(4e-9)) / 3.0
+
+    def lib_rhs(a, b, parts):
+        gd, gf = ldom.rhs(to_dev(a), to_dev(b), rep_t, parts=parts)
+        return gd.cpu().numpy().reshape(dg.shape), gf.cpu().numpy().reshape(fd.shape)
+
+    for parts in (1, 2, 3):
+        bd, bf = ldom.rhs_adjoint(to_dev(dg), to_dev(fd), rep_t, to_dev(lam_d), to_dev(lam_f), parts=parts)
+        bd = bd.cpu().numpy().reshape(dg.shape)
+        bf = bf.cpu().numpy().reshape(fd.shape)
+        # entries of the other representation stay untouched (zero here)
+        assert not bd[:, ~on_dg].any() and not bf[:, ~on_fd].any()
+        lhs = float((bd * del_d).sum() + (bf * del_f).sum())
+        rhs_o = ddir(lambda a, b: OR.rhs(odom, a, b, rep, parts=parts))
+        rhs_g = ddir(lambda a, b: lib_rhs(a, b, parts))
+        _say(f"rhs adjoint {label} ({int(on_dg.sum())} DG, {int(on_fd.sum())} FD) parts={parts}: <ubar,d> "
+             f"{lhs:.12e}  oracle FD {rhs_o:.12e} (rel {_rel(lhs, rhs_o):.1e})  library FD {rhs_g:.12e} "
+             f"(rel {_rel(lhs, rhs_g):.1e})")
+        assert _rel(lhs, rhs_o) <= tol, (label, parts)
+        assert _rel(lhs, rhs_g) <= tol, (label, parts)
+
+
+def test_mixed_rhs_adjoint_flat_periodic():
+    _torch()
+    w = dict(I.workload("wave", n_elem=(3, 2, 2)), kind="wave")
+    rng = np.random.default_rng(51)
+    odom, _, _ = make_pair(w)
+    dg = _wave_state(odom, w, rng)
+    fd = _fd_state(odom, w, rng, 1e-4)
+    _mixed_case(w, dict(eta=w["eta"]), dg, fd, "mixed wave 3x2x2 P5", rng)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_mixed_rhs_adjoint_outflow_boundaries(N):
+    _torch()
+    w = dict(n_elem=(3, 2, 2), lower=(-1.0, -0.5, -0.25), upper=(1.0, 0.75, 0.5), degree=N, bc=(1, 1, 0, 0, 1, 1),
+             curved=False, kind="wave")
+    rng = np.random.default_rng(52 + N)
+    odom, _, _ = make_pair(w)
+    dg = _wave_state(odom, w, rng)
+    fd = _fd_state(odom, w, rng, 1e-4)
+    _mixed_case(w, dict(eta=50.0), dg, fd, f"mixed ragged P{N} outflow", rng)
+
+
+def test_mixed_rhs_adjoint_second_order_flux():
+    _torch()
+    w = dict(I.workload("wave", n_elem=(2, 2, 2), degree=4), kind="wave")
+    rng = np.random.default_rng(57)
+    odom, _, _ = make_pair(w)
+    dg = _wave_state(odom, w, rng)
+    fd = _fd_state(odom, w, rng, 1e-4)
+    _mixed_case(w, dict(eta=1e3, fd_order=2), dg, fd, "mixed wave P4 FD2", rng)
+
+
+def test_mixed_rhs_adjoint_kerr_schild():
+    _torch()
+    w = I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3)
+    rng = np.random.default_rng(58)
+    odom, _, _ = make_pair(w)
+    with np.errstate(all="ignore"):
+        dg, fd = curved_state(odom, w, rng)
+    # B~x = B~y = 0 exactly in the uniform-field state: the no-incoming-Poynting
+    # switch on z faces (E~x B~y - E~y B~x = 0) would flip under any perturbation of
+    # them, so every component carries noise
+    dg += 1e-4 * rng.standard_normal(dg.shape)
+    fd += 1e-4 * rng.standard_normal(fd.shape)
+    _mixed_case(w, dict(eta=w["eta"]), dg, fd, "mixed kerr-schild 4^3 P5", rng)
+
+
 def _step_case(w, params, u, label, rng, dt=None):
     torch = _torch()
     params = dict(params, hybrid=0)
@@ -289,17 +391,16 @@ def test_autograd_checkpointed_objective():
     assert _rel(an, fd) <= TOL
 
 
-def test_adjoint_rejects_mixed_and_mixed_precision():
+def test_adjoint_rejects_mixed_precision_and_clamp():
     torch = _torch()
     from paper_2404_01531_amd import grffe
     w = I.workload("wave")
-    odom, ldom, _ = make_pair(w)
-    u = torch.zeros(ldom.dg_shape(), dtype=torch.float64, device="cuda")
-    f = torch.zeros(ldom.fd_shape(), dtype=torch.float64, device="cuda")
-    rep = torch.zeros(ldom.E, dtype=torch.int32, device="cuda")
-    rep[3] = FD
-    with pytest.raises(grffe.GrffeError):
-        ldom.rhs_adjoint(u, f, rep, u, f)
-    _, lmix, _ = make_pair(w, dict(precision=1))
-    with pytest.raises(grffe.GrffeError):
-        lmix.step_adjoint(u, u)
+    for extra in (dict(precision=1), dict(ff_clamp=1)):
+        _, ldom, _ = make_pair(w, extra)
+        u = torch.zeros(ldom.dg_shape(), dtype=torch.float64, device="cuda")
+        f = torch.zeros(ldom.fd_shape(), dtype=torch.float64, device="cuda")
+        rep = torch.zeros(ldom.E, dtype=torch.int32, device="cuda")
+        with pytest.raises(grffe.GrffeError):
+            ldom.rhs_adjoint(u, f, rep, u, f)
+        with pytest.raises(grffe.GrffeError):
+            ldom.step_adjoint(u, u)
