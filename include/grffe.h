@@ -213,6 +213,25 @@ int grffe_rhs_adjoint(grffe_domain* dom, const double* dg, const double* fd, con
 int grffe_step_adjoint(grffe_domain* dom, const double* u_dg, const double* lam_next, double* lam, double dt,
                        void* stream);
 
+/* Adjoint of one IMEX-SSP3(4,3,3) step (Sec. III B) with the representation of
+ * every element held at rep (the hybrid decisions frozen: no indicator, no
+ * rollback, no switch back; the forward step of GRFFE_HYBRID_FORCED):
+ *   (lam_dg, lam_fd) = (d U^{n+1} / d U^n)^T (mu_dg, mu_fd),
+ * with U = (DG nodal values of the DG elements, FD cell values of the FD elements)
+ * as in grffe_rhs_adjoint.  Every stage is transposed on both representations:
+ * the DG operator and filter, the FD WENO5-Z fluxes, the P-projected ghost slabs
+ * and R-traces between them (Sec. III C), the implicit solves (implicit function
+ * theorem) and the stiff sources.  dg, fd, rep are U^n and its representation
+ * (device, layouts of grffe_set_state); the domain re-runs the forward step from
+ * them, so its state is left at U^{n+1} with that representation.  dt <= 0 selects
+ * the CFL step.  lam_* may be the same buffers as mu_*; none may overlap dg or fd.
+ * Entries of elements in the other representation are left untouched.  Same
+ * restrictions as grffe_rhs_adjoint; the first call allocates the work space
+ * (7 DG-sized and 7 FD-sized arrays besides that of grffe_rhs_adjoint). */
+int grffe_step_adjoint_frozen(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep,
+                              const double* mu_dg, const double* mu_fd, double* lam_dg, double* lam_fd, double dt,
+                              void* stream);
+
 /* Batches: many independent domains advanced together, each with its own grid,
  * degree (3..7) and CFL time step (Eq. (spectre DG CFL condition) per domain).
  * Domains of one degree are concatenated into one pool, so every kernel of a step

@@ -156,4 +156,99 @@ __device__ inline void solve_vjp(const double* U, const Metric& M, const KArgs& 
   y[8] = ub[8];
 }
 
+// U_1, U_2 of the implicit pre-stages from U^n (as in the forward step).
+__device__ inline void pre_stages(const double* Un, const Metric& M, const KArgs& a, double dt, double* U1,
+                                  double* U2, double* S1) {
+  const double h = dt * IMEX_A;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) U1[v] = Un[v];
+  implicit_solve(U1, M, a.eta, a.kpsi, a.kphi, h);
+  source_stiff(U1, M, a.eta, a.kpsi, a.kphi, S1);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) U2[v] = Un[v] - dt * IMEX_A * S1[v];
+  implicit_solve(U2, M, a.eta, a.kpsi, a.kphi, h);
+}
+
+// The step's stage algebra transposed, point by point (the same on DG nodes and FD
+// cells; on DG, Z has been taken through the transposed filter first).
+// Last substep: U^{n+1} = Phi(Y3), Y3 = U^n + A' + dt S2/6 + (2/3) dt (L(U_4) + S(U_4)),
+// Z the adjoint of Y3.
+__device__ inline void adj_a3_tail(const AdjBufs& b, int E, int P, int e, int p, double dt, const double* Z) {
+  double V[NV], S2b[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    V[v] = (2.0 / 3.0) * dt * Z[v];
+    S2b[v] = dt / 6.0 * Z[v];
+  }
+  store9(b.un_bar, E, P, e, p, Z);
+  store9(b.a_bar, E, P, e, p, Z);
+  store9(b.s2_bar, E, P, e, p, S2b);
+  store9(b.v_out, E, P, e, p, V);
+  store9(b.w, E, P, e, p, V);
+}
+
+// Substeps 2 (B3: Y2 -> U_4) and 1 (B2: Y1 -> U_3), Z the adjoint of the substep's
+// input combination Y.
+template <int STAGE>
+__device__ inline void adj_b_tail(const AdjBufs& b, int E, int P, int e, int p, double dt, const double* Z) {
+  double unb[NV], Ab[NV];
+  load9(b.un_bar, E, P, e, p, unb);
+  load9(b.a_bar, E, P, e, p, Ab);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) unb[v] += Z[v];
+  store9(b.un_bar, E, P, e, p, unb);
+  double V[NV], Wn[NV];
+  if (STAGE == ADJ_B3) {
+    // Y2 = U^n + (A + dt L(U3))/4 + dt (b S1 + e S2 + c3 S(U3)),  A' = (A + dt L(U3))/6 + dt S(U3)/6
+    const double c3 = 0.5 - IMEX_B - IMEX_E - IMEX_A;
+    double S1b[NV], S2b[NV];
+    load9(b.s2_bar, E, P, e, p, S2b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double inc = 0.25 * Z[v] + Ab[v] / 6.0;
+      Wn[v] = c3 * dt * Z[v] + dt / 6.0 * Ab[v];
+      V[v] = dt * inc;
+      Ab[v] = inc;
+      S1b[v] = IMEX_B * dt * Z[v];
+      S2b[v] += IMEX_E * dt * Z[v];
+    }
+    store9(b.a_bar, E, P, e, p, Ab);
+    store9(b.s1_bar, E, P, e, p, S1b);
+    store9(b.s2_bar, E, P, e, p, S2b);
+  } else {
+    // Y1 = U^n + dt L(U2) + dt (1 - a) S(U2),  A = dt L(U2);  S2 = S(U2)
+    double S2b[NV];
+    load9(b.s2_bar, E, P, e, p, S2b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      V[v] = dt * (Z[v] + Ab[v]);
+      Wn[v] = (1.0 - IMEX_A) * dt * Z[v] + S2b[v];
+    }
+  }
+  store9(b.v_out, E, P, e, p, V);
+  store9(b.w, E, P, e, p, Wn);
+}
+
+// The implicit pre-stages: U_2 = solve(U^n - a dt S1), S1 = S(U_1), U_1 = solve(U^n);
+// ub is the adjoint of U_2 (operator and stiff parts of the first substep).
+__device__ inline void adj_b1_tail(const KArgs& a, const AdjBufs& b, int E, int P, int e, int p, const Metric& M,
+                                   double dt, const double* U2, const double* U1, const double* ub) {
+  const double h = dt * IMEX_A;
+  double Y[NV], S1b[NV], U1b[NV], Yn[NV], unb[NV];
+  solve_vjp(U2, M, a, h, ub, Y);
+  load9(b.s1_bar, E, P, e, p, S1b);
+  load9(b.un_bar, E, P, e, p, unb);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    unb[v] += Y[v];
+    S1b[v] -= IMEX_A * dt * Y[v];
+    U1b[v] = 0.0;
+  }
+  stiff_vjp(U1, M, a, S1b, U1b);
+  solve_vjp(U1, M, a, h, U1b, Yn);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) unb[v] += Yn[v];
+  store9(b.un_bar, E, P, e, p, unb);
+}
+
 }  // namespace grffe

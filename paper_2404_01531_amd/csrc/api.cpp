@@ -584,6 +584,30 @@ static int fd_adjoint_space(grffe_domain* d) {
   return GRFFE_OK;
 }
 
+// Work space of the step adjoint: six adjoint registers per representation
+// (accumulator, two stiff-source adjoints, stiff vector, two explicit vectors), the
+// copies of U^n and one DG-sized array for the slab transposes.
+static int step_adjoint_space(grffe_domain* d, bool with_fd) {
+  const size_t reg = (size_t)NV * d->E * d->nn, regf = (size_t)NV * d->E * d->mm;
+  void* p = nullptr;
+  if (!d->adj_ws) {
+    if (int rc = dalloc(d, &p, sizeof(double) * 6 * reg)) return rc;
+    d->adj_ws = reinterpret_cast<double*>(p);
+    if (int rc = dalloc(d, &p, sizeof(double) * reg)) return rc;
+    d->adj_u0 = reinterpret_cast<double*>(p);
+  }
+  if (with_fd && !d->adj_fd_ws) {
+    if (int rc = fd_adjoint_space(d)) return rc;
+    if (int rc = dalloc(d, &p, sizeof(double) * 6 * regf)) return rc;
+    d->adj_fd_ws = reinterpret_cast<double*>(p);
+    if (int rc = dalloc(d, &p, sizeof(double) * regf)) return rc;
+    d->adj_u0_fd = reinterpret_cast<double*>(p);
+    if (int rc = dalloc(d, &p, sizeof(double) * reg)) return rc;
+    d->adj_extra = reinterpret_cast<double*>(p);
+  }
+  return GRFFE_OK;
+}
+
 extern "C" int grffe_rhs_adjoint(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep,
                                  const double* lam_dg, const double* lam_fd, double* ubar_dg, double* ubar_fd,
                                  int parts, void* stream) {
@@ -621,14 +645,7 @@ extern "C" int grffe_step_adjoint(grffe_domain* d, const double* u_dg, const dou
   if (int rc = adjoint_supported(d)) return rc;
   hipStream_t st = S(stream);
   const size_t reg = (size_t)NV * d->E * d->nn;
-  if (!d->adj_ws) {
-    void* p1 = nullptr;
-    void* p2 = nullptr;
-    if (int rc = dalloc(d, &p1, sizeof(double) * 6 * reg)) return rc;
-    d->adj_ws = reinterpret_cast<double*>(p1);
-    if (int rc = dalloc(d, &p2, sizeof(double) * reg)) return rc;
-    d->adj_u0 = reinterpret_cast<double*>(p2);
-  }
+  if (int rc = step_adjoint_space(d, false)) return rc;
   // forward step from u_dg with every element on DG, keeping U_3, U_4 in the registers
   HIPCHK(hipMemcpyAsync(d->adj_u0, u_dg, sizeof(double) * reg, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(d->dg.Un, u_dg, sizeof(double) * reg, hipMemcpyDeviceToDevice, st));
@@ -642,6 +659,79 @@ extern "C" int grffe_step_adjoint(grffe_domain* d, const double* u_dg, const dou
   KArgs b = a;
   b.dg.Un = d->adj_u0;
   launch_step_adjoint(b, d->N, d->curved, lam_next, lam, d->adj_ws, st);
+  HIPCHK(hipGetLastError());
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_step_adjoint_frozen(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep,
+                                         const double* mu_dg, const double* mu_fd, double* lam_dg, double* lam_fd,
+                                         double dt, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (!dg || !fd || !rep || !mu_dg || !mu_fd || !lam_dg || !lam_fd)
+    return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
+  if (int rc = adjoint_supported(d)) return rc;
+  if (int rc = step_adjoint_space(d, true)) return rc;
+  hipStream_t st = S(stream);
+  const int N = d->N;
+  const bool cv = d->curved;
+  const size_t reg = (size_t)NV * d->E * d->nn, regf = (size_t)NV * d->E * d->mm;
+  // forward step from (dg, fd) with the representation held at rep, keeping the
+  // stage registers U_3 (X0) and U_4 (X1) of both representations
+  HIPCHK(hipMemcpyAsync(d->adj_u0, dg, sizeof(double) * reg, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d->adj_u0_fd, fd, sizeof(double) * regf, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d->dg.Un, dg, sizeof(double) * reg, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d->fd.Un, fd, sizeof(double) * regf, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d->rep, rep, sizeof(int32_t) * d->E, hipMemcpyDeviceToDevice, st));
+  KArgs a = make_args(d);
+  a.hybrid = GRFFE_HYBRID_FORCED;
+  if (dt > 0.0) a.dt = dt;
+  step_once(d, a, st);
+  HIPCHK(hipGetLastError());
+  // backward sweep: the last substep, substeps 2 and 1, then the implicit pre-stages
+  KArgs b = a;
+  b.dg.Un = d->adj_u0;
+  b.fd.Un = d->adj_u0_fd;
+  b.rep0 = d->rep;
+  b.sub = 3;
+  HIPCHK(hipMemsetAsync(d->troubled, 0, d->E, st));
+  HIPCHK(hipMemsetAsync(d->fd_count + 3, 0, sizeof(int32_t), st));
+  launch_begin_substep(b, false, st);
+  AdjBufs rd{}, rf{};
+  rd.mu = mu_dg;
+  rd.un_bar = lam_dg;
+  rd.a_bar = d->adj_ws;
+  rd.s1_bar = d->adj_ws + reg;
+  rd.s2_bar = d->adj_ws + 2 * reg;
+  rd.w = d->adj_ws + 3 * reg;
+  rf.mu = mu_fd;
+  rf.un_bar = lam_fd;
+  rf.a_bar = d->adj_fd_ws;
+  rf.s1_bar = d->adj_fd_ws + regf;
+  rf.s2_bar = d->adj_fd_ws + 2 * regf;
+  rf.w = d->adj_fd_ws + 3 * regf;
+  double* vd[2] = {d->adj_ws + 4 * reg, d->adj_ws + 5 * reg};
+  double* vf[2] = {d->adj_fd_ws + 4 * regf, d->adj_fd_ws + 5 * regf};
+  const int order[4] = {ADJ_A3, ADJ_B3, ADJ_B2, ADJ_B1};
+  for (int k = 0; k < 4; ++k) {
+    const int stage = order[k];
+    rd.v_in = vd[(k + 1) % 2];
+    rd.v_out = vd[k % 2];
+    rf.v_in = vf[(k + 1) % 2];
+    rf.v_out = vf[k % 2];
+    rd.extra = nullptr;
+    if (stage != ADJ_A3) {
+      const int mode = stage == ADJ_B3 ? MODE_SUB3 : (stage == ADJ_B2 ? MODE_SUB2 : MODE_SUB1);
+      if (stage == ADJ_B1) launch_dg_prestage(b, N, cv, st);  // X1 <- U_2 of U^n
+      launch_fd_stage(b, N, cv, mode, st);                     // the FD cells' stage values
+      launch_dg_slab(b, N, cv, mode, st);                      // the ghost slabs at the stage
+      HIPCHK(hipMemsetAsync(d->adj_extra, 0, sizeof(double) * reg, st));
+      launch_fd_step_coupling(b, N, cv, rf.v_in, rd.v_in, stage == ADJ_B2 ? d->dg.X0 : d->dg.X1, d->adj_extra,
+                              d->adj_fd_wbar, d->adj_fd_gbar, st);
+      rd.extra = d->adj_extra;
+    }
+    launch_dg_adjoint_stage(b, N, cv, stage, rd, st);
+    launch_fd_step_stage(b, N, cv, stage, rf, d->adj_fd_wbar, d->adj_fd_gbar, st);
+  }
   HIPCHK(hipGetLastError());
   return GRFFE_OK;
 }

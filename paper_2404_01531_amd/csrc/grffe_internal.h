@@ -139,6 +139,9 @@ struct grffe_domain {
   double* adj_u0 = nullptr;  // step adjoint: copy of U^n
   double* adj_fd_wbar = nullptr;  // FD adjoint: [3][10][E][m^3]
   double* adj_fd_gbar = nullptr;  // FD adjoint: [10][E][6][3][m^2]
+  double* adj_fd_ws = nullptr;    // step adjoint with FD elements: 6 FD-sized arrays
+  double* adj_u0_fd = nullptr;    // and the FD copy of U^n
+  double* adj_extra = nullptr;    // and the slab transposes of one stage (DG-sized)
   double dt_cfl = 0.0;
   double lambda_max = 0.0;
   std::vector<void*> allocs;
@@ -180,13 +183,37 @@ void launch_transfer(const KArgs& a, int N, int to_fd, const double* in, double*
 void launch_bg_derive(const KArgs& a, int N, hipStream_t s);
 void launch_lambda_max(const KArgs& a, int N, double* out, hipStream_t s);
 // launchers (kernels_adj.hip)
+// Stages of the step adjoint (the step's substeps backwards) and of the RHS adjoint.
+enum AdjStage { ADJ_A3 = 0, ADJ_B1 = 1, ADJ_B2 = 2, ADJ_B3 = 3, ADJ_RHS = 4 };
+
+// Adjoint registers of one representation ([9][E][P] each, P = n^3 on DG, m^3 on FD).
+struct AdjBufs {
+  const double* mu;      // adjoint of U^{n+1} (input of the step adjoint), or lambda of the RHS adjoint
+  double* un_bar;        // adjoint of U^n (output)
+  double* a_bar;         // adjoint of the accumulator
+  double* s1_bar;        // adjoint of S_stiff(U_1)
+  double* s2_bar;        // adjoint of S_stiff(U_2)
+  double* v_in;          // vector the transposed explicit operator is applied to (read by neighbours)
+  double* v_out;         // the next stage's vector
+  double* w;             // vector the transposed stiff source is applied to (pointwise)
+  const double* extra;   // DG only, nullable: adjoint contributions of the ghost slabs at this stage
+  int parts;             // RHS adjoint: GRFFE_PART_* of lambda
+};
+
 void launch_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar, int parts,
                         hipStream_t s);
+void launch_dg_adjoint_stage(const KArgs& a, int N, bool curved, int stage, const AdjBufs& b, hipStream_t s);
 void launch_step_adjoint(const KArgs& a, int N, bool curved, const double* mu, double* lam, double* ws,
                          hipStream_t s);
 // launchers (kernels_fd_adj.hip)
 void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar,
                            const double* lam_dg, double* ubar_dg, int parts, double* wbar, double* gbar,
                            hipStream_t s);
+// step adjoint with FD elements: the couplings and the flux adjoint of one stage
+// (V vectors v_fd, v_dg; slab transposes added to extra_dg), then the FD cells' stage
+void launch_fd_step_coupling(const KArgs& a, int N, bool curved, const double* v_fd, const double* v_dg,
+                             const double* x_dg, double* extra_dg, double* wbar, double* gbar, hipStream_t s);
+void launch_fd_step_stage(const KArgs& a, int N, bool curved, int stage, const AdjBufs& r, double* wbar,
+                          double* gbar, hipStream_t s);
 
 }  // namespace grffe

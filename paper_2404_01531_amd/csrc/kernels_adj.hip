@@ -28,34 +28,6 @@
 
 namespace grffe {
 
-enum AdjStage { ADJ_A3 = 0, ADJ_B1 = 1, ADJ_B2 = 2, ADJ_B3 = 3, ADJ_RHS = 4 };
-
-// U_1, U_2 of the implicit pre-stages from U^n (as in the forward step).
-__device__ inline void pre_stages(const double* Un, const Metric& M, const KArgs& a, double dt, double* U1,
-                                  double* U2, double* S1) {
-  const double h = dt * IMEX_A;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) U1[v] = Un[v];
-  implicit_solve(U1, M, a.eta, a.kpsi, a.kphi, h);
-  source_stiff(U1, M, a.eta, a.kpsi, a.kphi, S1);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) U2[v] = Un[v] - dt * IMEX_A * S1[v];
-  implicit_solve(U2, M, a.eta, a.kpsi, a.kphi, h);
-}
-
-// Adjoint buffers ([9][E][n^3] each).
-struct AdjBufs {
-  const double* mu;  // adjoint of U^{n+1} (input of the step adjoint), or lambda of the RHS adjoint
-  double* un_bar;    // adjoint of U^n (output)
-  double* a_bar;     // adjoint of the accumulator
-  double* s1_bar;    // adjoint of S_stiff(U_1)
-  double* s2_bar;    // adjoint of S_stiff(U_2)
-  double* v_in;      // vector the transposed explicit operator is applied to (read by neighbours)
-  double* v_out;     // the next stage's vector
-  double* w;         // vector the transposed stiff source is applied to (pointwise)
-  int parts;         // RHS adjoint: GRFFE_PART_* of lambda
-};
-
 // Element-wise transposed filter of the nine fields held in sZ (LDS, [9][nn]) at
 // node p: returns (F^T x F^T x F^T) Z at p.  All threads of the block must call it.
 template <int N>
@@ -277,16 +249,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adjoint(KArgs a, AdjBufs b)
     load9(b.mu, a.E, nn, e, p, Z);
     if (a.filter_on) filter_transpose<N>(sF, sV, p, act, Z);
     if (!act) return;
-    double V[NV], S2b[NV];
-    for (int v = 0; v < NV; ++v) {
-      V[v] = (2.0 / 3.0) * dt * Z[v];
-      S2b[v] = dt / 6.0 * Z[v];
-    }
-    store9(b.un_bar, a.E, nn, e, p, Z);
-    store9(b.a_bar, a.E, nn, e, p, Z);
-    store9(b.s2_bar, a.E, nn, e, p, S2b);
-    store9(b.v_out, a.E, nn, e, p, V);
-    store9(b.w, a.E, nn, e, p, V);
+    adj_a3_tail(b, a.E, nn, e, p, dt, Z);
     return;
   }
   // stage value the transposed operator is taken at
@@ -297,62 +260,22 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adjoint(KArgs a, AdjBufs b)
   double W[NV], ub[NV];
   load9(b.w, a.E, nn, e, p, W);
   operator_vjp<N, CURVED>(a, b, e, p, act, X, M, W, true, true, sV, sD, ub);
-  double unb[NV];
-  load9(b.un_bar, a.E, nn, e, p, unb);
+  if (b.extra && act) {
+    // the transposed ghost slabs read by FD neighbours at this stage
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] += b.extra[((size_t)v * a.E + e) * nn + p];
+  }
   if (STAGE == ADJ_B3 || STAGE == ADJ_B2) {
     // X = solve(Phi(Y)): Y_bar = Phi^T (I - h S'(X))^-T X_bar
     double Z[NV];
     if (act) solve_vjp(X, M, a, h, ub, Z);
     if (a.filter_on) filter_transpose<N>(sF, sV, p, act, Z);
     if (!act) return;
-    double Ab[NV];
-    load9(b.a_bar, a.E, nn, e, p, Ab);
-    for (int v = 0; v < NV; ++v) unb[v] += Z[v];
-    store9(b.un_bar, a.E, nn, e, p, unb);
-    double V[NV], Wn[NV];
-    if (STAGE == ADJ_B3) {
-      // Y2 = U^n + (A + dt L(U3))/4 + dt (b S1 + e S2 + c3 S(U3)),  A' = (A + dt L(U3))/6 + dt S(U3)/6
-      const double c3 = 0.5 - IMEX_B - IMEX_E - IMEX_A;
-      double S1b[NV], S2b[NV];
-      load9(b.s2_bar, a.E, nn, e, p, S2b);
-      for (int v = 0; v < NV; ++v) {
-        const double inc = 0.25 * Z[v] + Ab[v] / 6.0;
-        Wn[v] = c3 * dt * Z[v] + dt / 6.0 * Ab[v];
-        V[v] = dt * inc;
-        Ab[v] = inc;
-        S1b[v] = IMEX_B * dt * Z[v];
-        S2b[v] += IMEX_E * dt * Z[v];
-      }
-      store9(b.a_bar, a.E, nn, e, p, Ab);
-      store9(b.s1_bar, a.E, nn, e, p, S1b);
-      store9(b.s2_bar, a.E, nn, e, p, S2b);
-    } else {
-      // Y1 = U^n + dt L(U2) + dt (1 - a) S(U2),  A = dt L(U2);  S2 = S(U2)
-      double S2b[NV];
-      load9(b.s2_bar, a.E, nn, e, p, S2b);
-      for (int v = 0; v < NV; ++v) {
-        V[v] = dt * (Z[v] + Ab[v]);
-        Wn[v] = (1.0 - IMEX_A) * dt * Z[v] + S2b[v];
-      }
-    }
-    store9(b.v_out, a.E, nn, e, p, V);
-    store9(b.w, a.E, nn, e, p, Wn);
+    adj_b_tail<STAGE>(b, a.E, nn, e, p, dt, Z);
     return;
   }
-  // ADJ_B1: U2 = solve(U^n - a dt S1), S1 = S(U1), U1 = solve(U^n)
   if (!act) return;
-  double Y[NV], S1b[NV], U1b[NV], Yn[NV];
-  solve_vjp(X, M, a, h, ub, Y);
-  load9(b.s1_bar, a.E, nn, e, p, S1b);
-  for (int v = 0; v < NV; ++v) {
-    unb[v] += Y[v];
-    S1b[v] -= IMEX_A * dt * Y[v];
-    U1b[v] = 0.0;
-  }
-  stiff_vjp(U1, M, a, S1b, U1b);
-  solve_vjp(U1, M, a, h, U1b, Yn);
-  for (int v = 0; v < NV; ++v) unb[v] += Yn[v];
-  store9(b.un_bar, a.E, nn, e, p, unb);
+  adj_b1_tail(a, b, a.E, nn, e, p, M, dt, X, U1, ub);
 }
 
 template <int N, bool CURVED>
@@ -376,6 +299,11 @@ static void launch_adj_c(const KArgs& a, const AdjBufs& b, int N, int stage, hip
     case 6: launch_adj_t<6, CURVED>(a, b, stage, s); break;
     default: launch_adj_t<7, CURVED>(a, b, stage, s); break;
   }
+}
+
+void launch_dg_adjoint_stage(const KArgs& a, int N, bool curved, int stage, const AdjBufs& b, hipStream_t s) {
+  if (curved) launch_adj_c<true>(a, b, N, stage, s);
+  else launch_adj_c<false>(a, b, N, stage, s);
 }
 
 void launch_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar, int parts,

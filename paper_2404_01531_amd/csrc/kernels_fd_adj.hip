@@ -96,6 +96,7 @@ struct FdAdj {
   double* ubar;          // [9][E][m^3] output (accumulated)
   const double* lam_dg;  // [9][E][n^3] adjoint input of the DG elements
   double* ubar_dg;       // [9][E][n^3] output of the DG elements (accumulated)
+  const double* x_dg;    // [9][E][n^3] the DG values the ghost slabs were projected from
   double* wbar;          // [3][10][E][m^3] per-direction adjoints of the transported cell values
   double* gbar;          // [10][E][6][3][m^2] adjoints of ghost cells, per face and layer
   int parts;
@@ -302,108 +303,159 @@ __global__ __launch_bounds__(256) void k_fd_adj_flux(KArgs a, FdAdj b) {
   }
 }
 
-// Per FD cell: the adjoint with respect to U of the cell, from the three directions'
-// transported-component adjoints, the ghost adjoints the neighbours wrote for this
-// cell (or, at a physical boundary, this element's own ghosts through the
-// no-incoming-Poynting state), the current's gradient and the sources.
+// At FD cell p of element e:  ub = (dL_ex/dX)^T V + (dS_stiff/dX)^T W, with X the
+// cell's value (the stage value staged in w_fd).  The explicit part gathers the
+// three directions' transported-component adjoints, the ghost adjoints the FD
+// neighbours wrote for this cell (or, at a physical boundary, this element's own
+// ghosts through the no-incoming-Poynting state; a DG neighbour reads this cell
+// through its R-trace, whose transpose is already in wbar), the current's gradient
+// and the sources; use_v / use_w switch the two parts off.
 template <int N, bool CURVED>
-__global__ __launch_bounds__(256) void k_fd_adj_gather(KArgs a, FdAdj b) {
+__device__ inline void fd_cell_vjp(const KArgs& a, const FdAdj& b, int e, int p, const double* X, const Metric& M,
+                                   const double* V, bool use_v, const double* W, bool use_w, double* ub) {
   using Dm = Dims<N>;
   constexpr int m = Dm::m, mm = Dm::mm;
   constexpr int NR = NV + 1;
+  const int ci[3] = {p % m, (p / m) % m, p / (m * m)};
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ub[v] = 0.0;
+  double wJ[3] = {0.0, 0.0, 0.0};
+  if (use_v) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ub[v] += b.wbar[(((size_t)d * NR + v) * a.E + e) * mm + p];
+      wJ[d] += b.wbar[(((size_t)d * NR + NV) * a.E + e) * mm + p];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+      const int tt = ci[t1ax] + m * ci[t2ax];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int l = s ? (m - 1 - ci[d]) : ci[d];
+        if (l > 2) continue;
+        const int f = 2 * d + s;
+        const int o = a.nbr[e * 6 + f];
+        if (o >= 0 && a.rep0[o] == 0) continue;  // a DG neighbour reads the R-trace
+        if (o >= 0) {
+          // the FD neighbour's ghost layer l on its face towards us is this cell
+          const int fo = f ^ 1;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            const double g = b.gbar[((((size_t)k * a.E + o) * 6 + fo) * 3 + l) * (m * m) + tt];
+            if (k < NV) ub[k] += g;
+            else wJ[d] += g;
+          }
+        } else if (l == 0) {
+          // own ghosts: the no-incoming-Poynting state of this cell in all three layers
+          double G10[NR];
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            G10[k] = 0.0;
+#pragma unroll
+            for (int ll = 0; ll < 3; ++ll)
+              G10[k] += b.gbar[((((size_t)k * a.E + e) * 6 + f) * 3 + ll) * (m * m) + tt];
+          }
+          double Y[NV], gY[NV];
+          const double side = s ? 1.0 : -1.0;
+          boundary_state(d, side, X, M, Y);
+          double El[3], Bl[3];
+          lower3(M, X, El);
+          lower3(M, X + 3, Bl);
+          const int j1 = (d + 1) % 3, k1 = (d + 2) % 3;
+          const bool inward = side * (El[j1] * Bl[k1] - El[k1] * Bl[j1]) < 0.0;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) gY[v] = G10[v];
+          double cj[3] = {0.0, 0.0, 0.0};
+          cj[d] = G10[NV];
+          current_vjp(Y, M, a.eta, cj, cj, gY);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const bool keep = (v < 3) ? !inward : (v != 6 && v != 7);
+            if (keep) ub[v] += gY[v];
+          }
+        }
+      }
+    }
+  }
+  // the transported current J~^d of the cell, the explicit and the stiff sources
+  double wa[3], wb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    wa[i] = wJ[i] - (use_v ? V[i] : 0.0);
+    wb[i] = wJ[i] - (use_w ? W[i] : 0.0);
+  }
+  current_vjp(X, M, a.eta, wa, wb, ub);
+  if (use_v) {
+    MetricDeriv Dv;
+    load_deriv<CURVED>(a.bg_fd, a.E, mm, e, p, Dv);
+    source_lin_vjp<CURVED>(M, Dv, V, ub);
+  }
+  if (use_w) {
+    ub[6] += -M.alpha * a.kpsi * W[6];
+    ub[7] += -M.alpha * a.kphi * W[7];
+  }
+}
+
+// Right-hand side adjoint of the FD cells: ubar += (dL/dU)^T lambda.
+template <int N, bool CURVED>
+__global__ __launch_bounds__(256) void k_fd_adj_gather(KArgs a, FdAdj b) {
+  constexpr int mm = Dims<N>::mm;
   constexpr int BPE = (mm + 255) / 256;
   const int items = a.fd_count[a.sub] * BPE;
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     const int e = a.fd_list[item / BPE];
     const int p = (item % BPE) * 256 + threadIdx.x;
     if (p >= mm) continue;
-    const int ci[3] = {p % m, (p / m) % m, p / (m * m)};
     Metric M;
     load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
-    double U[NV], lam[NV], ub[NV];
-    load9(a.fd.Un, a.E, mm, e, p, U);
+    double X[NV], lam[NV], ub[NV];
+    load9(a.w_fd, a.E, mm, e, p, X);
     load9(b.lam, a.E, mm, e, p, lam);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ub[v] = 0.0;
-    double wJ[3] = {0.0, 0.0, 0.0};
-    if (b.parts & 1) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) ub[v] += b.wbar[(((size_t)d * NR + v) * a.E + e) * mm + p];
-        wJ[d] += b.wbar[(((size_t)d * NR + NV) * a.E + e) * mm + p];
-      }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
-        const int tt = ci[t1ax] + m * ci[t2ax];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const int l = s ? (m - 1 - ci[d]) : ci[d];
-          if (l > 2) continue;
-          const int f = 2 * d + s;
-          const int o = a.nbr[e * 6 + f];
-          if (o >= 0 && a.rep0[o] == 0) continue;  // a DG neighbour reads the R-trace
-          if (o >= 0) {
-            // the FD neighbour's ghost layer l on its face towards us is this cell
-            const int fo = f ^ 1;
-#pragma unroll
-            for (int k = 0; k < NR; ++k) {
-              const double g = b.gbar[((((size_t)k * a.E + o) * 6 + fo) * 3 + l) * (m * m) + tt];
-              if (k < NV) ub[k] += g;
-              else wJ[d] += g;
-            }
-          } else if (l == 0) {
-            // own ghosts: the no-incoming-Poynting state of this cell in all three layers
-            double G10[NR];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) {
-              G10[k] = 0.0;
-#pragma unroll
-              for (int ll = 0; ll < 3; ++ll)
-                G10[k] += b.gbar[((((size_t)k * a.E + e) * 6 + f) * 3 + ll) * (m * m) + tt];
-            }
-            double Y[NV], gY[NV];
-            const double side = s ? 1.0 : -1.0;
-            boundary_state(d, side, U, M, Y);
-            double El[3], Bl[3];
-            lower3(M, U, El);
-            lower3(M, U + 3, Bl);
-            const int j1 = (d + 1) % 3, k1 = (d + 2) % 3;
-            const bool inward = side * (El[j1] * Bl[k1] - El[k1] * Bl[j1]) < 0.0;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) gY[v] = G10[v];
-            double cj[3] = {0.0, 0.0, 0.0};
-            cj[d] = G10[NV];
-            current_vjp(Y, M, a.eta, cj, cj, gY);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-              const bool keep = (v < 3) ? !inward : (v != 6 && v != 7);
-              if (keep) ub[v] += gY[v];
-            }
-          }
-        }
-      }
-    }
-    // the transported current J~^d of the cell, the explicit and the stiff sources
-    double wa[3], wb[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      wa[i] = wJ[i] - ((b.parts & 1) ? lam[i] : 0.0);
-      wb[i] = wJ[i] - ((b.parts & 2) ? lam[i] : 0.0);
-    }
-    current_vjp(U, M, a.eta, wa, wb, ub);
-    if (b.parts & 1) {
-      MetricDeriv Dv;
-      load_deriv<CURVED>(a.bg_fd, a.E, mm, e, p, Dv);
-      source_lin_vjp<CURVED>(M, Dv, lam, ub);
-    }
-    if (b.parts & 2) {
-      ub[6] += -M.alpha * a.kpsi * lam[6];
-      ub[7] += -M.alpha * a.kphi * lam[7];
-    }
+    fd_cell_vjp<N, CURVED>(a, b, e, p, X, M, lam, (b.parts & 1) != 0, lam, (b.parts & 2) != 0, ub);
 #pragma unroll
     for (int v = 0; v < NV; ++v) b.ubar[((size_t)v * a.E + e) * mm + p] += ub[v];
+  }
+}
+
+// One stage of the step adjoint on the FD cells (the DG nodes' kernel without the
+// filter): the explicit operator is transposed at the stage value staged in w_fd,
+// applied to the stage's vector V = r.v_in and the stiff vector r.w, then the
+// implicit solve and the stage combination are transposed.
+template <int N, bool CURVED, int STAGE>
+__global__ __launch_bounds__(256) void k_fd_adj_stage(KArgs a, FdAdj b, AdjBufs r) {
+  constexpr int mm = Dims<N>::mm;
+  constexpr int BPE = (mm + 255) / 256;
+  const int items = a.fd_count[a.sub] * BPE;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int e = a.fd_list[item / BPE];
+    const int p = (item % BPE) * 256 + threadIdx.x;
+    if (p >= mm) continue;
+    const double dt = dt_of(a, e);
+    if (STAGE == ADJ_A3) {
+      double Z[NV];
+      load9(r.mu, a.E, mm, e, p, Z);
+      adj_a3_tail(r, a.E, mm, e, p, dt, Z);
+      continue;
+    }
+    Metric M;
+    load_metric<CURVED>(a.bg_fd, a.E, mm, e, p, M);
+    double X[NV], V[NV], W[NV], ub[NV];
+    load9(a.w_fd, a.E, mm, e, p, X);
+    load9(r.v_in, a.E, mm, e, p, V);
+    load9(r.w, a.E, mm, e, p, W);
+    fd_cell_vjp<N, CURVED>(a, b, e, p, X, M, V, true, W, true, ub);
+    if (STAGE == ADJ_B3 || STAGE == ADJ_B2) {
+      double Z[NV];
+      solve_vjp(X, M, a, dt * IMEX_A, ub, Z);
+      adj_b_tail<STAGE>(r, a.E, mm, e, p, dt, Z);
+    } else {
+      double Un[NV], U1[NV], U2[NV], S1[NV];
+      load9(a.fd.Un, a.E, mm, e, p, Un);
+      pre_stages(Un, M, a, dt, U1, U2, S1);
+      adj_b1_tail(a, r, a.E, mm, e, p, M, dt, X, U1, ub);
+    }
   }
 }
 
@@ -564,25 +616,62 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adj_slab(KArgs a, FdAdj b) 
   Metric M;
   load_metric<CURVED>(a.bg_dg, a.E, nn, g, p, M);
   double X[NV];
-  load9(a.dg.Un, a.E, nn, g, p, X);
+  load9(b.x_dg, a.E, nn, g, p, X);
   current_vjp(X, M, a.eta, Jb, Jb, Wb);
 #pragma unroll
   for (int v = 0; v < NV; ++v) b.ubar_dg[((size_t)v * a.E + g) * nn + p] += Wb[v];
 }
 
 template <int N, bool CURVED>
+static void fd_coupling_t(const KArgs& a, const FdAdj& b, hipStream_t s) {
+  constexpr int m = Dims<N>::m;
+  const size_t flux_items = (size_t)a.E * 3 * m;
+  launch_kernel(k_fd_adj_flux<N, CURVED>, dim3((unsigned)(flux_items < 2048 ? flux_items : 2048)), dim3(256), s, a,
+                b);
+  launch_kernel(k_fd_adj_trace<N, CURVED>, dim3((unsigned)(a.E < 2048 ? a.E : 2048)), dim3(256), s, a, b);
+  launch_kernel(k_dg_adj_slab<N, CURVED>, dim3(a.E), dim3(Dims<N>::tpb), s, a, b);
+}
+
+template <int N, bool CURVED>
 static void fd_rhs_adjoint_t(const KArgs& a, const FdAdj& b, hipStream_t s) {
-  constexpr int m = Dims<N>::m, mm = Dims<N>::mm;
-  const size_t flux_items = (size_t)a.E * 3 * m, cell_items = (size_t)a.E * ((mm + 255) / 256);
-  if (b.parts & 1) {
-    launch_kernel(k_fd_adj_flux<N, CURVED>, dim3((unsigned)(flux_items < 2048 ? flux_items : 2048)), dim3(256), s,
-                  a, b);
-    launch_kernel(k_fd_adj_trace<N, CURVED>, dim3((unsigned)(a.E < 2048 ? a.E : 2048)), dim3(256), s, a, b);
-  }
+  constexpr int mm = Dims<N>::mm;
+  const size_t cell_items = (size_t)a.E * ((mm + 255) / 256);
+  if (b.parts & 1) fd_coupling_t<N, CURVED>(a, b, s);
   launch_kernel(k_fd_adj_gather<N, CURVED>, dim3((unsigned)(cell_items < 2048 ? cell_items : 2048)), dim3(256), s,
                 a, b);
-  if (b.parts & 1) launch_kernel(k_dg_adj_slab<N, CURVED>, dim3(a.E), dim3(Dims<N>::tpb), s, a, b);
 }
+
+template <int N, bool CURVED>
+static void fd_stage_adjoint_t(const KArgs& a, const FdAdj& b, const AdjBufs& r, int stage, hipStream_t s) {
+  constexpr int mm = Dims<N>::mm;
+  const size_t cell_items = (size_t)a.E * ((mm + 255) / 256);
+  const dim3 grid((unsigned)(cell_items < 2048 ? cell_items : 2048)), block(256);
+  switch (stage) {
+    case ADJ_A3: launch_kernel(k_fd_adj_stage<N, CURVED, ADJ_A3>, grid, block, s, a, b, r); break;
+    case ADJ_B3: launch_kernel(k_fd_adj_stage<N, CURVED, ADJ_B3>, grid, block, s, a, b, r); break;
+    case ADJ_B2: launch_kernel(k_fd_adj_stage<N, CURVED, ADJ_B2>, grid, block, s, a, b, r); break;
+    default: launch_kernel(k_fd_adj_stage<N, CURVED, ADJ_B1>, grid, block, s, a, b, r); break;
+  }
+}
+
+#define GRFFE_FD_ADJ_DISPATCH(CALL)                 \
+  if (curved) {                                     \
+    switch (N) {                                    \
+      case 3: CALL(3, true); break;                 \
+      case 4: CALL(4, true); break;                 \
+      case 5: CALL(5, true); break;                 \
+      case 6: CALL(6, true); break;                 \
+      default: CALL(7, true); break;                \
+    }                                               \
+  } else {                                          \
+    switch (N) {                                    \
+      case 3: CALL(3, false); break;                \
+      case 4: CALL(4, false); break;                \
+      case 5: CALL(5, false); break;                \
+      case 6: CALL(6, false); break;                \
+      default: CALL(7, false); break;               \
+    }                                               \
+  }
 
 void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam, double* ubar,
                            const double* lam_dg, double* ubar_dg, int parts, double* wbar, double* gbar,
@@ -592,26 +681,39 @@ void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam
   b.ubar = ubar;
   b.lam_dg = lam_dg;
   b.ubar_dg = ubar_dg;
+  b.x_dg = a.dg.Un;
   b.wbar = wbar;
   b.gbar = gbar;
   b.parts = parts;
-  if (curved) {
-    switch (N) {
-      case 3: fd_rhs_adjoint_t<3, true>(a, b, s); break;
-      case 4: fd_rhs_adjoint_t<4, true>(a, b, s); break;
-      case 5: fd_rhs_adjoint_t<5, true>(a, b, s); break;
-      case 6: fd_rhs_adjoint_t<6, true>(a, b, s); break;
-      default: fd_rhs_adjoint_t<7, true>(a, b, s); break;
-    }
-  } else {
-    switch (N) {
-      case 3: fd_rhs_adjoint_t<3, false>(a, b, s); break;
-      case 4: fd_rhs_adjoint_t<4, false>(a, b, s); break;
-      case 5: fd_rhs_adjoint_t<5, false>(a, b, s); break;
-      case 6: fd_rhs_adjoint_t<6, false>(a, b, s); break;
-      default: fd_rhs_adjoint_t<7, false>(a, b, s); break;
-    }
-  }
+#define CALL(NN, CV) fd_rhs_adjoint_t<NN, CV>(a, b, s)
+  GRFFE_FD_ADJ_DISPATCH(CALL)
+#undef CALL
+}
+
+void launch_fd_step_coupling(const KArgs& a, int N, bool curved, const double* v_fd, const double* v_dg,
+                             const double* x_dg, double* extra_dg, double* wbar, double* gbar, hipStream_t s) {
+  FdAdj b{};
+  b.lam = v_fd;
+  b.lam_dg = v_dg;
+  b.ubar_dg = extra_dg;
+  b.x_dg = x_dg;
+  b.wbar = wbar;
+  b.gbar = gbar;
+  b.parts = 3;
+#define CALL(NN, CV) fd_coupling_t<NN, CV>(a, b, s)
+  GRFFE_FD_ADJ_DISPATCH(CALL)
+#undef CALL
+}
+
+void launch_fd_step_stage(const KArgs& a, int N, bool curved, int stage, const AdjBufs& r, double* wbar,
+                          double* gbar, hipStream_t s) {
+  FdAdj b{};
+  b.wbar = wbar;
+  b.gbar = gbar;
+  b.parts = 3;
+#define CALL(NN, CV) fd_stage_adjoint_t<NN, CV>(a, b, r, stage, s)
+  GRFFE_FD_ADJ_DISPATCH(CALL)
+#undef CALL
 }
 
 }  // namespace grffe

@@ -93,6 +93,7 @@ def lib():
     L.grffe_timing_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
     L.grffe_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
     L.grffe_step_adjoint.argtypes = [vp, vp, vp, vp, dbl, vp]
+    L.grffe_step_adjoint_frozen.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp]
     pvp = ctypes.POINTER(vp)
     L.grffe_batch_create.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(Params), pvp, vp, pvp]
     L.grffe_batch_destroy.argtypes = [vp]
@@ -110,7 +111,7 @@ def lib():
                  "grffe_timing_read", "grffe_batch_create", "grffe_batch_destroy", "grffe_batch_size",
                  "grffe_batch_init_from_fd", "grffe_batch_get_state", "grffe_batch_set_state",
                  "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step", "grffe_rhs_adjoint",
-                 "grffe_step_adjoint"):
+                 "grffe_step_adjoint", "grffe_step_adjoint_frozen"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -277,6 +278,19 @@ class Domain:
         lam = torch.empty_like(lam_next)
         _check(lib().grffe_step_adjoint(self._h, _ptr(u_dg), _ptr(lam_next), _ptr(lam), float(dt), _stream()))
         return lam
+
+    def step_adjoint_frozen(self, dg, fd, rep, mu_dg, mu_fd, dt=0.0):
+        """(lam_dg, lam_fd) = (dU^{n+1}/dU^n)^T (mu_dg, mu_fd) for one step from (dg, fd)
+        with the representation held at rep (see grffe_step_adjoint_frozen); the
+        entries of elements in the other representation are zero."""
+        import torch
+        self._check_state(dg, fd, rep)
+        self._check_state(mu_dg, mu_fd, None)
+        lam_dg = torch.zeros_like(mu_dg)
+        lam_fd = torch.zeros_like(mu_fd)
+        _check(lib().grffe_step_adjoint_frozen(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _ptr(mu_dg), _ptr(mu_fd),
+                                               _ptr(lam_dg), _ptr(lam_fd), float(dt), _stream()))
+        return lam_dg, lam_fd
 
     def tci(self, dg, fd, rep):
         import torch

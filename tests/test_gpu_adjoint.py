@@ -328,6 +328,136 @@ def _step_case(w, params, u, label, rng, dt=None):
     assert _rel(lhs, rhs_g) <= TOL, label
 
 
+def _frozen_step_case(w, params, dg, fd, label, rng, all_fd=False, tol=TOL_FD):
+    """Dot-product check of grffe_step_adjoint_frozen: one step with the
+    representation held fixed (forced partition), DG and FD elements side by side
+    (or every live element on FD).  The DG and FD parts of <lam, delta> can cancel,
+    so the difference is measured against |<lam_dg, delta_dg>| + |<lam_fd, delta_fd>|.
+    The driver coupling eta is kept moderate: with eta = 1e6 the rounding of the
+    stiff stage values is amplified by 1/eps and the Richardson differences needed by
+    the WENO weights are no longer resolved."""
+    torch = _torch()
+    params = dict(params, hybrid=2)
+    odom, ldom, _ = make_pair(w, params)
+    E = odom.E
+    act = odom.active
+    rep = np.ones(E, np.int64) if all_fd else (rng.random(E) < 0.5).astype(np.int64)
+    if not all_fd:
+        rep[np.nonzero(act)[0][:2]] = (DG, FD)
+    rep[~act] = DG
+    on_dg = act & (rep == DG)
+    on_fd = act & (rep == FD)
+    dg = dg.copy()
+    fd = fd.copy()
+    dg[:, ~on_dg] = 0.0
+    fd[:, ~on_fd] = 0.0
+    mu_d = rng.standard_normal(dg.shape)
+    mu_f = rng.standard_normal(fd.shape)
+    mu_d[:, ~on_dg] = 0.0
+    mu_f[:, ~on_fd] = 0.0
+    scale = np.maximum(np.abs(dg).max(axis=(1, 2, 3, 4)), np.abs(fd).max(axis=(1, 2, 3, 4)))[:, None, None, None, None]
+    del_d = rng.standard_normal(dg.shape) * scale
+    del_f = rng.standard_normal(fd.shape) * scale
+    del_d[:, ~on_dg] = 0.0
+    del_f[:, ~on_fd] = 0.0
+    dt = odom.dt()
+    rep_t = torch.from_numpy(rep.astype(np.int32)).cuda()
+    ld, lf = ldom.step_adjoint_frozen(to_dev(dg), to_dev(fd), rep_t, to_dev(mu_d), to_dev(mu_f), dt)
+    ld = ld.cpu().numpy().reshape(dg.shape)
+    lf = lf.cpu().numpy().reshape(fd.shape)
+    assert not ld[:, ~on_dg].any() and not lf[:, ~on_fd].any()
+    part_d, part_f = float((ld * del_d).sum()), float((lf * del_f).sum())
+    lhs = part_d + part_f
+    scale = abs(part_d) + abs(part_f)
+
+    def ddir(step):
+        def D(eps):
+            pd, pf = step(dg + eps * del_d, fd + eps * del_f)
+            md, mf = step(dg - eps * del_d, fd - eps * del_f)
+            return float(((mu_d * (pd - md)).sum() + (mu_f * (pf - mf)).sum()) / (2 * eps))
+        return (4.0 * D(2e-9) - D(4e-9)) / 3.0
+
+    def oracle_step(a, b):
+        st = OS.step(odom, OS.State(a, b, rep.copy()), dt)
+        assert np.array_equal(st.rep, rep)
+        return st.dg, st.fd
+
+    def lib_step(a, b):
+        ldom.set_state(to_dev(a), to_dev(b), rep_t)
+        ldom.step(1, dt)
+        gd, gf, gr = ldom.get_state()
+        assert np.array_equal(gr.cpu().numpy(), rep)
+        return gd.cpu().numpy().reshape(dg.shape), gf.cpu().numpy().reshape(fd.shape)
+
+    rhs_o = ddir(oracle_step)
+    rhs_g = ddir(lib_step)
+    err_o, err_g = abs(lhs - rhs_o) / scale, abs(lhs - rhs_g) / scale
+    _say(f"frozen step adjoint {label} ({int(on_dg.sum())} DG, {int(on_fd.sum())} FD): <lam,d> {lhs:.12e} "
+         f"(DG part {part_d:.6e}, FD part {part_f:.6e})  oracle FD {rhs_o:.12e} (err {err_o:.1e})  "
+         f"library FD {rhs_g:.12e} (err {err_g:.1e})")
+    assert err_o <= tol, label
+    assert err_g <= tol, label
+
+
+def test_frozen_step_adjoint_mixed_flat():
+    _torch()
+    w = dict(I.workload("wave", n_elem=(3, 2, 2)), kind="wave")
+    rng = np.random.default_rng(71)
+    odom, _, _ = make_pair(w)
+    _frozen_step_case(w, dict(eta=300.0, cfl=w["cfl"]), _wave_state(odom, w, rng), _fd_state(odom, w, rng, 1e-4),
+                      "mixed wave 3x2x2 P5", rng)
+
+
+def test_frozen_step_adjoint_all_fd_outflow():
+    _torch()
+    w = dict(n_elem=(3, 2, 1), lower=(-1.0, -0.5, -0.25), upper=(1.0, 0.75, 0.5), degree=3, bc=(1, 1, 0, 0, 1, 1),
+             curved=False, kind="wave")
+    rng = np.random.default_rng(72)
+    odom, _, _ = make_pair(w)
+    _frozen_step_case(w, dict(eta=50.0, cfl=0.25), _wave_state(odom, w, rng), _fd_state(odom, w, rng, 1e-4),
+                      "all-FD ragged P3 outflow", rng, all_fd=True)
+
+
+def test_frozen_step_adjoint_mixed_outflow_no_filter():
+    _torch()
+    w = dict(n_elem=(2, 2, 2), lower=(-1.0, -1.0, -1.0), upper=(1.0, 1.0, 1.0), degree=4, bc=(1, 1, 0, 0, 1, 1),
+             curved=False, kind="wave")
+    rng = np.random.default_rng(73)
+    odom, _, _ = make_pair(w)
+    _frozen_step_case(w, dict(eta=300.0, cfl=0.25, filter_on=0), _wave_state(odom, w, rng),
+                      _fd_state(odom, w, rng, 1e-4), "mixed P4 outflow, no filter", rng)
+
+
+def test_frozen_step_adjoint_mixed_kerr_schild():
+    _torch()
+    w = I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3)
+    rng = np.random.default_rng(74)
+    odom, _, _ = make_pair(w)
+    with np.errstate(all="ignore"):
+        dg, fd = curved_state(odom, w, rng)
+    dg += 1e-4 * rng.standard_normal(dg.shape)
+    fd += 1e-4 * rng.standard_normal(fd.shape)
+    _frozen_step_case(w, dict(eta=300.0, cfl=w["cfl"]), dg, fd, "mixed kerr-schild 4^3 P5", rng)
+
+
+def test_frozen_step_adjoint_all_dg_matches_dg_step_adjoint():
+    torch = _torch()
+    w = I.workload("wave")
+    rng = np.random.default_rng(75)
+    odom, ldom, _ = make_pair(w, dict(eta=w["eta"], cfl=w["cfl"], hybrid=2))
+    u = _wave_state(odom, w, rng)
+    mu = rng.standard_normal(u.shape)
+    dt = odom.dt()
+    fd0 = torch.zeros(ldom.fd_shape(), dtype=torch.float64, device="cuda")
+    rep = torch.zeros(ldom.E, dtype=torch.int32, device="cuda")
+    ld, lf = ldom.step_adjoint_frozen(to_dev(u), fd0, rep, to_dev(mu), fd0, dt)
+    ref = ldom.step_adjoint(to_dev(u), to_dev(mu), dt)
+    err = float((ld - ref).abs().max() / ref.abs().max())
+    _say(f"frozen step adjoint, all DG, against the DG step adjoint: max rel diff {err:.1e}")
+    assert err <= 1e-13
+    assert not lf.any()
+
+
 def test_step_adjoint_wave():
     _torch()
     w = I.workload("wave")
