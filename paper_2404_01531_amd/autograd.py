@@ -1,4 +1,4 @@
-"""torch.autograd wrapper of the all-DG IMEX step and its adjoint.
+"""torch.autograd wrappers of the IMEX step and its adjoint.
 
 GRFFEStep.apply(u0, dom, n_steps, dt, checkpoint_every) advances the DG state u0
 ((9, E, (N+1)^3) float64 on the device) by n_steps steps of `dom` (a Domain
@@ -8,6 +8,11 @@ pass keeps the state every `checkpoint_every` steps; the backward pass recompute
 each segment from its checkpoint, keeping the segment's step-start states, and
 runs the library's step adjoint back through them.  Every step and adjoint runs
 in the HIP library; this module only orders the calls and holds the checkpoints.
+
+GRFFEStepFrozen.apply(u_dg, u_fd, rep, dom, n_steps, dt, checkpoint_every) does
+the same for a state of DG and FD elements whose representation is held at rep
+(a Domain created with hybrid = HYBRID_FORCED: no indicator, no switching), with
+the frozen-representation step adjoint.
 """
 from __future__ import annotations
 
@@ -60,3 +65,57 @@ class GRFFEStep(torch.autograd.Function):
             for u in reversed(starts):
                 lam = ctx.dom.step_adjoint(u, lam, ctx.dt)
         return lam, None, None, None, None
+
+
+def _advance_frozen(dom, dg, fd, rep, n, dt):
+    starts = []
+    dom.set_state(dg.contiguous(), fd.contiguous(), rep)
+    for _ in range(n):
+        g, f, _ = dom.get_state()
+        starts.append((g, f))
+        dom.step(1, dt)
+    return starts
+
+
+class GRFFEStepFrozen(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u_dg, u_fd, rep, dom, n_steps, dt=0.0, checkpoint_every=20):
+        if dom.params.hybrid != grffe.HYBRID_FORCED:
+            raise grffe.GrffeError("GRFFEStepFrozen differentiates steps with the representation held fixed: "
+                                   "create the domain with hybrid = 2")
+        every = max(1, int(checkpoint_every))
+        dt = float(dt) if dt and dt > 0 else dom.dt()
+        rep = rep.detach().to(torch.int32).contiguous()
+        ckpts = []
+        g, f = u_dg.detach().contiguous(), u_fd.detach().contiguous()
+        done = 0
+        while done < n_steps:
+            k = min(every, n_steps - done)
+            ckpts.append((g.clone(), f.clone(), k))
+            dom.set_state(g, f, rep)
+            dom.step(k, dt)
+            g, f, _ = dom.get_state()
+            done += k
+        ctx.dom, ctx.dt, ctx.rep, ctx.ckpts = dom, dt, rep, ckpts
+        # each element's state lives in its own representation; the entries of the
+        # other one (the library's DG view of an FD element, and the unused FD
+        # entries of a DG element) are returned as zeros
+        on_fd = (rep == 1).view(1, -1, 1)
+        return torch.where(on_fd, torch.zeros_like(g), g), torch.where(on_fd, f, torch.zeros_like(f))
+
+    @staticmethod
+    def backward(ctx, grad_dg, grad_fd):
+        dom = ctx.dom
+        lam_dg = grad_dg.contiguous().clone() if grad_dg is not None else torch.zeros(
+            dom.dg_shape(), dtype=torch.float64, device="cuda")
+        lam_fd = grad_fd.contiguous().clone() if grad_fd is not None else torch.zeros(
+            dom.fd_shape(), dtype=torch.float64, device="cuda")
+        # only the entries of each element's own representation carry state
+        on_fd = (ctx.rep == 1).view(1, -1, 1)
+        lam_dg = torch.where(on_fd, torch.zeros_like(lam_dg), lam_dg)
+        lam_fd = torch.where(on_fd, lam_fd, torch.zeros_like(lam_fd))
+        for g0, f0, k in reversed(ctx.ckpts):
+            starts = _advance_frozen(dom, g0, f0, ctx.rep, k, ctx.dt)
+            for g, f in reversed(starts):
+                lam_dg, lam_fd = dom.step_adjoint_frozen(g, f, ctx.rep, lam_dg, lam_fd, ctx.dt)
+        return lam_dg, lam_fd, None, None, None, None, None

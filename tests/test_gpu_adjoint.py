@@ -521,6 +521,62 @@ def test_autograd_checkpointed_objective():
     assert _rel(an, fd) <= TOL
 
 
+def test_autograd_frozen_representation_checkpointed():
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd.autograd import GRFFEStepFrozen
+    w = dict(n_elem=(2, 2, 2), lower=(-1.0, -1.0, -1.0), upper=(1.0, 1.0, 1.0), degree=3, bc=(1, 1, 0, 0, 1, 1),
+             curved=False, kind="wave")
+    rng = np.random.default_rng(76)
+    odom, _, _ = make_pair(w)
+    dg0 = _wave_state(odom, w, rng)
+    fd0 = _fd_state(odom, w, rng, 1e-4)
+    E = odom.E
+    rep = np.array([0, 1, 1, 0, 1, 0, 0, 1], np.int32)
+    on_fd = rep == 1
+    dg0[:, on_fd] = 0.0
+    fd0[:, ~on_fd] = 0.0
+    p = grffe.default_params(eta=300.0, cfl=0.25, hybrid=2)
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], params=p)
+    rep_t = torch.from_numpy(rep).cuda()
+    wd = torch.from_numpy(rng.standard_normal(dg0.shape).reshape(9, E, -1)).cuda()
+    wf = torch.from_numpy(rng.standard_normal(fd0.shape).reshape(9, E, -1)).cuda()
+    nsteps = 7
+    dt = dom.dt()
+
+    def objective(a, b, every):
+        gN, fN = GRFFEStepFrozen.apply(a, b, rep_t, dom, nsteps, dt, every)
+        return (wd * gN).sum() + (wf * fN).sum()
+
+    a = to_dev(dg0).requires_grad_(True)
+    b = to_dev(fd0).requires_grad_(True)
+    objective(a, b, 3).backward()
+    ga, gb = a.grad.detach().clone(), b.grad.detach().clone()
+    a.grad = b.grad = None
+    objective(a, b, 1).backward()
+    assert torch.equal(ga, a.grad) and torch.equal(gb, b.grad), "checkpoint interval changed the gradient"
+    scale = max(np.abs(dg0).max(), np.abs(fd0).max())
+    dd = rng.standard_normal(dg0.shape) * scale
+    df = rng.standard_normal(fd0.shape) * scale
+    dd[:, on_fd] = 0.0
+    df[:, ~on_fd] = 0.0
+
+    def D(eps):
+        with torch.no_grad():
+            jp = float(objective(to_dev(dg0 + eps * dd), to_dev(fd0 + eps * df), 3))
+            jm = float(objective(to_dev(dg0 - eps * dd), to_dev(fd0 - eps * df), 3))
+        return (jp - jm) / (2 * eps)
+
+    fd = (4.0 * D(2e-9) - D(4e-9)) / 3.0
+    part_d = float((ga.cpu().numpy().reshape(dd.shape) * dd).sum())
+    part_f = float((gb.cpu().numpy().reshape(df.shape) * df).sum())
+    an = part_d + part_f
+    err = abs(an - fd) / (abs(part_d) + abs(part_f))
+    _say(f"autograd, representation frozen, {nsteps} steps (checkpoints every 3): <grad,d> {an:.12e} "
+         f"(DG {part_d:.6e}, FD {part_f:.6e})  FD {fd:.12e}  err {err:.1e}")
+    assert err <= TOL_FD
+
+
 def test_adjoint_rejects_mixed_precision_and_clamp():
     torch = _torch()
     from paper_2404_01531_amd import grffe
