@@ -272,68 +272,184 @@ def run_batch(steps, warmup, precision, use_graph=True):
             "hbm_GBps_dg_state": (nodes * sum(DG_BYTES_PER_NODE.values())) * steps / secs / 1e9}
 
 
-def run_adjoint(steps=200, every=20):
-    """All-DG Kerr-Schild black hole, 8^3 P5 elements on [-40,40]^3: forward steps,
-    one-step adjoints and the checkpointed gradient of a linear functional of the end
-    state, timed against the forward run."""
+def run_adjoint(steps=200, every=20, check_steps=10):
+    """The adjoint workload: Kerr-Schild black hole (a = 0.9), [-40,40]^3 with 8^3
+    DG-P5 elements (all DG, 8 excised), initial field with four seeded parameters
+    (B0, tilt, dipole amplitude, dipole offset from the spin axis); objective the
+    outgoing Poynting flux through r = 20 integrated over the steps; its gradient
+    with respect to the parameters through the checkpointed step adjoint, timed
+    against the forward run.  The gradient is checked by central differences of the
+    objective over `check_steps` steps: over the full horizon the objective crosses
+    many flips of the boundary state's inward/outward switch (it is piecewise
+    smooth in the parameters), and differences at any step size straddle some."""
+    import torch
+
+    from paper_2404_01531_amd import inputs as I
+    from paper_2404_01531_amd.poynting import AdjointWorkload, time_integral, time_integral_gradient
+    w = I.workload("kerr_schild", n_elem=(8, 8, 8))
+    aw = AdjointWorkload(w)
+    params = I.adjoint_parameters()
+    u0 = aw.initial(params)
+    du = aw.initial_derivatives(params)
+    time_integral(aw.dom, u0, 2, aw.dt, aw.L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi = time_integral(aw.dom, u0, steps, aw.dt, aw.L)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    # one step adjoint against one forward step
+    lam = torch.ones_like(u0)
+    aw.dom.step_adjoint(u0, lam, aw.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        lam = aw.dom.step_adjoint(u0, lam, aw.dt)
+    torch.cuda.synchronize()
+    t_adj1 = (time.perf_counter() - t0) / 20
+    t0 = time.perf_counter()
+    phi_g, lam0 = time_integral_gradient(aw.dom, u0, steps, aw.dt, every, aw.L)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    grad = {k: float((lam0 * du[k]).sum()) for k in aw.PARAMS}
+    _, lam_c = time_integral_gradient(aw.dom, u0, check_steps, aw.dt, every, aw.L)
+    check = {}
+    for k in aw.PARAMS:
+        g = float((lam_c * du[k]).sum())
+        row = {"adjoint": g}
+        errs = []
+        for rel in (1e-4, 1e-5, 1e-6):
+            h = rel * max(1.0, abs(params[k]))
+            fd = (aw.phi(dict(params, **{k: params[k] + h}), check_steps)
+                  - aw.phi(dict(params, **{k: params[k] - h}), check_steps)) / (2 * h)
+            row[f"fd_rel_step_{rel:g}"] = fd
+            errs.append(abs(g - fd) / max(abs(fd), 1e-300))
+        row["best_rel_err"] = min(errs)
+        check[k] = row
+    aw.close()
+    return {"workload": f"Kerr-Schild a=0.9, [-40,40]^3, 8^3 elements DG-P5 (all DG), {int(aw.exc.sum())} excised; "
+                        f"Phi = sum_n dt * (outgoing Poynting flux through r=20, 32x64 points) over {steps} steps; "
+                        f"gradient w.r.t. (B0, tilt, dipole amplitude, dipole offset), checkpoints every {every}",
+            "dtype": "f64", "parameters": params, "phi": phi, "phi_from_gradient_pass": phi_g,
+            "forward_ms_per_step": t_fwd * 1e3 / steps,
+            "step_adjoint_ms": t_adj1 * 1e3,
+            "step_adjoint_over_forward": t_adj1 / (t_fwd / steps),
+            "gradient_ms_total": t_grad * 1e3,
+            "gradient_over_forward": t_grad / t_fwd,
+            "gradient": grad,
+            "gradient_check_steps": check_steps,
+            "gradient_check": check,
+            "gradient_check_note": "central differences of the objective at three relative steps; the objective is "
+                                   "piecewise smooth (the boundary state's inward/outward switch flips at isolated "
+                                   "parameter values), so a step whose window holds a flip disagrees with every "
+                                   "other step and with the adjoint"}
+
+
+def run_forced_fractions(steps, warmup, fractions=(0.0, 0.1, 0.2, 0.5, 1.0)):
+    """The controlled experiment of the paper's performance section on the benchmark
+    sheet (8^3 P5 elements): the partition is forced (no indicator, no rollback) with
+    the elements of lowest y on FD, a fraction x of them, and the step's wall-clock
+    time is compared with the all-FD run; the ideal speedup 1 / (x + (1 - x)/f) uses
+    the measured all-DG / all-FD ratio f."""
     import numpy as np
     import torch
 
     from paper_2404_01531_amd import grffe
     from paper_2404_01531_amd import inputs as I
-    from paper_2404_01531_amd.autograd import GRFFEStep
-    w = I.workload("kerr_schild", n_elem=(8, 8, 8))
+    w = I.workload("sheet")
     N = w["degree"]
+    E = int(np.prod(w["n_elem"]))
+    n3, m3 = (N + 1) ** 3, (2 * N + 1) ** 3
     x, y, z = _dg_nodes(w)
-    with np.errstate(all="ignore"):
-        bg = I.background(w, x, y, z)
-        u = I.initial_data(w, x, y, z)
-    exc = I.excision_mask(w).astype(bool)
-    E, n3 = int(np.prod(w["n_elem"])), (N + 1) ** 3
-    bg = bg.reshape(26, E, n3)
-    u = u.reshape(9, E, n3)
-    bg[:, exc] = 0.0
-    bg[0, exc] = bg[4, exc] = bg[7, exc] = bg[9, exc] = 1.0
-    u[:, exc] = 0.0
-    p = grffe.default_params(eta=w["eta"], cfl=w["cfl"], hybrid=grffe.HYBRID_DG_ONLY)
-    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p,
-                       bg=torch.from_numpy(np.ascontiguousarray(bg)).cuda(), excised=exc.astype(np.uint8))
+    u_dg = torch.from_numpy(np.ascontiguousarray(I.initial_data(w, x, y, z).reshape(9, E, n3))).cuda()
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], N)
+    u_fd = torch.from_numpy(np.ascontiguousarray(I.initial_data(w, xf, yf, zf).reshape(9, E, m3))).cuda()
+    nx, ny, nz = w["n_elem"]
+    iy = (np.arange(E) // nx) % ny
+    order = np.lexsort((np.arange(E), iy))  # y-major: the lowest-y elements first
+    p = grffe.default_params(eta=w["eta"], cfl=w["cfl"], hybrid=grffe.HYBRID_FORCED)
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p)
     dt = dom.dt()
-    u0 = torch.from_numpy(np.ascontiguousarray(u)).cuda()
-    wt = torch.from_numpy(np.random.default_rng(1005).standard_normal(u.shape)).cuda()
-    wt[:, torch.from_numpy(exc).cuda()] = 0.0
-    # forward only
-    GRFFEStep.apply(u0, dom, 2, dt, every)
+    rows = []
+    for frac in fractions:
+        rep = np.zeros(E, np.int32)
+        rep[order[:int(round(frac * E))]] = 1
+        dom.set_state(u_dg, u_fd, torch.from_numpy(rep).cuda())
+        secs = _time_steps(lambda k: dom.step(k, dt), steps, warmup)
+        n_fd = int(rep.sum())
+        pts = (E - n_fd) * n3 + n_fd * m3
+        rows.append({"fd_fraction": n_fd / E, "fd_elements": n_fd, "ms_per_step": secs * 1e3 / steps,
+                     "G_updates_per_s": pts * 3 * steps / secs / 1e9})
+    t_fd = rows[-1]["ms_per_step"]
+    f = t_fd / rows[0]["ms_per_step"]
+    for r in rows:
+        r["speedup_vs_all_fd"] = t_fd / r["ms_per_step"]
+        r["ideal_speedup"] = 1.0 / (r["fd_fraction"] + (1.0 - r["fd_fraction"]) / f)
+    dom.close()
+    return {"workload": "current sheet 8^3 DG-P5 elements, partition forced with the lowest-y elements on FD "
+                        "(the paper's controlled DG/FD experiment, fp64)",
+            "dg_over_fd_speedup_f": f, "rows": rows,
+            "paper_context": "one CPU core: f = 9.6 (108K vs 69K zone-cycles/s per core), 3.3x (ideal 5.2x) at 10% "
+                             "FD, 2.6x (ideal 3.5x) at 20% FD"}
+
+
+def run_adjoint_frozen(steps=40, every=20):
+    """The benchmark's current sheet, 8^3 P5 elements, with the start-up DG/FD
+    partition held fixed (forced mode): forward steps, one-step adjoints through DG
+    and FD elements and their coupling, and the checkpointed gradient of a linear
+    functional of the end state, timed against the forward run."""
+    import numpy as np
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    from paper_2404_01531_amd.autograd import GRFFEStepFrozen
+    w = I.workload("sheet")
+    N = w["degree"]
+    p0 = grffe.default_params(eta=w["eta"], cfl=w["cfl"])
+    d0 = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p0)
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], N)
+    d0.init_from_fd(torch.from_numpy(I.initial_data(w, xf, yf, zf).reshape(9, d0.E, -1)).cuda())
+    dg, fd, rep = d0.get_state()
+    dg, fd, rep = dg.clone(), fd.clone(), rep.clone()
+    d0.close()
+    p = grffe.default_params(eta=w["eta"], cfl=w["cfl"], hybrid=grffe.HYBRID_FORCED)
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p)
+    dt = dom.dt()
+    gen = np.random.default_rng(1006)
+    wd = torch.from_numpy(gen.standard_normal(tuple(dg.shape))).cuda()
+    wf = torch.from_numpy(gen.standard_normal(tuple(fd.shape))).cuda()
+    GRFFEStepFrozen.apply(dg, fd, rep, dom, 2, dt, every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.no_grad():
-        GRFFEStep.apply(u0, dom, steps, dt, every)
+        GRFFEStepFrozen.apply(dg, fd, rep, dom, steps, dt, every)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
-    # one-step adjoints
-    lam = wt.clone()
-    dom.step_adjoint(u0, lam, dt)
+    ld, lf = dom.step_adjoint_frozen(dg, fd, rep, wd, wf, dt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(20):
-        lam = dom.step_adjoint(u0, lam, dt)
+    for _ in range(10):
+        ld, lf = dom.step_adjoint_frozen(dg, fd, rep, ld, lf, dt)
     torch.cuda.synchronize()
-    t_adj1 = (time.perf_counter() - t0) / 20
-    # checkpointed gradient of J = <wt, U_N>
-    uu = u0.clone().requires_grad_(True)
+    t_adj1 = (time.perf_counter() - t0) / 10
+    a = dg.clone().requires_grad_(True)
+    b = fd.clone().requires_grad_(True)
     t0 = time.perf_counter()
-    J = (wt * GRFFEStep.apply(uu, dom, steps, dt, every)).sum()
-    J.backward()
+    gN, fN = GRFFEStepFrozen.apply(a, b, rep, dom, steps, dt, every)
+    ((wd * gN).sum() + (wf * fN).sum()).backward()
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t0
-    return {"workload": f"Kerr-Schild a=0.9, [-40,40]^3, 8^3 elements DG-P5 (all DG), {int(exc.sum())} excised, "
-                        f"J = <w, U_N> after {steps} steps, checkpoints every {every}",
-            "dtype": "f64", "forward_ms_per_step": t_fwd * 1e3 / steps,
-            "step_adjoint_ms": t_adj1 * 1e3,
-            "step_adjoint_over_forward": t_adj1 / (t_fwd / steps),
-            "gradient_ms_total": t_grad * 1e3,
-            "gradient_over_forward": t_grad / t_fwd,
-            "grad_norm": float(uu.grad.norm())}
+    n_fd = int((rep == 1).sum())
+    out = {"workload": f"current sheet, 8^3 elements DG-P5, start-up partition frozen ({n_fd} FD elements), "
+                       f"J = <w, U_N> after {steps} steps, checkpoints every {every}",
+           "dtype": "f64", "forward_ms_per_step": t_fwd * 1e3 / steps,
+           "step_adjoint_ms": t_adj1 * 1e3,
+           "step_adjoint_over_forward": t_adj1 / (t_fwd / steps),
+           "gradient_ms_total": t_grad * 1e3,
+           "gradient_over_forward": t_grad / t_fwd,
+           "grad_norm": float(torch.sqrt((a.grad ** 2).sum() + (b.grad ** 2).sum()))}
+    dom.close()
+    return out
 
 
 def main():
@@ -425,7 +541,9 @@ def main():
                          ("kerr_schild_16^3_mixed", lambda: run_kerr_schild(args.extra_steps, 2, 1)),
                          ("batch_64_fp64", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0)),
                          ("batch_64_mixed", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 1)),
-                         ("adjoint_kerr_schild_8^3", lambda: run_adjoint())):
+                         ("forced_fd_fraction_sheet_8^3", lambda: run_forced_fractions(args.extra_steps, 2)),
+                         ("adjoint_poynting_kerr_schild_8^3", lambda: run_adjoint()),
+                         ("adjoint_sheet_8^3_frozen_partition", lambda: run_adjoint_frozen())):
             print(f"# extra workload {name}", file=sys.stderr, flush=True)
             ex[name] = fn()
             print(f"#   {json.dumps(ex[name])[:300]}", file=sys.stderr, flush=True)

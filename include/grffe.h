@@ -127,7 +127,8 @@ int grffe_destroy(grffe_domain* dom);
 int grffe_init_from_fd(grffe_domain* dom, const double* u_fd, const uint8_t* forced, void* stream);
 
 /* Copy the state in / out.  dg [9][E][n^3], fd [9][E][m^3] and rep [E] are device
- * pointers; on set, only the representation named by rep is read per element. */
+ * pointers; on set, only the representation named by rep is read per element (all
+ * three non-NULL); on get, a NULL pointer skips that part. */
 int grffe_set_state(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep, void* stream);
 int grffe_get_state(grffe_domain* dom, double* dg, double* fd, int32_t* rep, void* stream);
 

@@ -246,6 +246,13 @@ class Domain:
         _check(lib().grffe_get_state(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _stream()))
         return dg, fd, rep
 
+    def get_dg(self):
+        """The DG state array alone (grffe_get_state with the FD and flag outputs NULL)."""
+        import torch
+        dg = torch.empty(self.dg_shape(), dtype=torch.float64, device="cuda")
+        _check(lib().grffe_get_state(self._h, _ptr(dg), None, None, _stream()))
+        return dg
+
     def rhs(self, dg, fd, rep, parts=PART_ALL):
         import torch
         self._check_state(dg, fd, rep)

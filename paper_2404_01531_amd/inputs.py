@@ -254,6 +254,66 @@ def kerr_schild_uniform_field(x, y, z, M=1.0, a=0.0, B0=1.0):
     return U
 
 
+def _dipole_field(x, y, z, m, d, delta):
+    """B~ = curl A of the regularised dipole A = m (-y, x - d, 0) / (R^2 + delta^2)^(3/2),
+    R^2 = (x - d)^2 + y^2 + z^2, written out (complex-step safe):
+    B~ = 3 m s u ((x - d) z, y z, 0) + m s (0, 0, 2 - 3 ((x - d)^2 + y^2) u),
+    s = (R^2 + delta^2)^(-3/2), u = 1 / (R^2 + delta^2).  Divergence-free exactly."""
+    xp = x - d
+    u = 1.0 / (xp * xp + y * y + z * z + delta * delta)
+    s = u * np.sqrt(u)
+    return [3.0 * m * s * u * xp * z, 3.0 * m * s * u * y * z, m * s * (2.0 - 3.0 * (xp * xp + y * y) * u)]
+
+
+def kerr_schild_parametrised_field(x, y, z, M, a, B0, tilt, m, d, delta=0.1):
+    """Initial data of the adjoint workload: a uniform field of strength B0 tilted by
+    `tilt` about the x axis, B~ = B0 (0, -sin tilt, cos tilt), plus the regularised
+    dipole of amplitude m centred at (d, 0, 0) (off the spin axis by d); E~ from the
+    ideal condition (plasma at rest in Kerr-Schild coordinates) and q~ = d_i E~^i."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    z = np.asarray(z, np.float64)
+
+    def bt(x_, y_, z_):
+        dip = _dipole_field(x_, y_, z_, m, d, delta)
+        zero = 0.0 * x_
+        return [dip[0] + zero, dip[1] - B0 * np.sin(tilt) + zero, dip[2] + B0 * np.cos(tilt) + zero]
+
+    def et(x_, y_, z_):
+        return _ideal_e_tilde(x_, y_, z_, M, a, bt(x_, y_, z_))
+
+    Bt = bt(x, y, z)
+    Et = et(x, y, z)
+    der = _cstep(et, x, y, z)
+    U = np.zeros((9,) + x.shape)
+    for i in range(3):
+        U[i] = np.real(Et[i])
+        U[3 + i] = np.real(Bt[i])
+    U[8] = der[0][0] + der[1][1] + der[2][2]
+    return U
+
+
+def adjoint_parameters(seed=1005):
+    """The four seeded initial-field parameters of the adjoint workload:
+    B0 ~ 1 + 0.1 N(0,1), tilt ~ U(0, 0.3), dipole amplitude m ~ U(20, 60), offset d ~ U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    return dict(B0=1.0 + 0.1 * rng.standard_normal(), tilt=0.3 * rng.random(), m=20.0 + 40.0 * rng.random(),
+                d=-1.0 + 2.0 * rng.random())
+
+
+def sphere_quadrature(R=20.0, n_theta=32, n_phi=64):
+    """Points (3, n_theta * n_phi) on the Euclidean sphere of radius R and weights of
+    the surface integral: Gauss-Legendre in cos(theta), uniform midpoints in phi."""
+    ct, wt = np.polynomial.legendre.leggauss(n_theta)
+    ph = 2.0 * np.pi * (np.arange(n_phi) + 0.5) / n_phi
+    st = np.sqrt(1.0 - ct * ct)
+    X = R * np.outer(st, np.cos(ph)).ravel()
+    Y = R * np.outer(st, np.sin(ph)).ravel()
+    Z = R * np.outer(ct, np.ones(n_phi)).ravel()
+    W = np.outer(wt, np.full(n_phi, 2.0 * np.pi / n_phi)).ravel() * R * R
+    return np.stack([X, Y, Z]), W
+
+
 # ----------------------------------------------------------------------------
 # named workloads (shapes of the paper's flat-space wave tests and
 # black-hole magnetospheres)

@@ -1,0 +1,117 @@
+"""The adjoint workload's inputs and objective, on the CPU: the parametrised
+Kerr-Schild initial field (dipole = curl of its potential, divergence-free), the
+sphere quadrature, and the Poynting-flux functional on DG states against closed
+forms and a direct evaluation at the quadrature points."""
+import numpy as np
+import pytest
+
+from paper_2404_01531_amd import inputs as I
+
+
+def test_dipole_field_is_the_curl_of_its_potential_and_divergence_free():
+    rng = np.random.default_rng(3)
+    x, y, z = (rng.uniform(-30, 30, 50) for _ in range(3))
+    m, d, delta = 31.5, 0.28, 0.1
+
+    def A(x_, y_, z_):
+        xp = x_ - d
+        s = (xp * xp + y_ * y_ + z_ * z_ + delta * delta) ** -1.5
+        return [-m * y_ * s, m * xp * s, 0.0 * x_]
+
+    dA = I._cstep(A, x, y, z)
+    curl = [dA[1][2] - dA[2][1], dA[2][0] - dA[0][2], dA[0][1] - dA[1][0]]
+    B = I._dipole_field(x, y, z, m, d, delta)
+    scale = max(np.abs(b).max() for b in B)
+    for c, b in zip(curl, B):
+        assert np.abs(c - b).max() <= 1e-13 * scale
+    dB = I._cstep(lambda a, b_, c: I._dipole_field(a, b_, c, m, d, delta), x, y, z)
+    assert np.abs(dB[0][0] + dB[1][1] + dB[2][2]).max() <= 1e-13 * scale
+
+
+def test_parametrised_field_reduces_to_the_uniform_wald_like_field():
+    rng = np.random.default_rng(4)
+    x, y, z = (rng.uniform(-30, 30, 40) for _ in range(3))
+    U = I.kerr_schild_parametrised_field(x, y, z, 1.0, 0.9, B0=1.3, tilt=0.0, m=0.0, d=0.0)
+    ref = I.kerr_schild_uniform_field(x, y, z, 1.0, 0.9, 1.3)
+    assert np.abs(U - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_sphere_quadrature_area_and_second_moments():
+    R = 20.0
+    pts, w = I.sphere_quadrature(R, 32, 64)
+    assert np.isclose(w.sum(), 4 * np.pi * R * R, rtol=1e-14)
+    assert np.allclose(np.sqrt((pts ** 2).sum(0)), R, rtol=1e-14)
+    for d in range(3):
+        assert np.isclose((w * pts[d] ** 2).sum(), 4 * np.pi * R ** 4 / 3, rtol=1e-13)
+
+
+def _nodes_state(w, fn):
+    from paper_2404_01531_amd import grffe
+    x, y, z = I.points(w["n_elem"], w["lower"], w["upper"], grffe.operator(w["degree"], 0))
+    U = fn(x, y, z)
+    E = int(np.prod(w["n_elem"]))
+    return U.reshape(9, E, -1)
+
+
+def test_poynting_flux_of_a_radial_poynting_vector_flat():
+    torch = pytest.importorskip("torch")
+    from paper_2404_01531_amd.poynting import SphereFlux
+    w = dict(n_elem=(8, 8, 8), lower=(-40.0,) * 3, upper=(40.0,) * 3, degree=3, curved=False)
+
+    def fn(x, y, z):
+        U = np.zeros((9,) + x.shape)
+        U[0], U[1] = -y, x  # E = (-y, x, 0), B = (0, 0, 1): E x B = (x, y, 0)
+        U[5] = 1.0
+        return U
+
+    u = torch.from_numpy(_nodes_state(w, fn))
+    L = SphereFlux(w, device="cpu")
+    R = 20.0
+    exact = 8.0 * np.pi * R ** 3 / 3.0
+    assert abs(float(L(u)) - exact) <= 1e-12 * exact
+
+
+def test_poynting_flux_curved_matches_direct_evaluation():
+    torch = pytest.importorskip("torch")
+    from paper_2404_01531_amd.poynting import SphereFlux
+    w = I.workload("kerr_schild", n_elem=(8, 8, 8), degree=3)
+
+    def poly(x, y, z):
+        # degree <= 3 per axis: the DG interpolation is exact
+        U = np.zeros((9,) + np.shape(x))
+        U[0] = 0.01 * (y - 0.002 * x * y * z)
+        U[1] = 0.01 * (-x + 0.001 * z ** 3)
+        U[2] = 0.003 * x * y
+        U[3] = 0.02 + 1e-4 * y * y
+        U[4] = -0.01 * z
+        U[5] = 1.0 + 1e-5 * x * y * z
+        return U
+
+    with np.errstate(all="ignore"):
+        u = torch.from_numpy(_nodes_state(w, poly))
+        L = SphereFlux(w, device="cpu")
+    got = float(L(u))
+    pts, wq = I.sphere_quadrature(20.0, 32, 64)
+    Uq = poly(*pts)
+    bg = I.background(w, *pts)
+    g = np.array([[bg[4], bg[5], bg[6]], [bg[5], bg[7], bg[8]], [bg[6], bg[8], bg[9]]])
+    sg = np.sqrt(np.linalg.det(np.moveaxis(g, -1, 0)))
+    El = np.einsum("ijq,jq->iq", g, Uq[0:3] / sg)
+    Bl = np.einsum("ijq,jq->iq", g, Uq[3:6] / sg)
+    ref = float((wq * (pts * np.cross(El, Bl, axis=0)).sum(0) / 20.0).sum())
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+
+
+def test_poynting_flux_gradient_matches_autograd():
+    torch = pytest.importorskip("torch")
+    from paper_2404_01531_amd.poynting import SphereFlux
+    w = I.workload("kerr_schild", n_elem=(8, 8, 8), degree=3)
+    rng = np.random.default_rng(9)
+    with np.errstate(all="ignore"):
+        L = SphereFlux(w, device="cpu")
+    E = int(np.prod(w["n_elem"]))
+    u = torch.from_numpy(rng.standard_normal((9, E, 64)))
+    x = u.clone().requires_grad_(True)
+    (ref,) = torch.autograd.grad(L(x), x)
+    got = L.grad(u)
+    assert torch.allclose(got, ref, rtol=0, atol=1e-13 * float(ref.abs().max()))
