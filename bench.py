@@ -435,7 +435,7 @@ def run_adjoint_frozen(steps=40, every=20):
     a = dg.clone().requires_grad_(True)
     b = fd.clone().requires_grad_(True)
     t0 = time.perf_counter()
-    gN, fN = GRFFEStepFrozen.apply(a, b, rep, dom, steps, dt, every)
+    gN, fN, _ = GRFFEStepFrozen.apply(a, b, rep, dom, steps, dt, every)
     ((wd * gN).sum() + (wf * fN).sum()).backward()
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t0

@@ -214,24 +214,32 @@ int grffe_rhs_adjoint(grffe_domain* dom, const double* dg, const double* fd, con
 int grffe_step_adjoint(grffe_domain* dom, const double* u_dg, const double* lam_next, double* lam, double dt,
                        void* stream);
 
-/* Adjoint of one IMEX-SSP3(4,3,3) step (Sec. III B) with the representation of
- * every element held at rep (the hybrid decisions frozen: no indicator, no
- * rollback, no switch back; the forward step of GRFFE_HYBRID_FORCED):
- *   (lam_dg, lam_fd) = (d U^{n+1} / d U^n)^T (mu_dg, mu_fd),
- * with U = (DG nodal values of the DG elements, FD cell values of the FD elements)
- * as in grffe_rhs_adjoint.  Every stage is transposed on both representations:
- * the DG operator and filter, the FD WENO5-Z fluxes, the P-projected ghost slabs
- * and R-traces between them (Sec. III C), the implicit solves (implicit function
- * theorem) and the stiff sources.  dg, fd, rep are U^n and its representation
- * (device, layouts of grffe_set_state); the domain re-runs the forward step from
- * them, so its state is left at U^{n+1} with that representation.  dt <= 0 selects
- * the CFL step.  lam_* may be the same buffers as mu_*; none may overlap dg or fd.
- * Entries of elements in the other representation are left untouched.  Same
+/* Adjoint of one IMEX-SSP3(4,3,3) step (Sec. III B) with the hybrid decisions
+ * (Sec. III C 1) frozen from the forward pass:
+ *   (lam_dg, lam_fd) = (d U^{n+1} / d U^n)^T (mu_dg, mu_fd).
+ * The domain re-runs the forward step from (dg, fd, rep) in its own hybrid mode and
+ * logs the representation before each substep and after the step; the adjoint
+ * then takes every element through the same path: DG or FD per substep, the
+ * rollback of an element flagged in substep k (its registers projected by P, its
+ * FD pre-stages re-derived, transposed through P^T), the switch back at the end of
+ * the step (R, transposed through R^T).  Each stage is transposed on both
+ * representations: the DG operator and filter, the FD WENO5-Z fluxes, the
+ * P-projected ghost slabs and R-traces between them (Sec. III C), the implicit
+ * solves (implicit function theorem) and the stiff sources.  The indicator itself
+ * is not differentiated (a piecewise-constant decision).
+ * U = (DG nodal values of the DG elements, FD cell values of the FD elements) as in
+ * grffe_rhs_adjoint: dg, fd, rep are U^n and its representation (device, layouts
+ * of grffe_set_state); mu_* are given in the representation after the step (the
+ * domain's rep after the call: the re-run leaves the state at U^{n+1}); lam_* are
+ * returned in rep's representation, entries of elements in the other one left
+ * untouched.  rep_log (nullable, device [5][E]) receives the representation before
+ * the step, during substeps 1-3 and after the step.  dt <= 0 selects the CFL step.
+ * lam_* may be the same buffers as mu_*; none may overlap dg or fd.  Same
  * restrictions as grffe_rhs_adjoint; the first call allocates the work space
- * (7 DG-sized and 7 FD-sized arrays besides that of grffe_rhs_adjoint). */
+ * (8 DG-sized and 10 FD-sized arrays besides that of grffe_rhs_adjoint). */
 int grffe_step_adjoint_frozen(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep,
-                              const double* mu_dg, const double* mu_fd, double* lam_dg, double* lam_fd, double dt,
-                              void* stream);
+                              const double* mu_dg, const double* mu_fd, double* lam_dg, double* lam_fd,
+                              int32_t* rep_log, double dt, void* stream);
 
 /* Batches: many independent domains advanced together, each with its own grid,
  * degree (3..7) and CFL time step (Eq. (spectre DG CFL condition) per domain).

@@ -10,9 +10,11 @@ runs the library's step adjoint back through them.  Every step and adjoint runs
 in the HIP library; this module only orders the calls and holds the checkpoints.
 
 GRFFEStepFrozen.apply(u_dg, u_fd, rep, dom, n_steps, dt, checkpoint_every) does
-the same for a state of DG and FD elements whose representation is held at rep
-(a Domain created with hybrid = HYBRID_FORCED: no indicator, no switching), with
-the frozen-representation step adjoint.
+the same for a state of DG and FD elements (rep: the representation of each), in
+the domain's hybrid mode: forced (the partition held) or adaptive (the indicator
+decides; its decisions are frozen from the forward pass and the adjoint follows
+the same rollbacks and switches).  It returns (u_dg, u_fd, rep) after the steps,
+each element's state in its own representation (the other's entries zero).
 """
 from __future__ import annotations
 
@@ -71,51 +73,51 @@ def _advance_frozen(dom, dg, fd, rep, n, dt):
     starts = []
     dom.set_state(dg.contiguous(), fd.contiguous(), rep)
     for _ in range(n):
-        g, f, _ = dom.get_state()
-        starts.append((g, f))
+        starts.append(dom.get_state())
         dom.step(1, dt)
     return starts
+
+
+def _own(dg, fd, rep):
+    """The state with the entries of each element's other representation zeroed."""
+    on_fd = (rep == 1).view(1, -1, 1)
+    return torch.where(on_fd, torch.zeros_like(dg), dg), torch.where(on_fd, fd, torch.zeros_like(fd))
 
 
 class GRFFEStepFrozen(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u_dg, u_fd, rep, dom, n_steps, dt=0.0, checkpoint_every=20):
-        if dom.params.hybrid != grffe.HYBRID_FORCED:
-            raise grffe.GrffeError("GRFFEStepFrozen differentiates steps with the representation held fixed: "
-                                   "create the domain with hybrid = 2")
+        if dom.params.hybrid not in (grffe.HYBRID_FORCED, grffe.HYBRID_ADAPTIVE):
+            raise grffe.GrffeError("GRFFEStepFrozen differentiates hybrid steps: create the domain with hybrid = 1 "
+                                   "(adaptive, decisions frozen from the forward pass) or 2 (forced partition)")
         every = max(1, int(checkpoint_every))
         dt = float(dt) if dt and dt > 0 else dom.dt()
-        rep = rep.detach().to(torch.int32).contiguous()
+        r = rep.detach().to(torch.int32).contiguous()
         ckpts = []
         g, f = u_dg.detach().contiguous(), u_fd.detach().contiguous()
         done = 0
         while done < n_steps:
             k = min(every, n_steps - done)
-            ckpts.append((g.clone(), f.clone(), k))
-            dom.set_state(g, f, rep)
+            ckpts.append((g.clone(), f.clone(), r.clone(), k))
+            dom.set_state(g, f, r)
             dom.step(k, dt)
-            g, f, _ = dom.get_state()
+            g, f, r = dom.get_state()
             done += k
-        ctx.dom, ctx.dt, ctx.rep, ctx.ckpts = dom, dt, rep, ckpts
-        # each element's state lives in its own representation; the entries of the
-        # other one (the library's DG view of an FD element, and the unused FD
-        # entries of a DG element) are returned as zeros
-        on_fd = (rep == 1).view(1, -1, 1)
-        return torch.where(on_fd, torch.zeros_like(g), g), torch.where(on_fd, f, torch.zeros_like(f))
+        ctx.dom, ctx.dt, ctx.ckpts, ctx.rep_out = dom, dt, ckpts, r
+        gz, fz = _own(g, f, r)
+        ctx.mark_non_differentiable(r)
+        return gz, fz, r
 
     @staticmethod
-    def backward(ctx, grad_dg, grad_fd):
+    def backward(ctx, grad_dg, grad_fd, _grad_rep):
         dom = ctx.dom
         lam_dg = grad_dg.contiguous().clone() if grad_dg is not None else torch.zeros(
             dom.dg_shape(), dtype=torch.float64, device="cuda")
         lam_fd = grad_fd.contiguous().clone() if grad_fd is not None else torch.zeros(
             dom.fd_shape(), dtype=torch.float64, device="cuda")
-        # only the entries of each element's own representation carry state
-        on_fd = (ctx.rep == 1).view(1, -1, 1)
-        lam_dg = torch.where(on_fd, torch.zeros_like(lam_dg), lam_dg)
-        lam_fd = torch.where(on_fd, lam_fd, torch.zeros_like(lam_fd))
-        for g0, f0, k in reversed(ctx.ckpts):
-            starts = _advance_frozen(dom, g0, f0, ctx.rep, k, ctx.dt)
-            for g, f in reversed(starts):
-                lam_dg, lam_fd = dom.step_adjoint_frozen(g, f, ctx.rep, lam_dg, lam_fd, ctx.dt)
+        lam_dg, lam_fd = _own(lam_dg, lam_fd, ctx.rep_out)
+        for g0, f0, r0, k in reversed(ctx.ckpts):
+            starts = _advance_frozen(dom, g0, f0, r0, k, ctx.dt)
+            for g, f, r in reversed(starts):
+                lam_dg, lam_fd = dom.step_adjoint_frozen(g, f, r, lam_dg, lam_fd, ctx.dt)
         return lam_dg, lam_fd, None, None, None, None, None

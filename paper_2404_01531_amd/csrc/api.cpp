@@ -665,73 +665,128 @@ extern "C" int grffe_step_adjoint(grffe_domain* d, const double* u_dg, const dou
 
 extern "C" int grffe_step_adjoint_frozen(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep,
                                          const double* mu_dg, const double* mu_fd, double* lam_dg, double* lam_fd,
-                                         double dt, void* stream) {
+                                         int32_t* rep_log, double dt, void* stream) {
   if (int rc = check_dom(d)) return rc;
   if (!dg || !fd || !rep || !mu_dg || !mu_fd || !lam_dg || !lam_fd)
     return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
   if (int rc = adjoint_supported(d)) return rc;
   if (int rc = step_adjoint_space(d, true)) return rc;
+  const size_t reg = (size_t)NV * d->E * d->nn, regf = (size_t)NV * d->E * d->mm;
+  if (!d->adj_hyb) {
+    void* p = nullptr;
+    if (int rc = dalloc(d, &p, sizeof(double) * (2 * reg + 3 * regf))) return rc;
+    d->adj_hyb = reinterpret_cast<double*>(p);
+    if (int rc = dalloc(d, &p, sizeof(int32_t) * 5 * d->E)) return rc;
+    d->adj_rep_log = reinterpret_cast<int32_t*>(p);
+  }
   hipStream_t st = S(stream);
   const int N = d->N;
   const bool cv = d->curved;
-  const size_t reg = (size_t)NV * d->E * d->nn, regf = (size_t)NV * d->E * d->mm;
-  // forward step from (dg, fd) with the representation held at rep, keeping the
-  // stage registers U_3 (X0) and U_4 (X1) of both representations
+  double* ub_dg = d->adj_hyb;         // U^n adjoints of this sweep
+  double* t_dg = d->adj_hyb + reg;    // transfer at a rollback (DG)
+  double* ub_fd = d->adj_hyb + 2 * reg;
+  double* t_fd = ub_fd + regf;
+  double* mu_fd_w = ub_fd + 2 * regf;
+  int32_t* log[5];
+  for (int k = 0; k < 5; ++k) log[k] = d->adj_rep_log + (size_t)k * d->E;
+  // forward step from (dg, fd, rep), keeping the stage registers of both
+  // representations and logging the representation before each substep (the
+  // rollbacks of an adaptive step) and after the step (the switches back)
   HIPCHK(hipMemcpyAsync(d->adj_u0, dg, sizeof(double) * reg, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(d->adj_u0_fd, fd, sizeof(double) * regf, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(d->dg.Un, dg, sizeof(double) * reg, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(d->fd.Un, fd, sizeof(double) * regf, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(d->rep, rep, sizeof(int32_t) * d->E, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(log[0], rep, sizeof(int32_t) * d->E, hipMemcpyDeviceToDevice, st));
   KArgs a = make_args(d);
-  a.hybrid = GRFFE_HYBRID_FORCED;
   if (dt > 0.0) a.dt = dt;
-  step_once(d, a, st);
+  launch_dg_prestage(a, N, cv, st);
+  const int modes[3] = {MODE_SUB1, MODE_SUB2, MODE_SUB3};
+  for (int k = 0; k < 3; ++k) {
+    run_substep(d, a, modes[k], st);
+    HIPCHK(hipMemcpyAsync(log[k + 1], d->rep, sizeof(int32_t) * d->E, hipMemcpyDeviceToDevice, st));
+  }
+  // log[k] (k = 1..3) is the representation during substep k; log[4] after the step
+  if (a.hybrid == GRFFE_HYBRID_ADAPTIVE) launch_fd_to_dg(a, N, cv, 0, st);
+  HIPCHK(hipMemcpyAsync(log[4], d->rep, sizeof(int32_t) * d->E, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipGetLastError());
-  // backward sweep: the last substep, substeps 2 and 1, then the implicit pre-stages
+  // backward sweep
   KArgs b = a;
   b.dg.Un = d->adj_u0;
   b.fd.Un = d->adj_u0_fd;
-  b.rep0 = d->rep;
   b.sub = 3;
   HIPCHK(hipMemsetAsync(d->troubled, 0, d->E, st));
-  HIPCHK(hipMemsetAsync(d->fd_count + 3, 0, sizeof(int32_t), st));
-  launch_begin_substep(b, false, st);
+  // U^n on FD of the elements rolled back during the step, as the forward made it
+  launch_adj_project_un(b, N, log[0], log[3], d->adj_u0, d->adj_u0_fd, st);
+  // the switch back: mu of those elements on FD through R^T
+  HIPCHK(hipMemcpyAsync(mu_fd_w, mu_fd, sizeof(double) * regf, hipMemcpyDeviceToDevice, st));
+  launch_adj_switch_back(b, N, log[3], log[4], mu_dg, mu_fd_w, st);
   AdjBufs rd{}, rf{};
   rd.mu = mu_dg;
-  rd.un_bar = lam_dg;
+  rd.un_bar = ub_dg;
   rd.a_bar = d->adj_ws;
   rd.s1_bar = d->adj_ws + reg;
   rd.s2_bar = d->adj_ws + 2 * reg;
   rd.w = d->adj_ws + 3 * reg;
-  rf.mu = mu_fd;
-  rf.un_bar = lam_fd;
+  rd.transfer = t_dg;
+  rf.mu = mu_fd_w;
+  rf.un_bar = ub_fd;
   rf.a_bar = d->adj_fd_ws;
   rf.s1_bar = d->adj_fd_ws + regf;
   rf.s2_bar = d->adj_fd_ws + 2 * regf;
   rf.w = d->adj_fd_ws + 3 * regf;
+  rf.transfer = t_fd;
   double* vd[2] = {d->adj_ws + 4 * reg, d->adj_ws + 5 * reg};
   double* vf[2] = {d->adj_fd_ws + 4 * regf, d->adj_fd_ws + 5 * regf};
+  // stage k transposes the operator of substep `sub` (elements read in their
+  // representation at its start, log[sub - 1], updated in log[sub]) and the
+  // combination of substep sub - 1 (representation log[sub - 1]); A3 has no
+  // operator and transposes substep 3's combination (log[3])
   const int order[4] = {ADJ_A3, ADJ_B3, ADJ_B2, ADJ_B1};
+  const int sub[4] = {3, 3, 2, 1};
   for (int k = 0; k < 4; ++k) {
     const int stage = order[k];
+    const int32_t* upd = log[sub[k]];
+    const int32_t* start = stage == ADJ_A3 ? log[3] : log[sub[k] - 1];
+    rd.rep_upd = rf.rep_upd = upd;
     rd.v_in = vd[(k + 1) % 2];
     rd.v_out = vd[k % 2];
     rf.v_in = vf[(k + 1) % 2];
     rf.v_out = vf[k % 2];
     rd.extra = nullptr;
+    {
+      // FD list: the elements updated on FD
+      KArgs bl = b;
+      bl.rep0 = const_cast<int32_t*>(upd);
+      HIPCHK(hipMemsetAsync(d->fd_count + 3, 0, sizeof(int32_t), st));
+      launch_begin_substep(bl, false, st);
+    }
+    b.rep0 = const_cast<int32_t*>(start);
+    launch_adj_flags(b, upd, st);  // rolled back in this substep (the forward's flags)
     if (stage != ADJ_A3) {
       const int mode = stage == ADJ_B3 ? MODE_SUB3 : (stage == ADJ_B2 ? MODE_SUB2 : MODE_SUB1);
-      if (stage == ADJ_B1) launch_dg_prestage(b, N, cv, st);  // X1 <- U_2 of U^n
-      launch_fd_stage(b, N, cv, mode, st);                     // the FD cells' stage values
-      launch_dg_slab(b, N, cv, mode, st);                      // the ghost slabs at the stage
+      if (stage == ADJ_B1) {
+        // X1 <- U_2 of U^n on the elements that were DG at the step start
+        KArgs bp = b;
+        bp.rep = log[0];
+        launch_dg_prestage(bp, N, cv, st);
+      }
+      launch_fd_stage(b, N, cv, mode, st);  // the FD-updated cells' stage values
+      launch_dg_slab(b, N, cv, mode, st);   // the ghost slabs at the stage
       HIPCHK(hipMemsetAsync(d->adj_extra, 0, sizeof(double) * reg, st));
       launch_fd_step_coupling(b, N, cv, rf.v_in, rd.v_in, stage == ADJ_B2 ? d->dg.X0 : d->dg.X1, d->adj_extra,
-                              d->adj_fd_wbar, d->adj_fd_gbar, st);
+                              d->adj_fd_wbar, d->adj_fd_gbar, upd, st);
       rd.extra = d->adj_extra;
     }
-    launch_dg_adjoint_stage(b, N, cv, stage, rd, st);
     launch_fd_step_stage(b, N, cv, stage, rf, d->adj_fd_wbar, d->adj_fd_gbar, st);
+    if (stage != ADJ_A3) launch_adj_rollback(b, N, cv, rd, rf, upd, t_fd, t_dg, sub[k], st);
+    launch_dg_adjoint_stage(b, N, cv, stage, rd, st);
   }
+  // the adjoint of U^n in the representation it had
+  launch_copy_rep(b, log[0], 0, d->nn, ub_dg, lam_dg, st);
+  launch_copy_rep(b, log[0], 1, d->mm, ub_fd, lam_fd, st);
+  if (rep_log)
+    HIPCHK(hipMemcpyAsync(rep_log, d->adj_rep_log, sizeof(int32_t) * 5 * d->E, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipGetLastError());
   return GRFFE_OK;
 }

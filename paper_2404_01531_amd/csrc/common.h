@@ -206,4 +206,16 @@ __device__ inline void stage_update(const Regs& r, int E, int P, int e, int p, c
   }
 }
 
+// Dispatch of a launch over the supported degrees: CALL sees the degree as the
+// compile-time constant NN.
+#define GRFFE_SWITCH_N(CALL)      \
+  switch (N) {                    \
+    case 3: { constexpr int NN = 3; CALL; } break; \
+    case 4: { constexpr int NN = 4; CALL; } break; \
+    case 5: { constexpr int NN = 5; CALL; } break; \
+    case 6: { constexpr int NN = 6; CALL; } break; \
+    default: { constexpr int NN = 7; CALL; } break; \
+  }
+
+
 }  // namespace grffe

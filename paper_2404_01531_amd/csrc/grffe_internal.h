@@ -142,6 +142,8 @@ struct grffe_domain {
   double* adj_fd_ws = nullptr;    // step adjoint with FD elements: 6 FD-sized arrays
   double* adj_u0_fd = nullptr;    // and the FD copy of U^n
   double* adj_extra = nullptr;    // and the slab transposes of one stage (DG-sized)
+  double* adj_hyb = nullptr;      // adaptive steps: U^n adjoints (DG, FD), transfers (DG, FD), mu_fd copy
+  int32_t* adj_rep_log = nullptr; // representation before each substep and after the step [5][E]
   double dt_cfl = 0.0;
   double lambda_max = 0.0;
   std::vector<void*> allocs;
@@ -197,6 +199,19 @@ struct AdjBufs {
   double* v_out;         // the next stage's vector
   double* w;             // vector the transposed stiff source is applied to (pointwise)
   const double* extra;   // DG only, nullable: adjoint contributions of the ghost slabs at this stage
+  // Step adjoint with the decisions of an adaptive step frozen (nullable: the
+  // representation does not change within the substep).  a.rep0 is the
+  // representation at the start of the substep whose operator a stage transposes
+  // (what neighbours read, and the one of the combination the stage transposes);
+  // rep_upd the one that updated each element in that substep.  An element on DG in
+  // rep0 and on FD in rep_upd was rolled back there: its DG neighbours read its DG
+  // values and its FD neighbours its ghost slab, while it was updated on FD from
+  // its projected registers.  The FD stage kernel writes the adjoint of its
+  // substep input to `transfer` (FD) and stops; the DG stage kernel takes
+  // `transfer` (DG, after P^T) and the neighbours' terms in place of its own
+  // operator adjoint.
+  const int32_t* rep_upd;
+  double* transfer;
   int parts;             // RHS adjoint: GRFFE_PART_* of lambda
 };
 
@@ -212,8 +227,19 @@ void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam
 // step adjoint with FD elements: the couplings and the flux adjoint of one stage
 // (V vectors v_fd, v_dg; slab transposes added to extra_dg), then the FD cells' stage
 void launch_fd_step_coupling(const KArgs& a, int N, bool curved, const double* v_fd, const double* v_dg,
-                             const double* x_dg, double* extra_dg, double* wbar, double* gbar, hipStream_t s);
+                             const double* x_dg, double* extra_dg, double* wbar, double* gbar,
+                             const int32_t* rep_upd, hipStream_t s);
 void launch_fd_step_stage(const KArgs& a, int N, bool curved, int stage, const AdjBufs& r, double* wbar,
                           double* gbar, hipStream_t s);
+// launchers (kernels_adj_hybrid.hip): the frozen decisions of an adaptive step
+void launch_adj_rollback(const KArgs& a, int N, bool curved, const AdjBufs& rd, const AdjBufs& rf,
+                         const int32_t* rep_upd, const double* t_fd, double* t_dg, int k, hipStream_t s);
+void launch_adj_flags(const KArgs& a, const int32_t* rep_upd, hipStream_t s);
+void launch_adj_switch_back(const KArgs& a, int N, const int32_t* rep3, const int32_t* repF, const double* mu_dg,
+                            double* mu_fd, hipStream_t s);
+void launch_adj_project_un(const KArgs& a, int N, const int32_t* rep0, const int32_t* rep3, const double* un_dg,
+                           double* un_fd, hipStream_t s);
+void launch_copy_rep(const KArgs& a, const int32_t* rep, int want, int P, const double* src, double* dst,
+                     hipStream_t s);
 
 }  // namespace grffe

@@ -57,23 +57,26 @@ __device__ inline void filter_transpose(const double* sF, double* sZ, int p, boo
 // explicit DG operator evaluated on the stage field X (own value X, metric M).
 // V is read from b.v_in for this element and its neighbours, W is given.
 // use_v / use_w switch the two parts off.  All threads of the block must call it.
+// own_v = false keeps only the neighbours' terms (the element's own operator
+// result was discarded: rolled back to FD in this substep).
 template <int N, bool CURVED>
 __device__ void operator_vjp(const KArgs& a, const AdjBufs& b, int e, int p, bool act, const double* X,
                              const Metric& M, const double* Wst, bool use_v, bool use_w, double* sV, const double* sD,
-                             double* ub) {
+                             double* ub, bool own_v = true) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn;
   const int idx[3] = {p % n, (p / n) % n, p / (n * n)};
   const int str[3] = {1, n, n * n};
+  const int32_t* upd = b.rep_upd ? b.rep_upd : a.rep0;
   double Vp[NV];
   __syncthreads();
-  if (use_v) {
+  if (use_v && own_v) {
     if (act) load9(b.v_in, a.E, nn, e, p, Vp);
-    if (act)
-      for (int v = 0; v < NV; ++v) sV[v * nn + p] = Vp[v];
   } else {
     for (int v = 0; v < NV; ++v) Vp[v] = 0.0;
   }
+  if (use_v && act)
+    for (int v = 0; v < NV; ++v) sV[v * nn + p] = Vp[v];
   __syncthreads();
   for (int v = 0; v < NV; ++v) ub[v] = 0.0;
   double G[3][NV];
@@ -126,8 +129,9 @@ __device__ void operator_vjp(const KArgs& a, const AdjBufs& b, int e, int p, boo
         bside[d] = s ? 1 : -1;
         bA[d] = s ? -0.5 * wr : 0.5 * wl;
         bI[d] = s ? 0.5 * wr * lam : 0.5 * wl * lam;
-      } else if (a.rep0[o] == 0) {
-        // the DG neighbour's face term on its opposite face uses X as exterior state
+      } else if (upd[o] == 0) {
+        // the neighbour updated on DG: its face term on its opposite face uses X as
+        // exterior state
         const double sco = 2.0 / h_of(a, o, d);
         double Vo[NV];
         load9(b.v_in, a.E, nn, o, pn, Vo);
@@ -219,6 +223,8 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adjoint(KArgs a, AdjBufs b)
   __shared__ double sF[n * n];
   const int e = blockIdx.x;
   if (!a.live[e] || a.rep0[e] != 0) return;
+  // rolled back in this stage's substep: its own operator result was discarded
+  const bool own_op = (b.rep_upd ? b.rep_upd[e] : 0) == 0;
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int p = act ? t : 0;
@@ -259,7 +265,14 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adjoint(KArgs a, AdjBufs b)
   else pre_stages(Un, M, a, dt, U1, X, S1);                    // U_2
   double W[NV], ub[NV];
   load9(b.w, a.E, nn, e, p, W);
-  operator_vjp<N, CURVED>(a, b, e, p, act, X, M, W, true, true, sV, sD, ub);
+  operator_vjp<N, CURVED>(a, b, e, p, act, X, M, W, true, own_op, sV, sD, ub, own_op);
+  if (!own_op && STAGE != ADJ_B1 && act) {
+    // the substep input's adjoint from the FD redo, through P^T
+    double T[NV];
+    load9(b.transfer, a.E, nn, e, p, T);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] += T[v];
+  }
   if (b.extra && act) {
     // the transposed ghost slabs read by FD neighbours at this stage
 #pragma unroll

@@ -838,15 +838,6 @@ __global__ __launch_bounds__(256) void k_lambda_max(KArgs a, double* out) {
 
 
 // ------------------------------------------------------------------ launchers
-#define GRFFE_SWITCH_N(CALL)      \
-  switch (N) {                    \
-    case 3: { constexpr int NN = 3; CALL; } break; \
-    case 4: { constexpr int NN = 4; CALL; } break; \
-    case 5: { constexpr int NN = 5; CALL; } break; \
-    case 6: { constexpr int NN = 6; CALL; } break; \
-    default: { constexpr int NN = 7; CALL; } break; \
-  }
-
 // Persistent grids of the list-driven kernels: enough workgroups to fill the chip,
 // never more than the largest possible number of work items.
 static dim3 list_grid(size_t max_items, int cap) {

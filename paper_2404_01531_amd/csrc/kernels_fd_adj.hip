@@ -99,6 +99,9 @@ struct FdAdj {
   const double* x_dg;    // [9][E][n^3] the DG values the ghost slabs were projected from
   double* wbar;          // [3][10][E][m^3] per-direction adjoints of the transported cell values
   double* gbar;          // [10][E][6][3][m^2] adjoints of ghost cells, per face and layer
+  // nullable: the representation that updated each element in the substep, when
+  // it differs from a.rep0 (what neighbours read) for elements rolled back in it
+  const int32_t* rep_upd;
   int parts;
 };
 
@@ -317,6 +320,7 @@ __device__ inline void fd_cell_vjp(const KArgs& a, const FdAdj& b, int e, int p,
   constexpr int m = Dm::m, mm = Dm::mm;
   constexpr int NR = NV + 1;
   const int ci[3] = {p % m, (p / m) % m, p / (m * m)};
+  const int32_t* upd = b.rep_upd ? b.rep_upd : a.rep0;
 #pragma unroll
   for (int v = 0; v < NV; ++v) ub[v] = 0.0;
   double wJ[3] = {0.0, 0.0, 0.0};
@@ -337,7 +341,10 @@ __device__ inline void fd_cell_vjp(const KArgs& a, const FdAdj& b, int e, int p,
         if (l > 2) continue;
         const int f = 2 * d + s;
         const int o = a.nbr[e * 6 + f];
-        if (o >= 0 && a.rep0[o] == 0) continue;  // a DG neighbour reads the R-trace
+        // a neighbour updated on DG read this cell through the R-trace; a neighbour
+        // updated on FD read it as a ghost only if this element was on FD at the
+        // substep start (else it read this element's ghost slab)
+        if (o >= 0 && (upd[o] == 0 || a.rep0[e] != 1)) continue;
         if (o >= 0) {
           // the FD neighbour's ghost layer l on its face towards us is this cell
           const int fo = f ^ 1;
@@ -446,6 +453,11 @@ __global__ __launch_bounds__(256) void k_fd_adj_stage(KArgs a, FdAdj b, AdjBufs 
     load9(r.v_in, a.E, mm, e, p, V);
     load9(r.w, a.E, mm, e, p, W);
     fd_cell_vjp<N, CURVED>(a, b, e, p, X, M, V, true, W, true, ub);
+    if ((STAGE == ADJ_B3 || STAGE == ADJ_B2) && a.rep0[e] == 0) {
+      // rolled back in this substep: the input came from DG through P
+      store9(r.transfer, a.E, mm, e, p, ub);
+      continue;
+    }
     if (STAGE == ADJ_B3 || STAGE == ADJ_B2) {
       double Z[NV];
       solve_vjp(X, M, a, dt * IMEX_A, ub, Z);
@@ -477,12 +489,14 @@ __global__ __launch_bounds__(256) void k_fd_adj_trace(KArgs a, FdAdj b) {
   __shared__ double s2[NR * m * m];  // [k][c2][c1]
   const int t = threadIdx.x;
   for (int q = t; q < n * m; q += 256) sR[q] = a.ops->R[q];
+  const int32_t* upd = b.rep_upd ? b.rep_upd : a.rep0;
   const int items = a.fd_count[a.sub];
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     const int e = a.fd_list[item];
+    if (a.rep0[e] != 1) continue;  // rolled back in this substep: no trace was read
     for (int f = 0; f < 6; ++f) {
       const int g = a.nbr[e * 6 + f];
-      if (g < 0 || a.rep0[g] != 0) continue;
+      if (g < 0 || upd[g] != 0) continue;
       const int d = f >> 1;
       const int fg = f ^ 1, sg = fg & 1;  // the DG element's face and side
       const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
@@ -554,10 +568,11 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adj_slab(KArgs a, FdAdj b) 
   constexpr int NR = NV + 1;
   const int g = blockIdx.x;
   if (!a.live[g] || a.rep0[g] != 0) return;
+  const int32_t* upd = b.rep_upd ? b.rep_upd : a.rep0;
   int need = 0;
   for (int f = 0; f < 6; ++f) {
     const int o = a.nbr[g * 6 + f];
-    if (o >= 0 && a.rep0[o] == 1) need |= 1 << f;
+    if (o >= 0 && upd[o] == 1) need |= 1 << f;
   }
   if (!need) return;
   __shared__ double sP[m * n];
@@ -691,8 +706,10 @@ void launch_fd_rhs_adjoint(const KArgs& a, int N, bool curved, const double* lam
 }
 
 void launch_fd_step_coupling(const KArgs& a, int N, bool curved, const double* v_fd, const double* v_dg,
-                             const double* x_dg, double* extra_dg, double* wbar, double* gbar, hipStream_t s) {
+                             const double* x_dg, double* extra_dg, double* wbar, double* gbar,
+                             const int32_t* rep_upd, hipStream_t s) {
   FdAdj b{};
+  b.rep_upd = rep_upd;
   b.lam = v_fd;
   b.lam_dg = v_dg;
   b.ubar_dg = extra_dg;
@@ -708,6 +725,7 @@ void launch_fd_step_coupling(const KArgs& a, int N, bool curved, const double* v
 void launch_fd_step_stage(const KArgs& a, int N, bool curved, int stage, const AdjBufs& r, double* wbar,
                           double* gbar, hipStream_t s) {
   FdAdj b{};
+  b.rep_upd = r.rep_upd;
   b.wbar = wbar;
   b.gbar = gbar;
   b.parts = 3;

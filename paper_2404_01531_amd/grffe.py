@@ -93,7 +93,7 @@ def lib():
     L.grffe_timing_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
     L.grffe_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
     L.grffe_step_adjoint.argtypes = [vp, vp, vp, vp, dbl, vp]
-    L.grffe_step_adjoint_frozen.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp]
+    L.grffe_step_adjoint_frozen.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp]
     pvp = ctypes.POINTER(vp)
     L.grffe_batch_create.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(Params), pvp, vp, pvp]
     L.grffe_batch_destroy.argtypes = [vp]
@@ -286,18 +286,21 @@ class Domain:
         _check(lib().grffe_step_adjoint(self._h, _ptr(u_dg), _ptr(lam_next), _ptr(lam), float(dt), _stream()))
         return lam
 
-    def step_adjoint_frozen(self, dg, fd, rep, mu_dg, mu_fd, dt=0.0):
-        """(lam_dg, lam_fd) = (dU^{n+1}/dU^n)^T (mu_dg, mu_fd) for one step from (dg, fd)
-        with the representation held at rep (see grffe_step_adjoint_frozen); the
-        entries of elements in the other representation are zero."""
+    def step_adjoint_frozen(self, dg, fd, rep, mu_dg, mu_fd, dt=0.0, with_log=False):
+        """(lam_dg, lam_fd) = (dU^{n+1}/dU^n)^T (mu_dg, mu_fd) for one step from (dg, fd, rep)
+        with the hybrid decisions of the domain's own forward re-run frozen (see
+        grffe_step_adjoint_frozen); entries of elements in the other representation
+        are zero.  with_log: also the representation log (5, E) (before the step,
+        during substeps 1-3, after the step)."""
         import torch
         self._check_state(dg, fd, rep)
         self._check_state(mu_dg, mu_fd, None)
         lam_dg = torch.zeros_like(mu_dg)
         lam_fd = torch.zeros_like(mu_fd)
+        log = torch.empty((5, self.E), dtype=torch.int32, device="cuda") if with_log else None
         _check(lib().grffe_step_adjoint_frozen(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _ptr(mu_dg), _ptr(mu_fd),
-                                               _ptr(lam_dg), _ptr(lam_fd), float(dt), _stream()))
-        return lam_dg, lam_fd
+                                               _ptr(lam_dg), _ptr(lam_fd), _ptr(log), float(dt), _stream()))
+        return (lam_dg, lam_fd, log) if with_log else (lam_dg, lam_fd)
 
     def tci(self, dg, fd, rep):
         import torch

@@ -440,6 +440,87 @@ def test_frozen_step_adjoint_mixed_kerr_schild():
     _frozen_step_case(w, dict(eta=300.0, cfl=w["cfl"]), dg, fd, "mixed kerr-schild 4^3 P5", rng)
 
 
+def test_adaptive_step_adjoint_rollback_and_switch_back():
+    """One adaptive step with its decisions frozen: the elements next to the current
+    sheet start on DG and are flagged in substep 1 (rolled back: registers projected
+    by P, FD pre-stages re-derived), elements of the smooth region start on FD and
+    switch back to DG at the end of the step (R).  The decision log must show both;
+    the dot-product identity is checked against Richardson-extrapolated differences
+    of the oracle's and the library's adaptive step, whose decisions must not change
+    under the perturbation.  Every component carries 1e-4 noise (WENO and the
+    boundary switch need it, as in the frozen-partition tests) and eta = 300."""
+    torch = _torch()
+    w = dict(I.workload("sheet", n_elem=(4, 2, 2), degree=3))
+    rng = np.random.default_rng(77)
+    params = dict(eta=300.0, cfl=w["cfl"], hybrid=1)
+    odom, ldom, _ = make_pair(w, params)
+    E = odom.E
+    x, y, z = node_coords(w)
+    dg = I.initial_data(w, x, y, z) + 1e-4 * rng.standard_normal((9,) + x.shape)
+    dg = dg.reshape(9, E, odom.n, odom.n, odom.n)
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    fd = I.initial_data(w, xf, yf, zf) + 1e-4 * rng.standard_normal((9,) + xf.shape)
+    fd = fd.reshape(9, E, odom.m, odom.m, odom.m)
+    ix = np.arange(E) % w["n_elem"][0]
+    rep = (ix == 0).astype(np.int64)  # x in [-1, -0.5]: smooth, starts on FD
+    dg[:, rep == 1] = 0.0
+    fd[:, rep == 0] = 0.0
+    rep_t = torch.from_numpy(rep.astype(np.int32)).cuda()
+    dt = odom.dt()
+    zero_d = torch.zeros(ldom.dg_shape(), dtype=torch.float64, device="cuda")
+    zero_f = torch.zeros(ldom.fd_shape(), dtype=torch.float64, device="cuda")
+    _, _, log = ldom.step_adjoint_frozen(to_dev(dg), to_dev(fd), rep_t, zero_d, zero_f, dt, with_log=True)
+    log = log.cpu().numpy()
+    flagged = [int(((log[k - 1] == 0) & (log[k] == 1)).sum()) for k in (1, 2, 3)]
+    back = int(((log[3] == 1) & (log[4] == 0)).sum())
+    _say(f"adaptive step: rolled back in substeps 1-3: {flagged}, switched back: {back}")
+    assert flagged[0] > 0 and back > 0
+    rep_end = log[4].astype(np.int64)
+    mu_d = rng.standard_normal(dg.shape)
+    mu_f = rng.standard_normal(fd.shape)
+    mu_d[:, rep_end == 1] = 0.0
+    mu_f[:, rep_end == 0] = 0.0
+    scale = np.maximum(np.abs(dg).max(axis=(1, 2, 3, 4)), np.abs(fd).max(axis=(1, 2, 3, 4)))[:, None, None, None, None]
+    del_d = rng.standard_normal(dg.shape) * scale
+    del_f = rng.standard_normal(fd.shape) * scale
+    del_d[:, rep == 1] = 0.0
+    del_f[:, rep == 0] = 0.0
+    ld, lf = ldom.step_adjoint_frozen(to_dev(dg), to_dev(fd), rep_t, to_dev(mu_d), to_dev(mu_f), dt)
+    ld = ld.cpu().numpy().reshape(dg.shape)
+    lf = lf.cpu().numpy().reshape(fd.shape)
+    assert not ld[:, rep == 1].any() and not lf[:, rep == 0].any()
+    part_d, part_f = float((ld * del_d).sum()), float((lf * del_f).sum())
+    lhs = part_d + part_f
+
+    def ddir(step):
+        def D(eps):
+            pd, pf = step(dg + eps * del_d, fd + eps * del_f)
+            md, mf = step(dg - eps * del_d, fd - eps * del_f)
+            return float(((mu_d * (pd - md)).sum() + (mu_f * (pf - mf)).sum()) / (2 * eps))
+        return (4.0 * D(2e-9) - D(4e-9)) / 3.0
+
+    def oracle_step(a, b):
+        st = OS.step(odom, OS.State(a, b, rep.copy()), dt)
+        assert np.array_equal(st.rep, rep_end), "the oracle's decisions differ"
+        return st.dg, st.fd
+
+    def lib_step(a, b):
+        ldom.set_state(to_dev(a), to_dev(b), rep_t)
+        ldom.step(1, dt)
+        gd, gf, gr = ldom.get_state()
+        assert np.array_equal(gr.cpu().numpy(), rep_end), "the decisions changed under the perturbation"
+        return gd.cpu().numpy().reshape(dg.shape), gf.cpu().numpy().reshape(fd.shape)
+
+    rhs_o = ddir(oracle_step)
+    rhs_g = ddir(lib_step)
+    sc = abs(part_d) + abs(part_f)
+    err_o, err_g = abs(lhs - rhs_o) / sc, abs(lhs - rhs_g) / sc
+    _say(f"adaptive step adjoint: <lam,d> {lhs:.12e} (DG part {part_d:.6e}, FD part {part_f:.6e})  oracle FD "
+         f"{rhs_o:.12e} (err {err_o:.1e})  library FD {rhs_g:.12e} (err {err_g:.1e})")
+    assert err_o <= TOL_FD
+    assert err_g <= TOL_FD
+
+
 def test_frozen_step_adjoint_all_dg_matches_dg_step_adjoint():
     torch = _torch()
     w = I.workload("wave")
@@ -452,6 +533,7 @@ def test_frozen_step_adjoint_all_dg_matches_dg_step_adjoint():
     rep = torch.zeros(ldom.E, dtype=torch.int32, device="cuda")
     ld, lf = ldom.step_adjoint_frozen(to_dev(u), fd0, rep, to_dev(mu), fd0, dt)
     ref = ldom.step_adjoint(to_dev(u), to_dev(mu), dt)
+    torch.cuda.synchronize()
     err = float((ld - ref).abs().max() / ref.abs().max())
     _say(f"frozen step adjoint, all DG, against the DG step adjoint: max rel diff {err:.1e}")
     assert err <= 1e-13
@@ -545,7 +627,7 @@ def test_autograd_frozen_representation_checkpointed():
     dt = dom.dt()
 
     def objective(a, b, every):
-        gN, fN = GRFFEStepFrozen.apply(a, b, rep_t, dom, nsteps, dt, every)
+        gN, fN, _ = GRFFEStepFrozen.apply(a, b, rep_t, dom, nsteps, dt, every)
         return (wd * gN).sum() + (wf * fN).sum()
 
     a = to_dev(dg0).requires_grad_(True)
