@@ -690,6 +690,75 @@ def test_poynting_objective_parameter_gradient():
     aw.close()
 
 
+def test_autograd_adaptive_checkpointed():
+    """Three adaptive steps (sheet P3: the elements at the sheet start on DG and are
+    rolled back, smooth FD elements switch back) through GRFFEStepFrozen with
+    checkpoints every 2 steps: bit-identical to checkpoints every step, and the
+    gradient of a linear functional of the end state against Richardson-extrapolated
+    differences of the objective (the decisions, and so the end representation,
+    unchanged under the perturbation)."""
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd.autograd import GRFFEStepFrozen
+    w = dict(I.workload("sheet", n_elem=(4, 2, 2), degree=3))
+    rng = np.random.default_rng(78)
+    odom, _, _ = make_pair(w)
+    E = odom.E
+    x, y, z = node_coords(w)
+    dg0 = (I.initial_data(w, x, y, z) + 1e-4 * rng.standard_normal((9,) + x.shape)).reshape(9, E, -1)
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    fd0 = (I.initial_data(w, xf, yf, zf) + 1e-4 * rng.standard_normal((9,) + xf.shape)).reshape(9, E, -1)
+    rep0 = ((np.arange(E) % w["n_elem"][0]) == 0).astype(np.int32)
+    dg0[:, rep0 == 1] = 0.0
+    fd0[:, rep0 == 0] = 0.0
+    p = grffe.default_params(eta=300.0, cfl=0.25, hybrid=grffe.HYBRID_ADAPTIVE)
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], params=p)
+    rep_t = torch.from_numpy(rep0).cuda()
+    wd = torch.from_numpy(rng.standard_normal(dg0.shape)).cuda()
+    wf = torch.from_numpy(rng.standard_normal(fd0.shape)).cuda()
+    nsteps = 3
+    dt = dom.dt()
+
+    def run(a, b, every):
+        gN, fN, rN = GRFFEStepFrozen.apply(a, b, rep_t, dom, nsteps, dt, every)
+        return (wd * gN).sum() + (wf * fN).sum(), rN
+
+    a = to_dev(dg0).requires_grad_(True)
+    b = to_dev(fd0).requires_grad_(True)
+    J, rN = run(a, b, 2)
+    J.backward()
+    ga, gb = a.grad.detach().clone(), b.grad.detach().clone()
+    a.grad = b.grad = None
+    run(a, b, 1)[0].backward()
+    assert torch.equal(ga, a.grad) and torch.equal(gb, b.grad), "checkpoint interval changed the gradient"
+    rN = rN.cpu().numpy()
+    _say(f"adaptive autograd: FD elements {int(rep0.sum())} at the start, {int(rN.sum())} after {nsteps} steps")
+    scale = max(np.abs(dg0).max(), np.abs(fd0).max())
+    dd = rng.standard_normal(dg0.shape) * scale
+    df = rng.standard_normal(fd0.shape) * scale
+    dd[:, rep0 == 1] = 0.0
+    df[:, rep0 == 0] = 0.0
+
+    def D(eps):
+        vals = []
+        for sgn in (1.0, -1.0):
+            with torch.no_grad():
+                Jv, r = run(to_dev(dg0 + sgn * eps * dd), to_dev(fd0 + sgn * eps * df), 2)
+            assert np.array_equal(r.cpu().numpy(), rN), "the decisions changed under the perturbation"
+            vals.append(float(Jv))
+        return (vals[0] - vals[1]) / (2 * eps)
+
+    fd = (4.0 * D(2e-9) - D(4e-9)) / 3.0
+    part_d = float((ga.cpu().numpy() * dd).sum())
+    part_f = float((gb.cpu().numpy() * df).sum())
+    an = part_d + part_f
+    err = abs(an - fd) / (abs(part_d) + abs(part_f))
+    _say(f"adaptive autograd, {nsteps} steps (checkpoints every 2): <grad,d> {an:.12e} "
+         f"(DG {part_d:.6e}, FD {part_f:.6e})  FD {fd:.12e}  err {err:.1e}")
+    assert err <= TOL_FD
+    dom.close()
+
+
 def test_adjoint_rejects_mixed_precision_and_clamp():
     torch = _torch()
     from paper_2404_01531_amd import grffe
