@@ -475,9 +475,16 @@ struct TimedLaunch {
 static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   const int N = d->N;
   const bool cv = d->curved;
-  a.sub = mode == MODE_RHS ? 3 : mode - 1;
-  launch_begin_substep(a, mode != MODE_RHS, st);
-  { TimedLaunch t(d, 4, st); launch_fd_stage(a, N, cv, mode, st); }
+  // one FD work list per step (counter 0, emptied by the pre-stage pass): substep 1
+  // builds it from the representation at the step start, the DG substeps append the
+  // elements they flag, so it holds the FD elements at the start of every substep;
+  // the FD update of substeps 1 and 2 writes the next substep's stage values
+  a.sub = mode == MODE_RHS ? 3 : 0;
+  if (mode == MODE_RHS || mode == MODE_SUB1) {
+    launch_begin_substep(a, mode != MODE_RHS, st);
+    TimedLaunch t(d, 4, st);
+    launch_fd_stage(a, N, cv, mode, st);
+  }
   { TimedLaunch t(d, 5, st); launch_fd_trace(a, N, st); }
   { TimedLaunch t(d, 1, st); launch_dg_substep(a, N, cv, mode, st); }
   { TimedLaunch t(d, 6, st); launch_dg_slab(a, N, cv, mode, st); }

@@ -88,7 +88,8 @@ struct KArgs {
   int tci_mode, filter_on, fd_order, ff_clamp, hybrid, precision;
   double weno_eps, ff_margin;
   // work list of the FD kernels: element ids fd_list[0 .. fd_count[sub]), where sub
-  // is the substep (0, 1, 2) or 3 for a right-hand side evaluation
+  // is 0 for the substeps of a step (one list per step) and 3 for a right-hand
+  // side evaluation or an adjoint stage
   int32_t* fd_list;
   int32_t* fd_count;
   int sub;
@@ -134,7 +135,7 @@ struct grffe_domain {
   double* slab = nullptr;
   double* fhat = nullptr;
   int32_t* fd_list = nullptr;   // [E] work list of the FD kernels
-  int32_t* fd_count = nullptr;  // [4] list lengths (three substeps, right-hand side)
+  int32_t* fd_count = nullptr;  // [4] list lengths (0: the step's list, 3: right-hand side / adjoint)
   double* adj_ws = nullptr;  // step adjoint: 6 DG-sized arrays, allocated at first use
   double* adj_u0 = nullptr;  // step adjoint: copy of U^n
   double* adj_fd_wbar = nullptr;  // FD adjoint: [3][10][E][m^3]

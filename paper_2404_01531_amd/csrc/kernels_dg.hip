@@ -246,6 +246,9 @@ template <int N, bool CURVED>
 __global__ __launch_bounds__(256) void k_dg_prestage(KArgs a) {
   constexpr int nn = Dims<N>::nn;
   const int gid = blockIdx.x * 256 + threadIdx.x;
+  // the step's FD work list starts empty (substep 1 builds it, substeps 2 and 3
+  // extend it with the elements they flag)
+  if (gid == 0) a.fd_count[0] = 0;
   const int e = gid / nn, p = gid % nn;
   if (e >= a.E || !a.live[e] || a.rep[e] != 0) return;
   Metric M;

@@ -17,14 +17,15 @@
 namespace grffe {
 
 // ---------------------------------------------------------------- substep start
-// Opens a substep: with `copy` the representation at the substep start (rep0) is
-// taken from rep and the flags are cleared; every live FD element is appended to
-// the substep's work list fd_list (count fd_count[sub]).  The list of the next
-// substep is emptied here: its previous users ran in the previous step.  The
-// DG substep kernel appends the elements it flags, so the FD flux and update
-// launches see both.  List order does not affect any result.
+// Opens a step (or a right-hand side evaluation): with `copy` the representation
+// at the start (rep0) is taken from rep and the flags are cleared; every live FD
+// element is appended to the work list fd_list (count fd_count[sub], emptied
+// before: by the pre-stage pass for a step).  The DG substep kernel appends the
+// elements it flags, so the FD flux and update launches see both, and the FD
+// update of a flagged element marks it FD for the next substep: the list then
+// holds the FD elements at the start of every substep of the step.  List order
+// does not affect any result.
 __global__ __launch_bounds__(256) void k_begin_substep(KArgs a, int copy) {
-  if (a.sub < 3 && blockIdx.x == 0 && threadIdx.x == 0) a.fd_count[(a.sub + 1) % 3] = 0;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= a.E) return;
   int r;
@@ -541,7 +542,25 @@ __global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
   } else {
     store9(a.fd.Un, a.E, mm, e, p, Y);
   }
-  if (p == 0 && a.troubled[e]) a.rep[e] = 1;
+  if (MODE == MODE_SUB1 || MODE == MODE_SUB2) {
+    // the next substep's transported values (U, J~) of the cell: every element on FD
+    // at its start is in this substep's list (elements flagged in it get theirs from
+    // the projection)
+    double J[3];
+    current_total(Y, M, a.eta, J);
+    const size_t st = (size_t)a.E * mm;
+    double* w = a.w_fd + (size_t)e * mm + p;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v * st] = Y[v];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[(9 + c) * st] = J[c];
+  }
+  if (p == 0 && a.troubled[e]) {
+    // redone on FD: FD from here on (representation at the next substep's start)
+    a.rep[e] = 1;
+    a.rep0[e] = 1;
+    a.troubled[e] = 0;
+  }
   }
 }
 
