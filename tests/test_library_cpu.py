@@ -102,3 +102,22 @@ def test_null_handles_are_rejected():
     assert L.grffe_batch_step(None, 1, 1, None) == -1
     d = ctypes.c_double()
     assert L.grffe_batch_get_dt(None, 0, ctypes.byref(d)) == -1
+
+
+def test_adjoint_entry_points_reject_null_handles():
+    L = grffe.lib()
+    assert L.grffe_rhs_adjoint(None, None, None, None, None, None, None, None, 3, None) == -1
+    assert L.grffe_step_adjoint(None, None, None, None, 0.0, None) == -1
+    assert L.grffe_step_adjoint_frozen(None, None, None, None, None, None, None, None, None, 0.0, None) == -1
+    assert L.grffe_timing_read(None, 2, None, None) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
