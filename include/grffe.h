@@ -208,11 +208,25 @@ int grffe_rhs_adjoint(grffe_domain* dom, const double* dg, const double* fd, con
  * theorem), the stiff sources and the filter.  u_dg (device [9][E][n^3]) is U^n;
  * the domain re-runs the forward step from it, so its state is left at U^{n+1}
  * with every element on DG.  dt <= 0 selects the CFL step.  lam may be the same
- * buffer as lam_next; neither may overlap u_dg.  Same restrictions as
+ * buffer as lam_next; neither may overlap u_dg; the entries of excised elements are
+ * not written.  Same restrictions as
  * grffe_rhs_adjoint; the first call allocates the adjoint's work space
  * (7 arrays of the DG state's size). */
 int grffe_step_adjoint(grffe_domain* dom, const double* u_dg, const double* lam_next, double* lam, double dt,
                        void* stream);
+
+/* The DG stage values U_3 and U_4 of the domain's last step (device [9][E][n^3]
+ * each; either may be NULL), for grffe_step_adjoint_stages. */
+int grffe_get_stages(grffe_domain* dom, double* u3, double* u4, void* stream);
+
+/* grffe_step_adjoint with the step's stage values given instead of regenerated:
+ * u_dg is U^n and u3, u4 its U_3, U_4 (from grffe_get_stages after the step from
+ * u_dg with the same dt); the forward step is not re-run and the domain's state is
+ * left as it was.  Every element on DG; the same restrictions and work space as
+ * grffe_step_adjoint.  For checkpointed gradients whose segment recomputation
+ * already produces the stages. */
+int grffe_step_adjoint_stages(grffe_domain* dom, const double* u_dg, const double* u3, const double* u4,
+                              const double* lam_next, double* lam, double dt, void* stream);
 
 /* Adjoint of one IMEX-SSP3(4,3,3) step (Sec. III B) with the hybrid decisions
  * (Sec. III C 1) frozen from the forward pass:

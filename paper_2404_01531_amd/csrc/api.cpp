@@ -569,9 +569,7 @@ extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream)
   return GRFFE_OK;
 }
 
-// Representation check of the adjoint entry points: every live element on DG.
-// Representation of the live elements of `rep` (device): 0 all DG, 1 all FD,
-// 2 both (read on the host; synchronises the stream).
+// The adjoint entry points run in FP64 without the clamp.
 static int adjoint_supported(grffe_domain* d) {
   if (d->par.precision != GRFFE_PRECISION_FP64) return fail(GRFFE_EUNSUPPORTED, "the adjoint runs in FP64 only");
   if (d->par.ff_clamp) return fail(GRFFE_EUNSUPPORTED, "the adjoint does not differentiate the clamp");
@@ -588,6 +586,15 @@ static int fd_adjoint_space(grffe_domain* d) {
   if (int rc = dalloc(d, &p2, sizeof(double) * (NV + 1) * (size_t)d->E * 6 * 3 * d->m * d->m)) return rc;
   d->adj_fd_wbar = reinterpret_cast<double*>(p1);
   d->adj_fd_gbar = reinterpret_cast<double*>(p2);
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_get_stages(grffe_domain* d, double* u3, double* u4, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  hipStream_t st = S(stream);
+  const size_t bytes = sizeof(double) * NV * d->E * d->nn;
+  if (u3) HIPCHK(hipMemcpyAsync(u3, d->dg.X0, bytes, hipMemcpyDeviceToDevice, st));
+  if (u4) HIPCHK(hipMemcpyAsync(u4, d->dg.X1, bytes, hipMemcpyDeviceToDevice, st));
   return GRFFE_OK;
 }
 
@@ -665,6 +672,26 @@ extern "C" int grffe_step_adjoint(grffe_domain* d, const double* u_dg, const dou
   // backward sweep over the stages
   KArgs b = a;
   b.dg.Un = d->adj_u0;
+  launch_step_adjoint(b, d->N, d->curved, lam_next, lam, d->adj_ws, st);
+  HIPCHK(hipGetLastError());
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_step_adjoint_stages(grffe_domain* d, const double* u_dg, const double* u3, const double* u4,
+                                         const double* lam_next, double* lam, double dt, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (!u_dg || !u3 || !u4 || !lam_next || !lam) return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
+  if (int rc = adjoint_supported(d)) return rc;
+  if (int rc = step_adjoint_space(d, false)) return rc;
+  hipStream_t st = S(stream);
+  // every element on DG; the stage values are the caller's (read only)
+  HIPCHK(hipMemsetAsync(d->rep0, 0, sizeof(int32_t) * d->E, st));
+  KArgs b = make_args(d);
+  b.hybrid = GRFFE_HYBRID_DG_ONLY;
+  if (dt > 0.0) b.dt = dt;
+  b.dg.Un = const_cast<double*>(u_dg);
+  b.dg.X0 = const_cast<double*>(u3);
+  b.dg.X1 = const_cast<double*>(u4);
   launch_step_adjoint(b, d->N, d->curved, lam_next, lam, d->adj_ws, st);
   HIPCHK(hipGetLastError());
   return GRFFE_OK;

@@ -94,6 +94,8 @@ def lib():
     L.grffe_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
     L.grffe_step_adjoint.argtypes = [vp, vp, vp, vp, dbl, vp]
     L.grffe_step_adjoint_frozen.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp]
+    L.grffe_get_stages.argtypes = [vp, vp, vp, vp]
+    L.grffe_step_adjoint_stages.argtypes = [vp, vp, vp, vp, vp, vp, dbl, vp]
     pvp = ctypes.POINTER(vp)
     L.grffe_batch_create.argtypes = [ctypes.POINTER(Grid), i32, ctypes.POINTER(Params), pvp, vp, pvp]
     L.grffe_batch_destroy.argtypes = [vp]
@@ -111,7 +113,8 @@ def lib():
                  "grffe_timing_read", "grffe_batch_create", "grffe_batch_destroy", "grffe_batch_size",
                  "grffe_batch_init_from_fd", "grffe_batch_get_state", "grffe_batch_set_state",
                  "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step", "grffe_rhs_adjoint",
-                 "grffe_step_adjoint", "grffe_step_adjoint_frozen"):
+                 "grffe_step_adjoint", "grffe_step_adjoint_frozen", "grffe_get_stages",
+                 "grffe_step_adjoint_stages"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -282,8 +285,27 @@ class Domain:
         import torch
         self._check_state(u_dg, None, None)
         self._check_state(lam_next, None, None)
-        lam = torch.empty_like(lam_next)
+        lam = torch.zeros_like(lam_next)  # excised elements' entries are not written
         _check(lib().grffe_step_adjoint(self._h, _ptr(u_dg), _ptr(lam_next), _ptr(lam), float(dt), _stream()))
+        return lam
+
+    def get_stages(self):
+        """(U_3, U_4) of the last step, DG (see grffe_get_stages)."""
+        import torch
+        u3 = torch.empty(self.dg_shape(), dtype=torch.float64, device="cuda")
+        u4 = torch.empty_like(u3)
+        _check(lib().grffe_get_stages(self._h, _ptr(u3), _ptr(u4), _stream()))
+        return u3, u4
+
+    def step_adjoint_stages(self, u_dg, u3, u4, lam_next, dt=0.0):
+        """(dU^{n+1}/dU^n)^T lam_next from the step's stored stages (see
+        grffe_step_adjoint_stages)."""
+        import torch
+        for x in (u_dg, u3, u4, lam_next):
+            self._check_state(x, None, None)
+        lam = torch.zeros_like(lam_next)  # excised elements' entries are not written
+        _check(lib().grffe_step_adjoint_stages(self._h, _ptr(u_dg), _ptr(u3), _ptr(u4), _ptr(lam_next), _ptr(lam),
+                                               float(dt), _stream()))
         return lam
 
     def step_adjoint_frozen(self, dg, fd, rep, mu_dg, mu_fd, dt=0.0, with_log=False):

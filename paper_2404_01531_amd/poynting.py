@@ -16,7 +16,8 @@ time_integral_gradient(dom, u0, steps, dt, every, L) returns
 and dPhi/dU^0, by the adjoint recursion
     lam_steps = dt dL/dU^steps,  lam_n = (dU^{n+1}/dU^n)^T lam_{n+1} + dt dL/dU^n,
 with the states kept every `every` steps and each segment recomputed from its
-checkpoint; every step and step adjoint runs in the HIP library.
+checkpoint (keeping each step's stage values, so the step adjoints need no
+forward re-run); every step and step adjoint runs in the HIP library.
 """
 from __future__ import annotations
 
@@ -54,6 +55,23 @@ class SphereFlux:
         # node index i + n (j + n k): flatten (k, j, i)
         W = np.einsum("qi,qj,qk->qkji", Lx, Ly, Lz).reshape(-1, n ** 3)
         elem = idx[:, 0] + ne[0] * (idx[:, 1] + ne[1] * idx[:, 2])
+        # interpolation grouped by element: the elements holding points, each with its
+        # points' weights (zero-padded), as one batched product
+        Q, n3 = W.shape
+        uniq, uidx = np.unique(elem, return_inverse=True)
+        counts = np.bincount(uidx)
+        slot = np.zeros(Q, np.int64)
+        seen = np.zeros(len(uniq), np.int64)
+        for q in range(Q):
+            slot[q] = seen[uidx[q]]
+            seen[uidx[q]] += 1
+        Wp = np.zeros((len(uniq), int(counts.max()), n3))
+        Wp[uidx, slot] = W
+        self.uniq = torch.from_numpy(uniq).to(device)
+        self.uidx = torch.from_numpy(uidx).to(device)
+        self.slot = torch.from_numpy(slot).to(device)
+        self.Wp = torch.from_numpy(Wp).to(device)
+        self.WpT = self.Wp.transpose(1, 2).contiguous()
         if w.get("curved"):
             bg = I.background(w, pts[0], pts[1], pts[2])
             gl = bg[4:10]
@@ -72,7 +90,7 @@ class SphereFlux:
 
     def __call__(self, u):
         """L(U) for the DG state u, (9, E, (N+1)^3) float64 on the device."""
-        v = (u[:, self.elem, :] * self.W).sum(-1)  # (9, Q) at the sphere points
+        v = self._at_points(u)  # (9, Q) at the sphere points
         E = v[0:3] / self.sg
         B = v[3:6] / self.sg
         El = (self.g * E[None]).sum(1)
@@ -86,7 +104,7 @@ class SphereFlux:
         dL/dE~ = g (B_lo x x) w / (R sqrt(gamma)), dL/dB~ = g (x x E_lo) w / (R sqrt(gamma)) at
         the points, spread to the nodes of the containing elements with the
         interpolation weights."""
-        v = (u[:, self.elem, :] * self.W).sum(-1)
+        v = self._at_points(u)
         El = (self.g * (v[0:3] / self.sg)[None]).sum(1)
         Bl = (self.g * (v[3:6] / self.sg)[None]).sum(1)
         c = self.wq / (self.R * self.sg)
@@ -95,9 +113,23 @@ class SphereFlux:
         dv = torch.zeros_like(v)
         dv[0:3] = gE
         dv[3:6] = gB
+        dvp = torch.zeros((self.Wp.shape[0], self.Wp.shape[1], 6), dtype=u.dtype, device=u.device)
+        dvp[self.uidx, self.slot] = dv[0:6].t()
+        ge = torch.bmm(self.WpT, dvp)  # (elements, nodes, 6)
         out = torch.zeros_like(u)
-        out.index_add_(1, self.elem, dv[:, :, None] * self.W[None])
+        out[0:6, self.uniq, :] = ge.permute(2, 0, 1)
         return out
+
+    def _at_points(self, u):
+        """The DG interpolants at the points, (9, Q); only the six field rows are
+        formed (the other three are zero)."""
+        if u.requires_grad:
+            return (u[:, self.elem, :] * self.W).sum(-1)
+        ue = u[0:6, self.uniq, :].permute(1, 2, 0).contiguous()  # (elements, nodes, 6)
+        vq = torch.bmm(self.Wp, ue)  # (elements, points, 6)
+        v = torch.zeros((9, self.W.shape[0]), dtype=u.dtype, device=u.device)
+        v[0:6] = vq[self.uidx, self.slot].t()
+        return v
 
 
 def _set_dg(dom, u):
@@ -135,14 +167,16 @@ def time_integral_gradient(dom, u0, steps, dt, every, L):
     lam = torch.zeros_like(u0)
     for n0, uc in reversed(ckpts):
         k = min(every, steps - n0)
-        states = [uc]
+        # the segment recomputed, with each step's stage values kept for its adjoint
+        states, stages = [uc], []
         _set_dg(dom, uc)
         for _ in range(k):
             dom.step(1, dt)
+            stages.append(dom.get_stages())
             states.append(dom.get_dg())
         for j in range(k - 1, -1, -1):
             lam = lam + dt * L.grad(states[j + 1])
-            lam = dom.step_adjoint(states[j], lam, dt)
+            lam = dom.step_adjoint_stages(states[j], stages[j][0], stages[j][1], lam, dt)
     return float(phi), lam
 
 

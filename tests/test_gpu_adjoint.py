@@ -759,6 +759,29 @@ def test_autograd_adaptive_checkpointed():
     dom.close()
 
 
+def test_step_adjoint_from_stored_stages_matches():
+    """grffe_step_adjoint_stages with the stages kept from the forward step gives the
+    same bits as grffe_step_adjoint (which regenerates them)."""
+    torch = _torch()
+    w = I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3)
+    rng = np.random.default_rng(79)
+    odom, ldom, _ = make_pair(w, dict(eta=w["eta"], cfl=w["cfl"], hybrid=0))
+    with np.errstate(all="ignore"):
+        dg, _ = curved_state(odom, w, rng)
+    dg[:, ~odom.active] = 0.0
+    u = to_dev(dg)
+    mu = to_dev(rng.standard_normal(dg.shape))
+    dt = odom.dt()
+    ref = ldom.step_adjoint(u, mu, dt)
+    fd0 = torch.zeros(ldom.fd_shape(), dtype=torch.float64, device="cuda")
+    ldom.set_state(u, fd0, torch.zeros(ldom.E, dtype=torch.int32, device="cuda"))
+    ldom.step(1, dt)
+    u3, u4 = ldom.get_stages()
+    got = ldom.step_adjoint_stages(u, u3, u4, mu, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+
+
 def test_adjoint_rejects_mixed_precision_and_clamp():
     torch = _torch()
     from paper_2404_01531_amd import grffe
