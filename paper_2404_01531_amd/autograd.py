@@ -5,9 +5,10 @@ GRFFEStep.apply(u0, dom, n_steps, dt, checkpoint_every) advances the DG state u0
 created with hybrid = HYBRID_DG_ONLY, so no element leaves DG and the
 representation is the same in the forward and the backward pass).  The forward
 pass keeps the state every `checkpoint_every` steps; the backward pass recomputes
-each segment from its checkpoint, keeping the segment's step-start states, and
-runs the library's step adjoint back through them.  Every step and adjoint runs
-in the HIP library; this module only orders the calls and holds the checkpoints.
+each segment from its checkpoint, keeping the segment's step-start states and
+stage values, and runs the library's step adjoint back through them.  Every step
+and adjoint runs in the HIP library; this module only orders the calls and holds
+the checkpoints.
 
 GRFFEStepFrozen.apply(u_dg, u_fd, rep, dom, n_steps, dt, checkpoint_every) does
 the same for a state of DG and FD elements (rep: the representation of each), in
@@ -30,13 +31,15 @@ def _set_dg(dom, u):
 
 
 def _advance(dom, u, n, dt):
-    """States at the start of each of n steps from u, and the state after them."""
-    starts = []
+    """States at the start of each of n steps from u with each step's stage values
+    (U_3, U_4), and the state after them."""
+    starts, stages = [], []
     _set_dg(dom, u)
     for _ in range(n):
-        starts.append(dom.get_state()[0])
+        starts.append(dom.get_dg())
         dom.step(1, dt)
-    return starts, dom.get_state()[0]
+        stages.append(dom.get_stages())
+    return starts, stages, dom.get_dg()
 
 
 class GRFFEStep(torch.autograd.Function):
@@ -63,9 +66,9 @@ class GRFFEStep(torch.autograd.Function):
     def backward(ctx, grad):
         lam = grad.contiguous().clone()
         for u_start, k in reversed(ctx.ckpts):
-            starts, _ = _advance(ctx.dom, u_start, k, ctx.dt)
-            for u in reversed(starts):
-                lam = ctx.dom.step_adjoint(u, lam, ctx.dt)
+            starts, stages, _ = _advance(ctx.dom, u_start, k, ctx.dt)
+            for u, (u3, u4) in zip(reversed(starts), reversed(stages)):
+                lam = ctx.dom.step_adjoint_stages(u, u3, u4, lam, ctx.dt)
         return lam, None, None, None, None
 
 
