@@ -46,11 +46,11 @@ DG_BG_BYTES_PER_NODE = 26 * 8.0
 
 # HBM bytes per FD element per launch of k_fd_flux (FP64): rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (KiB per dispatch, 12 dispatches with 128 FD elements: fetch
-# 44376.2, write 39781.1), scaled by what the same counters read for a plain
+# 44293.9, write 39781.3), scaled by what the same counters read for a plain
 # 512 MiB device copy (fetch x 2.0, write x 1.0).  Valid for the kernel source
 # whose hash is FD_FLUX_TRAFFIC_SRC; reported as null for any other source.
-FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 44376.2 + 1.0 * 39781.1) * 1024.0 / 128.0
-FD_FLUX_TRAFFIC_SRC = "887fedb3aa71b81f"
+FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 44293.9 + 1.0 * 39781.3) * 1024.0 / 128.0
+FD_FLUX_TRAFFIC_SRC = "a7cc7bc4345d510a"
 
 
 def parse():
