@@ -44,6 +44,10 @@ DG_BYTES_PER_NODE = {1: 216.0, 2: 360.0, 3: 288.0}
 # The curved background adds its 26 FP64 fields per node, read once per substep.
 DG_BG_BYTES_PER_NODE = 26 * 8.0
 
+# Kernel timing: HIP events on the launches of one step in every TIMING_PERIOD of
+# the timed region.
+TIMING_PERIOD = 10
+
 # HBM bytes per FD element per launch of k_fd_flux (FP64): rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (KiB per dispatch, 12 dispatches with 128 FD elements: fetch
 # 44293.9, write 39781.3), scaled by what the same counters read for a plain
@@ -101,8 +105,9 @@ def run_workload(w, precision, steps, warmup, families):
     torch.cuda.synchronize()
     n_dg0, n_fd0 = dom.counts()
     # timed region: the whole step; the listed kernel families are timed with HIP
-    # events attached to their own dispatches on the launch stream
-    dom.timing_enable(*families)
+    # events attached to their own dispatches on the launch stream, in one step of
+    # every TIMING_PERIOD (the events cost a few microseconds per timed launch)
+    dom.timing_enable(*families, period=TIMING_PERIOD)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dom.step(steps, dt)
@@ -205,7 +210,7 @@ def run_kerr_schild(steps, warmup, precision, n_elem=16):
     dom.step(warmup, dt)
     torch.cuda.synchronize()
     n_dg0, n_fd0 = dom.counts()
-    dom.timing_enable(fam)
+    dom.timing_enable(fam, period=max(1, steps // 6))
     secs = _time_steps(lambda k: dom.step(k, dt), steps, 0)
     k_ms, k_n = dom.timing_read(fam)
     dom.timing_enable()

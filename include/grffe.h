@@ -183,6 +183,11 @@ int grffe_operator(int degree, int which, double* out, int capacity);
  * stream of the last timed launch, returns the summed duration (ms) and the
  * number of timed launches of one family, and resets that family's counters. */
 int grffe_timing_enable(grffe_domain* dom, int mask);
+/* Attach the timing events to the launches of one step in every `period` steps
+ * (the first step after this call, then every period-th; default 1: every step):
+ * the events add a few microseconds to each timed launch, sampling keeps that out
+ * of the rest.  EINVAL for period < 1. */
+int grffe_timing_period(grffe_domain* dom, int period);
 int grffe_timing_read(grffe_domain* dom, int family, double* total_ms, int64_t* launches);
 
 /* Adjoint of the right-hand side (a vector-Jacobian product), with the

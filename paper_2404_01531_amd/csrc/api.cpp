@@ -447,7 +447,7 @@ struct TimedLaunch {
   bool on;
   hipStream_t st;
   TimedLaunch(grffe_domain* dd, int family, hipStream_t s)
-      : d(dd), fam(family), on(((dd->timed_mask >> family) & 1) != 0), st(s) {
+      : d(dd), fam(family), on(dd->timing_now && ((dd->timed_mask >> family) & 1) != 0), st(s) {
     if (!on) return;
     auto& ev = d->ev[fam];
     if (d->ev_used[fam] + 2 > ev.size()) {
@@ -504,6 +504,14 @@ extern "C" int grffe_timing_enable(grffe_domain* d, int mask) {
   return GRFFE_OK;
 }
 
+extern "C" int grffe_timing_period(grffe_domain* d, int period) {
+  if (int rc = check_dom(d)) return rc;
+  if (period < 1) return fail(GRFFE_EINVAL, "the timing period is at least 1");
+  d->timing_period = period;
+  d->timing_step = 0;
+  return GRFFE_OK;
+}
+
 extern "C" int grffe_timing_read(grffe_domain* d, int family, double* total_ms, int64_t* launches) {
   if (int rc = check_dom(d)) return rc;
   if (family < 1 || family >= grffe_domain::NFAM) return fail(GRFFE_EINVAL, "unknown kernel family");
@@ -545,6 +553,7 @@ extern "C" int grffe_rhs(grffe_domain* d, const double* dg, const double* fd, co
 
 // One IMEX-SSP3(4,3,3) step of every element of the domain (or pool).
 static void step_once(grffe_domain* d, KArgs& a, hipStream_t st) {
+  d->timing_now = d->timing_period <= 1 || (d->timing_step++ % d->timing_period) == 0;
   {
     TimedLaunch t(d, 9, st);
     launch_dg_prestage(a, d->N, d->curved, st);
@@ -556,6 +565,7 @@ static void step_once(grffe_domain* d, KArgs& a, hipStream_t st) {
     TimedLaunch t(d, 8, st);
     launch_fd_to_dg(a, d->N, d->curved, 0, st);
   }
+  d->timing_now = true;
 }
 
 extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream) {

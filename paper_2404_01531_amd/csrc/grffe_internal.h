@@ -152,6 +152,10 @@ struct grffe_domain {
   // kernel timing: bit f of timed_mask times family f (1..9)
   static constexpr int NFAM = 10;
   int timed_mask = 0;
+  // events on the launches of one step in every timing_period steps
+  int timing_period = 1;
+  int64_t timing_step = 0;
+  bool timing_now = true;
   std::vector<hipEvent_t> ev[NFAM];  // start/stop pairs per family
   size_t ev_used[NFAM] = {};
   hipStream_t ev_stream = nullptr;

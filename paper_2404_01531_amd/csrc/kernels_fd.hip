@@ -880,7 +880,7 @@ void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, hipStream_t s
 }
 
 void launch_fd_trace(const KArgs& a, int N, hipStream_t s) {
-  GRFFE_SWITCH_N(launch_kernel(k_fd_trace<NN>, list_grid((size_t)a.E * NW, 1024), dim3(256), s, a))
+  GRFFE_SWITCH_N(launch_kernel(k_fd_trace<NN>, list_grid((size_t)a.E * NW, 4096), dim3(256), s, a))
 }
 
 template <int N, bool CURVED>

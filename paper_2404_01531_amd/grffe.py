@@ -91,6 +91,7 @@ def lib():
     L.grffe_operator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(dbl), ctypes.c_int]
     L.grffe_timing_enable.argtypes = [vp, ctypes.c_int]
     L.grffe_timing_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
+    L.grffe_timing_period.argtypes = [vp, ctypes.c_int]
     L.grffe_rhs_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
     L.grffe_step_adjoint.argtypes = [vp, vp, vp, vp, dbl, vp]
     L.grffe_step_adjoint_frozen.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp]
@@ -110,7 +111,7 @@ def lib():
     for name in ("grffe_init_domain", "grffe_destroy", "grffe_init_from_fd", "grffe_set_state", "grffe_get_state",
                  "grffe_rhs", "grffe_step", "grffe_tci", "grffe_project_dg_to_fd", "grffe_reconstruct_fd_to_dg",
                  "grffe_get_dt", "grffe_get_counts", "grffe_operator", "grffe_timing_enable",
-                 "grffe_timing_read", "grffe_batch_create", "grffe_batch_destroy", "grffe_batch_size",
+                 "grffe_timing_read", "grffe_timing_period", "grffe_batch_create", "grffe_batch_destroy", "grffe_batch_size",
                  "grffe_batch_init_from_fd", "grffe_batch_get_state", "grffe_batch_set_state",
                  "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step", "grffe_rhs_adjoint",
                  "grffe_step_adjoint", "grffe_step_adjoint_frozen", "grffe_get_stages",
@@ -351,13 +352,15 @@ class Domain:
         _check(lib().grffe_get_dt(self._h, ctypes.byref(v)))
         return v.value
 
-    def timing_enable(self, *families):
-        """Time every launch of the given kernel families with HIP events (see
-        grffe_timing_enable); no argument switches timing off."""
+    def timing_enable(self, *families, period=1):
+        """Time the launches of the given kernel families with HIP events (see
+        grffe_timing_enable), in one step of every `period` steps
+        (grffe_timing_period); no family switches timing off."""
         mask = 0
         for f in families:
             mask |= 1 << int(f)
         _check(lib().grffe_timing_enable(self._h, mask))
+        _check(lib().grffe_timing_period(self._h, int(period)))
 
     def timing_read(self, family):
         """(summed ms, launches) of one family since timing was enabled or last read."""
