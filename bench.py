@@ -349,6 +349,60 @@ def run_adjoint(steps=200, every=20, check_steps=10):
                                    "other step and with the adjoint"}
 
 
+def roofline_fd(rec, N, counted=True):
+    """FP64-ALU roofline of the FD face-flux kernel from the run record's timed launches;
+    the counter traffic is attached only to the counted source and workload."""
+    from paper_2404_01531_amd import grffe
+    m = 2 * N + 1
+    k_ms, k_n = rec["kern"][grffe.KERNEL_FAMILIES["fd_flux"]]
+    n_fd = 0.5 * sum(rec["n_fd"])
+    flop = n_fd * 3 * (m + 1) * m * m * FD_FLOP_PER_FACE
+    avg = (k_ms / 1e3) / max(k_n, 1)
+    ach = flop / avg / 1e12
+    return {"kernel": "k_fd_flux (FD subcell WENO5-Z face fluxes)", "bound": "alu", "achieved": ach,
+            "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK_TFLOPS,
+            "traffic": (FD_FLUX_TRAFFIC_PER_FD_ELEMENT * n_fd
+                        if counted and kernel_source_hash() == FD_FLUX_TRAFFIC_SRC else None),
+            "mean_launch_us": avg * 1e6, "launches": int(k_n), "flop_per_launch": flop}
+
+
+def roofline_dg(rec, N):
+    """HBM roofline of the fused flat DG substep kernel from the run record's timed launches."""
+    from paper_2404_01531_amd import grffe
+    k_ms, k_n = rec["kern"][grffe.KERNEL_FAMILIES["dg_substep"]]
+    n_dg = 0.5 * sum(rec["n_dg"])
+    byt = n_dg * (N + 1) ** 3 * (sum(DG_BYTES_PER_NODE.values()) / 3.0)
+    avg = (k_ms / 1e3) / max(k_n, 1)
+    return {"kernel": "k_dg_substep (fused DG substep)", "bound": "hbm", "achieved": byt / avg / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": byt / avg / 1e9 / HBM_PEAK_GBS,
+            "mean_launch_us": avg * 1e6, "launches": int(k_n), "bytes_per_launch": byt}
+
+
+def run_sheet_sweep(steps, warmup, sizes=(16, 32)):
+    """The benchmark's current sheet on the same domain with n^3 elements (h = 2/n):
+    the element-count diagnostic, FP64, adaptive DG-FD, the sheet workload's seed."""
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    fam = (grffe.KERNEL_FAMILIES["fd_flux"], grffe.KERNEL_FAMILIES["dg_substep"])
+    rows = []
+    for n in sizes:
+        w = I.workload("sheet", n_elem=(n, n, n))
+        rec, st = run_workload(w, 0, steps, warmup, fam)
+        del st
+        torch.cuda.empty_cache()
+        rf, rd = roofline_fd(rec, w["degree"], counted=False), roofline_dg(rec, w["degree"])
+        rows.append({"n_elem": n, "elements": int(rec["E"]), "fd_elements": [int(x) for x in rec["n_fd"]],
+                     "value": rec["value"], "ms_per_step": rec["secs"] * 1e3 / steps, "dt": rec["dt"],
+                     "fd_flux_tflops": rf["achieved"], "fd_flux_mean_us": rf["mean_launch_us"],
+                     "dg_substep_gbs": rd["achieved"], "dg_substep_frac": rd["frac"],
+                     "dg_substep_mean_us": rd["mean_launch_us"]})
+    return {"workload": "current sheet, periodic [-1,1]^3, n^3 elements DG-P5 / FD 11^3, eta 1e6, CFL 0.25, "
+                        "adaptive DG-FD, seed 1002, fp64 (element-count diagnostic)",
+            "unit": "grid-point updates/s", "steps": steps, "rows": rows}
+
+
 def run_forced_fractions(steps, warmup, fractions=(0.0, 0.1, 0.2, 0.5, 1.0)):
     """The controlled experiment of the paper's performance section on the benchmark
     sheet (8^3 P5 elements): the partition is forced (no indicator, no rollback) with
@@ -476,8 +530,6 @@ def main():
     if w.get("curved"):
         raise SystemExit("the benchmark workload is flat; curved workloads are parity cases")
     N = w["degree"]
-    m = 2 * N + 1
-    n3 = (N + 1) ** 3
     fam_fd, fam_dg = grffe.KERNEL_FAMILIES["fd_flux"], grffe.KERNEL_FAMILIES["dg_substep"]
     res = {}
     states = {}
@@ -488,27 +540,6 @@ def main():
         k_ms, k_n = rec["kern"][fam_fd]
         print(f"# {name}: {args.steps} steps in {rec['secs']:.4f} s, {rec['n_dg']} DG / {rec['n_fd']} FD elements; "
               f"fd_flux {k_n} launches, mean {k_ms / max(k_n, 1) * 1e3:.2f} us", file=sys.stderr, flush=True)
-
-    def roofline_fd(rec, counted=True):
-        k_ms, k_n = rec["kern"][fam_fd]
-        n_fd = 0.5 * sum(rec["n_fd"])
-        flop = n_fd * 3 * (m + 1) * m * m * FD_FLOP_PER_FACE
-        avg = (k_ms / 1e3) / max(k_n, 1)
-        ach = flop / avg / 1e12
-        return {"kernel": "k_fd_flux (FD subcell WENO5-Z face fluxes)", "bound": "alu", "achieved": ach,
-                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK_TFLOPS,
-                "traffic": (FD_FLUX_TRAFFIC_PER_FD_ELEMENT * n_fd
-                            if counted and kernel_source_hash() == FD_FLUX_TRAFFIC_SRC else None),
-                "mean_launch_us": avg * 1e6, "launches": int(k_n), "flop_per_launch": flop}
-
-    def roofline_dg(rec):
-        k_ms, k_n = rec["kern"][fam_dg]
-        n_dg = 0.5 * sum(rec["n_dg"])
-        byt = n_dg * n3 * (sum(DG_BYTES_PER_NODE.values()) / 3.0)
-        avg = (k_ms / 1e3) / max(k_n, 1)
-        return {"kernel": "k_dg_substep (fused DG substep)", "bound": "hbm", "achieved": byt / avg / 1e9,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": byt / avg / 1e9 / HBM_PEAK_GBS,
-                "mean_launch_us": avg * 1e6, "launches": int(k_n), "bytes_per_launch": byt}
 
     f64, mix = res["fp64"], res["mixed"]
     cpu = None
@@ -531,13 +562,13 @@ def main():
                                "eta 1e6, CFL 0.25, adaptive DG-FD, seed 1002",
                    "elements": int(f64["E"]), "fd_elements": [int(x) for x in f64["n_fd"]],
                    "points_per_substep": f64["pts"], "dt": f64["dt"]},
-        "roofline": roofline_fd(f64),
-        "roofline_dg": roofline_dg(f64),
+        "roofline": roofline_fd(f64, N),
+        "roofline_dg": roofline_dg(f64, N),
         "mixed": {"value": mix["value"], "ms_per_step": mix["secs"] * 1e3 / args.steps,
                   "dtype": "f64 state, f32 fluxes and DG contractions",
                   "fd_elements": [int(x) for x in mix["n_fd"]],
                   "error_vs_fp64_run": state_diff(states["mixed"], states["fp64"]),
-                  "roofline": roofline_fd(mix, counted=False), "roofline_dg": roofline_dg(mix)},
+                  "roofline": roofline_fd(mix, N, counted=False), "roofline_dg": roofline_dg(mix, N)},
         "cpu_baseline": cpu,
     }
     if args.extras == "all":
@@ -546,6 +577,7 @@ def main():
                          ("kerr_schild_16^3_mixed", lambda: run_kerr_schild(args.extra_steps, 2, 1)),
                          ("batch_64_fp64", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0)),
                          ("batch_64_mixed", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 1)),
+                         ("sheet_element_sweep_16^3_32^3", lambda: run_sheet_sweep(args.extra_steps, 2)),
                          ("forced_fd_fraction_sheet_8^3", lambda: run_forced_fractions(args.extra_steps, 2)),
                          ("adjoint_poynting_kerr_schild_8^3", lambda: run_adjoint()),
                          ("adjoint_sheet_8^3_frozen_partition", lambda: run_adjoint_frozen())):

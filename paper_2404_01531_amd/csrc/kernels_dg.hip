@@ -14,45 +14,68 @@
 
 namespace grffe {
 
-// External (neighbour or boundary) state (Ux, Jx) and metric for the face node
-// (i, j, k) of element e on face f = 2 d + s.
-template <int N, bool CURVED, int MODE>
-__device__ inline void external_state(const KArgs& a, int e, int f, int i, int j, int k, const double* Ui,
-                                      const Metric& Mi, double* Ux, double* Jx, Metric& Mx) {
-  using Dm = Dims<N>;
-  constexpr int n = Dm::n, nn = Dm::nn;
-  const int d = f >> 1, s = f & 1;
-  const int o = a.nbr[e * 6 + f];
+// Exterior data of the element's six faces, staged in LDS at the start of the
+// substep so that their loads are in flight together with the element's own: for a
+// DG neighbour its stage input at the nodes of its face towards this element (the
+// nine state components), for an FD neighbour its R-trace on that face (state and
+// J~).  Layout sX[f][c][t1 + n t2], with (t1, t2) the face node's two tangential
+// indices in increasing axis order; sO[f], sR[f] hold the neighbour across face f
+// and its representation (set by the caller, visible to every thread).
+template <int N, int MODE, int TPB>
+__device__ inline void stage_faces(const KArgs& a, const int* sO, const int* sR, double* sX) {
+  constexpr int n = N + 1, nf = n * n, nn = n * n * n;
+  constexpr int ITEMS = 6 * NW * nf, PER = (ITEMS + TPB - 1) / TPB;
+  const double* src = (MODE == MODE_RHS) ? a.dg.Un : (MODE == MODE_SUB2 ? a.dg.X0 : a.dg.X1);
+  const int t = threadIdx.x;
+  double v[PER];
+  // all loads first, then the LDS writes: one memory latency for the whole stage
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int q = t + r * TPB;
+    v[r] = 0.0;
+    if (q >= ITEMS) continue;
+    const int f = q / (NW * nf), c = (q / nf) % NW, tt = q % nf;
+    const int o = sO[f], ro = sR[f];
+    if (o < 0) continue;
+    const int d = f >> 1, s = f & 1;
+    if (ro == 0) {
+      if (c >= NV) continue;
+      const int t1 = tt % n, t2 = tt / n, lay = s ? 0 : N;  // the neighbour's layer facing us
+      const int pn = (d == 0) ? lay + n * (t1 + n * t2) : (d == 1 ? t1 + n * (lay + n * t2) : t1 + n * (t2 + n * lay));
+      v[r] = src[((size_t)c * a.E + o) * nn + pn];
+    } else {
+      const int fo = 2 * d + (1 - s);
+      v[r] = a.trace[(((size_t)c * a.E + o) * 6 + fo) * nf + tt];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int q = t + r * TPB;
+    if (q < ITEMS) sX[q] = v[r];
+  }
+}
+
+// External (neighbour or boundary) state (Ux, Jx) at the face node tt of face f, from
+// the staged face data (neighbour o, representation ro).  The face node is one point
+// of a continuous background: the element's own nodal metric Mi there is the
+// neighbour's as well.
+template <int N>
+__device__ inline void external_state(const KArgs& a, int f, int o, int ro, int tt, const double* sX,
+                                      const double* Ui, const Metric& Mi, double* Ux, double* Jx) {
+  constexpr int nf = (N + 1) * (N + 1);
   if (o < 0) {
-    boundary_state(d, s ? 1.0 : -1.0, Ui, Mi, Ux);
+    boundary_state(f >> 1, (f & 1) ? 1.0 : -1.0, Ui, Mi, Ux);
     current_total(Ux, Mi, a.eta, Jx);
-    Mx = Mi;
     return;
   }
-  int ii = i, jj = j, kk = k;
-  if (d == 0) ii = s ? 0 : N;
-  else if (d == 1) jj = s ? 0 : N;
-  else kk = s ? 0 : N;
-  const int pn = ii + n * (jj + n * kk);
-  // the face node is one point of a continuous background: the element's own nodal
-  // metric there is the neighbour's as well
-  Mx = Mi;
-  if (a.rep0[o] == 0) {
-    stage_input<MODE, true>(a.dg, a.E, nn, o, pn, Mx, a, Ux);
-    current_total(Ux, Mx, a.eta, Jx);
+  const double* x = sX + (size_t)f * NW * nf + tt;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) Ux[c] = x[c * nf];
+  if (ro == 0) {
+    current_total(Ux, Mi, a.eta, Jx);
   } else {
-    // FD neighbour: R-trace on its face facing us (face 2d + 1 - s)
-    const int fo = 2 * d + (1 - s);
-    int t1, t2;
-    if (d == 0) { t1 = j; t2 = k; }
-    else if (d == 1) { t1 = i; t2 = k; }
-    else { t1 = i; t2 = j; }
-    const size_t base = ((size_t)o * 6 + fo) * (n * n) + t1 + n * t2;
-    const size_t stride = (size_t)a.E * 6 * n * n;
 #pragma unroll
-    for (int c = 0; c < NV; ++c) Ux[c] = a.trace[base + c * stride];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) Jx[c] = a.trace[base + (NV + c) * stride];
+    for (int c = 0; c < 3; ++c) Jx[c] = x[(NV + c) * nf];
   }
 }
 
@@ -74,12 +97,19 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
   __shared__ double sred[2 * (TPB / 64)];
   __shared__ double sop[2 * n * n];  // filter, indicator operator
   __shared__ R sD[n * n];            // derivative matrix in the flux arithmetic type
+  __shared__ double sX[6 * NW * n * n];  // exterior face data
+  __shared__ int sO[6], sR[6];
   const int e = blockIdx.x;
   if (!a.live[e] || a.rep0[e] != 0) return;
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int p = act ? t : 0;
   const int i = p % n, j = (p / n) % n, k = p / (n * n);
+  if (t < 6) {
+    const int o = a.nbr[e * 6 + t];
+    sO[t] = o;
+    sR[t] = o >= 0 ? a.rep0[o] : -1;
+  }
   for (int q = t; q < n * n; q += TPB) {
     sD[q] = (R)a.ops->D[q];
     sop[q] = a.ops->F[q];
@@ -89,6 +119,8 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
   load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
   double X[NV], Jd[3], Je[3], dU[NV];
   stage_input<MODE, true>(a.dg, a.E, nn, e, p, M, a, X);
+  __syncthreads();
+  stage_faces<N, MODE, TPB>(a, sO, sR, sX);
   current(X, M, a.eta, Jd, Je);
   {
     MetricDeriv Dv;
@@ -131,18 +163,18 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
     }
     if (act && (id == 0 || id == N)) {
       const int s = (id == N) ? 1 : 0;
+      const int f = 2 * d + s;
+      const int tt = (d == 0) ? j + n * k : (d == 1 ? i + n * k : i + n * j);
       double Wx[NV], Jx[3];
-      Metric Mx;
-      external_state<N, CURVED, MODE>(a, e, 2 * d + s, i, j, k, X, M, Wx, Jx, Mx);
-      MetricT<R> Mxr;
-      metric_cast(Mx, Mxr);
+      external_state<N>(a, f, sO[f], sR[f], tt, sX, X, M, Wx, Jx);
       R Wr[NV], Jxr[3], Fx[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Wr[v] = (R)Wx[v];
 #pragma unroll
       for (int c = 0; c < 3; ++c) Jxr[c] = (R)Jx[c];
-      flux_any(d, Wr, Jxr, Mxr, Fx);
-      const R lam = CURVED ? (R)fmax(char_speed(d, M), char_speed(d, Mx)) : R(1);
+      flux_any(d, Wr, Jxr, Mr, Fx);
+      // Rusanov speed: the larger of the two sides', which share the metric
+      const R lam = CURVED ? (R)char_speed(d, M) : R(1);
       if (s == 0) {
         const R wl = (R)(sc / a.ops->w[0]);
         for (int v = 0; v < NV; ++v) {
