@@ -48,6 +48,7 @@ extern "C" {
 
 #define GRFFE_BC_PERIODIC 0
 #define GRFFE_BC_NO_INCOMING_POYNTING 1 /* Sec. III D */
+#define GRFFE_BC_DIRICHLET 2            /* exterior state held fixed: grffe_set_boundary_state */
 
 #define GRFFE_PART_EXPLICIT 1 /* fluxes + non-stiff sources */
 #define GRFFE_PART_STIFF 2    /* driver current + kappa damping (treated implicitly) */
@@ -70,7 +71,8 @@ extern "C" {
  * bc[2d + s] is the boundary kind of the lower (s = 0) / upper (s = 1) face
  * along direction d; periodic faces must come in pairs.  excised (host, E
  * bytes, nullable) removes elements: their faces towards live elements take the
- * no-incoming-Poynting state with the normal pointing into the hole. */
+ * no-incoming-Poynting state with the normal pointing into the hole (also when the
+ * grid's outer faces are Dirichlet faces). */
 typedef struct grffe_grid {
   int32_t n_elem[3];
   double lower[3];
@@ -117,6 +119,23 @@ void grffe_default_params(grffe_params* p);
  * The state is zero and every element is DG until set.  Returns the domain in *out. */
 int grffe_init_domain(const grffe_grid* grid, const grffe_params* params, const double* bg, void* stream,
                       grffe_domain** out);
+
+/* Exterior state of the grid's Dirichlet faces (the boundary condition of the
+ * one-dimensional test problems, Sec. IV A: both ends of the x axis).  state (host,
+ * [6][9], row f = 2d + s for the face of direction d and side s, components in the
+ * state's order, densitized) is copied into the domain; the row of each face of
+ * kind GRFFE_BC_DIRICHLET is the exterior state of the Rusanov flux at every DG node
+ * of that face and the value of all three ghost layers of FD elements on it (with
+ * its current J~ computed from it at the interior node's or cell's metric); the
+ * other rows are not read.  The state is uniform over the face: an analytic state
+ * that does not vary along the face and is constant in time at the face over the
+ * evolved interval.  Entry points that evaluate the right-hand side (steps, RHS,
+ * adjoints) return GRFFE_EINVAL on a domain with Dirichlet faces until this has
+ * been called.  The adjoints treat the exterior state as a constant.  Returns
+ * GRFFE_EINVAL for a NULL pointer or a non-finite value, GRFFE_EHIP if the copy
+ * fails; the call returns after the copy has completed (stream order is kept). */
+int grffe_set_boundary_state(grffe_domain* dom, const double* state, void* stream);
+
 int grffe_destroy(grffe_domain* dom);
 
 /* Set the state from FD subcell data u_fd (device, [9][E][m^3]), as at
@@ -267,7 +286,8 @@ int grffe_step_adjoint_frozen(grffe_domain* dom, const double* dg, const double*
  * on concurrent branches of a HIP graph that holds one step of the whole batch.
  * All grids share `params`; bgs (host array of `count` device pointers, each
  * [26][E_k][n_k^3] as for grffe_init_domain) is NULL for flat space, otherwise
- * every entry is non-NULL.  Domain k is addressed by its index in `grids`. */
+ * every entry is non-NULL.  Domain k is addressed by its index in `grids`.  Grids
+ * with Dirichlet faces are refused (GRFFE_EUNSUPPORTED). */
 typedef struct grffe_batch grffe_batch;
 int grffe_batch_create(const grffe_grid* grids, int32_t count, const grffe_params* params,
                        const double* const* bgs, void* stream, grffe_batch** out);

@@ -18,6 +18,7 @@ from .physics import Geometry
 
 BC_PERIODIC = 0
 BC_NO_INCOMING_POYNTING = 1
+BC_DIRICHLET = 2
 
 DG = 0
 FD = 1
@@ -28,7 +29,7 @@ def axis_of(d):
 
 
 class Domain:
-    def __init__(self, n_elem, lower, upper, degree, bc, excised=None, bg=None, params=None):
+    def __init__(self, n_elem, lower, upper, degree, bc, excised=None, bg=None, params=None, boundary_state=None):
         self.n_elem = tuple(int(v) for v in n_elem)
         self.lower = np.asarray(lower, np.float64)
         self.upper = np.asarray(upper, np.float64)
@@ -41,6 +42,11 @@ class Domain:
         self.excised = np.zeros(self.E, bool) if excised is None else np.asarray(excised).astype(bool)
         self.active = ~self.excised
         self.params = default_params() if params is None else {**default_params(), **params}
+        # Dirichlet faces (Sec. IV A, the 1D problems): a fixed exterior state per
+        # outer face f = 2 d + s, uniform over the face
+        self.boundary_state = None if boundary_state is None else np.asarray(boundary_state, np.float64).reshape(6, 9)
+        if any(b == BC_DIRICHLET for b in self.bc) and self.boundary_state is None:
+            raise ValueError("Dirichlet faces need boundary_state (6, 9)")
         self._build_neighbours()
         self._build_geometry(bg)
 
@@ -71,6 +77,15 @@ class Domain:
                         continue
                     nbr[e, 2 * d + s] = o
         self.nbr = nbr
+
+    def dirichlet_faces(self, elems, f):
+        """Mask over `elems`: face f of the element is an outer face of Dirichlet kind
+        (faces towards excised elements keep the no-incoming-Poynting state)."""
+        if self.bc[f] != BC_DIRICHLET:
+            return np.zeros(len(elems), bool)
+        d, s = divmod(f, 2)
+        c = np.array([self.coords(int(e))[d] for e in elems])
+        return c == (self.n_elem[d] - 1 if s else 0)
 
     # -------------------------------------------------------------- geometry
     def _build_geometry(self, bg):

@@ -22,7 +22,8 @@ Neighbour data across element faces: a DG neighbour's nodal trace; an FD
 neighbour seen from a DG element is reconstructed with R (x) R (x) R; a DG
 neighbour seen from an FD element is projected with P (x) P (x) P into three
 ghost layers; at domain boundaries the no-incoming-Poynting state (Sec. III D)
-is the external state / fills the ghost layers.
+is the external state / fills the ghost layers, except on Dirichlet faces
+(Sec. IV A), whose fixed exterior state plays that role.
 
 The densitized current J~ travels with U across DG<->FD interfaces: the
 state handed over is W = (U, J~(U)) with J~ evaluated where U lives, and the
@@ -50,6 +51,20 @@ def _slice_geo(geo, axis, idx):
     for k, v in vars(geo).items():
         setattr(g, k, np.take(v, idx, axis=axis))
     return g
+
+
+def exterior(dom, elems, f, Ui, gi):
+    """External state at the boundary face f of each element of `elems` from its
+    interior values Ui (9, len(elems), ...): the face's stored state on Dirichlet
+    faces, the no-incoming-Poynting state of Ui elsewhere."""
+    d, s = divmod(f, 2)
+    Ub = ph.boundary_state(Ui, gi, d, +1 if s else -1)
+    mask = dom.dirichlet_faces(elems, f)
+    if np.any(mask):
+        fixed = dom.boundary_state[f].reshape((9, 1) + (1,) * (Ui.ndim - 2))
+        sel = mask.reshape((1, -1) + (1,) * (Ui.ndim - 2))
+        Ub = np.where(sel, np.broadcast_to(fixed, Ui.shape), Ub)
+    return Ub
 
 
 def with_current(dom, U, geo):
@@ -104,7 +119,7 @@ def dg_rhs(dom, elems, W_dg, W_fd, rep, parts=3):
             oo = np.where(has, o, 0)
             Wx = _take_slice(nbr_dg[:, oo], ax, i_nbr)
             gx = _slice_geo(geo_take(dom.geo_dg, oo), ax, i_nbr)
-            Ub = ph.boundary_state(Ui, gi, d, +1 if s else -1)
+            Ub = exterior(dom, elems, f, Ui, gi)
             Wb = with_current(dom, Ub, gi)
             Wx = np.where(has[None, :, None, None], Wx, Wb)
             # metric of the external side: the neighbour's face node, or the interior node at a boundary
@@ -190,7 +205,7 @@ def ghost_extended(dom, elems, W_own, geo_own, W_dg, W_fd, rep, d):
         i_out = 0 if s == 0 else m - 1
         Ui = np.take(W_own[:9], [i_out], axis=ax)
         gi = _take_geo_idx(geo_own, ax, [i_out])
-        Ub = ph.boundary_state(Ui, gi, d, +1 if s else -1)
+        Ub = exterior(dom, elems, f, Ui, gi)
         Wb = np.repeat(with_current(dom, Ub, gi), 3, axis=ax)
         gb = _take_geo_idx(geo_own, ax, [i_out, i_out, i_out])
         mask = has[None, :, None, None, None]

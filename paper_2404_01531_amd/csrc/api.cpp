@@ -37,6 +37,14 @@ static int check_dom(grffe_domain* d) {
   return GRFFE_OK;
 }
 
+// A domain whose right-hand side can be evaluated: every Dirichlet face has its state.
+static int check_ready(grffe_domain* d) {
+  if (int rc = check_dom(d)) return rc;
+  if (d->bc_missing)
+    return fail(GRFFE_EINVAL, "the domain has Dirichlet faces: set their exterior state (grffe_set_boundary_state)");
+  return GRFFE_OK;
+}
+
 extern "C" const char* grffe_last_error(void) { return g_err.c_str(); }
 
 extern "C" void grffe_default_params(grffe_params* p) {
@@ -69,6 +77,7 @@ KArgs make_args(grffe_domain* d) {
   a.eh = d->eh;
   a.edt = d->edt;
   a.nbr = d->nbr;
+  a.bstate = d->bstate;
   a.live = d->live;
   a.bg_dg = d->bg_dg;
   a.bg_fd = d->bg_fd;
@@ -157,7 +166,7 @@ static int validate(const grffe_grid* g, const grffe_params* p) {
     if (!(g->upper[k] > g->lower[k])) return fail(GRFFE_EINVAL, "upper must exceed lower");
   }
   for (int k = 0; k < 6; ++k)
-    if (g->bc[k] != GRFFE_BC_PERIODIC && g->bc[k] != GRFFE_BC_NO_INCOMING_POYNTING)
+    if (g->bc[k] != GRFFE_BC_PERIODIC && g->bc[k] != GRFFE_BC_NO_INCOMING_POYNTING && g->bc[k] != GRFFE_BC_DIRICHLET)
       return fail(GRFFE_EINVAL, "unknown boundary kind");
   for (int d = 0; d < 3; ++d)
     if ((g->bc[2 * d] == GRFFE_BC_PERIODIC) != (g->bc[2 * d + 1] == GRFFE_BC_PERIODIC))
@@ -204,7 +213,10 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
     d->upper[k] = g0->upper[k];
     d->h[k] = (g0->upper[k] - g0->lower[k]) / g0->n_elem[k];
   }
-  for (int k = 0; k < 6; ++k) d->bc[k] = g0->bc[k];
+  for (int k = 0; k < 6; ++k) {
+    d->bc[k] = g0->bc[k];
+    if (d->bc[k] == GRFFE_BC_DIRICHLET) d->bc_missing |= 1 << k;
+  }
   d->par = *p;
   d->curved = curved;
   int E = 0;
@@ -239,6 +251,11 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
           int cc[3] = {c[0], c[1], c[2]};
           cc[dd] += sd ? 1 : -1;
           if (cc[dd] < 0 || cc[dd] >= ne[dd]) {
+            if (g->bc[2 * dd + sd] == GRFFE_BC_DIRICHLET) {
+              // slot of the face's exterior state (Dirichlet faces exist on single-grid domains only)
+              d->nbr_h[(size_t)(pt.off + e) * 6 + 2 * dd + sd] = -2 - (2 * dd + sd);
+              continue;
+            }
             if (g->bc[2 * dd + sd] != GRFFE_BC_PERIODIC) continue;
             cc[dd] = (cc[dd] + ne[dd]) % ne[dd];
           }
@@ -275,6 +292,7 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
     d->field = reinterpret_cast<decltype(d->field)>(ptr); \
   } while (0)
   ALLOC(nbr, sizeof(int32_t) * E * 6);
+  ALLOC(bstate, sizeof(double) * 6 * NV);
   ALLOC(live, E);
   ALLOC(eh, sizeof(double) * E * 3);
   ALLOC(edt, sizeof(double) * E);
@@ -320,6 +338,7 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
     }                                                                                        \
   } while (0)
   CHK(hipMemcpyAsync(d->nbr, d->nbr_h.data(), sizeof(int32_t) * E * 6, hipMemcpyHostToDevice, st));
+  CHK(hipMemsetAsync(d->bstate, 0, sizeof(double) * 6 * NV, st));
   CHK(hipMemcpyAsync(d->live, d->live_h.data(), E, hipMemcpyHostToDevice, st));
   CHK(hipMemcpyAsync(d->eh, d->eh_h.data(), sizeof(double) * E * 3, hipMemcpyHostToDevice, st));
   CHK(hipMemcpyAsync(d->ops, &ho, sizeof(DevOps), hipMemcpyHostToDevice, st));
@@ -387,6 +406,18 @@ extern "C" int grffe_init_domain(const grffe_grid* g, const grffe_params* p, con
   const grffe_grid* gs[1] = {g};
   const double* bs[1] = {bg};
   return build_pool(gs, 1, p, bs, S(stream), out);
+}
+
+extern "C" int grffe_set_boundary_state(grffe_domain* d, const double* state, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (!state) return fail(GRFFE_EINVAL, "state must not be NULL");
+  for (int k = 0; k < 6 * NV; ++k)
+    if (!std::isfinite(state[k])) return fail(GRFFE_EINVAL, "boundary state must be finite");
+  hipStream_t st = S(stream);
+  HIPCHK(hipMemcpyAsync(d->bstate, state, sizeof(double) * 6 * NV, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  d->bc_missing = 0;
+  return GRFFE_OK;
 }
 
 extern "C" int grffe_set_state(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep, void* stream) {
@@ -533,7 +564,7 @@ extern "C" int grffe_timing_read(grffe_domain* d, int family, double* total_ms, 
 
 extern "C" int grffe_rhs(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep, double* ddg,
                          double* dfd, int parts, void* stream) {
-  if (int rc = check_dom(d)) return rc;
+  if (int rc = check_ready(d)) return rc;
   if (!dg || !fd || !rep || !ddg || !dfd) return fail(GRFFE_EINVAL, "rhs pointers must not be NULL");
   if (parts < 1 || parts > 3) return fail(GRFFE_EINVAL, "parts must be 1, 2 or 3");
   hipStream_t st = S(stream);
@@ -569,7 +600,7 @@ static void step_once(grffe_domain* d, KArgs& a, hipStream_t st) {
 }
 
 extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream) {
-  if (int rc = check_dom(d)) return rc;
+  if (int rc = check_ready(d)) return rc;
   if (n_steps < 0) return fail(GRFFE_EINVAL, "n_steps must be >= 0");
   hipStream_t st = S(stream);
   KArgs a = make_args(d);
@@ -635,7 +666,7 @@ static int step_adjoint_space(grffe_domain* d, bool with_fd) {
 extern "C" int grffe_rhs_adjoint(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep,
                                  const double* lam_dg, const double* lam_fd, double* ubar_dg, double* ubar_fd,
                                  int parts, void* stream) {
-  if (int rc = check_dom(d)) return rc;
+  if (int rc = check_ready(d)) return rc;
   if (!dg || !fd || !rep || !lam_dg || !lam_fd || !ubar_dg || !ubar_fd)
     return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
   if (parts < 1 || parts > 3) return fail(GRFFE_EINVAL, "parts must be 1, 2 or 3");
@@ -664,7 +695,7 @@ extern "C" int grffe_rhs_adjoint(grffe_domain* d, const double* dg, const double
 
 extern "C" int grffe_step_adjoint(grffe_domain* d, const double* u_dg, const double* lam_next, double* lam,
                                   double dt, void* stream) {
-  if (int rc = check_dom(d)) return rc;
+  if (int rc = check_ready(d)) return rc;
   if (!u_dg || !lam_next || !lam) return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
   if (int rc = adjoint_supported(d)) return rc;
   hipStream_t st = S(stream);
@@ -689,7 +720,7 @@ extern "C" int grffe_step_adjoint(grffe_domain* d, const double* u_dg, const dou
 
 extern "C" int grffe_step_adjoint_stages(grffe_domain* d, const double* u_dg, const double* u3, const double* u4,
                                          const double* lam_next, double* lam, double dt, void* stream) {
-  if (int rc = check_dom(d)) return rc;
+  if (int rc = check_ready(d)) return rc;
   if (!u_dg || !u3 || !u4 || !lam_next || !lam) return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
   if (int rc = adjoint_supported(d)) return rc;
   if (int rc = step_adjoint_space(d, false)) return rc;
@@ -710,7 +741,7 @@ extern "C" int grffe_step_adjoint_stages(grffe_domain* d, const double* u_dg, co
 extern "C" int grffe_step_adjoint_frozen(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep,
                                          const double* mu_dg, const double* mu_fd, double* lam_dg, double* lam_fd,
                                          int32_t* rep_log, double dt, void* stream) {
-  if (int rc = check_dom(d)) return rc;
+  if (int rc = check_ready(d)) return rc;
   if (!dg || !fd || !rep || !mu_dg || !mu_fd || !lam_dg || !lam_fd)
     return fail(GRFFE_EINVAL, "adjoint pointers must not be NULL");
   if (int rc = adjoint_supported(d)) return rc;
@@ -963,6 +994,10 @@ extern "C" int grffe_batch_create(const grffe_grid* grids, int32_t count, const 
   if (!grids || !params || count < 1) return fail(GRFFE_EINVAL, "a batch needs at least one grid");
   for (int k = 0; k < count; ++k)
     if (grids[k].degree < 3 || grids[k].degree > MAX_DEG) return fail(GRFFE_EINVAL, "degree must be in 3..7");
+  for (int k = 0; k < count; ++k)
+    for (int f = 0; f < 6; ++f)
+      if (grids[k].bc[f] == GRFFE_BC_DIRICHLET)
+        return fail(GRFFE_EUNSUPPORTED, "Dirichlet faces are supported on single domains, not in batches");
   const bool curved = bgs && bgs[0];
   for (int k = 0; k < count; ++k)
     if ((bgs && bgs[k]) != curved) return fail(GRFFE_EINVAL, "a batch is all flat or all curved");

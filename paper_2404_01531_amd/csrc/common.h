@@ -89,6 +89,21 @@ __device__ inline void store9(double* base, int E, int P, int e, int p, const do
   for (int v = 0; v < NV; ++v) base[((size_t)v * E + e) * P + p] = U[v];
 }
 
+// Exterior state of a boundary face (neighbour entry o < 0 of face f): a Dirichlet
+// face (o = -2 - slot) holds the stored state bstate[slot]; any other boundary face
+// (o = -1: an outer face of the no-incoming-Poynting kind, or a face towards an
+// excised element) takes the no-incoming-Poynting state of the interior value Ui.
+__device__ inline void exterior_state(const KArgs& a, int o, int f, const double* Ui, const Metric& M,
+                                      double* Ub) {
+  if (o < -1) {
+    const double* s = a.bstate + (size_t)(-2 - o) * NV;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Ub[c] = s[c];
+  } else {
+    boundary_state(f >> 1, (f & 1) ? 1.0 : -1.0, Ui, M, Ub);
+  }
+}
+
 __device__ inline double dt_of(const KArgs& a, int e) { return a.dt > 0.0 ? a.dt : a.edt[e]; }
 __device__ inline double h_of(const KArgs& a, int e, int d) { return a.eh[3 * e + d]; }
 

@@ -9,6 +9,7 @@ struct CellSrc {
   const double* ptr;  // component 0; null for the computed boundary state
   size_t stride;      // between components
   int elem, cell;     // element / cell index used for the cell metric
+  int bnd;            // the face's neighbour entry (< 0) when ptr is null
 };
 
 template <int N>
@@ -33,6 +34,7 @@ __device__ inline CellSrc cell_source(const KArgs& a, int e, int d, int c, int t
     cs.elem = e;
     cs.ptr = nullptr;
     cs.stride = 0;
+    cs.bnd = o;
     return cs;
   }
   const int cn = s ? c - m : c + m;  // cell index inside the neighbour

@@ -61,7 +61,9 @@ struct KArgs {
   int E;
   const double* eh;        // [E][3] element widths
   const double* edt;       // [E] time step of the element's domain
-  const int32_t* nbr;      // [E][6], -1 at a boundary
+  const int32_t* nbr;      // [E][6]: neighbour, -1 at a no-incoming-Poynting boundary,
+                           // -2 - slot at a Dirichlet face (exterior state bstate[slot])
+  const double* bstate;    // [slots][9] exterior states of Dirichlet faces
   const uint8_t* live;     // [E]
   const double* bg_dg;     // [26][E][n^3] or null
   const double* bg_fd;     // [26][E][m^3] or null
@@ -111,11 +113,13 @@ struct grffe_domain {
   std::vector<grffe_part> parts;
   double lower[3], upper[3], h[3];
   int bc[6];
+  int bc_missing = 0;         // Dirichlet faces whose exterior state is not set (bit f)
   grffe_params par;
   bool curved;
   std::vector<int32_t> nbr_h;
   std::vector<uint8_t> live_h;
   int32_t* nbr = nullptr;
+  double* bstate = nullptr;   // [6][9] exterior states of the Dirichlet faces
   uint8_t* live = nullptr;
   double* eh = nullptr;   // [E][3]
   double* edt = nullptr;  // [E]

@@ -125,10 +125,13 @@ __device__ void operator_vjp(const KArgs& a, const AdjBufs& b, int e, int p, boo
         }
       }
       if (o < 0) {
-        // exterior state = no-incoming-Poynting state of X itself
-        bside[d] = s ? 1 : -1;
-        bA[d] = s ? -0.5 * wr : 0.5 * wl;
-        bI[d] = s ? 0.5 * wr * lam : 0.5 * wl * lam;
+        // exterior state = no-incoming-Poynting state of X itself (a Dirichlet face's
+        // exterior state is constant)
+        if (o == -1) {
+          bside[d] = s ? 1 : -1;
+          bA[d] = s ? -0.5 * wr : 0.5 * wl;
+          bI[d] = s ? 0.5 * wr * lam : 0.5 * wl * lam;
+        }
       } else if (upd[o] == 0) {
         // the neighbour updated on DG: its face term on its opposite face uses X as
         // exterior state

@@ -64,7 +64,7 @@ __device__ inline void external_state(const KArgs& a, int f, int o, int ro, int 
                                       const double* Ui, const Metric& Mi, double* Ux, double* Jx) {
   constexpr int nf = (N + 1) * (N + 1);
   if (o < 0) {
-    boundary_state(f >> 1, (f & 1) ? 1.0 : -1.0, Ui, Mi, Ux);
+    exterior_state(a, o, f, Ui, Mi, Ux);
     current_total(Ux, Mi, a.eta, Jx);
     return;
   }

@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "grffe.h")
 
 BC_PERIODIC = 0
 BC_NO_INCOMING_POYNTING = 1
+BC_DIRICHLET = 2
 PART_EXPLICIT, PART_STIFF, PART_ALL = 1, 2, 3
 HYBRID_DG_ONLY, HYBRID_ADAPTIVE, HYBRID_FORCED = 0, 1, 2
 KERNEL_FAMILIES = {"dg_substep": 1, "fd_flux": 2, "fd_update": 3, "fd_stage": 4, "fd_trace": 5,
@@ -77,6 +78,7 @@ def lib():
     L.grffe_default_params.argtypes = [ctypes.POINTER(Params)]
     L.grffe_default_params.restype = None
     L.grffe_init_domain.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
+    L.grffe_set_boundary_state.argtypes = [vp, ctypes.POINTER(dbl), vp]
     L.grffe_destroy.argtypes = [vp]
     L.grffe_init_from_fd.argtypes = [vp, vp, vp, vp]
     L.grffe_set_state.argtypes = [vp, vp, vp, vp, vp]
@@ -115,7 +117,7 @@ def lib():
                  "grffe_batch_init_from_fd", "grffe_batch_get_state", "grffe_batch_set_state",
                  "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step", "grffe_rhs_adjoint",
                  "grffe_step_adjoint", "grffe_step_adjoint_frozen", "grffe_get_stages",
-                 "grffe_step_adjoint_stages"):
+                 "grffe_step_adjoint_stages", "grffe_set_boundary_state"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -241,6 +243,13 @@ class Domain:
     def set_state(self, dg, fd, rep):
         self._check_state(dg, fd, rep)
         _check(lib().grffe_set_state(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _stream()))
+
+    def set_boundary_state(self, state):
+        """Exterior states of the Dirichlet faces: (6, 9) host array, row f = 2 d + s."""
+        st = np.ascontiguousarray(np.asarray(state, np.float64))
+        if st.shape != (6, 9):
+            raise GrffeError("boundary state must have shape (6, 9)")
+        _check(lib().grffe_set_boundary_state(self._h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
 
     def get_state(self):
         import torch

@@ -206,6 +206,68 @@ def current_sheet(x, width=0.05, half_length=1.0):
     return U
 
 
+def fast_wave_1d(x):
+    """Fast-wave problem (Appendix A): B = (1, B_y, 0), E = (0, 0, -B_y) with B_y = 1
+    for x < -0.1, 0.85 - 1.5 x for |x| < 0.1, 0.7 for x > 0.1 (flat space, so the
+    densitized and plain fields agree; div E = 0).  Exact solution Q(x - t)."""
+    x = np.asarray(x, np.float64)
+    by = np.where(x < -0.1, 1.0, np.where(x > 0.1, 0.7, 0.85 - 1.5 * x))
+    U = np.zeros((9,) + x.shape)
+    U[3] = 1.0
+    U[4] = by
+    U[2] = -by
+    return U
+
+
+def alfven_stationary_1d(x):
+    """Stationary Alfven wave (Appendix A): B = (1, 1, B_z), E = (-B_z, 0, 1) with
+    B_z = 1 for x < -0.1, 1.15 + 0.15 sin(5 pi x) for |x| < 0.1, 1.3 for x > 0.1;
+    q = d_x E_x = -dB_z/dx."""
+    x = np.asarray(x, np.float64)
+    inner = np.abs(x) < 0.1
+    bz = np.where(x < -0.1, 1.0, np.where(x > 0.1, 1.3, 1.15 + 0.15 * np.sin(5.0 * np.pi * x)))
+    dbz = np.where(inner, 0.75 * np.pi * np.cos(5.0 * np.pi * x), 0.0)
+    U = np.zeros((9,) + x.shape)
+    U[0] = -bz
+    U[2] = 1.0
+    U[3] = 1.0
+    U[4] = 1.0
+    U[5] = bz
+    U[8] = -dbz
+    return U
+
+
+def ffe_breakdown_1d(x):
+    """FFE breakdown problem (Appendix A): B = (1, b, b) with b = 1 for x < -0.1,
+    -10 x for |x| < 0.1, -1 for x > 0.1; E = (0, 0.5, -0.5); div E = 0."""
+    x = np.asarray(x, np.float64)
+    b = np.where(x < -0.1, 1.0, np.where(x > 0.1, -1.0, -10.0 * x))
+    U = np.zeros((9,) + x.shape)
+    U[1] = 0.5
+    U[2] = -0.5
+    U[3] = 1.0
+    U[4] = b
+    U[5] = b
+    return U
+
+
+def smooth_pulses_1d(x, amplitude=0.1, centres=(0.7, 0.3), half_width=0.2):
+    """Two vacuum fast-wave pulses on B = (1, 0, 0): B_y = A g(x - c0) + A g(x - c1),
+    E_z = -A g(x - c0) + A g(x - c1) (the first moves towards +x, the second towards
+    -x, both at the speed of light), g(s) = cos^8(pi s / (2 w)) for |s| < w."""
+    x = np.asarray(x, np.float64)
+
+    def g(s):
+        return np.where(np.abs(s) < half_width, np.cos(0.5 * np.pi * s / half_width) ** 8, 0.0)
+
+    gr, gl = amplitude * g(x - centres[0]), amplitude * g(x - centres[1])
+    U = np.zeros((9,) + x.shape)
+    U[3] = 1.0
+    U[4] = gr + gl
+    U[2] = -gr + gl
+    return U
+
+
 def add_noise_by_and_ez(U, seed, sigma=1e-3):
     """Independent noise on B_y and E_z at every point (drawn B_y first, then E_z)."""
     U = U.copy()
@@ -320,6 +382,11 @@ def sphere_quadrature(R=20.0, n_theta=32, n_phi=64):
 
 BC_PERIODIC = 0
 BC_NO_INCOMING_POYNTING = 1
+BC_DIRICHLET = 2
+
+_ONE_D = {"fast_wave_1d": ((-0.5, 1.5), 9.22e-4, fast_wave_1d),
+          "alfven_1d": ((-1.5, 1.5), 1.38e-3, alfven_stationary_1d),
+          "ffe_breakdown_1d": ((-0.5, 0.5), 4.61e-4, ffe_breakdown_1d)}
 
 
 def workload(name, **over):
@@ -336,10 +403,33 @@ def workload(name, **over):
         w = dict(n_elem=(16, 16, 16), lower=(-40.0,) * 3, upper=(40.0,) * 3, degree=5,
                  bc=(BC_NO_INCOMING_POYNTING,) * 6, eta=1e5, cfl=0.25, steps=1000, seed=1003,
                  curved=True, M=1.0, spin=0.9, B0=1.0, r_excise=1.8, kind="kerr_schild")
+    elif name in _ONE_D:
+        # one-dimensional problems (Sec. IV A, Table 1): 32 * 2^level elements of P5
+        # along x, one along y and z ([-0.1, 0.1], periodic), Dirichlet at both x ends
+        (x0, x1), _, _ = _ONE_D[name]
+        level = int(over.pop("level", 0))
+        w = dict(n_elem=(32 * 2 ** level, 1, 1), lower=(x0, -0.1, -0.1), upper=(x1, 0.1, 0.1), degree=5,
+                 bc=(BC_DIRICHLET, BC_DIRICHLET) + (BC_PERIODIC,) * 4, eta=1e6, cfl=0.3, curved=False,
+                 kind=name, level=level)
     else:
         raise ValueError(f"unknown workload {name!r}")
     w.update(over)
     return w
+
+
+def table1_dt(name, level=0):
+    """The time step Table 1 prints for a one-dimensional problem (x 2^-level)."""
+    return _ONE_D[name][1] * 2.0 ** -level
+
+
+def boundary_states(w):
+    """(6, 9) exterior states of a workload's Dirichlet faces: its initial data at the
+    two ends of the x axis (uniform over each face); rows of other faces are zero."""
+    out = np.zeros((6, 9))
+    for s, x in ((0, w["lower"][0]), (1, w["upper"][0])):
+        if w["bc"][s] == BC_DIRICHLET:
+            out[s] = initial_data(w, np.array([x]), np.zeros(1), np.zeros(1), with_noise=False)[:, 0]
+    return out
 
 
 def batch_workloads(count=64, seed=4, n_range=(4, 12), degree_range=(3, 7)):
@@ -380,6 +470,10 @@ def initial_data(w, x, y, z, with_noise=True):
         U = kerr_schild_uniform_field(x, y, z, w.get("M", 1.0), w.get("spin", 0.0), w.get("B0", 1.0))
     elif kind == "wald_a0":
         U = wald_a0(x, y, z, w.get("M", 1.0), w.get("B0", 1.0))
+    elif kind in _ONE_D:
+        U = _ONE_D[kind][2](x)
+    elif kind == "pulses_1d":
+        U = smooth_pulses_1d(x)
     else:
         raise ValueError(kind)
     if with_noise and kind in ("wave", "sheet"):

@@ -30,11 +30,15 @@ def make_pair(w, params=None):
     if w.get("curved"):
         x, y, z = node_coords(w)
         bg = I.background(w, x, y, z)
+    # Dirichlet faces hold the workload's initial data at the ends of the x axis
+    bstate = I.boundary_states(w) if I.BC_DIRICHLET in tuple(w["bc"]) else None
     odom = ODomain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], excised=exc, bg=bg,
-                   params=oracle_params(p))
+                   params=oracle_params(p), boundary_state=bstate)
     E, n = odom.E, odom.n
     bg_t = None if bg is None else torch.from_numpy(np.ascontiguousarray(bg.reshape(26, E, n ** 3))).cuda()
     ldom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], params=p, bg=bg_t, excised=exc)
+    if bstate is not None:
+        ldom.set_boundary_state(bstate)
     return odom, ldom, bg
 
 

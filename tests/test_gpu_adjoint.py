@@ -277,6 +277,19 @@ def test_mixed_rhs_adjoint_second_order_flux():
     _mixed_case(w, dict(eta=1e3, fd_order=2), dg, fd, "mixed wave P4 FD2", rng)
 
 
+def test_mixed_rhs_adjoint_dirichlet_faces():
+    """Dirichlet x faces (a fixed exterior state: no dependence on the state through
+    them) next to no-incoming-Poynting z faces, DG and FD elements mixed."""
+    _torch()
+    w = dict(n_elem=(3, 2, 2), lower=(-1.0, -0.5, -0.25), upper=(1.0, 0.75, 0.5), degree=4, bc=(2, 2, 0, 0, 1, 1),
+             curved=False, kind="alfven_1d")
+    rng = np.random.default_rng(59)
+    odom, _, _ = make_pair(w)
+    dg = _wave_state(odom, w, rng)
+    fd = _fd_state(odom, w, rng, 1e-4)
+    _mixed_case(w, dict(eta=50.0), dg, fd, "mixed P4 Dirichlet x faces", rng)
+
+
 def test_mixed_rhs_adjoint_kerr_schild():
     _torch()
     w = I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3)

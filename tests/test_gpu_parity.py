@@ -210,3 +210,52 @@ def test_step_dg_only_degree3():
 def test_step_kerr_schild_small():
     w = I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3)
     _run_steps(w, 2, dict(eta=w["eta"], cfl=w["cfl"]), label="kerr-schild 4^3 P5")
+
+
+# ------------------------------------------------- Dirichlet faces (the 1D problems)
+
+
+def test_rhs_dirichlet_faces_dg_and_fd():
+    """Dirichlet x faces with DG and FD elements on them: the DG face flux and the FD
+    ghost layers take the stored exterior state (a noisy interior, so the face terms
+    do not vanish)."""
+    w = I.workload("fast_wave_1d", n_elem=(4, 1, 1))
+    odom, ldom, _ = make_pair(w, dict(eta=w["eta"], cfl=w["cfl"]))
+    rng = np.random.default_rng(1102)
+    for rep in ([1, 0, 0, 1], [0, 1, 1, 0], [0, 0, 0, 0], [1, 1, 1, 1]):
+        rep = np.array(rep, np.int64)
+        dg, fd = _state_arrays(odom, rng, rep)
+        _compare_rhs(odom, ldom, dg, fd, rep, 3, label=f"dirichlet faces, rep {rep.tolist()}")
+
+
+def test_step_fast_wave_dirichlet():
+    """The fast-wave problem (kinks on FD) on 8 x 1 x 1 elements between Dirichlet faces."""
+    w = I.workload("fast_wave_1d", n_elem=(8, 1, 1))
+    st, _ = _run_steps(w, 6, dict(eta=w["eta"], cfl=w["cfl"]), label="fast wave 8x1x1 P5, Dirichlet x faces")
+    assert (st.rep == FD).any()
+
+
+def test_step_pulses_through_dirichlet_faces():
+    """Two vacuum pulses reaching the Dirichlet faces (4 x 1 x 1 elements, 40 steps)."""
+    w = I.workload("fast_wave_1d", n_elem=(4, 1, 1), lower=(0.0, -0.125, -0.125), upper=(1.0, 0.125, 0.125),
+                   kind="pulses_1d")
+    _run_steps(w, 40, dict(eta=w["eta"], cfl=w["cfl"]), label="pulses through Dirichlet faces")
+
+
+def test_dirichlet_state_required_and_checked():
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    w = I.workload("fast_wave_1d", n_elem=(4, 1, 1))
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], 5, w["bc"], params=dict(eta=w["eta"], cfl=w["cfl"]))
+    with pytest.raises(grffe.GrffeError, match="Dirichlet"):
+        dom.step(1)
+    bad = I.boundary_states(w)
+    bad[0, 2] = np.nan
+    with pytest.raises(grffe.GrffeError, match="finite"):
+        dom.set_boundary_state(bad)
+    dom.set_boundary_state(I.boundary_states(w))
+    dom.step(1)
+    torch.cuda.synchronize()
+    dom.close()
+    with pytest.raises(grffe.GrffeError, match="batches"):
+        grffe.Batch([dict(n_elem=w["n_elem"], lower=w["lower"], upper=w["upper"], degree=5, bc=w["bc"])])
