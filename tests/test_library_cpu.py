@@ -61,6 +61,7 @@ def _grid(**over):
 @pytest.mark.parametrize("bad, code", [
     (dict(degree=2), -1), (dict(degree=8), -1), (dict(n_elem=(0, 2, 2)), -1),
     (dict(upper=(1.0, -1.0, 1.0)), -1), (dict(bc=(0, 1, 0, 0, 0, 0)), -1), (dict(bc=(0, 0, 7, 7, 0, 0)), -1),
+    (dict(bc=(2, 0, 0, 0, 0, 0)), -1), (dict(bc=(3, 3, 0, 0, 0, 0)), -1),
 ])
 def test_init_domain_rejects_bad_grids(bad, code):
     """Validation happens before any device call, so it runs without a GPU."""
@@ -102,6 +103,18 @@ def test_null_handles_are_rejected():
     assert L.grffe_batch_step(None, 1, 1, None) == -1
     d = ctypes.c_double()
     assert L.grffe_batch_get_dt(None, 0, ctypes.byref(d)) == -1
+
+
+def test_dirichlet_entry_points_on_the_host():
+    L = grffe.lib()
+    state = (ctypes.c_double * 54)()
+    assert L.grffe_set_boundary_state(None, state, None) == -1
+    p = grffe.default_params()
+    h = ctypes.c_void_p()
+    arr = (grffe.Grid * 1)(_grid(bc=(2, 2, 0, 0, 0, 0)))
+    # batches refuse Dirichlet grids before touching the device
+    assert L.grffe_batch_create(arr, 1, ctypes.byref(p), None, None, ctypes.byref(h)) == -5
+    assert "Dirichlet" in L.grffe_last_error().decode()
 
 
 def test_adjoint_entry_points_reject_null_handles():
