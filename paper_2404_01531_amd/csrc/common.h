@@ -89,19 +89,20 @@ __device__ inline void store9(double* base, int E, int P, int e, int p, const do
   for (int v = 0; v < NV; ++v) base[((size_t)v * E + e) * P + p] = U[v];
 }
 
-// Exterior state of a boundary face (neighbour entry o < 0 of face f): a Dirichlet
-// face (o = -2 - slot) holds the stored state bstate[slot]; any other boundary face
-// (o = -1: an outer face of the no-incoming-Poynting kind, or a face towards an
-// excised element) takes the no-incoming-Poynting state of the interior value Ui.
-__device__ inline void exterior_state(const KArgs& a, int o, int f, const double* Ui, const Metric& M,
+// Exterior state of a boundary face (neighbour entry o < 0 of the face of direction d
+// and side s): a Dirichlet face (o = -2 - slot) holds the stored state bstate[slot];
+// any other boundary face (o = -1: an outer face of the no-incoming-Poynting kind, or
+// a face towards an excised element) takes the no-incoming-Poynting state of the
+// interior value Ui.
+__device__ inline void exterior_state(const KArgs& a, int o, int d, int s, const double* Ui, const Metric& M,
                                       double* Ub) {
-  if (o < -1) {
-    const double* s = a.bstate + (size_t)(-2 - o) * NV;
+  // branch-free, so that Ub stays in registers: both states are formed and the
+  // Dirichlet one selected (slot 0, always allocated, is read and unused elsewhere)
+  boundary_state(d, s ? 1.0 : -1.0, Ui, M, Ub);
+  const bool dir = o < -1;
+  const double* st = a.bstate + (size_t)(dir ? -2 - o : 0) * NV;
 #pragma unroll
-    for (int c = 0; c < NV; ++c) Ub[c] = s[c];
-  } else {
-    boundary_state(f >> 1, (f & 1) ? 1.0 : -1.0, Ui, M, Ub);
-  }
+  for (int c = 0; c < NV; ++c) Ub[c] = dir ? st[c] : Ub[c];
 }
 
 __device__ inline double dt_of(const KArgs& a, int e) { return a.dt > 0.0 ? a.dt : a.edt[e]; }

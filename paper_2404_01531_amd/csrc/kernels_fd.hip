@@ -345,7 +345,7 @@ __global__ __launch_bounds__(FLUX_TPB) void k_fd_flux(KArgs a) {
       double Ui[NV], Ub[NV], J[3];
       load_metric<CURVED>(a.bg_fd, a.E, mm, e, cs.cell, Mc);
       load9(a.w_fd, a.E, mm, e, cs.cell, Ui);
-      exterior_state(a, cs.bnd, 2 * d + ((c >= m + 3) ? 1 : 0), Ui, Mc, Ub);
+      exterior_state(a, cs.bnd, d, (c >= m + 3) ? 1 : 0, Ui, Mc, Ub);
       current_total(Ub, Mc, a.eta, J);
 #pragma unroll
       for (int k = 0; k < NV; ++k) W[k] = Ub[k];

@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_fd_adj_flux(KArgs a, FdAdj b) {
         double Ui[NV], Ub[NV], J[3];
         load_metric<CURVED>(a.bg_fd, a.E, mm, e, cs.cell, Mc);
         load9(a.w_fd, a.E, mm, e, cs.cell, Ui);
-        exterior_state(a, cs.bnd, 2 * d + ((c >= m + 3) ? 1 : 0), Ui, Mc, Ub);
+        exterior_state(a, cs.bnd, d, (c >= m + 3) ? 1 : 0, Ui, Mc, Ub);
         current_total(Ub, Mc, a.eta, J);
 #pragma unroll
         for (int k = 0; k < NV; ++k) W[k] = Ub[k];
@@ -297,9 +297,12 @@ __global__ __launch_bounds__(256) void k_fd_adj_flux(KArgs a, FdAdj b) {
         const int s = (c >= m) ? 1 : 0;
         const int l = s ? (c - m) : (-1 - c);
         const int f = 2 * d + s;
+        // the ghosts of a Dirichlet face are constants: their adjoints are dropped
+        const bool fixed = a.nbr[e * 6 + f] < -1;
 #pragma unroll
         for (int k = 0; k < NR; ++k)
-          b.gbar[((((size_t)k * a.E + e) * 6 + f) * 3 + l) * (m * m) + t1 + m * t2] = sWb[(k * C + x) * L + t1];
+          b.gbar[((((size_t)k * a.E + e) * 6 + f) * 3 + l) * (m * m) + t1 + m * t2] =
+              fixed ? 0.0 : sWb[(k * C + x) * L + t1];
       }
     }
     __syncthreads();  // the next item restages the tiles
@@ -309,8 +312,9 @@ __global__ __launch_bounds__(256) void k_fd_adj_flux(KArgs a, FdAdj b) {
 // At FD cell p of element e:  ub = (dL_ex/dX)^T V + (dS_stiff/dX)^T W, with X the
 // cell's value (the stage value staged in w_fd).  The explicit part gathers the
 // three directions' transported-component adjoints, the ghost adjoints the FD
-// neighbours wrote for this cell (or, at a no-incoming-Poynting boundary, this
-// element's own ghosts through that state; a DG neighbour reads this cell
+// neighbours wrote for this cell (or, at a physical boundary, this element's own
+// ghosts through the no-incoming-Poynting state; those of a Dirichlet face are
+// zero, as its ghosts do not depend on the state; a DG neighbour reads this cell
 // through its R-trace, whose transpose is already in wbar), the current's gradient
 // and the sources; use_v / use_w switch the two parts off.
 template <int N, bool CURVED>
@@ -354,9 +358,8 @@ __device__ inline void fd_cell_vjp(const KArgs& a, const FdAdj& b, int e, int p,
             if (k < NV) ub[k] += g;
             else wJ[d] += g;
           }
-        } else if (l == 0 && o == -1) {
+        } else if (l == 0) {
           // own ghosts: the no-incoming-Poynting state of this cell in all three layers
-          // (a Dirichlet face's ghosts are constant)
           double G10[NR];
 #pragma unroll
           for (int k = 0; k < NR; ++k) {
