@@ -230,24 +230,17 @@ __global__ __launch_bounds__(256) void k_project_troubled(KArgs a) {
 // (beta_k + eps))^2) with tau5 = |beta_0 - beta_2| (exponent q = 2).  With
 // b_k = beta_k + eps the normalised combination sum alpha_k q_k / sum alpha_k is
 // evaluated after multiplying numerator and denominator by b_0^2 b_1^2 b_2^2,
-// which leaves a single division.
-__device__ inline double weno5z(double vm2, double vm1, double v0, double vp1, double vp2, double eps) {
-  const double q0 = (3.0 * vm2 - 10.0 * vm1 + 15.0 * v0) * 0.125;
-  const double q1 = (-vm1 + 6.0 * v0 + 3.0 * vp1) * 0.125;
-  const double q2 = (3.0 * v0 + 6.0 * vp1 - vp2) * 0.125;
-  const double d0 = vm2 - 2.0 * vm1 + v0, e0 = vm2 - 4.0 * vm1 + 3.0 * v0;
-  const double d1 = vm1 - 2.0 * v0 + vp1, e1 = vm1 - vp1;
-  const double d2 = v0 - 2.0 * vp1 + vp2, e2 = 3.0 * v0 - 4.0 * vp1 + vp2;
-  const double b0 = (13.0 / 12.0) * d0 * d0 + 0.25 * e0 * e0 + eps;
-  const double b1 = (13.0 / 12.0) * d1 * d1 + 0.25 * e1 * e1 + eps;
-  const double b2 = (13.0 / 12.0) * d2 * d2 + 0.25 * e2 * e2 + eps;
-  const double tau = fabs(b0 - b2);
-  const double t2 = tau * tau;
-  const double s0 = b0 * b0, s1 = b1 * b1, s2 = b2 * b2;
-  const double w0 = (1.0 / 16.0) * (s0 + t2) * (s1 * s2);
-  const double w1 = (10.0 / 16.0) * (s1 + t2) * (s0 * s2);
-  const double w2 = (5.0 / 16.0) * (s2 + t2) * (s0 * s1);
-  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+// which leaves a single quotient.
+
+// n / d for the WENO normalisation, whose denominator is positive and in the normal
+// range (at least eps^6 / 16): the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r (2 - d r), then one multiplication (within about one
+// unit in the last place of the correctly rounded quotient).
+__device__ inline double div_weno(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return n * r;
 }
 
 // Both WENO5-Z reconstructions whose target cell is c, from the five point
@@ -256,8 +249,8 @@ __device__ inline double weno5z(double vm2, double vm1, double v0, double vp1, d
 // smoothness indicators of the target cell (the mirrored reconstruction sees
 // beta_0 and beta_2 swapped) and tau5 = |beta_0 - beta_2|.  Z weights with
 // exponent 2, optimal weights (1, 10, 5)/16, candidates are quadratic Lagrange
-// interpolants of point values; the normalisation is done with one division
-// per state after multiplying by b_0^2 b_1^2 b_2^2, b_k = beta_k + eps.
+// interpolants of point values; the normalisation is done with one quotient
+// (div_weno) per state after multiplying by b_0^2 b_1^2 b_2^2, b_k = beta_k + eps.
 __device__ inline void weno5z_cell(const double* v, double eps, double& left, double& right) {
   const double d0 = v[0] - 2.0 * v[1] + v[2], e0 = v[0] - 4.0 * v[1] + 3.0 * v[2];
   const double d1 = v[1] - 2.0 * v[2] + v[3], e1 = v[1] - v[3];
@@ -277,7 +270,7 @@ __device__ inline void weno5z_cell(const double* v, double eps, double& left, do
     const double q0 = (3.0 * v[0] - 10.0 * v[1] + 15.0 * v[2]) * 0.125;
     const double q1 = (-v[1] + 6.0 * v[2] + 3.0 * v[3]) * 0.125;
     const double q2 = (3.0 * v[2] + 6.0 * v[3] - v[4]) * 0.125;
-    left = (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+    left = div_weno(w0 * q0 + w1 * q1 + w2 * q2, w0 + w1 + w2);
   }
   {
     const double w0 = (1.0 / 16.0) * a2 * p01;
@@ -286,7 +279,7 @@ __device__ inline void weno5z_cell(const double* v, double eps, double& left, do
     const double q0 = (3.0 * v[4] - 10.0 * v[3] + 15.0 * v[2]) * 0.125;
     const double q1 = (-v[3] + 6.0 * v[2] + 3.0 * v[1]) * 0.125;
     const double q2 = (3.0 * v[2] + 6.0 * v[1] - v[0]) * 0.125;
-    right = (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+    right = div_weno(w0 * q0 + w1 * q1 + w2 * q2, w0 + w1 + w2);
   }
 }
 

@@ -84,6 +84,22 @@ def test_alfven_wave_stationary():
     assert errs[2] < errs[1] < errs[0]
 
 
+def test_ffe_breakdown_converges_to_reference():
+    """No closed form: as in the paper, the run with 256 elements (level 3) is the
+    reference; B_z at t = 0.02 (before the layer reaches breakdown) approaches it as
+    the grid is refined.  The finer run's points are compared at the coarser run's
+    points by linear interpolation of the reference along x."""
+    ref_X, ref_U, _ = _run("ffe_breakdown_1d", 3, 0.02)
+    order = np.argsort(ref_X)
+    rx, rbz = ref_X[order], ref_U[5][order]
+    errs = []
+    for level in (0, 1, 2):
+        X, U, t = _run("ffe_breakdown_1d", level, 0.02)
+        errs.append(np.abs(U[5] - np.interp(X, rx, rbz)).mean())
+        _say(f"FFE breakdown level {level}: t = {t:.4f}, mean |B_z - reference| {errs[-1]:.2e}")
+    assert errs[1] < errs[0] and errs[2] < errs[1]
+
+
 def test_ffe_breakdown_magnetic_dominance():
     for level in (0, 1):
         X, U, t = _run("ffe_breakdown_1d", level, 0.04)

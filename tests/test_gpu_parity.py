@@ -259,3 +259,20 @@ def test_dirichlet_state_required_and_checked():
     dom.close()
     with pytest.raises(grffe.GrffeError, match="batches"):
         grffe.Batch([dict(n_elem=w["n_elem"], lower=w["lower"], upper=w["upper"], degree=5, bc=w["bc"])])
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_step_dirichlet_ragged_degrees_forced_partition(N):
+    """Dirichlet x faces on degrees 3 and 4 with a forced partition: FD elements on
+    both Dirichlet faces and in the middle.  The fast wave at its own eta = 1e6; the
+    stationary Alfven wave at eta = 1e3: its layer carries a parallel current that
+    the driver term holds at E.B ~ J.B B^2 / eta, and with eta dt ~ 1e3 the last-bit
+    differences of E.B grow to ~1e-9 of the field scale within four steps (the
+    problem itself runs at eta = 1e6 in the exact-solution tests)."""
+    w = I.workload("fast_wave_1d", n_elem=(8, 1, 1), degree=N)
+    _run_steps(w, 4, dict(eta=w["eta"], cfl=w["cfl"], hybrid=2), forced=np.array([1, 0, 0, 1, 0, 0, 0, 1], bool),
+               label=f"fast wave P{N}, Dirichlet x faces, forced partition")
+    w = I.workload("alfven_1d", n_elem=(10, 1, 1), degree=N)
+    _run_steps(w, 4, dict(eta=1e3, cfl=w["cfl"], hybrid=2),
+               forced=np.array([1, 0, 0, 0, 1, 0, 0, 0, 0, 1], bool),
+               label=f"Alfven wave P{N}, Dirichlet x faces, forced partition")
