@@ -412,6 +412,18 @@ def _frozen_step_case(w, params, dg, fd, label, rng, all_fd=False, tol=TOL_FD):
     assert err_g <= tol, label
 
 
+def test_frozen_step_adjoint_mixed_dirichlet_faces():
+    """One frozen-partition step between Dirichlet x faces (DG and FD elements on
+    them), z faces of the no-incoming-Poynting kind."""
+    _torch()
+    w = dict(n_elem=(3, 2, 2), lower=(-1.0, -0.5, -0.25), upper=(1.0, 0.75, 0.5), degree=4, bc=(2, 2, 0, 0, 1, 1),
+             curved=False, kind="alfven_1d")
+    rng = np.random.default_rng(79)
+    odom, _, _ = make_pair(w)
+    _frozen_step_case(w, dict(eta=300.0, cfl=0.25), _wave_state(odom, w, rng), _fd_state(odom, w, rng, 1e-4),
+                      "mixed P4 Dirichlet x faces", rng)
+
+
 def test_frozen_step_adjoint_mixed_flat():
     _torch()
     w = dict(I.workload("wave", n_elem=(3, 2, 2)), kind="wave")
@@ -568,6 +580,15 @@ def test_step_adjoint_no_filter_boundaries_p4():
     rng = np.random.default_rng(52)
     odom, _, _ = make_pair(w)
     _step_case(w, dict(eta=300.0, cfl=0.25, filter_on=0), _wave_state(odom, w, rng), "P4 outflow, no filter", rng)
+
+
+def test_step_adjoint_dirichlet_faces():
+    _torch()
+    w = dict(n_elem=(3, 2, 2), lower=(-1.0, -1.0, -1.0), upper=(1.0, 1.0, 1.0), degree=4, bc=(2, 2, 0, 0, 1, 1),
+             curved=False, kind="alfven_1d")
+    rng = np.random.default_rng(53)
+    odom, _, _ = make_pair(w)
+    _step_case(w, dict(eta=300.0, cfl=0.25), _wave_state(odom, w, rng), "P4 Dirichlet x faces", rng)
 
 
 def test_step_adjoint_kerr_schild():
