@@ -28,7 +28,8 @@
  *  - Return value: GRFFE_OK (0) or a negative status; the message of the last
  *    failure on the calling thread is returned by grffe_last_error().  No
  *    implicit device synchronisation happens except where a host value is
- *    returned (grffe_get_dt, grffe_get_counts).
+ *    returned (grffe_get_dt, grffe_get_counts, grffe_timing_read) and in
+ *    grffe_set_boundary_state, which waits for its host-to-device copy.
  *  - A domain is not thread-safe; separate domains are independent.
  */
 #ifndef GRFFE_H
