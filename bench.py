@@ -468,6 +468,57 @@ def run_forced_fractions_alfven(steps, warmup):
                         "Dirichlet x faces, partition forced with the lowest-y elements on FD (fp64)", **r}
 
 
+def run_accuracy_smooth_wave(crossings=20):
+    """The paper's accuracy comparison of the DG and FD grids: the smooth fast wave
+    (E_z = -B_y = sin(pi x), lambda = 2) on [0, 2]^3 with 4^3 P5 elements, periodic,
+    evolved for `crossings` crossing times with every element on DG (filtered and
+    unfiltered) or every element on FD (with and without the fourth-order
+    corrector).  Reported: the RMS over the grid points of |B - B_exact| after each
+    crossing, B_exact(x, t) = B(x - t, 0).  The time step is the CFL step rounded
+    down to a whole number of steps per crossing."""
+    import numpy as np
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    w = I.workload("smooth_fast_wave")
+    N = w["degree"]
+    E = int(np.prod(w["n_elem"]))
+    n3, m3 = (N + 1) ** 3, (2 * N + 1) ** 3
+    x, y, z = _dg_nodes(w)
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], N)
+    lam = w["wavelength"]
+    variants = (("dg_filtered", dict(hybrid=grffe.HYBRID_DG_ONLY)),
+                ("dg_unfiltered", dict(hybrid=grffe.HYBRID_DG_ONLY, filter_on=0)),
+                ("fd4", dict(hybrid=grffe.HYBRID_FORCED, fd_order=4)),
+                ("fd2", dict(hybrid=grffe.HYBRID_FORCED, fd_order=2)))
+    out = {}
+    for name, over in variants:
+        p = grffe.default_params(eta=w["eta"], cfl=w["cfl"], **over)
+        dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p)
+        on_fd = over["hybrid"] == grffe.HYBRID_FORCED
+        u_dg = torch.from_numpy(np.ascontiguousarray(I.initial_data(w, x, y, z).reshape(9, E, n3))).cuda()
+        u_fd = torch.from_numpy(np.ascontiguousarray(I.initial_data(w, xf, yf, zf).reshape(9, E, m3))).cuda()
+        dom.set_state(u_dg, u_fd, torch.full((E,), 1 if on_fd else 0, dtype=torch.int32, device="cuda"))
+        per = int(np.ceil(lam / dom.dt()))
+        dt = lam / per
+        xs = (xf if on_fd else x).reshape(E, -1)
+        errs = []
+        t0 = time.perf_counter()
+        for k in range(1, crossings + 1):
+            dom.step(per, dt)
+            g, f, _ = dom.get_state()
+            u = (f if on_fd else g).cpu().numpy().reshape(9, E, -1)
+            ex = I.smooth_fast_wave(xs - k * lam, lam)  # periodic: x - k lambda is x
+            errs.append(float(np.sqrt(np.mean((u[3:6] - ex[3:6]) ** 2))))
+        torch.cuda.synchronize()
+        out[name] = {"rms_B_error_per_crossing": errs, "steps_per_crossing": per, "dt": dt,
+                     "secs": time.perf_counter() - t0}
+        dom.close()
+    return {"workload": "smooth fast wave E_z = -B_y = sin(pi x) on [0,2]^3 periodic, 4^3 DG-P5 / FD 11^3 elements, "
+                        "eta 1e6, CFL 0.3 (the paper's accuracy comparison of the DG and FD grids)", **out}
+
+
 def run_adjoint_frozen(steps=40, every=20):
     """The benchmark's current sheet, 8^3 P5 elements, with the start-up DG/FD
     partition held fixed (forced mode): forward steps, one-step adjoints through DG
@@ -595,6 +646,7 @@ def main():
                          ("batch_64_fp64", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0)),
                          ("batch_64_mixed", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 1)),
                          ("sheet_element_sweep_16^3_32^3", lambda: run_sheet_sweep(args.extra_steps, 2)),
+                         ("accuracy_smooth_fast_wave_4^3", lambda: run_accuracy_smooth_wave(20)),
                          ("forced_fd_fraction_sheet_8^3", lambda: run_forced_fractions_sheet(args.extra_steps, 2)),
                          ("forced_fd_fraction_alfven_8x32x8",
                           lambda: run_forced_fractions_alfven(args.extra_steps, 2)),

@@ -251,6 +251,19 @@ def ffe_breakdown_1d(x):
     return U
 
 
+def smooth_fast_wave(x, wavelength=2.0):
+    """The fast wave made smooth (Sec. IV D 1, accuracy comparison): B = (1, -s, 0),
+    E = (0, 0, s) with s = sin(2 pi x / wavelength); a vacuum mode moving towards +x
+    at the speed of light, exact solution Q(x - t) (periodic)."""
+    x = np.asarray(x, np.float64)
+    sn = np.sin(2.0 * np.pi * x / wavelength)
+    U = np.zeros((9,) + x.shape)
+    U[3] = 1.0
+    U[4] = -sn
+    U[2] = sn
+    return U
+
+
 def smooth_pulses_1d(x, amplitude=0.1, centres=(0.7, 0.3), half_width=0.2):
     """Two vacuum fast-wave pulses on B = (1, 0, 0): B_y = A g(x - c0) + A g(x - c1),
     E_z = -A g(x - c0) + A g(x - c1) (the first moves towards +x, the second towards
@@ -403,6 +416,9 @@ def workload(name, **over):
         w = dict(n_elem=(16, 16, 16), lower=(-40.0,) * 3, upper=(40.0,) * 3, degree=5,
                  bc=(BC_NO_INCOMING_POYNTING,) * 6, eta=1e5, cfl=0.25, steps=1000, seed=1003,
                  curved=True, M=1.0, spin=0.9, B0=1.0, r_excise=1.8, kind="kerr_schild")
+    elif name == "smooth_fast_wave":  # Sec. IV D 1: [0, 2]^3, 4^3 P5 elements, periodic
+        w = dict(n_elem=(4, 4, 4), lower=(0.0,) * 3, upper=(2.0,) * 3, degree=5, bc=(BC_PERIODIC,) * 6, eta=1e6,
+                 cfl=0.3, curved=False, kind="smooth_fast_wave", wavelength=2.0)
     elif name in _ONE_D:
         # one-dimensional problems (Sec. IV A, Table 1): 32 * 2^level elements of P5
         # along x, one along y and z ([-0.1, 0.1], periodic), Dirichlet at both x ends
@@ -474,6 +490,8 @@ def initial_data(w, x, y, z, with_noise=True):
         U = _ONE_D[kind][2](x)
     elif kind == "pulses_1d":
         U = smooth_pulses_1d(x)
+    elif kind == "smooth_fast_wave":
+        U = smooth_fast_wave(x, w.get("wavelength", 2.0))
     else:
         raise ValueError(kind)
     if with_noise and kind in ("wave", "sheet"):
