@@ -137,6 +137,19 @@ int grffe_init_domain(const grffe_grid* grid, const grffe_params* params, const 
  * fails; the call returns after the copy has completed (stream order is kept). */
 int grffe_set_boundary_state(grffe_domain* dom, const double* state, void* stream);
 
+/* Exterior states of the Dirichlet faces given point by point (an analytic state
+ * that varies along the face, constant in time), in place of the uniform rows of
+ * grffe_set_boundary_state: ext_dg (device, [9][E][6][n^2]) holds the state at
+ * every DG face node, node t1 + n t2 of face f of element e with (t1, t2) the
+ * node's indices along the face's two tangential axes in increasing axis order;
+ * ext_fd (device, [9][E][6][3][m^2]) the state at every FD ghost cell, layer
+ * l = 0, 1, 2 counted outwards from face f, cell t1 + m t2.  Entries of faces that
+ * are not Dirichlet faces are not read.  Both arrays are copied into the domain
+ * (allocated at the first call) on `stream`; a later grffe_set_boundary_state
+ * does not undo this.  Returns GRFFE_EINVAL for NULL pointers, GRFFE_ENOMEM,
+ * GRFFE_EHIP. */
+int grffe_set_boundary_field(grffe_domain* dom, const double* ext_dg, const double* ext_fd, void* stream);
+
 int grffe_destroy(grffe_domain* dom);
 
 /* Set the state from FD subcell data u_fd (device, [9][E][m^3]), as at

@@ -29,7 +29,8 @@ def axis_of(d):
 
 
 class Domain:
-    def __init__(self, n_elem, lower, upper, degree, bc, excised=None, bg=None, params=None, boundary_state=None):
+    def __init__(self, n_elem, lower, upper, degree, bc, excised=None, bg=None, params=None, boundary_state=None,
+                 boundary_field=None):
         self.n_elem = tuple(int(v) for v in n_elem)
         self.lower = np.asarray(lower, np.float64)
         self.upper = np.asarray(upper, np.float64)
@@ -45,8 +46,16 @@ class Domain:
         # Dirichlet faces (Sec. IV A, the 1D problems): a fixed exterior state per
         # outer face f = 2 d + s, uniform over the face
         self.boundary_state = None if boundary_state is None else np.asarray(boundary_state, np.float64).reshape(6, 9)
-        if any(b == BC_DIRICHLET for b in self.bc) and self.boundary_state is None:
-            raise ValueError("Dirichlet faces need boundary_state (6, 9)")
+        # or point by point (an analytic state varying along the face): the state at
+        # every DG face node (9, E, 6, n^2) and at every FD ghost cell (9, E, 6, 3, m^2),
+        # node or cell t1 + n t2 (t1 along the lower tangential axis), layer l counted
+        # outwards from the face
+        self.boundary_field = None
+        if boundary_field is not None:
+            bd, bf = boundary_field
+            self.boundary_field = (np.asarray(bd, np.float64), np.asarray(bf, np.float64))
+        if any(b == BC_DIRICHLET for b in self.bc) and self.boundary_state is None and self.boundary_field is None:
+            raise ValueError("Dirichlet faces need boundary_state (6, 9) or boundary_field")
         self._build_neighbours()
         self._build_geometry(bg)
 

@@ -53,17 +53,28 @@ def _slice_geo(geo, axis, idx):
     return g
 
 
-def exterior(dom, elems, f, Ui, gi):
+def exterior(dom, elems, f, Ui, gi, layer=None):
     """External state at the boundary face f of each element of `elems` from its
-    interior values Ui (9, len(elems), ...): the face's stored state on Dirichlet
-    faces, the no-incoming-Poynting state of Ui elsewhere."""
+    interior values Ui (9, len(elems), ...): the stored state on Dirichlet faces
+    (the face's uniform row, or the point's entry of the per-point field: at the
+    face nodes for a DG face, layer `layer` of the ghost cells for an FD face), the
+    no-incoming-Poynting state of Ui elsewhere."""
     d, s = divmod(f, 2)
     Ub = ph.boundary_state(Ui, gi, d, +1 if s else -1)
     mask = dom.dirichlet_faces(elems, f)
     if np.any(mask):
-        fixed = dom.boundary_state[f].reshape((9, 1) + (1,) * (Ui.ndim - 2))
+        if dom.boundary_field is not None:
+            if layer is None:
+                n = dom.n
+                fixed = dom.boundary_field[0][:, elems, f].reshape(9, len(elems), n, n)
+            else:
+                m = dom.m
+                fixed = np.expand_dims(dom.boundary_field[1][:, elems, f, layer].reshape(9, len(elems), m, m),
+                                       axis_of(d))
+        else:
+            fixed = np.broadcast_to(dom.boundary_state[f].reshape((9, 1) + (1,) * (Ui.ndim - 2)), Ui.shape)
         sel = mask.reshape((1, -1) + (1,) * (Ui.ndim - 2))
-        Ub = np.where(sel, np.broadcast_to(fixed, Ui.shape), Ub)
+        Ub = np.where(sel, fixed, Ub)
     return Ub
 
 
@@ -205,8 +216,10 @@ def ghost_extended(dom, elems, W_own, geo_own, W_dg, W_fd, rep, d):
         i_out = 0 if s == 0 else m - 1
         Ui = np.take(W_own[:9], [i_out], axis=ax)
         gi = _take_geo_idx(geo_own, ax, [i_out])
-        Ub = exterior(dom, elems, f, Ui, gi)
-        Wb = np.repeat(with_current(dom, Ub, gi), 3, axis=ax)
+        # ghost layers l = 0, 1, 2 counted outwards from the face, in their order
+        # along the axis
+        layers = [with_current(dom, exterior(dom, elems, f, Ui, gi, layer=l), gi) for l in range(3)]
+        Wb = np.concatenate(layers[::-1] if s == 0 else layers, axis=ax)
         gb = _take_geo_idx(geo_own, ax, [i_out, i_out, i_out])
         mask = has[None, :, None, None, None]
         parts[s] = np.where(mask, G, Wb)

@@ -78,6 +78,8 @@ KArgs make_args(grffe_domain* d) {
   a.edt = d->edt;
   a.nbr = d->nbr;
   a.bstate = d->bstate;
+  a.bfield_dg = d->bfield_dg;
+  a.bfield_fd = d->bfield_fd;
   a.live = d->live;
   a.bg_dg = d->bg_dg;
   a.bg_fd = d->bg_fd;
@@ -416,6 +418,27 @@ extern "C" int grffe_set_boundary_state(grffe_domain* d, const double* state, vo
   hipStream_t st = S(stream);
   HIPCHK(hipMemcpyAsync(d->bstate, state, sizeof(double) * 6 * NV, hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
+  d->bc_missing = 0;
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_set_boundary_field(grffe_domain* d, const double* ext_dg, const double* ext_fd, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (!ext_dg || !ext_fd) return fail(GRFFE_EINVAL, "boundary field pointers must not be NULL");
+  if (d->parts.size() != 1) return fail(GRFFE_EUNSUPPORTED, "boundary fields are set on single domains");
+  const size_t ndg = (size_t)NV * d->E * 6 * d->n * d->n;
+  const size_t nfd = (size_t)NV * d->E * 6 * 3 * d->m * d->m;
+  if (!d->bfield_dg) {
+    void* p1 = nullptr;
+    void* p2 = nullptr;
+    if (int rc = dalloc(d, &p1, sizeof(double) * ndg)) return rc;
+    if (int rc = dalloc(d, &p2, sizeof(double) * nfd)) return rc;
+    d->bfield_dg = static_cast<double*>(p1);
+    d->bfield_fd = static_cast<double*>(p2);
+  }
+  hipStream_t st = S(stream);
+  HIPCHK(hipMemcpyAsync(d->bfield_dg, ext_dg, sizeof(double) * ndg, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d->bfield_fd, ext_fd, sizeof(double) * nfd, hipMemcpyDeviceToDevice, st));
   d->bc_missing = 0;
   return GRFFE_OK;
 }

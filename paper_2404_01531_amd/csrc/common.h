@@ -90,19 +90,23 @@ __device__ inline void store9(double* base, int E, int P, int e, int p, const do
 }
 
 // Exterior state of a boundary face (neighbour entry o < 0 of the face of direction d
-// and side s): a Dirichlet face (o = -2 - slot) holds the stored state bstate[slot];
-// any other boundary face (o = -1: an outer face of the no-incoming-Poynting kind, or
-// a face towards an excised element) takes the no-incoming-Poynting state of the
-// interior value Ui.
+// and side s): a Dirichlet face (o = -2 - slot) holds a stored state, the point's
+// own entry of a per-point field (component 0 at field[fidx], components fstride
+// apart) when one is set, else the face's uniform row bstate[slot]; any other
+// boundary face (o = -1: an outer face of the no-incoming-Poynting kind, or a face
+// towards an excised element) takes the no-incoming-Poynting state of the interior
+// value Ui.
 __device__ inline void exterior_state(const KArgs& a, int o, int d, int s, const double* Ui, const Metric& M,
-                                      double* Ub) {
+                                      const double* field, size_t fidx, size_t fstride, double* Ub) {
   // branch-free, so that Ub stays in registers: both states are formed and the
   // Dirichlet one selected (slot 0, always allocated, is read and unused elsewhere)
   boundary_state(d, s ? 1.0 : -1.0, Ui, M, Ub);
   const bool dir = o < -1;
-  const double* st = a.bstate + (size_t)(dir ? -2 - o : 0) * NV;
+  const bool per_point = dir && field != nullptr;
+  const double* st = per_point ? field + fidx : a.bstate + (size_t)(dir ? -2 - o : 0) * NV;
+  const size_t str = per_point ? fstride : 1;
 #pragma unroll
-  for (int c = 0; c < NV; ++c) Ub[c] = dir ? st[c] : Ub[c];
+  for (int c = 0; c < NV; ++c) Ub[c] = dir ? st[c * str] : Ub[c];
 }
 
 __device__ inline double dt_of(const KArgs& a, int e) { return a.dt > 0.0 ? a.dt : a.edt[e]; }

@@ -64,6 +64,8 @@ struct KArgs {
   const int32_t* nbr;      // [E][6]: neighbour, -1 at a no-incoming-Poynting boundary,
                            // -2 - slot at a Dirichlet face (exterior state bstate[slot])
   const double* bstate;    // [slots][9] exterior states of Dirichlet faces
+  const double* bfield_dg; // [9][E][6][n^2] per-node exterior states of Dirichlet faces, or null
+  const double* bfield_fd; // [9][E][6][3][m^2] per-ghost-cell exterior states, or null
   const uint8_t* live;     // [E]
   const double* bg_dg;     // [26][E][n^3] or null
   const double* bg_fd;     // [26][E][m^3] or null
@@ -120,6 +122,8 @@ struct grffe_domain {
   std::vector<uint8_t> live_h;
   int32_t* nbr = nullptr;
   double* bstate = nullptr;   // [6][9] exterior states of the Dirichlet faces
+  double* bfield_dg = nullptr;  // per-point exterior states (grffe_set_boundary_field)
+  double* bfield_fd = nullptr;
   uint8_t* live = nullptr;
   double* eh = nullptr;   // [E][3]
   double* edt = nullptr;  // [E]

@@ -60,11 +60,11 @@ __device__ inline void stage_faces(const KArgs& a, const int* sO, const int* sR,
 // of a continuous background: the element's own nodal metric Mi there is the
 // neighbour's as well.
 template <int N>
-__device__ inline void external_state(const KArgs& a, int d, int s, int o, int ro, int tt, const double* sX,
+__device__ inline void external_state(const KArgs& a, int e, int d, int s, int o, int ro, int tt, const double* sX,
                                       const double* Ui, const Metric& Mi, double* Ux, double* Jx) {
   constexpr int nf = (N + 1) * (N + 1);
   if (o < 0) {
-    exterior_state(a, o, d, s, Ui, Mi, Ux);
+    exterior_state(a, o, d, s, Ui, Mi, a.bfield_dg, ((size_t)e * 6 + 2 * d + s) * nf + tt, (size_t)a.E * 6 * nf, Ux);
     current_total(Ux, Mi, a.eta, Jx);
     return;
   }
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
       const int f = 2 * d + s;
       const int tt = (d == 0) ? j + n * k : (d == 1 ? i + n * k : i + n * j);
       double Wx[NV], Jx[3];
-      external_state<N>(a, d, s, sO[f], sR[f], tt, sX, X, M, Wx, Jx);
+      external_state<N>(a, e, d, s, sO[f], sR[f], tt, sX, X, M, Wx, Jx);
       R Wr[NV], Jxr[3], Fx[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Wr[v] = (R)Wx[v];

@@ -338,7 +338,11 @@ __global__ __launch_bounds__(FLUX_TPB) void k_fd_flux(KArgs a) {
       double Ui[NV], Ub[NV], J[3];
       load_metric<CURVED>(a.bg_fd, a.E, mm, e, cs.cell, Mc);
       load9(a.w_fd, a.E, mm, e, cs.cell, Ui);
-      exterior_state(a, cs.bnd, d, (c >= m + 3) ? 1 : 0, Ui, Mc, Ub);
+      // ghost layer lg (0 next to the face) of the pencil's cell (t1, t2)
+      const int sg = (c >= m + 3) ? 1 : 0, lg = sg ? c - 3 - m : 2 - c;
+      exterior_state(a, cs.bnd, d, sg, Ui, Mc, a.bfield_fd,
+                     ((((size_t)e * 6 + 2 * d + sg) * 3 + lg) * m + t2) * m + t1,
+                     (size_t)a.E * 6 * 3 * m * m, Ub);
       current_total(Ub, Mc, a.eta, J);
 #pragma unroll
       for (int k = 0; k < NV; ++k) W[k] = Ub[k];

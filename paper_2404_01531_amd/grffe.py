@@ -79,6 +79,7 @@ def lib():
     L.grffe_default_params.restype = None
     L.grffe_init_domain.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
     L.grffe_set_boundary_state.argtypes = [vp, ctypes.POINTER(dbl), vp]
+    L.grffe_set_boundary_field.argtypes = [vp, vp, vp, vp]
     L.grffe_destroy.argtypes = [vp]
     L.grffe_init_from_fd.argtypes = [vp, vp, vp, vp]
     L.grffe_set_state.argtypes = [vp, vp, vp, vp, vp]
@@ -117,7 +118,7 @@ def lib():
                  "grffe_batch_init_from_fd", "grffe_batch_get_state", "grffe_batch_set_state",
                  "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step", "grffe_rhs_adjoint",
                  "grffe_step_adjoint", "grffe_step_adjoint_frozen", "grffe_get_stages",
-                 "grffe_step_adjoint_stages", "grffe_set_boundary_state"):
+                 "grffe_step_adjoint_stages", "grffe_set_boundary_state", "grffe_set_boundary_field"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -250,6 +251,15 @@ class Domain:
         if st.shape != (6, 9):
             raise GrffeError("boundary state must have shape (6, 9)")
         _check(lib().grffe_set_boundary_state(self._h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+
+    def set_boundary_field(self, ext_dg, ext_fd):
+        """Per-point exterior states of the Dirichlet faces: device float64 tensors
+        (9, E, 6, n^2) at the DG face nodes and (9, E, 6, 3, m^2) at the FD ghost cells."""
+        n2, m2 = self.n ** 2, self.m ** 2
+        if tuple(ext_dg.shape) != (9, self.E, 6, n2) or tuple(ext_fd.shape) != (9, self.E, 6, 3, m2):
+            raise GrffeError(f"boundary field shapes must be (9, E, 6, {n2}) and (9, E, 6, 3, {m2})")
+        _check(lib().grffe_set_boundary_field(self._h, _ptr(ext_dg.contiguous()), _ptr(ext_fd.contiguous()),
+                                              _stream()))
 
     def get_state(self):
         import torch

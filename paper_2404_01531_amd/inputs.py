@@ -433,6 +433,34 @@ def workload(name, **over):
     return w
 
 
+def boundary_field(w, fn, ref_dg):
+    """Per-point exterior states of Dirichlet faces from an analytic state
+    fn(x, y, z) -> (9, ...): at every DG face node ((9, E, 6, n^2), node t1 + n t2 of
+    face f = 2 d + s, t1 along the lower tangential axis; ref_dg are the caller's 1D
+    DG nodes) and at every FD ghost cell ((9, E, 6, 3, m^2), layer l = 0, 1, 2 counted
+    outwards from the face: the boundary cell's centre moved by (l + 1) cell widths)."""
+    ne = w["n_elem"]
+    N = w["degree"]
+    n, m = N + 1, 2 * N + 1
+    E = int(np.prod(ne))
+    h = (np.asarray(w["upper"], np.float64) - np.asarray(w["lower"], np.float64)) / np.asarray(ne)
+    x, y, z = points(ne, w["lower"], w["upper"], ref_dg)
+    xf, yf, zf = fd_points(ne, w["lower"], w["upper"], N)
+    dg = np.zeros((9, E, 6, n * n))
+    fd = np.zeros((9, E, 6, 3, m * m))
+    for d in range(3):
+        ax = 3 - d  # point arrays are (E, z, y, x)
+        for s in (0, 1):
+            f = 2 * d + s
+            pts = [np.take(c, [0 if s == 0 else N], axis=ax).reshape(E, n * n) for c in (x, y, z)]
+            dg[:, :, f] = fn(*pts)
+            for l in range(3):
+                gp = [np.take(c, [0 if s == 0 else m - 1], axis=ax).reshape(E, m * m).copy() for c in (xf, yf, zf)]
+                gp[d] += (1 if s else -1) * (l + 1) * h[d] / m
+                fd[:, :, f, l] = fn(*gp)
+    return dg, fd
+
+
 def table1_dt(name, level=0):
     """The time step Table 1 prints for a one-dimensional problem (x 2^-level)."""
     return _ONE_D[name][1] * 2.0 ** -level

@@ -30,15 +30,24 @@ def make_pair(w, params=None):
     if w.get("curved"):
         x, y, z = node_coords(w)
         bg = I.background(w, x, y, z)
-    # Dirichlet faces hold the workload's initial data at the ends of the x axis
-    bstate = I.boundary_states(w) if I.BC_DIRICHLET in tuple(w["bc"]) else None
+    # Dirichlet faces hold the workload's initial data: at the ends of the x axis
+    # (uniform over each face), or point by point when the workload asks for it
+    dirichlet = I.BC_DIRICHLET in tuple(w["bc"])
+    bstate = I.boundary_states(w) if dirichlet and not w.get("boundary_field") else None
+    field = None
+    if dirichlet and w.get("boundary_field"):
+        field = I.boundary_field(w, lambda x, y, z: I.initial_data(w, x, y, z, with_noise=False),
+                                 ops.gll(w["degree"])[0])
     odom = ODomain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], excised=exc, bg=bg,
-                   params=oracle_params(p), boundary_state=bstate)
+                   params=oracle_params(p), boundary_state=bstate, boundary_field=field)
     E, n = odom.E, odom.n
     bg_t = None if bg is None else torch.from_numpy(np.ascontiguousarray(bg.reshape(26, E, n ** 3))).cuda()
     ldom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], params=p, bg=bg_t, excised=exc)
     if bstate is not None:
         ldom.set_boundary_state(bstate)
+    if field is not None:
+        ldom.set_boundary_field(torch.from_numpy(np.ascontiguousarray(field[0])).cuda(),
+                                torch.from_numpy(np.ascontiguousarray(field[1])).cuda())
     return odom, ldom, bg
 
 

@@ -134,3 +134,23 @@ def test_dg_fd_accuracy_comparison():
     assert dg.max() < 1.5 * dg.min()
     assert np.all(fd2 > 10 * dg)
     assert np.all(dgu[9:] < fd4[9:]) and np.all(dgu < dg)
+
+
+def test_exact_wald_convergence():
+    """The exact a = 0 Wald field on a Kerr-Schild background (Sec. IV B; the paper's
+    convergence table uses a spherical grid, here a Cartesian box beside the hole
+    with the exact field on every face, point by point): the error of B~ at t = 5M
+    falls with the element count at an order above N - 2 between the two finest
+    levels (the paper measures 4.7-5.0 for P5 and 6.4-6.9 for P7), and P7 is more
+    accurate than P5."""
+    _torch()
+    import bench
+    rows = bench.run_exact_wald(levels=(2, 4, 8), degrees=(5, 7))["rows"]
+    err = {(r["degree"], r["n_elem"]): r["rms_B_error"] for r in rows}
+    for r in rows:
+        _say(f"exact Wald P{r['degree']} n = {r['n_elem']}: error {r['rms_B_error']:.2e}, order {r['order']}")
+    for N in (5, 7):
+        o1, o2 = np.log2(err[N, 2] / err[N, 4]), np.log2(err[N, 4] / err[N, 8])
+        assert o1 > 3.0 and o2 > N - 2.0, (N, o1, o2)
+    for n in (2, 4, 8):
+        assert err[7, n] < err[5, n]

@@ -276,3 +276,32 @@ def test_step_dirichlet_ragged_degrees_forced_partition(N):
     _run_steps(w, 4, dict(eta=1e3, cfl=w["cfl"], hybrid=2),
                forced=np.array([1, 0, 0, 0, 1, 0, 0, 0, 0, 1], bool),
                label=f"Alfven wave P{N}, Dirichlet x faces, forced partition")
+
+
+def _wald_box(N, ne=(2, 2, 2)):
+    """The a = 0 Wald field on a box away from the hole, every face a Dirichlet face
+    holding the exact field point by point."""
+    return dict(n_elem=ne, lower=(4.0, -2.0, -2.0), upper=(8.0, 2.0, 2.0), degree=N, bc=(2,) * 6, curved=True,
+                kind="wald_a0", M=1.0, spin=0.0, B0=1.0, boundary_field=True, eta=1e5, cfl=0.25)
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_rhs_dirichlet_field_curved(N):
+    """Per-point Dirichlet states (the exact Wald field) on a curved background, DG
+    and FD elements on the faces, against the oracle."""
+    w = _wald_box(N)
+    odom, ldom, _ = make_pair(w, dict(eta=w["eta"]))
+    x, y, z = node_coords(w)
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], N)
+    rng = np.random.default_rng(1103)
+    dg = I.wald_a0(x, y, z) + 1e-3 * rng.standard_normal((9,) + x.shape)
+    fd = I.wald_a0(xf, yf, zf) + 1e-3 * rng.standard_normal((9,) + xf.shape)
+    for rep in ([0] * 8, [1, 0, 0, 1, 0, 1, 1, 0], [1] * 8):
+        _compare_rhs(odom, ldom, dg, fd, np.array(rep, np.int64), 3, label=f"Wald field faces P{N}, rep {rep}")
+
+
+def test_step_dirichlet_field_curved():
+    w = _wald_box(5, ne=(3, 2, 2))
+    forced = np.array([1, 0, 0, 0, 0, 1, 0, 1, 0, 0, 0, 1], bool)
+    _run_steps(w, 3, dict(eta=w["eta"], cfl=w["cfl"], hybrid=2), forced=forced,
+               label="Wald field on Dirichlet faces, P5, forced partition")

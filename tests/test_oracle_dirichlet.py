@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 from oracle import operators as ops
+from oracle import rhs as R
 from oracle import step as S
 from oracle.domain import DG, FD, Domain
 from paper_2404_01531_amd import inputs as I
@@ -105,3 +106,38 @@ def test_boundary_states_and_required():
     assert not bs[2:].any()
     with pytest.raises(ValueError):
         Domain(w["n_elem"], w["lower"], w["upper"], 5, w["bc"])
+
+
+def test_per_point_dirichlet_keeps_exact_wald_stationary():
+    """The a = 0 Wald field (Kerr-Schild background, Sec. IV B) is stationary.  On a
+    box away from the hole with every face a Dirichlet face holding the exact field
+    point by point, the right-hand side of every element -- boundary elements
+    included -- vanishes spectrally as N grows; with no-incoming-Poynting faces it
+    does not.  An FD element's residual falls with N too, and is larger when its
+    ghost layers are taken in the wrong order."""
+    ne, lo, hi = (2, 2, 2), (4.0, -2.0, -2.0), (8.0, 2.0, 2.0)
+    res, res_fd, res_fd_rev = [], [], []
+    rep_mixed = np.array([1, 0, 0, 0, 0, 0, 0, 1])
+    for N in (3, 5, 7):
+        w = dict(n_elem=ne, lower=lo, upper=hi, degree=N)
+        x, y, z = I.points(ne, lo, hi, ops.gll(N)[0])
+        xf, yf, zf = I.fd_points(ne, lo, hi, N)
+        bg = I.kerr_schild_background(x, y, z, 1.0, 0.0)
+        field = I.boundary_field(w, I.wald_a0, ops.gll(N)[0])
+        U, Uf = I.wald_a0(x, y, z), I.wald_a0(xf, yf, zf)
+        dom = Domain(ne, lo, hi, N, (2,) * 6, bg=bg, params=dict(eta=1e5), boundary_field=field)
+        L, _ = R.rhs(dom, U, Uf, np.zeros(8, np.int64), parts=3)
+        res.append(np.abs(L).max())
+        _, Lf = R.rhs(dom, U, Uf, rep_mixed, parts=3)
+        res_fd.append(np.abs(Lf[:, rep_mixed == 1]).max())
+        rev = Domain(ne, lo, hi, N, (2,) * 6, bg=bg, params=dict(eta=1e5),
+                     boundary_field=(field[0], field[1][:, :, :, ::-1]))
+        _, Lr = R.rhs(rev, U, Uf, rep_mixed, parts=3)
+        res_fd_rev.append(np.abs(Lr[:, rep_mixed == 1]).max())
+        if N == 7:
+            nip = Domain(ne, lo, hi, N, (1,) * 6, bg=bg, params=dict(eta=1e5))
+            Ln, _ = R.rhs(nip, U, Uf, np.zeros(8, np.int64), parts=3)
+            assert np.abs(Ln).max() > 1.0
+    assert res[1] < res[0] / 30 and res[2] < res[1] / 30 and res[2] < 1e-5
+    assert res_fd[1] < res_fd[0] / 10 and res_fd[2] < res_fd[1] / 3
+    assert res_fd_rev[2] > 5 * res_fd[2]
