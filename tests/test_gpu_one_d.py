@@ -154,3 +154,36 @@ def test_exact_wald_convergence():
         assert o1 > 3.0 and o2 > N - 2.0, (N, o1, o2)
     for n in (2, 4, 8):
         assert err[7, n] < err[5, n]
+
+
+def test_exact_wald_adaptive_stays_on_dg():
+    """Under the adaptive DG-FD control the smooth Wald field never trips the
+    indicator: no element goes to FD and the error equals the all-DG run's."""
+    torch = _torch()
+    import bench
+    from paper_2404_01531_amd import grffe
+    ref = bench.run_exact_wald(levels=(4,), degrees=(5,))["rows"][0]["rms_B_error"]
+    lo, hi, n, N = (4.0, -12.0, -12.0), (28.0, 12.0, 12.0), 4, 5
+    w = dict(n_elem=(n, n, n), lower=lo, upper=hi, degree=N)
+    r1 = grffe.operator(N, 0)
+    x, y, z = I.points(w["n_elem"], lo, hi, r1)
+    E, n3, m3 = n ** 3, (N + 1) ** 3, (2 * N + 1) ** 3
+    bg = I.kerr_schild_background(x, y, z, 1.0, 0.0).reshape(26, E, n3)
+    u = I.wald_a0(x, y, z).reshape(9, E, n3)
+    dom = grffe.Domain(w["n_elem"], lo, hi, N, (2,) * 6, params=dict(eta=1e6, cfl=0.25),
+                       bg=torch.from_numpy(np.ascontiguousarray(bg)).cuda())
+    fdg, ffd = I.boundary_field(w, I.wald_a0, r1)
+    dom.set_boundary_field(torch.from_numpy(fdg).cuda(), torch.from_numpy(ffd).cuda())
+    dom.set_state(torch.from_numpy(np.ascontiguousarray(u)).cuda(), torch.zeros((9, E, m3), dtype=torch.float64,
+                  device="cuda"), torch.zeros(E, dtype=torch.int32, device="cuda"))
+    steps = int(np.ceil(5.0 / dom.dt()))
+    n_fd = 0
+    for _ in range(steps):
+        dom.step(1, 5.0 / steps)
+        n_fd = max(n_fd, dom.counts()[1])
+    g = dom.get_state()[0].cpu().numpy().reshape(9, E, n3)
+    dom.close()
+    err = float(np.sqrt(np.mean((g[3:6] - u[3:6]) ** 2)))
+    _say(f"exact Wald adaptive P5 n = 4: error {err:.3e} (all DG {ref:.3e}), most FD elements {n_fd}")
+    assert n_fd == 0
+    assert abs(err - ref) <= 1e-12 * ref + 1e-15

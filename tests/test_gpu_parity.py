@@ -305,3 +305,19 @@ def test_step_dirichlet_field_curved():
     forced = np.array([1, 0, 0, 0, 0, 1, 0, 1, 0, 0, 0, 1], bool)
     _run_steps(w, 3, dict(eta=w["eta"], cfl=w["cfl"], hybrid=2), forced=forced,
                label="Wald field on Dirichlet faces, P5, forced partition")
+
+
+def test_rhs_kerr_schild_excision_and_dirichlet_field():
+    """Both boundary kinds in one domain: Dirichlet outer faces holding the
+    Wald-like field point by point, no-incoming-Poynting faces towards the excised
+    elements, DG and FD elements mixed."""
+    _torch()
+    w = dict(I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3, degree=5),
+             bc=(2,) * 6, boundary_field=True)
+    odom, ldom, _ = make_pair(w)
+    assert (~odom.active).sum() == 8
+    rng = np.random.default_rng(15)
+    rep = (rng.random(odom.E) < 0.3).astype(np.int64)
+    rep[~odom.active] = DG
+    dg, fd = _curved_state(odom, w, rng)
+    _compare_rhs(odom, ldom, dg, fd, rep, 3, label="kerr-schild, Dirichlet field outside, excision inside")
