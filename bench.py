@@ -519,7 +519,7 @@ def run_accuracy_smooth_wave(crossings=20):
                         "eta 1e6, CFL 0.3 (the paper's accuracy comparison of the DG and FD grids)", **out}
 
 
-def run_exact_wald(levels=(2, 4, 8, 16), degrees=(5, 7), t_end=5.0):
+def run_exact_wald(levels=(2, 4, 8, 16), degrees=(5, 7, 9), t_end=5.0):
     """Convergence on the exact a = 0 Wald field (Sec. IV B, the paper's exact-Wald
     table, here on a Cartesian box): Kerr-Schild background, M = 1, the box
     [4, 28] x [-12, 12]^2 beside the hole with n^3 elements, every face a Dirichlet

@@ -68,7 +68,7 @@ extern "C" {
 #define GRFFE_PRECISION_MIXED 1
 
 /* Element grid (Sec. III A): an axis-aligned box [lower, upper] cut into
- * n_elem[0] x n_elem[1] x n_elem[2] equal elements of degree N (3 <= N <= 7).
+ * n_elem[0] x n_elem[1] x n_elem[2] equal elements of degree N (3 <= N <= 9).
  * bc[2d + s] is the boundary kind of the lower (s = 0) / upper (s = 1) face
  * along direction d; periodic faces must come in pairs.  excised (host, E
  * bytes, nullable) removes elements: their faces towards live elements take the
@@ -294,7 +294,7 @@ int grffe_step_adjoint_frozen(grffe_domain* dom, const double* dg, const double*
                               int32_t* rep_log, double dt, void* stream);
 
 /* Batches: many independent domains advanced together, each with its own grid,
- * degree (3..7) and CFL time step (Eq. (spectre DG CFL condition) per domain).
+ * degree (3..9) and CFL time step (Eq. (spectre DG CFL condition) per domain).
  * Domains of one degree are concatenated into one pool, so every kernel of a step
  * is one launch over the elements of all of them; pools of different degrees run
  * on concurrent branches of a HIP graph that holds one step of the whole batch.

@@ -162,7 +162,7 @@ static double ssp_rk3_stability_c() {
 
 static int validate(const grffe_grid* g, const grffe_params* p) {
   if (!g || !p) return fail(GRFFE_EINVAL, "grid and params must not be NULL");
-  if (g->degree < 3 || g->degree > MAX_DEG) return fail(GRFFE_EINVAL, "degree must be in [3, 7]");
+  if (g->degree < 3 || g->degree > MAX_DEG) return fail(GRFFE_EINVAL, "degree must be in [3, 9]");
   for (int k = 0; k < 3; ++k) {
     if (g->n_elem[k] < 1) return fail(GRFFE_EINVAL, "n_elem must be positive");
     if (!(g->upper[k] > g->lower[k])) return fail(GRFFE_EINVAL, "upper must exceed lower");
@@ -635,6 +635,7 @@ extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream)
 
 // The adjoint entry points run in FP64 without the clamp.
 static int adjoint_supported(grffe_domain* d) {
+  if (d->N > 8) return fail(GRFFE_EUNSUPPORTED, "the adjoint is built for degrees 3..8");
   if (d->par.precision != GRFFE_PRECISION_FP64) return fail(GRFFE_EUNSUPPORTED, "the adjoint runs in FP64 only");
   if (d->par.ff_clamp) return fail(GRFFE_EUNSUPPORTED, "the adjoint does not differentiate the clamp");
   return GRFFE_OK;
@@ -946,7 +947,7 @@ extern "C" int grffe_get_counts(grffe_domain* d, int32_t* n_dg, int32_t* n_fd) {
 }
 
 extern "C" int grffe_operator(int degree, int which, double* out, int capacity) {
-  if (degree < 3 || degree > MAX_DEG) return fail(GRFFE_EINVAL, "degree must be in [3, 7]");
+  if (degree < 3 || degree > MAX_DEG) return fail(GRFFE_EINVAL, "degree must be in [3, 9]");
   grffe_params p;
   grffe_default_params(&p);
   Ops1D o = build_ops(degree, p.filter_a, p.filter_b, default_tci_M(degree), 2);
@@ -1016,7 +1017,7 @@ extern "C" int grffe_batch_create(const grffe_grid* grids, int32_t count, const 
   *out = nullptr;
   if (!grids || !params || count < 1) return fail(GRFFE_EINVAL, "a batch needs at least one grid");
   for (int k = 0; k < count; ++k)
-    if (grids[k].degree < 3 || grids[k].degree > MAX_DEG) return fail(GRFFE_EINVAL, "degree must be in 3..7");
+    if (grids[k].degree < 3 || grids[k].degree > MAX_DEG) return fail(GRFFE_EINVAL, "degree must be in 3..9");
   for (int k = 0; k < count; ++k)
     for (int f = 0; f < 6; ++f)
       if (grids[k].bc[f] == GRFFE_BC_DIRICHLET)

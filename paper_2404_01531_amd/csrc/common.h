@@ -234,7 +234,9 @@ __device__ inline void stage_update(const Regs& r, int E, int P, int e, int p, c
     case 4: { constexpr int NN = 4; CALL; } break; \
     case 5: { constexpr int NN = 5; CALL; } break; \
     case 6: { constexpr int NN = 6; CALL; } break; \
-    default: { constexpr int NN = 7; CALL; } break; \
+    case 7: { constexpr int NN = 7; CALL; } break; \
+    case 8: { constexpr int NN = 8; CALL; } break; \
+    default: { constexpr int NN = 9; CALL; } break; \
   }
 
 

@@ -15,7 +15,7 @@ constexpr int NV = 9;      // evolved components
 constexpr int NW = 12;     // evolved components + densitized current J~
 constexpr int NBG = 26;    // background fields at DG nodes / FD cells
 constexpr int NBGF = 10;   // background fields at FD faces (alpha, beta, gamma)
-constexpr int MAX_DEG = 7; // largest degree with a fused DG kernel
+constexpr int MAX_DEG = 9; // largest degree with a fused DG kernel
 
 // IMEX-SSP3(4,3,3) (Pareschi & Russo 2005): implicit diagonal a, and b, e of the last row.
 constexpr double IMEX_A = 0.24169426078821;

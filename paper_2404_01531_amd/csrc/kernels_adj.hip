@@ -313,7 +313,8 @@ static void launch_adj_c(const KArgs& a, const AdjBufs& b, int N, int stage, hip
     case 4: launch_adj_t<4, CURVED>(a, b, stage, s); break;
     case 5: launch_adj_t<5, CURVED>(a, b, stage, s); break;
     case 6: launch_adj_t<6, CURVED>(a, b, stage, s); break;
-    default: launch_adj_t<7, CURVED>(a, b, stage, s); break;
+    case 7: launch_adj_t<7, CURVED>(a, b, stage, s); break;
+    default: launch_adj_t<8, CURVED>(a, b, stage, s); break;  // the adjoint entry points refuse N > 8
   }
 }
 

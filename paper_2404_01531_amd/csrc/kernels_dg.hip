@@ -309,9 +309,11 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
     if (o >= 0 && (a.rep0[o] == 1 || a.troubled[o])) need |= 1 << f;
   }
   if (!need) return;
+  // the components are projected in chunks of CH so that the tiles fit in LDS at high degree
+  constexpr int CH = (NW * (nn + 3 * n * n + 3 * m * n) * 8 <= 150 * 1024) ? NW : NW / 2;
   __shared__ double sW[NW * nn];
-  __shared__ double sA[NW * 3 * n * n];
-  __shared__ double sB[NW * 3 * m * n];
+  __shared__ double sA[CH * 3 * n * n];
+  __shared__ double sB[CH * 3 * m * n];
   __shared__ double sP[m * n];
   const int t = threadIdx.x;
   for (int q = t; q < m * n; q += TPB) sP[q] = a.ops->P[q];
@@ -332,35 +334,37 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
     const int d = f >> 1, s = f & 1;
     // axes: normal d, tangential t1 < t2
     const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
-    // 1) normal direction: layers l = 0..2, cell index m-1-l (upper face) or l (lower face)
-    for (int q = t; q < NW * 3 * n * n; q += TPB) {
-      const int c = q / (3 * n * n), r0 = q % (3 * n * n);
-      const int l = r0 / (n * n), r = r0 % (n * n);
-      const int a1 = r % n, a2 = r / n;
-      const int cell = s ? (m - 1 - l) : l;
-      const double* W = sW + c * nn;
-      double acc = 0.0;
-      for (int z = 0; z < n; ++z) acc += sP[cell * n + z] * W[z * str[d] + a1 * str[t1ax] + a2 * str[t2ax]];
-      sA[q] = acc;  // [c][l][a2][a1]
+    for (int c0 = 0; c0 < NW; c0 += CH) {
+      // 1) normal direction: layers l = 0..2, cell index m-1-l (upper face) or l (lower face)
+      for (int q = t; q < CH * 3 * n * n; q += TPB) {
+        const int c = q / (3 * n * n), r0 = q % (3 * n * n);
+        const int l = r0 / (n * n), r = r0 % (n * n);
+        const int a1 = r % n, a2 = r / n;
+        const int cell = s ? (m - 1 - l) : l;
+        const double* W = sW + (c0 + c) * nn;
+        double acc = 0.0;
+        for (int z = 0; z < n; ++z) acc += sP[cell * n + z] * W[z * str[d] + a1 * str[t1ax] + a2 * str[t2ax]];
+        sA[q] = acc;  // [c][l][a2][a1]
+      }
+      __syncthreads();
+      // 2) first tangential axis: a1 (n) -> c1 (m)
+      for (int q = t; q < CH * 3 * m * n; q += TPB) {
+        const int c1 = q % m, rest = q / m;  // rest = (c*3 + l)*n + a2
+        double acc = 0.0;
+        for (int z = 0; z < n; ++z) acc += sP[c1 * n + z] * sA[rest * n + z];
+        sB[q] = acc;  // [c][l][a2][c1]
+      }
+      __syncthreads();
+      // 3) second tangential axis: a2 (n) -> c2 (m), written as [c][l][c2][c1]
+      for (int q = t; q < CH * 3 * m * m; q += TPB) {
+        const int c1 = q % m, c2 = (q / m) % m, cl = q / (m * m);  // cl = c*3 + l
+        const int c = c0 + cl / 3, l = cl % 3;
+        double acc = 0.0;
+        for (int z = 0; z < n; ++z) acc += sP[c2 * n + z] * sB[(cl * n + z) * m + c1];
+        a.slab[((size_t)c * a.E * 6 + (size_t)e * 6 + f) * (3 * m * m) + (l * m + c2) * m + c1] = acc;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    // 2) first tangential axis: a1 (n) -> c1 (m)
-    for (int q = t; q < NW * 3 * m * n; q += TPB) {
-      const int c1 = q % m, rest = q / m;  // rest = (c*3 + l)*n + a2
-      double acc = 0.0;
-      for (int z = 0; z < n; ++z) acc += sP[c1 * n + z] * sA[rest * n + z];
-      sB[q] = acc;  // [c][l][a2][c1]
-    }
-    __syncthreads();
-    // 3) second tangential axis: a2 (n) -> c2 (m), written as [c][l][c2][c1]
-    for (int q = t; q < NW * 3 * m * m; q += TPB) {
-      const int c1 = q % m, c2 = (q / m) % m, cl = q / (m * m);  // cl = c*3 + l
-      const int c = cl / 3, l = cl % 3;
-      double acc = 0.0;
-      for (int z = 0; z < n; ++z) acc += sP[c2 * n + z] * sB[(cl * n + z) * m + c1];
-      a.slab[((size_t)c * a.E * 6 + (size_t)e * 6 + f) * (3 * m * m) + (l * m + c2) * m + c1] = acc;
-    }
-    __syncthreads();
   }
 }
 
@@ -398,7 +402,9 @@ static void launch_dg_slab_t(const KArgs& a, int mode, hipStream_t s) {
     case 4: FN<4, CURVED_T>(__VA_ARGS__); break;  \
     case 5: FN<5, CURVED_T>(__VA_ARGS__); break;  \
     case 6: FN<6, CURVED_T>(__VA_ARGS__); break;  \
-    default: FN<7, CURVED_T>(__VA_ARGS__); break; \
+    case 7: FN<7, CURVED_T>(__VA_ARGS__); break;  \
+    case 8: FN<8, CURVED_T>(__VA_ARGS__); break;  \
+    default: FN<9, CURVED_T>(__VA_ARGS__); break; \
   }
 
 void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t s) {

@@ -283,8 +283,12 @@ __device__ inline void weno5z_cell(const double* v, double eps, double& left, do
   }
 }
 
-// Threads of an FD flux workgroup.
-constexpr int FLUX_TPB = 256;
+// Threads of an FD flux workgroup: at least one per (cell -1 .. m, pencil) of a row,
+// the flux phase's work items.
+template <int N>
+constexpr int flux_tpb() {
+  return (2 * N + 1) * (2 * N + 3) <= 256 ? 256 : 512;
+}
 
 // One workgroup per (FD element, direction d, row t2 of pencils along d): the
 // m pencils of the row, with three ghost cells at each end, are staged in LDS
@@ -296,7 +300,7 @@ constexpr int FLUX_TPB = 256;
 // m = 2N+1 is odd, so both the pencil-contiguous and the cell-contiguous thread
 // mappings touch 16 distinct bank pairs per 16 lanes (no bank conflicts).
 template <int N, bool CURVED, typename R>
-__global__ __launch_bounds__(FLUX_TPB) void k_fd_flux(KArgs a) {
+__global__ __launch_bounds__(flux_tpb<N>()) void k_fd_flux(KArgs a) {
   using Dm = Dims<N>;
   constexpr int m = Dm::m, mm = Dm::mm;
   constexpr int nf = (m + 1) * m * m;
@@ -304,6 +308,7 @@ __global__ __launch_bounds__(FLUX_TPB) void k_fd_flux(KArgs a) {
   constexpr int C = m + 6;  // cells per pencil including ghosts
   constexpr int F = m + 1;  // faces per pencil
   constexpr int NR = NV + 1;  // reconstructed components: U and J~^d
+  constexpr int TPB = flux_tpb<N>();
   static_assert(L % 2 == 1, "odd pencil count keeps the LDS tiles free of bank conflicts");
   __shared__ double sW[NR * C * L];   // [k][extended cell][pencil]
   __shared__ double sLf[NR * F * L];  // [k][face][pencil]
@@ -317,7 +322,7 @@ __global__ __launch_bounds__(FLUX_TPB) void k_fd_flux(KArgs a) {
   const int d = (item / m) % 3;
   const int t2 = item % m;
   // phase 1: stage cells -3 .. m+2 of every pencil (and the metric of cells -1 .. m)
-  for (int q = t; q < L * C; q += FLUX_TPB) {
+  for (int q = t; q < L * C; q += TPB) {
     int c, t1;
     if (d == 0) {
       c = q % C;
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(FLUX_TPB) void k_fd_flux(KArgs a) {
   // cell-centred fluxes of cells -1 .. m used by the corrector
   const double eps = a.weno_eps;
   // target cells c = -1 .. m: left state of face c+1 and right state of face c
-  for (int q = t; q < NR * L * (m + 2); q += FLUX_TPB) {
+  for (int q = t; q < NR * L * (m + 2); q += TPB) {
     const int t1 = q % L;
     const int c = (q / L) % (m + 2) - 1;
     const int k = q / (L * (m + 2));
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(FLUX_TPB) void k_fd_flux(KArgs a) {
   __syncthreads();
   // phase 3a: cell-centred fluxes of cells -1 .. m of every pencil (the corrector's
   // F_i), each computed once; they replace the staged cells in LDS
-  static_assert(L * (m + 2) <= FLUX_TPB && L * F <= FLUX_TPB, "one cell / one face per thread in phase 3");
+  static_assert(L * (m + 2) <= TPB && L * F <= TPB, "one cell / one face per thread in phase 3");
   constexpr int CF = m + 2;  // cells -1 .. m
   R Fcell[NV];
   const bool corr = a.fd_order == 4;
@@ -470,7 +475,7 @@ __global__ __launch_bounds__(FLUX_TPB) void k_fd_flux(KArgs a) {
   const double sc = (double)m / h_of(a, e, d);
   const int str[3] = {1, m, m * m};
   const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
-  for (int q = t; q < L * m; q += FLUX_TPB) {
+  for (int q = t; q < L * m; q += TPB) {
     int c, t1;
     if (d == 0) {
       c = q % m;
@@ -738,8 +743,8 @@ __global__ __launch_bounds__(256) void k_transfer(KArgs a, int to_fd, const doub
   const int e = blockIdx.x;
   const int v = blockIdx.y;
   __shared__ double sin_[mm];
-  __shared__ double s1[m * m * m];
-  __shared__ double s2[m * m * m];
+  __shared__ double s1[n * m * m + nn];  // P: first stage; R: first stage, then the result
+  __shared__ double s2[m * m * n];       // P and R: second stage
   __shared__ double sO[n * m];
   const int t = threadIdx.x;
   if (to_fd) {
@@ -897,7 +902,7 @@ void launch_project_troubled(const KArgs& a, int N, bool curved, int mode, hipSt
 template <int N, bool CURVED>
 static void fd_flux_t(const KArgs& a, hipStream_t s) {
   constexpr int m = Dims<N>::m;
-  const dim3 grid = list_grid((size_t)a.E * 3 * m, 2048), block(FLUX_TPB);
+  const dim3 grid = list_grid((size_t)a.E * 3 * m, 2048), block(flux_tpb<N>());
   if (a.precision == GRFFE_PRECISION_MIXED) launch_kernel(k_fd_flux<N, CURVED, float>, grid, block, s, a);
   else launch_kernel(k_fd_flux<N, CURVED, double>, grid, block, s, a);
 }

@@ -677,6 +677,7 @@ static void fd_stage_adjoint_t(const KArgs& a, const FdAdj& b, const AdjBufs& r,
   }
 }
 
+// Degrees 3..8 (the adjoint entry points refuse N > 8).
 #define GRFFE_FD_ADJ_DISPATCH(CALL)                 \
   if (curved) {                                     \
     switch (N) {                                    \
@@ -684,7 +685,8 @@ static void fd_stage_adjoint_t(const KArgs& a, const FdAdj& b, const AdjBufs& r,
       case 4: CALL(4, true); break;                 \
       case 5: CALL(5, true); break;                 \
       case 6: CALL(6, true); break;                 \
-      default: CALL(7, true); break;                \
+      case 7: CALL(7, true); break;                 \
+      default: CALL(8, true); break;                \
     }                                               \
   } else {                                          \
     switch (N) {                                    \
@@ -692,7 +694,8 @@ static void fd_stage_adjoint_t(const KArgs& a, const FdAdj& b, const AdjBufs& r,
       case 4: CALL(4, false); break;                \
       case 5: CALL(5, false); break;                \
       case 6: CALL(6, false); break;                \
-      default: CALL(7, false); break;               \
+      case 7: CALL(7, false); break;                \
+      default: CALL(8, false); break;               \
     }                                               \
   }
 

@@ -829,3 +829,10 @@ def test_adjoint_rejects_mixed_precision_and_clamp():
             ldom.rhs_adjoint(u, f, rep, u, f)
         with pytest.raises(grffe.GrffeError):
             ldom.step_adjoint(u, u)
+    # the adjoint is built for degrees up to 8
+    _, ldom, _ = make_pair(I.workload("wave", degree=9))
+    u = torch.zeros(ldom.dg_shape(), dtype=torch.float64, device="cuda")
+    f = torch.zeros(ldom.fd_shape(), dtype=torch.float64, device="cuda")
+    rep = torch.zeros(ldom.E, dtype=torch.int32, device="cuda")
+    with pytest.raises(grffe.GrffeError, match="degrees"):
+        ldom.rhs_adjoint(u, f, rep, u, f)

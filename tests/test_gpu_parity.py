@@ -75,7 +75,7 @@ def test_rhs_flat_all_dg(parts):
     _compare_rhs(odom, ldom, dg, fd, rep, parts, label=f"wave parts={parts}")
 
 
-@pytest.mark.parametrize("N", [3, 4, 6, 7])
+@pytest.mark.parametrize("N", [3, 4, 6, 7, 8, 9])
 def test_rhs_flat_ragged_degrees(N):
     _torch()
     w = dict(n_elem=(3, 2, 1), lower=(-1.0, -0.5, -0.25), upper=(1.0, 0.75, 0.5), degree=N,
@@ -321,3 +321,14 @@ def test_rhs_kerr_schild_excision_and_dirichlet_field():
     rep[~odom.active] = DG
     dg, fd = _curved_state(odom, w, rng)
     _compare_rhs(odom, ldom, dg, fd, rep, 3, label="kerr-schild, Dirichlet field outside, excision inside")
+
+
+@pytest.mark.parametrize("N", [8, 9])
+def test_step_high_degree_adaptive(N):
+    """Degrees 8 and 9 (the paper's exact-Wald table reaches P9): adaptive steps of a
+    small current sheet with DG and FD elements."""
+    w = I.workload("sheet", n_elem=(3, 2, 2), degree=N)
+    _run_steps(w, 2, dict(eta=w["eta"], cfl=w["cfl"]), label=f"sheet 3x2x2 P{N} adaptive")
+    w = I.workload("wave", degree=N)
+    st, _ = _run_steps(w, 2, dict(eta=w["eta"], cfl=w["cfl"]), label=f"wave 2^3 P{N}")
+    assert (st.rep == DG).all()

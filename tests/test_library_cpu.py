@@ -29,7 +29,7 @@ def test_default_params_match_paper_values():
     assert p.filter_a == 36.0 and p.filter_b == 50.0 and p.fd_order == 4 and p.weno_eps == 1e-40
 
 
-@pytest.mark.parametrize("N", [3, 4, 5, 6, 7])
+@pytest.mark.parametrize("N", [3, 4, 5, 6, 7, 8, 9])
 def test_host_operators_match_oracle(N):
     n, m = N + 1, 2 * N + 1
     x, w = ops.gll(N)
@@ -59,7 +59,7 @@ def _grid(**over):
 
 
 @pytest.mark.parametrize("bad, code", [
-    (dict(degree=2), -1), (dict(degree=8), -1), (dict(n_elem=(0, 2, 2)), -1),
+    (dict(degree=2), -1), (dict(degree=10), -1), (dict(n_elem=(0, 2, 2)), -1),
     (dict(upper=(1.0, -1.0, 1.0)), -1), (dict(bc=(0, 1, 0, 0, 0, 0)), -1), (dict(bc=(0, 0, 7, 7, 0, 0)), -1),
     (dict(bc=(2, 0, 0, 0, 0, 0)), -1), (dict(bc=(3, 3, 0, 0, 0, 0)), -1),
 ])
@@ -98,7 +98,7 @@ def test_null_handles_are_rejected():
     h = ctypes.c_void_p()
     arr = (grffe.Grid * 1)(g)
     assert L.grffe_batch_create(arr, 0, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
-    bad = (grffe.Grid * 1)(_grid(degree=9))
+    bad = (grffe.Grid * 1)(_grid(degree=10))
     assert L.grffe_batch_create(bad, 1, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
     assert L.grffe_batch_step(None, 1, 1, None) == -1
     d = ctypes.c_double()
