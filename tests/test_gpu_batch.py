@@ -139,7 +139,7 @@ def test_batch_rejects_bad_input():
     with pytest.raises(grffe.GrffeError):
         grffe.Batch([], params=PARAMS)
     bad = _grid(MEMBERS[0])
-    bad["degree"] = 9
+    bad["degree"] = 10
     with pytest.raises(grffe.GrffeError):
         grffe.Batch([bad], params=PARAMS)
     b = _make_batch(MEMBERS[:1])
