@@ -329,6 +329,7 @@ def test_step_high_degree_adaptive(N):
     small current sheet with DG and FD elements."""
     w = I.workload("sheet", n_elem=(3, 2, 2), degree=N)
     _run_steps(w, 2, dict(eta=w["eta"], cfl=w["cfl"]), label=f"sheet 3x2x2 P{N} adaptive")
+    # the DG kernels at these degrees: the wave with every element held on DG
     w = I.workload("wave", degree=N)
-    st, _ = _run_steps(w, 2, dict(eta=w["eta"], cfl=w["cfl"]), label=f"wave 2^3 P{N}")
+    st, _ = _run_steps(w, 2, dict(eta=w["eta"], cfl=w["cfl"], hybrid=0), label=f"wave 2^3 P{N}, DG only")
     assert (st.rep == DG).all()
