@@ -28,8 +28,9 @@
  *  - Return value: GRFFE_OK (0) or a negative status; the message of the last
  *    failure on the calling thread is returned by grffe_last_error().  No
  *    implicit device synchronisation happens except where a host value is
- *    returned (grffe_get_dt, grffe_get_counts, grffe_timing_read) and in
- *    grffe_set_boundary_state, which waits for its host-to-device copy.
+ *    returned (grffe_get_dt, grffe_get_counts, grffe_timing_read,
+ *    grffe_check_finite) and in grffe_set_boundary_state, which waits for its
+ *    host-to-device copy.
  *  - A domain is not thread-safe; separate domains are independent.
  */
 #ifndef GRFFE_H
@@ -45,6 +46,7 @@ extern "C" {
 #define GRFFE_EINVAL (-1)      /* bad shape, degree, parameter or pointer */
 #define GRFFE_ENOMEM (-2)      /* device allocation failed */
 #define GRFFE_EHIP (-3)        /* HIP runtime error */
+#define GRFFE_ENONFINITE (-4)  /* the state holds NaN or infinite values (grffe_check_finite) */
 #define GRFFE_EUNSUPPORTED (-5)
 
 #define GRFFE_BC_PERIODIC 0
@@ -196,6 +198,13 @@ int grffe_reconstruct_fd_to_dg(grffe_domain* dom, const double* u_fd, double* u_
 
 /* Time step of Eq. (spectre DG CFL condition) (host value; synchronises). */
 int grffe_get_dt(grffe_domain* dom, double* dt);
+
+/* Scan the domain's state for blow-up: every live element's values in its own
+ * representation (DG nodes or FD cells).  *n_bad (host, nullable) receives the
+ * number of elements holding a NaN or infinite value.  Returns GRFFE_ENONFINITE when
+ * that number is positive, GRFFE_OK otherwise; synchronises `stream`.  The first
+ * call allocates an E-byte work array. */
+int grffe_check_finite(grffe_domain* dom, int32_t* n_bad, void* stream);
 
 /* Number of live elements on DG and on FD (host values; synchronises). */
 int grffe_get_counts(grffe_domain* dom, int32_t* n_dg, int32_t* n_fd);

@@ -946,6 +946,31 @@ extern "C" int grffe_get_counts(grffe_domain* d, int32_t* n_dg, int32_t* n_fd) {
   return GRFFE_OK;
 }
 
+namespace grffe {
+void launch_check_finite(const KArgs& a, int nn, int mm, uint8_t* bad, hipStream_t s);
+}
+
+extern "C" int grffe_check_finite(grffe_domain* d, int32_t* n_bad, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (!d->bad_flags) {
+    void* p = nullptr;
+    if (int rc = dalloc(d, &p, d->E)) return rc;
+    d->bad_flags = static_cast<uint8_t*>(p);
+  }
+  hipStream_t st = S(stream);
+  KArgs a = make_args(d);
+  launch_check_finite(a, d->nn, d->mm, d->bad_flags, st);
+  HIPCHK(hipGetLastError());
+  std::vector<uint8_t> h(d->E);
+  HIPCHK(hipMemcpyAsync(h.data(), d->bad_flags, d->E, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int32_t nb = 0;
+  for (int e = 0; e < d->E; ++e) nb += h[e] ? 1 : 0;
+  if (n_bad) *n_bad = nb;
+  if (nb) return fail(GRFFE_ENONFINITE, std::to_string(nb) + " element(s) hold non-finite values");
+  return GRFFE_OK;
+}
+
 extern "C" int grffe_operator(int degree, int which, double* out, int capacity) {
   if (degree < 3 || degree > MAX_DEG) return fail(GRFFE_EINVAL, "degree must be in [3, 9]");
   grffe_params p;

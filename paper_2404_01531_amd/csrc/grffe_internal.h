@@ -124,6 +124,7 @@ struct grffe_domain {
   double* bstate = nullptr;   // [6][9] exterior states of the Dirichlet faces
   double* bfield_dg = nullptr;  // per-point exterior states (grffe_set_boundary_field)
   double* bfield_fd = nullptr;
+  uint8_t* bad_flags = nullptr;  // [E] scratch of grffe_check_finite
   uint8_t* live = nullptr;
   double* eh = nullptr;   // [E][3]
   double* edt = nullptr;  // [E]

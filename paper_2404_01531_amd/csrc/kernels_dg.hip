@@ -396,6 +396,32 @@ static void launch_dg_slab_t(const KArgs& a, int mode, hipStream_t s) {
   }
 }
 
+// Elements holding a non-finite value in their own representation (DG registers
+// U^n for DG elements, FD registers U^n for FD elements): bad[e] = 1, else 0.
+__global__ __launch_bounds__(256) void k_check_finite(KArgs a, int nn, int mm, uint8_t* bad) {
+  const int e = blockIdx.x;
+  __shared__ int flag;
+  if (threadIdx.x == 0) flag = 0;
+  __syncthreads();
+  if (a.live[e]) {
+    const bool fd = a.rep[e] == 1;
+    const double* u = fd ? a.fd.Un : a.dg.Un;
+    const int P = fd ? mm : nn;
+    int mine = 0;
+    for (int q = threadIdx.x; q < NV * P; q += 256) {
+      const int v = q / P, p = q % P;
+      if (!isfinite(u[((size_t)v * a.E + e) * P + p])) mine = 1;
+    }
+    if (mine) flag = 1;  // every writer stores the same value
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) bad[e] = (uint8_t)flag;
+}
+
+void launch_check_finite(const KArgs& a, int nn, int mm, uint8_t* bad, hipStream_t s) {
+  launch_kernel(k_check_finite, dim3(a.E), dim3(256), s, a, nn, mm, bad);
+}
+
 #define GRFFE_DISPATCH_N(FN, ...)                 \
   switch (N) {                                    \
     case 3: FN<3, CURVED_T>(__VA_ARGS__); break;  \

@@ -80,6 +80,7 @@ def lib():
     L.grffe_init_domain.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
     L.grffe_set_boundary_state.argtypes = [vp, ctypes.POINTER(dbl), vp]
     L.grffe_set_boundary_field.argtypes = [vp, vp, vp, vp]
+    L.grffe_check_finite.argtypes = [vp, ctypes.POINTER(i32), vp]
     L.grffe_destroy.argtypes = [vp]
     L.grffe_init_from_fd.argtypes = [vp, vp, vp, vp]
     L.grffe_set_state.argtypes = [vp, vp, vp, vp, vp]
@@ -118,7 +119,8 @@ def lib():
                  "grffe_batch_init_from_fd", "grffe_batch_get_state", "grffe_batch_set_state",
                  "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step", "grffe_rhs_adjoint",
                  "grffe_step_adjoint", "grffe_step_adjoint_frozen", "grffe_get_stages",
-                 "grffe_step_adjoint_stages", "grffe_set_boundary_state", "grffe_set_boundary_field"):
+                 "grffe_step_adjoint_stages", "grffe_set_boundary_state", "grffe_set_boundary_field",
+                 "grffe_check_finite"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -251,6 +253,14 @@ class Domain:
         if st.shape != (6, 9):
             raise GrffeError("boundary state must have shape (6, 9)")
         _check(lib().grffe_set_boundary_state(self._h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+
+    def check_finite(self):
+        """Number of elements holding NaN or infinite values (0 for a healthy state)."""
+        n = ctypes.c_int32(0)
+        rc = lib().grffe_check_finite(self._h, ctypes.byref(n), _stream())
+        if rc not in (0, -4):
+            _check(rc)
+        return int(n.value)
 
     def set_boundary_field(self, ext_dg, ext_fd):
         """Per-point exterior states of the Dirichlet faces: device float64 tensors

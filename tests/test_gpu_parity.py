@@ -333,3 +333,24 @@ def test_step_high_degree_adaptive(N):
     w = I.workload("wave", degree=N)
     st, _ = _run_steps(w, 2, dict(eta=w["eta"], cfl=w["cfl"], hybrid=0), label=f"wave 2^3 P{N}, DG only")
     assert (st.rep == DG).all()
+
+
+def test_check_finite_reports_blown_up_elements():
+    """grffe_check_finite counts the elements holding NaN or infinite values in their
+    own representation (a non-finite entry of the other representation is ignored)."""
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    w = I.workload("sheet", n_elem=(3, 2, 2))
+    _, ldom, _ = make_pair(w, dict(eta=w["eta"], cfl=w["cfl"]))
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    ldom.init_from_fd(to_dev(I.initial_data(w, xf, yf, zf)))
+    assert ldom.check_finite() == 0
+    dg, fd, rep = ldom.get_state()
+    r = rep.cpu().numpy()
+    e_dg, e_fd = int(np.nonzero(r == 0)[0][0]), int(np.nonzero(r == 1)[0][0])
+    dg[4, e_dg, 7] = float("nan")
+    fd[2, e_fd, 3] = float("inf")
+    dg[0, e_fd, 0] = float("nan")  # an FD element's DG entries are not its state
+    ldom.set_state(dg, fd, rep)
+    assert ldom.check_finite() == 2
+    assert "non-finite" in grffe.lib().grffe_last_error().decode()

@@ -110,6 +110,7 @@ def test_dirichlet_entry_points_on_the_host():
     state = (ctypes.c_double * 54)()
     assert L.grffe_set_boundary_state(None, state, None) == -1
     assert L.grffe_set_boundary_field(None, None, None, None) == -1
+    assert L.grffe_check_finite(None, None, None) == -1
     p = grffe.default_params()
     h = ctypes.c_void_p()
     arr = (grffe.Grid * 1)(_grid(bc=(2, 2, 0, 0, 0, 0)))
