@@ -176,9 +176,11 @@ def _time_steps(step, steps, warmup):
     return time.perf_counter() - t0
 
 
-def run_kerr_schild(steps, warmup, precision, n_elem=16):
-    """Kerr-Schild black hole (M = 1, a = 0.9, B0 = 1, Wald-like data with the ideal
-    E), [-40,40]^3 with n_elem^3 DG-P5 elements, elements meeting r < 1.8 excised."""
+def kerr_schild_domain(precision, n_elem=16):
+    """The Kerr-Schild black-hole domain (M = 1, a = 0.9, B0 = 1, Wald-like data with
+    the ideal E), [-40,40]^3 with n_elem^3 DG-P5 elements, elements meeting r < 1.8
+    excised, every element on DG.  Returns (domain, workload, excision mask, DG node
+    coordinates)."""
     import numpy as np
     import torch
 
@@ -205,6 +207,18 @@ def run_kerr_schild(steps, warmup, precision, n_elem=16):
     dom.set_state(torch.from_numpy(np.ascontiguousarray(u)).cuda(),
                   torch.zeros((9, E, m3), dtype=torch.float64, device="cuda"),
                   torch.zeros(E, dtype=torch.int32, device="cuda"))
+    return dom, w, exc, (x, y, z)
+
+
+def run_kerr_schild(steps, warmup, precision, n_elem=16):
+    """Kerr-Schild black hole (M = 1, a = 0.9, B0 = 1, Wald-like data with the ideal
+    E), [-40,40]^3 with n_elem^3 DG-P5 elements, elements meeting r < 1.8 excised."""
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    dom, w, exc, _ = kerr_schild_domain(precision, n_elem)
+    N = w["degree"]
+    n3, m3 = (N + 1) ** 3, (2 * N + 1) ** 3
     dt = dom.dt()
     fam = grffe.KERNEL_FAMILIES["dg_substep"]
     dom.step(warmup, dt)
@@ -215,6 +229,7 @@ def run_kerr_schild(steps, warmup, precision, n_elem=16):
     k_ms, k_n = dom.timing_read(fam)
     dom.timing_enable()
     n_dg1, n_fd1 = dom.counts()
+    n_bad = dom.check_finite()
     pts = 0.5 * ((n_dg0 + n_dg1) * n3 + (n_fd0 + n_fd1) * m3)
     n_dg = 0.5 * (n_dg0 + n_dg1)
     byt = n_dg * n3 * (sum(DG_BYTES_PER_NODE.values()) / 3.0 + DG_BG_BYTES_PER_NODE)
@@ -224,6 +239,7 @@ def run_kerr_schild(steps, warmup, precision, n_elem=16):
             "value": pts * 3 * steps / secs, "unit": "grid-point updates/s", "steps": steps,
             "ms_per_step": secs * 1e3 / steps, "dt": dt, "elements_dg_fd": [[int(n_dg0), int(n_fd0)],
                                                                             [int(n_dg1), int(n_fd1)]],
+            "non_finite_elements": n_bad,
             "roofline_dg": {"kernel": "k_dg_substep (fused DG substep, curved)", "bound": "hbm",
                             "achieved": byt / avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": byt / avg / 1e9 / HBM_PEAK_GBS, "mean_launch_us": avg * 1e6,
