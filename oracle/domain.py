@@ -30,7 +30,7 @@ def axis_of(d):
 
 class Domain:
     def __init__(self, n_elem, lower, upper, degree, bc, excised=None, bg=None, params=None, boundary_state=None,
-                 boundary_field=None):
+                 boundary_field=None, conductor=None):
         self.n_elem = tuple(int(v) for v in n_elem)
         self.lower = np.asarray(lower, np.float64)
         self.upper = np.asarray(upper, np.float64)
@@ -56,6 +56,14 @@ class Domain:
             self.boundary_field = (np.asarray(bd, np.float64), np.asarray(bf, np.float64))
         if any(b == BC_DIRICHLET for b in self.bc) and self.boundary_state is None and self.boundary_field is None:
             raise ValueError("Dirichlet faces need boundary_state (6, 9) or boundary_field")
+        # rotating perfect conductor (Sec. IV C): dict(centre=(3,), radius=R, omega=W),
+        # rotation about the z axis through the centre; flat space only
+        self.conductor = None
+        if conductor is not None:
+            if bg is not None:
+                raise ValueError("the rotating conductor is defined in flat space")
+            self.conductor = dict(centre=np.asarray(conductor["centre"], np.float64),
+                                  radius=float(conductor["radius"]), omega=float(conductor["omega"]))
         self._build_neighbours()
         self._build_geometry(bg)
 
@@ -63,6 +71,26 @@ class Domain:
     def coords(self, e):
         nx, ny, _ = self.n_elem
         return e % nx, (e // nx) % ny, e // (nx * ny)
+
+    def point_coords(self, elems, fd):
+        """Coordinates x, y, z (len(elems), k, k, k), axes (z, y, x), of the DG nodes
+        (GLL points of each element, k = N + 1) or of the FD cell centres (k = 2N + 1
+        uniform subcells) of the listed elements."""
+        elems = np.asarray(elems, np.int64)
+        if fd:
+            ref = -1.0 + (2.0 * np.arange(self.m) + 1.0) / self.m
+        else:
+            ref = ops.gll(self.N)[0]
+        k = ref.size
+        out = []
+        for d in range(3):
+            idx = np.array([self.coords(e)[d] for e in elems], np.float64)
+            lo = self.lower[d] + idx * self.h[d]
+            c = lo[:, None] + 0.5 * self.h[d] * (ref[None, :] + 1.0)
+            shape = [len(elems), 1, 1, 1]
+            shape[3 - d] = k
+            out.append(np.broadcast_to(c.reshape(shape), (len(elems), k, k, k)).copy())
+        return out
 
     def index(self, ex, ey, ez):
         nx, ny, _ = self.n_elem

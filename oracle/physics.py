@@ -197,6 +197,26 @@ def constraint_clamp(U, geo, margin):
     return U
 
 
+def corotating_conductor(U, x, y, z, centre, radius, omega):
+    """Rotating perfect conductor (Sec. IV C, pulsar magnetospheres; flat space): at
+    every point with |x - centre| <= radius, E is replaced by the value the ideal
+    condition E^i + eps^{ijk} v_j B_k = 0 gives for the rigid rotation about the
+    z axis through the centre, v = omega z^ x (x - centre) = omega (-(y - c_y),
+    x - c_x, 0), i.e. E = -(v x B); psi~ and q~ are set to zero there.  B and phi~
+    are left to the evolution.  Points outside are returned unchanged."""
+    U = U.copy()
+    rx, ry, rz = x - centre[0], y - centre[1], z - centre[2]
+    inside = rx * rx + ry * ry + rz * rz <= radius * radius
+    v = np.array([-omega * ry, omega * rx, np.zeros_like(rx)])
+    B = U[3:6]
+    vxB = np.einsum("ijk,j...,k...->i...", LEVI, v, B)
+    for i in range(3):
+        U[i] = np.where(inside, -vxB[i], U[i])
+    U[6] = np.where(inside, 0.0, U[6])
+    U[8] = np.where(inside, 0.0, U[8])
+    return U
+
+
 def char_speed(geo, d):
     """Coordinate speed alpha sqrt(gamma^dd) + |beta^d| bounding the light cone along x^d."""
     return geo.alpha * np.sqrt(geo.ginv[d, d]) + np.abs(geo.beta[d])

@@ -151,18 +151,27 @@ def _identity(u):
     return u
 
 
-def _post_dg(dom, C, geo):
+def _post(dom, C, geo, el, fd):
+    """What follows the update of every substep: the optional algebraic clamp, then
+    the rotating conductor's E, psi~, q~ inside its sphere (Sec. IV C: enforced at
+    every substep; here on the three substep results U_3, U_4, U^{n+1}, before the
+    indicator looks at them -- it sees only B~, which neither changes)."""
     p = dom.params
     if p["ff_clamp"]:
         C = ph.constraint_clamp(C, geo, p["ff_margin"])
+    if dom.conductor is not None:
+        c = dom.conductor
+        x, y, z = dom.point_coords(el, fd)
+        C = ph.corotating_conductor(C, x, y, z, c["centre"], c["radius"], c["omega"])
     return C
 
 
-def _post_fd(dom, C, geo):
-    p = dom.params
-    if p["ff_clamp"]:
-        C = ph.constraint_clamp(C, geo, p["ff_margin"])
-    return C
+def _post_dg(dom, C, geo, el):
+    return _post(dom, C, geo, el, False)
+
+
+def _post_fd(dom, C, geo, el):
+    return _post(dom, C, geo, el, True)
 
 
 def _M(dom):
@@ -207,7 +216,7 @@ def step(dom, st, dt, log=None):
                 Lk = fd_rhs(dom, el, W[1][:, el], W[0], W[1], rep0, parts=1)
             Hs = {key: v[r][:, el] for key, v in H.items()}
             C, upd = _candidate(dom, k, Hs, X[r][:, el], Lk, geo, dt, _filter_fn(dom) if r == 0 else _identity)
-            C = _post_dg(dom, C, geo) if r == 0 else _post_fd(dom, C, geo)
+            C = _post_dg(dom, C, geo, el) if r == 0 else _post_fd(dom, C, geo, el)
             cand[r][:, el] = C
             for key, v in upd.items():
                 newH.setdefault(key, _pair_zeros(dom))
@@ -232,7 +241,7 @@ def step(dom, st, dt, log=None):
                 Xb = Hs["U%d" % (k + 1)]
             Lk = fd_rhs(dom, bad, with_current(dom, Xb, geo), W[0], W[1], rep0, parts=1)
             C, upd = _candidate(dom, k, Hs, Xb, Lk, geo, dt, _identity)
-            cand[1][:, bad] = _post_fd(dom, C, geo)
+            cand[1][:, bad] = _post_fd(dom, C, geo, bad)
             for key, v in upd.items():
                 newH.setdefault(key, _pair_zeros(dom))
                 newH[key][1][:, bad] = v

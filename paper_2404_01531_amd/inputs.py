@@ -300,6 +300,27 @@ def wald_a0(x, y, z, M=1.0, B0=1.0):
     return U
 
 
+def rotator_dipole(x, y, z, mu=1.0, theta=0.0, delta=0.1):
+    """Initial data of the rotating-star tests (Sec. IV C, flat space): the field of
+    the regularised dipole A = mu m x r / (r^2 + delta^2)^(3/2) with moment direction
+    m = (sin theta, 0, cos theta) (theta = 0: A_phi = mu (x^2 + y^2) / (r^2 +
+    delta^2)^(3/2)),
+        B = curl A = mu [3 r (m . r) - m (r^2 - 2 delta^2)] / (r^2 + delta^2)^(5/2),
+    and E = psi = phi = q = 0."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    z = np.asarray(z, np.float64)
+    m = (np.sin(theta), 0.0, np.cos(theta))
+    r2 = x * x + y * y + z * z
+    s = r2 + delta * delta
+    mr = m[0] * x + m[1] * y + m[2] * z
+    f = mu / (s * s * np.sqrt(s))
+    U = np.zeros((9,) + x.shape)
+    for i, xi in enumerate((x, y, z)):
+        U[3 + i] = f * (3.0 * xi * mr - m[i] * (r2 - 2.0 * delta * delta))
+    return U
+
+
 def _ideal_e_tilde(x, y, z, M, a, Bt):
     """E~^i from E_i = -[ijk] v^j B~^k with v = beta/alpha (plasma at rest in KS coordinates)."""
     alpha, beta, g, ginv, sqrtg = _ks_3p1(x, y, z, M, a)
@@ -416,6 +437,12 @@ def workload(name, **over):
         w = dict(n_elem=(16, 16, 16), lower=(-40.0,) * 3, upper=(40.0,) * 3, degree=5,
                  bc=(BC_NO_INCOMING_POYNTING,) * 6, eta=1e5, cfl=0.25, steps=1000, seed=1003,
                  curved=True, M=1.0, spin=0.9, B0=1.0, r_excise=1.8, kind="kerr_schild")
+    elif name == "rotator":
+        # rotating magnetised star (Sec. IV C): R = 1, one element per R, Omega = 1/(5R),
+        # eta = 1e5/R, dipole regularised with delta = 0.1R, inclination theta
+        w = dict(n_elem=(24, 24, 24), lower=(-12.0,) * 3, upper=(12.0,) * 3, degree=5,
+                 bc=(BC_NO_INCOMING_POYNTING,) * 6, eta=1e5, cfl=0.25, curved=False, kind="rotator",
+                 mu=1.0, theta=0.0, delta=0.1, radius=1.0, omega=0.2, centre=(0.0, 0.0, 0.0))
     elif name == "smooth_fast_wave":  # Sec. IV D 1: [0, 2]^3, 4^3 P5 elements, periodic
         w = dict(n_elem=(4, 4, 4), lower=(0.0,) * 3, upper=(2.0,) * 3, degree=5, bc=(BC_PERIODIC,) * 6, eta=1e6,
                  cfl=0.3, curved=False, kind="smooth_fast_wave", wavelength=2.0)
@@ -514,6 +541,10 @@ def initial_data(w, x, y, z, with_noise=True):
         U = kerr_schild_uniform_field(x, y, z, w.get("M", 1.0), w.get("spin", 0.0), w.get("B0", 1.0))
     elif kind == "wald_a0":
         U = wald_a0(x, y, z, w.get("M", 1.0), w.get("B0", 1.0))
+    elif kind == "rotator":
+        c = w.get("centre", (0.0, 0.0, 0.0))
+        U = rotator_dipole(np.asarray(x) - c[0], np.asarray(y) - c[1], np.asarray(z) - c[2], w.get("mu", 1.0),
+                           w.get("theta", 0.0), w.get("delta", 0.1))
     elif kind in _ONE_D:
         U = _ONE_D[kind][2](x)
     elif kind == "pulses_1d":
