@@ -2,6 +2,7 @@
 // orchestration of one IMEX-SSP3(4,3,3) step with the hybrid DG-FD control.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -443,6 +444,61 @@ extern "C" int grffe_set_boundary_field(grffe_domain* d, const double* ext_dg, c
   return GRFFE_OK;
 }
 
+extern "C" int grffe_set_conductor(grffe_domain* d, const double* centre, double radius, double omega,
+                                   void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (d->parts.size() != 1) return fail(GRFFE_EUNSUPPORTED, "the conductor is set on single domains");
+  if (d->curved) return fail(GRFFE_EUNSUPPORTED, "the rotating conductor is defined in flat space");
+  if (!std::isfinite(radius) || !std::isfinite(omega)) return fail(GRFFE_EINVAL, "radius and omega must be finite");
+  if (radius <= 0.0) {
+    d->cond_count = 0;
+    return GRFFE_OK;
+  }
+  if (!centre) return fail(GRFFE_EINVAL, "centre must not be NULL");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(centre[k])) return fail(GRFFE_EINVAL, "centre must be finite");
+  if (!d->cond_list) {
+    void* p1 = nullptr;
+    void* p2 = nullptr;
+    void* p3 = nullptr;
+    if (int rc = dalloc(d, &p1, sizeof(int32_t) * d->E)) return rc;
+    if (int rc = dalloc(d, &p2, sizeof(double) * 3 * d->E)) return rc;
+    if (int rc = dalloc(d, &p3, sizeof(double) * (MAX_DEG + 1))) return rc;
+    d->cond_list = static_cast<int32_t*>(p1);
+    d->cond_corner = static_cast<double*>(p2);
+    d->cond_ref = static_cast<double*>(p3);
+  }
+  // every element whose box comes within the radius (slightly enlarged, so that no
+  // element holding a point of the sphere is missed; the kernel tests each point)
+  std::vector<int32_t> list;
+  std::vector<double> corner;
+  const double reach = radius * (1.0 + 1e-9);
+  for (int e = 0; e < d->E; ++e) {
+    const int c[3] = {e % d->nx, (e / d->nx) % d->ny, e / (d->nx * d->ny)};
+    double dist2 = 0.0, lo[3];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = d->lower[k] + c[k] * d->h[k];
+      const double q = std::min(std::max(centre[k], lo[k]), lo[k] + d->h[k]);
+      dist2 += (q - centre[k]) * (q - centre[k]);
+    }
+    if (dist2 > reach * reach) continue;
+    list.push_back(e);
+    for (int k = 0; k < 3; ++k) corner.push_back(lo[k]);
+  }
+  hipStream_t st = S(stream);
+  if (!list.empty()) {
+    HIPCHK(hipMemcpyAsync(d->cond_list, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d->cond_corner, corner.data(), sizeof(double) * corner.size(), hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(d->cond_ref, d->ops_h.x.data(), sizeof(double) * d->n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < 3; ++k) d->cond_c[k] = centre[k];
+  d->cond_r = radius;
+  d->cond_omega = omega;
+  d->cond_count = (int)list.size();
+  return GRFFE_OK;
+}
+
 extern "C" int grffe_set_state(grffe_domain* d, const double* dg, const double* fd, const int32_t* rep, void* stream) {
   if (int rc = check_dom(d)) return rc;
   if (!dg || !fd || !rep) return fail(GRFFE_EINVAL, "state pointers must not be NULL");
@@ -525,6 +581,10 @@ struct TimedLaunch {
   }
 };
 
+namespace grffe {
+void launch_conductor(const KArgs& a, int N, const CondArgs& c, int mode, hipStream_t s);
+}  // namespace grffe
+
 // One substep (or a pure right-hand side evaluation when mode == MODE_RHS).
 static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   const int N = d->N;
@@ -547,6 +607,11 @@ static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   }
   { TimedLaunch t(d, 2, st); launch_fd_flux(a, N, cv, st); }
   { TimedLaunch t(d, 3, st); launch_fd_update(a, N, cv, mode, st); }
+  if (mode != MODE_RHS && d->cond_count > 0) {
+    const CondArgs c{d->cond_list, d->cond_corner, d->cond_ref, d->cond_count,
+                     d->cond_c[0], d->cond_c[1], d->cond_c[2], d->cond_r * d->cond_r, d->cond_omega};
+    launch_conductor(a, N, c, mode, st);
+  }
 }
 
 extern "C" int grffe_timing_enable(grffe_domain* d, int mask) {
@@ -638,6 +703,7 @@ static int adjoint_supported(grffe_domain* d) {
   if (d->N > 8) return fail(GRFFE_EUNSUPPORTED, "the adjoint is built for degrees 3..8");
   if (d->par.precision != GRFFE_PRECISION_FP64) return fail(GRFFE_EUNSUPPORTED, "the adjoint runs in FP64 only");
   if (d->par.ff_clamp) return fail(GRFFE_EUNSUPPORTED, "the adjoint does not differentiate the clamp");
+  if (d->cond_count > 0) return fail(GRFFE_EUNSUPPORTED, "the adjoint does not differentiate the rotating conductor");
   return GRFFE_OK;
 }
 

@@ -99,6 +99,15 @@ struct KArgs {
   int sub;
 };
 
+// The rotating conductor's kernel arguments.
+struct CondArgs {
+  const int32_t* list;   // [count] elements that may hold a point of the sphere
+  const double* corner;  // [count][3] lower corners of those elements
+  const double* ref;     // [N + 1] GLL nodes on [-1, 1]
+  int count;
+  double cx, cy, cz, r2, omega;  // centre, radius squared, angular velocity about z
+};
+
 }  // namespace grffe
 
 // One grid of a pool (a batch concatenates several grids of one degree).
@@ -125,6 +134,14 @@ struct grffe_domain {
   double* bfield_dg = nullptr;  // per-point exterior states (grffe_set_boundary_field)
   double* bfield_fd = nullptr;
   uint8_t* bad_flags = nullptr;  // [E] scratch of grffe_check_finite
+  // rotating perfect conductor (grffe_set_conductor): the elements meeting its
+  // sphere, their lower corners, the GLL nodes; off while cond_count == 0
+  int cond_count = 0;
+  int32_t* cond_list = nullptr;
+  double* cond_corner = nullptr;
+  double* cond_ref = nullptr;
+  double cond_c[3] = {0.0, 0.0, 0.0};
+  double cond_r = 0.0, cond_omega = 0.0;
   uint8_t* live = nullptr;
   double* eh = nullptr;   // [E][3]
   double* edt = nullptr;  // [E]

@@ -81,6 +81,7 @@ def lib():
     L.grffe_set_boundary_state.argtypes = [vp, ctypes.POINTER(dbl), vp]
     L.grffe_set_boundary_field.argtypes = [vp, vp, vp, vp]
     L.grffe_check_finite.argtypes = [vp, ctypes.POINTER(i32), vp]
+    L.grffe_set_conductor.argtypes = [vp, vp, dbl, dbl, vp]
     L.grffe_destroy.argtypes = [vp]
     L.grffe_init_from_fd.argtypes = [vp, vp, vp, vp]
     L.grffe_set_state.argtypes = [vp, vp, vp, vp, vp]
@@ -120,7 +121,7 @@ def lib():
                  "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step", "grffe_rhs_adjoint",
                  "grffe_step_adjoint", "grffe_step_adjoint_frozen", "grffe_get_stages",
                  "grffe_step_adjoint_stages", "grffe_set_boundary_state", "grffe_set_boundary_field",
-                 "grffe_check_finite"):
+                 "grffe_check_finite", "grffe_set_conductor"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -253,6 +254,13 @@ class Domain:
         if st.shape != (6, 9):
             raise GrffeError("boundary state must have shape (6, 9)")
         _check(lib().grffe_set_boundary_state(self._h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+
+    def set_conductor(self, centre, radius, omega):
+        """Rotating perfect conductor of the given centre (3,), radius and angular
+        velocity about z; radius <= 0 switches it off."""
+        c = np.ascontiguousarray(np.asarray(centre, np.float64).reshape(3))
+        _check(lib().grffe_set_conductor(self._h, c.ctypes.data_as(ctypes.c_void_p), float(radius), float(omega),
+                                         _stream()))
 
     def check_finite(self):
         """Number of elements holding NaN or infinite values (0 for a healthy state)."""
