@@ -70,7 +70,27 @@ def parse():
     ap.add_argument("--extra-steps", type=int, default=30)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--rotator", action="store_true",
+                    help="only run the rotating-star spin-down sweep (inclinations 0, 30, 45, 60, 90 degrees, "
+                         "two periods each, about 7 minutes) and fit L = L0 (k1 + k2 sin^2 theta)")
     return ap.parse_args()
+
+
+def rotator_sweep():
+    """Spin-down luminosity against inclination (Sec. IV C, oblique rotator): one JSON
+    line per angle, then the least-squares fit of L / L(0) = k1 + k2 sin^2 theta."""
+    import math
+
+    import numpy as np
+    L = []
+    angles = (0.0, math.pi / 6, math.pi / 4, math.pi / 3, math.pi / 2)
+    for th in angles:
+        r = run_rotator(th)
+        print(json.dumps(r), flush=True)
+        L.append(r["luminosity"])
+    s2 = np.sin(np.asarray(angles)) ** 2
+    k2, k1 = np.polyfit(s2, np.asarray(L) / L[0], 1)
+    print(json.dumps({"fit": "L/L(0) = k1 + k2 sin^2 theta", "k1": float(k1), "k2": float(k2)}), flush=True)
 
 
 def copy_probe():
@@ -244,6 +264,65 @@ def run_kerr_schild(steps, warmup, precision, n_elem=16):
                             "achieved": byt / avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": byt / avg / 1e9 / HBM_PEAK_GBS, "mean_launch_us": avg * 1e6,
                             "launches": int(k_n), "bytes_per_launch": byt}}
+
+
+def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, samples=8):
+    """Rotating magnetised star (Sec. IV C): the regularised dipole of inclination
+    theta inside a perfect conductor of radius R = 1 rotating at Omega = 0.2 about z,
+    flat space, [-half_width, half_width]^3 with n_elem^3 P5 elements (one element per
+    R at the defaults), no-incoming-Poynting faces, eta = 1e5, CFL 0.25, adaptive
+    DG/FD.  After `periods` rotation periods the Poynting luminosity through the
+    sphere r = r_measure (Eq. of the spin-down luminosity; FD elements taken through
+    R to their DG polynomial) is averaged over the last tenth of a period."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    from paper_2404_01531_amd.poynting import SphereFlux
+    w = I.workload("rotator", n_elem=(n_elem,) * 3, lower=(-half_width,) * 3, upper=(half_width,) * 3, theta=theta)
+    N = w["degree"]
+    p = grffe.default_params(eta=w["eta"], cfl=w["cfl"])
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p)
+    dom.set_conductor(w["centre"], w["radius"], w["omega"])
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], N)
+    E = int(np.prod(w["n_elem"]))
+    dom.init_from_fd(torch.from_numpy(np.ascontiguousarray(I.initial_data(w, xf, yf, zf).reshape(9, E, -1))).cuda())
+    del xf, yf, zf
+    dt = dom.dt()
+    period = 2.0 * math.pi / w["omega"]
+    total = int(math.ceil(periods * period / dt))
+    tail = int(math.ceil(0.1 * period / dt))
+    flux = SphereFlux(w, R=r_measure)
+
+    def luminosity():
+        dg, fd, rep = dom.get_state()
+        el = torch.nonzero(rep == 1).flatten().to(torch.int32)
+        if el.numel():
+            dg[:, el.long()] = dom.reconstruct_fd_to_dg(fd[:, el.long()].contiguous(), el)
+        return float(flux(dg))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dom.step(total - tail, dt)
+    Ls = []
+    chunk = max(1, tail // samples)
+    done = total - tail
+    while done < total:
+        k = min(chunk, total - done)
+        dom.step(k, dt)
+        done += k
+        Ls.append(luminosity())
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    n_dg, n_fd = dom.counts()
+    L0 = 4.0 * math.pi * w["mu"] ** 2 * w["omega"] ** 4
+    return {"theta": theta, "steps": total, "dt": dt, "t": total * dt, "seconds": secs,
+            "luminosity": float(np.mean(Ls)), "luminosity_spread": float(np.ptp(Ls)),
+            "luminosity_over_4pi_mu2_omega4": float(np.mean(Ls)) / L0, "elements_dg_fd": [int(n_dg), int(n_fd)],
+            "non_finite_elements": dom.check_finite()}
 
 
 def run_batch(steps, warmup, precision, use_graph=True):
@@ -643,6 +722,9 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.rotator:
+        rotator_sweep()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
