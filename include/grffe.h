@@ -29,8 +29,8 @@
  *    failure on the calling thread is returned by grffe_last_error().  No
  *    implicit device synchronisation happens except where a host value is
  *    returned (grffe_get_dt, grffe_get_counts, grffe_timing_read,
- *    grffe_check_finite) and in grffe_set_boundary_state, which waits for its
- *    host-to-device copy.
+ *    grffe_check_finite) and in grffe_set_boundary_state and grffe_set_conductor,
+ *    which wait for their host-to-device copies.
  *  - A domain is not thread-safe; separate domains are independent.
  */
 #ifndef GRFFE_H
