@@ -318,10 +318,23 @@ def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, s
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     n_dg, n_fd = dom.counts()
+    # where the FD elements are: the band around the equatorial plane beyond the
+    # light cylinder (the current sheet) against the polar caps inside it
+    _, _, rep = dom.get_state()
+    on_fd = rep.cpu().numpy() == 1
+    h = (w["upper"][0] - w["lower"][0]) / w["n_elem"][0]
+    idx = np.arange(E)
+    ne = w["n_elem"][0]
+    cx, cy, cz = (w["lower"][0] + h * (0.5 + v) for v in (idx % ne, (idx // ne) % ne, idx // (ne * ne)))
+    rho = np.hypot(cx, cy)
+    lc = 1.0 / w["omega"]
+    sheet = (np.abs(cz) < 1.5 * h) & (rho > 1.2 * lc) & (rho < 2.0 * lc)
+    polar = (np.abs(cz) > 1.2 * lc) & (np.abs(cz) < 2.0 * lc) & (rho < 0.6 * lc)
     L0 = 4.0 * math.pi * w["mu"] ** 2 * w["omega"] ** 4
     return {"theta": theta, "steps": total, "dt": dt, "t": total * dt, "seconds": secs,
             "luminosity": float(np.mean(Ls)), "luminosity_spread": float(np.ptp(Ls)),
             "luminosity_over_4pi_mu2_omega4": float(np.mean(Ls)) / L0, "elements_dg_fd": [int(n_dg), int(n_fd)],
+            "fd_fraction_equatorial_band": float(on_fd[sheet].mean()), "fd_fraction_polar": float(on_fd[polar].mean()),
             "non_finite_elements": dom.check_finite()}
 
 

@@ -5,7 +5,9 @@ mu^2 Omega^4 (Gaussian units; 4 pi mu^2 Omega^4 in the units of these equations,
 where the energy density is (E^2 + B^2)/2), and the orthogonal rotator's is larger
 by the factor k1 + k2 of L = L0 (k1 + k2 sin^2 theta) (paper: k1 = 1.04, k2 = 1.24;
 measured here with all five inclinations: k1 = 1.07, k2 = 1.33).  The luminosity is
-steady over the last tenth of a period and the state stays finite.  These are
+steady over the last tenth of a period, the state stays finite, and in the aligned
+case the FD elements gather in the equatorial current sheet beyond the light
+cylinder rather than over the polar caps.  These are
 physics checks of the whole path (no oracle: 13824 elements over 5109 steps), about
 80 s per inclination."""
 import math
@@ -32,11 +34,15 @@ def test_rotator_spin_down_aligned_and_orthogonal():
         _say(f"rotator theta = {th:.3f}: L = {r['luminosity']:.5f} ({r['luminosity_over_4pi_mu2_omega4']:.3f} of "
              f"4 pi mu^2 Omega^4), spread {r['luminosity_spread']:.2e}, DG/FD {r['elements_dg_fd']}, "
              f"{r['seconds']:.0f} s")
+        _say(f"  FD fraction: equatorial band beyond the light cylinder {r['fd_fraction_equatorial_band']:.2f}, "
+             f"polar caps {r['fd_fraction_polar']:.2f}")
         assert r["non_finite_elements"] == 0
         assert r["luminosity_spread"] < 0.05 * r["luminosity"]
         out[th] = r["luminosity"]
         if th == 0.0:
             assert 0.6 < r["luminosity_over_4pi_mu2_omega4"] < 1.2
+            # the indicator tracks the equatorial current sheet (Sec. IV C)
+            assert r["fd_fraction_equatorial_band"] > 2.0 * r["fd_fraction_polar"]
     ratio = out[math.pi / 2] / out[0.0]
     _say(f"L(90 deg) / L(0) = {ratio:.3f} (paper's fit: {1.04 + 1.24:.2f})")
     assert 1.8 < ratio < 2.8
