@@ -315,9 +315,19 @@ __global__ __launch_bounds__(flux_tpb<N>()) void k_fd_flux(KArgs a) {
   __shared__ double sRf[NR * F * L];
   __shared__ double sM[CURVED ? NBGF * L * (m + 2) : 1];
   const int t = threadIdx.x;
-  // work items: (listed FD element, direction, row of pencils)
+  // work items: (listed FD element, direction, row of pencils).  Workgroups are
+  // dealt to the eight XCDs in turn (block b to XCD b mod 8), each with its own
+  // L2: every XCD takes a contiguous run of items, so that the 3m items of one
+  // element, which read the same cells, share one L2.
   const int items = a.fd_count[a.sub] * 3 * m;
-  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+  constexpr int NX = 8;
+  const bool split = gridDim.x % NX == 0;
+  const int xcd = split ? (int)blockIdx.x % NX : 0;
+  const int per = split ? (items + NX - 1) / NX : items;
+  const int step = split ? (int)gridDim.x / NX : (int)gridDim.x;
+  for (int l = split ? (int)blockIdx.x / NX : (int)blockIdx.x; l < per; l += step) {
+  const int item = xcd * per + l;
+  if (item >= items) break;  // the same for every thread of the block
   const int e = a.fd_list[item / (3 * m)];
   const int d = (item / m) % 3;
   const int t2 = item % m;
