@@ -53,8 +53,8 @@ TIMING_PERIOD = 10
 # 44293.9, write 39781.3), scaled by what the same counters read for a plain
 # 512 MiB device copy (fetch x 2.0, write x 1.0).  Valid for the kernel source
 # whose hash is FD_FLUX_TRAFFIC_SRC; reported as null for any other source.
-FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 45459.3 + 1.0 * 39781.2) * 1024.0 / 128.0
-FD_FLUX_TRAFFIC_SRC = "df012830e428c309"
+FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 14938.3 + 1.0 * 36196.7) * 1024.0 / 128.0
+FD_FLUX_TRAFFIC_SRC = "8627b7c1377cba16"
 
 
 def parse():
