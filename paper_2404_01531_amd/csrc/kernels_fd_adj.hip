@@ -123,7 +123,17 @@ __global__ __launch_bounds__(256) void k_fd_adj_flux(KArgs a, FdAdj b) {
   __shared__ double sM[CURVED ? NBGF * CF * L : 1];
   const int t = threadIdx.x;
   const int items = a.fd_count[a.sub] * 3 * m;
-  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+  // XCD-aware order, as in the forward flux kernel: each of the eight XCDs (which
+  // receive workgroups in turn) takes a contiguous run of items, so the rows of
+  // one element share one L2
+  constexpr int NX = 8;
+  const bool split = gridDim.x % NX == 0;
+  const int xcd = split ? (int)blockIdx.x % NX : 0;
+  const int per = split ? (items + NX - 1) / NX : items;
+  const int step = split ? (int)gridDim.x / NX : (int)gridDim.x;
+  for (int l = split ? (int)blockIdx.x / NX : (int)blockIdx.x; l < per; l += step) {
+    const int item = xcd * per + l;
+    if (item >= items) break;  // the same for every thread of the block
     const int e = a.fd_list[item / (3 * m)];
     const int d = (item / m) % 3;
     const int t2 = item % m;
