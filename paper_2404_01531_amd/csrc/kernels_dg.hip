@@ -99,8 +99,13 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
   __shared__ R sD[n * n];            // derivative matrix in the flux arithmetic type
   __shared__ double sX[6 * NW * n * n];  // exterior face data
   __shared__ int sO[6], sR[6];
-  const int e = blockIdx.x;
-  if (!a.live[e] || a.rep0[e] != 0) return;
+  // XCD-aware order: workgroups are dealt to the eight XCDs in turn, each with its
+  // own L2; XCD x takes the contiguous run of elements [x per, (x + 1) per), so the
+  // face data an element reads from its neighbours is mostly in the same L2 (the
+  // grid is 8 per blocks; those past the last element exit)
+  const int per = (a.E + 7) / 8;
+  const int e = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (e >= a.E || !a.live[e] || a.rep0[e] != 0) return;
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int p = act ? t : 0;
@@ -370,7 +375,7 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
 
 template <int N, bool CURVED, typename R>
 static void launch_dg_substep_r(const KArgs& a, int mode, hipStream_t s) {
-  dim3 grid(a.E), block(Dims<N>::tpb);
+  dim3 grid(8 * ((a.E + 7) / 8)), block(Dims<N>::tpb);
   switch (mode) {
     case MODE_RHS: launch_kernel(k_dg_substep<N, CURVED, MODE_RHS, R>, grid, block, s, a); break;
     case MODE_SUB1: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB1, R>, grid, block, s, a); break;
