@@ -53,7 +53,7 @@ TIMING_PERIOD = 10
 # 44293.9, write 39781.3), scaled by what the same counters read for a plain
 # 512 MiB device copy (fetch x 2.0, write x 1.0).  Valid for the kernel source
 # whose hash is FD_FLUX_TRAFFIC_SRC; reported as null for any other source.
-FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 14938.3 + 1.0 * 36196.7) * 1024.0 / 128.0
+FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 14940.0 + 1.0 * 36196.0) * 1024.0 / 128.0
 FD_FLUX_TRAFFIC_SRC = "8627b7c1377cba16"
 
 
