@@ -181,7 +181,7 @@ def default_params():
         eta=1e6, kappa_psi=1.0, kappa_phi=1.0,
         cfl=0.25, stab_c=0.0,
         tci_M=0, tci_alpha=4.0, tci_alpha_fd=5.0, tci_mode=2,
-        filter_a=36.0, filter_b=50.0, filter_on=1,
+        filter_a=36.0, filter_b=50.0, filter_on=1, filter_after_solve=0,
         weno_eps=1e-40, fd_order=4,
         ff_clamp=0, ff_margin=1e-12,
         hybrid=1,

@@ -121,18 +121,26 @@ def _candidate(dom, k, H, X, Lk, geo, dt, filt):
 
     ``filt`` is applied to the explicit update of the substep: before the
     pointwise implicit solve in substeps 1 and 2, to the final combination in
-    substep 3 (which has no solve).
+    substep 3 (which has no solve).  The parameter ``filter_after_solve`` = 1
+    moves it behind the solve in substeps 1 and 2 (the other reading of "filter
+    after every substep"; kept only to show that it is unstable with a stiff
+    driver current).
     """
     Un = H["Un"]
     _, _, S1, S2 = derived_stages(dom, Un, geo, dt)
+    post = bool(dom.params.get("filter_after_solve", 0))
+
+    def solve_filtered(Y, h):
+        return filt(_solve(dom, Y, geo, h)) if post else _solve(dom, filt(Y), geo, h)
+
     if k == 1:
         Y = Un + dt * AEX[2, 1] * Lk + dt * (AIM[2, 0] * S1 + AIM[2, 1] * S2)
-        return _solve(dom, filt(Y), geo, dt * AIM[2, 2]), {"L1": Lk}
+        return solve_filtered(Y, dt * AIM[2, 2]), {"L1": Lk}
     if k == 2:
         S3 = _stiff(dom, X, geo)
         Y = (Un + dt * (AEX[3, 1] * H["L1"] + AEX[3, 2] * Lk)
              + dt * (AIM[3, 0] * S1 + AIM[3, 1] * S2 + AIM[3, 2] * S3))
-        return _solve(dom, filt(Y), geo, dt * AIM[3, 3]), {"L2": Lk, "S3": S3}
+        return solve_filtered(Y, dt * AIM[3, 3]), {"L2": Lk, "S3": S3}
     S4 = _stiff(dom, X, geo)
     out = (Un + dt * (BW[1] * H["L1"] + BW[2] * H["L2"] + BW[3] * Lk)
            + dt * (BW[1] * S2 + BW[2] * H["S3"] + BW[3] * S4))
@@ -179,8 +187,13 @@ def _M(dom):
     return p["tci_M"] if p["tci_M"] else ops.tci_M(dom.N)
 
 
-def step(dom, st, dt, log=None):
-    """Advance State ``st`` by one step of size dt; returns a new State."""
+def step(dom, st, dt, log=None, force=None):
+    """Advance State ``st`` by one step of size dt; returns a new State.
+
+    ``force`` (test instrument, nullable): boolean array (3, E); in the adaptive
+    mode an element on DG with force[k - 1] set is treated as troubled in
+    substep k whatever its indicator ratio (a host-forced flag, so that rollbacks
+    can be made to happen in any substep)."""
     p = dom.params
     act = dom.active
     N, M = dom.N, _M(dom)
@@ -225,7 +238,10 @@ def step(dom, st, dt, log=None):
         bad = np.zeros(0, np.int64)
         if p["hybrid"] == HYBRID_ADAPTIVE and dg_e.size:
             ratio = tci_ratio(cand[0][:, dg_e], geo_take(dom.geo_dg, dg_e), N, M, p["tci_mode"])
-            bad = dg_e[ratio > thr]
+            hit = ratio > thr
+            if force is not None:
+                hit = hit | np.asarray(force, bool)[k - 1][dg_e]
+            bad = dg_e[hit]
             if log is not None:
                 log.append(("substep", k, dg_e.copy(), ratio.copy(), thr))
         if bad.size:
