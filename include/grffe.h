@@ -175,6 +175,17 @@ int grffe_destroy(grffe_domain* dom);
  * all go DG. */
 int grffe_init_from_fd(grffe_domain* dom, const double* u_fd, const uint8_t* forced, void* stream);
 
+/* Host-forced indicator flags, a test instrument (fault injection): mask (device
+ * uint8 [3][E], row k - 1 for substep k) marks elements that the adaptive step
+ * (GRFFE_HYBRID_ADAPTIVE) treats as troubled in substep k of every following step
+ * whatever their indicator ratio, so that the rollback of Sec. III C 1 (discard the
+ * DG candidate, project the element's registers with P, redo the substep on FD) can
+ * be made to happen in any substep; elements already on FD ignore it.  The mask is
+ * copied into the domain (allocated at the first call) on `stream`; mask = NULL
+ * switches the forcing off.  The frozen step adjoint re-runs its forward step with
+ * the same forcing.  Returns GRFFE_ENOMEM or GRFFE_EHIP on failure. */
+int grffe_force_flags(grffe_domain* dom, const uint8_t* mask, void* stream);
+
 /* Copy the state in / out.  dg [9][E][n^3], fd [9][E][m^3] and rep [E] are device
  * pointers; on set, only the representation named by rep is read per element (all
  * three non-NULL); on get, a NULL pointer skips that part. */

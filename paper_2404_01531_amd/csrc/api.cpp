@@ -91,6 +91,7 @@ KArgs make_args(grffe_domain* d) {
   a.rep0 = d->rep0;
   a.rep = d->rep;
   a.troubled = d->troubled;
+  a.force = d->force_on ? d->force : nullptr;
   a.ratio = d->ratio;
   a.w_fd = d->w_fd;
   a.trace = d->trace;
@@ -496,6 +497,22 @@ extern "C" int grffe_set_conductor(grffe_domain* d, const double* centre, double
   d->cond_r = radius;
   d->cond_omega = omega;
   d->cond_count = (int)list.size();
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_force_flags(grffe_domain* d, const uint8_t* mask, void* stream) {
+  if (int rc = check_dom(d)) return rc;
+  if (!mask) {
+    d->force_on = false;
+    return GRFFE_OK;
+  }
+  if (!d->force) {
+    void* p = nullptr;
+    if (int rc = dalloc(d, &p, (size_t)3 * d->E)) return rc;
+    d->force = static_cast<uint8_t*>(p);
+  }
+  HIPCHK(hipMemcpyAsync(d->force, mask, (size_t)3 * d->E, hipMemcpyDeviceToDevice, S(stream)));
+  d->force_on = true;
   return GRFFE_OK;
 }
 

@@ -76,6 +76,7 @@ struct KArgs {
   int32_t* rep0;           // representation at the start of the substep
   int32_t* rep;            // representation being built
   uint8_t* troubled;       // [E] flags of the current substep
+  const uint8_t* force;    // [3][E] host-forced indicator flags of substeps 1..3, or null
   double* ratio;           // [E] indicator ratios (diagnostic)
   // scratch
   double* w_fd;            // [12][E][m^3]  FD stage values + J~
@@ -134,6 +135,8 @@ struct grffe_domain {
   double* bfield_dg = nullptr;  // per-point exterior states (grffe_set_boundary_field)
   double* bfield_fd = nullptr;
   uint8_t* bad_flags = nullptr;  // [E] scratch of grffe_check_finite
+  uint8_t* force = nullptr;      // [3][E] forced indicator flags (grffe_force_flags)
+  bool force_on = false;
   // rotating perfect conductor (grffe_set_conductor): the elements meeting its
   // sphere, their lower corners, the GLL nodes; off while cond_count == 0
   int cond_count = 0;

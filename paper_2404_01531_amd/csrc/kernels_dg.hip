@@ -252,7 +252,7 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
     double den = act ? u * u : 0.0;
     block_sum2<TPB>(num, den, sred);
     const double ratio = den > 0.0 ? sqrt(num / den) : 0.0;
-    bad = ratio > a.tci_thr;
+    bad = ratio > a.tci_thr || (a.force != nullptr && a.force[(size_t)(MODE - 1) * a.E + e] != 0);
     if (t == 0) {
       a.ratio[e] = ratio;
       if (bad) {

@@ -578,17 +578,19 @@ __global__ __launch_bounds__(256) void k_fd_update(KArgs a) {
 
 // ---------------------------------------------------------------- indicator helpers
 // u = |B~| at the DG nodes of R (x) R (x) R applied to the FD B~ of element e (from `fd`),
-// or taken directly from `dg`; returns the indicator ratio (block-wide).
+// or taken directly from `dg`; returns the indicator ratio (block-wide).  Each of the
+// 256 threads holds PER = ceil((N+1)^3 / 256) nodes (up to four at N = 9).
 template <int N, bool CURVED>
 __device__ inline double block_ratio(const KArgs& a, int e, const double* Bn /* [3][nn] in LDS */,
                                      double* su, double* sred, const double* sL) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn, TPB = 256;
+  constexpr int PER = (nn + TPB - 1) / TPB;
   const int t = threadIdx.x;
   double num = 0.0, den = 0.0;
-  // up to two nodes per thread for N <= 7 (nn <= 512)
-  double u[2], uh[2];
-  for (int r = 0; r < 2; ++r) {
+  double u[PER], uh[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
     const int p = t + r * TPB;
     u[r] = 0.0;
     if (p < nn) {
@@ -602,10 +604,12 @@ __device__ inline double block_ratio(const KArgs& a, int e, const double* Bn /* 
   const int str[3] = {1, n, n * n};
   for (int d = 0; d < 3; ++d) {
     __syncthreads();
-    for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
       if (t + r * TPB < nn) su[t + r * TPB] = uh[r];
     __syncthreads();
-    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
       const int p = t + r * TPB;
       if (p >= nn) continue;
       const int id = (p / str[d]) % n;
@@ -615,7 +619,8 @@ __device__ inline double block_ratio(const KArgs& a, int e, const double* Bn /* 
       uh[r] = acc;
     }
   }
-  for (int r = 0; r < 2; ++r) {
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
     if (t + r * TPB >= nn) continue;
     const double hp = (a.tci_mode == 1) ? uh[r] : (u[r] - uh[r]);
     num += hp * hp;

@@ -85,6 +85,7 @@ def lib():
     L.grffe_destroy.argtypes = [vp]
     L.grffe_init_from_fd.argtypes = [vp, vp, vp, vp]
     L.grffe_set_state.argtypes = [vp, vp, vp, vp, vp]
+    L.grffe_force_flags.argtypes = [vp, vp, vp]
     L.grffe_get_state.argtypes = [vp, vp, vp, vp, vp]
     L.grffe_rhs.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
     L.grffe_step.argtypes = [vp, ctypes.c_int, dbl, vp]
@@ -247,6 +248,17 @@ class Domain:
     def set_state(self, dg, fd, rep):
         self._check_state(dg, fd, rep)
         _check(lib().grffe_set_state(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _stream()))
+
+    def force_flags(self, mask):
+        """Host-forced indicator flags (test instrument): mask is a device uint8 tensor
+        (3, E), row k - 1 forcing the rollback of its DG elements in substep k of every
+        following adaptive step; None switches the forcing off."""
+        if mask is not None:
+            if tuple(mask.shape) != (3, self.E) or str(mask.dtype) != "torch.uint8":
+                raise GrffeError("forced flags must be a uint8 tensor of shape (3, E)")
+            mask = mask.contiguous()
+        _check(lib().grffe_force_flags(self._h, _ptr(mask), _stream()))
+        self._force = mask  # kept alive until the copy on the stream has run
 
     def set_boundary_state(self, state):
         """Exterior states of the Dirichlet faces: (6, 9) host array, row f = 2 d + s."""

@@ -1,0 +1,266 @@
+"""GPU parity of the hybrid control (Sec. III C 1) in every substep, and of the
+indicator at high degree.
+
+Rollbacks happen in substep 1 on their own (the first candidate of a step is the
+roughest); to reach the transitions of substeps 2 and 3 the tests force the
+indicator's flags from the host (grffe_force_flags in the library, the `force`
+argument of the oracle's step): a forced element discards its DG candidate,
+moves its registers to FD with P and redoes the substep there, exactly as a
+flagged one.  Both sides take the same forced flags; the indicator's own flags,
+the representation after every step and the state (per variable group, 1e-12 of
+the field scale) must agree.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from oracle import step as OS
+from oracle import tci as OT
+from oracle.domain import DG, FD
+from paper_2404_01531_amd import inputs as I
+
+from helpers import from_dev, group_err, make_pair, node_coords, rel_err, to_dev
+from helpers import state_arrays as _state_arrays
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+TOL_FD = 2e-6
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _mask(E, rolls):
+    m = np.zeros((3, E), bool)
+    for k, els in rolls.items():
+        m[k - 1, els] = True
+    return m
+
+
+def _compare(odom, st, ldom, label, k):
+    gdg, gfd, grep = ldom.get_state()
+    grep = grep.cpu().numpy()
+    assert np.array_equal(grep, st.rep), f"{label}: representation differs after step {k}"
+    gdg, gfd = from_dev(gdg, st.dg.shape), from_dev(gfd, st.fd.shape)
+    worst = 0.0
+    for r, G, R in ((DG, gdg, st.dg), (FD, gfd, st.fd)):
+        el = np.nonzero(odom.active & (st.rep == r))[0]
+        if el.size:
+            e = group_err(G[:, el], R[:, el])
+            worst = max(worst, float(e.max()))
+            assert np.all(e <= RTOL), (label, k, r, e.tolist())
+    return worst
+
+
+def _forced_run(w, params, rolls, nsteps, label, u_dg=None):
+    """Adaptive steps with host-forced flags on both sides; returns the oracle's logs."""
+    torch = _torch()
+    odom, ldom, _ = make_pair(w, params)
+    force = _mask(odom.E, rolls)
+    if u_dg is None:
+        xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+        u_fd = I.initial_data(w, xf, yf, zf)
+        st = OS.initial_state(odom, u_fd)
+        ldom.init_from_fd(to_dev(u_fd))
+    else:
+        rep = np.zeros(odom.E, np.int64)
+        st = OS.State(u_dg, np.zeros((9, odom.E, odom.m, odom.m, odom.m)), rep)
+        ldom.set_state(to_dev(u_dg), to_dev(st.fd), torch.from_numpy(rep.astype(np.int32)).cuda())
+    ldom.force_flags(torch.from_numpy(force.astype(np.uint8)).cuda())
+    dt = ldom.dt()
+    logs, worst = [], 0.0
+    for k in range(nsteps):
+        log = []
+        rep_before = st.rep.copy()
+        st = OS.step(odom, st, dt, log=log, force=force)
+        ldom.step(1, dt)
+        worst = max(worst, _compare(odom, st, ldom, label, k + 1))
+        # which DG elements moved to FD in each substep (forced or flagged)
+        moved = {kk: sorted(set(dg_e[(ratio > thr) | force[kk - 1][dg_e]].tolist()))
+                 for (tag, kk, dg_e, ratio, thr) in [l for l in log if l[0] == "substep"]}
+        logs.append((rep_before, moved))
+    ldom.force_flags(None)
+    _say(f"forced rollbacks {label}: {nsteps} steps, moved per substep {[m for _, m in logs]}, "
+         f"worst group err {worst:.2e}")
+    return logs
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_forced_rollbacks_in_every_substep_flat(N):
+    """Smooth wave (every element starts on DG): elements forced in substep 1, 2 and 3
+    (one of each pair next to the other), two steps; the forced elements go back to
+    DG at the end of each step (smooth data), so every step repeats the rollbacks."""
+    w = I.workload("wave", n_elem=(4, 2, 2), degree=N)
+    rolls = {1: [0], 2: [1, 6], 3: [2, 13]}
+    logs = _forced_run(w, dict(eta=w["eta"], cfl=w["cfl"]), rolls, 2, f"wave 4x2x2 P{N}")
+    for _, moved in logs:
+        for k, els in rolls.items():
+            assert set(els) <= set(moved[k])
+
+
+def test_forced_rollbacks_sheet_with_natural_flags():
+    """The current sheet: the indicator's own rollbacks in substep 1 next to forced
+    ones in substeps 2 and 3 of elements away from the sheet."""
+    w = I.workload("sheet", n_elem=(4, 2, 2))
+    rolls = {2: [0, 8], 3: [3, 15]}
+    _forced_run(w, dict(eta=w["eta"], cfl=w["cfl"]), rolls, 3, "sheet 4x2x2 P5")
+
+
+def test_forced_rollbacks_kerr_schild():
+    """Curved background with excision: rollbacks forced in substeps 2 and 3 next to the
+    hole and at the outer (no-incoming-Poynting) faces."""
+    w = I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3)
+    rolls = {1: [1], 2: [5, 20], 3: [9, 63]}
+    _forced_run(w, dict(eta=w["eta"], cfl=w["cfl"]), rolls, 2, "kerr-schild 4^3 P5")
+
+
+def test_forced_flags_switch_off():
+    """force_flags(None) restores the indicator's own decisions."""
+    torch = _torch()
+    w = I.workload("wave", n_elem=(2, 2, 2), degree=3)
+    odom, ldom, _ = make_pair(w, dict(eta=w["eta"], cfl=w["cfl"]))
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    u_fd = I.initial_data(w, xf, yf, zf)
+    ldom.init_from_fd(to_dev(u_fd))
+    ldom.force_flags(torch.from_numpy(_mask(odom.E, {3: [0, 1, 2, 3, 4, 5, 6, 7]}).astype(np.uint8)).cuda())
+    ldom.force_flags(None)
+    st = OS.initial_state(odom, u_fd)
+    dt = ldom.dt()
+    st = OS.step(odom, st, dt)
+    ldom.step(1, dt)
+    assert _compare(odom, st, ldom, "forcing off", 1) <= RTOL
+    assert (st.rep == DG).all()
+
+
+# ----------------------------------------------------------- high-degree indicator
+
+
+@pytest.mark.parametrize("N", [8, 9])
+def test_tci_ratio_parity_high_degree(N):
+    """Eq. (persson tci) at N = 8, 9 ((N+1)^3 = 729, 1000 nodes: several per thread of a
+    256-thread workgroup): ratios and flags of DG elements and of FD elements
+    (reconstructed with R) against the oracle."""
+    torch = _torch()
+    w = I.workload("sheet", n_elem=(4, 2, 2), degree=N)
+    odom, ldom, _ = make_pair(w)
+    rng = np.random.default_rng(40 + N)
+    rep = (np.arange(odom.E) % 2).astype(np.int64)
+    dg, fd = _state_arrays(odom, rng, rep, smooth_kind="sheet", noise=1e-4)
+    tr, ratio = ldom.tci(to_dev(dg), to_dev(fd), torch.from_numpy(rep.astype(np.int32)).cuda())
+    tr, ratio = tr.cpu().numpy(), ratio.cpu().numpy()
+    M = ops.tci_M(N)
+    r_dg = OT.tci_ratio(dg, odom.geo_dg, N, M)
+    r_fd = OT.tci_ratio(OT.reconstruct_fd_to_dg(fd, N), odom.geo_dg, N, M)
+    ref = np.where(rep == FD, r_fd, r_dg)
+    thr = np.where(rep == FD, OT.tci_threshold(N, M, 5.0), OT.tci_threshold(N, M, 4.0))
+    _say(f"P{N} indicator: ratios {np.array2string(ref, precision=3)}")
+    assert np.abs(ratio - ref).max() <= 1e-12 * ref.max()
+    assert np.array_equal(tr.astype(bool), ref > thr)
+
+
+@pytest.mark.parametrize("N", [8, 9])
+def test_high_degree_adaptive_start_with_dg_elements(N):
+    """P8 / P9 start-up and adaptive steps where the indicator keeps the smooth part on
+    DG: the noise (1e-7) sits below (N + 1 - M)^-(alpha + 1) (6e-5 at N = 9), so only
+    the elements at the sheet start on FD."""
+    torch = _torch()
+    w = I.workload("sheet", n_elem=(4, 2, 2), degree=N, noise=1e-7)
+    odom, ldom, _ = make_pair(w, dict(eta=w["eta"], cfl=w["cfl"]))
+    xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
+    u_fd = I.initial_data(w, xf, yf, zf)
+    st = OS.initial_state(odom, u_fd)
+    ldom.init_from_fd(to_dev(u_fd))
+    _, _, grep = ldom.get_state()
+    assert np.array_equal(grep.cpu().numpy(), st.rep)
+    n_dg = int((st.rep == DG).sum())
+    _say(f"P{N} start-up: {n_dg} DG and {odom.E - n_dg} FD elements")
+    assert 0 < n_dg < odom.E
+    dt = ldom.dt()
+    for k in range(2):
+        st = OS.step(odom, st, dt)
+        ldom.step(1, dt)
+        _compare(odom, st, ldom, f"sheet P{N} low noise", k + 1)
+
+
+# ----------------------------------------------- adjoint through forced rollbacks
+
+
+def test_frozen_step_adjoint_through_rollbacks_in_substeps_2_and_3():
+    """The step adjoint with the decisions frozen (grffe_step_adjoint_frozen) through
+    rollbacks in substeps 2 and 3 (forced) and the switches back at the end of the
+    step: dot-product identity against Richardson-extrapolated central differences of
+    the oracle's and the library's forced adaptive step (P3 wave, every component
+    with 1e-4 noise, eta = 300 as in the other FD adjoint tests)."""
+    torch = _torch()
+    w = dict(I.workload("wave", n_elem=(4, 2, 2), degree=3))
+    rng = np.random.default_rng(91)
+    params = dict(eta=300.0, cfl=w["cfl"], hybrid=1)
+    odom, ldom, _ = make_pair(w, params)
+    E = odom.E
+    x, y, z = node_coords(w)
+    dg = I.initial_data(w, x, y, z, with_noise=False) + 1e-4 * rng.standard_normal((9,) + x.shape)
+    dg = dg.reshape(9, E, odom.n, odom.n, odom.n)
+    fd = np.zeros((9, E, odom.m, odom.m, odom.m))
+    rep = np.zeros(E, np.int64)
+    rep_t = torch.from_numpy(rep.astype(np.int32)).cuda()
+    force = _mask(E, {2: [1, 6], 3: [2, 13]})
+    ldom.force_flags(torch.from_numpy(force.astype(np.uint8)).cuda())
+    dt = odom.dt()
+    zero_d = torch.zeros(ldom.dg_shape(), dtype=torch.float64, device="cuda")
+    zero_f = torch.zeros(ldom.fd_shape(), dtype=torch.float64, device="cuda")
+    _, _, log = ldom.step_adjoint_frozen(to_dev(dg), to_dev(fd), rep_t, zero_d, zero_f, dt, with_log=True)
+    log = log.cpu().numpy()
+    flagged = [sorted(np.nonzero((log[k - 1] == 0) & (log[k] == 1))[0].tolist()) for k in (1, 2, 3)]
+    back = sorted(np.nonzero((log[3] == 1) & (log[4] == 0))[0].tolist())
+    _say(f"forced adaptive step: moved to FD in substeps 1-3: {flagged}, switched back: {back}")
+    assert flagged == [[], [1, 6], [2, 13]]
+    rep_end = log[4].astype(np.int64)
+    mu_d = rng.standard_normal(dg.shape)
+    mu_f = rng.standard_normal(fd.shape)
+    mu_d[:, rep_end == 1] = 0.0
+    mu_f[:, rep_end == 0] = 0.0
+    scale = np.abs(dg).max(axis=(1, 2, 3, 4))[:, None, None, None, None]
+    del_d = rng.standard_normal(dg.shape) * scale
+    ld, lf = ldom.step_adjoint_frozen(to_dev(dg), to_dev(fd), rep_t, to_dev(mu_d), to_dev(mu_f), dt)
+    ld = ld.cpu().numpy().reshape(dg.shape)
+    lhs = float((ld * del_d).sum())
+
+    def ddir(step):
+        def D(eps):
+            pd, pf = step(dg + eps * del_d)
+            md, mf = step(dg - eps * del_d)
+            return float(((mu_d * (pd - md)).sum() + (mu_f * (pf - mf)).sum()) / (2 * eps))
+        return (4.0 * D(2e-9) - D(4e-9)) / 3.0
+
+    def oracle_step(a):
+        st = OS.step(odom, OS.State(a, fd, rep.copy()), dt, force=force)
+        assert np.array_equal(st.rep, rep_end), "the oracle's decisions differ"
+        return st.dg, st.fd
+
+    def lib_step(a):
+        ldom.set_state(to_dev(a), to_dev(fd), rep_t)
+        ldom.step(1, dt)
+        gd, gf, gr = ldom.get_state()
+        assert np.array_equal(gr.cpu().numpy(), rep_end), "the decisions changed under the perturbation"
+        return gd.cpu().numpy().reshape(dg.shape), gf.cpu().numpy().reshape(fd.shape)
+
+    rhs_o = ddir(oracle_step)
+    rhs_g = ddir(lib_step)
+    ldom.force_flags(None)
+    err_o, err_g = abs(lhs - rhs_o) / abs(lhs), abs(lhs - rhs_g) / abs(lhs)
+    _say(f"forced adaptive step adjoint: <lam,d> {lhs:.12e}  oracle FD {rhs_o:.12e} (err {err_o:.1e})  "
+         f"library FD {rhs_g:.12e} (err {err_g:.1e})")
+    assert err_o <= TOL_FD
+    assert err_g <= TOL_FD

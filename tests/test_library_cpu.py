@@ -111,6 +111,7 @@ def test_dirichlet_entry_points_on_the_host():
     assert L.grffe_set_boundary_state(None, state, None) == -1
     assert L.grffe_set_boundary_field(None, None, None, None) == -1
     assert L.grffe_check_finite(None, None, None) == -1
+    assert L.grffe_force_flags(None, None, None) == -1
     centre = (ctypes.c_double * 3)()
     assert L.grffe_set_conductor(None, centre, 1.0, 0.2, None) == -1
     p = grffe.default_params()
