@@ -128,3 +128,26 @@ def group_l2(got, ref, floor=1.0):
         rms = max(np.sqrt(np.mean(ref[a:b] ** 2)), floor * rms_all)
         out.append(np.sqrt(np.mean((got[a:b] - ref[a:b]) ** 2)) / rms)
     return np.array(out)
+
+
+U_ROUND = 2.0 ** -53
+
+
+def q_floor(odom, dt, nsteps, emax):
+    """Conditioning floor of the charge density q~ (an absolute bound, added to the
+    1e-12 relative bar of the q~ group when comparing steps at a stiff eta).
+
+    The flux of q~ is the current J~, whose driver part is eta alpha sqrt(gamma)
+    [(E.B / B^2) B + R(E^2 - B^2) / B^2 E] (Eq. electric current density).  After the
+    implicit relaxation E.B and R(E^2 - B^2) sit at the rounding level of their own
+    evaluation, so two correct evaluations of J~ differ by up to about
+    8 u eta max|E~| at a point (u = 2^-53; three-product dot products on each side,
+    two sides).  One step moves q~ by dt times a discrete divergence of J~, at most
+    Lambda = sum_d 4 (2N + 1) / h_d times the largest value (the FD flux difference
+    with its corrector; the DG derivative and lift of the same degree are smaller),
+    so after n steps the two q~ may differ by n dt Lambda 8 u eta max|E~|.  With the
+    paper's eta = 1e6 this is 1e-10 of the field scale on the small test grids; with
+    eta = 1e3 it falls below the 1e-12 bar."""
+    N = odom.N
+    lam = sum(4.0 * (2 * N + 1) / h for h in odom.h)
+    return nsteps * dt * lam * 8.0 * U_ROUND * odom.params["eta"] * emax

@@ -21,7 +21,7 @@ from oracle import tci as OT
 from oracle.domain import DG, FD
 from paper_2404_01531_amd import inputs as I
 
-from helpers import from_dev, group_err, make_pair, node_coords, rel_err, to_dev
+from helpers import from_dev, group_err, make_pair, node_coords, q_floor, rel_err, to_dev
 from helpers import state_arrays as _state_arrays
 
 pytestmark = pytest.mark.gpu
@@ -49,18 +49,28 @@ def _mask(E, rolls):
     return m
 
 
-def _compare(odom, st, ldom, label, k):
+def _compare(odom, st, ldom, label, k, dt):
+    """Representation identical; per variable group max |gpu - oracle| <= 1e-12 of the
+    field scale, the q~ group with the stiff-current conditioning floor added
+    (helpers.q_floor, k steps)."""
     gdg, gfd, grep = ldom.get_state()
     grep = grep.cpu().numpy()
     assert np.array_equal(grep, st.rep), f"{label}: representation differs after step {k}"
     gdg, gfd = from_dev(gdg, st.dg.shape), from_dev(gfd, st.fd.shape)
     worst = 0.0
+    act = odom.active
+    emax = max(np.abs(st.dg[0:3, act & (st.rep == DG)]).max(initial=0.0),
+               np.abs(st.fd[0:3, act & (st.rep == FD)]).max(initial=0.0))
     for r, G, R in ((DG, gdg, st.dg), (FD, gfd, st.fd)):
-        el = np.nonzero(odom.active & (st.rep == r))[0]
+        el = np.nonzero(act & (st.rep == r))[0]
         if el.size:
             e = group_err(G[:, el], R[:, el])
+            overall = np.abs(R[:, el]).max()
+            tol = np.full(5, RTOL)
+            tol[4] += q_floor(odom, dt, k, emax) / overall
             worst = max(worst, float(e.max()))
-            assert np.all(e <= RTOL), (label, k, r, e.tolist())
+            _say(f"  step {k} rep {r}: group err {np.array2string(e, precision=2)} (q~ bound {tol[4]:.1e})")
+            assert np.all(e <= tol), (label, k, r, e.tolist())
     return worst
 
 
@@ -86,7 +96,7 @@ def _forced_run(w, params, rolls, nsteps, label, u_dg=None):
         rep_before = st.rep.copy()
         st = OS.step(odom, st, dt, log=log, force=force)
         ldom.step(1, dt)
-        worst = max(worst, _compare(odom, st, ldom, label, k + 1))
+        worst = max(worst, _compare(odom, st, ldom, label, k + 1, dt))
         # which DG elements moved to FD in each substep (forced or flagged)
         moved = {kk: sorted(set(dg_e[(ratio > thr) | force[kk - 1][dg_e]].tolist()))
                  for (tag, kk, dg_e, ratio, thr) in [l for l in log if l[0] == "substep"]}
@@ -140,7 +150,7 @@ def test_forced_flags_switch_off():
     dt = ldom.dt()
     st = OS.step(odom, st, dt)
     ldom.step(1, dt)
-    assert _compare(odom, st, ldom, "forcing off", 1) <= RTOL
+    _compare(odom, st, ldom, "forcing off", 1, dt)
     assert (st.rep == DG).all()
 
 
@@ -173,10 +183,11 @@ def test_tci_ratio_parity_high_degree(N):
 @pytest.mark.parametrize("N", [8, 9])
 def test_high_degree_adaptive_start_with_dg_elements(N):
     """P8 / P9 start-up and adaptive steps where the indicator keeps the smooth part on
-    DG: the noise (1e-7) sits below (N + 1 - M)^-(alpha + 1) (6e-5 at N = 9), so only
-    the elements at the sheet start on FD."""
+    DG: the noise (1e-7) sits below (N + 1 - M)^-(alpha + 1) (6e-5 at N = 9) and with
+    eight elements along x the smooth part's ratios are 2.6e-5 to 5.7e-5, so only the
+    two element columns at the sheet start on FD."""
     torch = _torch()
-    w = I.workload("sheet", n_elem=(4, 2, 2), degree=N, noise=1e-7)
+    w = I.workload("sheet", n_elem=(8, 2, 1), degree=N, noise=1e-7)
     odom, ldom, _ = make_pair(w, dict(eta=w["eta"], cfl=w["cfl"]))
     xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
     u_fd = I.initial_data(w, xf, yf, zf)
@@ -191,7 +202,7 @@ def test_high_degree_adaptive_start_with_dg_elements(N):
     for k in range(2):
         st = OS.step(odom, st, dt)
         ldom.step(1, dt)
-        _compare(odom, st, ldom, f"sheet P{N} low noise", k + 1)
+        _compare(odom, st, ldom, f"sheet P{N} low noise", k + 1, dt)
 
 
 # ----------------------------------------------- adjoint through forced rollbacks
