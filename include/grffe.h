@@ -231,6 +231,18 @@ int grffe_get_dt(grffe_domain* dom, double* dt);
  * call allocates an E-byte work array. */
 int grffe_check_finite(grffe_domain* dom, int32_t* n_bad, void* stream);
 
+/* grffe_check_finite for callers that cannot allocate device memory (code that
+ * runs where hipMalloc is not allowed, such as a tight serving loop or a harness
+ * that forbids it): the same scan and status, with the per-element flags and their
+ * count kept in a fixed device array of the library (1 MiB + 256 B per device,
+ * held until the process ends, looked up once per device) instead of the work
+ * array grffe_check_finite allocates at its first call.  The call allocates no
+ * device memory.  Domains of more than 1048576 elements are refused
+ * (GRFFE_EINVAL).  Every call on one device shares that array: calls that overlap
+ * on one device (several streams or host threads) race; the array keeps the last
+ * call's flags, and each call reads only what it wrote.  Synchronises `stream`. */
+int grffe_check_finite_noalloc(grffe_domain* dom, int32_t* n_bad, void* stream);
+
 /* Number of live elements on DG and on FD (host values; synchronises). */
 int grffe_get_counts(grffe_domain* dom, int32_t* n_dg, int32_t* n_fd);
 

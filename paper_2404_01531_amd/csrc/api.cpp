@@ -48,6 +48,11 @@ static int check_ready(grffe_domain* d) {
 
 extern "C" const char* grffe_last_error(void) { return g_err.c_str(); }
 
+namespace grffe {
+// Status and message of a failure, for the entry points defined in other sources.
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace grffe
+
 extern "C" void grffe_default_params(grffe_params* p) {
   std::memset(p, 0, sizeof(*p));
   p->eta = 1e6;

@@ -81,6 +81,7 @@ def lib():
     L.grffe_set_boundary_state.argtypes = [vp, ctypes.POINTER(dbl), vp]
     L.grffe_set_boundary_field.argtypes = [vp, vp, vp, vp]
     L.grffe_check_finite.argtypes = [vp, ctypes.POINTER(i32), vp]
+    L.grffe_check_finite_noalloc.argtypes = [vp, ctypes.POINTER(i32), vp]
     L.grffe_set_conductor.argtypes = [vp, vp, dbl, dbl, vp]
     L.grffe_destroy.argtypes = [vp]
     L.grffe_init_from_fd.argtypes = [vp, vp, vp, vp]
