@@ -1,18 +1,20 @@
 """Throughput of the GRFFE DG-FD step on one MI355X.
 
-Workload (default): flat-space current sheet, periodic cube [-1,1]^3 with 8^3
-elements of DG degree 5 (6^3 GLL nodes; 11^3 FD subcells when flagged),
-eta = 1e6, CFL 0.25, seeded 1e-3 noise on B_y and E_z, adaptive DG-FD
-control (about a quarter of the elements stay on FD).  One step = one
-IMEX-SSP3(4,3,3) step of the whole domain (three explicit substeps, pointwise
-implicit solves, filter, indicator, DG<->FD switching).
+Workload (the JSON line): the Kerr-Schild black hole, M = 1, a = 0.9, uniform seed
+field B0 = 1 with the ideal E, [-40,40]^3 cut into 16^3 elements of DG degree 5
+(6^3 GLL nodes; 11^3 FD subcells when flagged), the 8 elements meeting r < 1.8
+excised, no-incoming-Poynting outer faces, eta = 1e5, CFL 0.25, adaptive DG-FD
+control from an all-DG start.  One step = one IMEX-SSP3(4,3,3) step of the whole
+domain (three explicit substeps, pointwise implicit solves, filter, indicator,
+DG<->FD switching), FP64; the same in the mixed mode beside it.
 
-Metric: grid-point updates per second per RK substep (a DG node on DG
-elements, an FD cell on FD elements, counted for each of the three substeps).
+Metric: grid-point updates per second per RK substep (a DG node on DG elements, an
+FD cell on FD elements, counted for each of the three substeps).
 
-Prints one JSON line with the throughput, a roofline entry for the dominant
-kernel (timed live with HIP events on its launch stream) and the CPU oracle
-timed on a bounded sample on the host.
+Prints one JSON line with the throughput, the roofline of the dominant kernel (the
+fused curved DG substep, timed live with HIP events on its launch stream), the
+whole step's algorithmic HBM rate, the error against the oracle on sampled elements,
+and the oracle timed on a bounded sample on the host.
 """
 from __future__ import annotations
 
@@ -60,13 +62,13 @@ FD_FLUX_TRAFFIC_SRC = "8627b7c1377cba16"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sheet")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=5)
-    ap.add_argument("--extras", choices=("all", "none"), default="all",
-                    help="also measure the black-hole, batch and adjoint workloads (nested in the JSON line)")
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--extras", choices=("core", "all", "none"), default="core",
+                    help="also measure the batch, sheet, full-length black-hole and adjoint workloads (core), "
+                         "and the paper's accuracy experiments (all); nested in the JSON line")
     ap.add_argument("--extra-steps", type=int, default=30)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (counter calibration)")
@@ -230,9 +232,13 @@ def kerr_schild_domain(precision, n_elem=16):
     return dom, w, exc, (x, y, z)
 
 
-def run_kerr_schild(steps, warmup, precision, n_elem=16):
+def run_kerr_schild(steps, warmup, precision, n_elem=16, families=None):
     """Kerr-Schild black hole (M = 1, a = 0.9, B0 = 1, Wald-like data with the ideal
-    E), [-40,40]^3 with n_elem^3 DG-P5 elements, elements meeting r < 1.8 excised."""
+    E), [-40,40]^3 with n_elem^3 DG-P5 elements, elements meeting r < 1.8 excised,
+    every element starting on DG: `warmup` untimed steps, then `steps` timed steps.
+    The listed kernel families are timed with HIP events attached to their own
+    dispatches on the launch stream, on the launches of one step in every
+    TIMING_PERIOD (family 1, the fused DG substep, is the dominant kernel)."""
     import torch
 
     from paper_2404_01531_amd import grffe
@@ -240,30 +246,115 @@ def run_kerr_schild(steps, warmup, precision, n_elem=16):
     N = w["degree"]
     n3, m3 = (N + 1) ** 3, (2 * N + 1) ** 3
     dt = dom.dt()
-    fam = grffe.KERNEL_FAMILIES["dg_substep"]
+    fams = tuple(families) if families else (grffe.KERNEL_FAMILIES["dg_substep"],)
     dom.step(warmup, dt)
     torch.cuda.synchronize()
     n_dg0, n_fd0 = dom.counts()
-    dom.timing_enable(fam, period=max(1, steps // 6))
+    dom.timing_enable(*fams, period=min(TIMING_PERIOD, max(1, steps // 2)))
     secs = _time_steps(lambda k: dom.step(k, dt), steps, 0)
-    k_ms, k_n = dom.timing_read(fam)
+    kern = {f: dom.timing_read(f) for f in fams}
     dom.timing_enable()
     n_dg1, n_fd1 = dom.counts()
     n_bad = dom.check_finite()
+    state = dom.get_state()
+    dom.close()
     pts = 0.5 * ((n_dg0 + n_dg1) * n3 + (n_fd0 + n_fd1) * m3)
     n_dg = 0.5 * (n_dg0 + n_dg1)
+    fam = grffe.KERNEL_FAMILIES["dg_substep"]
+    k_ms, k_n = kern[fam]
     byt = n_dg * n3 * (sum(DG_BYTES_PER_NODE.values()) / 3.0 + DG_BG_BYTES_PER_NODE)
     avg = (k_ms / 1e3) / max(k_n, 1)
-    return {"workload": f"Kerr-Schild a=0.9 B0=1, [-40,40]^3, {n_elem}^3 elements DG-P5, eta 1e5, CFL 0.25, "
-                        f"{int(exc.sum())} excised", "dtype": "f64" if precision == 0 else "mixed",
-            "value": pts * 3 * steps / secs, "unit": "grid-point updates/s", "steps": steps,
-            "ms_per_step": secs * 1e3 / steps, "dt": dt, "elements_dg_fd": [[int(n_dg0), int(n_fd0)],
-                                                                            [int(n_dg1), int(n_fd1)]],
-            "non_finite_elements": n_bad,
-            "roofline_dg": {"kernel": "k_dg_substep (fused DG substep, curved)", "bound": "hbm",
-                            "achieved": byt / avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": byt / avg / 1e9 / HBM_PEAK_GBS, "mean_launch_us": avg * 1e6,
-                            "launches": int(k_n), "bytes_per_launch": byt}}
+    # the whole step's algorithmic bytes: every DG node and FD cell moves the register
+    # scheme's mean 288 B and reads its 208 B of background in each of three substeps
+    step_bytes = 3 * pts * (sum(DG_BYTES_PER_NODE.values()) / 3.0 + DG_BG_BYTES_PER_NODE)
+    ms = secs * 1e3 / steps
+    names = {v: k for k, v in grffe.KERNEL_FAMILIES.items()}
+    rec = {"workload": f"Kerr-Schild black hole M=1 a=0.9, uniform seed field B0=1 with the ideal E, [-40,40]^3, "
+                       f"{n_elem}^3 elements DG-P5 (FD 11^3 when flagged), {int(exc.sum())} elements excised "
+                       f"(r < 1.8), eta 1e5, CFL 0.25, adaptive DG-FD, start on DG",
+           "dtype": "f64" if precision == 0 else "mixed",
+           "value": pts * 3 * steps / secs, "unit": "grid-point updates/s", "steps": steps,
+           "ms_per_step": ms, "dt": dt, "elements": int(dom.E), "live_elements": int(dom.E - exc.sum()),
+           "elements_dg_fd": [[int(n_dg0), int(n_fd0)], [int(n_dg1), int(n_fd1)]],
+           "points_per_substep": pts, "non_finite_elements": n_bad,
+           "roofline": {"kernel": "k_dg_substep (fused DG substep, curved)", "bound": "hbm",
+                        "achieved": byt / avg / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": byt / avg / 1e9 / HBM_PEAK_GBS, "traffic": None, "mean_launch_us": avg * 1e6,
+                        "launches": int(k_n), "bytes_per_launch": byt},
+           "step_hbm": {"algorithmic_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / (ms / 1e3) / 1e9,
+                        "frac": step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+           "kernels_mean_us": {names[f]: {"mean_us": kern[f][0] * 1e3 / max(kern[f][1], 1),
+                                          "launches": int(kern[f][1])} for f in fams}}
+    return rec, state
+
+
+def run_kerr_schild_full(precision=0, n_elem=16, steps=1000, segment=100):
+    """The Kerr-Schild configuration over its full length (1000 steps, t = 61.5M) from
+    the initial data: the rate of every 100-step segment and of the whole run, with the
+    FD element count at each segment's end (the elements by the box's outer faces
+    switch to FD as the transient meets the no-incoming-Poynting faces)."""
+    import torch
+    dom, w, exc, _ = kerr_schild_domain(precision, n_elem)
+    N = w["degree"]
+    n3, m3 = (N + 1) ** 3, (2 * N + 1) ** 3
+    dt = dom.dt()
+    rows, tot_pts, tot_secs = [], 0.0, 0.0
+    a0, f0 = dom.counts()
+    for s in range(0, steps, segment):
+        secs = _time_steps(lambda k: dom.step(k, dt), segment, 0)
+        a1, f1 = dom.counts()
+        pts = 0.5 * ((a0 + a1) * n3 + (f0 + f1) * m3) * 3 * segment
+        rows.append({"steps": [s + 1, s + segment], "fd_elements_end": int(f1), "ms_per_step": secs * 1e3 / segment,
+                     "value": pts / secs})
+        tot_pts += pts
+        tot_secs += secs
+        a0, f0 = a1, f1
+    n_bad = dom.check_finite()
+    dom.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"the Kerr-Schild {n_elem}^3 configuration over its full {steps} steps (t = {steps * dt:.1f}M)",
+            "dtype": "f64" if precision == 0 else "mixed", "value": tot_pts / tot_secs,
+            "unit": "grid-point updates/s", "ms_per_step": tot_secs * 1e3 / steps, "segments": rows,
+            "non_finite_elements": n_bad}
+
+
+GOLDEN_KS = os.path.join(ROOT, "tests", "golden", "kerr_schild_16_p5_10steps.npz")
+
+
+def kerr_schild_parity(precision, floor):
+    """Error of the Kerr-Schild 16^3 run against the oracle: the library's first 10 steps
+    from the initial data against the stored oracle run of the same configuration
+    (tests/golden/kerr_schild_16_p5_10steps.npz, written by make_kerr_schild_16.py
+    beside it from the oracle and the seeded inputs), on its sampled elements.  Per
+    variable group (E~, B~, psi~, phi~, q~): the largest and the RMS difference, each
+    relative to the group's own scale floored at `floor` times the whole state's."""
+    import numpy as np
+    ref = np.load(GOLDEN_KS)
+    dom, w, exc, _ = kerr_schild_domain(precision, 16)
+    N = w["degree"]
+    dt = dom.dt()
+    mism = 0
+    for k in range(int(ref["steps"])):
+        dom.step(1, dt)
+        _, _, rep = dom.get_state()
+        mism = max(mism, int((rep.cpu().numpy() != ref["rep"][k]).sum()))
+    dg, fd, rep = (x.cpu().numpy() for x in dom.get_state())
+    dom.close()
+    E = dg.shape[1]
+    got = np.concatenate([dg[:, ref["dg_elements"]].reshape(9, -1), fd[:, ref["fd_elements"]].reshape(9, -1)], axis=1)
+    want = np.concatenate([ref["dg_values"].reshape(9, -1), ref["fd_values"].reshape(9, -1)], axis=1)
+    groups = ((0, 3), (3, 6), (6, 7), (7, 8), (8, 9))
+    names = ["E", "B", "psi", "phi", "q"]
+    amax, rms_all = np.abs(want).max(), np.sqrt(np.mean(want ** 2))
+    mx, l2 = {}, {}
+    for nm, (a, b) in zip(names, groups):
+        d = got[a:b] - want[a:b]
+        mx[nm] = float(np.abs(d).max() / max(np.abs(want[a:b]).max(), floor * amax))
+        l2[nm] = float(np.sqrt(np.mean(d ** 2)) / max(np.sqrt(np.mean(want[a:b] ** 2)), floor * rms_all))
+    return {"reference": "stored oracle run (tests/golden/kerr_schild_16_p5_10steps.npz)",
+            "steps": int(ref["steps"]), "dt": float(ref["dt"]),
+            "sampled_elements": {"dg": int(ref["dg_elements"].size), "fd": int(ref["fd_elements"].size)},
+            "representation_mismatches": mism, "group_scale_floor": floor, "max": mx, "l2": l2}
 
 
 def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, samples=8):
@@ -731,6 +822,29 @@ def run_adjoint_frozen(steps=40, every=20):
     return out
 
 
+def sheet_line(steps, warmup):
+    """The flat current sheet (8^3 DG-P5 elements, about a quarter on FD): FP64 and mixed
+    rates with the FD face-flux kernel's FP64-ALU roofline and the flat DG substep's
+    HBM roofline."""
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    w = I.workload("sheet")
+    N = w["degree"]
+    fam_fd, fam_dg = grffe.KERNEL_FAMILIES["fd_flux"], grffe.KERNEL_FAMILIES["dg_substep"]
+    out, states = {}, {}
+    for prec, name in ((0, "fp64"), (1, "mixed")):
+        rec, st = run_workload(w, prec, steps, warmup, (fam_fd, fam_dg))
+        states[name] = st
+        out[name] = {"value": rec["value"], "ms_per_step": rec["secs"] * 1e3 / steps,
+                     "fd_elements": [int(x) for x in rec["n_fd"]], "points_per_substep": rec["pts"],
+                     "roofline_fd_flux": roofline_fd(rec, N, counted=prec == 0), "roofline_dg": roofline_dg(rec, N)}
+    out["mixed"]["error_vs_fp64_run"] = state_diff(states["mixed"], states["fp64"])
+    out["workload"] = ("flat current sheet, periodic [-1,1]^3, 8^3 elements DG-P5 / FD 11^3, eta 1e6, CFL 0.25, "
+                       "adaptive DG-FD, seed 1002")
+    out["steps"] = steps
+    return out
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -746,28 +860,25 @@ def main():
     import torch
 
     from paper_2404_01531_amd import grffe
-    from paper_2404_01531_amd import inputs as I
 
     torch.cuda.set_device(0)
-    w = I.workload(args.workload)
-    if w.get("curved"):
-        raise SystemExit("the benchmark workload is flat; curved workloads are parity cases")
-    N = w["degree"]
-    fam_fd, fam_dg = grffe.KERNEL_FAMILIES["fd_flux"], grffe.KERNEL_FAMILIES["dg_substep"]
-    res = {}
-    states = {}
+    fams = tuple(sorted(grffe.KERNEL_FAMILIES.values()))
+    res, states = {}, {}
     for prec, name in ((0, "fp64"), (1, "mixed")):
-        rec, st = run_workload(w, prec, args.steps, args.warmup, (fam_fd, fam_dg))
-        res[name] = rec
-        states[name] = st
-        k_ms, k_n = rec["kern"][fam_fd]
-        print(f"# {name}: {args.steps} steps in {rec['secs']:.4f} s, {rec['n_dg']} DG / {rec['n_fd']} FD elements; "
-              f"fd_flux {k_n} launches, mean {k_ms / max(k_n, 1) * 1e3:.2f} us", file=sys.stderr, flush=True)
-
+        rec, st = run_kerr_schild(args.steps, args.warmup, prec, families=fams)
+        res[name], states[name] = rec, st
+        print(f"# kerr-schild 16^3 {name}: {args.steps} steps, {rec['ms_per_step']:.4f} ms/step, "
+              f"{rec['elements_dg_fd']} DG/FD elements; dg_substep mean {rec['roofline']['mean_launch_us']:.1f} us "
+              f"over {rec['roofline']['launches']} launches", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
     f64, mix = res["fp64"], res["mixed"]
+    f64["roofline"]["traffic"] = dg_substep_traffic(f64)
+    err64 = kerr_schild_parity(0, 1.0)
+    errmx = kerr_schild_parity(1, 1e-3)
+    torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_sample_steps)
+        cpu = cpu_baseline(args.cpu_sample_steps)
     out = {
         "metric": "grid-point updates/s per RK substep, FP64 vs mixed, at stated L2 error",
         "value": f64["value"],
@@ -775,84 +886,133 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": f64["secs"] * 1e3 / args.steps,
+        "ms_per_step": f64["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "flat current sheet, periodic [-1,1]^3, 8^3 elements DG-P5 / FD 11^3, "
-                               "eta 1e6, CFL 0.25, adaptive DG-FD, seed 1002",
-                   "elements": int(f64["E"]), "fd_elements": [int(x) for x in f64["n_fd"]],
-                   "points_per_substep": f64["pts"], "dt": f64["dt"]},
-        "roofline": roofline_fd(f64, N),
-        "roofline_dg": roofline_dg(f64, N),
-        "mixed": {"value": mix["value"], "ms_per_step": mix["secs"] * 1e3 / args.steps,
-                  "dtype": "f64 state, f32 fluxes and DG contractions",
-                  "fd_elements": [int(x) for x in mix["n_fd"]],
-                  "error_vs_fp64_run": state_diff(states["mixed"], states["fp64"]),
-                  "roofline": roofline_fd(mix, N, counted=False), "roofline_dg": roofline_dg(mix, N)},
+        "config": {"workload": f64["workload"], "elements": f64["elements"], "live_elements": f64["live_elements"],
+                   "elements_dg_fd": f64["elements_dg_fd"], "points_per_substep": f64["points_per_substep"],
+                   "dt": f64["dt"]},
+        "roofline": f64["roofline"],
+        "step_hbm": f64["step_hbm"],
+        "kernels_mean_us": f64["kernels_mean_us"],
+        "error_vs_oracle": err64,
+        "mixed": {"value": mix["value"], "ms_per_step": mix["ms_per_step"],
+                  "dtype": "f64 state, f32 fluxes and DG contractions", "elements_dg_fd": mix["elements_dg_fd"],
+                  "roofline": mix["roofline"], "step_hbm": mix["step_hbm"], "error_vs_oracle": errmx,
+                  "error_vs_fp64_run": state_diff(states["mixed"], states["fp64"])},
         "cpu_baseline": cpu,
     }
-    if args.extras == "all":
+    del states
+    torch.cuda.empty_cache()
+    if args.extras != "none":
         ex = {}
-        for name, fn in (("kerr_schild_16^3_fp64", lambda: run_kerr_schild(args.extra_steps, 2, 0)),
-                         ("kerr_schild_16^3_mixed", lambda: run_kerr_schild(args.extra_steps, 2, 1)),
-                         ("batch_64_fp64", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0)),
-                         ("batch_64_mixed", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 1)),
-                         ("sheet_element_sweep_16^3_32^3", lambda: run_sheet_sweep(args.extra_steps, 2)),
-                         ("accuracy_smooth_fast_wave_4^3", lambda: run_accuracy_smooth_wave(20)),
-                         ("exact_wald_convergence", lambda: run_exact_wald()),
-                         ("forced_fd_fraction_sheet_8^3", lambda: run_forced_fractions_sheet(args.extra_steps, 2)),
-                         ("forced_fd_fraction_alfven_8x32x8",
-                          lambda: run_forced_fractions_alfven(args.extra_steps, 2)),
-                         ("adjoint_poynting_kerr_schild_8^3", lambda: run_adjoint()),
-                         ("adjoint_sheet_8^3_frozen_partition", lambda: run_adjoint_frozen())):
+        jobs = [("batch_64_fp64", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0)),
+                ("batch_64_mixed", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 1)),
+                ("sheet_8^3", lambda: sheet_line(args.extra_steps, 2)),
+                ("kerr_schild_16^3_full_run", lambda: run_kerr_schild_full()),
+                ("sheet_element_sweep_16^3_32^3", lambda: run_sheet_sweep(args.extra_steps, 2)),
+                ("forced_fd_fraction_sheet_8^3", lambda: run_forced_fractions_sheet(args.extra_steps, 2)),
+                ("adjoint_poynting_kerr_schild_8^3", lambda: run_adjoint()),
+                ("adjoint_sheet_8^3_frozen_partition", lambda: run_adjoint_frozen())]
+        if args.extras == "all":
+            jobs += [("accuracy_smooth_fast_wave_4^3", lambda: run_accuracy_smooth_wave(20)),
+                     ("exact_wald_convergence", lambda: run_exact_wald()),
+                     ("forced_fd_fraction_alfven_8x32x8", lambda: run_forced_fractions_alfven(args.extra_steps, 2))]
+        for name, fn in jobs:
             print(f"# extra workload {name}", file=sys.stderr, flush=True)
             ex[name] = fn()
             print(f"#   {json.dumps(ex[name])[:300]}", file=sys.stderr, flush=True)
-            import torch
             torch.cuda.empty_cache()
         out["extras"] = ex
     print(json.dumps(out))
 
 
-def kernel_source_hash():
-    """SHA-256 (first 16 hex digits) of the FD kernel source and the headers it includes."""
+# HBM bytes per DG node per launch of the curved k_dg_substep (FP64) on the Kerr-Schild
+# 16^3 workload: rocprofv3 FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, averaged
+# over the three substeps' launches), each scaled by what the same counter reads for a
+# plain 512 MiB device copy (fetch x 2.0, write x 1.0).  Valid for the kernel source
+# whose hash is DG_TRAFFIC_SRC; reported as null for any other source.
+DG_TRAFFIC_PER_NODE = None
+DG_TRAFFIC_SRC = None
+
+
+def dg_substep_traffic(rec):
+    """Counted HBM bytes per launch of the curved DG substep for this run's DG node
+    count, or None when the counters were taken on other kernel sources."""
+    if DG_TRAFFIC_PER_NODE is None or kernel_source_hash("kernels_dg.hip") != DG_TRAFFIC_SRC:
+        return None
+    n_dg = 0.5 * sum(x[0] for x in rec["elements_dg_fd"])
+    return DG_TRAFFIC_PER_NODE * n_dg * 216
+
+
+def kernel_source_hash(main="kernels_fd.hip"):
+    """SHA-256 (first 16 hex digits) of a kernel source and the headers it includes."""
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(ROOT, "paper_2404_01531_amd", "csrc")
-    for f in ("kernels_fd.hip", "fd_common.h", "common.h", "physics.h", "grffe_internal.h"):
+    for f in (main, "fd_common.h", "common.h", "physics.h", "grffe_internal.h"):
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(w, steps):
-    """The oracle (numpy FP64, one thread) on the same workload for `steps` steps."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
+
+def cpu_baseline(steps):
+    """The oracle (numpy FP64) on a bounded sample of the benchmark's Kerr-Schild
+    workload: the octant [-40, 0]^3 of the same grid (8^3 of its 16^3 elements, h = 5,
+    the same background, data and parameters; the element at the hole excised, the cut
+    faces outer faces), `steps` steps from the initial data, on every host core the
+    process may use (numpy's BLAS threads; the elementwise work is single-threaded)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import operators as ops
     from oracle import step as OS
     from oracle.domain import Domain as ODomain
     from paper_2404_01531_amd import inputs as I
 
+    w = I.workload("kerr_schild", n_elem=(8, 8, 8), lower=(-40.0,) * 3, upper=(0.0,) * 3)
     N = w["degree"]
-    with threadpool_limits(limits=1):
-        odom = ODomain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=dict(eta=w["eta"], cfl=w["cfl"]))
-        xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], N)
-        st = OS.initial_state(odom, I.initial_data(w, xf, yf, zf))
-        dt = odom.dt()
-        t0 = time.perf_counter()
-        pts = 0.0
-        for _ in range(steps):
-            nfd = int((st.rep == 1).sum())
-            pts += 3 * ((odom.E - nfd) * (N + 1) ** 3 + nfd * (2 * N + 1) ** 3)
-            st = OS.step(odom, st, dt)
-        secs = time.perf_counter() - t0
-    return {"value": pts / secs, "unit": "grid-point updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} step(s) of the same 8^3-element sheet workload from its initial state, "
-                      f"numpy FP64 on one host core, {secs:.1f} s"}
+    x, y, z = I.points(w["n_elem"], w["lower"], w["upper"], ops.gll(N)[0])
+    with np.errstate(all="ignore"):
+        bg = I.background(w, x, y, z)
+        u = I.initial_data(w, x, y, z)
+    exc = I.excision_mask(w).astype(bool)
+    bg[:, exc] = 0.0
+    bg[0, exc] = 1.0
+    bg[4, exc] = bg[7, exc] = bg[9, exc] = 1.0
+    u[:, exc] = 0.0
+    odom = ODomain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], excised=exc, bg=bg,
+                   params=dict(eta=w["eta"], cfl=w["cfl"]))
+    st = OS.State(u, np.zeros((9, odom.E, odom.m, odom.m, odom.m)), np.zeros(odom.E, np.int64))
+    dt = odom.dt()
+    t0 = time.perf_counter()
+    pts = 0.0
+    for _ in range(steps):
+        nfd = int((st.rep[odom.active] == 1).sum())
+        pts += 3 * ((int(odom.active.sum()) - nfd) * (N + 1) ** 3 + nfd * (2 * N + 1) ** 3)
+        st = OS.step(odom, st, dt)
+    secs = time.perf_counter() - t0
+    threads = max([int(t.get("num_threads", 1)) for t in threadpool_info()] or [1])
+    return {"value": pts / secs, "unit": "grid-point updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus": len(os.sched_getaffinity(0)),
+            "sample": f"{steps} step(s) of the octant [-40,0]^3 of the Kerr-Schild 16^3 grid (8^3 of its elements, "
+                      f"same element size, background, data and parameters) from the initial data, numpy FP64 with "
+                      f"{threads} BLAS thread(s), {secs:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -151,3 +151,34 @@ def q_floor(odom, dt, nsteps, emax):
     N = odom.N
     lam = sum(4.0 * (2 * N + 1) / h for h in odom.h)
     return nsteps * dt * lam * 8.0 * U_ROUND * odom.params["eta"] * emax
+
+
+def kerr_schild_config(n_elem=16):
+    """The Kerr-Schild black-hole configuration (M = 1, a = 0.9, B0 = 1, Wald-like field
+    with the ideal E, [-40, 40]^3, n_elem^3 DG-P5 elements, elements meeting r < 1.8
+    excised) sampled at the oracle's GLL nodes: (workload, bg (26, E, n, n, n), u (9,
+    E, n, n, n), excision mask).  The excised elements carry a unit metric and zero
+    fields (never read)."""
+    w = I.workload("kerr_schild", n_elem=(n_elem,) * 3)
+    x, y, z = node_coords(w)
+    with np.errstate(all="ignore"):
+        bg = I.background(w, x, y, z)
+        u = I.initial_data(w, x, y, z)
+    exc = I.excision_mask(w).astype(bool)
+    bg[:, exc] = 0.0
+    bg[0, exc] = 1.0
+    bg[4, exc] = bg[7, exc] = bg[9, exc] = 1.0
+    u[:, exc] = 0.0
+    return w, bg, u, exc
+
+
+def stiff_tolerance(odom, dt, nsteps, emax, overall, rtol=1e-12):
+    """Per-group bound (E~, B~, psi~, phi~, q~) after n steps at a stiff eta, relative to
+    the field scale `overall`: rtol for every group, plus the conditioning floor of q~
+    (q_floor) on q~, plus what that q~ difference feeds into E~ (the drift current
+    q~ E x B / B^2, |E x B| / B^2 <= 1 where E < B) and psi~ (its source alpha q~)
+    within each step: dt times the q~ floor reached so far, summed over the steps,
+    dt q_floor(1 step) n (n + 1) / 2."""
+    qf = q_floor(odom, dt, nsteps, emax)
+    ef = dt * q_floor(odom, dt, 1, emax) * nsteps * (nsteps + 1) / 2.0
+    return np.array([rtol + ef / overall, rtol, rtol + ef / overall, rtol, rtol + qf / overall])

@@ -21,7 +21,7 @@ from oracle import tci as OT
 from oracle.domain import DG, FD
 from paper_2404_01531_amd import inputs as I
 
-from helpers import from_dev, group_err, make_pair, node_coords, q_floor, rel_err, to_dev
+from helpers import from_dev, group_err, make_pair, node_coords, stiff_tolerance, rel_err, to_dev
 from helpers import state_arrays as _state_arrays
 
 pytestmark = pytest.mark.gpu
@@ -52,7 +52,7 @@ def _mask(E, rolls):
 def _compare(odom, st, ldom, label, k, dt):
     """Representation identical; per variable group max |gpu - oracle| <= 1e-12 of the
     field scale, the q~ group with the stiff-current conditioning floor added
-    (helpers.q_floor, k steps)."""
+    (helpers.stiff_tolerance, k steps)."""
     gdg, gfd, grep = ldom.get_state()
     grep = grep.cpu().numpy()
     assert np.array_equal(grep, st.rep), f"{label}: representation differs after step {k}"
@@ -65,9 +65,7 @@ def _compare(odom, st, ldom, label, k, dt):
         el = np.nonzero(act & (st.rep == r))[0]
         if el.size:
             e = group_err(G[:, el], R[:, el])
-            overall = np.abs(R[:, el]).max()
-            tol = np.full(5, RTOL)
-            tol[4] += q_floor(odom, dt, k, emax) / overall
+            tol = stiff_tolerance(odom, dt, k, emax, np.abs(R[:, el]).max(), RTOL)
             worst = max(worst, float(e.max()))
             _say(f"  step {k} rep {r}: group err {np.array2string(e, precision=2)} (q~ bound {tol[4]:.1e})")
             assert np.all(e <= tol), (label, k, r, e.tolist())
