@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--only", choices=("sheet", "batch"), default=None,
+                    help="run one secondary workload alone and print its record (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--extras", choices=("core", "all", "none"), default="core",
@@ -862,6 +864,12 @@ def main():
     from paper_2404_01531_amd import grffe
 
     torch.cuda.set_device(0)
+    if args.only == "sheet":
+        print(json.dumps(sheet_line(args.steps, args.warmup)))
+        return
+    if args.only == "batch":
+        print(json.dumps(run_batch(args.steps, args.warmup, 0)))
+        return
     fams = tuple(sorted(grffe.KERNEL_FAMILIES.values()))
     res, states = {}, {}
     for prec, name in ((0, "fp64"), (1, "mixed")):

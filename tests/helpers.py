@@ -174,11 +174,17 @@ def kerr_schild_config(n_elem=16):
 
 def stiff_tolerance(odom, dt, nsteps, emax, overall, rtol=1e-12):
     """Per-group bound (E~, B~, psi~, phi~, q~) after n steps at a stiff eta, relative to
-    the field scale `overall`: rtol for every group, plus the conditioning floor of q~
-    (q_floor) on q~, plus what that q~ difference feeds into E~ (the drift current
-    q~ E x B / B^2, |E x B| / B^2 <= 1 where E < B) and psi~ (its source alpha q~)
-    within each step: dt times the q~ floor reached so far, summed over the steps,
-    dt q_floor(1 step) n (n + 1) / 2."""
-    qf = q_floor(odom, dt, nsteps, emax)
-    ef = dt * q_floor(odom, dt, 1, emax) * nsteps * (nsteps + 1) / 2.0
-    return np.array([rtol + ef / overall, rtol, rtol + ef / overall, rtol, rtol + qf / overall])
+    the field scale `overall`: rtol for every group plus the conditioning floor of the
+    stiff current carried through the equations.  With F1 = q_floor(1 step), the q~
+    difference one step can make, q~ differs by up to F_q(n) = n F1 after n steps.
+    Through the drift current q~ E x B / B^2 (|E x B| / B^2 <= 1 where E < B) each step
+    injects at most dt F_q(k) into E~, so F_E(n) = dt F1 n (n + 1) / 2; the scheme is
+    stable (a perturbation of the fields does not grow over a step: CFL below the
+    stability limit, Rusanov and the filter dissipate), so what reaches B~ and phi~
+    through the curl and the cleaning stays below F_E(n) as well, and psi~, which also
+    takes alpha q~ directly, below 2 F_E(n)."""
+    n = nsteps
+    f1 = q_floor(odom, dt, 1, emax)
+    fq = n * f1
+    fe = dt * f1 * n * (n + 1) / 2.0
+    return rtol + np.array([fe, fe, 2.0 * fe, fe, fq]) / overall
