@@ -88,6 +88,7 @@ KArgs make_args(grffe_domain* d) {
   a.bfield_fd = d->bfield_fd;
   a.live = d->live;
   a.bg_dg = d->bg_dg;
+  a.bg_dg32 = d->bg_dg32;
   a.bg_fd = d->bg_fd;
   a.bg_face = d->bg_face;
   a.ops = d->ops;
@@ -331,6 +332,7 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
     ALLOC(bg_dg, sizeof(double) * NBG * E * nn);
     ALLOC(bg_fd, sizeof(double) * NBG * E * mm);
     ALLOC(bg_face, sizeof(double) * 3 * NBGF * E * nf);
+    if (p->precision == GRFFE_PRECISION_MIXED) ALLOC(bg_dg32, sizeof(float) * NBG * E * nn);
     if ((rc = dalloc(d, &ptr, sizeof(double) * (m + 1) * n))) {
       grffe_destroy(d);
       return rc;
@@ -370,6 +372,7 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
       CHK(hipMemcpy2DAsync(d->bg_dg + (size_t)pt.off * nn, sizeof(double) * E * nn, bgs[k],
                            sizeof(double) * pt.E * nn, sizeof(double) * pt.E * nn, NBG, hipMemcpyDeviceToDevice, st));
     }
+    if (d->bg_dg32) launch_to_float(d->bg_dg, d->bg_dg32, (size_t)NBG * E * nn, st);
     CHK(hipMemcpyAsync(qdev, d->ops_h.Q.data(), sizeof(double) * (m + 1) * n, hipMemcpyHostToDevice, st));
     KArgs a = make_args(d);
     launch_bg_derive_q(a, d->N, d->bg_fd, d->bg_face, qdev, st);

@@ -54,29 +54,62 @@ __device__ inline void block_sum2(double& a, double& b, double* sred) {
   __syncthreads();
 }
 
-// Metric (10 leading fields) of point `p` of element `e` from a [F][E][P] array.
-template <bool CURVED>
-__device__ inline void load_metric(const double* bg, int E, int P, int e, int p, Metric& M) {
+// Metric (10 leading fields) of point `p` of element `e` from a [F][E][P] array (FP64, or
+// its FP32 copy; the metric is formed in FP64 either way).
+template <bool CURVED, typename TB>
+__device__ inline void load_metric(const TB* bg, int E, int P, int e, int p, Metric& M) {
   if (!CURVED) {
     metric_flat(M);
     return;
   }
   double f[10];
 #pragma unroll
-  for (int k = 0; k < 10; ++k) f[k] = bg[((size_t)k * E + e) * P + p];
+  for (int k = 0; k < 10; ++k) f[k] = (double)bg[((size_t)k * E + e) * P + p];
   metric_from10(f, M);
 }
 
-template <bool CURVED>
-__device__ inline void load_deriv(const double* bg, int E, int P, int e, int p, MetricDeriv& Dv) {
+template <bool CURVED, typename TB>
+__device__ inline void load_deriv(const TB* bg, int E, int P, int e, int p, MetricDeriv& Dv) {
   if (!CURVED) return;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) Dv.da[k] = bg[((size_t)(10 + k) * E + e) * P + p];
+  for (int k = 0; k < 3; ++k) Dv.da[k] = (double)bg[((size_t)(10 + k) * E + e) * P + p];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Dv.db[k] = bg[((size_t)(13 + k) * E + e) * P + p];
-  Dv.K = bg[((size_t)22 * E + e) * P + p];
+  for (int k = 0; k < 9; ++k) Dv.db[k] = (double)bg[((size_t)(13 + k) * E + e) * P + p];
+  Dv.K = (double)bg[((size_t)22 * E + e) * P + p];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) Dv.Gam[k] = bg[((size_t)(23 + k) * E + e) * P + p];
+  for (int k = 0; k < 3; ++k) Dv.Gam[k] = (double)bg[((size_t)(23 + k) * E + e) * P + p];
+}
+
+// The background at DG node p of element e for the kernels that work on DG nodes:
+// from the FP32 copy when the domain keeps one (mixed precision on a curved
+// background: every DG-node kernel then sees the same rounded metric, so that the
+// stiff current, which multiplies the metric's rounding of E.B by eta, is consistent
+// between them), else from the FP64 array.
+template <bool CURVED>
+__device__ inline void load_metric_dg(const KArgs& a, int nn, int e, int p, Metric& M) {
+  if (CURVED && a.bg_dg32) load_metric<CURVED>(a.bg_dg32, a.E, nn, e, p, M);
+  else load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
+}
+
+template <bool CURVED>
+__device__ inline void load_deriv_dg(const KArgs& a, int nn, int e, int p, MetricDeriv& Dv) {
+  if (CURVED && a.bg_dg32) load_deriv<CURVED>(a.bg_dg32, a.E, nn, e, p, Dv);
+  else load_deriv<CURVED>(a.bg_dg, a.E, nn, e, p, Dv);
+}
+
+// The same for a kernel compiled for one arithmetic R of the flux evaluation: the
+// FP64 instantiations (which run only in the FP64 mode, where no FP32 copy exists)
+// read the FP64 array without the run-time choice.
+template <bool CURVED, typename R>
+__device__ inline void load_metric_dg_r(const KArgs& a, int nn, int e, int p, Metric& M) {
+  if (sizeof(R) == sizeof(double)) load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
+  else load_metric_dg<CURVED>(a, nn, e, p, M);
+}
+
+template <bool CURVED, typename R>
+__device__ inline void load_deriv_dg_r(const KArgs& a, int nn, int e, int p, MetricDeriv& Dv) {
+  if (sizeof(R) == sizeof(double)) load_deriv<CURVED>(a.bg_dg, a.E, nn, e, p, Dv);
+  else load_deriv_dg<CURVED>(a, nn, e, p, Dv);
 }
 
 __device__ inline void load9(const double* base, int E, int P, int e, int p, double* U) {

@@ -68,6 +68,7 @@ struct KArgs {
   const double* bfield_fd; // [9][E][6][3][m^2] per-ghost-cell exterior states, or null
   const uint8_t* live;     // [E]
   const double* bg_dg;     // [26][E][n^3] or null
+  const float* bg_dg32;    // the same rounded to FP32 (mixed precision on a curved background), or null
   const double* bg_fd;     // [26][E][m^3] or null
   const double* bg_face;   // [3][10][E][(m+1) m^2] or null
   const DevOps* ops;
@@ -150,6 +151,7 @@ struct grffe_domain {
   double* edt = nullptr;  // [E]
   std::vector<double> eh_h, edt_h;
   double* bg_dg = nullptr;
+  float* bg_dg32 = nullptr;  // FP32 copy of bg_dg read by the mixed-precision DG substep
   double* bg_fd = nullptr;
   double* bg_face = nullptr;
   grffe::DevOps* ops = nullptr;
@@ -205,6 +207,7 @@ LaunchEvents& armed_launch_events();
 void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_dg_slab(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_dg_prestage(const KArgs& a, int N, bool curved, hipStream_t s);
+void launch_to_float(const double* in, float* out, size_t count, hipStream_t s);
 // launchers (kernels_fd.hip)
 void launch_fd_stage(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_fd_trace(const KArgs& a, int N, hipStream_t s);

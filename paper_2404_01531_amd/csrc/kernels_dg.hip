@@ -121,7 +121,7 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
     sop[n * n + q] = a.ops->L[q];
   }
   Metric M;
-  load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
+  load_metric_dg_r<CURVED, R>(a, nn, e, p, M);
   double X[NV], Jd[3], Je[3], dU[NV];
   stage_input<MODE, true>(a.dg, a.E, nn, e, p, M, a, X);
   __syncthreads();
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
   current(X, M, a.eta, Jd, Je);
   {
     MetricDeriv Dv;
-    load_deriv<CURVED>(a.bg_dg, a.E, nn, e, p, Dv);
+    load_deriv_dg_r<CURVED, R>(a, nn, e, p, Dv);
     source_explicit<CURVED>(X, M, Dv, Jd, dU);
   }
   // fluxes, derivative and lift in R (FP64, or FP32 in the mixed-precision mode),
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_dg_prestage(KArgs a) {
   const int e = gid / nn, p = gid % nn;
   if (e >= a.E || !a.live[e] || a.rep[e] != 0) return;
   Metric M;
-  load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
+  load_metric_dg<CURVED>(a, nn, e, p, M);
   double Un[NV], U2[NV], S1[NV], S2[NV];
   load9(a.dg.Un, a.E, nn, e, p, Un);
   const double dt = dt_of(a, e);
@@ -300,20 +300,15 @@ __global__ __launch_bounds__(256) void k_dg_prestage(KArgs a) {
 
 // P-projection (3 subcell layers next to each face) of the DG stage input of
 // elements whose neighbour across that face is on FD or has just been flagged.
-// The twelve transported components (U, J~) are projected together, one face at
-// a time, in three separable stages.
+// Work items: (listed element o, face f of o), the list holding the elements on FD
+// at the substep start and those flagged in it: the DG neighbour e across f projects
+// its face towards o.  Every (e, face) pair is one item, so no two items write the
+// same slab.  The twelve transported components (U, J~) are projected together in
+// three separable stages.
 template <int N, bool CURVED, int MODE>
 __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, TPB = Dm::tpb;
-  const int e = blockIdx.x;
-  if (!a.live[e] || a.rep0[e] != 0) return;
-  int need = 0;
-  for (int f = 0; f < 6; ++f) {
-    const int o = a.nbr[e * 6 + f];
-    if (o >= 0 && (a.rep0[o] == 1 || a.troubled[o])) need |= 1 << f;
-  }
-  if (!need) return;
   // the components are projected in chunks of CH so that the tiles fit in LDS at high degree
   constexpr int CH = (NW * (nn + 3 * n * n + 3 * m * n) * 8 <= 150 * 1024) ? NW : NW / 2;
   __shared__ double sW[NW * nn];
@@ -322,20 +317,25 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
   __shared__ double sP[m * n];
   const int t = threadIdx.x;
   for (int q = t; q < m * n; q += TPB) sP[q] = a.ops->P[q];
-  if (t < nn) {
-    Metric M;
-    load_metric<CURVED>(a.bg_dg, a.E, nn, e, t, M);
-    double X[NV];
-    stage_input<MODE, true>(a.dg, a.E, nn, e, t, M, a, X);
-    double J[3];
-    current_total(X, M, a.eta, J);
-    for (int v = 0; v < NV; ++v) sW[v * nn + t] = X[v];
-    for (int c = 0; c < 3; ++c) sW[(9 + c) * nn + t] = J[c];
-  }
-  __syncthreads();
   const int str[3] = {1, n, n * n};
-  for (int f = 0; f < 6; ++f) {
-    if (!(need & (1 << f))) continue;
+  const int items = a.fd_count[a.sub] * 6;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int o = a.fd_list[item / 6], fo = item % 6;
+    const int e = a.nbr[o * 6 + fo];
+    if (e < 0 || !a.live[e] || a.rep0[e] != 0) continue;  // the same for every thread of the block
+    const int f = 2 * (fo >> 1) + 1 - (fo & 1);          // e's face towards o
+    __syncthreads();  // the previous item's tiles are no longer read
+    if (t < nn) {
+      Metric M;
+      load_metric_dg<CURVED>(a, nn, e, t, M);
+      double X[NV];
+      stage_input<MODE, true>(a.dg, a.E, nn, e, t, M, a, X);
+      double J[3];
+      current_total(X, M, a.eta, J);
+      for (int v = 0; v < NV; ++v) sW[v * nn + t] = X[v];
+      for (int c = 0; c < 3; ++c) sW[(9 + c) * nn + t] = J[c];
+    }
+    __syncthreads();
     const int d = f >> 1, s = f & 1;
     // axes: normal d, tangential t1 < t2
     const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
@@ -392,13 +392,28 @@ static void launch_dg_substep_t(const KArgs& a, int mode, hipStream_t s) {
 
 template <int N, bool CURVED>
 static void launch_dg_slab_t(const KArgs& a, int mode, hipStream_t s) {
-  dim3 grid(a.E), block(Dims<N>::tpb);
+  // persistent grid over the (listed element, face) items: enough workgroups to fill
+  // the chip, never more than the largest possible number of items
+  const size_t max_items = (size_t)a.E * 6;
+  dim3 grid((unsigned)(max_items < 2048 ? max_items : 2048)), block(Dims<N>::tpb);
   switch (mode) {
     case MODE_RHS: launch_kernel(k_dg_slab<N, CURVED, MODE_RHS>, grid, block, s, a); break;
     case MODE_SUB1: launch_kernel(k_dg_slab<N, CURVED, MODE_SUB1>, grid, block, s, a); break;
     case MODE_SUB2: launch_kernel(k_dg_slab<N, CURVED, MODE_SUB2>, grid, block, s, a); break;
     default: launch_kernel(k_dg_slab<N, CURVED, MODE_SUB3>, grid, block, s, a); break;
   }
+}
+
+// Element-wise rounding of an FP64 array to FP32 (the mixed-precision background copy).
+__global__ __launch_bounds__(256) void k_to_float(const double* in, float* out, size_t count) {
+  for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < count; q += (size_t)gridDim.x * 256)
+    out[q] = (float)in[q];
+}
+
+void launch_to_float(const double* in, float* out, size_t count, hipStream_t s) {
+  const size_t blocks = (count + 255) / 256;
+  launch_kernel(k_to_float, dim3((unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192)), dim3(256), s, in, out,
+                count);
 }
 
 // Elements holding a non-finite value in their own representation (DG registers

@@ -595,7 +595,7 @@ __device__ inline double block_ratio(const KArgs& a, int e, const double* Bn /* 
     u[r] = 0.0;
     if (p < nn) {
       Metric M;
-      load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
+      load_metric_dg<CURVED>(a, nn, e, p, M);
       double B[3] = {Bn[p], Bn[nn + p], Bn[2 * nn + p]};
       u[r] = sqrt(dot3(M, B, B));
     }
@@ -661,12 +661,14 @@ __device__ inline void recon3(const double* sR, const double* s_in, double* s1, 
 
 // End of step (and start-up): FD elements whose reconstruction passes the indicator with
 // alpha_fd go back to DG.  policy: 0 indicator decides, 1 all go DG, 2 forced mask decides.
+// With `listed` the elements are those of the step's FD work list (every element on FD
+// at the end of the step: FD at the step start or flagged in one of its substeps), on a
+// persistent grid; otherwise one workgroup per element of the domain (start-up).
 template <int N, bool CURVED>
-__global__ __launch_bounds__(256) void k_fd_to_dg(KArgs a, int policy, const uint8_t* forced) {
+__device__ inline void fd_to_dg_one(const KArgs& a, int e, int policy, const uint8_t* forced) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, mm = Dm::mm;
-  const int e = blockIdx.x;
-  if (!a.live[e] || a.rep[e] != 1) return;
+  __syncthreads();  // the previous element's tiles are no longer read
   __shared__ double sin_[mm];
   __shared__ double s1[n * m * m];
   __shared__ double s2[n * n * m];
@@ -703,6 +705,16 @@ __global__ __launch_bounds__(256) void k_fd_to_dg(KArgs a, int policy, const uin
     for (int q = t; q < nn; q += 256) a.dg.Un[((size_t)v * a.E + e) * nn + q] = su[q];
   }
   if (t == 0) a.rep[e] = 0;
+}
+
+template <int N, bool CURVED>
+__global__ __launch_bounds__(256) void k_fd_to_dg(KArgs a, int policy, const uint8_t* forced, int listed) {
+  const int items = listed ? a.fd_count[a.sub] : a.E;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int e = listed ? a.fd_list[item] : item;
+    if (!a.live[e] || a.rep[e] != 1) continue;  // the same for every thread of the block
+    fd_to_dg_one<N, CURVED>(a, e, policy, forced);
+  }
 }
 
 // Stand-alone indicator: DG elements on dg (alpha), FD elements on R(fd) (alpha_fd).
@@ -944,12 +956,19 @@ void launch_fd_update(const KArgs& a, int N, bool curved, int mode, hipStream_t 
 }
 
 void launch_fd_to_dg_policy(const KArgs& a, int N, bool curved, int policy, const uint8_t* forced, hipStream_t s) {
-  if (curved) GRFFE_SWITCH_N(launch_kernel(k_fd_to_dg<NN, true>, dim3(a.E), dim3(256), s, a, policy, forced))
-  else GRFFE_SWITCH_N(launch_kernel(k_fd_to_dg<NN, false>, dim3(a.E), dim3(256), s, a, policy, forced))
+  if (curved) GRFFE_SWITCH_N(launch_kernel(k_fd_to_dg<NN, true>, dim3(a.E), dim3(256), s, a, policy, forced, 0))
+  else GRFFE_SWITCH_N(launch_kernel(k_fd_to_dg<NN, false>, dim3(a.E), dim3(256), s, a, policy, forced, 0))
 }
 
 void launch_fd_to_dg(const KArgs& a, int N, bool curved, int init, hipStream_t s) {
-  launch_fd_to_dg_policy(a, N, curved, init, nullptr, s);
+  if (init) {
+    launch_fd_to_dg_policy(a, N, curved, init, nullptr, s);
+    return;
+  }
+  // end of a step: the step's FD work list holds every element on FD
+  const dim3 grid = list_grid((size_t)a.E, 2048);
+  if (curved) GRFFE_SWITCH_N(launch_kernel(k_fd_to_dg<NN, true>, grid, dim3(256), s, a, 0, nullptr, 1))
+  else GRFFE_SWITCH_N(launch_kernel(k_fd_to_dg<NN, false>, grid, dim3(256), s, a, 0, nullptr, 1))
 }
 
 void launch_begin_substep(const KArgs& a, bool copy, hipStream_t s) {
