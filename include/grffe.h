@@ -175,6 +175,17 @@ int grffe_destroy(grffe_domain* dom);
  * all go DG. */
 int grffe_init_from_fd(grffe_domain* dom, const double* u_fd, const uint8_t* forced, void* stream);
 
+/* Engine of the DG derivative contraction (Sec. III A, the tensor-product derivative
+ * D along each axis of an element's fluxes) in the fused DG substep of FP64 domains:
+ * GRFFE_CONTRACTION_VALU (default) contracts each node's line from LDS on the vector
+ * ALUs; GRFFE_CONTRACTION_MFMA forms the contraction of every line of the element as
+ * 16 x 16 x 4 FP64 matrix-core tiles.  The two give the same result up to the order of
+ * the additions.  The mixed-precision mode, and degree 9, always use the VALU form.  Returns
+ * GRFFE_EINVAL for an unknown engine. */
+#define GRFFE_CONTRACTION_VALU 0
+#define GRFFE_CONTRACTION_MFMA 1
+int grffe_set_contraction(grffe_domain* dom, int engine);
+
 /* Host-forced indicator flags, a test instrument (fault injection): mask (device
  * uint8 [3][E], row k - 1 for substep k) marks elements that the adaptive step
  * (GRFFE_HYBRID_ADAPTIVE) treats as troubled in substep k of every following step

@@ -98,6 +98,7 @@ KArgs make_args(grffe_domain* d) {
   a.rep = d->rep;
   a.troubled = d->troubled;
   a.force = d->force_on ? d->force : nullptr;
+  a.contraction = d->contraction;
   a.ratio = d->ratio;
   a.w_fd = d->w_fd;
   a.trace = d->trace;
@@ -505,6 +506,14 @@ extern "C" int grffe_set_conductor(grffe_domain* d, const double* centre, double
   d->cond_r = radius;
   d->cond_omega = omega;
   d->cond_count = (int)list.size();
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_set_contraction(grffe_domain* d, int engine) {
+  if (int rc = check_dom(d)) return rc;
+  if (engine != GRFFE_CONTRACTION_VALU && engine != GRFFE_CONTRACTION_MFMA)
+    return fail(GRFFE_EINVAL, "engine must be GRFFE_CONTRACTION_VALU or GRFFE_CONTRACTION_MFMA");
+  d->contraction = engine;
   return GRFFE_OK;
 }
 

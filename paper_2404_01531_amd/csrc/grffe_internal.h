@@ -92,6 +92,7 @@ struct KArgs {
   double dt, eta, kpsi, kphi;
   double tci_thr, tci_thr_fd;
   int tci_mode, filter_on, fd_order, ff_clamp, hybrid, precision;
+  int contraction;         // GRFFE_CONTRACTION_*: DG derivative on the VALU from LDS, or on the matrix cores
   double weno_eps, ff_margin;
   // work list of the FD kernels: element ids fd_list[0 .. fd_count[sub]), where sub
   // is 0 for the substeps of a step (one list per step) and 3 for a right-hand
@@ -137,6 +138,7 @@ struct grffe_domain {
   double* bfield_fd = nullptr;
   uint8_t* bad_flags = nullptr;  // [E] scratch of grffe_check_finite
   uint8_t* force = nullptr;      // [3][E] forced indicator flags (grffe_force_flags)
+  int contraction = 0;           // GRFFE_CONTRACTION_* of the DG substep (grffe_set_contraction)
   bool force_on = false;
   // rotating perfect conductor (grffe_set_conductor): the elements meeting its
   // sphere, their lower corners, the GLL nodes; off while cond_count == 0

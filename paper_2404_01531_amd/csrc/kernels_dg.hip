@@ -79,6 +79,49 @@ __device__ inline void external_state(const KArgs& a, int e, int d, int s, int o
   }
 }
 
+// The derivative contraction of one direction on the matrix cores: for every column
+// (component v, line of the element along d) out[v][node(line, i)] = sum_q D[i][q]
+// F[v][node(line, q)], as 16 x 16 x 4 FP64 MFMA tiles (rows i and the contraction
+// index q padded to 16 and to a multiple of 4, 16 columns per tile, the tiles dealt
+// to the workgroup's wavefronts).  Operand layouts of v_mfma_f64_16x16x4: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result register r holds row 4 r + l / 16,
+// column l % 16.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <int N, int TPB, int D>
+__device__ inline void mfma_derivative(const double* sFd, const double* sDd, double* sOut) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, COLS = NV * nf, TILES = (COLS + 15) / 16;
+  constexpr int KS = (n + 3) / 4, WAVES = TPB / 64;
+  constexpr int STR = D == 0 ? 1 : (D == 1 ? n : nf);
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lo = l & 15, kq = l >> 4;
+  double av[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int q = 4 * ks + kq;
+    av[ks] = (lo < n && q < n) ? sDd[lo * n + q] : 0.0;
+  }
+  for (int tile = w; tile < TILES; tile += WAVES) {
+    const int c = 16 * tile + lo;
+    const bool cv = c < COLS;
+    const int v = cv ? c / nf : 0, line = cv ? c % nf : 0;
+    const int t1 = line % n, t2 = line / n;
+    const int base = v * nn + (D == 0 ? n * (t1 + n * t2) : (D == 1 ? t1 + nf * t2 : t1 + n * t2));
+    mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int q = 4 * ks + kq;
+      const double b = (cv && q < n) ? sFd[base + q * STR] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * r + kq;
+      if (cv && i < n) sOut[base + i * STR] = acc[r];
+    }
+  }
+}
+
 // Workgroups per CU the substep kernel is compiled for: two resident wavefronts per
 // SIMD when curved (about 256 VGPRs per lane hold the metric next to the state),
 // three when flat.
@@ -89,11 +132,13 @@ constexpr int dg_min_blocks() {
   return want > 1 ? want : 1;
 }
 
-template <int N, bool CURVED, int MODE, typename R>
+template <int N, bool CURVED, int MODE, typename R, bool MF = false>
 __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_dg_substep(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn, TPB = Dm::tpb;
+  static_assert(!MF || sizeof(R) == sizeof(double), "the MFMA contraction is the FP64 one");
   __shared__ double sF[NV * nn];
+  __shared__ double sOut[MF ? NV * nn : 1];  // the MFMA contraction's results
   __shared__ double sred[2 * (TPB / 64)];
   __shared__ double sop[2 * n * n];  // filter, indicator operator
   __shared__ R sD[n * n];            // derivative matrix in the flux arithmetic type
@@ -158,13 +203,22 @@ __global__ __launch_bounds__(Dims<N>::tpb, (dg_min_blocks<N, CURVED>())) void k_
     const double sc = 2.0 / h_of(a, e, d);
     const int id = idx[d];
     const int p0 = p - id * strideN[d];
-    const R* Drow = sD + id * n;
+    if (MF) {
+      if (d == 0) mfma_derivative<N, TPB, 0>(sF, reinterpret_cast<const double*>(sD), sOut);
+      else if (d == 1) mfma_derivative<N, TPB, 1>(sF, reinterpret_cast<const double*>(sD), sOut);
+      else mfma_derivative<N, TPB, 2>(sF, reinterpret_cast<const double*>(sD), sOut);
+      __syncthreads();
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      R acc = 0;
+      for (int v = 0; v < NV; ++v) dUr[v] -= (R)sc * (R)sOut[v * nn + p];
+    } else {
+      const R* Drow = sD + id * n;
 #pragma unroll
-      for (int q = 0; q < n; ++q) acc += Drow[q] * sFr[v * nn + p0 + q * strideN[d]];
-      dUr[v] -= (R)sc * acc;
+      for (int v = 0; v < NV; ++v) {
+        R acc = 0;
+#pragma unroll
+        for (int q = 0; q < n; ++q) acc += Drow[q] * sFr[v * nn + p0 + q * strideN[d]];
+        dUr[v] -= (R)sc * acc;
+      }
     }
     if (act && (id == 0 || id == N)) {
       const int s = (id == N) ? 1 : 0;
@@ -373,21 +427,23 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
   }
 }
 
-template <int N, bool CURVED, typename R>
+template <int N, bool CURVED, typename R, bool MF>
 static void launch_dg_substep_r(const KArgs& a, int mode, hipStream_t s) {
   dim3 grid(8 * ((a.E + 7) / 8)), block(Dims<N>::tpb);
   switch (mode) {
-    case MODE_RHS: launch_kernel(k_dg_substep<N, CURVED, MODE_RHS, R>, grid, block, s, a); break;
-    case MODE_SUB1: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB1, R>, grid, block, s, a); break;
-    case MODE_SUB2: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB2, R>, grid, block, s, a); break;
-    default: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB3, R>, grid, block, s, a); break;
+    case MODE_RHS: launch_kernel(k_dg_substep<N, CURVED, MODE_RHS, R, MF>, grid, block, s, a); break;
+    case MODE_SUB1: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB1, R, MF>, grid, block, s, a); break;
+    case MODE_SUB2: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB2, R, MF>, grid, block, s, a); break;
+    default: launch_kernel(k_dg_substep<N, CURVED, MODE_SUB3, R, MF>, grid, block, s, a); break;
   }
 }
 
 template <int N, bool CURVED>
 static void launch_dg_substep_t(const KArgs& a, int mode, hipStream_t s) {
-  if (a.precision == GRFFE_PRECISION_MIXED) launch_dg_substep_r<N, CURVED, float>(a, mode, s);
-  else launch_dg_substep_r<N, CURVED, double>(a, mode, s);
+  if (a.precision == GRFFE_PRECISION_MIXED) launch_dg_substep_r<N, CURVED, float, false>(a, mode, s);
+  // (at N = 9 the MFMA result tile does not fit in LDS beside the others: VALU there)
+  else if (a.contraction == GRFFE_CONTRACTION_MFMA) launch_dg_substep_r<N, CURVED, double, (N <= 8)>(a, mode, s);
+  else launch_dg_substep_r<N, CURVED, double, false>(a, mode, s);
 }
 
 template <int N, bool CURVED>

@@ -21,6 +21,8 @@ BC_NO_INCOMING_POYNTING = 1
 BC_DIRICHLET = 2
 PART_EXPLICIT, PART_STIFF, PART_ALL = 1, 2, 3
 HYBRID_DG_ONLY, HYBRID_ADAPTIVE, HYBRID_FORCED = 0, 1, 2
+CONTRACTION_VALU = 0
+CONTRACTION_MFMA = 1
 KERNEL_FAMILIES = {"dg_substep": 1, "fd_flux": 2, "fd_update": 3, "fd_stage": 4, "fd_trace": 5,
                    "dg_slab": 6, "project": 7, "fd_to_dg": 8, "dg_prestage": 9}
 
@@ -87,6 +89,7 @@ def lib():
     L.grffe_init_from_fd.argtypes = [vp, vp, vp, vp]
     L.grffe_set_state.argtypes = [vp, vp, vp, vp, vp]
     L.grffe_force_flags.argtypes = [vp, vp, vp]
+    L.grffe_set_contraction.argtypes = [vp, ctypes.c_int]
     L.grffe_get_state.argtypes = [vp, vp, vp, vp, vp]
     L.grffe_rhs.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
     L.grffe_step.argtypes = [vp, ctypes.c_int, dbl, vp]
@@ -249,6 +252,10 @@ class Domain:
     def set_state(self, dg, fd, rep):
         self._check_state(dg, fd, rep)
         _check(lib().grffe_set_state(self._h, _ptr(dg), _ptr(fd), _ptr(rep), _stream()))
+
+    def set_contraction(self, engine):
+        """DG derivative contraction engine: CONTRACTION_VALU (0) or CONTRACTION_MFMA (1)."""
+        _check(lib().grffe_set_contraction(self._h, int(engine)))
 
     def force_flags(self, mask):
         """Host-forced indicator flags (test instrument): mask is a device uint8 tensor

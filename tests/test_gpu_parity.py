@@ -150,13 +150,15 @@ def test_tci_project_reconstruct():
 # ------------------------------------------------------------------------ steps
 
 
-def _run_steps(w, nsteps, params=None, forced=None, rtol=1e-12, label="", stiff_floor=False):
+def _run_steps(w, nsteps, params=None, forced=None, rtol=1e-12, label="", stiff_floor=False, engine=None):
     """Steps of workload w on both sides from the same FD start-up; after every step the
     representation must match and every variable group agree to rtol of the field
     scale.  stiff_floor adds the q~ conditioning floor of a stiff driver current
     (helpers.q_floor: n dt Lambda 8 u eta max|E~| after n steps) to the q~ group."""
     torch = _torch()
     odom, ldom, _ = make_pair(w, params)
+    if engine is not None:
+        ldom.set_contraction(engine)
     xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], w["degree"])
     u_fd = I.initial_data(w, xf, yf, zf)
     st = OS.initial_state(odom, u_fd, forced)
@@ -383,3 +385,24 @@ def test_check_finite_reports_blown_up_elements():
     ldom.set_state(dg, fd, rep)
     assert ldom.check_finite() == 2
     assert "non-finite" in grffe.lib().grffe_last_error().decode()
+
+
+@pytest.mark.parametrize("curved", [False, True])
+def test_mfma_contraction_engine(curved):
+    """The DG derivative contraction on the matrix cores (grffe_set_contraction MFMA):
+    right-hand sides and adaptive steps against the oracle at the 1e-12 bar, flat (P3,
+    P5) and on the Kerr-Schild background with excision (P5)."""
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    cases = ([I.workload("kerr_schild", n_elem=(4, 4, 4), lower=(-16.0,) * 3, upper=(16.0,) * 3)] if curved
+             else [I.workload("sheet", n_elem=(4, 2, 2), degree=3), I.workload("sheet", n_elem=(4, 2, 2))])
+    for w in cases:
+        odom, ldom, _ = make_pair(w, dict(eta=w["eta"], cfl=w["cfl"]))
+        ldom.set_contraction(grffe.CONTRACTION_MFMA)
+        rng = np.random.default_rng(61)
+        rep = (rng.random(odom.E) < 0.3).astype(np.int64)
+        rep[~odom.active] = DG
+        dg, fd = (_curved_state(odom, w, rng) if curved else _state_arrays(odom, rng, rep, smooth_kind="sheet"))
+        _compare_rhs(odom, ldom, dg, fd, rep, 3, label=f"MFMA contraction P{w['degree']} curved={curved}")
+    st, _ = _run_steps(cases[-1], 2, dict(eta=cases[-1]["eta"], cfl=cases[-1]["cfl"]), label="MFMA contraction steps",
+                       engine=grffe.CONTRACTION_MFMA)
