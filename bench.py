@@ -50,13 +50,14 @@ DG_BG_BYTES_PER_NODE = 26 * 8.0
 # the timed region.
 TIMING_PERIOD = 10
 
-# HBM bytes per FD element per launch of k_fd_flux (FP64): rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs (KiB per dispatch, 12 dispatches with 128 FD elements: fetch
-# 44293.9, write 39781.3), scaled by what the same counters read for a plain
-# 512 MiB device copy (fetch x 2.0, write x 1.0).  Valid for the kernel source
-# whose hash is FD_FLUX_TRAFFIC_SRC; reported as null for any other source.
-FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 14940.0 + 1.0 * 36196.0) * 1024.0 / 128.0
-FD_FLUX_TRAFFIC_SRC = "8627b7c1377cba16"
+# HBM bytes per FD element per launch of k_fd_flux (FP64, flat): rocprofv3 FETCH_SIZE
+# and WRITE_SIZE runs on the current-sheet 8^3 workload (KiB per dispatch, 12
+# dispatches with 128 FD elements: fetch 14800, write 36200), each scaled by what the
+# same counter reads for a plain 512 MiB device copy (fetch x 2.0, write x 1.0).
+# Valid for the kernel source whose hash is FD_FLUX_TRAFFIC_SRC; reported as null for
+# any other source.
+FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 14800.0 + 1.0 * 36200.0) * 1024.0 / 128.0
+FD_FLUX_TRAFFIC_SRC = "5ba12e5f66aa51de"
 
 
 def parse():
@@ -66,6 +67,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--only", choices=("sheet", "batch"), default=None,
                     help="run one secondary workload alone and print its record (profiling runs)")
+    ap.add_argument("--contraction", choices=("valu", "mfma"), default="valu",
+                    help="DG derivative contraction engine of the black-hole domains (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--extras", choices=("core", "all", "none"), default="core",
@@ -200,6 +203,9 @@ def _time_steps(step, steps, warmup):
     return time.perf_counter() - t0
 
 
+CONTRACTION = 0  # DG derivative contraction engine of the black-hole domains (--contraction)
+
+
 def kerr_schild_domain(precision, n_elem=16):
     """The Kerr-Schild black-hole domain (M = 1, a = 0.9, B0 = 1, Wald-like data with
     the ideal E), [-40,40]^3 with n_elem^3 DG-P5 elements, elements meeting r < 1.8
@@ -228,6 +234,7 @@ def kerr_schild_domain(precision, n_elem=16):
     dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p,
                        bg=torch.from_numpy(np.ascontiguousarray(bg)).cuda(), excised=exc)
     m3 = (2 * N + 1) ** 3
+    dom.set_contraction(CONTRACTION)
     dom.set_state(torch.from_numpy(np.ascontiguousarray(u)).cuda(),
                   torch.zeros((9, E, m3), dtype=torch.float64, device="cuda"),
                   torch.zeros(E, dtype=torch.int32, device="cuda"))
@@ -864,6 +871,8 @@ def main():
     from paper_2404_01531_amd import grffe
 
     torch.cuda.set_device(0)
+    global CONTRACTION
+    CONTRACTION = grffe.CONTRACTION_MFMA if args.contraction == "mfma" else grffe.CONTRACTION_VALU
     if args.only == "sheet":
         print(json.dumps(sheet_line(args.steps, args.warmup)))
         return
@@ -939,12 +948,17 @@ def main():
 
 
 # HBM bytes per DG node per launch of the curved k_dg_substep (FP64) on the Kerr-Schild
-# 16^3 workload: rocprofv3 FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, averaged
-# over the three substeps' launches), each scaled by what the same counter reads for a
-# plain 512 MiB device copy (fetch x 2.0, write x 1.0).  Valid for the kernel source
-# whose hash is DG_TRAFFIC_SRC; reported as null for any other source.
-DG_TRAFFIC_PER_NODE = None
-DG_TRAFFIC_SRC = None
+# 16^3 workload: rocprofv3 FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, 14
+# dispatches per substep with 4064-4088 DG elements; fetch 167345 / 215786 / 215337,
+# write 123756 / 123759 / 61891 for substeps 1 / 2 / 3), each scaled by what the same
+# counter reads for a plain 512 MiB device copy (fetch x 2.0, write x 1.0), averaged
+# over the substeps and divided by 4072 x 216 nodes: 584.6 B against the 496 B of
+# algorithmic traffic.  Most of the excess (~89 B per node) is the neighbours' face
+# states the surface term reads (6 x 36 x 9 FP64 values per element, 72 B per node),
+# which the algorithmic figure leaves out.  Valid for the kernel source whose hash is
+# DG_TRAFFIC_SRC; reported as null for any other source.
+DG_TRAFFIC_PER_NODE = 584.6
+DG_TRAFFIC_SRC = "281b13abe5a3abf4"
 
 
 def dg_substep_traffic(rec):
