@@ -203,9 +203,10 @@ int grffe_force_flags(grffe_domain* dom, const uint8_t* mask, void* stream);
 int grffe_set_state(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep, void* stream);
 int grffe_get_state(grffe_domain* dom, double* dg, double* fd, int32_t* rep, void* stream);
 
-/* Semi-discrete right-hand side dU/dt of every live element in its
- * representation given by rep (a pure function of the arguments; the domain's
- * own state is not touched).  parts = GRFFE_PART_*.  Outputs have the layouts of
+/* Semi-discrete right-hand side dU/dt (Sec. II A fluxes and sources; DG operator of
+ * Sec. III A, FD subcell operator of Sec. III C 2 with the fourth-order corrector)
+ * of every live element in its representation given by rep (a pure function of the
+ * arguments; the domain's own state is not touched).  parts = GRFFE_PART_*.  Outputs have the layouts of
  * the inputs; entries of the other representation are left unchanged. */
 int grffe_rhs(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep, double* ddg, double* dfd,
               int parts, void* stream);

@@ -6,7 +6,7 @@ The indicator is applied to u = |B~| = sqrt(gamma_ij B~^i B~^j) at the DG
 nodes.  u_hat is u with its lowest modes removed; an element is troubled
 when sqrt(sum u_hat^2 / sum u^2) > (N + 1 - M)^(-alpha), sums over the nodes.
 
-Two readings of "lowest M modes removed" are provided:
+Two readings of removing the lowest M modes are provided:
 * mode 2 (default): u_hat = u - (L (x) L (x) L) u with L = V diag(p < M) V^-1,
   i.e. every mode with at least one index >= M is kept;
 * mode 1: u_hat = (H (x) H (x) H) u with H = V diag(p >= M) V^-1, i.e. only

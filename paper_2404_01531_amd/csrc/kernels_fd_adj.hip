@@ -1,5 +1,6 @@
 // Adjoint of the FD subcell right-hand side (Sec. III C 2) and of the DG-FD
-// coupling (Sec. III C 3) for any mix of DG and FD elements.
+// coupling (ghost data and traces between the two grids, Sec. III C 1 and 2) for
+// any mix of DG and FD elements.
 //
 // Along each pencil of direction d the right-hand side of cell c is
 //   L_c = -(m/h) (Fhat_{c+1/2} - Fhat_{c-1/2}) + S(U_c),

@@ -224,7 +224,8 @@ def test_butcher_hybrid_without_rollbacks_matches_filtered_step():
 
 
 def test_substep1_rollback_equals_step_with_element_on_fd():
-    """Sec. III C 1, "undo, project, repeat on FD": with N = 5 (R P = I), flat space and
+    """Sec. III C 1 (a flagged DG substep is discarded, the element projected to FD and
+    the substep redone there): with N = 5 (R P = I), flat space and
     no current (eta = 0, q~ = 0: the stiff solve is a pointwise linear map that
     commutes with P), an element flagged by the indicator in substep 1 and redone on
     FD gives the same step as the forced partition with that element on FD from
@@ -449,7 +450,7 @@ def _low(V, u, n, M):
 
 
 def test_filter_after_the_solve_is_unstable_on_the_noisy_wave():
-    """Reading 13 (Sec. III A's filter "after every substep" with Sec. III B's stiff
+    """Reading 13 (Sec. III A's filter, applied at every substep, with Sec. III B's stiff
     solve): filtering the solved stage values changes E parallel to B after the
     relaxation, and the next stiff source multiplies that change by eta dt ~ 10^3.
     On the noisy wave (eta = 10^6) that placement grows the field tenfold per step
