@@ -12,8 +12,26 @@ struct CellSrc {
   int bnd;            // the face's neighbour entry (< 0) when ptr is null
 };
 
+// The neighbours of element e across its two faces normal to d (lower, upper) and
+// their representations: read once per work item, whose element and direction are
+// the same for every thread, so that the ghost cells' sources need no dependent
+// per-thread loads.
+struct RowNbrs {
+  int o0, o1;  // neighbour entries (< 0: a physical face)
+  int r0, r1;  // their representations (-1 for a physical face)
+};
+
+__device__ inline RowNbrs row_neighbours(const KArgs& a, int e, int d) {
+  RowNbrs nb;
+  nb.o0 = a.nbr[e * 6 + 2 * d];
+  nb.o1 = a.nbr[e * 6 + 2 * d + 1];
+  nb.r0 = nb.o0 >= 0 ? a.rep0[nb.o0] : -1;
+  nb.r1 = nb.o1 >= 0 ? a.rep0[nb.o1] : -1;
+  return nb;
+}
+
 template <int N>
-__device__ inline CellSrc cell_source(const KArgs& a, int e, int d, int c, int t1, int t2) {
+__device__ inline CellSrc cell_source(const KArgs& a, const RowNbrs& nb, int e, int d, int c, int t1, int t2) {
   using Dm = Dims<N>;
   constexpr int m = Dm::m, mm = Dm::mm;
   const int str[3] = {1, m, m * m};
@@ -27,7 +45,7 @@ __device__ inline CellSrc cell_source(const KArgs& a, int e, int d, int c, int t
     return cs;
   }
   const int s = (c >= m) ? 1 : 0;
-  const int o = a.nbr[e * 6 + 2 * d + s];
+  const int o = s ? nb.o1 : nb.o0;
   if (o < 0) {
     const int cb = s ? m - 1 : 0;
     cs.cell = cb * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
@@ -40,7 +58,7 @@ __device__ inline CellSrc cell_source(const KArgs& a, int e, int d, int c, int t
   const int cn = s ? c - m : c + m;  // cell index inside the neighbour
   cs.cell = cn * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
   cs.elem = o;
-  if (a.rep0[o] == 1) {
+  if ((s ? nb.r1 : nb.r0) == 1) {
     cs.ptr = a.w_fd + (size_t)o * mm + cs.cell;
     cs.stride = (size_t)a.E * mm;
   } else {

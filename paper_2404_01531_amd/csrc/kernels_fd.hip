@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_project_troubled(KArgs a) {
 // which leaves a single quotient.
 
 // n / d for the WENO normalisation, whose denominator is positive and in the normal
-// range (at least eps^6 / 16): the hardware reciprocal estimate refined by two
+// range (at least eps^6): the hardware reciprocal estimate refined by two
 // Newton-Raphson steps r <- r (2 - d r), then one multiplication (within about one
 // unit in the last place of the correctly rounded quotient).
 __device__ inline double div_weno(double n, double d) {
@@ -263,23 +263,24 @@ __device__ inline void weno5z_cell(const double* v, double eps, double& left, do
   const double s0 = b0 * b0, s1 = b1 * b1, s2 = b2 * b2;
   const double p01 = s0 * s1, p02 = s0 * s2, p12 = s1 * s2;
   const double a0 = (s0 + t2), a1 = (s1 + t2), a2 = (s2 + t2);
+  // the common factors 1/16 of the weights (which cancels in the normalisation) and
+  // 1/8 of the candidates (applied once to the result) are left out
+  const double a1p = 10.0 * a1 * p02;
   {
-    const double w0 = (1.0 / 16.0) * a0 * p12;
-    const double w1 = (10.0 / 16.0) * a1 * p02;
-    const double w2 = (5.0 / 16.0) * a2 * p01;
-    const double q0 = (3.0 * v[0] - 10.0 * v[1] + 15.0 * v[2]) * 0.125;
-    const double q1 = (-v[1] + 6.0 * v[2] + 3.0 * v[3]) * 0.125;
-    const double q2 = (3.0 * v[2] + 6.0 * v[3] - v[4]) * 0.125;
-    left = div_weno(w0 * q0 + w1 * q1 + w2 * q2, w0 + w1 + w2);
+    const double w0 = a0 * p12;
+    const double w2 = 5.0 * a2 * p01;
+    const double q0 = 3.0 * v[0] - 10.0 * v[1] + 15.0 * v[2];
+    const double q1 = -v[1] + 6.0 * v[2] + 3.0 * v[3];
+    const double q2 = 3.0 * v[2] + 6.0 * v[3] - v[4];
+    left = 0.125 * div_weno(w0 * q0 + a1p * q1 + w2 * q2, w0 + a1p + w2);
   }
   {
-    const double w0 = (1.0 / 16.0) * a2 * p01;
-    const double w1 = (10.0 / 16.0) * a1 * p02;
-    const double w2 = (5.0 / 16.0) * a0 * p12;
-    const double q0 = (3.0 * v[4] - 10.0 * v[3] + 15.0 * v[2]) * 0.125;
-    const double q1 = (-v[3] + 6.0 * v[2] + 3.0 * v[1]) * 0.125;
-    const double q2 = (3.0 * v[2] + 6.0 * v[1] - v[0]) * 0.125;
-    right = div_weno(w0 * q0 + w1 * q1 + w2 * q2, w0 + w1 + w2);
+    const double w0 = a2 * p01;
+    const double w2 = 5.0 * a0 * p12;
+    const double q0 = 3.0 * v[4] - 10.0 * v[3] + 15.0 * v[2];
+    const double q1 = -v[3] + 6.0 * v[2] + 3.0 * v[1];
+    const double q2 = 3.0 * v[2] + 6.0 * v[1] - v[0];
+    right = 0.125 * div_weno(w0 * q0 + a1p * q1 + w2 * q2, w0 + a1p + w2);
   }
 }
 
@@ -299,8 +300,16 @@ constexpr int flux_tpb() {
 // [component][cell or face][pencil] with the pencil index fastest: the row length
 // m = 2N+1 is odd, so both the pencil-contiguous and the cell-contiguous thread
 // mappings touch 16 distinct bank pairs per 16 lanes (no bank conflicts).
+// Workgroups per CU the flux kernel is compiled for: the curved FP64 instantiations
+// of degree <= 5 fit three in LDS, and are held to the registers of three (168 per
+// lane; without the bound they take ~175, which allows two).
+template <int N, bool CURVED>
+constexpr int flux_min_blocks() {
+  return (CURVED && N <= 5) ? 3 : 1;
+}
+
 template <int N, bool CURVED, typename R>
-__global__ __launch_bounds__(flux_tpb<N>()) void k_fd_flux(KArgs a) {
+__global__ __launch_bounds__(flux_tpb<N>(), (flux_min_blocks<N, CURVED>())) void k_fd_flux(KArgs a) {
   using Dm = Dims<N>;
   constexpr int m = Dm::m, mm = Dm::mm;
   constexpr int nf = (m + 1) * m * m;
@@ -331,6 +340,7 @@ __global__ __launch_bounds__(flux_tpb<N>()) void k_fd_flux(KArgs a) {
   const int e = a.fd_list[item / (3 * m)];
   const int d = (item / m) % 3;
   const int t2 = item % m;
+  const RowNbrs nb = row_neighbours(a, e, d);
   // phase 1: stage cells -3 .. m+2 of every pencil (and the metric of cells -1 .. m)
   for (int q = t; q < L * C; q += TPB) {
     int c, t1;
@@ -341,7 +351,7 @@ __global__ __launch_bounds__(flux_tpb<N>()) void k_fd_flux(KArgs a) {
       t1 = q % L;
       c = q / L;
     }
-    const CellSrc cs = cell_source<N>(a, e, d, c - 3, t1, t2);
+    const CellSrc cs = cell_source<N>(a, nb, e, d, c - 3, t1, t2);
     double W[NR];
     Metric Mc;
     if (cs.ptr) {

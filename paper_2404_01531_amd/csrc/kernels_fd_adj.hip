@@ -138,6 +138,7 @@ __global__ __launch_bounds__(256) void k_fd_adj_flux(KArgs a, FdAdj b) {
     const int e = a.fd_list[item / (3 * m)];
     const int d = (item / m) % 3;
     const int t2 = item % m;
+    const RowNbrs nb = row_neighbours(a, e, d);
     const int str[3] = {1, m, m * m};
     const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
     // stage the cells -3 .. m+2 (as the forward kernel) and clear their adjoints
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(256) void k_fd_adj_flux(KArgs a, FdAdj b) {
         t1 = q % L;
         c = q / L;
       }
-      const CellSrc cs = cell_source<N>(a, e, d, c - 3, t1, t2);
+      const CellSrc cs = cell_source<N>(a, nb, e, d, c - 3, t1, t2);
       double W[NR];
       Metric Mc;
       if (cs.ptr) {

@@ -307,7 +307,13 @@ __device__ inline void boundary_state(int d, double side, const T* Ui, const Met
 }
 
 __device__ inline double char_speed(int d, const Metric& M) {
-  return M.alpha * sqrt(M.gi[sym(d, d)]) + fabs(M.beta[d]);
+  // blended with 0/1 weights (exact for finite metric values), not indexed or
+  // selected: with a run-time direction either form is turned into an indexed load,
+  // which puts the whole Metric in private memory
+  const double w0 = d == 0 ? 1.0 : 0.0, w1 = d == 1 ? 1.0 : 0.0, w2 = d == 2 ? 1.0 : 0.0;
+  const double gdd = w0 * M.gi[0] + w1 * M.gi[3] + w2 * M.gi[5];
+  const double bd = w0 * M.beta[0] + w1 * M.beta[1] + w2 * M.beta[2];
+  return M.alpha * sqrt(gdd) + fabs(bd);
 }
 
 }  // namespace grffe

@@ -724,6 +724,65 @@ def test_poynting_objective_parameter_gradient():
     aw.close()
 
 
+def test_poynting_objective_parameter_gradient_adaptive():
+    """The same objective with the hybrid control on: the adaptive indicator, and
+    three elements holding sphere points forced onto FD in substeps 1, 2 and 3 of
+    every step, so that every step has rollbacks in each substep and switches back at
+    its end.  The checkpointed gradient with the forward pass's decisions frozen
+    (grffe_step_adjoint_frozen) against central differences of the objective, taken
+    only at steps whose perturbed runs make the same decisions (the same
+    representation after every step).  eta = 300: at the workload's eta = 1e5 the
+    elements that stay on FD make the objective so rough at small scales (stiff
+    relaxation over WENO5-Z weights with eps = 1e-40) that the differences approach
+    the adjoint only as h -> 1e-8 (measured 2e-2, 4e-3, 4e-4 for B0 at relative steps
+    1e-6, 1e-7, 1e-8), too slowly for a tight bound.  Best agreement within 1e-6."""
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd.poynting import AdjointWorkload
+    w = dict(I.workload("kerr_schild", n_elem=(8, 8, 8), degree=3), eta=300.0)
+    aw = AdjointWorkload(w, hybrid=grffe.HYBRID_ADAPTIVE)
+    E = aw.E
+    mask = torch.zeros((3, E), dtype=torch.uint8, device="cuda")
+    held = aw.L.uniq.cpu().numpy()
+    for k in range(3):
+        mask[k, int(held[7 * k + 3])] = 1
+    aw.dom.force_flags(mask)
+    params = I.adjoint_parameters()
+    # the decisions of one step: a rollback in each substep, switches back at the end
+    u0 = aw.initial(params)
+    zf = torch.zeros(aw.dom.fd_shape(), dtype=torch.float64, device="cuda")
+    zr = torch.zeros(E, dtype=torch.int32, device="cuda")
+    _, _, rlog = aw.dom.step_adjoint_frozen(u0, zf, zr, torch.zeros_like(u0), zf, aw.dt, with_log=True)
+    counts = [int(x) for x in rlog.sum(1).cpu()]
+    _say(f"adaptive Poynting objective: representation counts of one step {counts}")
+    assert counts[0] == 0 and counts[1] >= 1 and counts[2] >= 2 and counts[3] >= 3
+    steps, every = 12, 5
+    log = []
+    phi, grad = aw.gradient(params, steps, every, log=log)
+    log0 = []
+    assert abs(phi - aw.phi(params, steps, log0)) <= 1e-13 * abs(phi)
+    for k in aw.PARAMS:
+        fds, errs = [], []
+        for rel in (1e-4, 1e-5, 1e-6):
+            h = rel * max(1.0, abs(params[k]))
+            lp, lm = [], []
+            fp = aw.phi(dict(params, **{k: params[k] + h}), steps, lp)
+            fm = aw.phi(dict(params, **{k: params[k] - h}), steps, lm)
+            same = all(torch.equal(a, b) and torch.equal(a, c) for a, b, c in zip(log0, lp, lm))
+            f = (fp - fm) / (2 * h)
+            fds.append((f, same))
+            if same:
+                errs.append(_rel(grad[k], f))
+        _say(f"adaptive Poynting objective ({steps} steps, checkpoints every {every}) dPhi/d{k}: adjoint "
+             f"{grad[k]:.12e}  FD " + "  ".join(f"{f:.12e}{'' if ok else ' (decisions differ)'}" for f, ok in fds))
+        assert errs and min(errs) <= TOL, k
+    # checkpoint interval: one segment (no recomputation) gives the same gradient bits
+    _, grad1 = aw.gradient(params, steps, steps)
+    assert all(grad1[k] == grad[k] for k in aw.PARAMS)
+    aw.dom.force_flags(None)
+    aw.close()
+
+
 def test_autograd_adaptive_checkpointed():
     """Three adaptive steps (sheet P3: the elements at the sheet start on DG and are
     rolled back, smooth FD elements switch back) through GRFFEStepFrozen with
