@@ -491,36 +491,41 @@ __global__ __launch_bounds__(256) void k_fd_adj_stage(KArgs a, FdAdj b, AdjBufs 
   }
 }
 
-// Adjoint of the R-traces the DG neighbours of an FD element read: one workgroup
-// per listed FD element, its faces with a DG neighbour one after the other.  At the
-// DG face node the exterior state enters the lower-face lift as
+// Adjoint of the R-traces the DG neighbours of an FD element read: one work item per
+// (listed FD element, direction d), its two faces normal to d handled together.  At
+// the DG face node the exterior state enters the lower-face lift as
 // +(2/h)/w_0 (F(Ux)/2 + lambda Ux/2) and the upper-face lift as
 // -(2/h)/w_N (F(Ux)/2 - lambda Ux/2); the adjoint of (Ux, J~x^d) is taken through
-// R (x) R (x) R restricted to the face (row 0 or N along the normal) transposed and
-// added to the element's per-direction adjoints wbar (after the flux adjoint).
+// R (x) R (x) R restricted to the face (row 0 or N along the normal) transposed, and
+// the two faces' results are added to the element's adjoints wbar of direction d
+// (after the flux adjoint) in one pass over its cells.  Work items of different
+// directions write different parts of wbar, so none of them collide.
 template <int N, bool CURVED>
 __global__ __launch_bounds__(256) void k_fd_adj_trace(KArgs a, FdAdj b) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, m = Dm::m, nn = Dm::nn, mm = Dm::mm;
   constexpr int NR = NV + 1;
   __shared__ double sR[n * m];
-  __shared__ double sT[NR * n * n];  // trace adjoint [k][a2][a1]
-  __shared__ double s1[NR * n * m];  // [k][a2][c1]
-  __shared__ double s2[NR * m * m];  // [k][c2][c1]
+  __shared__ double sT[NR * n * n];     // trace adjoint [k][a2][a1]
+  __shared__ double s1[NR * n * m];     // [k][a2][c1]
+  __shared__ double s2[2 * NR * m * m];  // per face side: [s][k][c2][c1]
   const int t = threadIdx.x;
   for (int q = t; q < n * m; q += 256) sR[q] = a.ops->R[q];
   const int32_t* upd = b.rep_upd ? b.rep_upd : a.rep0;
-  const int items = a.fd_count[a.sub];
+  const int items = a.fd_count[a.sub] * 3;
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
-    const int e = a.fd_list[item];
+    const int e = a.fd_list[item / 3];
+    const int d = item % 3;
     if (a.rep0[e] != 1) continue;  // rolled back in this substep: no trace was read
-    for (int f = 0; f < 6; ++f) {
+    const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+    const int strn[3] = {1, n, n * n};
+    bool used[2];
+    for (int s = 0; s < 2; ++s) {
+      const int f = 2 * d + s;
       const int g = a.nbr[e * 6 + f];
-      if (g < 0 || upd[g] != 0) continue;
-      const int d = f >> 1;
-      const int fg = f ^ 1, sg = fg & 1;  // the DG element's face and side
-      const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
-      const int strn[3] = {1, n, n * n};
+      used[s] = g >= 0 && upd[g] == 0;
+      if (!used[s]) continue;
+      const int sg = 1 - s;  // the DG element's side of the shared face
       __syncthreads();
       for (int q = t; q < n * n; q += 256) {
         const int a1 = q % n, a2 = q / n;
@@ -555,25 +560,33 @@ __global__ __launch_bounds__(256) void k_fd_adj_trace(KArgs a, FdAdj b) {
       }
       __syncthreads();
       // second tangential axis: a2 (n) -> c2 (m)
+      double* s2s = s2 + s * NR * m * m;
       for (int q = t; q < NR * m * m; q += 256) {
         const int c1 = q % m, c2 = (q / m) % m, k = q / (m * m);
         double acc = 0.0;
 #pragma unroll
         for (int z = 0; z < n; ++z) acc += sR[z * m + c2] * s1[(k * n + z) * m + c1];
-        s2[q] = acc;
-      }
-      __syncthreads();
-      // normal axis: row 0 (lower face) or N (upper face) of R, spread over the line
-      const int row = (f & 1) ? N : 0;
-      for (int q = t; q < mm; q += 256) {
-        const int ci[3] = {q % m, (q / m) % m, q / (m * m)};
-        const double r = sR[row * m + ci[d]];
-        const int tt = ci[t1ax] + m * ci[t2ax];
-#pragma unroll
-        for (int k = 0; k < NR; ++k)
-          b.wbar[(((size_t)d * NR + k) * a.E + e) * mm + q] += r * s2[k * m * m + tt];
+        s2s[q] = acc;
       }
     }
+    if (!used[0] && !used[1]) continue;  // the same for every thread of the block
+    __syncthreads();
+    // normal axis: row 0 of R for the lower face, row N for the upper one, spread
+    // over the line, both faces in one pass
+    for (int q = t; q < mm; q += 256) {
+      const int ci[3] = {q % m, (q / m) % m, q / (m * m)};
+      const double r0 = used[0] ? sR[ci[d]] : 0.0;
+      const double r1 = used[1] ? sR[N * m + ci[d]] : 0.0;
+      const int tt = ci[t1ax] + m * ci[t2ax];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        double add = 0.0;
+        if (used[0]) add += r0 * s2[k * m * m + tt];
+        if (used[1]) add += r1 * s2[(NR + k) * m * m + tt];
+        b.wbar[(((size_t)d * NR + k) * a.E + e) * mm + q] += add;
+      }
+    }
+    __syncthreads();  // the next item rewrites s2
   }
 }
 
@@ -663,7 +676,9 @@ static void fd_coupling_t(const KArgs& a, const FdAdj& b, hipStream_t s) {
   const size_t flux_items = (size_t)a.E * 3 * m;
   launch_kernel(k_fd_adj_flux<N, CURVED>, dim3((unsigned)(flux_items < 2048 ? flux_items : 2048)), dim3(256), s, a,
                 b);
-  launch_kernel(k_fd_adj_trace<N, CURVED>, dim3((unsigned)(a.E < 2048 ? a.E : 2048)), dim3(256), s, a, b);
+  const size_t trace_items = (size_t)a.E * 3;
+  launch_kernel(k_fd_adj_trace<N, CURVED>, dim3((unsigned)(trace_items < 2048 ? trace_items : 2048)), dim3(256), s,
+                a, b);
   launch_kernel(k_dg_adj_slab<N, CURVED>, dim3(a.E), dim3(Dims<N>::tpb), s, a, b);
 }
 
