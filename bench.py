@@ -438,9 +438,11 @@ def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, s
             "non_finite_elements": dom.check_finite()}
 
 
-def run_batch(steps, warmup, precision, use_graph=True):
+def run_batch(steps, warmup, precision, use_graph=True, tune=False):
     """64 independent flat periodic domains (n^3 elements, n ~ U{4..12}, degree
-    N ~ U{3..7}, wave or sheet), each advanced by its own CFL step, one call per step."""
+    N ~ U{3..7}, wave or sheet), each advanced by its own CFL step, one call per step.
+    tune: the contraction engine of every degree pool picked by the batch's
+    autotuner first (untimed; the members' states are restored)."""
     import numpy as np
     import torch
 
@@ -460,6 +462,7 @@ def run_batch(steps, warmup, precision, use_graph=True):
                     torch.zeros(E, dtype=torch.int32, device="cuda"))
         nodes += E * n3
     torch.cuda.synchronize()
+    table = b.autotune(steps=2, reps=3) if tune else None
     b.step(warmup, use_graph=use_graph)
     torch.cuda.synchronize()
 
@@ -482,7 +485,9 @@ def run_batch(steps, warmup, precision, use_graph=True):
             "degrees": sorted({w["degree"] for w in ws}), "value": pts * 3 * steps / secs,
             "unit": "grid-point updates/s", "steps": steps, "ms_per_step": secs * 1e3 / steps,
             "fd_elements": [int(f0), int(f1)],
-            "hbm_GBps_dg_state": (nodes * sum(DG_BYTES_PER_NODE.values())) * steps / secs / 1e9}
+            "hbm_GBps_dg_state": (nodes * sum(DG_BYTES_PER_NODE.values())) * steps / secs / 1e9,
+            "contraction_per_degree": ({str(N): ("mfma" if e == 1 else "valu") for N, e in table.items()}
+                                       if table is not None else "valu (default)")}
 
 
 def run_adjoint(steps=200, every=20, check_steps=10):
@@ -1022,6 +1027,7 @@ def main():
     if args.extras != "none":
         ex = {}
         jobs = [("batch_64_fp64", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0)),
+                ("batch_64_fp64_autotuned", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0, tune=True)),
                 ("batch_64_mixed", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 1)),
                 ("sheet_8^3", lambda: sheet_line(args.extra_steps, 2)),
                 ("kerr_schild_16^3_full_run", lambda: run_kerr_schild_full()),

@@ -385,6 +385,15 @@ int grffe_batch_get_counts(grffe_batch* batch, int32_t k, int32_t* n_dg, int32_t
  * directly.  The two give identical results. */
 int grffe_batch_step(grffe_batch* batch, int32_t n_steps, int32_t use_graph, void* stream);
 
+/* Contraction engine (GRFFE_CONTRACTION_*, as grffe_set_contraction) of the batch's
+ * pool of degree `degree`, or of every pool for degree = 0: the tunable an autotuner
+ * picks per degree (the two engines give the same result up to the order of the
+ * additions, and their speed depends on the degree).  Changing an engine drops the
+ * captured step graph; the next grffe_batch_step with use_graph captures again.
+ * Returns GRFFE_EINVAL for an unknown engine or a degree with no pool. */
+int grffe_batch_set_contraction(grffe_batch* batch, int32_t degree, int32_t engine);
+int grffe_batch_get_contraction(grffe_batch* batch, int32_t degree, int32_t* engine);
+
 const char* grffe_last_error(void);
 
 #ifdef __cplusplus

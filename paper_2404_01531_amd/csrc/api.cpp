@@ -1294,6 +1294,41 @@ extern "C" int grffe_batch_get_counts(grffe_batch* b, int32_t k, int32_t* n_dg, 
   return GRFFE_OK;
 }
 
+// Contraction engine per degree pool.  A change drops the captured step graph, which
+// holds the launches of the previous engine; the next graph step captures again.
+extern "C" int grffe_batch_set_contraction(grffe_batch* b, int32_t degree, int32_t engine) {
+  if (int rc = check_batch(b)) return rc;
+  if (engine != GRFFE_CONTRACTION_VALU && engine != GRFFE_CONTRACTION_MFMA)
+    return fail(GRFFE_EINVAL, "engine must be GRFFE_CONTRACTION_VALU or GRFFE_CONTRACTION_MFMA");
+  if (degree != 0 && (degree < 3 || degree > MAX_DEG)) return fail(GRFFE_EINVAL, "degree must be 0 or in 3..9");
+  bool found = false, changed = false;
+  for (grffe_domain* d : b->pools) {
+    if (degree != 0 && d->N != degree) continue;
+    found = true;
+    if (d->contraction != engine) changed = true;
+    d->contraction = engine;
+  }
+  if (!found) return fail(GRFFE_EINVAL, "the batch has no domain of that degree");
+  if (changed && b->exec) {
+    HIPCHK(hipGraphExecDestroy(b->exec));
+    b->exec = nullptr;
+    if (b->graph) HIPCHK(hipGraphDestroy(b->graph));
+    b->graph = nullptr;
+  }
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_batch_get_contraction(grffe_batch* b, int32_t degree, int32_t* engine) {
+  if (int rc = check_batch(b)) return rc;
+  if (!engine) return fail(GRFFE_EINVAL, "engine must not be NULL");
+  for (grffe_domain* d : b->pools)
+    if (d->N == degree) {
+      *engine = d->contraction;
+      return GRFFE_OK;
+    }
+  return fail(GRFFE_EINVAL, "the batch has no domain of that degree");
+}
+
 // One step of every pool: pool 0 on `st`, every other pool on its own branch stream
 // forked from and joined back to `st`.
 static int batch_step_once(grffe_batch* b, hipStream_t st) {

@@ -117,6 +117,8 @@ def lib():
     L.grffe_batch_get_dt.argtypes = [vp, i32, ctypes.POINTER(dbl)]
     L.grffe_batch_get_counts.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.grffe_batch_step.argtypes = [vp, i32, i32, vp]
+    L.grffe_batch_set_contraction.argtypes = [vp, i32, i32]
+    L.grffe_batch_get_contraction.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.grffe_last_error.restype = ctypes.c_char_p
     for name in ("grffe_init_domain", "grffe_destroy", "grffe_init_from_fd", "grffe_set_state", "grffe_get_state",
                  "grffe_rhs", "grffe_step", "grffe_tci", "grffe_project_dg_to_fd", "grffe_reconstruct_fd_to_dg",
@@ -126,7 +128,8 @@ def lib():
                  "grffe_batch_get_dt", "grffe_batch_get_counts", "grffe_batch_step", "grffe_rhs_adjoint",
                  "grffe_step_adjoint", "grffe_step_adjoint_frozen", "grffe_get_stages",
                  "grffe_step_adjoint_stages", "grffe_set_boundary_state", "grffe_set_boundary_field",
-                 "grffe_check_finite", "grffe_set_conductor"):
+                 "grffe_check_finite", "grffe_set_conductor", "grffe_batch_set_contraction",
+                 "grffe_batch_get_contraction"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -530,3 +533,55 @@ class Batch:
 
     def step(self, n_steps=1, use_graph=True):
         _check(lib().grffe_batch_step(self._h, int(n_steps), int(bool(use_graph)), _stream()))
+
+    def degrees(self):
+        """The degrees of the batch's pools, ascending."""
+        return sorted({N for _, N in self.shapes})
+
+    def set_contraction(self, degree, engine):
+        """DG contraction engine of the pool of one degree (0: every pool)."""
+        _check(lib().grffe_batch_set_contraction(self._h, int(degree), int(engine)))
+
+    def contraction(self, degree):
+        v = ctypes.c_int32()
+        _check(lib().grffe_batch_get_contraction(self._h, int(degree), ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, steps=3, reps=3, margin=0.02):
+        """Pick each pool's contraction engine by measurement: one degree at a time,
+        the batch's graph step (all pools, as it runs) is timed with each engine, the
+        median of `reps` runs of `steps` steps, and an engine other than the default
+        (VALU) is kept only when it is faster by more than `margin`.  The state of
+        every member is restored afterwards.  Returns {degree: engine}."""
+        import time
+
+        import torch
+        saved = [self.get_state(k) for k in range(self.count)]
+
+        def timed():
+            self.step(1)  # captures the graph after a change
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                self.step(steps)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            return sorted(ts)[len(ts) // 2]
+
+        table = {}
+        try:
+            self.set_contraction(0, CONTRACTION_VALU)
+            for N in self.degrees():
+                t = {}
+                for eng in (CONTRACTION_VALU, CONTRACTION_MFMA):
+                    self.set_contraction(N, eng)
+                    t[eng] = timed()
+                best = CONTRACTION_MFMA if t[CONTRACTION_MFMA] < (1.0 - margin) * t[CONTRACTION_VALU] else CONTRACTION_VALU
+                self.set_contraction(N, best)
+                table[N] = best
+        finally:
+            for k, st in enumerate(saved):
+                self.set_state(k, *st)
+            torch.cuda.synchronize()
+        return table

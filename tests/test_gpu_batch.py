@@ -133,6 +133,57 @@ def test_batch_graph_replays_equal_eager_and_standalone():
     _say("graph replays: 4 steps bit-identical to eager and stand-alone runs")
 
 
+def test_batch_autotune_contraction_per_degree():
+    """The autotuner picks each degree pool's contraction engine by timing the
+    batch's graph step: it returns one engine per degree, leaves the members' states
+    as they were, and the tuned batch (graph replays, after the engine change dropped
+    and recaptured the graph) matches the same kernels enqueued directly and each
+    member stepped alone with its pool's engine, bit for bit; an explicit switch of
+    one pool back and forth also recaptures."""
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    members = MEMBERS + [I.workload("wave", n_elem=(2, 1, 1), degree=8, lower=(-1.0, -0.5, -0.5),
+                                    upper=(1.0, 0.5, 0.5))]
+    bg = _make_batch(members)
+    be = _make_batch(members)
+    bg.step(1)
+    be.step(1, use_graph=False)
+    before = [bg.get_state(k) for k in range(len(members))]
+    table = bg.autotune(steps=2, reps=3)
+    _say(f"autotuned contraction engines per degree: {table}")
+    assert sorted(table) == [3, 4, 5, 8] and set(table.values()) <= {grffe.CONTRACTION_VALU, grffe.CONTRACTION_MFMA}
+    for k in range(len(members)):
+        for x, y in zip(bg.get_state(k), before[k]):
+            assert torch.equal(x, y), f"member {k}: the autotuner changed the state"
+    # force a mixed table (MFMA on P3 and P8), whatever the measurement chose
+    for N, eng in ((3, 1), (4, 0), (5, 0), (8, 1)):
+        bg.set_contraction(N, eng)
+        be.set_contraction(N, eng)
+        assert bg.contraction(N) == eng
+    solos = []
+    for k in (1, 4):
+        w = members[k]
+        d = grffe.Domain(w["n_elem"], w["lower"], w["upper"], w["degree"], w["bc"], params=grffe.default_params(**PARAMS))
+        d.set_state(*bg.get_state(k))
+        d.set_contraction(bg.contraction(w["degree"]))
+        solos.append((k, d))
+    for it in range(3):
+        bg.step(1, use_graph=True)
+        be.step(1, use_graph=False)
+        for k, d in solos:
+            d.step(1, d.dt())
+        for k in range(len(members)):
+            for x, y in zip(bg.get_state(k), be.get_state(k)):
+                assert torch.equal(x, y), f"step {it + 1}, member {k}: tuned graph and eager differ"
+        for k, d in solos:
+            for x, y in zip(bg.get_state(k), d.get_state()):
+                assert torch.equal(x, y), f"step {it + 1}, member {k}: batch and stand-alone differ"
+    with pytest.raises(grffe.GrffeError):
+        bg.set_contraction(6, 1)  # no pool of degree 6
+    with pytest.raises(grffe.GrffeError):
+        bg.set_contraction(5, 7)
+
+
 def test_batch_rejects_bad_input():
     _torch()
     from paper_2404_01531_amd import grffe
