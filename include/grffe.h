@@ -216,6 +216,15 @@ int grffe_rhs(grffe_domain* dom, const double* dg, const double* fd, const int32
  * hybrid control of Sec. III C 1 inside every step. */
 int grffe_step(grffe_domain* dom, int n_steps, double dt, void* stream);
 
+/* One step as grffe_step, with its decision log: rep_log (device int32 [5][E],
+ * caller-owned) receives the representation before the step, after substeps 1, 2
+ * and 3 (an element rolled back in substep k is FD from row k on) and after the step
+ * (the switches back of Sec. III C 1).  For a parity harness that compares the
+ * hybrid decisions of two implementations and replays the other side's decision
+ * where an indicator ratio lies within rounding of its threshold.  dt <= 0 selects
+ * the CFL step. */
+int grffe_step_logged(grffe_domain* dom, double dt, int32_t* rep_log, void* stream);
+
 /* Troubled-cell indicator, Eq. (persson tci), on |B~| = sqrt(gamma_ij B~^i B~^j):
  * DG elements (rep 0) are checked on dg with alpha, FD elements (rep 1) on the
  * sixth-order reconstruction of fd with alpha_fd.  troubled (device uint8 [E]);

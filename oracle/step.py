@@ -187,13 +187,35 @@ def _M(dom):
     return p["tci_M"] if p["tci_M"] else ops.tci_M(dom.N)
 
 
-def step(dom, st, dt, log=None, force=None):
+def _replay(decided, ratio, thr, theirs, tol, events, where, elems):
+    """Parity harness (not part of the method): where an indicator ratio lies within
+    ``tol`` (relative) of its threshold, rounding alone can decide the comparison, so
+    the other implementation's decision ``theirs`` is taken instead of ``decided``;
+    every such event is appended to ``events`` as (where, element, ratio, threshold,
+    own decision, taken decision)."""
+    near = np.abs(ratio / thr - 1.0) <= tol
+    out = decided.copy()
+    out[near] = theirs[near]
+    if events is not None:
+        for i in np.nonzero(near)[0]:
+            events.append((where, int(elems[i]), float(ratio[i]), float(thr), bool(decided[i]), bool(out[i])))
+    return out
+
+
+def step(dom, st, dt, log=None, force=None, replay=None, replay_tol=1e-10, replay_events=None):
     """Advance State ``st`` by one step of size dt; returns a new State.
 
     ``force`` (test instrument, nullable): boolean array (3, E); in the adaptive
     mode an element on DG with force[k - 1] set is treated as troubled in
     substep k whatever its indicator ratio (a host-forced flag, so that rollbacks
-    can be made to happen in any substep)."""
+    can be made to happen in any substep).
+
+    ``replay`` (parity harness, nullable): the other implementation's
+    representation log of the same step, integer array (5, E): before the step,
+    after substeps 1, 2, 3 and after the step.  A decision whose ratio lies within
+    ``replay_tol`` of its threshold follows that log (an element flagged in substep
+    k is FD in row k; an element switched back at the end is DG in row 4) and is
+    recorded in ``replay_events``."""
     p = dom.params
     act = dom.active
     N, M = dom.N, _M(dom)
@@ -239,6 +261,9 @@ def step(dom, st, dt, log=None, force=None):
         if p["hybrid"] == HYBRID_ADAPTIVE and dg_e.size:
             ratio = tci_ratio(cand[0][:, dg_e], geo_take(dom.geo_dg, dg_e), N, M, p["tci_mode"])
             hit = ratio > thr
+            if replay is not None:
+                hit = _replay(hit, ratio, thr, np.asarray(replay)[k][dg_e] == FD, replay_tol, replay_events,
+                              ("substep", k), dg_e)
             if force is not None:
                 hit = hit | np.asarray(force, bool)[k - 1][dg_e]
             bad = dg_e[hit]
@@ -275,6 +300,9 @@ def step(dom, st, dt, log=None, force=None):
             rec = reconstruct_fd_to_dg(out.fd[:, fd_e], N)
             ratio = tci_ratio(rec, geo_take(dom.geo_dg, fd_e), N, M, p["tci_mode"])
             ok = ratio <= thr_fd
+            if replay is not None:
+                ok = ~_replay(~ok, ratio, thr_fd, np.asarray(replay)[4][fd_e] == FD, replay_tol, replay_events,
+                              ("fd_check",), fd_e)
             if log is not None:
                 log.append(("fd_check", fd_e.copy(), ratio.copy(), thr_fd))
             back = fd_e[ok]
@@ -283,17 +311,24 @@ def step(dom, st, dt, log=None, force=None):
     return out
 
 
-def initial_state(dom, u_fd, forced=None):
+def initial_state(dom, u_fd, forced=None, replay=None, replay_tol=1e-10, replay_events=None):
     """Sec. III C 1: data given on the FD grid is reconstructed to DG; the indicator
     (alpha + 1) decides which elements start on DG.  ``forced`` (bool, E) pins
-    elements to FD in the forced-partition mode."""
+    elements to FD in the forced-partition mode.  ``replay`` (nullable, integer E):
+    the other implementation's start-up representation, taken for ratios within
+    ``replay_tol`` of the threshold (see step)."""
     p = dom.params
     N, M = dom.N, _M(dom)
     dg = reconstruct_fd_to_dg(u_fd, N)
     rep = np.full(dom.E, DG, np.int64)
     if p["hybrid"] == HYBRID_ADAPTIVE:
         ratio = tci_ratio(dg, dom.geo_dg, N, M, p["tci_mode"])
-        rep[ratio > tci_threshold(N, M, p["tci_alpha_fd"])] = FD
+        thr_fd = tci_threshold(N, M, p["tci_alpha_fd"])
+        hit = ratio > thr_fd
+        if replay is not None:
+            hit = _replay(hit, ratio, thr_fd, np.asarray(replay) == FD, replay_tol, replay_events, ("start",),
+                          np.arange(dom.E))
+        rep[hit] = FD
     elif p["hybrid"] == HYBRID_FORCED and forced is not None:
         rep[np.asarray(forced, bool)] = FD
     rep[~dom.active] = DG

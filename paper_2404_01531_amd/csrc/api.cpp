@@ -704,21 +704,29 @@ extern "C" int grffe_rhs(grffe_domain* d, const double* dg, const double* fd, co
   return GRFFE_OK;
 }
 
-// One IMEX-SSP3(4,3,3) step of every element of the domain (or pool).
-static void step_once(grffe_domain* d, KArgs& a, hipStream_t st) {
+// One IMEX-SSP3(4,3,3) step of every element of the domain (or pool).  rep_log
+// (nullable, device [5][E]) receives the representation before the step, after each
+// substep and after the step.
+static int step_once(grffe_domain* d, KArgs& a, hipStream_t st, int32_t* rep_log = nullptr) {
   d->timing_now = d->timing_period <= 1 || (d->timing_step++ % d->timing_period) == 0;
+  const size_t row = sizeof(int32_t) * d->E;
+  if (rep_log) HIPCHK(hipMemcpyAsync(rep_log, d->rep, row, hipMemcpyDeviceToDevice, st));
   {
     TimedLaunch t(d, 9, st);
     launch_dg_prestage(a, d->N, d->curved, st);
   }
-  run_substep(d, a, MODE_SUB1, st);
-  run_substep(d, a, MODE_SUB2, st);
-  run_substep(d, a, MODE_SUB3, st);
+  const int modes[3] = {MODE_SUB1, MODE_SUB2, MODE_SUB3};
+  for (int k = 0; k < 3; ++k) {
+    run_substep(d, a, modes[k], st);
+    if (rep_log) HIPCHK(hipMemcpyAsync(rep_log + (size_t)(k + 1) * d->E, d->rep, row, hipMemcpyDeviceToDevice, st));
+  }
   if (a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
     TimedLaunch t(d, 8, st);
     launch_fd_to_dg(a, d->N, d->curved, 0, st);
   }
+  if (rep_log) HIPCHK(hipMemcpyAsync(rep_log + (size_t)4 * d->E, d->rep, row, hipMemcpyDeviceToDevice, st));
   d->timing_now = true;
+  return GRFFE_OK;
 }
 
 extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream) {
@@ -727,7 +735,19 @@ extern "C" int grffe_step(grffe_domain* d, int n_steps, double dt, void* stream)
   hipStream_t st = S(stream);
   KArgs a = make_args(d);
   if (dt > 0.0) a.dt = dt;
-  for (int it = 0; it < n_steps; ++it) step_once(d, a, st);
+  for (int it = 0; it < n_steps; ++it)
+    if (int rc = step_once(d, a, st)) return rc;
+  HIPCHK(hipGetLastError());
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_step_logged(grffe_domain* d, double dt, int32_t* rep_log, void* stream) {
+  if (int rc = check_ready(d)) return rc;
+  if (!rep_log) return fail(GRFFE_EINVAL, "rep_log must not be NULL");
+  hipStream_t st = S(stream);
+  KArgs a = make_args(d);
+  if (dt > 0.0) a.dt = dt;
+  if (int rc = step_once(d, a, st, rep_log)) return rc;
   HIPCHK(hipGetLastError());
   return GRFFE_OK;
 }
@@ -1341,7 +1361,7 @@ static int batch_step_once(grffe_batch* b, hipStream_t st) {
     grffe_domain* d = b->pools[pi];
     hipStream_t s = pi == 0 ? st : b->side[pi - 1];
     KArgs a = make_args(d);
-    step_once(d, a, s);
+    if (int rc = step_once(d, a, s)) return rc;
     HIPCHK(hipGetLastError());
   }
   if (np > 1)

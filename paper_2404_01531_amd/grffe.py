@@ -118,6 +118,7 @@ def lib():
     L.grffe_batch_get_counts.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.grffe_batch_step.argtypes = [vp, i32, i32, vp]
     L.grffe_batch_set_contraction.argtypes = [vp, i32, i32]
+    L.grffe_step_logged.argtypes = [vp, dbl, vp, vp]
     L.grffe_batch_get_contraction.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.grffe_last_error.restype = ctypes.c_char_p
     for name in ("grffe_init_domain", "grffe_destroy", "grffe_init_from_fd", "grffe_set_state", "grffe_get_state",
@@ -129,7 +130,7 @@ def lib():
                  "grffe_step_adjoint", "grffe_step_adjoint_frozen", "grffe_get_stages",
                  "grffe_step_adjoint_stages", "grffe_set_boundary_state", "grffe_set_boundary_field",
                  "grffe_check_finite", "grffe_set_conductor", "grffe_batch_set_contraction",
-                 "grffe_batch_get_contraction"):
+                 "grffe_batch_get_contraction", "grffe_step_logged"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -327,6 +328,14 @@ class Domain:
 
     def step(self, n_steps=1, dt=0.0):
         _check(lib().grffe_step(self._h, int(n_steps), float(dt), _stream()))
+
+    def step_logged(self, dt=0.0):
+        """One step with its decision log (see grffe_step_logged): int32 (5, E) device
+        tensor, the representation before the step, after substeps 1-3, after it."""
+        import torch
+        log = torch.empty((5, self.E), dtype=torch.int32, device="cuda")
+        _check(lib().grffe_step_logged(self._h, float(dt), _ptr(log), _stream()))
+        return log
 
     def rhs_adjoint(self, dg, fd, rep, lam_dg, lam_fd, parts=PART_ALL):
         """(ubar_dg, ubar_fd) = (dRHS/du)^T (lam_dg, lam_fd) for a state of DG and FD
