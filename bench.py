@@ -80,24 +80,32 @@ def parse():
     ap.add_argument("--rotator", action="store_true",
                     help="only run the rotating-star spin-down sweep (inclinations 0, 30, 45, 60, 90 degrees, "
                          "two periods each, about 7 minutes) and fit L = L0 (k1 + k2 sin^2 theta)")
+    ap.add_argument("--rotator-frame", choices=("inertial", "rotating"), default="inertial",
+                    help="grid at rest or rotating with the star (the rotating frame's shift; its CFL step is "
+                         "smaller by the shift's speed at the box corners)")
+    ap.add_argument("--rotator-angles", default="0,30,45,60,90", help="inclinations in degrees")
+    ap.add_argument("--rotator-periods", type=float, default=2.0)
     return ap.parse_args()
 
 
-def rotator_sweep():
+def rotator_sweep(frame="inertial", degrees=(0.0, 30.0, 45.0, 60.0, 90.0), periods=2.0):
     """Spin-down luminosity against inclination (Sec. IV C, oblique rotator): one JSON
-    line per angle, then the least-squares fit of L / L(0) = k1 + k2 sin^2 theta."""
+    line per angle, then the least-squares fit of L / L(0) = k1 + k2 sin^2 theta
+    (when the first angle is 0 and there are three or more)."""
     import math
 
     import numpy as np
     L = []
-    angles = (0.0, math.pi / 6, math.pi / 4, math.pi / 3, math.pi / 2)
+    angles = [math.radians(a) for a in degrees]
     for th in angles:
-        r = run_rotator(th)
+        r = run_rotator(th, periods=periods, frame=frame)
         print(json.dumps(r), flush=True)
         L.append(r["luminosity"])
-    s2 = np.sin(np.asarray(angles)) ** 2
-    k2, k1 = np.polyfit(s2, np.asarray(L) / L[0], 1)
-    print(json.dumps({"fit": "L/L(0) = k1 + k2 sin^2 theta", "k1": float(k1), "k2": float(k2)}), flush=True)
+    if len(angles) >= 3 and angles[0] == 0.0:
+        s2 = np.sin(np.asarray(angles)) ** 2
+        k2, k1 = np.polyfit(s2, np.asarray(L) / L[0], 1)
+        print(json.dumps({"fit": "L/L(0) = k1 + k2 sin^2 theta", "frame": frame, "k1": float(k1), "k2": float(k2)}),
+              flush=True)
 
 
 def copy_probe():
@@ -366,14 +374,17 @@ def kerr_schild_parity(precision, floor):
             "representation_mismatches": mism, "group_scale_floor": floor, "max": mx, "l2": l2}
 
 
-def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, samples=8):
+def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, samples=8, frame="inertial"):
     """Rotating magnetised star (Sec. IV C): the regularised dipole of inclination
     theta inside a perfect conductor of radius R = 1 rotating at Omega = 0.2 about z,
     flat space, [-half_width, half_width]^3 with n_elem^3 P5 elements (one element per
     R at the defaults), no-incoming-Poynting faces, eta = 1e5, CFL 0.25, adaptive
     DG/FD.  After `periods` rotation periods the Poynting luminosity through the
     sphere r = r_measure (Eq. of the spin-down luminosity; FD elements taken through
-    R to their DG polynomial) is averaged over the last tenth of a period."""
+    R to their DG polynomial) is averaged over the last tenth of a period.
+    frame = "rotating": the grid rotates with the star (flat space with the rotating
+    frame's shift, the conductor at rest on the grid); its normal observers are the
+    inertial ones, so E, B and the luminosity are measured the same way."""
     import math
 
     import numpy as np
@@ -382,11 +393,17 @@ def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, s
     from paper_2404_01531_amd import grffe
     from paper_2404_01531_amd import inputs as I
     from paper_2404_01531_amd.poynting import SphereFlux
-    w = I.workload("rotator", n_elem=(n_elem,) * 3, lower=(-half_width,) * 3, upper=(half_width,) * 3, theta=theta)
+    w = I.workload("rotator", n_elem=(n_elem,) * 3, lower=(-half_width,) * 3, upper=(half_width,) * 3, theta=theta,
+                   frame=frame)
     N = w["degree"]
     p = grffe.default_params(eta=w["eta"], cfl=w["cfl"])
-    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p)
-    dom.set_conductor(w["centre"], w["radius"], w["omega"])
+    bg = None
+    if frame == "rotating":
+        bg = I.background(w, *_dg_nodes(w)).reshape(26, int(np.prod(w["n_elem"])), -1)
+        bg = torch.from_numpy(np.ascontiguousarray(bg)).cuda()
+    dom = grffe.Domain(w["n_elem"], w["lower"], w["upper"], N, w["bc"], params=p, bg=bg)
+    del bg
+    dom.set_conductor(w["centre"], w["radius"], 0.0 if frame == "rotating" else w["omega"])
     xf, yf, zf = I.fd_points(w["n_elem"], w["lower"], w["upper"], N)
     E = int(np.prod(w["n_elem"]))
     dom.init_from_fd(torch.from_numpy(np.ascontiguousarray(I.initial_data(w, xf, yf, zf).reshape(9, E, -1))).cuda())
@@ -406,7 +423,13 @@ def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, s
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    dom.step(total - tail, dt)
+    done = 0
+    while done < total - tail:
+        k = min(1000, total - tail - done)
+        dom.step(k, dt)
+        done += k
+        torch.cuda.synchronize()
+        print(f"# rotator theta {theta:.3f} ({frame} frame): step {done} of {total}", file=sys.stderr, flush=True)
     Ls = []
     chunk = max(1, tail // samples)
     done = total - tail
@@ -431,7 +454,7 @@ def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, s
     sheet = (np.abs(cz) < 1.5 * h) & (rho > 1.2 * lc) & (rho < 2.0 * lc)
     polar = (np.abs(cz) > 1.2 * lc) & (np.abs(cz) < 2.0 * lc) & (rho < 0.6 * lc)
     L0 = 4.0 * math.pi * w["mu"] ** 2 * w["omega"] ** 4
-    return {"theta": theta, "steps": total, "dt": dt, "t": total * dt, "seconds": secs,
+    return {"theta": theta, "frame": frame, "steps": total, "dt": dt, "t": total * dt, "seconds": secs,
             "luminosity": float(np.mean(Ls)), "luminosity_spread": float(np.ptp(Ls)),
             "luminosity_over_4pi_mu2_omega4": float(np.mean(Ls)) / L0, "elements_dg_fd": [int(n_dg), int(n_fd)],
             "fd_fraction_equatorial_band": float(on_fd[sheet].mean()), "fd_fraction_polar": float(on_fd[polar].mean()),
@@ -957,7 +980,8 @@ def main():
         copy_probe()
         return
     if args.rotator:
-        rotator_sweep()
+        rotator_sweep(args.rotator_frame, tuple(float(a) for a in args.rotator_angles.split(",")),
+                      args.rotator_periods)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "

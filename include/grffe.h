@@ -152,18 +152,22 @@ int grffe_set_boundary_state(grffe_domain* dom, const double* state, void* strea
  * GRFFE_EHIP. */
 int grffe_set_boundary_field(grffe_domain* dom, const double* ext_dg, const double* ext_fd, void* stream);
 
-/* Rotating perfect conductor (Sec. IV C, the pulsar magnetospheres; flat space
- * only): after the update of every substep of grffe_step, at each DG node or FD
- * cell centre x of the substep's result with |x - centre| <= radius, E~ is set to
- * the value the ideal condition E + v x B = 0 gives for the rigid rotation
- * v = omega z^ x (x - centre) (rotation about the z axis through centre), and
- * psi~ and q~ are set to zero; B~ and phi~ are evolved as everywhere else.  The
- * pre-stages U_1, U_2 and grffe_rhs are not affected; the indicator, which reads
- * |B~| only, sees the same values either way.  centre is a host array of 3
- * doubles; radius <= 0 switches the conductor off.  The call copies what it needs
- * (synchronises the stream).  Returns GRFFE_EUNSUPPORTED for curved domains and
- * batch pools, GRFFE_EINVAL for a NULL centre or non-finite values; the adjoint
- * entry points refuse a domain with the conductor on. */
+/* Rotating perfect conductor (Sec. IV C, the pulsar magnetospheres): after the
+ * update of every substep of grffe_step, at each DG node or FD cell centre x of
+ * the substep's result with |x - centre| <= radius, E~ is set to the value the
+ * ideal condition E + v x B = 0 gives for the conductor's rigid rotation about the
+ * z axis through centre, and psi~ and q~ are set to zero; B~ and phi~ are evolved
+ * as everywhere else.  omega is the rotation relative to the grid: in flat space
+ * with the grid at rest v = omega z^ x (x - centre); on a background (e.g. the
+ * rotating frame of the star, shift beta = Omega z^ x x, where omega = 0 keeps the
+ * star at rest on the grid) v = (omega z^ x (x - centre) + beta) / alpha, and
+ * E_i = -[ijk] v^j B~^k, E~^i = sqrt(gamma) gamma^{ij} E_j.  The pre-stages U_1,
+ * U_2 and grffe_rhs are not affected; the indicator, which reads |B~| only, sees
+ * the same values either way.  centre is a host array of 3 doubles; radius <= 0
+ * switches the conductor off.  The call copies what it needs (synchronises the
+ * stream).  Returns GRFFE_EUNSUPPORTED for batch pools, GRFFE_EINVAL for a NULL
+ * centre or non-finite values; the adjoint entry points refuse a domain with the
+ * conductor on. */
 int grffe_set_conductor(grffe_domain* dom, const double* centre, double radius, double omega, void* stream);
 
 int grffe_destroy(grffe_domain* dom);

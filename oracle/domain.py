@@ -57,11 +57,10 @@ class Domain:
         if any(b == BC_DIRICHLET for b in self.bc) and self.boundary_state is None and self.boundary_field is None:
             raise ValueError("Dirichlet faces need boundary_state (6, 9) or boundary_field")
         # rotating perfect conductor (Sec. IV C): dict(centre=(3,), radius=R, omega=W),
-        # rotation about the z axis through the centre; flat space only
+        # rotation about the z axis through the centre at W relative to the grid (on
+        # a background, e.g. the rotating frame, the shift adds to that motion)
         self.conductor = None
         if conductor is not None:
-            if bg is not None:
-                raise ValueError("the rotating conductor is defined in flat space")
             self.conductor = dict(centre=np.asarray(conductor["centre"], np.float64),
                                   radius=float(conductor["radius"]), omega=float(conductor["omega"]))
         self._build_neighbours()

@@ -197,21 +197,37 @@ def constraint_clamp(U, geo, margin):
     return U
 
 
-def corotating_conductor(U, x, y, z, centre, radius, omega):
-    """Rotating perfect conductor (Sec. IV C, pulsar magnetospheres; flat space): at
-    every point with |x - centre| <= radius, E is replaced by the value the ideal
-    condition E^i + eps^{ijk} v_j B_k = 0 gives for the rigid rotation about the
-    z axis through the centre, v = omega z^ x (x - centre) = omega (-(y - c_y),
-    x - c_x, 0), i.e. E = -(v x B); psi~ and q~ are set to zero there.  B and phi~
-    are left to the evolution.  Points outside are returned unchanged."""
+def corotating_conductor(U, x, y, z, centre, radius, omega, geo=None):
+    """Rotating perfect conductor (Sec. IV C, pulsar magnetospheres): at every point
+    with |x - centre| <= radius, E is replaced by the value the ideal condition
+    E + v x B = 0 gives for the conductor's rigid rotation, and psi~ and q~ are set
+    to zero there.  B and phi~ are left to the evolution.  Points outside are
+    returned unchanged.
+
+    Flat space, grid at rest (geo None): v = omega z^ x (x - centre) =
+    omega (-(y - c_y), x - c_x, 0), E = -(v x B).
+
+    With a 3+1 background geo (e.g. flat space in coordinates that rotate with the
+    star, whose shift is beta = Omega z^ x x): the conductor moves through the grid
+    with coordinate velocity omega z^ x (x - centre) (omega its rotation relative to
+    the grid, 0 for a grid that rotates with it), so its velocity relative to the
+    normal observers is v^i = (omega (z^ x (x - centre))^i + beta^i) / alpha; the
+    condition E_i = -eps_ijk v^j B^k with eps_ijk = sqrt(gamma) [ijk] and
+    B^k = B~^k / sqrt(gamma) gives E_i = -[ijk] v^j B~^k, and E~^i =
+    sqrt(gamma) gamma^{ij} E_j."""
     U = U.copy()
     rx, ry, rz = x - centre[0], y - centre[1], z - centre[2]
     inside = rx * rx + ry * ry + rz * rz <= radius * radius
     v = np.array([-omega * ry, omega * rx, np.zeros_like(rx)])
     B = U[3:6]
-    vxB = np.einsum("ijk,j...,k...->i...", LEVI, v, B)
+    if geo is None:
+        Et = -np.einsum("ijk,j...,k...->i...", LEVI, v, B)
+    else:
+        v = (v + geo.beta) / geo.alpha
+        El = -np.einsum("ijk,j...,k...->i...", LEVI, v, B)
+        Et = geo.sqrtg * np.einsum("ij...,j...->i...", geo.ginv, El)
     for i in range(3):
-        U[i] = np.where(inside, -vxB[i], U[i])
+        U[i] = np.where(inside, Et[i], U[i])
     U[6] = np.where(inside, 0.0, U[6])
     U[8] = np.where(inside, 0.0, U[8])
     return U

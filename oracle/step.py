@@ -170,7 +170,8 @@ def _post(dom, C, geo, el, fd):
     if dom.conductor is not None:
         c = dom.conductor
         x, y, z = dom.point_coords(el, fd)
-        C = ph.corotating_conductor(C, x, y, z, c["centre"], c["radius"], c["omega"])
+        C = ph.corotating_conductor(C, x, y, z, c["centre"], c["radius"], c["omega"],
+                                    geo if dom.bg is not None else None)
     return C
 
 

@@ -458,7 +458,6 @@ extern "C" int grffe_set_conductor(grffe_domain* d, const double* centre, double
                                    void* stream) {
   if (int rc = check_dom(d)) return rc;
   if (d->parts.size() != 1) return fail(GRFFE_EUNSUPPORTED, "the conductor is set on single domains");
-  if (d->curved) return fail(GRFFE_EUNSUPPORTED, "the rotating conductor is defined in flat space");
   if (!std::isfinite(radius) || !std::isfinite(omega)) return fail(GRFFE_EINVAL, "radius and omega must be finite");
   if (radius <= 0.0) {
     d->cond_count = 0;
@@ -616,7 +615,7 @@ struct TimedLaunch {
 };
 
 namespace grffe {
-void launch_conductor(const KArgs& a, int N, const CondArgs& c, int mode, hipStream_t s);
+void launch_conductor(const KArgs& a, int N, bool curved, const CondArgs& c, int mode, hipStream_t s);
 }  // namespace grffe
 
 // One substep (or a pure right-hand side evaluation when mode == MODE_RHS).
@@ -644,7 +643,7 @@ static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   if (mode != MODE_RHS && d->cond_count > 0) {
     const CondArgs c{d->cond_list, d->cond_corner, d->cond_ref, d->cond_count,
                      d->cond_c[0], d->cond_c[1], d->cond_c[2], d->cond_r * d->cond_r, d->cond_omega};
-    launch_conductor(a, N, c, mode, st);
+    launch_conductor(a, N, cv, c, mode, st);
   }
 }
 

@@ -1,18 +1,23 @@
-// Rotating perfect conductor (Sec. IV C, pulsar magnetospheres; flat space).
+// Rotating perfect conductor (Sec. IV C, pulsar magnetospheres).
 //
 // After the update of every substep, at each DG node or FD cell centre of the
 // substep's result that lies inside the conductor's sphere |x - c| <= R, the
 // electric field is replaced by the value the ideal condition E + v x B = 0 gives
-// for the rigid rotation v = Omega z^ x (x - c), and psi~ and q~ are set to zero;
-// B~ and phi~ keep their evolved values.  The indicator of the DG substep has
-// already looked at the candidate by then, but it reads only |B~|, which the
-// overwrite leaves alone.  The FD elements of substeps 1 and 2 also get their
-// next-substep transported values (U and J~) rewritten at those cells.
+// for the conductor's rigid rotation, and psi~ and q~ are set to zero; B~ and phi~
+// keep their evolved values.  Flat space with the grid at rest: v = Omega z^ x
+// (x - c).  On a 3+1 background (the frame that rotates with the star, whose shift
+// is beta = Omega_frame z^ x x): the conductor's coordinate velocity is
+// Omega z^ x (x - c) (Omega relative to the grid, 0 when the grid rotates with it),
+// its velocity relative to the normal observers v = (Omega z^ x (x - c) + beta) /
+// alpha, and E_i = -[ijk] v^j B~^k, E~^i = sqrt(gamma) gamma^{ij} E_j.  The indicator
+// of the DG substep has already looked at the candidate by then, but it reads only
+// |B~|, which the overwrite leaves alone.  The FD elements of substeps 1 and 2 also
+// get their next-substep transported values (U and J~) rewritten at those cells.
 #include "common.h"
 
 namespace grffe {
 
-template <int N>
+template <int N, bool CURVED>
 __global__ __launch_bounds__(256) void k_conductor(KArgs a, CondArgs c, int mode) {
   constexpr int n = N + 1, m = 2 * N + 1;
   constexpr int nn = n * n * n, mm = m * m * m;
@@ -40,16 +45,28 @@ __global__ __launch_bounds__(256) void k_conductor(KArgs a, CondArgs c, int mode
     double* out = mode == MODE_SUB1 ? R.X0 : (mode == MODE_SUB2 ? R.X1 : R.Un);
     double U[NV];
     load9(out, a.E, P, e, p, U);
-    const double vx = -c.omega * r[1], vy = c.omega * r[0];  // v_z = 0
-    U[0] = -(vy * U[5]);
-    U[1] = vx * U[5];
-    U[2] = -(vx * U[4] - vy * U[3]);
+    Metric M;
+    if (CURVED) load_metric<true>(fd ? a.bg_fd : a.bg_dg, a.E, P, e, p, M);
+    else metric_flat(M);
+    double vx = -c.omega * r[1], vy = c.omega * r[0], vz = 0.0;
+    if (CURVED) {
+      vx = (vx + M.beta[0]) / M.alpha;
+      vy = (vy + M.beta[1]) / M.alpha;
+      vz = (vz + M.beta[2]) / M.alpha;
+      // E_i = -[ijk] v^j B~^k, raised and densitized
+      const double El[3] = {-(vy * U[5] - vz * U[4]), -(vz * U[3] - vx * U[5]), -(vx * U[4] - vy * U[3])};
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        U[i] = M.sqrtg * (M.gi[sym(i, 0)] * El[0] + M.gi[sym(i, 1)] * El[1] + M.gi[sym(i, 2)] * El[2]);
+    } else {
+      U[0] = -(vy * U[5]);
+      U[1] = vx * U[5];
+      U[2] = -(vx * U[4] - vy * U[3]);
+    }
     U[6] = 0.0;
     U[8] = 0.0;
     store9(out, a.E, P, e, p, U);
     if (fd && mode != MODE_SUB3) {
-      Metric M;
-      metric_flat(M);
       double J[3];
       current_total(U, M, a.eta, J);
       const size_t st = (size_t)a.E * mm;
@@ -62,12 +79,13 @@ __global__ __launch_bounds__(256) void k_conductor(KArgs a, CondArgs c, int mode
   }
 }
 
-void launch_conductor(const KArgs& a, int N, const CondArgs& c, int mode, hipStream_t s) {
+void launch_conductor(const KArgs& a, int N, bool curved, const CondArgs& c, int mode, hipStream_t s) {
   if (c.count <= 0) return;
   GRFFE_SWITCH_N({
     constexpr int m = 2 * NN + 1;
     const int items = c.count * ((m * m * m + 255) / 256);
-    launch_kernel(k_conductor<NN>, dim3(items), dim3(256), s, a, c, mode);
+    if (curved) launch_kernel(k_conductor<NN, true>, dim3(items), dim3(256), s, a, c, mode);
+    else launch_kernel(k_conductor<NN, false>, dim3(items), dim3(256), s, a, c, mode);
   })
 }
 

@@ -174,6 +174,25 @@ def flat_background(shape):
     return bg
 
 
+def rotating_frame_background(x, y, z, omega, centre=(0.0, 0.0, 0.0)):
+    """The 26 background fields of flat space in Cartesian coordinates that rotate
+    at omega about the z axis through `centre` (the rotating grid of the pulsar
+    runs, Sec. IV C): with phi' = phi - omega t the line element is
+    -dt^2 + dr^2 + r^2 (dphi' + omega dt)^2 + dz^2, so alpha = 1, gamma_ij = delta_ij
+    and the shift is beta = omega z^ x (x - centre) = omega (-(y - c_y), x - c_x, 0);
+    d_y beta^x = -omega, d_x beta^y = omega, the lapse is constant, and K = 0 (a
+    rigid rotation is a Killing motion)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    z = np.asarray(z, np.float64)
+    bg = flat_background(np.broadcast(x, y, z).shape)
+    bg[1] = -omega * (y - centre[1])
+    bg[2] = omega * (x - centre[0])
+    bg[13 + 3 * 1 + 0] = -omega  # d_y beta^x
+    bg[13 + 3 * 0 + 1] = omega   # d_x beta^y
+    return bg
+
+
 # ----------------------------------------------------------------------------
 # initial data (all returned as densitized evolved variables, shape (9, ...))
 
@@ -559,7 +578,11 @@ def initial_data(w, x, y, z, with_noise=True):
 
 
 def background(w, x, y, z):
-    """Background fields (26, ...) of workload ``w`` at given points (None when flat)."""
+    """Background fields (26, ...) of workload ``w`` at given points (None when flat
+    in coordinates at rest); the rotator with frame = "rotating" runs in the frame
+    that rotates with the star."""
+    if w.get("kind") == "rotator" and w.get("frame") == "rotating":
+        return rotating_frame_background(x, y, z, w["omega"], w.get("centre", (0.0, 0.0, 0.0)))
     if not w.get("curved"):
         return None
     return kerr_schild_background(x, y, z, w.get("M", 1.0), w.get("spin", 0.0))

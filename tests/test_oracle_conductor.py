@@ -116,3 +116,63 @@ def test_rotating_dipole_field_is_ideal_inside():
     assert np.abs((E * B).sum(0)).max() < 1e-12 * scale
     assert np.abs((E * v).sum(0)).max() < 1e-12 * scale
     assert np.sqrt((E * E).sum(0)).max() > 0.01
+
+
+# ------------------------------------------------------------------ rotating frame
+
+
+def _rotating_domain(N, omega, params=None, conductor=None):
+    from oracle import operators as ops
+    ne, lo, hi = (4, 4, 2), (-2.0, -2.0, -1.0), (2.0, 2.0, 1.0)
+    x, y, z = I.points(ne, lo, hi, ops.gll(N)[0])
+    bg = I.rotating_frame_background(x, y, z, omega)
+    return Domain(ne, lo, hi, N, (0,) * 6, bg=bg, params=params or dict(eta=0.0), conductor=conductor)
+
+
+def test_uniform_field_rotates_backwards_in_the_rotating_frame():
+    """Sec. IV C's rotating grid: in coordinates rotating at Omega the normal observers
+    are the inertial ones, so a field that is uniform and static in the inertial frame
+    (E = 0, B uniform) keeps E = 0 and appears to turn at -Omega: dB/dt = -Omega z^ x B
+    exactly (the right-hand side of the scheme with the rotating frame's shift,
+    every flux divergence of uniform data vanishing), on DG nodes and on FD cells."""
+    from oracle import rhs as R
+    omega = 0.3
+    for N in (3, 5):
+        dom = _rotating_domain(N, omega)
+        Bv = np.array([0.4, -0.7, 1.1])
+        dg = np.zeros((9, dom.E, dom.n, dom.n, dom.n))
+        fd = np.zeros((9, dom.E, dom.m, dom.m, dom.m))
+        for i in range(3):
+            dg[3 + i] = Bv[i]
+            fd[3 + i] = Bv[i]
+        rep = (np.arange(dom.E) % 2).astype(np.int64)  # DG and FD elements side by side
+        ddg, dfd = R.rhs(dom, dg, fd, rep)
+        want = np.array([omega * Bv[1], -omega * Bv[0], 0.0])
+        # rounding: the fluxes beta^d B^i (up to ~1.3) differentiated by operators of
+        # norm ~ N^2 / h leave ~1e-14
+        tol = 2e-13
+        for r, D in ((0, ddg), (1, dfd)):
+            el = np.nonzero(rep == r)[0]
+            assert np.abs(D[0:3, el]).max() < tol
+            for i in range(3):
+                assert np.abs(D[3 + i, el] - want[i]).max() < tol, (N, r, i)
+            assert np.abs(D[6:9, el]).max() < tol
+
+
+def test_conductor_at_rest_in_the_rotating_frame_is_the_corotating_one():
+    """The conductor at rest on the rotating grid (omega = 0 relative to it) is moved
+    by the frame's shift alone: its E equals the inertial frame's corotation field
+    -(Omega z^ x (x - c)) x B at the same points (with c on the axis)."""
+    from oracle import physics as ph
+    omega = 0.3
+    dom = _rotating_domain(3, omega)
+    rng = np.random.default_rng(12)
+    U = rng.standard_normal((9, dom.E, dom.n, dom.n, dom.n))
+    x, y, z = dom.point_coords(np.arange(dom.E), False)
+    centre = (0.0, 0.0, 0.1)
+    got = ph.corotating_conductor(U, x, y, z, centre, 1.5, 0.0, dom.geo_dg)
+    ref = ph.corotating_conductor(U, x, y, z, centre, 1.5, omega)
+    inside = x ** 2 + y ** 2 + (z - 0.1) ** 2 <= 1.5 ** 2
+    assert inside.sum() > 50
+    assert np.abs(got - ref).max() < 1e-14
+    assert np.array_equal(got[:, ~inside], U[:, ~inside])
