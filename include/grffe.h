@@ -231,14 +231,14 @@ int grffe_step_logged(grffe_domain* dom, double dt, int32_t* rep_log, void* stre
 
 /* Troubled-cell indicator, Eq. (persson tci), on |B~| = sqrt(gamma_ij B~^i B~^j):
  * DG elements (rep 0) are checked on dg with alpha, FD elements (rep 1) on the
- * sixth-order reconstruction of fd with alpha_fd.  troubled (device uint8 [E]);
+ * reconstruction of fd (the least-squares inverse of the projection) with alpha_fd.  troubled (device uint8 [E]);
  * ratio (device double [E], nullable) receives sqrt(sum u_hat^2 / sum u^2). */
 int grffe_tci(grffe_domain* dom, const double* dg, const double* fd, const int32_t* rep, uint8_t* troubled,
               double* ratio, void* stream);
 
 /* DG -> FD projection (evaluation of the nodal polynomial at the subcell
- * centres, Sec. III C 2) and FD -> DG sixth-order least-squares reconstruction
- * (Sec. III C 1) of the n listed elements.  Compact layouts: u_dg [9][n][n^3],
+ * centres, Sec. III C 2) and FD -> DG reconstruction, the least-squares inverse
+ * of that projection (degree N, Sec. III C 1) of the n listed elements.  Compact layouts: u_dg [9][n][n^3],
  * u_fd [9][n][m^3]; elems (device int32 [n]) only selects the element degree and
  * must hold valid element ids. */
 int grffe_project_dg_to_fd(grffe_domain* dom, const double* u_dg, double* u_fd, const int32_t* elems, int32_t n,

@@ -138,23 +138,22 @@ def face_eval_matrix(N):
     return lagrange_matrix(gll(N)[0], fd_faces(N))
 
 
-RECON_DEGREE = 5
-
-
 @lru_cache(maxsize=None)
 def reconstruction_matrix(N):
-    """FD -> DG: R[j, k], sixth-order least-squares reconstruction (Sec. III C 1).
+    """FD -> DG: R[j, k], the least-squares inverse of the projection (Sec. III C 1).
 
     The cell-centre values of one axis are fitted in the least-squares sense
-    by a polynomial of degree 5 (sixth order), using all 2N+1 cells, and the
-    fit is evaluated at the GLL nodes: R = V5(nodes) pinv(V5(centres)) with
-    V5 the Legendre Vandermonde matrix of degree 5.  R is exact on
-    polynomials of degree <= 5, so R P = I for N <= 5.
+    by a polynomial of degree N (the DG space), using all 2N+1 cells, and the
+    fit is evaluated at the GLL nodes: R = V(nodes) pinv(V(centres)) with V
+    the Legendre Vandermonde matrix of degree N, i.e. R = (P^T P)^-1 P^T.  R is
+    exact on polynomials of degree <= N, so R P = I.  (The exact-Wald table's
+    P7 and P9 errors come out only with the fit of degree N; a fit of degree 5
+    leaves them 1.7 and 66 times larger.)
     """
     x, _ = gll(N)
     xc = fd_centres(N)
-    Vc = np.stack([legendre(p, xc) for p in range(RECON_DEGREE + 1)], axis=1)
-    Vn = np.stack([legendre(p, x) for p in range(RECON_DEGREE + 1)], axis=1)
+    Vc = np.stack([legendre(p, xc) for p in range(N + 1)], axis=1)
+    Vn = np.stack([legendre(p, x) for p in range(N + 1)], axis=1)
     return Vn @ np.linalg.solve(Vc.T @ Vc, Vc.T)
 
 

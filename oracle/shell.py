@@ -1,0 +1,347 @@
+"""Spherical shell of cubed-sphere wedges with curved element maps; the DG
+right-hand side and the DG step on it.
+
+TEST INFRASTRUCTURE ONLY (see oracle/operators.py).
+
+Grid (Sec. IV B, the black-hole grid; Sec. III A, the map x(xi) of each element):
+the shell r_in <= r <= r_out is cut into six wedges, one about each of the
+directions +x, -x, +y, -y, +z, -z.  A wedge has coordinates (A, B, Z) in
+[-1, 1]^3 with the equiangular map along the two angular directions and the
+logarithmic map along the radial one,
+
+    X = tan(pi A / 4),  Y = tan(pi B / 4),  r = r_in (r_out / r_in)^((Z + 1) / 2),
+    local point  r (X, Y, 1) / sqrt(1 + X^2 + Y^2),
+
+and the local axes (1, 2, 3) are turned onto (s e_{k+1}, e_{k+2}, s e_k) for the
+wedge about s e_k (s = +-1, indices mod 3; a proper rotation).  Wedge w = 2 k +
+(0 for s = +1, 1 for s = -1) is cut into n_radial x n_angular x n_angular
+elements of equal extent in (A, B, Z); element e = w n_r n_a^2 + ir n_a^2 +
+ib n_a + ia, with its reference coordinates (xi^1, xi^2, xi^3) along (A, B, Z),
+node (i, j, k) along them, arrays over nodes with axes (..., k, j, i) as on the
+Cartesian grid.
+
+DG on curved elements (Sec. III A): nodal DG-SEM in strong form with a lumped
+GLL mass matrix.  The divergence of the flux is the logical derivative of every
+Cartesian flux component contracted with the inverse Jacobian at the node,
+
+    dU/dt = S - sum_{i, j} (d xi^i / d x^j) D_i F^j - sum_faces lift,
+
+the same placement of the inverse Jacobian as in the paper's FD time derivative
+(Eq. (fd time derivative)).  At a node of the face xi^i = +-1 with outward
+covector m = +-grad xi^i (the row i of the inverse Jacobian, unnormalised) the
+lift is (1 / w_end) (G*(m) - m_j F^j(U_int)), with the Rusanov flux along m
+
+    G*(m) = (m_j F^j(U_int) + m_j F^j(U_ext)) / 2 - lambda(m) (U_ext - U_int) / 2,
+    lambda(m) = alpha sqrt(gamma^{jk} m_j m_k) + |beta^j m_j|,
+
+the largest characteristic speed along m times |m| (both homogeneous of degree
+one in m, so no normalisation enters).  On an axis-aligned affine element this
+is the Cartesian operator term by term.  Neighbours across wedge faces have
+their own orientation; the exterior state of a face node is the neighbour's
+node at the same point, found by matching coordinates.
+
+Boundaries: the inner and outer spheres take one of: Dirichlet (a given
+exterior state at every face node), outflow (no boundary condition, the
+exterior state is the interior one, so the face adds nothing: the inner
+boundary of the exact-Wald test inside the horizon, Sec. IV B 1), or the
+no-incoming-Poynting state along the face normal (Sec. III D).
+
+Time step (Eq. (spectre DG CFL condition)): (dx)_min is the smallest distance
+between neighbouring DG nodes along a reference line, lambda_max the largest
+alpha + |beta|_gamma over the nodes (the largest characteristic speed over all
+directions); this reading gives the exact-Wald table's nine time steps.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import operators as ops
+from . import physics as ph
+from .domain import axis_of, default_params
+from .step import _candidate, _filter_fn, derived_stages
+
+SHELL_DIRICHLET = 2
+SHELL_NO_INCOMING_POYNTING = 1
+SHELL_OUTFLOW = 3
+
+
+def wedge_axes(w):
+    """Columns: the images of the wedge's local axes 1, 2, 3 (a rotation)."""
+    k, s = w // 2, (1.0 if w % 2 == 0 else -1.0)
+    R = np.zeros((3, 3))
+    R[(k + 1) % 3, 0] = s
+    R[(k + 2) % 3, 1] = 1.0
+    R[k, 2] = s
+    return R
+
+
+class Shell:
+    def __init__(self, degree, n_radial, n_angular, r_in, r_out, bc_inner=SHELL_OUTFLOW, bc_outer=SHELL_DIRICHLET,
+                 bg=None, params=None, boundary_field=None):
+        self.N = int(degree)
+        self.n = self.N + 1
+        self.m = 2 * self.N + 1
+        self.nr, self.na = int(n_radial), int(n_angular)
+        self.r_in, self.r_out = float(r_in), float(r_out)
+        self.bc_inner, self.bc_outer = int(bc_inner), int(bc_outer)
+        self.E = 6 * self.nr * self.na * self.na
+        self.params = default_params() if params is None else {**default_params(), **params}
+        self.x_dg = self.points(fd=False)
+        self.dxdxi = self.jacobian(fd=False)  # [a][i] = d x^a / d xi^i
+        jm = np.moveaxis(self.dxdxi, (0, 1), (-2, -1))
+        self.invJ = np.moveaxis(np.linalg.inv(jm), (-2, -1), (0, 1))  # [i][a] = d xi^i / d x^a
+        self.detJ = np.linalg.det(jm)
+        shape = (self.E, self.n, self.n, self.n)
+        self.bg = None if bg is None else np.asarray(bg, np.float64)
+        self.geo = ph.Geometry(self.bg, shape)
+        # exterior states of Dirichlet spheres at every face node (9, E, 6, n^2); may be
+        # set after construction (it is usually computed from the node coordinates)
+        self.boundary_field = None if boundary_field is None else np.asarray(boundary_field, np.float64)
+        self._connect()
+
+    # ------------------------------------------------------------------ map
+    def element_index(self, w, ir, ib, ia):
+        return ((w * self.nr + ir) * self.na + ib) * self.na + ia
+
+    def _wedge_coords(self, e, ref):
+        """Wedge coordinates (A, B, Z) of the reference points ref (1D) of element e,
+        each of shape (k, k, k) with axes (Z, B, A)."""
+        na, nr = self.na, self.nr
+        ia, ib = e % na, (e // na) % na
+        ir, w = (e // (na * na)) % nr, e // (na * na * nr)
+        A = -1.0 + (ia + 0.5 * (ref + 1.0)) * 2.0 / na
+        B = -1.0 + (ib + 0.5 * (ref + 1.0)) * 2.0 / na
+        Z = -1.0 + (ir + 0.5 * (ref + 1.0)) * 2.0 / nr
+        ZZ, BB, AA = np.meshgrid(Z, B, A, indexing="ij")
+        return w, AA, BB, ZZ
+
+    def _ref(self, fd):
+        return ops.fd_centres(self.N) if fd else ops.gll(self.N)[0]
+
+    def points(self, fd=False):
+        """Cartesian coordinates (3, E, k, k, k) of the DG nodes or FD cell centres."""
+        ref = self._ref(fd)
+        k = ref.size
+        out = np.empty((3, self.E, k, k, k))
+        for e in range(self.E):
+            w, A, B, Z = self._wedge_coords(e, ref)
+            X, Y = np.tan(0.25 * np.pi * A), np.tan(0.25 * np.pi * B)
+            r = self.r_in * (self.r_out / self.r_in) ** (0.5 * (Z + 1.0))
+            s = r / np.sqrt(1.0 + X * X + Y * Y)
+            local = np.stack([s * X, s * Y, s])
+            out[:, e] = np.einsum("al,l...->a...", wedge_axes(w), local)
+        return out
+
+    def jacobian(self, fd=False):
+        """d x^a / d xi^i (3, 3, E, k, k, k) in closed form (chain rule through X, Y, r)."""
+        ref = self._ref(fd)
+        k = ref.size
+        out = np.empty((3, 3, self.E, k, k, k))
+        for e in range(self.E):
+            w, A, B, Z = self._wedge_coords(e, ref)
+            X, Y = np.tan(0.25 * np.pi * A), np.tan(0.25 * np.pi * B)
+            r = self.r_in * (self.r_out / self.r_in) ** (0.5 * (Z + 1.0))
+            rho = np.sqrt(1.0 + X * X + Y * Y)
+            v = np.stack([X, Y, np.ones_like(X)])
+            dL_dX = r * (np.stack([np.ones_like(X), 0 * X, 0 * X]) / rho - X * v / rho ** 3)
+            dL_dY = r * (np.stack([0 * X, np.ones_like(X), 0 * X]) / rho - Y * v / rho ** 3)
+            dL_dr = v / rho
+            dX_dxi = 0.25 * np.pi * (1.0 + X * X) / self.na
+            dY_dxi = 0.25 * np.pi * (1.0 + Y * Y) / self.na
+            dr_dxi = 0.5 * r * np.log(self.r_out / self.r_in) / self.nr
+            local = np.stack([dL_dX * dX_dxi, dL_dY * dY_dxi, dL_dr * dr_dxi], axis=1)  # [l][i]
+            out[:, :, e] = np.einsum("al,li...->ai...", wedge_axes(w), local)
+        return out
+
+    # ---------------------------------------------------------- connectivity
+    def face_nodes(self, x, f):
+        """Values (..., E, n^2) of x (..., E, n, n, n) at the nodes of face f = 2 i + s,
+        node t1 + n t2 with t1 along the lower tangential reference axis."""
+        i, s = divmod(f, 2)
+        a = np.take(x, self.N if s else 0, axis=axis_of(i))
+        return a.reshape(a.shape[:-2] + (self.n * self.n,))
+
+    def _face_volume_index(self, f):
+        """Flat node index i + n (j + n k) of each node of face f, in face order."""
+        idx = np.arange(self.n ** 3).reshape(self.n, self.n, self.n)
+        return self.face_nodes(idx, f)
+
+    def _connect(self):
+        """nbr[e, f]: neighbour across face f (-1 on the inner sphere, -2 on the outer);
+        nbr_node[e, f, t]: flat node index, in the neighbour, of the point of face node t."""
+        E, n = self.E, self.n
+        self.nbr = np.full((E, 6), -1, np.int64)
+        self.nbr_node = np.full((E, 6, n * n), -1, np.int64)
+        fx = [np.moveaxis(self.face_nodes(self.x_dg, f), 0, -1) for f in range(6)]  # (E, n^2, 3)
+        scale = 1e-9 * self.r_out
+        table = {}
+        for e in range(E):
+            for f in range(6):
+                key = tuple(np.round(fx[f][e].mean(axis=0) / scale).astype(np.int64))
+                table.setdefault(key, []).append((e, f))
+        vidx = [self._face_volume_index(f) for f in range(6)]
+        for pair in table.values():
+            if len(pair) == 1:
+                e, f = pair[0]
+                if f not in (4, 5):
+                    raise RuntimeError("an angular face without a neighbour")
+                ir = (e // (self.na * self.na)) % self.nr
+                if (f == 4 and ir != 0) or (f == 5 and ir != self.nr - 1):
+                    raise RuntimeError("a radial face inside the shell without a neighbour")
+                self.nbr[e, f] = -1 if f == 4 else -2
+                continue
+            if len(pair) != 2:
+                raise RuntimeError("a face shared by more than two elements")
+            for (e, f), (o, fo) in (pair, pair[::-1]):
+                self.nbr[e, f] = o
+                d = np.linalg.norm(fx[f][e][:, None, :] - fx[fo][o][None, :, :], axis=-1)
+                t = np.argmin(d, axis=1)
+                if np.max(d[np.arange(n * n), t]) > scale or len(set(t.tolist())) != n * n:
+                    raise RuntimeError("face nodes of neighbours do not coincide")
+                self.nbr_node[e, f] = vidx[fo][t]
+
+    # -------------------------------------------------------------- geometry
+    def dx_min(self):
+        """Smallest distance between neighbouring DG nodes along a reference line."""
+        best = np.inf
+        for i in range(3):
+            dx = np.diff(self.x_dg, axis=axis_of(i))
+            best = min(best, float(np.sqrt((dx * dx).sum(axis=0)).min()))
+        return best
+
+    def lambda_max(self):
+        """max over nodes of alpha + |beta|_gamma."""
+        g = self.geo
+        return float((g.alpha + np.sqrt(ph.dot(g.beta, g.beta, g))).max())
+
+    def dt(self):
+        p = self.params
+        c = p["stab_c"] if p.get("stab_c") else ops.ssp_rk3_c()
+        return p["cfl"] * self.dx_min() / self.lambda_max() * c / 3.0
+
+    def volume(self):
+        """sum over nodes of w_i w_j w_k |det J|: the shell's volume up to quadrature error."""
+        _, w = ops.gll(self.N)
+        W = w[:, None, None] * w[None, :, None] * w[None, None, :]
+        return float((np.abs(self.detJ) * W[None]).sum())
+
+
+def _face_geo(sh, f):
+    """Geometry at the nodes of face f (point shape (E, n^2))."""
+    g = ph.Geometry.__new__(ph.Geometry)
+    for k, v in vars(sh.geo).items():
+        setattr(g, k, sh.face_nodes(v, f))
+    return g
+
+
+def char_speed_normal(geo, m):
+    """lambda(m) = alpha sqrt(gamma^{jk} m_j m_k) + |beta^j m_j| for a covector m."""
+    mm = np.einsum("ij...,i...,j...->...", geo.ginv, m, m)
+    return geo.alpha * np.sqrt(mm) + np.abs(np.einsum("i...,i...->...", geo.beta, m))
+
+
+def normal_flux(U, geo, J, m):
+    """m_j F^j(U)."""
+    return sum(m[j] * ph.flux(U, geo, j, J) for j in range(3))
+
+
+def boundary_state_normal(U, geo, m):
+    """No-incoming-Poynting state (Sec. III D) for the outward covector m: copy E~, B~,
+    q~, set psi~ = phi~ = 0, and E~ = 0 where m_i [ijk] E~_j B~_k < 0 (the Poynting
+    flux points into the domain)."""
+    Ub = U.copy()
+    Ub[6] = 0.0
+    Ub[7] = 0.0
+    El, Bl = ph.lower(U[0:3], geo), ph.lower(U[3:6], geo)
+    cross = np.einsum("ijk,j...,k...->i...", ph.LEVI, El, Bl)
+    inward = np.einsum("i...,i...->...", m, cross) < 0.0
+    Ub[0:3] = np.where(inward, 0.0, U[0:3])
+    return Ub
+
+
+def shell_rhs(sh, U, parts=3):
+    """Right-hand side (9, E, n, n, n) of the DG state U on the shell."""
+    p = sh.params
+    N, n = sh.N, sh.n
+    _, w = ops.gll(N)
+    D = ops.diff_matrix(N)
+    out = np.zeros_like(U)
+    if parts & 2:
+        out += ph.source_stiff(U, sh.geo, p["eta"], p["kappa_psi"], p["kappa_phi"])
+    if not parts & 1:
+        return out
+    jd, je = ph.split_current(U, sh.geo, p["eta"])
+    J = jd + je
+    out += ph.source_explicit(U, sh.geo, p["eta"])
+    F = [ph.flux(U, sh.geo, j, J) for j in range(3)]
+    for i in range(3):
+        for j in range(3):
+            out -= sh.invJ[i, j] * ops.apply_1d(D, F[j], axis_of(i))
+    Uflat = U.reshape(9, sh.E, n ** 3)
+    lift = np.zeros((6, 9, sh.E, n * n))
+    for f in range(6):
+        i, s = divmod(f, 2)
+        gf = _face_geo(sh, f)
+        Ui = sh.face_nodes(U, f)
+        Ji = sh.face_nodes(J, f)
+        mvec = (1.0 if s else -1.0) * sh.face_nodes(sh.invJ[i], f)  # (3, E, n^2)
+        Ue = np.empty_like(Ui)
+        inner = sh.nbr[:, f] >= 0
+        o = sh.nbr[inner, f]
+        Ue[:, inner] = Uflat[:, o[:, None], sh.nbr_node[inner, f]]
+        for code, bc in ((-1, sh.bc_inner), (-2, sh.bc_outer)):
+            sel = sh.nbr[:, f] == code
+            if not np.any(sel):
+                continue
+            if bc == SHELL_OUTFLOW:
+                Ue[:, sel] = Ui[:, sel]
+            elif bc == SHELL_DIRICHLET:
+                if sh.boundary_field is None:
+                    raise ValueError("Dirichlet spheres need boundary_field (9, E, 6, n^2)")
+                Ue[:, sel] = sh.boundary_field[:, sel, f]
+            else:
+                gsel = ph.Geometry.__new__(ph.Geometry)
+                for k, v in vars(gf).items():
+                    setattr(gsel, k, v[..., sel, :])
+                Ue[:, sel] = boundary_state_normal(Ui[:, sel], gsel, mvec[:, sel])
+        jde, jee = ph.split_current(Ue, gf, p["eta"])
+        Fi = normal_flux(Ui, gf, Ji, mvec)
+        Fe = normal_flux(Ue, gf, jde + jee, mvec)
+        lam = char_speed_normal(gf, mvec)
+        G = 0.5 * (Fi + Fe) - 0.5 * lam * (Ue - Ui)
+        lift[f] = (G - Fi) / w[N if s else 0]
+    for f in range(6):
+        i, s = divmod(f, 2)
+        ax = axis_of(i)
+        sl = [slice(None)] * 5
+        sl[ax] = N if s else 0
+        out[tuple(sl)] -= lift[f].reshape(9, sh.E, n, n)
+    return out
+
+
+def shell_step(sh, Un, dt):
+    """One IMEX-SSP3(4,3,3) step of the all-DG shell: the implicit pre-stages, then the
+    three substeps with the filtered explicit update (the stage algebra of the
+    Cartesian oracle's step, with every element on DG)."""
+    geo = sh.geo
+    _, U2, _, _ = derived_stages(sh, Un, geo, dt)
+    filt = _filter_fn(sh)
+    H = {"Un": Un}
+    X = U2
+    for k in (1, 2, 3):
+        Lk = shell_rhs(sh, X, parts=1)
+        X, upd = _candidate(sh, k, H, X, Lk, geo, dt, filt)
+        H.update(upd)
+    return X
+
+
+def initial_dg(sh, u_fd):
+    """DG nodal data from FD cell-centre data (the start-up of Sec. III C 1, every
+    element kept on DG): the reconstruction R (x) R (x) R."""
+    return ops.apply_3d(ops.reconstruction_matrix(sh.N), u_fd)
+
+
+def l2_error(a, b):
+    """sqrt(mean over nodes of |a - b|^2) over the three components given (Sec. IV B 1)."""
+    d = a - b
+    return float(np.sqrt((d * d).sum(axis=0).mean()))

@@ -48,5 +48,5 @@ def project_dg_to_fd(U_dg, N):
 
 
 def reconstruct_fd_to_dg(U_fd, N):
-    """Sec. III C 1: sixth-order interpolation from subcell centres to GLL nodes, R (x) R (x) R."""
+    """Sec. III C 1: reconstruction from subcell centres to GLL nodes, R (x) R (x) R."""
     return ops.apply_3d(ops.reconstruction_matrix(N), U_fd)

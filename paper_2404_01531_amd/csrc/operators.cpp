@@ -3,9 +3,9 @@
 // Sec. III A: nodal basis on Legendre-Gauss-Lobatto (GLL) points with a lumped
 // mass matrix, modal Legendre representation (Eq. modal expansion), exponential
 // filter (Eq. exponential filter).  Sec. III C: 2N+1 uniform subcells, DG -> FD
-// by evaluating the nodal polynomial at subcell centres, FD -> DG by a
-// sixth-order reconstruction (here: the degree-5 least-squares fit of the
-// cell-centre values of one axis, evaluated at the GLL nodes).
+// by evaluating the nodal polynomial at subcell centres, FD -> DG by the
+// least-squares inverse of that projection (the degree-N least-squares fit of
+// the cell-centre values of one axis, evaluated at the GLL nodes).
 #include "grffe_internal.h"
 
 #include <cmath>
@@ -192,8 +192,8 @@ Ops1D build_ops(int N, double filter_a, double filter_b, int tci_M, int tci_mode
   xf[m] = 1.0;
   o.P = lagrange_eval(o.x, xc);   // m x n
   o.Q = lagrange_eval(o.x, xf);   // (m+1) x n
-  // reconstruction: least-squares degree-5 fit of the m cell values, evaluated at the nodes
-  const int q = 6;
+  // reconstruction: least-squares fit of degree N to the m cell values, evaluated at the nodes
+  const int q = n;
   std::vector<double> A(m * q), AtA(q * q, 0.0);
   for (int k = 0; k < m; ++k)
     for (int p = 0; p < q; ++p) A[k * q + p] = legendre(p, xc[k]);

@@ -131,7 +131,7 @@ def _poly3(x, y, z):
 
 def test_poynting_flux_reads_fd_elements_through_the_reconstruction():
     """Elements on FD enter through R U_FD (Sec. III C 1): the reconstruction of the
-    degree-5 least-squares fit is exact for a cubic sampled at the cell centres, so
+    least-squares fit of degree N = 3 is exact for a cubic sampled at the cell centres, so
     moving half of the point-holding elements onto FD leaves L unchanged."""
     torch = pytest.importorskip("torch")
     from paper_2404_01531_amd.poynting import SphereFlux

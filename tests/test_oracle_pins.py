@@ -100,12 +100,11 @@ def test_projection_exact_and_reconstruction_order(N):
     assert np.allclose(xc[1:] - xc[:-1], 2.0 / (2 * N + 1))
     for k in range(N + 1):
         assert np.allclose(P @ x ** k, xc ** k, atol=1e-13)
-    for k in range(6):  # sixth-order: exact up to degree 5
+    for k in range(N + 1):  # the least-squares inverse of P: exact up to degree N
         assert np.allclose(Rm @ xc ** k, x ** k, atol=1e-12)
-    if N <= 5:
-        assert np.allclose(Rm @ P, np.eye(N + 1), atol=1e-13)
-    else:  # degree-6 data is not reproduced: the transfer is sixth order
-        assert np.abs(Rm @ xc ** 6 - x ** 6).max() > 1e-6
+    assert np.allclose(Rm @ P, np.eye(N + 1), atol=1e-12)
+    # degree N + 1 data is not reproduced
+    assert np.abs(Rm @ xc ** (N + 1) - x ** (N + 1)).max() > 1e-6
 
 
 def test_tci_single_modes_and_thresholds():

@@ -8,7 +8,7 @@ curved indicator against formulations other than its own.
   its pre-stages re-derived from the projected U^n) for rollbacks in each of the
   three substeps.
 * A substep-1 rollback against a step with the element on FD from the start (the
-  two agree exactly when P, R and the stiff solve commute: N <= 5, flat space,
+  two agree exactly when P, R and the stiff solve commute: R P = I, flat space,
   vanishing current).
 * The end-of-step switch back (alpha + 1 = 5, Sec. III C 3) on data whose
   indicator ratio is known in closed form.
