@@ -118,18 +118,28 @@ class Shell:
     def _ref(self, fd):
         return ops.fd_centres(self.N) if fd else ops.gll(self.N)[0]
 
+    def map_points(self, e, ref1, ref2, ref3):
+        """x(xi) of element e at the reference points (ref3, ref2, ref1) (arrays of one
+        shape; complex arguments are carried through, for derivative checks)."""
+        na, nr = self.na, self.nr
+        ia, ib = e % na, (e // na) % na
+        ir, w = (e // (na * na)) % nr, e // (na * na * nr)
+        A = -1.0 + (ia + 0.5 * (ref1 + 1.0)) * 2.0 / na
+        B = -1.0 + (ib + 0.5 * (ref2 + 1.0)) * 2.0 / na
+        Z = -1.0 + (ir + 0.5 * (ref3 + 1.0)) * 2.0 / nr
+        X, Y = np.tan(0.25 * np.pi * A), np.tan(0.25 * np.pi * B)
+        r = self.r_in * (self.r_out / self.r_in) ** (0.5 * (Z + 1.0))
+        s = r / np.sqrt(1.0 + X * X + Y * Y)
+        return np.einsum("al,l...->a...", wedge_axes(w), np.stack([s * X, s * Y, s]))
+
     def points(self, fd=False):
         """Cartesian coordinates (3, E, k, k, k) of the DG nodes or FD cell centres."""
         ref = self._ref(fd)
         k = ref.size
+        R3, R2, R1 = np.meshgrid(ref, ref, ref, indexing="ij")
         out = np.empty((3, self.E, k, k, k))
         for e in range(self.E):
-            w, A, B, Z = self._wedge_coords(e, ref)
-            X, Y = np.tan(0.25 * np.pi * A), np.tan(0.25 * np.pi * B)
-            r = self.r_in * (self.r_out / self.r_in) ** (0.5 * (Z + 1.0))
-            s = r / np.sqrt(1.0 + X * X + Y * Y)
-            local = np.stack([s * X, s * Y, s])
-            out[:, e] = np.einsum("al,l...->a...", wedge_axes(w), local)
+            out[:, e] = self.map_points(e, R1, R2, R3)
         return out
 
     def jacobian(self, fd=False):
