@@ -52,6 +52,8 @@ extern "C" {
 #define GRFFE_BC_PERIODIC 0
 #define GRFFE_BC_NO_INCOMING_POYNTING 1 /* Sec. III D */
 #define GRFFE_BC_DIRICHLET 2            /* exterior state held fixed: grffe_set_boundary_state */
+#define GRFFE_BC_OUTFLOW 3              /* shell spheres only: no boundary condition, the exterior
+                                           state is the interior one (the face adds nothing) */
 
 #define GRFFE_PART_EXPLICIT 1 /* fluxes + non-stiff sources */
 #define GRFFE_PART_STIFF 2    /* driver current + kappa damping (treated implicitly) */
@@ -123,6 +125,53 @@ void grffe_default_params(grffe_params* p);
 int grffe_init_domain(const grffe_grid* grid, const grffe_params* params, const double* bg, void* stream,
                       grffe_domain** out);
 
+/* Spherical shell of curved elements (Sec. IV B, the black-hole grid; Sec. III A,
+ * the element map x(xi)).  The shell r_in <= r <= r_out is cut into six
+ * cubed-sphere wedges about +x, -x, +y, -y, +z, -z (wedge w = 2k for +e_k, 2k + 1
+ * for -e_k).  A wedge has coordinates (A, B, Z) in [-1, 1]^3 with the equiangular
+ * angular map X = tan(pi A / 4), Y = tan(pi B / 4) and the logarithmic radial map
+ * r = r_in (r_out / r_in)^((Z + 1) / 2); its local point r (X, Y, 1) /
+ * sqrt(1 + X^2 + Y^2) is turned onto the axes (s e_{k+1}, e_{k+2}, s e_k),
+ * s = +-1.  Each wedge is cut into n_radial x n_angular x n_angular elements of
+ * equal extent in (A, B, Z): element e = ((w n_radial + ir) n_angular + ib)
+ * n_angular + ia, E = 6 n_radial n_angular^2, its reference axes xi^1, xi^2, xi^3
+ * along A, B, Z and its nodes ordered as on the box grid.  Faces f = 4 (xi^3 = -1)
+ * of the innermost and f = 5 of the outermost elements lie on the spheres and take
+ * bc_inner and bc_outer: GRFFE_BC_OUTFLOW, GRFFE_BC_DIRICHLET (per-node exterior
+ * states, grffe_set_boundary_field) or GRFFE_BC_NO_INCOMING_POYNTING (along the
+ * face normal).  Neighbours across wedge faces meet in other orientations; the
+ * library matches their face nodes by position. */
+typedef struct grffe_shell {
+  int32_t degree;      /* 3 <= N <= 9 */
+  int32_t n_radial;
+  int32_t n_angular;   /* elements along each angular side of a wedge */
+  double r_in, r_out;  /* 0 < r_in < r_out */
+  int32_t bc_inner, bc_outer;
+} grffe_shell;
+
+/* Cartesian coordinates of the DG nodes (fd = 0, k = N + 1 per axis) or of the FD
+ * cell centres (fd = 1, k = 2N + 1) of a shell: xyz (host, [3][E][k^3]), written by
+ * the call; the caller evaluates the background and the initial data there. */
+int grffe_shell_points(const grffe_shell* shell, int32_t fd, double* xyz);
+
+/* Create a domain on a shell.  bg (device, nullable for flat space) as for
+ * grffe_init_domain at the points grffe_shell_points(fd = 0) gives.  The DG
+ * operator on curved elements is the strong form with the logical derivative of
+ * each Cartesian flux component contracted with the inverse Jacobian at the node,
+ * dU/dt = S - sum_{i,j} (d xi^i / d x^j) D_i F^j, and at every face node the lift
+ * (1 / w_end) (G*(m) - m_j F^j) along the outward covector m = +-grad xi^i, with the
+ * Rusanov flux G*(m) of speed alpha sqrt(gamma^{jk} m_j m_k) + |beta^j m_j|.  The
+ * time step is Eq. (spectre DG CFL condition) with (dx)_min the smallest distance
+ * between neighbouring nodes along a reference line and lambda_max the largest
+ * alpha + |beta|_gamma.  Shells run every element on DG in FP64: params->hybrid
+ * must be GRFFE_HYBRID_DG_ONLY and params->precision GRFFE_PRECISION_FP64
+ * (GRFFE_EUNSUPPORTED otherwise); the rotating conductor, the adjoint, batches and
+ * the matrix-core contraction are not available on shells.  grffe_init_from_fd
+ * (reconstruction of FD data), grffe_set_state / _get_state, grffe_rhs (rep all
+ * 0), grffe_step, grffe_get_dt and grffe_check_finite work as on the box grid. */
+int grffe_init_shell(const grffe_shell* shell, const grffe_params* params, const double* bg, void* stream,
+                     grffe_domain** out);
+
 /* Exterior state of the grid's Dirichlet faces (the boundary condition of the
  * one-dimensional test problems, Sec. IV A: both ends of the x axis).  state (host,
  * [6][9], row f = 2d + s for the face of direction d and side s, components in the
@@ -146,8 +195,10 @@ int grffe_set_boundary_state(grffe_domain* dom, const double* state, void* strea
  * node's indices along the face's two tangential axes in increasing axis order;
  * ext_fd (device, [9][E][6][3][m^2]) the state at every FD ghost cell, layer
  * l = 0, 1, 2 counted outwards from face f, cell t1 + m t2.  Entries of faces that
- * are not Dirichlet faces are not read.  Both arrays are copied into the domain
- * (allocated at the first call) on `stream`; a later grffe_set_boundary_state
+ * are not Dirichlet faces are not read.  On a shell ext_fd may be NULL (every
+ * element is DG) and this is the only way to set a Dirichlet sphere's states
+ * (grffe_set_boundary_state returns GRFFE_EUNSUPPORTED there).  Both arrays are
+ * copied into the domain (allocated at the first call) on `stream`; a later grffe_set_boundary_state
  * does not undo this.  Returns GRFFE_EINVAL for NULL pointers, GRFFE_ENOMEM,
  * GRFFE_EHIP. */
 int grffe_set_boundary_field(grffe_domain* dom, const double* ext_dg, const double* ext_fd, void* stream);

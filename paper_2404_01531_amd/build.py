@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(LIBDIR, "libgrffe.so")
 
 SOURCES = ["api.cpp", "operators.cpp", "kernels_dg.hip", "kernels_fd.hip", "kernels_adj.hip", "kernels_fd_adj.hip",
-           "kernels_adj_hybrid.hip", "kernels_cond.hip", "noalloc.hip"]
+           "kernels_adj_hybrid.hip", "kernels_cond.hip", "noalloc.hip", "shell.cpp", "kernels_mapped.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

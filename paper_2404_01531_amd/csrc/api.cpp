@@ -92,6 +92,8 @@ KArgs make_args(grffe_domain* d) {
   a.bg_fd = d->bg_fd;
   a.bg_face = d->bg_face;
   a.ops = d->ops;
+  a.jinv = d->jinv;
+  a.fnode = d->fnode;
   a.dg = d->dg;
   a.fd = d->fd;
   a.rep0 = d->rep0;
@@ -197,8 +199,11 @@ static int validate(const grffe_grid* g, const grffe_params* p) {
 // Build a domain over one or more grids of the same degree: the elements of the
 // grids are concatenated (grid k occupies elements off_k .. off_k + E_k - 1) and
 // every grid keeps its own neighbour table, element widths and time step.
+// A shell (sg non-null) is built as one pseudo-grid of E elements whose neighbour
+// table, map and time step come from the shell's geometry.
 static int build_pool(const grffe_grid* const* grids, int count, const grffe_params* p, const double* const* bgs,
-                      hipStream_t st, grffe_domain** out) {
+                      hipStream_t st, grffe_domain** out, const ShellGeom* sg = nullptr,
+                      const grffe_shell* shell = nullptr) {
   *out = nullptr;
   if (count < 1) return fail(GRFFE_EINVAL, "no grid");
   for (int k = 0; k < count; ++k)
@@ -248,7 +253,7 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   d->live_h.assign(E, 1);
   d->nbr_h.assign((size_t)E * 6, -1);
   d->eh_h.assign((size_t)E * 3, 0.0);
-  for (int k = 0; k < count; ++k) {
+  for (int k = 0; k < count && !sg; ++k) {
     const grffe_grid* g = grids[k];
     const grffe_part& pt = d->parts[k];
     if (g->excised)
@@ -275,6 +280,14 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
           d->nbr_h[(size_t)(pt.off + e) * 6 + 2 * dd + sd] = pt.off + o;
         }
     }
+  }
+  if (sg) {
+    d->mapped = true;
+    d->nbr_h = sg->nbr;
+    for (int k = 0; k < 6; ++k) d->bc[k] = GRFFE_BC_NO_INCOMING_POYNTING;
+    d->bc_missing = 0;
+    if (shell->bc_inner == GRFFE_BC_DIRICHLET) d->bc_missing |= 1 << 4;
+    if (shell->bc_outer == GRFFE_BC_DIRICHLET) d->bc_missing |= 1 << 5;
   }
   const int M = p->tci_M > 0 ? p->tci_M : default_tci_M(d->N);
   d->ops_h = build_ops(d->N, p->filter_a, p->filter_b, M, p->tci_mode);
@@ -328,6 +341,10 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   ALLOC(fhat, sizeof(double) * 3 * NV * E * mm);
   ALLOC(fd_list, sizeof(int32_t) * E);
   ALLOC(fd_count, sizeof(int32_t) * 4);
+  if (sg) {
+    ALLOC(jinv, sizeof(double) * 9 * E * nn);
+    ALLOC(fnode, sizeof(int32_t) * E * 6 * n * n);
+  }
   double* qdev = nullptr;
   if (d->curved) {
     ALLOC(bg_dg, sizeof(double) * NBG * E * nn);
@@ -365,9 +382,39 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   CHK(hipMemsetAsync(d->troubled, 0, E, st));
   CHK(hipMemsetAsync(d->ratio, 0, sizeof(double) * E, st));
   CHK(hipMemsetAsync(d->fd_count, 0, sizeof(int32_t) * 4, st));
+  if (sg) {
+    CHK(hipMemcpyAsync(d->jinv, sg->jinv.data(), sizeof(double) * 9 * E * nn, hipMemcpyHostToDevice, st));
+    CHK(hipMemcpyAsync(d->fnode, sg->fnode.data(), sizeof(int32_t) * E * 6 * n * n, hipMemcpyHostToDevice, st));
+  }
   // time step per grid: lambda_max from the background (1 in flat space)
   for (auto& pt : d->parts) pt.lambda_max = 1.0;
-  if (d->curved) {
+  if (d->curved && sg) {
+    // lambda_max = max over the nodes of alpha + |beta|_gamma (the largest
+    // characteristic speed over all directions), from a host copy of alpha, beta, gamma
+    CHK(hipMemcpyAsync(d->bg_dg, bgs[0], sizeof(double) * NBG * E * nn, hipMemcpyDeviceToDevice, st));
+    std::vector<double> hb((size_t)10 * E * nn);
+    CHK(hipMemcpyAsync(hb.data(), bgs[0], sizeof(double) * 10 * E * nn, hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    double lam = 0.0;
+    const size_t P = (size_t)E * nn;
+    for (size_t q = 0; q < P; ++q) {
+      const double al = hb[q], b[3] = {hb[P + q], hb[2 * P + q], hb[3 * P + q]};
+      const double g[6] = {hb[4 * P + q], hb[5 * P + q], hb[6 * P + q], hb[7 * P + q], hb[8 * P + q], hb[9 * P + q]};
+      const double bb = g[0] * b[0] * b[0] + g[3] * b[1] * b[1] + g[5] * b[2] * b[2] +
+                        2.0 * (g[1] * b[0] * b[1] + g[2] * b[0] * b[2] + g[4] * b[1] * b[2]);
+      const double v = al + std::sqrt(std::fmax(bb, 0.0));
+      if (!std::isfinite(v)) {
+        grffe_destroy(d);
+        return fail(GRFFE_EINVAL, "the background holds non-finite values");
+      }
+      lam = std::fmax(lam, v);
+    }
+    d->parts[0].lambda_max = lam;
+    CHK(hipMemcpyAsync(qdev, d->ops_h.Q.data(), sizeof(double) * (m + 1) * n, hipMemcpyHostToDevice, st));
+    KArgs a = make_args(d);
+    launch_bg_derive_q(a, d->N, d->bg_fd, d->bg_face, qdev, st);
+    CHK(hipGetLastError());
+  } else if (d->curved) {
     for (int k = 0; k < count; ++k) {
       const grffe_part& pt = d->parts[k];
       CHK(hipMemcpy2DAsync(d->bg_dg + (size_t)pt.off * nn, sizeof(double) * E * nn, bgs[k],
@@ -400,7 +447,9 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   d->edt_h.assign(E, 0.0);
   for (auto& pt : d->parts) {
     const double hmin = std::fmin(pt.h[0], std::fmin(pt.h[1], pt.h[2]));
-    pt.dt = p->cfl * gap * hmin / 2.0 / pt.lambda_max * c / 3.0;
+    // Eq. (spectre DG CFL condition): (dx)_min is gap * h / 2 on affine elements
+    const double dxmin = sg ? sg->dx_min : gap * hmin / 2.0;
+    pt.dt = p->cfl * dxmin / pt.lambda_max * c / 3.0;
     for (int e = pt.off; e < pt.off + pt.E; ++e) d->edt_h[e] = pt.dt;
   }
   d->dt_cfl = d->parts[0].dt;
@@ -421,8 +470,45 @@ extern "C" int grffe_init_domain(const grffe_grid* g, const grffe_params* p, con
   return build_pool(gs, 1, p, bs, S(stream), out);
 }
 
+extern "C" int grffe_shell_points(const grffe_shell* s, int32_t fd, double* xyz) {
+  std::string err;
+  if (int rc = shell_validate(s, err)) return fail(rc, err);
+  if (!xyz) return fail(GRFFE_EINVAL, "xyz must not be NULL");
+  std::vector<double> pts;
+  shell_points(*s, fd != 0, pts);
+  std::copy(pts.begin(), pts.end(), xyz);
+  return GRFFE_OK;
+}
+
+extern "C" int grffe_init_shell(const grffe_shell* s, const grffe_params* p, const double* bg, void* stream,
+                                grffe_domain** out) {
+  if (!out) return fail(GRFFE_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  std::string err;
+  if (int rc = shell_validate(s, err)) return fail(rc, err);
+  if (!p) return fail(GRFFE_EINVAL, "params must not be NULL");
+  if (p->hybrid != GRFFE_HYBRID_DG_ONLY)
+    return fail(GRFFE_EUNSUPPORTED, "shells run every element on DG (hybrid = GRFFE_HYBRID_DG_ONLY)");
+  if (p->precision != GRFFE_PRECISION_FP64) return fail(GRFFE_EUNSUPPORTED, "shells run in FP64");
+  ShellGeom g;
+  if (int rc = shell_geometry(*s, g, err)) return fail(rc, err);
+  grffe_grid pseudo{};
+  pseudo.n_elem[0] = g.E;
+  pseudo.n_elem[1] = pseudo.n_elem[2] = 1;
+  for (int k = 0; k < 3; ++k) {
+    pseudo.lower[k] = 0.0;
+    pseudo.upper[k] = 1.0;
+  }
+  pseudo.degree = s->degree;
+  for (int k = 0; k < 6; ++k) pseudo.bc[k] = GRFFE_BC_NO_INCOMING_POYNTING;
+  const grffe_grid* gs[1] = {&pseudo};
+  const double* bs[1] = {bg};
+  return build_pool(gs, 1, p, bs, S(stream), out, &g, s);
+}
+
 extern "C" int grffe_set_boundary_state(grffe_domain* d, const double* state, void* stream) {
   if (int rc = check_dom(d)) return rc;
+  if (d->mapped) return fail(GRFFE_EUNSUPPORTED, "shells take per-node exterior states (grffe_set_boundary_field)");
   if (!state) return fail(GRFFE_EINVAL, "state must not be NULL");
   for (int k = 0; k < 6 * NV; ++k)
     if (!std::isfinite(state[k])) return fail(GRFFE_EINVAL, "boundary state must be finite");
@@ -435,7 +521,7 @@ extern "C" int grffe_set_boundary_state(grffe_domain* d, const double* state, vo
 
 extern "C" int grffe_set_boundary_field(grffe_domain* d, const double* ext_dg, const double* ext_fd, void* stream) {
   if (int rc = check_dom(d)) return rc;
-  if (!ext_dg || !ext_fd) return fail(GRFFE_EINVAL, "boundary field pointers must not be NULL");
+  if (!ext_dg || (!ext_fd && !d->mapped)) return fail(GRFFE_EINVAL, "boundary field pointers must not be NULL");
   if (d->parts.size() != 1) return fail(GRFFE_EUNSUPPORTED, "boundary fields are set on single domains");
   const size_t ndg = (size_t)NV * d->E * 6 * d->n * d->n;
   const size_t nfd = (size_t)NV * d->E * 6 * 3 * d->m * d->m;
@@ -449,7 +535,7 @@ extern "C" int grffe_set_boundary_field(grffe_domain* d, const double* ext_dg, c
   }
   hipStream_t st = S(stream);
   HIPCHK(hipMemcpyAsync(d->bfield_dg, ext_dg, sizeof(double) * ndg, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(d->bfield_fd, ext_fd, sizeof(double) * nfd, hipMemcpyDeviceToDevice, st));
+  if (ext_fd) HIPCHK(hipMemcpyAsync(d->bfield_fd, ext_fd, sizeof(double) * nfd, hipMemcpyDeviceToDevice, st));
   d->bc_missing = 0;
   return GRFFE_OK;
 }
@@ -458,6 +544,7 @@ extern "C" int grffe_set_conductor(grffe_domain* d, const double* centre, double
                                    void* stream) {
   if (int rc = check_dom(d)) return rc;
   if (d->parts.size() != 1) return fail(GRFFE_EUNSUPPORTED, "the conductor is set on single domains");
+  if (d->mapped) return fail(GRFFE_EUNSUPPORTED, "the conductor is not available on shells");
   if (!std::isfinite(radius) || !std::isfinite(omega)) return fail(GRFFE_EINVAL, "radius and omega must be finite");
   if (radius <= 0.0) {
     d->cond_count = 0;
@@ -512,6 +599,8 @@ extern "C" int grffe_set_contraction(grffe_domain* d, int engine) {
   if (int rc = check_dom(d)) return rc;
   if (engine != GRFFE_CONTRACTION_VALU && engine != GRFFE_CONTRACTION_MFMA)
     return fail(GRFFE_EINVAL, "engine must be GRFFE_CONTRACTION_VALU or GRFFE_CONTRACTION_MFMA");
+  if (d->mapped && engine != GRFFE_CONTRACTION_VALU)
+    return fail(GRFFE_EUNSUPPORTED, "shells contract on the VALU");
   d->contraction = engine;
   return GRFFE_OK;
 }
@@ -627,6 +716,12 @@ static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   // elements they flag, so it holds the FD elements at the start of every substep;
   // the FD update of substeps 1 and 2 writes the next substep's stage values
   a.sub = mode == MODE_RHS ? 3 : 0;
+  if (d->mapped) {
+    // every element on DG: the one fused kernel per substep
+    TimedLaunch t(d, 1, st);
+    launch_dg_mapped(a, N, cv, mode, st);
+    return;
+  }
   if (mode == MODE_RHS || mode == MODE_SUB1) {
     launch_begin_substep(a, mode != MODE_RHS, st);
     TimedLaunch t(d, 4, st);
@@ -753,6 +848,7 @@ extern "C" int grffe_step_logged(grffe_domain* d, double dt, int32_t* rep_log, v
 
 // The adjoint entry points run in FP64 without the clamp.
 static int adjoint_supported(grffe_domain* d) {
+  if (d->mapped) return fail(GRFFE_EUNSUPPORTED, "the adjoint is not available on shells");
   if (d->N > 8) return fail(GRFFE_EUNSUPPORTED, "the adjoint is built for degrees 3..8");
   if (d->par.precision != GRFFE_PRECISION_FP64) return fail(GRFFE_EUNSUPPORTED, "the adjoint runs in FP64 only");
   if (d->par.ff_clamp) return fail(GRFFE_EUNSUPPORTED, "the adjoint does not differentiate the clamp");

@@ -16,6 +16,7 @@ constexpr int NW = 12;     // evolved components + densitized current J~
 constexpr int NBG = 26;    // background fields at DG nodes / FD cells
 constexpr int NBGF = 10;   // background fields at FD faces (alpha, beta, gamma)
 constexpr int MAX_DEG = 9; // largest degree with a fused DG kernel
+constexpr int NBR_OUTFLOW = -8;  // neighbour code of a face with no boundary condition
 
 // IMEX-SSP3(4,3,3) (Pareschi & Russo 2005): implicit diagonal a, and b, e of the last row.
 constexpr double IMEX_A = 0.24169426078821;
@@ -28,6 +29,20 @@ struct Ops1D {
 };
 
 Ops1D build_ops(int N, double filter_a, double filter_b, int tci_M, int tci_mode);
+
+// Host geometry of a spherical shell (shell.cpp): node coordinates, inverse
+// Jacobian, neighbours (with the boundary codes of the spheres) and the matched
+// neighbour node of every face node, the smallest node distance.
+struct ShellGeom {
+  int E = 0;
+  std::vector<double> jinv;     // [9][E][n^3]
+  std::vector<int32_t> nbr;     // [E][6]
+  std::vector<int32_t> fnode;   // [E][6][n^2]
+  double dx_min = 0.0;
+};
+int shell_validate(const grffe_shell* s, std::string& err);
+void shell_points(const grffe_shell& s, bool fd, std::vector<double>& xyz);
+int shell_geometry(const grffe_shell& s, ShellGeom& g, std::string& err);
 void gll_nodes_weights(int N, std::vector<double>& x, std::vector<double>& w);
 int default_tci_M(int N);
 
@@ -62,7 +77,8 @@ struct KArgs {
   const double* eh;        // [E][3] element widths
   const double* edt;       // [E] time step of the element's domain
   const int32_t* nbr;      // [E][6]: neighbour, -1 at a no-incoming-Poynting boundary,
-                           // -2 - slot at a Dirichlet face (exterior state bstate[slot])
+                           // -2 - slot at a Dirichlet face (exterior state bstate[slot]),
+                           // NBR_OUTFLOW at an outflow sphere of a shell
   const double* bstate;    // [slots][9] exterior states of Dirichlet faces
   const double* bfield_dg; // [9][E][6][n^2] per-node exterior states of Dirichlet faces, or null
   const double* bfield_fd; // [9][E][6][3][m^2] per-ghost-cell exterior states, or null
@@ -72,6 +88,11 @@ struct KArgs {
   const double* bg_fd;     // [26][E][m^3] or null
   const double* bg_face;   // [3][10][E][(m+1) m^2] or null
   const DevOps* ops;
+  // curved element maps (shells), else null: the inverse Jacobian d xi^i / d x^j
+  // [9][E][n^3] (row i, column j: component 3 i + j) and, per face node, the node
+  // of the neighbour at the same point [E][6][n^2] (flat index in that element)
+  const double* jinv;
+  const int32_t* fnode;
   // state
   Regs dg, fd;
   int32_t* rep0;           // representation at the start of the substep
@@ -130,6 +151,9 @@ struct grffe_domain {
   int bc_missing = 0;         // Dirichlet faces whose exterior state is not set (bit f)
   grffe_params par;
   bool curved;
+  bool mapped = false;          // a shell of curved elements (grffe_init_shell)
+  double* jinv = nullptr;       // [9][E][n^3] inverse Jacobian (shells)
+  int32_t* fnode = nullptr;     // [E][6][n^2] neighbour node of each face node (shells)
   std::vector<int32_t> nbr_h;
   std::vector<uint8_t> live_h;
   int32_t* nbr = nullptr;
@@ -205,6 +229,8 @@ struct LaunchEvents {
 };
 LaunchEvents& armed_launch_events();
 
+// launchers (kernels_mapped.hip)
+void launch_dg_mapped(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 // launchers (kernels_dg.hip)
 void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_dg_slab(const KArgs& a, int N, bool curved, int mode, hipStream_t s);

@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "grffe.h")
 BC_PERIODIC = 0
 BC_NO_INCOMING_POYNTING = 1
 BC_DIRICHLET = 2
+BC_OUTFLOW = 3
 PART_EXPLICIT, PART_STIFF, PART_ALL = 1, 2, 3
 HYBRID_DG_ONLY, HYBRID_ADAPTIVE, HYBRID_FORCED = 0, 1, 2
 CONTRACTION_VALU = 0
@@ -40,6 +41,38 @@ class Grid(ctypes.Structure):
         ("bc", ctypes.c_int32 * 6),
         ("excised", ctypes.POINTER(ctypes.c_uint8)),
     ]
+
+
+class ShellGrid(ctypes.Structure):
+    _fields_ = [
+        ("degree", ctypes.c_int32),
+        ("n_radial", ctypes.c_int32),
+        ("n_angular", ctypes.c_int32),
+        ("r_in", ctypes.c_double),
+        ("r_out", ctypes.c_double),
+        ("bc_inner", ctypes.c_int32),
+        ("bc_outer", ctypes.c_int32),
+    ]
+
+
+def _fill_shell(degree, n_radial, n_angular, r_in, r_out, bc_inner=BC_OUTFLOW, bc_outer=BC_DIRICHLET):
+    s = ShellGrid()
+    s.degree, s.n_radial, s.n_angular = int(degree), int(n_radial), int(n_angular)
+    s.r_in, s.r_out = float(r_in), float(r_out)
+    s.bc_inner, s.bc_outer = int(bc_inner), int(bc_outer)
+    return s
+
+
+def shell_points(degree, n_radial, n_angular, r_in, r_out, fd=False):
+    """Coordinates (3, E, k^3) of a shell's DG nodes (k = N + 1) or FD cell centres
+    (k = 2N + 1), computed by the library on the host."""
+    s = _fill_shell(degree, n_radial, n_angular, r_in, r_out)
+    E = 6 * int(n_radial) * int(n_angular) ** 2
+    k = 2 * int(degree) + 1 if fd else int(degree) + 1
+    out = np.empty((3, E, k ** 3), np.float64)
+    _check(lib().grffe_shell_points(ctypes.byref(s), 1 if fd else 0,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
 
 
 class Params(ctypes.Structure):
@@ -80,6 +113,8 @@ def lib():
     L.grffe_default_params.argtypes = [ctypes.POINTER(Params)]
     L.grffe_default_params.restype = None
     L.grffe_init_domain.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
+    L.grffe_shell_points.argtypes = [ctypes.POINTER(ShellGrid), i32, ctypes.POINTER(dbl)]
+    L.grffe_init_shell.argtypes = [ctypes.POINTER(ShellGrid), ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
     L.grffe_set_boundary_state.argtypes = [vp, ctypes.POINTER(dbl), vp]
     L.grffe_set_boundary_field.argtypes = [vp, vp, vp, vp]
     L.grffe_check_finite.argtypes = [vp, ctypes.POINTER(i32), vp]
@@ -130,7 +165,7 @@ def lib():
                  "grffe_step_adjoint", "grffe_step_adjoint_frozen", "grffe_get_stages",
                  "grffe_step_adjoint_stages", "grffe_set_boundary_state", "grffe_set_boundary_field",
                  "grffe_check_finite", "grffe_set_conductor", "grffe_batch_set_contraction",
-                 "grffe_batch_get_contraction", "grffe_step_logged"):
+                 "grffe_batch_get_contraction", "grffe_step_logged", "grffe_shell_points", "grffe_init_shell"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -222,6 +257,33 @@ class Domain:
         _check(L.grffe_init_domain(ctypes.byref(g), ctypes.byref(p), _ptr(bg), _stream(), ctypes.byref(h)))
         self._h = h
 
+    @classmethod
+    def shell(cls, degree, n_radial, n_angular, r_in, r_out, bc_inner=BC_OUTFLOW, bc_outer=BC_DIRICHLET,
+              params=None, bg=None):
+        """A domain on the spherical shell of cubed-sphere wedges (grffe_init_shell);
+        bg (26, E, (N+1)^3) float64 at the points of shell_points(..., fd=False)."""
+        import torch
+        if not torch.cuda.is_available():
+            raise GrffeError("no HIP device available")
+        L = lib()
+        s = _fill_shell(degree, n_radial, n_angular, r_in, r_out, bc_inner, bc_outer)
+        self = cls.__new__(cls)
+        self._exc = None
+        p = params if isinstance(params, Params) else default_params(**(params or {}))
+        self.params = p
+        self.N = int(degree)
+        self.n = self.N + 1
+        self.m = 2 * self.N + 1
+        self.E = 6 * int(n_radial) * int(n_angular) ** 2
+        if bg is not None:
+            bg = bg.contiguous()
+            if tuple(bg.shape) != (26, self.E, self.n ** 3) or bg.dtype != torch.float64:
+                raise GrffeError("bg must be float64 of shape (26, E, (N+1)^3)")
+        h = ctypes.c_void_p()
+        _check(L.grffe_init_shell(ctypes.byref(s), ctypes.byref(p), _ptr(bg), _stream(), ctypes.byref(h)))
+        self._h = h
+        return self
+
     def close(self):
         if getattr(self, "_h", None):
             lib().grffe_destroy(self._h)
@@ -298,10 +360,10 @@ class Domain:
         """Per-point exterior states of the Dirichlet faces: device float64 tensors
         (9, E, 6, n^2) at the DG face nodes and (9, E, 6, 3, m^2) at the FD ghost cells."""
         n2, m2 = self.n ** 2, self.m ** 2
-        if tuple(ext_dg.shape) != (9, self.E, 6, n2) or tuple(ext_fd.shape) != (9, self.E, 6, 3, m2):
+        if tuple(ext_dg.shape) != (9, self.E, 6, n2) or (ext_fd is not None and tuple(ext_fd.shape) != (9, self.E, 6, 3, m2)):
             raise GrffeError(f"boundary field shapes must be (9, E, 6, {n2}) and (9, E, 6, 3, {m2})")
-        _check(lib().grffe_set_boundary_field(self._h, _ptr(ext_dg.contiguous()), _ptr(ext_fd.contiguous()),
-                                              _stream()))
+        _check(lib().grffe_set_boundary_field(self._h, _ptr(ext_dg.contiguous()),
+                                              _ptr(None if ext_fd is None else ext_fd.contiguous()), _stream()))
 
     def get_state(self):
         import torch

@@ -1,0 +1,187 @@
+"""GPU parity of the DG operator on curved element maps: the spherical shell of
+cubed-sphere wedges (Sec. IV B) against the oracle's shell, through the C ABI.
+
+* Right-hand side, element by element, in flat space and on Kerr-Schild, with
+  outflow, Dirichlet and no-incoming-Poynting spheres, at degrees 3, 5 and 9 and
+  one to three elements per wedge side.
+* Steps with the driver current and the damping on (eta dt ~ 1), against the
+  oracle's step.
+* The time step against the oracle's and the exact-Wald table's.
+* The exact-Wald evolution (Sec. IV B 1) to t = 5M: equal to the oracle's at P5 on
+  the coarsest grid, and the table's errors at every degree and resolution.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import shell as S
+from paper_2404_01531_amd import inputs as I
+
+from helpers import oracle_params
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+R_IN, R_OUT = 1.99, 20.0
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(N, nr, na, r_in=R_IN, r_out=R_OUT, bc_inner=S.SHELL_OUTFLOW, bc_outer=S.SHELL_DIRICHLET, curved=True,
+          spin=0.0, params=None):
+    """(oracle Shell, library Domain, exact Wald state (9, E, n, n, n)) with the exact
+    Wald solution as the Dirichlet state wherever a sphere is Dirichlet."""
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    p = grffe.default_params(**{"hybrid": 0, **(params or {})})
+    geo = S.Shell(N, nr, na, r_in, r_out)
+    x = geo.x_dg
+    bg = I.kerr_schild_background(x[0], x[1], x[2], 1.0, spin) if curved else None
+    sh = S.Shell(N, nr, na, r_in, r_out, bc_inner=bc_inner, bc_outer=bc_outer, bg=bg, params=oracle_params(p))
+    Uex = I.wald_a0(x[0], x[1], x[2], 1.0, 1.0)
+    field = np.stack([sh.face_nodes(Uex, f) for f in range(6)], axis=2)
+    sh.boundary_field = field
+    bg_t = None if bg is None else torch.from_numpy(np.ascontiguousarray(bg.reshape(26, sh.E, -1))).cuda()
+    dom = grffe.Domain.shell(N, nr, na, r_in, r_out, bc_inner, bc_outer, params=p, bg=bg_t)
+    if S.SHELL_DIRICHLET in (bc_inner, bc_outer):
+        dom.set_boundary_field(torch.from_numpy(np.ascontiguousarray(field)).cuda(), None)
+    return sh, dom, Uex
+
+
+def _perturbed(sh, Uex, seed):
+    """The exact state plus smooth perturbations of every component (psi~, phi~, q~
+    and E.B non-zero) and a little noise."""
+    rng = np.random.default_rng(seed)
+    x, y, z = sh.x_dg
+    U = Uex.copy()
+    for c in range(9):
+        a, b, k = rng.uniform(-1, 1, 3)
+        U[c] += 0.05 * np.sin(0.3 * k * x + a * y) * np.cos(0.2 * z + b)
+    U += 1e-3 * rng.standard_normal(U.shape)
+    return U
+
+
+def _dev(U):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(U.reshape(9, U.shape[1], -1))).cuda()
+
+
+def _rhs_lib(dom, U):
+    torch = _torch()
+    E = U.shape[1]
+    fd = torch.zeros((9, E, dom.m ** 3), dtype=torch.float64, device="cuda")
+    rep = torch.zeros(E, dtype=torch.int32, device="cuda")
+    out, _ = dom.rhs(_dev(U), fd, rep)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().reshape(U.shape)
+
+
+CASES = [
+    # N, nr, na, curved, bc_inner, bc_outer, r_in, eta
+    (3, 1, 1, False, S.SHELL_OUTFLOW, S.SHELL_OUTFLOW, 1.0, 0.0),
+    (5, 1, 1, True, S.SHELL_OUTFLOW, S.SHELL_DIRICHLET, R_IN, 0.0),
+    (5, 2, 2, True, S.SHELL_DIRICHLET, S.SHELL_NO_INCOMING_POYNTING, 2.5, 50.0),
+    (4, 1, 3, False, S.SHELL_NO_INCOMING_POYNTING, S.SHELL_DIRICHLET, 1.0, 50.0),
+    (9, 1, 1, True, S.SHELL_OUTFLOW, S.SHELL_NO_INCOMING_POYNTING, R_IN, 5.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"P{c[0]}_{c[1]}x{6 * c[2] ** 2}_{'ks' if c[3] else 'flat'}")
+def test_shell_rhs_parity(case):
+    N, nr, na, curved, bci, bco, r_in, eta = case
+    _say("shell rhs", case)
+    sh, dom, Uex = _pair(N, nr, na, r_in=r_in, bc_inner=bci, bc_outer=bco, curved=curved,
+                         params=dict(eta=eta, kappa_psi=1.0, kappa_phi=1.0))
+    U = _perturbed(sh, Uex, 11 + N)
+    want = S.shell_rhs(sh, U)
+    got = _rhs_lib(dom, U)
+    for c in range(9):
+        scale = max(np.abs(want[c]).max(), 1e-300)
+        assert np.abs(got[c] - want[c]).max() <= 1e-12 * scale, (c, np.abs(got[c] - want[c]).max(), scale)
+    dom.close()
+
+
+@pytest.mark.parametrize("N,nr,na", [(4, 1, 2), (5, 2, 1)])
+def test_shell_steps_parity(N, nr, na):
+    """Five steps with the driver current, the damping and the filter on."""
+    torch = _torch()
+    _say("shell steps", N, nr, na)
+    sh, dom, Uex = _pair(N, nr, na, r_in=2.5, bc_inner=S.SHELL_OUTFLOW, bc_outer=S.SHELL_DIRICHLET,
+                         params=dict(eta=20.0, kappa_psi=1.0, kappa_phi=1.0, cfl=0.3))
+    U = _perturbed(sh, Uex, 3)
+    fd = torch.zeros((9, sh.E, dom.m ** 3), dtype=torch.float64, device="cuda")
+    rep = torch.zeros(sh.E, dtype=torch.int32, device="cuda")
+    dom.set_state(_dev(U), fd, rep)
+    dt = dom.dt()
+    assert abs(dt / sh.dt() - 1.0) < 1e-13
+    for _ in range(5):
+        U = S.shell_step(sh, U, dt)
+    dom.step(5)
+    got = dom.get_dg().cpu().numpy().reshape(U.shape)
+    for c in range(9):
+        scale = max(np.abs(U[c]).max(), 1e-300)
+        assert np.abs(got[c] - U[c]).max() <= 1e-11 * scale, (c, np.abs(got[c] - U[c]).max(), scale)
+    dom.close()
+
+
+def _table():
+    import os
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "exact_wald_table.txt")):
+        if line.strip() and not line.startswith("#"):
+            N, nr, na, dt, err = line.split()
+            rows.append((int(N), int(nr), int(na), float(dt), float(err)))
+    return rows
+
+
+def _wald_run(N, nr, na):
+    """The exact-Wald run on the library: FD data reconstructed to DG, t = 5M with the
+    last step shortened to land on it; returns (dt, error, oracle shell, exact state)."""
+    torch = _torch()
+    sh, dom, Uex = _pair(N, nr, na, params=dict(eta=0.0, cfl=0.3))
+    xf = sh.points(fd=True)
+    u_fd = I.wald_a0(xf[0], xf[1], xf[2], 1.0, 1.0)
+    dom.init_from_fd(torch.from_numpy(np.ascontiguousarray(u_fd.reshape(9, sh.E, -1))).cuda())
+    dt = dom.dt()
+    n_full = int(np.floor(5.0 / dt + 1e-9))
+    dom.step(n_full)
+    rest = 5.0 - n_full * dt
+    if rest > 1e-12:
+        dom.step(1, rest)
+    U = dom.get_dg().cpu().numpy().reshape(Uex.shape)
+    dom.close()
+    return dt, S.l2_error(U[3:6], Uex[3:6]), sh, Uex, U
+
+
+def test_shell_exact_wald_p5_equals_oracle():
+    _say("exact Wald P5 1x6, library against oracle")
+    dt, err, sh, Uex, U = _wald_run(5, 1, 1)
+    V = S.initial_dg(sh, I.wald_a0(*sh.points(fd=True), 1.0, 1.0))
+    t = 0.0
+    while t < 5.0 - 1e-12:
+        h = min(dt, 5.0 - t)
+        V = S.shell_step(sh, V, h)
+        t += h
+    assert np.abs(U - V).max() <= 1e-10 * np.abs(V).max()
+    assert abs(err / S.l2_error(V[3:6], Uex[3:6]) - 1.0) < 1e-8
+
+
+def test_shell_exact_wald_table():
+    """Every row of the exact-Wald table: the time step to its printed digits and the
+    error of B~ at t = 5M against the printed value."""
+    for N, nr, na, dt_paper, err_paper in _table():
+        dt, err, *_ = _wald_run(N, nr, na)
+        _say(f"exact Wald P{N} {nr}x{6 * na * na}: dt {dt:.4e} (paper {dt_paper:.2e}), "
+             f"error {err:.4e} (paper {err_paper:.2e}), ratio {err / err_paper:.4f}")
+        assert abs(dt - dt_paper) <= 0.5 * 10.0 ** (np.floor(np.log10(dt_paper)) - 2) + 1e-12
+        assert abs(err / err_paper - 1.0) < 0.05

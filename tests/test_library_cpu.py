@@ -139,3 +139,31 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+@pytest.mark.parametrize("N, nr, na", [(3, 1, 1), (5, 2, 2), (9, 1, 3)])
+def test_shell_points_match_oracle(N, nr, na):
+    """The library's host map of the shell (grffe_shell_points) against the oracle's."""
+    from oracle import shell as S
+    sh = S.Shell(N, nr, na, 1.99, 20.0)
+    for fd in (False, True):
+        got = grffe.shell_points(N, nr, na, 1.99, 20.0, fd=fd)
+        want = sh.points(fd=fd).reshape(3, sh.E, -1)
+        assert np.abs(got - want).max() < 1e-13 * 20.0
+
+
+@pytest.mark.parametrize("shell, over, code", [
+    (dict(), dict(hybrid=1), -5), (dict(), dict(precision=1), -5), (dict(degree=2), dict(), -1),
+    (dict(r_in=3.0), dict(), -1), (dict(r_in=0.0), dict(), -1), (dict(n_angular=0), dict(), -1),
+    (dict(bc_inner=0), dict(), -1), (dict(bc_outer=7), dict(), -1),
+])
+def test_init_shell_rejects_unsupported(shell, over, code):
+    """Refused before any device call, so it runs without a GPU."""
+    L = grffe.lib()
+    args = dict(degree=5, n_radial=1, n_angular=1, r_in=2.0, r_out=3.0, bc_inner=3, bc_outer=2)
+    args.update(shell)
+    s = grffe._fill_shell(**args)
+    p = grffe.default_params(**{"hybrid": 0, **over})
+    h = ctypes.c_void_p()
+    assert L.grffe_init_shell(ctypes.byref(s), ctypes.byref(p), None, None, ctypes.byref(h)) == code
+    assert not h.value and L.grffe_last_error().decode()
