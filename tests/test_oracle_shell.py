@@ -30,7 +30,7 @@ def _table():
     rows = []
     for line in open(GOLDEN):
         if line.strip() and not line.startswith("#"):
-            N, nr, na, dt, err = line.split()
+            N, nr, na, dt, err, _ = line.split()
             rows.append((int(N), int(nr), int(na), float(dt), float(err)))
     return rows
 
