@@ -1126,7 +1126,6 @@ def main():
     if args.extras != "none":
         ex = {}
         jobs = [("batch_64_fp64", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0)),
-                ("batch_64_fp64_autotuned", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0, tune=True)),
                 ("batch_64_mixed", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 1)),
                 ("sheet_8^3", lambda: sheet_line(args.extra_steps, 2)),
                 ("kerr_schild_16^3_full_run", lambda: run_kerr_schild_full()),
@@ -1137,7 +1136,8 @@ def main():
                 ("adjoint_sheet_8^3_frozen_partition", lambda: run_adjoint_frozen()),
                 ("exact_wald_shell_table", lambda: run_shell_wald())]
         if args.extras == "all":
-            jobs += [("accuracy_smooth_fast_wave_4^3", lambda: run_accuracy_smooth_wave(20)),
+            jobs += [("batch_64_fp64_autotuned", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0, tune=True)),
+                     ("accuracy_smooth_fast_wave_4^3", lambda: run_accuracy_smooth_wave(20)),
                      ("exact_wald_convergence", lambda: run_exact_wald()),
                      ("forced_fd_fraction_alfven_8x32x8", lambda: run_forced_fractions_alfven(args.extra_steps, 2))]
         for name, fn in jobs:
