@@ -65,10 +65,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--only", choices=("sheet", "batch", "adjoint_adaptive", "shell_wald"), default=None,
+    ap.add_argument("--only", choices=("sheet", "batch", "adjoint_adaptive", "shell_wald", "vacuum_wald"), default=None,
                     help="run one secondary workload alone and print its record (profiling runs)")
     ap.add_argument("--shell-degrees", default="5,7,9",
                     help="degrees of the exact-Wald shell rows (--only shell_wald)")
+    ap.add_argument("--spins", default="0,0.5,0.7,0.8", help="spins of the vacuum Wald runs (--only vacuum_wald)")
     ap.add_argument("--contraction", choices=("valu", "mfma"), default="valu",
                     help="DG derivative contraction engine of the black-hole domains (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -962,6 +963,118 @@ def run_shell_wald(cases=tuple(EXACT_WALD_TABLE), t_end=5.0):
             "rows": rows}
 
 
+def _shell_sample(u, pts, N, nr, na, r_in, r_out, nodes):
+    """Values (C, P) of the nodal DG data u (C, E, n^3) of a shell at the points pts
+    (3, P): the wedge and element from the inverse map, then the element's Lagrange
+    interpolant at the reference coordinates."""
+    import numpy as np
+    n = N + 1
+    x = np.asarray(pts, np.float64)
+    k = np.argmax(np.abs(x), axis=0)
+    P = x.shape[1]
+    idx = np.arange(P)
+    xk = x[k, idx]
+    s = np.sign(xk)
+    X = x[(k + 1) % 3, idx] / xk
+    Y = s * x[(k + 2) % 3, idx] / xk
+    r = np.sqrt((x * x).sum(axis=0))
+    ref = [4.0 / np.pi * np.arctan(X), 4.0 / np.pi * np.arctan(Y),
+           2.0 * np.log(r / r_in) / np.log(r_out / r_in) - 1.0]
+    cnt = (na, na, nr)
+    cell, xi = [], []
+    for d in range(3):
+        t = 0.5 * (ref[d] + 1.0) * cnt[d]
+        c = np.clip(np.floor(t), 0, cnt[d] - 1).astype(np.int64)
+        cell.append(c)
+        xi.append(2.0 * (t - c) - 1.0)
+    w = 2 * k + (s < 0)
+    e = ((w * nr + cell[2]) * na + cell[1]) * na + cell[0]
+    L = []
+    for d in range(3):
+        l = np.ones((n, P))
+        for j in range(n):
+            for m in range(n):
+                if m != j:
+                    l[j] *= (xi[d] - nodes[m]) / (nodes[j] - nodes[m])
+        L.append(l)
+    basis = np.einsum("kp,jp,ip->pkji", L[2], L[1], L[0]).reshape(P, n ** 3)  # node i + n (j + n k)
+    return np.stack([(u[c][e] * basis).sum(axis=1) for c in range(u.shape[0])])
+
+
+def hemisphere_flux(u, N, nr, na, r_in, r_out, nodes, R, n_mu=48, n_phi=96):
+    """Flux of B~ through the upper hemisphere of the coordinate sphere of radius R:
+    Gauss-Legendre in cos(theta) on [0, 1], uniform in phi."""
+    import numpy as np
+    g, gw = np.polynomial.legendre.leggauss(n_mu)
+    mu, wmu = 0.5 * (g + 1.0), 0.5 * gw
+    ph = 2.0 * np.pi * (np.arange(n_phi) + 0.5) / n_phi
+    MU, PH = np.meshgrid(mu, ph, indexing="ij")
+    st = np.sqrt(1.0 - MU ** 2)
+    nrm = np.stack([st * np.cos(PH), st * np.sin(PH), MU]).reshape(3, -1)
+    B = _shell_sample(u[3:6], R * nrm, N, nr, na, r_in, r_out, nodes)
+    Bn = (B * nrm).sum(axis=0).reshape(n_mu, n_phi)
+    return float((wmu[:, None] * Bn).sum() * (2.0 * np.pi / n_phi) * R * R)
+
+
+def run_vacuum_wald(spins=(0.0, 0.5, 0.7, 0.8), degree=5, n_radial=16, n_angular=4, r_in=1.2, r_out=125.0,
+                    t_end=125.0, cfl=0.25, checks=(80.0, 100.0, 125.0)):
+    """The vacuum Wald problem (Sec. IV B 2) on the shell: Kerr-Schild background of
+    spin a (M = 1, Cartesian Kerr-Schild coordinates), Wald's magnetic field with
+    E = 0 at t = 0, eta = 0, outflow inner sphere inside the horizon, no-incoming-
+    Poynting outer sphere, all DG.  The flux of B~ through the upper half of the outer
+    horizon is measured through the upper hemisphere of the coordinate sphere that
+    shares the horizon's equator (radius sqrt(r_+^2 + a^2); B~ is divergence-free
+    between the two) and compared with King's closed form (Eq. vacuum wald magnetic
+    flux) at the check times."""
+    import numpy as np
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    N = degree
+    nodes = np.asarray(grffe.operator(N, 0))
+    rows = []
+    for a in spins:
+        x = grffe.shell_points(N, n_radial, n_angular, r_in, r_out)
+        xf = grffe.shell_points(N, n_radial, n_angular, r_in, r_out, fd=True)
+        bg = I.kerr_schild_background(x[0], x[1], x[2], 1.0, a)
+        p = grffe.default_params(eta=0.0, cfl=cfl, hybrid=grffe.HYBRID_DG_ONLY)
+        dom = grffe.Domain.shell(N, n_radial, n_angular, r_in, r_out, grffe.BC_OUTFLOW,
+                                 grffe.BC_NO_INCOMING_POYNTING, params=p,
+                                 bg=torch.from_numpy(np.ascontiguousarray(bg)).cuda())
+        dom.init_from_fd(torch.from_numpy(np.ascontiguousarray(I.wald_vacuum(xf[0], xf[1], xf[2], 1.0, a))).cuda())
+        dt = dom.dt()
+        rp = 1.0 + np.sqrt(1.0 - a * a)
+        R = np.sqrt(rp * rp + a * a)
+        king = I.king_flux(a)
+        t, flux, t0 = 0.0, {}, time.perf_counter()
+        steps = 0
+        for tc in checks:
+            n = int(round((tc - t) / dt))
+            chunk = 2000
+            while n > 0:
+                k = min(chunk, n)
+                dom.step(k)
+                n -= k
+                steps += k
+                t += k * dt
+                torch.cuda.synchronize()
+                print(f"#   vacuum Wald a = {a}: t = {t:.1f}M", file=sys.stderr, flush=True)
+            u = dom.get_dg().cpu().numpy()
+            if not np.all(np.isfinite(u)):
+                flux[tc] = None
+                break
+            flux[tc] = hemisphere_flux(u, N, n_radial, n_angular, r_in, r_out, nodes, R)
+        wall = time.perf_counter() - t0
+        dom.close()
+        rows.append({"spin": a, "dt": dt, "steps": steps, "wall_s": wall, "r_plus": rp,
+                     "flux": {str(k): v for k, v in flux.items()}, "king": king,
+                     "rel_error_last": None if flux.get(checks[-1]) is None else flux[checks[-1]] / king - 1.0})
+    return {"workload": f"vacuum Wald problem on the shell r = {r_in}M..{r_out}M, {n_radial}x{6 * n_angular ** 2} "
+                        f"P{degree} elements, Kerr-Schild M=1 (Cartesian KS), eta=0, CFL {cfl}, outflow inner / "
+                        "no-incoming-Poynting outer sphere, all DG", "rows": rows}
+
+
 def run_adjoint_frozen(steps=40, every=20):
     """The benchmark's current sheet, 8^3 P5 elements, with the start-up DG/FD
     partition held fixed (forced mode): forward steps, one-step adjoints through DG
@@ -1074,6 +1187,9 @@ def main():
     if args.only == "adjoint_adaptive":
         print(json.dumps(run_adjoint_adaptive()))
         return
+    if args.only == "vacuum_wald":
+        print(json.dumps(run_vacuum_wald(tuple(float(v) for v in args.spins.split(",")))))
+        return
     if args.only == "shell_wald":
         degs = {int(v) for v in args.shell_degrees.split(",")}
         print(json.dumps(run_shell_wald(tuple(c for c in EXACT_WALD_TABLE if c[0] in degs))))
@@ -1136,7 +1252,8 @@ def main():
                 ("adjoint_sheet_8^3_frozen_partition", lambda: run_adjoint_frozen()),
                 ("exact_wald_shell_table", lambda: run_shell_wald())]
         if args.extras == "all":
-            jobs += [("batch_64_fp64_autotuned", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0, tune=True)),
+            jobs += [("vacuum_wald_king_flux", lambda: run_vacuum_wald()),
+                     ("batch_64_fp64_autotuned", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0, tune=True)),
                      ("accuracy_smooth_fast_wave_4^3", lambda: run_accuracy_smooth_wave(20)),
                      ("exact_wald_convergence", lambda: run_exact_wald()),
                      ("forced_fd_fraction_alfven_8x32x8", lambda: run_forced_fractions_alfven(args.extra_steps, 2))]

@@ -336,6 +336,41 @@ def wald_a0(x, y, z, M=1.0, B0=1.0):
     return U
 
 
+def _wald_potential(x, y, z, M, a, B0):
+    """Spatial covariant components A_k of Wald's potential A = (B0 / 2) (d_phi + 2 a d_t)
+    (Eq. exact wald solution) in Cartesian Kerr-Schild coordinates: with the Killing
+    vectors d_phi = -y d_x + x d_y and d_t, A_k = (B0 / 2) (gamma_kj phi^j + 2 a g_k0),
+    where g_k0 = gamma_kj beta^j (complex-safe)."""
+    _, beta, g, _, _ = _ks_3p1(x, y, z, M, a)
+    phi = (-y, x, 0.0 * x)
+    return [0.5 * B0 * sum(g[k][j] * (phi[j] + 2.0 * a * beta[j]) for j in range(3)) for k in range(3)]
+
+
+@_at_singularity_nan
+def wald_vacuum(x, y, z, M=1.0, a=0.0, B0=1.0):
+    """Initial data of the vacuum Wald problem (Sec. IV B 2): the magnetic field of
+    Wald's potential, B~^i = [ijk] d_j A_k (densitized, so divergence-free in
+    coordinates), with E~ = psi~ = phi~ = q~ = 0.  At a = 0 it is the uniform
+    B~ = (0, 0, B0)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    z = np.asarray(z, np.float64)
+    dA = _cstep(lambda x_, y_, z_: _wald_potential(x_, y_, z_, M, a, B0), x, y, z)  # dA[j][k] = d_j A_k
+    U = np.zeros((9,) + x.shape)
+    U[3] = dA[1][2] - dA[2][1]
+    U[4] = dA[2][0] - dA[0][2]
+    U[5] = dA[0][1] - dA[1][0]
+    return U
+
+
+def king_flux(a, B0=1.0):
+    """Magnetic flux of the stationary vacuum field through the upper half of the outer
+    horizon (Eq. vacuum wald magnetic flux), in units M = 1: pi r_+^2 B0 (1 - a^4 / r_+^4)
+    with r_+ = 1 + sqrt(1 - a^2) and a the dimensionless spin."""
+    rp = 1.0 + np.sqrt(1.0 - a * a)
+    return np.pi * rp * rp * B0 * (1.0 - a ** 4 / rp ** 4)
+
+
 def rotator_dipole(x, y, z, mu=1.0, theta=0.0, delta=0.1):
     """Initial data of the rotating-star tests (Sec. IV C, flat space): the field of
     the regularised dipole A = mu m x r / (r^2 + delta^2)^(3/2) with moment direction

@@ -205,3 +205,28 @@ def test_shell_exact_wald_table():
         assert abs(err / want - 1.0) < (0.05 if want > 1e-10 else 0.15), (N, nr, err, want)
         if order_paper is not None:
             assert abs(order - order_paper) < 0.15, (N, nr, order, order_paper)
+
+
+def test_shell_rhs_parity_spinning_hole():
+    """The vacuum Wald set-up (Sec. IV B 2): Kerr-Schild a = 0.7, the inner sphere at
+    1.2M inside the horizon and outside the ring singularity, no-incoming-Poynting
+    outer sphere, Wald's field of the spinning hole with E = 0 plus perturbations."""
+    torch = _torch()
+    from paper_2404_01531_amd import grffe
+    _say("shell rhs, a = 0.7")
+    N, nr, na, a = 5, 2, 2, 0.7
+    p = grffe.default_params(hybrid=0, eta=0.0)
+    geo = S.Shell(N, nr, na, 1.2, 30.0)
+    x = geo.x_dg
+    bg = I.kerr_schild_background(x[0], x[1], x[2], 1.0, a)
+    sh = S.Shell(N, nr, na, 1.2, 30.0, bc_inner=S.SHELL_OUTFLOW, bc_outer=S.SHELL_NO_INCOMING_POYNTING, bg=bg,
+                 params=oracle_params(p))
+    dom = grffe.Domain.shell(N, nr, na, 1.2, 30.0, S.SHELL_OUTFLOW, S.SHELL_NO_INCOMING_POYNTING, params=p,
+                             bg=torch.from_numpy(np.ascontiguousarray(bg.reshape(26, sh.E, -1))).cuda())
+    U = _perturbed(sh, I.wald_vacuum(x[0], x[1], x[2], 1.0, a), 5)
+    want = S.shell_rhs(sh, U)
+    got = _rhs_lib(dom, U)
+    for c in range(9):
+        scale = max(np.abs(want[c]).max(), 1e-300)
+        assert np.abs(got[c] - want[c]).max() <= 1e-12 * scale, (c, np.abs(got[c] - want[c]).max(), scale)
+    dom.close()
