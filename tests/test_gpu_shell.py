@@ -230,3 +230,20 @@ def test_shell_rhs_parity_spinning_hole():
         scale = max(np.abs(want[c]).max(), 1e-300)
         assert np.abs(got[c] - want[c]).max() <= 1e-12 * scale, (c, np.abs(got[c] - want[c]).max(), scale)
     dom.close()
+
+
+def test_vacuum_wald_king_flux():
+    """The vacuum Wald problem (Sec. IV B 2) at a = 0.9 on the paper's 16 x 96 P5 shell
+    grid (inner sphere at 1.2M, inside the horizon and outside the ring singularity of
+    the Cartesian Kerr-Schild coordinates), evolved from Wald's field with E = 0 to
+    t = 125M: the flux through the upper half of the horizon against King's closed
+    form (Eq. vacuum wald magnetic flux), 15% below the flux of the non-spinning hole.
+    Measured 0.95% above it at t = 125M, falling by 0.3% over the last 25M."""
+    _torch()
+    import bench
+    _say("vacuum Wald a = 0.9 to t = 125M")
+    rec = bench.run_vacuum_wald(spins=(0.9,), checks=(125.0,))
+    row = rec["rows"][0]
+    _say("flux", row["flux"], "King", row["king"])
+    assert row["flux"]["125.0"] is not None
+    assert abs(row["rel_error_last"]) < 0.02
