@@ -608,10 +608,11 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adj_slab(KArgs a, FdAdj b) 
     if (o >= 0 && upd[o] == 1) need |= 1 << f;
   }
   if (!need) return;
+  // the ten components pass the three stages together (four barriers per face)
   __shared__ double sP[m * n];
-  __shared__ double sG[3 * m * m];  // [l][c2][c1]
-  __shared__ double sB[3 * n * m];  // [l][a2][c1]
-  __shared__ double sA[3 * n * n];  // [l][a2][a1]
+  __shared__ double sG[NR * 3 * m * m];  // [k][l][c2][c1]
+  __shared__ double sB[NR * 3 * n * m];  // [k][l][a2][c1]
+  __shared__ double sA[NR * 3 * n * n];  // [k][l][a2][a1]
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int p = act ? t : 0;
@@ -625,36 +626,39 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_adj_slab(KArgs a, FdAdj b) 
     const int e = a.nbr[g * 6 + f];
     const int d = f >> 1, s = f & 1, fe = f ^ 1;
     const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
-    for (int k = 0; k < NR; ++k) {
-      __syncthreads();
-      for (int q = t; q < 3 * m * m; q += TPB)
-        sG[q] = b.gbar[(((size_t)k * a.E + e) * 6 + fe) * (3 * m * m) + q];
-      __syncthreads();
-      // second tangential axis back: c2 (m) -> a2 (n)
-      for (int q = t; q < 3 * n * m; q += TPB) {
-        const int c1 = q % m, a2 = (q / m) % n, l = q / (n * m);
-        double acc = 0.0;
-        for (int z = 0; z < m; ++z) acc += sP[z * n + a2] * sG[(l * m + z) * m + c1];
-        sB[q] = acc;
-      }
-      __syncthreads();
-      // first tangential axis back: c1 (m) -> a1 (n)
-      for (int q = t; q < 3 * n * n; q += TPB) {
-        const int a1 = q % n, rest = q / n;  // rest = l n + a2
-        double acc = 0.0;
-        for (int z = 0; z < m; ++z) acc += sP[z * n + a1] * sB[rest * m + z];
-        sA[q] = acc;
-      }
-      __syncthreads();
-      // normal axis back: layers l (cells l or m-1-l) -> node index along d
-      if (act) {
-        const int zi = idx[d], a1 = idx[t1ax], a2 = idx[t2ax];
+    __syncthreads();
+    for (int q = t; q < NR * 3 * m * m; q += TPB) {
+      const int k = q / (3 * m * m), r = q % (3 * m * m);
+      sG[q] = b.gbar[(((size_t)k * a.E + e) * 6 + fe) * (3 * m * m) + r];
+    }
+    __syncthreads();
+    // second tangential axis back: c2 (m) -> a2 (n)
+    for (int q = t; q < NR * 3 * n * m; q += TPB) {
+      const int c1 = q % m, a2 = (q / m) % n, kl = q / (n * m);  // kl = k 3 + l
+      double acc = 0.0;
+      for (int z = 0; z < m; ++z) acc += sP[z * n + a2] * sG[(kl * m + z) * m + c1];
+      sB[q] = acc;
+    }
+    __syncthreads();
+    // first tangential axis back: c1 (m) -> a1 (n)
+    for (int q = t; q < NR * 3 * n * n; q += TPB) {
+      const int a1 = q % n, rest = q / n;  // rest = (k 3 + l) n + a2
+      double acc = 0.0;
+      for (int z = 0; z < m; ++z) acc += sP[z * n + a1] * sB[rest * m + z];
+      sA[q] = acc;
+    }
+    __syncthreads();
+    // normal axis back: layers l (cells l or m-1-l) -> node index along d
+    if (act) {
+      const int zi = idx[d], a1 = idx[t1ax], a2 = idx[t2ax];
+      double w3[3];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) w3[l] = sP[(s ? (m - 1 - l) : l) * n + zi];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
         double acc = 0.0;
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          const int cell = s ? (m - 1 - l) : l;
-          acc += sP[cell * n + zi] * sA[(l * n + a2) * n + a1];
-        }
+        for (int l = 0; l < 3; ++l) acc += w3[l] * sA[((k * 3 + l) * n + a2) * n + a1];
         if (k < NV) Wb[k] += acc;
         else Jb[d] += acc;
       }
