@@ -65,7 +65,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--only", choices=("sheet", "batch", "adjoint_adaptive", "shell_wald", "vacuum_wald"), default=None,
+    ap.add_argument("--only", choices=("sheet", "batch", "adjoint_adaptive", "shell_wald", "vacuum_wald", "shell_scale"),
+                    default=None,
                     help="run one secondary workload alone and print its record (profiling runs)")
     ap.add_argument("--shell-degrees", default="5,7,9",
                     help="degrees of the exact-Wald shell rows (--only shell_wald)")
@@ -1075,6 +1076,54 @@ def run_vacuum_wald(spins=(0.0, 0.5, 0.7, 0.8), degree=5, n_radial=16, n_angular
                         "no-incoming-Poynting outer sphere, all DG", "rows": rows}
 
 
+def run_shell_scale(steps=20, warmup=5, degree=5, n_radial=32, n_angular=8, spin=0.7):
+    """The curved-element DG step at a full-chip size: the magnetospheric-Wald grid of
+    Sec. IV B 3 (32 x 384 elements; here P5 from 1.2M to 125M in Cartesian
+    Kerr-Schild coordinates, a = 0.7, the vacuum Wald data, eta = 1e5, all DG), timed
+    over `steps` steps; the DG substep's mean launch from HIP events and its
+    algorithmic HBM fraction (the box kernel's bytes per node plus 72 B of inverse
+    Jacobian)."""
+    import numpy as np
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    N, n = degree, degree + 1
+    r_in, r_out = 1.2, 125.0
+    x = grffe.shell_points(N, n_radial, n_angular, r_in, r_out)
+    E = x.shape[1]
+    bg = I.kerr_schild_background(x[0], x[1], x[2], 1.0, spin)
+    p = grffe.default_params(eta=1e5, cfl=0.25, hybrid=grffe.HYBRID_DG_ONLY)
+    dom = grffe.Domain.shell(N, n_radial, n_angular, r_in, r_out, grffe.BC_OUTFLOW, grffe.BC_NO_INCOMING_POYNTING,
+                             params=p, bg=torch.from_numpy(np.ascontiguousarray(bg)).cuda())
+    del bg
+    # the data set at the nodes (the FD start-up grid of 16 M cells is not needed for timing)
+    dom.set_state(torch.from_numpy(np.ascontiguousarray(I.wald_vacuum(x[0], x[1], x[2], 1.0, spin))).cuda(),
+                  torch.zeros((9, E, (2 * N + 1) ** 3), dtype=torch.float64, device="cuda"),
+                  torch.zeros(E, dtype=torch.int32, device="cuda"))
+    dom.step(warmup)
+    fam = grffe.KERNEL_FAMILIES["dg_substep"]
+    dom.timing_enable(fam, period=TIMING_PERIOD)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dom.step(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    tot, launches = dom.timing_read(fam)
+    dom.timing_enable()
+    ok = bool(torch.isfinite(dom.get_dg()).all().item())
+    dom.close()
+    nodes = E * n ** 3
+    mean_us = tot * 1e3 / max(launches, 1)
+    per_node = sum(DG_BYTES_PER_NODE.values()) / 3.0 + DG_BG_BYTES_PER_NODE + 72.0
+    achieved = nodes * per_node / (mean_us * 1e-6) / 1e9
+    return {"workload": f"shell {r_in}M..{r_out}M, {n_radial}x{6 * n_angular ** 2} P{N} elements, Kerr-Schild a={spin} "
+                        "(Cartesian KS), vacuum Wald data, eta 1e5, all DG", "elements": E, "dg_nodes": nodes,
+            "ms_per_step": ms, "node_updates_per_s": 3 * nodes / (ms * 1e-3), "finite": ok,
+            "dg_mapped_mean_us": mean_us, "launches": launches, "algorithmic_bytes_per_node": per_node,
+            "achieved_GBps": achieved, "frac_hbm": achieved / 8000.0}
+
+
 def run_adjoint_frozen(steps=40, every=20):
     """The benchmark's current sheet, 8^3 P5 elements, with the start-up DG/FD
     partition held fixed (forced mode): forward steps, one-step adjoints through DG
@@ -1187,6 +1236,9 @@ def main():
     if args.only == "adjoint_adaptive":
         print(json.dumps(run_adjoint_adaptive()))
         return
+    if args.only == "shell_scale":
+        print(json.dumps(run_shell_scale(args.steps, args.warmup)))
+        return
     if args.only == "vacuum_wald":
         print(json.dumps(run_vacuum_wald(tuple(float(v) for v in args.spins.split(",")))))
         return
@@ -1250,7 +1302,8 @@ def main():
                 ("adjoint_poynting_kerr_schild_8^3", lambda: run_adjoint()),
                 ("adjoint_poynting_kerr_schild_8^3_adaptive", lambda: run_adjoint_adaptive()),
                 ("adjoint_sheet_8^3_frozen_partition", lambda: run_adjoint_frozen()),
-                ("exact_wald_shell_table", lambda: run_shell_wald())]
+                ("exact_wald_shell_table", lambda: run_shell_wald()),
+                ("shell_32x384_p5", lambda: run_shell_scale(args.extra_steps, 3))]
         if args.extras == "all":
             jobs += [("vacuum_wald_king_flux", lambda: run_vacuum_wald()),
                      ("batch_64_fp64_autotuned", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0, tune=True)),
