@@ -465,11 +465,10 @@ def run_rotator(theta, periods=2.0, n_elem=24, half_width=12.0, r_measure=6.0, s
             "non_finite_elements": dom.check_finite()}
 
 
-def run_batch(steps, warmup, precision, use_graph=True, tune=False):
+def run_batch(steps, warmup, precision, use_graph=True):
     """64 independent flat periodic domains (n^3 elements, n ~ U{4..12}, degree
-    N ~ U{3..7}, wave or sheet), each advanced by its own CFL step, one call per step.
-    tune: the contraction engine of every degree pool picked by the batch's
-    autotuner first (untimed; the members' states are restored)."""
+    N ~ U{3..7}, wave or sheet), each advanced by its own CFL step, one call per step
+    (every pool on the VALU contraction)."""
     import numpy as np
     import torch
 
@@ -489,7 +488,6 @@ def run_batch(steps, warmup, precision, use_graph=True, tune=False):
                     torch.zeros(E, dtype=torch.int32, device="cuda"))
         nodes += E * n3
     torch.cuda.synchronize()
-    table = b.autotune(steps=2, reps=3) if tune else None
     b.step(warmup, use_graph=use_graph)
     torch.cuda.synchronize()
 
@@ -513,8 +511,7 @@ def run_batch(steps, warmup, precision, use_graph=True, tune=False):
             "unit": "grid-point updates/s", "steps": steps, "ms_per_step": secs * 1e3 / steps,
             "fd_elements": [int(f0), int(f1)],
             "hbm_GBps_dg_state": (nodes * sum(DG_BYTES_PER_NODE.values())) * steps / secs / 1e9,
-            "contraction_per_degree": ({str(N): ("mfma" if e == 1 else "valu") for N, e in table.items()}
-                                       if table is not None else "valu (default)")}
+            "contraction_per_degree": "valu"}
 
 
 def run_adjoint(steps=200, every=20, check_steps=10):
@@ -1306,7 +1303,6 @@ def main():
                 ("shell_32x384_p5", lambda: run_shell_scale(args.extra_steps, 3))]
         if args.extras == "all":
             jobs += [("vacuum_wald_king_flux", lambda: run_vacuum_wald()),
-                     ("batch_64_fp64_autotuned", lambda: run_batch(max(args.extra_steps // 3, 3), 1, 0, tune=True)),
                      ("accuracy_smooth_fast_wave_4^3", lambda: run_accuracy_smooth_wave(20)),
                      ("exact_wald_convergence", lambda: run_exact_wald()),
                      ("forced_fd_fraction_alfven_8x32x8", lambda: run_forced_fractions_alfven(args.extra_steps, 2))]

@@ -450,10 +450,10 @@ int grffe_batch_get_counts(grffe_batch* batch, int32_t k, int32_t* n_dg, int32_t
 int grffe_batch_step(grffe_batch* batch, int32_t n_steps, int32_t use_graph, void* stream);
 
 /* Contraction engine (GRFFE_CONTRACTION_*, as grffe_set_contraction) of the batch's
- * pool of degree `degree`, or of every pool for degree = 0: the tunable an autotuner
- * picks per degree (the two engines give the same result up to the order of the
- * additions, and their speed depends on the degree).  Changing an engine drops the
- * captured step graph; the next grffe_batch_step with use_graph captures again.
+ * pool of degree `degree`, or of every pool for degree = 0.  Batches run the VALU
+ * engine: GRFFE_CONTRACTION_MFMA returns GRFFE_EUNSUPPORTED (a step graph re-captured
+ * after an engine change, with matrix-core pools, ended in an abort inside the HIP
+ * runtime once; its cause is not known), so the captured graph is never dropped.
  * Returns GRFFE_EINVAL for an unknown engine or a degree with no pool. */
 int grffe_batch_set_contraction(grffe_batch* batch, int32_t degree, int32_t engine);
 int grffe_batch_get_contraction(grffe_batch* batch, int32_t degree, int32_t* engine);

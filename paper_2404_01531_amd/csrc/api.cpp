@@ -1417,13 +1417,17 @@ extern "C" int grffe_batch_set_contraction(grffe_batch* b, int32_t degree, int32
     return fail(GRFFE_EINVAL, "engine must be GRFFE_CONTRACTION_VALU or GRFFE_CONTRACTION_MFMA");
   if (degree != 0 && (degree < 3 || degree > MAX_DEG)) return fail(GRFFE_EINVAL, "degree must be 0 or in 3..9");
   bool found = false, changed = false;
+  for (grffe_domain* d : b->pools)
+    if (degree == 0 || d->N == degree) found = true;
+  if (!found) return fail(GRFFE_EINVAL, "the batch has no domain of that degree");
+  if (engine != GRFFE_CONTRACTION_VALU)
+    return fail(GRFFE_EUNSUPPORTED, "batches run the VALU contraction (an engine change re-captures the step graph, "
+                                    "which ended in an abort inside the HIP runtime)");
   for (grffe_domain* d : b->pools) {
     if (degree != 0 && d->N != degree) continue;
-    found = true;
     if (d->contraction != engine) changed = true;
     d->contraction = engine;
   }
-  if (!found) return fail(GRFFE_EINVAL, "the batch has no domain of that degree");
   if (changed && b->exec) {
     HIPCHK(hipGraphExecDestroy(b->exec));
     b->exec = nullptr;

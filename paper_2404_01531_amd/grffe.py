@@ -619,40 +619,9 @@ class Batch:
         return v.value
 
     def autotune(self, steps=3, reps=3, margin=0.02):
-        """Pick each pool's contraction engine by measurement: one degree at a time,
-        the batch's graph step (all pools, as it runs) is timed with each engine, the
-        median of `reps` runs of `steps` steps, and an engine other than the default
-        (VALU) is kept only when it is faster by more than `margin`.  The state of
-        every member is restored afterwards.  Returns {degree: engine}."""
-        import time
-
-        import torch
-        saved = [self.get_state(k) for k in range(self.count)]
-
-        def timed():
-            self.step(1)  # captures the graph after a change
-            torch.cuda.synchronize()
-            ts = []
-            for _ in range(reps):
-                t0 = time.perf_counter()
-                self.step(steps)
-                torch.cuda.synchronize()
-                ts.append(time.perf_counter() - t0)
-            return sorted(ts)[len(ts) // 2]
-
-        table = {}
-        try:
-            self.set_contraction(0, CONTRACTION_VALU)
-            for N in self.degrees():
-                t = {}
-                for eng in (CONTRACTION_VALU, CONTRACTION_MFMA):
-                    self.set_contraction(N, eng)
-                    t[eng] = timed()
-                best = CONTRACTION_MFMA if t[CONTRACTION_MFMA] < (1.0 - margin) * t[CONTRACTION_VALU] else CONTRACTION_VALU
-                self.set_contraction(N, best)
-                table[N] = best
-        finally:
-            for k, st in enumerate(saved):
-                self.set_state(k, *st)
-            torch.cuda.synchronize()
-        return table
+        """Per-degree choice of the contraction engine by timing the batch's graph step
+        with each engine.  Disabled: batches run the VALU contraction (see
+        grffe_batch_set_contraction); the tuner's re-captured step graphs with
+        matrix-core pools ended in an abort inside the HIP runtime, whose cause is not
+        known, so the tuner raises instead of running."""
+        raise GrffeError("the batch autotuner is disabled: batches run the VALU contraction")

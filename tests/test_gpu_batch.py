@@ -133,6 +133,9 @@ def test_batch_graph_replays_equal_eager_and_standalone():
     _say("graph replays: 4 steps bit-identical to eager and stand-alone runs")
 
 
+@pytest.mark.skip(reason="the batch autotuner and the matrix-core engine on batches are switched off: a "
+                         "re-captured step graph with matrix-core pools ended in an abort inside the HIP runtime "
+                         "(cause not found by reading the capture, drop and launch code)")
 def test_batch_autotune_contraction_per_degree():
     """The autotuner picks each degree pool's contraction engine by timing the
     batch's graph step: it returns one engine per degree, leaves the members' states
@@ -196,3 +199,10 @@ def test_batch_rejects_bad_input():
     b = _make_batch(MEMBERS[:1])
     with pytest.raises(grffe.GrffeError):
         b.dt(5)
+    # batches keep the VALU contraction; the tuner is switched off (both refuse
+    # before any device work)
+    with pytest.raises(grffe.GrffeError):
+        b.set_contraction(0, grffe.CONTRACTION_MFMA)
+    with pytest.raises(grffe.GrffeError):
+        b.autotune()
+    b.set_contraction(0, grffe.CONTRACTION_VALU)
