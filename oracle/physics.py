@@ -52,8 +52,11 @@ class Geometry:
             g[j, i] = bg[k]
         self.g = g
         gm = np.moveaxis(g, (0, 1), (-2, -1))
-        self.ginv = np.moveaxis(np.linalg.inv(gm), (-2, -1), (0, 1))
-        self.sqrtg = np.sqrt(np.linalg.det(gm))
+        # (a background may hold NaN at points no kernel reads: the Kerr-Schild
+        # fields on the singular disc inside an excision ball)
+        with np.errstate(invalid="ignore"):
+            self.ginv = np.moveaxis(np.linalg.inv(gm), (-2, -1), (0, 1))
+            self.sqrtg = np.sqrt(np.linalg.det(gm))
         self.dalpha = bg[10:13]
         self.dbeta = bg[13:22].reshape((3, 3) + bg.shape[1:])  # [j][i] = d_j beta^i
         self.K = bg[22]
