@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--shell-degrees", default="5,7,9",
                     help="degrees of the exact-Wald shell rows (--only shell_wald)")
     ap.add_argument("--spins", default="0,0.5,0.7,0.8", help="spins of the vacuum Wald runs (--only vacuum_wald)")
+    ap.add_argument("--coords", choices=("cartesian", "spherical"), default="spherical",
+                    help="Kerr-Schild coordinates of the vacuum Wald runs (--only vacuum_wald)")
     ap.add_argument("--contraction", choices=("valu", "mfma"), default="valu",
                     help="DG derivative contraction engine of the black-hole domains (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1014,36 +1016,44 @@ def hemisphere_flux(u, N, nr, na, r_in, r_out, nodes, R, n_mu=48, n_phi=96):
     return float((wmu[:, None] * Bn).sum() * (2.0 * np.pi / n_phi) * R * R)
 
 
-def run_vacuum_wald(spins=(0.0, 0.5, 0.7, 0.8), degree=5, n_radial=16, n_angular=4, r_in=1.2, r_out=125.0,
-                    t_end=125.0, cfl=0.25, checks=(80.0, 100.0, 125.0)):
-    """The vacuum Wald problem (Sec. IV B 2) on the shell: Kerr-Schild background of
-    spin a (M = 1, Cartesian Kerr-Schild coordinates), Wald's magnetic field with
-    E = 0 at t = 0, eta = 0, outflow inner sphere inside the horizon, no-incoming-
-    Poynting outer sphere, all DG.  The flux of B~ through the upper half of the outer
-    horizon is measured through the upper hemisphere of the coordinate sphere that
-    shares the horizon's equator (radius sqrt(r_+^2 + a^2); B~ is divergence-free
-    between the two) and compared with King's closed form (Eq. vacuum wald magnetic
-    flux) at the check times."""
+def run_vacuum_wald(spins=(0.0, 0.5, 0.7, 0.8), degree=5, n_radial=16, n_angular=4, r_in=None, r_out=125.0,
+                    t_end=125.0, cfl=0.25, checks=(80.0, 100.0, 125.0), coords="cartesian"):
+    """The vacuum Wald problem (Sec. IV B 2) on the shell: Kerr background of spin a
+    (M = 1), Wald's magnetic field with E = 0 at t = 0, eta = 0, outflow inner sphere
+    inside the horizon, no-incoming-Poynting outer sphere, all DG.  coords
+    "spherical": the Cartesian projection of spherical Kerr-Schild coordinates
+    (Appendix B), inner sphere at M as in the paper, the horizon the sphere r_+;
+    "cartesian": Kerr-Schild Cartesian coordinates, inner sphere at 1.2M (inside the
+    horizon, outside the ring singularity for a <= 0.9), the horizon the ellipsoid
+    sharing its equator with the sphere of radius sqrt(r_+^2 + a^2), through whose
+    upper hemisphere the flux is measured (B~ is divergence-free between the two).
+    The flux of B~ through the upper half of the horizon is compared with King's
+    closed form (Eq. vacuum wald magnetic flux) at the check times."""
     import numpy as np
     import torch
 
     from paper_2404_01531_amd import grffe
     from paper_2404_01531_amd import inputs as I
     N = degree
+    sph = coords == "spherical"
+    if r_in is None:
+        r_in = 1.0 if sph else 1.2
+    bgf = I.spherical_kerr_schild_background if sph else I.kerr_schild_background
+    datf = I.wald_vacuum_spherical if sph else I.wald_vacuum
     nodes = np.asarray(grffe.operator(N, 0))
     rows = []
     for a in spins:
         x = grffe.shell_points(N, n_radial, n_angular, r_in, r_out)
         xf = grffe.shell_points(N, n_radial, n_angular, r_in, r_out, fd=True)
-        bg = I.kerr_schild_background(x[0], x[1], x[2], 1.0, a)
+        bg = bgf(x[0], x[1], x[2], 1.0, a)
         p = grffe.default_params(eta=0.0, cfl=cfl, hybrid=grffe.HYBRID_DG_ONLY)
         dom = grffe.Domain.shell(N, n_radial, n_angular, r_in, r_out, grffe.BC_OUTFLOW,
                                  grffe.BC_NO_INCOMING_POYNTING, params=p,
                                  bg=torch.from_numpy(np.ascontiguousarray(bg)).cuda())
-        dom.init_from_fd(torch.from_numpy(np.ascontiguousarray(I.wald_vacuum(xf[0], xf[1], xf[2], 1.0, a))).cuda())
+        dom.init_from_fd(torch.from_numpy(np.ascontiguousarray(datf(xf[0], xf[1], xf[2], 1.0, a))).cuda())
         dt = dom.dt()
         rp = 1.0 + np.sqrt(1.0 - a * a)
-        R = np.sqrt(rp * rp + a * a)
+        R = rp if sph else np.sqrt(rp * rp + a * a)
         king = I.king_flux(a)
         t, flux, t0 = 0.0, {}, time.perf_counter()
         steps = 0
@@ -1069,8 +1079,8 @@ def run_vacuum_wald(spins=(0.0, 0.5, 0.7, 0.8), degree=5, n_radial=16, n_angular
                      "flux": {str(k): v for k, v in flux.items()}, "king": king,
                      "rel_error_last": None if flux.get(checks[-1]) is None else flux[checks[-1]] / king - 1.0})
     return {"workload": f"vacuum Wald problem on the shell r = {r_in}M..{r_out}M, {n_radial}x{6 * n_angular ** 2} "
-                        f"P{degree} elements, Kerr-Schild M=1 (Cartesian KS), eta=0, CFL {cfl}, outflow inner / "
-                        "no-incoming-Poynting outer sphere, all DG", "rows": rows}
+                        f"P{degree} elements, Kerr M=1 ({coords} Kerr-Schild coordinates), eta=0, CFL {cfl}, "
+                        "outflow inner / no-incoming-Poynting outer sphere, all DG", "rows": rows}
 
 
 def run_shell_scale(steps=20, warmup=5, degree=5, n_radial=32, n_angular=8, spin=0.7):
@@ -1237,7 +1247,7 @@ def main():
         print(json.dumps(run_shell_scale(args.steps, args.warmup)))
         return
     if args.only == "vacuum_wald":
-        print(json.dumps(run_vacuum_wald(tuple(float(v) for v in args.spins.split(",")))))
+        print(json.dumps(run_vacuum_wald(tuple(float(v) for v in args.spins.split(",")), coords=args.coords)))
         return
     if args.only == "shell_wald":
         degs = {int(v) for v in args.shell_degrees.split(",")}

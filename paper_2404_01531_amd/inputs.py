@@ -141,16 +141,54 @@ def _cstep(fun, x, y, z, h=1e-30):
     return out  # out[d][k] = d_d of value k
 
 
-@_at_singularity_nan
-def kerr_schild_background(x, y, z, M=1.0, a=0.0):
-    """The 26 background fields at the given points (see module docstring)."""
-    x = np.asarray(x, np.float64)
-    y = np.asarray(y, np.float64)
-    z = np.asarray(z, np.float64)
+def _sks_map(xb, yb, zb, a):
+    """Kerr-Schild Cartesian coordinates (x, y, z) of the point with Cartesian projection
+    (xb, yb, zb) of the spherical Kerr-Schild coordinates (r, theta, phi) (Appendix B:
+    x = (r cos phi - a sin phi) sin theta, y = (r sin phi + a cos phi) sin theta,
+    z = r cos theta, with xb = r sin theta cos phi, ...): x = xb - a yb / r,
+    y = yb + a xb / r, z = zb, r = |xb|; and the Jacobian J[p][i] = d x^p / d xb^i
+    (complex-safe)."""
+    r = np.sqrt(xb * xb + yb * yb + zb * zb)
+    r3 = r * r * r
+    x = xb - a * yb / r
+    y = yb + a * xb / r
+    one, zero = 1.0 + 0.0 * r, 0.0 * r
+    J = [[one + a * yb * xb / r3, -a / r + a * yb * yb / r3, a * yb * zb / r3],
+         [a / r - a * xb * xb / r3, one - a * xb * yb / r3, -a * xb * zb / r3],
+         [zero, zero, one]]
+    return x, y, zb, J
+
+
+def _inv3(m):
+    """Inverse of a 3x3 matrix of arrays (nested lists), by cofactors."""
+    c = [[m[(j + 1) % 3][(i + 1) % 3] * m[(j + 2) % 3][(i + 2) % 3]
+          - m[(j + 1) % 3][(i + 2) % 3] * m[(j + 2) % 3][(i + 1) % 3] for j in range(3)] for i in range(3)]
+    det = m[0][0] * c[0][0] + m[0][1] * c[1][0] + m[0][2] * c[2][0]
+    return [[c[i][j] / det for j in range(3)] for i in range(3)], det
+
+
+def _sks_3p1(xb, yb, zb, M, a):
+    """alpha, beta^i, gamma_ij, gamma^ij, sqrt(gamma) of the Kerr metric in the
+    Cartesian projection of spherical Kerr-Schild coordinates: the Kerr-Schild
+    fields pulled back through _sks_map (a time-independent change of the spatial
+    coordinates: the lapse is a scalar, the shift a vector, gamma a tensor)."""
+    x, y, z, J = _sks_map(xb, yb, zb, a)
     alpha, beta, g, ginv, sqrtg = _ks_3p1(x, y, z, M, a)
+    Ji, detJ = _inv3(J)  # Ji[i][p] = d xb^i / d x^p
+    gb = [[sum(J[p][i] * J[q][j] * g[p][q] for p in range(3) for q in range(3)) for j in range(3)] for i in range(3)]
+    gib = [[sum(Ji[i][p] * Ji[j][q] * ginv[p][q] for p in range(3) for q in range(3)) for j in range(3)]
+           for i in range(3)]
+    bb = [sum(Ji[i][p] * beta[p] for p in range(3)) for i in range(3)]
+    return alpha, bb, gb, gib, sqrtg * detJ
+
+
+def _background_26(f3p1, x, y, z):
+    """The 26 background fields from a complex-safe function of the points returning
+    (alpha, beta^i, gamma_ij, gamma^ij, sqrt(gamma)) of a stationary metric."""
+    alpha, beta, g, ginv, sqrtg = f3p1(x, y, z)
 
     def flat_vals(x_, y_, z_):
-        al, be, gg, _, sg = _ks_3p1(x_, y_, z_, M, a)
+        al, be, gg, _, sg = f3p1(x_, y_, z_)
         vals = [al] + list(be) + [gg[i][j] for i in range(3) for j in range(3)] + [sg * be[i] for i in range(3)]
         return vals
 
@@ -180,6 +218,26 @@ def kerr_schild_background(x, y, z, M=1.0, a=0.0):
     fields.extend(Gam)
     out = np.stack([np.broadcast_to(np.real(f), x.shape) for f in fields], axis=0).astype(np.float64)
     return out
+
+
+@_at_singularity_nan
+def kerr_schild_background(x, y, z, M=1.0, a=0.0):
+    """The 26 background fields at the given points (see module docstring)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    z = np.asarray(z, np.float64)
+    return _background_26(lambda x_, y_, z_: _ks_3p1(x_, y_, z_, M, a), x, y, z)
+
+
+@_at_singularity_nan
+def spherical_kerr_schild_background(xb, yb, zb, M=1.0, a=0.0):
+    """The 26 background fields of the Kerr metric in the Cartesian projection of
+    spherical Kerr-Schild coordinates (Appendix B), where the horizons are the
+    spheres r = M (1 +- sqrt(1 - a^2)); equal to kerr_schild_background at a = 0."""
+    xb = np.asarray(xb, np.float64)
+    yb = np.asarray(yb, np.float64)
+    zb = np.asarray(zb, np.float64)
+    return _background_26(lambda x_, y_, z_: _sks_3p1(x_, y_, z_, M, a), xb, yb, zb)
 
 
 def flat_background(shape):
@@ -357,6 +415,27 @@ def wald_vacuum(x, y, z, M=1.0, a=0.0, B0=1.0):
     z = np.asarray(z, np.float64)
     dA = _cstep(lambda x_, y_, z_: _wald_potential(x_, y_, z_, M, a, B0), x, y, z)  # dA[j][k] = d_j A_k
     U = np.zeros((9,) + x.shape)
+    U[3] = dA[1][2] - dA[2][1]
+    U[4] = dA[2][0] - dA[0][2]
+    U[5] = dA[0][1] - dA[1][0]
+    return U
+
+
+@_at_singularity_nan
+def wald_vacuum_spherical(xb, yb, zb, M=1.0, a=0.0, B0=1.0):
+    """The vacuum Wald initial data in the Cartesian projection of spherical
+    Kerr-Schild coordinates: Wald's potential pulled back, A_bar_i = (d x^p / d xb^i) A_p,
+    B~^i = [ijk] d_j A_bar_k (densitized), E~ = psi~ = phi~ = q~ = 0."""
+    xb = np.asarray(xb, np.float64)
+    yb = np.asarray(yb, np.float64)
+    zb = np.asarray(zb, np.float64)
+
+    def potential(x_, y_, z_):
+        x, y, z, J = _sks_map(x_, y_, z_, a)
+        A = _wald_potential(x, y, z, M, a, B0)
+        return [sum(J[p][i] * A[p] for p in range(3)) for i in range(3)]
+    dA = _cstep(potential, xb, yb, zb)
+    U = np.zeros((9,) + xb.shape)
     U[3] = dA[1][2] - dA[2][1]
     U[4] = dA[2][0] - dA[0][2]
     U[5] = dA[0][1] - dA[1][0]

@@ -179,3 +179,43 @@ def test_shell_exact_wald_error_matches_table(N):
         t += h
     err = S.l2_error(U[3:6], Uex[3:6])
     assert abs(err / err_paper - 1.0) < 0.01, err
+
+
+def test_spherical_kerr_schild_wald_field_matches_appendix():
+    """Wald's field pulled back to the Cartesian projection of spherical Kerr-Schild
+    coordinates (the curl of the pulled-back potential) against the closed form the
+    paper prints for B~ there (Appendix C, Eq. wald problem-cartesian projection in
+    spherical ks), and the background at a = 0 equal to the Cartesian one."""
+    rng = np.random.default_rng(0)
+    P = rng.normal(size=(3, 60))
+    P *= rng.uniform(1.5, 10.0, 60) / np.linalg.norm(P, axis=0)
+    x, y, z = P
+    assert np.abs(I.spherical_kerr_schild_background(x, y, z, 1.0, 0.0)
+                  - I.kerr_schild_background(x, y, z, 1.0, 0.0)).max() < 1e-14
+    for a in (0.5, 0.999):
+        M, B0 = 1.0, 1.3
+        U = I.wald_vacuum_spherical(x, y, z, M, a, B0)
+        r = np.sqrt(x * x + y * y + z * z)
+        D = r ** 4 + a * a * z * z
+        t1 = 1.0 / r ** 4 + 2.0 * M * r * (r * r - a * a) / D ** 2
+        t2 = (r * r - z * z) / (r ** 4 * D) - 4.0 * (r * r + z * z) / D ** 2
+        Bx = a * B0 * z * ((a * x - r * y) * t1 + a * M * r * x * t2)
+        By = a * B0 * z * ((r * x + a * y) * t1 + a * M * r * y * t2)
+        Bz = B0 * (1.0 + a * a * z * z / r ** 4
+                   + M * a * a / r ** 3 * (1.0 - z * z * (a * a + z * z) * (5.0 * r ** 4 + a * a * z * z) / D ** 2))
+        assert np.abs(U[3] - Bx).max() < 1e-13 and np.abs(U[4] - By).max() < 1e-13
+        assert np.abs(U[5] - Bz).max() < 1e-13
+        assert np.abs(U[[0, 1, 2, 6, 7, 8]]).max() == 0.0
+
+
+def test_shell_dt_matches_spinning_hole_runs():
+    """The time steps printed for the vacuum Wald (16 x 96) and magnetospheric Wald
+    (32 x 384) runs (Sec. IV B 2 and 3: a = 0.999 in spherical Kerr-Schild
+    coordinates, inner sphere at M, CFL 0.25; DG-P5 and the outer sphere at 125M,
+    which the second run does not restate), with the shell's reading of the step."""
+    for nr, na, dt_paper in ((16, 4, 1.97e-3), (32, 8, 9.86e-4)):
+        sh = S.Shell(5, nr, na, 1.0, 125.0, params=dict(cfl=0.25))
+        x = sh.x_dg
+        sh.geo = S.ph.Geometry(I.spherical_kerr_schild_background(x[0], x[1], x[2], 1.0, 0.999))
+        dt = sh.dt()
+        assert abs(dt - dt_paper) <= 0.5 * 10.0 ** (np.floor(np.log10(dt_paper)) - 2), (nr, dt)
