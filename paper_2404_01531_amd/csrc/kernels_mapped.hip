@@ -136,12 +136,42 @@ __device__ inline void face_part(const KArgs& a, int e, int id, int tt, const in
   }
 }
 
+// The three Cartesian flux components staged together (sF3 [j][v][node]): each
+// reference derivative reads the three at the same line point, three independent
+// accumulator chains per component.
+template <int N, int D>
+__device__ inline void ref_derivative3(const double* sF3, const double* sD, int p, int id, const double* ji,
+                                       double* dU) {
+  constexpr int n = N + 1, nn = n * n * n, str = D == 0 ? 1 : (D == 1 ? n : n * n);
+  const int p0 = p - id * str;
+  const double* Drow = sD + id * n;
+  const double c0 = ji[3 * D], c1 = ji[3 * D + 1], c2 = ji[3 * D + 2];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 2
+    for (int q = 0; q < n; ++q) {
+      const double dq = Drow[q];
+      const int o = v * nn + p0 + q * str;
+      s0 += dq * sF3[o];
+      s1 += dq * sF3[NV * nn + o];
+      s2 += dq * sF3[2 * NV * nn + o];
+    }
+    dU[v] -= c0 * s0 + c1 * s1 + c2 * s2;
+  }
+}
+
 template <int N, bool CURVED, int MODE>
 __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_mapped(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn, nf = n * n, TPB = Dm::tpb;
   constexpr int ITEMS = 6 * NV * nf, PER = (ITEMS + TPB - 1) / TPB;
-  __shared__ double sF[NV * nn];
+  // at N <= 5 the three flux components are staged together (three independent
+  // accumulator chains per component in the derivative: at one wave per SIMD the
+  // latency is hidden inside the wave; -10% at P5); above, one component at a time
+  // (the merged form spills at P7)
+  constexpr bool MERGE = N <= 5;
+  __shared__ double sF[MERGE ? 3 * NV * nn : NV * nn];
   __shared__ double sFil[n * n];  // filter
   __shared__ double sD[n * n];    // derivative matrix
   __shared__ double sX[ITEMS];    // neighbours' face nodes [f][c][t]
@@ -201,9 +231,26 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_mapped(KArgs a) {
   for (int c = 0; c < 3; ++c) J[c] = Jd[c] + Je[c];
   // volume term: every Cartesian flux component differentiated along every
   // reference direction, contracted with the inverse Jacobian at the node
-  volume_part<N, 0>(X, J, M, ji, sF, sD, act, p, i, j, k, dU);
-  volume_part<N, 1>(X, J, M, ji, sF, sD, act, p, i, j, k, dU);
-  volume_part<N, 2>(X, J, M, ji, sF, sD, act, p, i, j, k, dU);
+  if (MERGE) {
+    double F[NV];
+    flux_dir<0>(X, J[0], M, F);
+    if (act)
+      for (int v = 0; v < NV; ++v) sF[v * nn + p] = F[v];
+    flux_dir<1>(X, J[1], M, F);
+    if (act)
+      for (int v = 0; v < NV; ++v) sF[(NV + v) * nn + p] = F[v];
+    flux_dir<2>(X, J[2], M, F);
+    if (act)
+      for (int v = 0; v < NV; ++v) sF[(2 * NV + v) * nn + p] = F[v];
+    __syncthreads();
+    ref_derivative3<N, 0>(sF, sD, p, i, ji, dU);
+    ref_derivative3<N, 1>(sF, sD, p, j, ji, dU);
+    ref_derivative3<N, 2>(sF, sD, p, k, ji, dU);
+  } else {
+    volume_part<N, 0>(X, J, M, ji, sF, sD, act, p, i, j, k, dU);
+    volume_part<N, 1>(X, J, M, ji, sF, sD, act, p, i, j, k, dU);
+    volume_part<N, 2>(X, J, M, ji, sF, sD, act, p, i, j, k, dU);
+  }
   // face terms
   if (act) {
     face_part<N, 0>(a, e, i, j + n * k, sO, sX, X, J, M, ji, dU);
