@@ -149,7 +149,7 @@ __device__ inline void ref_derivative3(const double* sF3, const double* sD, int 
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll 2
+#pragma unroll
     for (int q = 0; q < n; ++q) {
       const double dq = Drow[q];
       const int o = v * nn + p0 + q * str;
@@ -161,15 +161,18 @@ __device__ inline void ref_derivative3(const double* sF3, const double* sD, int 
   }
 }
 
+// Workgroups per CU: two at N <= 5 in the substeps (256 VGPRs, two waves per SIMD,
+// 12 B of spills per lane, against one wave and 120 AGPRs unbounded: 1023 -> 620 us
+// per launch on the 32 x 384 P5 shell); the right-hand side entry point would spill
+// ~500 B there and keeps one.
 template <int N, bool CURVED, int MODE>
-__global__ __launch_bounds__(Dims<N>::tpb) void k_dg_mapped(KArgs a) {
+__global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1)) void k_dg_mapped(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn, nf = n * n, TPB = Dm::tpb;
   constexpr int ITEMS = 6 * NV * nf, PER = (ITEMS + TPB - 1) / TPB;
-  // at N <= 5 the three flux components are staged together (three independent
-  // accumulator chains per component in the derivative: at one wave per SIMD the
-  // latency is hidden inside the wave; -10% at P5); above, one component at a time
-  // (the merged form spills at P7)
+  // at N <= 5 the three flux components are staged together and differentiated in
+  // one fully unrolled loop (three independent accumulator chains per component);
+  // above, one component at a time (the merged form spills at P7)
   constexpr bool MERGE = N <= 5;
   __shared__ double sF[MERGE ? 3 * NV * nn : NV * nn];
   __shared__ double sFil[n * n];  // filter
