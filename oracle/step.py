@@ -159,6 +159,12 @@ def _identity(u):
     return u
 
 
+def _rhs_pair(dom):
+    """The DG and FD right-hand sides of the domain's grid: the Cartesian box's, or
+    those a grid of curved elements provides (attribute ``rhs_pair``)."""
+    return getattr(dom, "rhs_pair", (dg_rhs, fd_rhs))
+
+
 def _post(dom, C, geo, el, fd):
     """What follows the update of every substep: the optional algebraic clamp, then
     the rotating conductor's E, psi~, q~ inside its sphere (Sec. IV C: enforced at
@@ -247,9 +253,9 @@ def step(dom, st, dt, log=None, force=None, replay=None, replay_tol=1e-10, repla
                 continue
             geo = geo_take(_geos(dom)[r], el)
             if r == 0:
-                Lk = dg_rhs(dom, el, W[0], W[1], rep0, parts=1)
+                Lk = _rhs_pair(dom)[0](dom, el, W[0], W[1], rep0, parts=1)
             else:
-                Lk = fd_rhs(dom, el, W[1][:, el], W[0], W[1], rep0, parts=1)
+                Lk = _rhs_pair(dom)[1](dom, el, W[1][:, el], W[0], W[1], rep0, parts=1)
             Hs = {key: v[r][:, el] for key, v in H.items()}
             C, upd = _candidate(dom, k, Hs, X[r][:, el], Lk, geo, dt, _filter_fn(dom) if r == 0 else _identity)
             C = _post_dg(dom, C, geo, el) if r == 0 else _post_fd(dom, C, geo, el)
@@ -281,7 +287,7 @@ def step(dom, st, dt, log=None, force=None, replay=None, replay_tol=1e-10, repla
                 Xb = derived_stages(dom, Hs["Un"], geo, dt)[1]
             else:
                 Xb = Hs["U%d" % (k + 1)]
-            Lk = fd_rhs(dom, bad, with_current(dom, Xb, geo), W[0], W[1], rep0, parts=1)
+            Lk = _rhs_pair(dom)[1](dom, bad, with_current(dom, Xb, geo), W[0], W[1], rep0, parts=1)
             C, upd = _candidate(dom, k, Hs, Xb, Lk, geo, dt, _identity)
             cand[1][:, bad] = _post_fd(dom, C, geo, bad)
             for key, v in upd.items():

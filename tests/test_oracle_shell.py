@@ -219,3 +219,189 @@ def test_shell_dt_matches_spinning_hole_runs():
         sh.geo = S.ph.Geometry(I.spherical_kerr_schild_background(x[0], x[1], x[2], 1.0, 0.999))
         dt = sh.dt()
         assert abs(dt - dt_paper) <= 0.5 * 10.0 ** (np.floor(np.log10(dt_paper)) - 2), (nr, dt)
+
+
+# ------------------------------------------------------------ FD subcells on the shell
+
+from oracle import step as ST  # noqa: E402
+from oracle.domain import DG, FD  # noqa: E402
+from oracle.rhs import with_current  # noqa: E402
+
+
+def _curl_field(x, y, z):
+    B = (np.sin(0.3 * y) * z, np.cos(0.2 * z) + 0.1 * x * x, 0.05 * x * y * z)
+    bxy, bxz = 0.3 * np.cos(0.3 * y) * z, np.sin(0.3 * y)
+    byx, byz = 0.2 * x, -0.2 * np.sin(0.2 * z)
+    bzx, bzy = 0.05 * y * z, 0.05 * x * z
+    return B, (bzy - byz, bxz - bzx, byx - bxy), 0.05 * x * y
+
+
+def _cells_off(sh, wedge=True, sphere=True):
+    """Cells whose reconstruction stencils stay off the wedge faces / the spheres."""
+    m, na, nr = sh.m, sh.na, sh.nr
+    M = np.ones((sh.E, m, m, m), bool)
+    for e in range(sh.E):
+        ia, ib, ir = e % na, (e // na) % na, (e // (na * na)) % nr
+        if wedge:
+            M[e, :, :, :3] &= ia != 0
+            M[e, :, :, -3:] &= ia != na - 1
+            M[e, :, :3, :] &= ib != 0
+            M[e, :, -3:, :] &= ib != na - 1
+        if sphere:
+            M[e, :3] &= ir != 0
+            M[e, -3:] &= ir != nr - 1
+    return M
+
+
+def test_shell_fd_constant_state_is_stationary():
+    """A constant state in flat space (no current) is stationary on FD cells and across
+    DG/FD interfaces: F-hat is the same at every face, P and R keep constants."""
+    sh = S.Shell(3, 1, 2, 1.0, 3.0, bc_inner=S.SHELL_OUTFLOW, bc_outer=S.SHELL_OUTFLOW, params=dict(eta=0.0))
+    c = np.array([0.1, -0.2, 0.0, 0.7, 0.0, 1.1, 0.0, 0.0, 0.0])
+    Udg = np.broadcast_to(c[:, None, None, None, None], (9, sh.E, sh.n, sh.n, sh.n)).copy()
+    Ufd = np.broadcast_to(c[:, None, None, None, None], (9, sh.E, sh.m, sh.m, sh.m)).copy()
+    Wdg, Wfd = with_current(sh, Udg, sh.geo_dg), with_current(sh, Ufd, sh.geo_fd)
+    rep = np.zeros(sh.E, np.int64)
+    rep[::3] = FD
+    fd_e, dg_e = np.nonzero(rep == FD)[0], np.nonzero(rep == DG)[0]
+    assert np.abs(S.shell_fd_rhs(sh, fd_e, Wfd[:, fd_e], Wdg, Wfd, rep, parts=1)).max() < 1e-13
+    assert np.abs(S.shell_dg_rhs(sh, dg_e, Wdg, Wfd, rep, parts=1)).max() < 1e-13
+
+
+def test_shell_fd_divergence_converges_inside_wedges():
+    """Flat space, a smooth B on every FD cell: dE~/dt = curl B and dphi/dt = -div B at
+    second order (the flux difference of face point values) wherever the stencils stay
+    inside a wedge; at the wedge faces the neighbour's cells stand in for the ghost
+    cells of this element's grid (their positions differ by O(h) along the face), which
+    leaves an O(1) truncation error in the three cell layers there."""
+    errs, wedge = [], []
+    for nr, na in ((1, 2), (2, 4)):
+        sh = S.Shell(3, nr, na, 1.0, 3.0, bc_inner=S.SHELL_OUTFLOW, bc_outer=S.SHELL_OUTFLOW, params=dict(eta=0.0))
+        x, y, z = sh.points(fd=True)
+        B, curlB, divB = _curl_field(x, y, z)
+        U = np.zeros((9,) + x.shape)
+        U[3:6] = np.stack(B)
+        W = with_current(sh, U, sh.geo_fd)
+        rep = np.full(sh.E, FD)
+        r = S.shell_fd_rhs(sh, np.arange(sh.E), W, None, W, rep, parts=1)
+        err = np.maximum(np.abs(r[0:3] - np.stack(curlB)).max(axis=0), np.abs(r[7] + divB))
+        err = np.maximum(err, np.abs(r[[3, 4, 5, 6, 8]]).max(axis=0))
+        errs.append(err[_cells_off(sh)].max())
+        wedge.append(err[_cells_off(sh, wedge=False)].max())
+    # measured 1.76e-3, 6.27e-4 (then 2.14e-4 at 4 x 8: 2.8, 2.9 per halving); wedge
+    # faces 0.063, 0.080
+    assert errs[0] > 2.5 * errs[1] and errs[1] < 1e-3
+    assert max(wedge) < 0.1
+
+
+def test_shell_fd_ghost_cells_lie_beyond_the_face():
+    """Ghost layer l of face f is the neighbour's cell next to the shared face: inside a
+    wedge exactly the element's own map continued past the face; across wedge faces the
+    mirror image of the own layer-l cell through the matched face-cell centre, up to
+    the kink of the grid lines there (same distance from the face point within 25%,
+    on the other side)."""
+    sh = S.Shell(3, 2, 2, 1.0, 3.0, bc_inner=S.SHELL_OUTFLOW, bc_outer=S.SHELL_OUTFLOW)
+    m = sh.m
+    xf = sh.points(fd=True).reshape(3, sh.E, m ** 3)
+    cen = ops.fd_centres(3)
+    same, ratio, side = 0.0, 0.0, -1.0
+    for e in range(sh.E):
+        for f in range(6):
+            o = sh.nbr[e, f]
+            if o < 0:
+                continue
+            d, s = divmod(f, 2)
+            ref = [cen, cen, cen]
+            ref[d] = np.array([1.0 if s else -1.0])
+            R3, R2, R1 = np.meshgrid(ref[2], ref[1], ref[0], indexing="ij")
+            pf = sh.map_points(e, R1, R2, R3).reshape(3, m * m)
+            for l in range(3):
+                ext = [cen, cen, cen]
+                ext[d] = np.array([(1.0 if s else -1.0) * (1.0 + (2 * l + 1) / m)])
+                R3, R2, R1 = np.meshgrid(ext[2], ext[1], ext[0], indexing="ij")
+                want = sh.map_points(e, R1, R2, R3).reshape(3, m * m)
+                got = xf[:, o, sh.nbr_cell[e, f, l]]
+                if o // (sh.nr * sh.na ** 2) == e // (sh.nr * sh.na ** 2):
+                    same = max(same, np.sqrt(((got - want) ** 2).sum(axis=0)).max())
+                    continue
+                own = xf[:, e, sh.cell_index(f, l, np.arange(m * m))]
+                a, b = got - pf, own - pf
+                na_, nb_ = np.sqrt((a * a).sum(axis=0)), np.sqrt((b * b).sum(axis=0))
+                ratio = max(ratio, np.abs(na_ / nb_ - 1.0).max())
+                side = max(side, ((a * b).sum(axis=0) / (na_ * nb_)).max())
+    assert same < 1e-12 and ratio < 0.25 and side < 0.0
+
+
+def test_shell_dg_face_from_fd_neighbour_is_the_projected_state():
+    """R P = I: a DG element whose neighbour is on FD with P (x) P (x) P of the
+    neighbour's nodal (U, J~) sees the same face states as with the neighbour on DG."""
+    N = 4
+    geo_only = S.Shell(N, 1, 2, 1.2, 6.0)
+    x = geo_only.x_dg
+    bg = I.kerr_schild_background(x[0], x[1], x[2], 1.0, 0.0)
+    sh = S.Shell(N, 1, 2, 1.2, 6.0, bc_inner=S.SHELL_OUTFLOW, bc_outer=S.SHELL_NO_INCOMING_POYNTING, bg=bg,
+                 params=dict(eta=50.0))
+    rng = np.random.default_rng(5)
+    U = rng.normal(size=(9, sh.E, sh.n, sh.n, sh.n))
+    W = with_current(sh, U, sh.geo_dg)
+    want = S.shell_dg_rhs(sh, np.arange(sh.E), W, None, np.zeros(sh.E, np.int64), parts=1)
+    rep = np.zeros(sh.E, np.int64)
+    fd_e = np.array([1, 7, 14, 20])
+    rep[fd_e] = FD
+    Wfd = np.zeros((12, sh.E, sh.m, sh.m, sh.m))
+    Wfd[:, fd_e] = ops.apply_3d(ops.projection_matrix(N), W[:, fd_e])
+    dg_e = np.nonzero(rep == DG)[0]
+    got = S.shell_dg_rhs(sh, dg_e, W, Wfd, rep, parts=1)
+    scale = np.abs(want).max()
+    assert np.abs(got - want[:, dg_e]).max() < 1e-11 * scale
+
+
+def _flat_shell(N, hybrid):
+    # indicator thresholds that flag nothing on DG and switch nothing back (only the
+    # forced flags act)
+    return S.Shell(N, 1, 2, 1.0, 3.0, bc_inner=S.SHELL_OUTFLOW, bc_outer=S.SHELL_NO_INCOMING_POYNTING,
+                   params=dict(eta=0.0, hybrid=hybrid, tci_alpha=0.01, tci_alpha_fd=100.0))
+
+
+def _smooth_state(sh):
+    x, y, z = sh.x_dg
+    B, _, _ = _curl_field(x, y, z)
+    U = np.zeros((9,) + x.shape)
+    U[3:6] = np.stack(B)
+    U[0] = 0.05 * np.sin(0.4 * z)
+    U[6] = 0.01 * np.cos(0.3 * x)
+    return U
+
+
+def test_shell_hybrid_step_without_fd_is_the_dg_step():
+    sh = _flat_shell(3, ST.HYBRID_FORCED)
+    U = _smooth_state(sh)
+    dt = sh.dt()
+    got = ST.step(sh, ST.State(U, np.zeros((9, sh.E, sh.m, sh.m, sh.m)), np.zeros(sh.E, np.int64)), dt)
+    assert np.abs(got.dg - S.shell_step(sh, U, dt)).max() == 0.0
+
+
+def test_shell_substep1_rollback_equals_step_with_element_on_fd():
+    """Sec. III C 1 on the shell: flat space, no current, R P = I: an element flagged in
+    substep 1 (a host-forced flag) and redone on FD gives the forced partition's step
+    with that element on FD from P U^n."""
+    N, e = 3, 5
+    sh = _flat_shell(N, ST.HYBRID_ADAPTIVE)
+    U = _smooth_state(sh)
+    dt = sh.dt()
+    force = np.zeros((3, sh.E), bool)
+    force[0, e] = True
+    zero_fd = np.zeros((9, sh.E, sh.m, sh.m, sh.m))
+    got = ST.step(sh, ST.State(U, zero_fd, np.zeros(sh.E, np.int64)), dt, force=force)
+    assert got.rep[e] == FD
+    fsh = _flat_shell(N, ST.HYBRID_FORCED)
+    fd0 = zero_fd.copy()
+    fd0[:, e] = ops.apply_3d(ops.projection_matrix(N), U[:, e])
+    rep0 = np.zeros(sh.E, np.int64)
+    rep0[e] = FD
+    ref = ST.step(fsh, ST.State(U, fd0, rep0), dt)
+    keep = got.rep == ref.rep
+    assert keep.all()
+    dg = np.nonzero(ref.rep == DG)[0]
+    assert np.abs(got.dg[:, dg] - ref.dg[:, dg]).max() < 1e-13
+    assert np.abs(got.fd[:, e] - ref.fd[:, e]).max() < 1e-13
