@@ -94,6 +94,10 @@ KArgs make_args(grffe_domain* d) {
   a.ops = d->ops;
   a.jinv = d->jinv;
   a.fnode = d->fnode;
+  a.nface = d->nface;
+  a.fcell = d->fcell;
+  a.jinv_fd = d->jinv_fd;
+  a.nu_face = d->nu_face;
   a.dg = d->dg;
   a.fd = d->fd;
   a.rep0 = d->rep0;
@@ -344,6 +348,12 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   if (sg) {
     ALLOC(jinv, sizeof(double) * 9 * E * nn);
     ALLOC(fnode, sizeof(int32_t) * E * 6 * n * n);
+    if (!sg->jinv_fd.empty()) {
+      ALLOC(nface, sizeof(int32_t) * E * 6);
+      ALLOC(fcell, sizeof(int32_t) * E * 6 * m * m);
+      ALLOC(jinv_fd, sizeof(double) * 9 * E * mm);
+      ALLOC(nu_face, sizeof(double) * 9 * E * nf);
+    }
   }
   double* qdev = nullptr;
   if (d->curved) {
@@ -385,6 +395,14 @@ static int build_pool(const grffe_grid* const* grids, int count, const grffe_par
   if (sg) {
     CHK(hipMemcpyAsync(d->jinv, sg->jinv.data(), sizeof(double) * 9 * E * nn, hipMemcpyHostToDevice, st));
     CHK(hipMemcpyAsync(d->fnode, sg->fnode.data(), sizeof(int32_t) * E * 6 * n * n, hipMemcpyHostToDevice, st));
+    if (!sg->jinv_fd.empty()) {
+      CHK(hipMemcpyAsync(d->nface, sg->nface.data(), sizeof(int32_t) * E * 6, hipMemcpyHostToDevice, st));
+      CHK(hipMemcpyAsync(d->fcell, sg->fcell.data(), sizeof(int32_t) * E * 6 * m * m, hipMemcpyHostToDevice, st));
+      CHK(hipMemcpyAsync(d->jinv_fd, sg->jinv_fd.data(), sizeof(double) * 9 * E * mm, hipMemcpyHostToDevice, st));
+      CHK(hipMemcpyAsync(d->nu_face, sg->nu_face.data(), sizeof(double) * 9 * E * nf, hipMemcpyHostToDevice, st));
+      // the host tables are only needed for the copies, which must finish first
+      CHK(hipStreamSynchronize(st));
+    }
   }
   // time step per grid: lambda_max from the background (1 in flat space)
   for (auto& pt : d->parts) pt.lambda_max = 1.0;
@@ -487,11 +505,13 @@ extern "C" int grffe_init_shell(const grffe_shell* s, const grffe_params* p, con
   std::string err;
   if (int rc = shell_validate(s, err)) return fail(rc, err);
   if (!p) return fail(GRFFE_EINVAL, "params must not be NULL");
-  if (p->hybrid != GRFFE_HYBRID_DG_ONLY)
-    return fail(GRFFE_EUNSUPPORTED, "shells run every element on DG (hybrid = GRFFE_HYBRID_DG_ONLY)");
   if (p->precision != GRFFE_PRECISION_FP64) return fail(GRFFE_EUNSUPPORTED, "shells run in FP64");
+  if (p->hybrid != GRFFE_HYBRID_DG_ONLY && p->fd_order != 2)
+    return fail(GRFFE_EUNSUPPORTED, "FD subcells on curved elements are second order (fd_order = 2)");
   ShellGeom g;
   if (int rc = shell_geometry(*s, g, err)) return fail(rc, err);
+  if (p->hybrid != GRFFE_HYBRID_DG_ONLY)
+    if (int rc = shell_fd_geometry(*s, g, err)) return fail(rc, err);
   grffe_grid pseudo{};
   pseudo.n_elem[0] = g.E;
   pseudo.n_elem[1] = pseudo.n_elem[2] = 1;
@@ -522,6 +542,8 @@ extern "C" int grffe_set_boundary_state(grffe_domain* d, const double* state, vo
 extern "C" int grffe_set_boundary_field(grffe_domain* d, const double* ext_dg, const double* ext_fd, void* stream) {
   if (int rc = check_dom(d)) return rc;
   if (!ext_dg || (!ext_fd && !d->mapped)) return fail(GRFFE_EINVAL, "boundary field pointers must not be NULL");
+  if (!ext_fd && d->mapped && d->par.hybrid != GRFFE_HYBRID_DG_ONLY)
+    return fail(GRFFE_EINVAL, "a shell whose elements may go to FD needs the ghost-cell states (ext_fd)");
   if (d->parts.size() != 1) return fail(GRFFE_EUNSUPPORTED, "boundary fields are set on single domains");
   const size_t ndg = (size_t)NV * d->E * 6 * d->n * d->n;
   const size_t nfd = (size_t)NV * d->E * 6 * 3 * d->m * d->m;
@@ -716,10 +738,28 @@ static void run_substep(grffe_domain* d, KArgs& a, int mode, hipStream_t st) {
   // elements they flag, so it holds the FD elements at the start of every substep;
   // the FD update of substeps 1 and 2 writes the next substep's stage values
   a.sub = mode == MODE_RHS ? 3 : 0;
-  if (d->mapped) {
+  if (d->mapped && a.hybrid == GRFFE_HYBRID_DG_ONLY) {
     // every element on DG: the one fused kernel per substep
     TimedLaunch t(d, 1, st);
-    launch_dg_mapped(a, N, cv, mode, st);
+    launch_dg_mapped(a, N, cv, mode, false, st);
+    return;
+  }
+  if (d->mapped) {
+    // the box grid's sequence with the curved DG and FD kernels (FD second order)
+    if (mode == MODE_RHS || mode == MODE_SUB1) {
+      launch_begin_substep(a, mode != MODE_RHS, st);
+      TimedLaunch t(d, 4, st);
+      launch_fd_stage(a, N, cv, mode, st);
+    }
+    { TimedLaunch t(d, 5, st); launch_fd_trace(a, N, st); }
+    { TimedLaunch t(d, 1, st); launch_dg_mapped(a, N, cv, mode, true, st); }
+    { TimedLaunch t(d, 6, st); launch_dg_slab(a, N, cv, mode, st); }
+    if (mode != MODE_RHS && a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
+      TimedLaunch t(d, 7, st);
+      launch_project_troubled(a, N, cv, mode, st);
+    }
+    { TimedLaunch t(d, 2, st); launch_fd_flux_mapped(a, N, cv, st); }
+    { TimedLaunch t(d, 3, st); launch_fd_update(a, N, cv, mode, st); }
     return;
   }
   if (mode == MODE_RHS || mode == MODE_SUB1) {

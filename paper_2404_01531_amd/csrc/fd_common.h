@@ -71,4 +71,71 @@ __device__ inline CellSrc cell_source(const KArgs& a, const RowNbrs& nb, int e, 
   return cs;
 }
 
+// ---------------------------------------------------------------- WENO5-Z on point values
+// Candidates are the quadratic Lagrange interpolants of the point values at the
+// face; optimal weights (1, 10, 5)/16; Z weights alpha_k = d_k (1 + (tau5 /
+// (beta_k + eps))^2) with tau5 = |beta_0 - beta_2| (exponent q = 2).  With
+// b_k = beta_k + eps the normalised combination sum alpha_k q_k / sum alpha_k is
+// evaluated after multiplying numerator and denominator by b_0^2 b_1^2 b_2^2,
+// which leaves a single quotient.
+
+// n / d for the WENO normalisation, whose denominator is positive and in the normal
+// range (at least eps^6): the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r (2 - d r), then one multiplication (within about one
+// unit in the last place of the correctly rounded quotient).
+__device__ inline double div_weno(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return n * r;
+}
+
+// Both WENO5-Z reconstructions whose target cell is c, from the five point
+// values v[0..4] = cells c-2 .. c+2: `left` is the state on the left of face
+// c+1/2, `right` the state on the right of face c-1/2.  The two share the
+// smoothness indicators of the target cell (the mirrored reconstruction sees
+// beta_0 and beta_2 swapped) and tau5 = |beta_0 - beta_2|.  Z weights with
+// exponent 2, optimal weights (1, 10, 5)/16, candidates are quadratic Lagrange
+// interpolants of point values; the normalisation is done with one quotient
+// (div_weno) per state after multiplying by b_0^2 b_1^2 b_2^2, b_k = beta_k + eps.
+__device__ inline void weno5z_cell(const double* v, double eps, double& left, double& right) {
+  const double d0 = v[0] - 2.0 * v[1] + v[2], e0 = v[0] - 4.0 * v[1] + 3.0 * v[2];
+  const double d1 = v[1] - 2.0 * v[2] + v[3], e1 = v[1] - v[3];
+  const double d2 = v[2] - 2.0 * v[3] + v[4], e2 = 3.0 * v[2] - 4.0 * v[3] + v[4];
+  const double b0 = (13.0 / 12.0) * d0 * d0 + 0.25 * e0 * e0 + eps;
+  const double b1 = (13.0 / 12.0) * d1 * d1 + 0.25 * e1 * e1 + eps;
+  const double b2 = (13.0 / 12.0) * d2 * d2 + 0.25 * e2 * e2 + eps;
+  const double tau = fabs(b0 - b2);
+  const double t2 = tau * tau;
+  const double s0 = b0 * b0, s1 = b1 * b1, s2 = b2 * b2;
+  const double p01 = s0 * s1, p02 = s0 * s2, p12 = s1 * s2;
+  const double a0 = (s0 + t2), a1 = (s1 + t2), a2 = (s2 + t2);
+  // the common factors 1/16 of the weights (which cancels in the normalisation) and
+  // 1/8 of the candidates (applied once to the result) are left out
+  const double a1p = 10.0 * a1 * p02;
+  {
+    const double w0 = a0 * p12;
+    const double w2 = 5.0 * a2 * p01;
+    const double q0 = 3.0 * v[0] - 10.0 * v[1] + 15.0 * v[2];
+    const double q1 = -v[1] + 6.0 * v[2] + 3.0 * v[3];
+    const double q2 = 3.0 * v[2] + 6.0 * v[3] - v[4];
+    left = 0.125 * div_weno(w0 * q0 + a1p * q1 + w2 * q2, w0 + a1p + w2);
+  }
+  {
+    const double w0 = a2 * p01;
+    const double w2 = 5.0 * a0 * p12;
+    const double q0 = 3.0 * v[4] - 10.0 * v[3] + 15.0 * v[2];
+    const double q1 = -v[3] + 6.0 * v[2] + 3.0 * v[1];
+    const double q2 = 3.0 * v[2] + 6.0 * v[1] - v[0];
+    right = 0.125 * div_weno(w0 * q0 + a1p * q1 + w2 * q2, w0 + a1p + w2);
+  }
+}
+
+// Threads of an FD flux workgroup: at least one per (cell -1 .. m, pencil) of a row,
+// the flux phase's work items.
+template <int N>
+constexpr int flux_tpb() {
+  return (2 * N + 1) * (2 * N + 3) <= 256 ? 256 : 512;
+}
+
 }  // namespace grffe

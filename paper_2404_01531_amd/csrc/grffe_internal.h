@@ -39,10 +39,16 @@ struct ShellGeom {
   std::vector<int32_t> nbr;     // [E][6]
   std::vector<int32_t> fnode;   // [E][6][n^2]
   double dx_min = 0.0;
+  // FD subcells (built by shell_fd_geometry when elements may go to FD)
+  std::vector<int32_t> nface;   // [E][6] the neighbour's face towards e
+  std::vector<int32_t> fcell;   // [E][6][m^2] the neighbour's face cell at face cell t1 + m t2
+  std::vector<double> jinv_fd;  // [9][E][m^3] inverse Jacobian at the cell centres
+  std::vector<double> nu_face;  // [3][3][E][(m+1) m^2] unit covector grad xi^d / |grad xi^d| at the faces
 };
 int shell_validate(const grffe_shell* s, std::string& err);
 void shell_points(const grffe_shell& s, bool fd, std::vector<double>& xyz);
 int shell_geometry(const grffe_shell& s, ShellGeom& g, std::string& err);
+int shell_fd_geometry(const grffe_shell& s, ShellGeom& g, std::string& err);
 void gll_nodes_weights(int N, std::vector<double>& x, std::vector<double>& w);
 int default_tci_M(int N);
 
@@ -93,6 +99,10 @@ struct KArgs {
   // of the neighbour at the same point [E][6][n^2] (flat index in that element)
   const double* jinv;
   const int32_t* fnode;
+  const int32_t* nface;     // shells with FD subcells: [E][6]
+  const int32_t* fcell;     // [E][6][m^2]
+  const double* jinv_fd;    // [9][E][m^3]
+  const double* nu_face;    // [3][3][E][(m+1) m^2]
   // state
   Regs dg, fd;
   int32_t* rep0;           // representation at the start of the substep
@@ -154,6 +164,10 @@ struct grffe_domain {
   bool mapped = false;          // a shell of curved elements (grffe_init_shell)
   double* jinv = nullptr;       // [9][E][n^3] inverse Jacobian (shells)
   int32_t* fnode = nullptr;     // [E][6][n^2] neighbour node of each face node (shells)
+  int32_t* nface = nullptr;     // FD subcells on shells: the tables of ShellGeom
+  int32_t* fcell = nullptr;
+  double* jinv_fd = nullptr;
+  double* nu_face = nullptr;
   std::vector<int32_t> nbr_h;
   std::vector<uint8_t> live_h;
   int32_t* nbr = nullptr;
@@ -230,7 +244,8 @@ struct LaunchEvents {
 LaunchEvents& armed_launch_events();
 
 // launchers (kernels_mapped.hip)
-void launch_dg_mapped(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
+void launch_dg_mapped(const KArgs& a, int N, bool curved, int mode, bool hybrid, hipStream_t s);
+void launch_fd_flux_mapped(const KArgs& a, int N, bool curved, hipStream_t s);
 // launchers (kernels_dg.hip)
 void launch_dg_substep(const KArgs& a, int N, bool curved, int mode, hipStream_t s);
 void launch_dg_slab(const KArgs& a, int N, bool curved, int mode, hipStream_t s);

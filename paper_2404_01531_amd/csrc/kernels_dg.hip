@@ -377,7 +377,8 @@ __global__ __launch_bounds__(Dims<N>::tpb) void k_dg_slab(KArgs a) {
     const int o = a.fd_list[item / 6], fo = item % 6;
     const int e = a.nbr[o * 6 + fo];
     if (e < 0 || !a.live[e] || a.rep0[e] != 0) continue;  // the same for every thread of the block
-    const int f = 2 * (fo >> 1) + 1 - (fo & 1);          // e's face towards o
+    // e's face towards o (the opposite face on the box grid; a table on shells)
+    const int f = a.nface ? a.nface[o * 6 + fo] : 2 * (fo >> 1) + 1 - (fo & 1);
     __syncthreads();  // the previous item's tiles are no longer read
     if (t < nn) {
       Metric M;

@@ -16,6 +16,7 @@
 // stage input, sources, IMEX stage update, exponential filter on the explicit
 // update, pointwise implicit solve and the optional clamp -- is the box grid's.
 #include "common.h"
+#include "fd_common.h"
 
 namespace grffe {
 
@@ -100,9 +101,12 @@ __device__ inline void volume_part(const double* X, const double* J, const Metri
 
 // Lift of the face of reference direction D on which the node lies (index id along
 // D, face node tt), if any.
-template <int N, int D>
-__device__ inline void face_part(const KArgs& a, int e, int id, int tt, const int* sO, const double* sX,
-                                 const double* X, const double* J, const Metric& M, const double* ji, double* dU) {
+// NC components staged per face node (NV, or NW with the R-traces of FD neighbours);
+// sR[f] is the neighbour's representation (1: FD, whose staged J~ is taken as it is).
+template <int N, int D, int NC>
+__device__ inline void face_part(const KArgs& a, int e, int id, int tt, const int* sO, const int* sR,
+                                 const double* sX, const double* X, const double* J, const Metric& M,
+                                 const double* ji, double* dU) {
   constexpr int nf = (N + 1) * (N + 1);
   if (id != 0 && id != N) return;
   const int s = (id == N) ? 1 : 0;
@@ -111,10 +115,16 @@ __device__ inline void face_part(const KArgs& a, int e, int id, int tt, const in
   if (o == NBR_OUTFLOW) return;  // the exterior state is the interior one
   const double sg = s ? 1.0 : -1.0;
   const double m[3] = {sg * ji[3 * D], sg * ji[3 * D + 1], sg * ji[3 * D + 2]};
-  double Ux[NV];
+  double Ux[NV], Jx[3];
+  bool have_j = false;
   if (o >= 0) {
 #pragma unroll
-    for (int c = 0; c < NV; ++c) Ux[c] = sX[(f * NV + c) * nf + tt];
+    for (int c = 0; c < NV; ++c) Ux[c] = sX[(f * NC + c) * nf + tt];
+    if (NC > NV && sR[f] == 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Jx[c] = sX[(f * NC + NV + c) * nf + tt];
+      have_j = true;
+    }
   } else if (o < -1) {
     const size_t fs = (size_t)a.E * 6 * nf;
     const double* b = a.bfield_dg + ((size_t)e * 6 + f) * nf + tt;
@@ -123,8 +133,8 @@ __device__ inline void face_part(const KArgs& a, int e, int id, int tt, const in
   } else {
     boundary_state_normal(m, X, M, Ux);
   }
-  double Jx[3], Gi[NV], Gx[NV];
-  current_total(Ux, M, a.eta, Jx);
+  double Gi[NV], Gx[NV];
+  if (!have_j) current_total(Ux, M, a.eta, Jx);
   normal_flux(X, J, M, m, Gi);
   normal_flux(Ux, Jx, M, m, Gx);
   const double lam = M.alpha * sqrt(gi_norm2(M, m)) + fabs(M.beta[0] * m[0] + M.beta[1] * m[1] + M.beta[2] * m[2]);
@@ -165,11 +175,19 @@ __device__ inline void ref_derivative3(const double* sF3, const double* sD, int 
 // 12 B of spills per lane, against one wave and 120 AGPRs unbounded: 1023 -> 620 us
 // per launch on the 32 x 384 P5 shell); the right-hand side entry point would spill
 // ~500 B there and keeps one.
-template <int N, bool CURVED, int MODE>
+//
+// HYB: elements may be on FD (hybrid modes).  Only the DG elements run; an FD
+// neighbour's face state is its R-trace (U and J~, written by the trace kernel),
+// read at the face node matched to ours; with the adaptive mode the troubled-cell
+// indicator (Eq. persson tci) runs on the substep's result, and a troubled element
+// is appended to the substep's FD list and keeps its substep-start registers for the
+// FD redo, as on the box grid.
+template <int N, bool CURVED, int MODE, bool HYB>
 __global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1)) void k_dg_mapped(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn, nf = n * n, TPB = Dm::tpb;
-  constexpr int ITEMS = 6 * NV * nf, PER = (ITEMS + TPB - 1) / TPB;
+  constexpr int NC = HYB ? NW : NV;
+  constexpr int ITEMS = 6 * NC * nf, PER = (ITEMS + TPB - 1) / TPB;
   // at N <= 5 the three flux components are staged together and differentiated in
   // one fully unrolled loop (three independent accumulator chains per component);
   // above, one component at a time (the merged form spills at P7)
@@ -178,19 +196,27 @@ __global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1
   __shared__ double sFil[n * n];  // filter
   __shared__ double sD[n * n];    // derivative matrix
   __shared__ double sX[ITEMS];    // neighbours' face nodes [f][c][t]
-  __shared__ int sO[6];
+  __shared__ double sL[HYB ? n * n : 1];  // indicator operator
+  __shared__ double sred[2 * (TPB / 64)];
+  __shared__ int sO[6], sR[6], sFo[6];
   // XCD-aware order (as on the box grid): XCD x takes elements [x per, (x + 1) per)
   const int per = (a.E + 7) / 8;
   const int e = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (e >= a.E || !a.live[e]) return;
+  if (e >= a.E || !a.live[e] || (HYB && a.rep0[e] != 0)) return;
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int p = act ? t : 0;
   const int i = p % n, j = (p / n) % n, k = p / (n * n);
-  if (t < 6) sO[t] = a.nbr[e * 6 + t];
+  if (t < 6) {
+    const int o = a.nbr[e * 6 + t];
+    sO[t] = o;
+    sR[t] = (HYB && o >= 0) ? a.rep0[o] : 0;
+    sFo[t] = (HYB && o >= 0) ? a.nface[e * 6 + t] : 0;
+  }
   for (int q = t; q < n * n; q += TPB) {
     sD[q] = a.ops->D[q];
     sFil[q] = a.ops->F[q];
+    if (HYB) sL[q] = a.ops->L[q];
   }
   Metric M;
   load_metric<CURVED>(a.bg_dg, a.E, nn, e, p, M);
@@ -210,11 +236,19 @@ __global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1
       const int q = t + r * TPB;
       v[r] = 0.0;
       if (q >= ITEMS) continue;
-      const int f = q / (NV * nf), c = (q / nf) % NV, tt = q % nf;
+      const int f = q / (NC * nf), c = (q / nf) % NC, tt = q % nf;
       const int o = sO[f];
       if (o < 0) continue;
       const int pn = a.fnode[((size_t)e * 6 + f) * nf + tt];
-      v[r] = src[((size_t)c * a.E + o) * nn + pn];
+      if (HYB && sR[f] == 1) {
+        // the FD neighbour's R-trace on its face towards us, at the matched node
+        const int fo = sFo[f], dd = fo >> 1;
+        const int ci[3] = {pn % n, (pn / n) % n, pn / (n * n)};
+        const int u1 = ci[dd == 0 ? 1 : 0], u2 = ci[dd == 2 ? 1 : 2];
+        v[r] = a.trace[(((size_t)c * a.E + o) * 6 + fo) * nf + u1 + n * u2];
+      } else if (c < NV) {
+        v[r] = src[((size_t)c * a.E + o) * nn + pn];
+      }
     }
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
@@ -256,9 +290,9 @@ __global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1
   }
   // face terms
   if (act) {
-    face_part<N, 0>(a, e, i, j + n * k, sO, sX, X, J, M, ji, dU);
-    face_part<N, 1>(a, e, j, i + n * k, sO, sX, X, J, M, ji, dU);
-    face_part<N, 2>(a, e, k, i + n * j, sO, sX, X, J, M, ji, dU);
+    face_part<N, 0, NC>(a, e, i, j + n * k, sO, sR, sX, X, J, M, ji, dU);
+    face_part<N, 1, NC>(a, e, j, i + n * k, sO, sR, sX, X, J, M, ji, dU);
+    face_part<N, 2, NC>(a, e, k, i + n * j, sO, sR, sX, X, J, M, ji, dU);
   }
   const int idx[3] = {i, j, k};
   const int strideN[3] = {1, n, n * n};
@@ -294,9 +328,42 @@ __global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1
       }
     }
   }
+  if (!HYB && !act) return;
+  if (act) {
+    if (MODE != MODE_SUB3) implicit_solve(Y, M, a.eta, a.kpsi, a.kphi, dt_of(a, e) * IMEX_A);
+    if (a.ff_clamp) constraint_clamp(Y, M, a.ff_margin);
+  }
+  if (HYB && a.hybrid == GRFFE_HYBRID_ADAPTIVE) {
+    // troubled-cell indicator on u = |B~| (every thread of the block takes part)
+    const double u = act ? sqrt(dot3(M, Y + 3, Y + 3)) : 0.0;
+    double uh = u;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      __syncthreads();
+      if (act) sF[p] = uh;
+      __syncthreads();
+      const int id = idx[d];
+      const int p0 = p - id * strideN[d];
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < n; ++q) acc += sL[id * n + q] * sF[p0 + q * strideN[d]];
+      uh = acc;
+    }
+    double num = act ? (a.tci_mode == 1 ? uh * uh : (u - uh) * (u - uh)) : 0.0;
+    double den = act ? u * u : 0.0;
+    block_sum2<TPB>(num, den, sred);
+    const double ratio = den > 0.0 ? sqrt(num / den) : 0.0;
+    const bool bad = ratio > a.tci_thr || (a.force != nullptr && a.force[(size_t)(MODE - 1) * a.E + e] != 0);
+    if (t == 0) {
+      a.ratio[e] = ratio;
+      if (bad) {
+        a.troubled[e] = 1;
+        a.fd_list[atomicAdd(a.fd_count + a.sub, 1)] = e;  // redone on FD in this substep
+      }
+    }
+    if (bad) return;
+  }
   if (!act) return;
-  if (MODE != MODE_SUB3) implicit_solve(Y, M, a.eta, a.kpsi, a.kphi, dt_of(a, e) * IMEX_A);
-  if (a.ff_clamp) constraint_clamp(Y, M, a.ff_margin);
   if (MODE == MODE_SUB1) {
     store9(a.dg.X0, a.E, nn, e, p, Y);
     store9(a.dg.A, a.E, nn, e, p, Anew);
@@ -308,22 +375,247 @@ __global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1
   }
 }
 
+// ---------------------------------------------------------------- FD subcells on curved elements
+// Sec. III C 2, Eq. (fd time derivative), second order (F-hat = F*: the corrector is
+// Cartesian only).  Work items: (listed FD element, reference direction d, plane of
+// pencils t2), as on the box grid.  Per item: the m pencils along xi^d with three
+// ghost cells per side are staged in LDS (all twelve transported components: every
+// Cartesian flux needs its component of J~); ghost cells are the neighbour's cells
+// next to the shared face in its own orientation (face cell from the host's match
+// table), its P-slab if it is on DG, or on a sphere the outermost own cell (outflow),
+// its no-incoming-Poynting state along the outward covector, or the given exterior
+// state of the ghost cell (Dirichlet).  WENO5-Z gives both states at every face; the
+// Rusanov flux of each Cartesian component j, with the dissipation along the face's
+// unit covector nu, is
+//   F-hat^j = (F^j(U_L) + F^j(U_R)) / 2 - lambda(nu) (U_R - U_L) nu_j / 2;
+// each cell then takes -(m / 2) sum_j (d xi^d / d x^j) (F-hat^j_{+} - F-hat^j_{-})
+// with the inverse Jacobian at its centre, written as direction d's share of the
+// flux divergence for the update kernel.
 template <int N, bool CURVED>
-static void launch_dg_mapped_t(const KArgs& a, int mode, hipStream_t s) {
-  dim3 grid(8 * ((a.E + 7) / 8)), block(Dims<N>::tpb);
-  switch (mode) {
-    case MODE_RHS: launch_kernel(k_dg_mapped<N, CURVED, MODE_RHS>, grid, block, s, a); break;
-    case MODE_SUB1: launch_kernel(k_dg_mapped<N, CURVED, MODE_SUB1>, grid, block, s, a); break;
-    case MODE_SUB2: launch_kernel(k_dg_mapped<N, CURVED, MODE_SUB2>, grid, block, s, a); break;
-    default: launch_kernel(k_dg_mapped<N, CURVED, MODE_SUB3>, grid, block, s, a); break;
+__global__ __launch_bounds__(flux_tpb<N>()) void k_fd_flux_mapped(KArgs a) {
+  using Dm = Dims<N>;
+  constexpr int m = Dm::m, mm = Dm::mm, mf = m * m;
+  constexpr int nfc = (m + 1) * m * m;
+  constexpr int L = m, C = m + 6, F = m + 1;
+  constexpr int TPB = flux_tpb<N>();
+  constexpr int NA = (NW * C > 3 * NV * F) ? NW * C * L : 3 * NV * F * L;
+  __shared__ double sA[NA];          // staged cells [k][cell][pencil], then F-hat [j][v][face][pencil]
+  __shared__ double sLf[NW * F * L];  // [k][face][pencil]
+  __shared__ double sRf[NW * F * L];
+  __shared__ int sNb[8];
+  const int t = threadIdx.x;
+  const int items = a.fd_count[a.sub] * 3 * m;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int e = a.fd_list[item / (3 * m)];
+    const int d = (item / m) % 3;
+    const int t2 = item % m;
+    const int str[3] = {1, m, mf};
+    const int t1ax = (d == 0) ? 1 : 0, t2ax = (d == 2) ? 1 : 2;
+    __syncthreads();  // the previous item's tiles are no longer read
+    if (t < 2) {
+      const int f = 2 * d + t, o = a.nbr[e * 6 + f];
+      sNb[t] = o;
+      sNb[2 + t] = o >= 0 ? a.rep0[o] : -1;
+      sNb[4 + t] = o >= 0 ? a.nface[e * 6 + f] : -1;
+    }
+    __syncthreads();
+    // phase 1: cells -3 .. m+2 of every pencil
+    for (int q = t; q < L * C; q += TPB) {
+      int c, t1;
+      if (d == 0) {
+        c = q % C;
+        t1 = q / C;
+      } else {
+        t1 = q % L;
+        c = q / L;
+      }
+      const int cc = c - 3;
+      double W[NW];
+      if (cc >= 0 && cc < m) {
+        const int idx = cc * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) W[k] = a.w_fd[((size_t)k * a.E + e) * mm + idx];
+      } else {
+        const int s = cc >= m ? 1 : 0, f = 2 * d + s, l = s ? cc - m : -1 - cc;
+        const int o = sNb[s];
+        if (o >= 0) {
+          const int tp = a.fcell[((size_t)e * 6 + f) * mf + t1 + m * t2];
+          const int fo = sNb[4 + s];
+          if (sNb[2 + s] == 1) {
+            const int dd = fo >> 1, so = fo & 1;
+            int ci[3];
+            ci[dd] = so ? m - 1 - l : l;
+            ci[dd == 0 ? 1 : 0] = tp % m;
+            ci[dd == 2 ? 1 : 2] = tp / m;
+            const int idx = ci[0] + m * ci[1] + mf * ci[2];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) W[k] = a.w_fd[((size_t)k * a.E + o) * mm + idx];
+          } else {
+#pragma unroll
+            for (int k = 0; k < NW; ++k)
+              W[k] = a.slab[((size_t)k * a.E * 6 + (size_t)o * 6 + fo) * (3 * mf) + l * mf + tp];
+          }
+        } else {
+          // a sphere: from the outermost own cell of the pencil
+          const int ib = (s ? m - 1 : 0) * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
+#pragma unroll
+          for (int k = 0; k < NW; ++k) W[k] = a.w_fd[((size_t)k * a.E + e) * mm + ib];
+          if (o != NBR_OUTFLOW) {
+            Metric Mc;
+            load_metric<CURVED>(a.bg_fd, a.E, mm, e, ib, Mc);
+            double Ub[NV], J[3];
+            if (o == -1) {
+              const double sg = s ? 1.0 : -1.0;
+              double mv[3];
+#pragma unroll
+              for (int j = 0; j < 3; ++j) mv[j] = sg * a.jinv_fd[((size_t)(3 * d + j) * a.E + e) * mm + ib];
+              boundary_state_normal(mv, W, Mc, Ub);
+            } else {
+              const size_t fs = (size_t)a.E * 6 * 3 * mf;
+              const double* b = a.bfield_fd + (((size_t)e * 6 + f) * 3 + l) * mf + t1 + m * t2;
+#pragma unroll
+              for (int k = 0; k < NV; ++k) Ub[k] = b[k * fs];
+            }
+            current_total(Ub, Mc, a.eta, J);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) W[k] = Ub[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) W[NV + k] = J[k];
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NW; ++k) sA[(k * C + c) * L + t1] = W[k];
+    }
+    __syncthreads();
+    // phase 2: WENO5-Z of every component; target cells c = -1 .. m give the left
+    // state of face c+1 and the right state of face c
+    const double eps = a.weno_eps;
+    for (int q = t; q < NW * L * (m + 2); q += TPB) {
+      const int t1 = q % L;
+      const int c = (q / L) % (m + 2) - 1;
+      const int k = q / (L * (m + 2));
+      const double* v = sA + (k * C + c + 1) * L + t1;
+      double vl[5];
+#pragma unroll
+      for (int z = 0; z < 5; ++z) vl[z] = v[z * L];
+      double lft, rgt;
+      weno5z_cell(vl, eps, lft, rgt);
+      if (c < m) sLf[(k * F + c + 1) * L + t1] = lft;
+      if (c >= 0) sRf[(k * F + c) * L + t1] = rgt;
+    }
+    __syncthreads();
+    // phase 3: F-hat^j at every face of every pencil, into sA
+    for (int q = t; q < L * F; q += TPB) {
+      int f3, t13;
+      if (d == 0) {
+        f3 = q % F;
+        t13 = q / F;
+      } else {
+        t13 = q % L;
+        f3 = q / L;
+      }
+      int tix;
+      if (d == 0) tix = f3 + (m + 1) * (t13 + m * t2);
+      else if (d == 1) tix = t13 + m * (f3 + (m + 1) * t2);
+      else tix = t13 + m * (t2 + m * f3);
+      double WL[NW], WR[NW];
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        WL[k] = sLf[(k * F + f3) * L + t13];
+        WR[k] = sRf[(k * F + f3) * L + t13];
+      }
+      Metric Mf;
+      load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nfc, a.E, nfc, e, tix, Mf);
+      double nu[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) nu[j] = a.nu_face[((size_t)(3 * d + j) * a.E + e) * nfc + tix];
+      const double lam =
+          Mf.alpha * sqrt(gi_norm2(Mf, nu)) + fabs(Mf.beta[0] * nu[0] + Mf.beta[1] * nu[1] + Mf.beta[2] * nu[2]);
+      double FL[NV], FR[NV];
+      flux_dir<0>(WL, WL[NV], Mf, FL);
+      flux_dir<0>(WR, WR[NV], Mf, FR);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        sA[((0 * NV + v) * F + f3) * L + t13] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * nu[0] * (WR[v] - WL[v]);
+      flux_dir<1>(WL, WL[NV + 1], Mf, FL);
+      flux_dir<1>(WR, WR[NV + 1], Mf, FR);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        sA[((1 * NV + v) * F + f3) * L + t13] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * nu[1] * (WR[v] - WL[v]);
+      flux_dir<2>(WL, WL[NV + 2], Mf, FL);
+      flux_dir<2>(WR, WR[NV + 2], Mf, FR);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        sA[((2 * NV + v) * F + f3) * L + t13] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * nu[2] * (WR[v] - WL[v]);
+    }
+    __syncthreads();
+    // phase 4: -(m/2) sum_j (d xi^d / d x^j) (F-hat^j_{c+1/2} - F-hat^j_{c-1/2}) per cell
+    const double sc = 0.5 * (double)m;
+    for (int q = t; q < L * m; q += TPB) {
+      int c, t1;
+      if (d == 0) {
+        c = q % m;
+        t1 = q / m;
+      } else {
+        t1 = q % L;
+        c = q / L;
+      }
+      const int cell = c * str[d] + t1 * str[t1ax] + t2 * str[t2ax];
+      double ji[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) ji[j] = a.jinv_fd[((size_t)(3 * d + j) * a.E + e) * mm + cell];
+      double* out = a.fhat + ((size_t)d * NV * a.E + e) * mm + cell;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const double* fh = sA + ((j * NV + v) * F + c) * L + t1;
+          acc += ji[j] * (fh[L] - fh[0]);
+        }
+        out[(size_t)v * a.E * mm] = -sc * acc;
+      }
+    }
   }
 }
 
-void launch_dg_mapped(const KArgs& a, int N, bool curved, int mode, hipStream_t s) {
+template <int N, bool CURVED>
+static void launch_fd_flux_mapped_t(const KArgs& a, hipStream_t s) {
+  constexpr int m = Dims<N>::m;
+  const size_t cap = (size_t)a.E * 3 * m;
+  const dim3 grid((unsigned)(cap < 2048 ? (cap > 0 ? cap : 1) : 2048)), block(flux_tpb<N>());
+  launch_kernel(k_fd_flux_mapped<N, CURVED>, grid, block, s, a);
+}
+
+void launch_fd_flux_mapped(const KArgs& a, int N, bool curved, hipStream_t s) {
   if (curved) {
-    GRFFE_SWITCH_N((launch_dg_mapped_t<NN, true>(a, mode, s)))
+    GRFFE_SWITCH_N((launch_fd_flux_mapped_t<NN, true>(a, s)))
   } else {
-    GRFFE_SWITCH_N((launch_dg_mapped_t<NN, false>(a, mode, s)))
+    GRFFE_SWITCH_N((launch_fd_flux_mapped_t<NN, false>(a, s)))
+  }
+}
+
+template <int N, bool CURVED, bool HYB>
+static void launch_dg_mapped_t(const KArgs& a, int mode, hipStream_t s) {
+  dim3 grid(8 * ((a.E + 7) / 8)), block(Dims<N>::tpb);
+  switch (mode) {
+    case MODE_RHS: launch_kernel(k_dg_mapped<N, CURVED, MODE_RHS, HYB>, grid, block, s, a); break;
+    case MODE_SUB1: launch_kernel(k_dg_mapped<N, CURVED, MODE_SUB1, HYB>, grid, block, s, a); break;
+    case MODE_SUB2: launch_kernel(k_dg_mapped<N, CURVED, MODE_SUB2, HYB>, grid, block, s, a); break;
+    default: launch_kernel(k_dg_mapped<N, CURVED, MODE_SUB3, HYB>, grid, block, s, a); break;
+  }
+}
+
+void launch_dg_mapped(const KArgs& a, int N, bool curved, int mode, bool hybrid, hipStream_t s) {
+  if (curved && hybrid) {
+    GRFFE_SWITCH_N((launch_dg_mapped_t<NN, true, true>(a, mode, s)))
+  } else if (curved) {
+    GRFFE_SWITCH_N((launch_dg_mapped_t<NN, true, false>(a, mode, s)))
+  } else if (hybrid) {
+    GRFFE_SWITCH_N((launch_dg_mapped_t<NN, false, true>(a, mode, s)))
+  } else {
+    GRFFE_SWITCH_N((launch_dg_mapped_t<NN, false, false>(a, mode, s)))
   }
 }
 

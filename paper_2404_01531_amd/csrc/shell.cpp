@@ -67,6 +67,19 @@ void map_point(const grffe_shell& s, int e, double x1, double x2, double x3, dou
   }
 }
 
+// inv[3 i + a] = d xi^i / d x^a from J[3 a + i] = d x^a / d xi^i, by cofactors;
+// returns det J.
+double invert(const double* J, double* inv) {
+  const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+  const double c10 = J[2] * J[7] - J[1] * J[8], c11 = J[0] * J[8] - J[2] * J[6], c12 = J[1] * J[6] - J[0] * J[7];
+  const double c20 = J[1] * J[5] - J[2] * J[4], c21 = J[2] * J[3] - J[0] * J[5], c22 = J[0] * J[4] - J[1] * J[3];
+  const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+  const double cof[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) inv[3 * i + a] = cof[3 * a + i] / det;
+  return det;
+}
+
 // Flat node index of face node t = t1 + n t2 of face f = 2 d + s.
 int face_node(int n, int f, int t) {
   const int d = f >> 1, lay = (f & 1) ? n - 1 : 0, t1 = t % n, t2 = t / n;
@@ -124,15 +137,9 @@ int shell_geometry(const grffe_shell& s, ShellGeom& g, std::string& err) {
       double P[3], J[9];
       map_point(s, e, x[p % n], x[(p / n) % n], x[p / (n * n)], P, J);
       for (int q = 0; q < 3; ++q) pos[((size_t)e * nn + p) * 3 + q] = P[q];
-      // inverse of J by cofactors: inv[i][a] = cof[a][i] / det
-      const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
-      const double c10 = J[2] * J[7] - J[1] * J[8], c11 = J[0] * J[8] - J[2] * J[6], c12 = J[1] * J[6] - J[0] * J[7];
-      const double c20 = J[1] * J[5] - J[2] * J[4], c21 = J[2] * J[3] - J[0] * J[5], c22 = J[0] * J[4] - J[1] * J[3];
-      const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
-      if (!(det > 0.0)) return err = "degenerate element map", GRFFE_EINVAL;
-      const double cof[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
-      for (int i = 0; i < 3; ++i)
-        for (int a = 0; a < 3; ++a) g.jinv[((size_t)(3 * i + a) * E + e) * nn + p] = cof[3 * a + i] / det;
+      double inv[9];
+      if (!(invert(J, inv) > 0.0)) return err = "degenerate element map", GRFFE_EINVAL;
+      for (int q = 0; q < 9; ++q) g.jinv[((size_t)q * E + e) * nn + p] = inv[q];
     }
   // smallest distance between neighbouring nodes along a reference line
   g.dx_min = 1e300;
@@ -221,6 +228,103 @@ int shell_geometry(const grffe_shell& s, ShellGeom& g, std::string& err) {
         g.fnode[((size_t)e * 6 + f) * nf + t] = face_node(n, fo, hit);
       }
     }
+  return GRFFE_OK;
+}
+
+// FD subcells: the inverse Jacobian at the cell centres, the unit covectors at the
+// faces, and for every face between elements the neighbour's face and, per face
+// cell, its face cell at the same point.  The orientation between two matched faces
+// is one of the eight symmetries of the square; it is read off the DG face-node
+// match (three corners), applied to the face cells, and every face-cell pair is
+// checked by position.  Needs shell_geometry's tables.
+int shell_fd_geometry(const grffe_shell& s, ShellGeom& g, std::string& err) {
+  const int N = s.degree, n = N + 1, nf = n * n, m = 2 * N + 1, mm = m * m * m, mf = m * m;
+  const int E = g.E;
+  std::vector<double> cen(m), fac(m + 1);
+  for (int c = 0; c < m; ++c) cen[c] = -1.0 + (2.0 * c + 1.0) / m;
+  for (int c = 0; c <= m; ++c) fac[c] = -1.0 + 2.0 * c / m;
+  g.jinv_fd.assign(9 * (size_t)E * mm, 0.0);
+  const size_t nfc = (size_t)(m + 1) * mf;
+  g.nu_face.assign(9 * (size_t)E * nfc, 0.0);
+  for (int e = 0; e < E; ++e) {
+    for (int p = 0; p < mm; ++p) {
+      double P[3], J[9], inv[9];
+      map_point(s, e, cen[p % m], cen[(p / m) % m], cen[p / mf], P, J);
+      if (!(invert(J, inv) > 0.0)) return err = "degenerate element map", GRFFE_EINVAL;
+      for (int q = 0; q < 9; ++q) g.jinv_fd[((size_t)q * E + e) * mm + p] = inv[q];
+    }
+    for (int d = 0; d < 3; ++d) {
+      const int lx = d == 0 ? m + 1 : m, ly = d == 1 ? m + 1 : m;
+      for (size_t q = 0; q < nfc; ++q) {
+        const int cx = (int)(q % lx), cy = (int)((q / lx) % ly), cz = (int)(q / ((size_t)lx * ly));
+        double P[3], J[9], inv[9];
+        map_point(s, e, d == 0 ? fac[cx] : cen[cx], d == 1 ? fac[cy] : cen[cy], d == 2 ? fac[cz] : cen[cz], P, J);
+        invert(J, inv);
+        const double* r = inv + 3 * d;
+        const double len = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        for (int j = 0; j < 3; ++j) g.nu_face[(((size_t)d * 3 + j) * E + e) * nfc + q] = r[j] / len;
+      }
+    }
+  }
+  // tangential coordinates (u1, u2) of a node or cell on face f (lower axis first)
+  auto tang = [](int k, int f, int p, int& u1, int& u2) {
+    const int d = f >> 1, c[3] = {p % k, (p / k) % k, p / (k * k)};
+    const int lo = d == 0 ? 1 : 0, hi = d == 2 ? 1 : 2;
+    u1 = c[lo];
+    u2 = c[hi];
+  };
+  // point of face cell (c1, c2) on face f of element e
+  auto face_cell_point = [&](int e, int f, int c1, int c2, double* P) {
+    const int d = f >> 1;
+    double r[3];
+    const int lo = d == 0 ? 1 : 0, hi = d == 2 ? 1 : 2;
+    r[d] = (f & 1) ? 1.0 : -1.0;
+    r[lo] = cen[c1];
+    r[hi] = cen[c2];
+    map_point(s, e, r[0], r[1], r[2], P, nullptr);
+  };
+  const double tol = 1e-9 * s.r_out;
+  g.nface.assign((size_t)E * 6, -1);
+  g.fcell.assign((size_t)E * 6 * mf, -1);
+  for (int e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f) {
+      const int o = g.nbr[(size_t)e * 6 + f];
+      if (o < 0) continue;
+      const int32_t* fn = &g.fnode[((size_t)e * 6 + f) * nf];
+      // the neighbour's face: the one on which its matched nodes lie
+      int fo = -1;
+      for (int cand = 0; cand < 6 && fo < 0; ++cand) {
+        const int dd = cand >> 1, lay = (cand & 1) ? N : 0;
+        bool all = true;
+        for (int t = 0; t < nf && all; ++t) {
+          const int pn = fn[t], c[3] = {pn % n, (pn / n) % n, pn / (n * n)};
+          all = c[dd] == lay;
+        }
+        if (all && g.nbr[(size_t)o * 6 + cand] == e) fo = cand;
+      }
+      if (fo < 0) return err = "no neighbour face holds the matched nodes", GRFFE_EINVAL;
+      g.nface[(size_t)e * 6 + f] = fo;
+      int u00[2], u10[2], u01[2];
+      tang(n, fo, fn[0], u00[0], u00[1]);
+      tang(n, fo, fn[N], u10[0], u10[1]);
+      tang(n, fo, fn[N * n], u01[0], u01[1]);
+      const int a1[2] = {(u10[0] - u00[0]) / N, (u10[1] - u00[1]) / N};
+      const int a2[2] = {(u01[0] - u00[0]) / N, (u01[1] - u00[1]) / N};
+      const int b[2] = {u00[0] / N * (m - 1), u00[1] / N * (m - 1)};
+      for (int c2 = 0; c2 < m; ++c2)
+        for (int c1 = 0; c1 < m; ++c1) {
+          const int v1 = b[0] + a1[0] * c1 + a2[0] * c2, v2 = b[1] + a1[1] * c1 + a2[1] * c2;
+          if (v1 < 0 || v1 >= m || v2 < 0 || v2 >= m) return err = "face orientation out of range", GRFFE_EINVAL;
+          double Pe[3], Po[3];
+          face_cell_point(e, f, c1, c2, Pe);
+          face_cell_point(o, fo, v1, v2, Po);
+          const double d2 = (Pe[0] - Po[0]) * (Pe[0] - Po[0]) + (Pe[1] - Po[1]) * (Pe[1] - Po[1]) +
+                            (Pe[2] - Po[2]) * (Pe[2] - Po[2]);
+          if (!(d2 <= tol * tol)) return err = "face cells of neighbours do not coincide", GRFFE_EINVAL;
+          g.fcell[((size_t)e * 6 + f) * mf + c1 + m * c2] = v1 + m * v2;
+        }
+    }
+  (void)tang;
   return GRFFE_OK;
 }
 

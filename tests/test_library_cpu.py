@@ -153,7 +153,8 @@ def test_shell_points_match_oracle(N, nr, na):
 
 
 @pytest.mark.parametrize("shell, over, code", [
-    (dict(), dict(hybrid=1), -5), (dict(), dict(precision=1), -5), (dict(degree=2), dict(), -1),
+    (dict(), dict(hybrid=1, fd_order=4), -5), (dict(), dict(hybrid=2, fd_order=4), -5),
+    (dict(), dict(precision=1), -5), (dict(degree=2), dict(), -1),
     (dict(r_in=3.0), dict(), -1), (dict(r_in=0.0), dict(), -1), (dict(n_angular=0), dict(), -1),
     (dict(bc_inner=0), dict(), -1), (dict(bc_outer=7), dict(), -1),
 ])
