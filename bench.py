@@ -65,7 +65,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--only", choices=("sheet", "batch", "adjoint_adaptive", "shell_wald", "vacuum_wald", "shell_scale"),
+    ap.add_argument("--only", choices=("sheet", "batch", "adjoint_adaptive", "shell_wald", "vacuum_wald", "shell_scale",
+                                        "shell_hybrid"),
                     default=None,
                     help="run one secondary workload alone and print its record (profiling runs)")
     ap.add_argument("--shell-degrees", default="5,7,9",
@@ -1131,6 +1132,70 @@ def run_shell_scale(steps=20, warmup=5, degree=5, n_radial=32, n_angular=8, spin
             "achieved_GBps": achieved, "frac_hbm": achieved / 8000.0}
 
 
+def run_shell_hybrid_scale(steps=20, warmup=3, degree=5, n_radial=32, n_angular=8, spin=0.7):
+    """The hybrid step on curved elements at the same full-chip size: the grid of
+    run_shell_scale with FD subcells (second order) on a band of elements about the
+    equator near the hole -- where the magnetospheric-Wald run of Sec. IV B 3 keeps
+    its troubled elements, the equatorial current sheet -- held there (forced
+    partition).  Timed over `steps` steps; the curved FD flux kernel's mean launch and
+    its FP64 rate (WENO5-Z of twelve components at 78 flop each side of every face,
+    1872 flop per face: a lower bound of its arithmetic) against the vector peak."""
+    import numpy as np
+    import torch
+
+    from paper_2404_01531_amd import grffe
+    from paper_2404_01531_amd import inputs as I
+    N, n, m = degree, degree + 1, 2 * degree + 1
+    r_in, r_out = 1.2, 125.0
+    x = grffe.shell_points(N, n_radial, n_angular, r_in, r_out)
+    E = x.shape[1]
+    bg = I.kerr_schild_background(x[0], x[1], x[2], 1.0, spin)
+    p = grffe.default_params(eta=1e5, cfl=0.25, hybrid=grffe.HYBRID_FORCED, fd_order=2)
+    dom = grffe.Domain.shell(N, n_radial, n_angular, r_in, r_out, grffe.BC_OUTFLOW, grffe.BC_NO_INCOMING_POYNTING,
+                             params=p, bg=torch.from_numpy(np.ascontiguousarray(bg)).cuda())
+    del bg
+    c = x.mean(axis=2)
+    rc = np.sqrt((c * c).sum(axis=0))
+    band = (rc < 4.0) & (np.abs(c[2]) < 0.2 * rc)
+    fd_e = np.nonzero(band)[0]
+    u = torch.from_numpy(np.ascontiguousarray(I.wald_vacuum(x[0], x[1], x[2], 1.0, spin))).cuda()
+    el = torch.from_numpy(fd_e.astype(np.int32)).cuda()
+    fd = torch.zeros((9, E, m ** 3), dtype=torch.float64, device="cuda")
+    fd[:, el.long()] = dom.project_dg_to_fd(u, el)
+    rep = torch.zeros(E, dtype=torch.int32, device="cuda")
+    rep[el.long()] = 1
+    u[:, el.long()] = 0.0
+    dom.set_state(u, fd, rep)
+    del u, fd
+    dom.step(warmup)
+    fams = {k: grffe.KERNEL_FAMILIES[k] for k in ("dg_substep", "fd_flux", "fd_update", "fd_stage", "fd_trace",
+                                                   "dg_slab")}
+    dom.timing_enable(*fams.values(), period=TIMING_PERIOD)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dom.step(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    times = {}
+    for k, f in fams.items():
+        tot, launches = dom.timing_read(f)
+        times[k] = {"mean_us": tot * 1e3 / max(launches, 1), "launches": launches}
+    dom.timing_enable()
+    dg, fdd, r = dom.get_state()
+    ok = bool(torch.isfinite(dg).all().item() and torch.isfinite(fdd).all().item())
+    n_fd = int(r.sum().item())
+    dom.close()
+    faces = n_fd * 3 * (m + 1) * m * m
+    flux_us = times["fd_flux"]["mean_us"]
+    tflops = faces * 1872.0 / (flux_us * 1e-6) / 1e12
+    updates = 3 * ((E - n_fd) * n ** 3 + n_fd * m ** 3)
+    return {"workload": f"shell {r_in}M..{r_out}M, {n_radial}x{6 * n_angular ** 2} P{N} elements, Kerr-Schild "
+                        f"a={spin} (Cartesian KS), vacuum Wald data, eta 1e5, {n_fd} elements on FD (second "
+                        "order) in an equatorial band r < 4M, forced partition", "elements": E, "fd_elements": n_fd,
+            "ms_per_step": ms, "point_updates_per_s": updates / (ms * 1e-3), "finite": ok, "kernels": times,
+            "fd_flux_weno_tflops": tflops, "fd_flux_frac_fp64_valu_weno_only": tflops / 78.6}
+
+
 def run_adjoint_frozen(steps=40, every=20):
     """The benchmark's current sheet, 8^3 P5 elements, with the start-up DG/FD
     partition held fixed (forced mode): forward steps, one-step adjoints through DG
@@ -1246,6 +1311,9 @@ def main():
     if args.only == "shell_scale":
         print(json.dumps(run_shell_scale(args.steps, args.warmup)))
         return
+    if args.only == "shell_hybrid":
+        print(json.dumps(run_shell_hybrid_scale(args.steps, args.warmup)))
+        return
     if args.only == "vacuum_wald":
         print(json.dumps(run_vacuum_wald(tuple(float(v) for v in args.spins.split(",")), coords=args.coords)))
         return
@@ -1310,7 +1378,8 @@ def main():
                 ("adjoint_poynting_kerr_schild_8^3_adaptive", lambda: run_adjoint_adaptive()),
                 ("adjoint_sheet_8^3_frozen_partition", lambda: run_adjoint_frozen()),
                 ("exact_wald_shell_table", lambda: run_shell_wald()),
-                ("shell_32x384_p5", lambda: run_shell_scale(args.extra_steps, 3))]
+                ("shell_32x384_p5", lambda: run_shell_scale(args.extra_steps, 3)),
+                ("shell_32x384_p5_hybrid", lambda: run_shell_hybrid_scale(args.extra_steps, 3))]
         if args.extras == "all":
             jobs += [("vacuum_wald_king_flux", lambda: run_vacuum_wald()),
                      ("accuracy_smooth_fast_wave_4^3", lambda: run_accuracy_smooth_wave(20)),

@@ -163,12 +163,32 @@ int grffe_shell_points(const grffe_shell* shell, int32_t fd, double* xyz);
  * Rusanov flux G*(m) of speed alpha sqrt(gamma^{jk} m_j m_k) + |beta^j m_j|.  The
  * time step is Eq. (spectre DG CFL condition) with (dx)_min the smallest distance
  * between neighbouring nodes along a reference line and lambda_max the largest
- * alpha + |beta|_gamma.  Shells run every element on DG in FP64: params->hybrid
- * must be GRFFE_HYBRID_DG_ONLY and params->precision GRFFE_PRECISION_FP64
- * (GRFFE_EUNSUPPORTED otherwise); the rotating conductor, the adjoint, batches and
- * the matrix-core contraction are not available on shells.  grffe_init_from_fd
- * (reconstruction of FD data), grffe_set_state / _get_state, grffe_rhs (rep all
- * 0), grffe_step, grffe_get_dt and grffe_check_finite work as on the box grid. */
+ * alpha + |beta|_gamma.
+ *
+ * FD subcells on curved elements (Sec. III C 2, Eq. (fd time derivative)) with
+ * params->hybrid GRFFE_HYBRID_FORCED or _ADAPTIVE: second order only (the
+ * fourth-order corrector is Cartesian only), so params->fd_order must be 2.  Along
+ * each reference direction xi^d the cell values of U and of the three components of
+ * J~ are reconstructed with WENO5-Z; at a face, F-hat^j = (F^j(U_L) + F^j(U_R)) / 2
+ * - lambda(nu) (U_R - U_L) nu_j / 2 for each Cartesian component j, with nu the
+ * face's unit covector grad xi^d / |grad xi^d|; a cell adds
+ * -(m / 2) sum_j (d xi^d / d x^j) (F-hat^j_{+} - F-hat^j_{-}) with the inverse
+ * Jacobian at its centre.  Ghost cells are the neighbour's cells next to the shared
+ * face in its own orientation (matched by position; across wedge faces their
+ * positions differ from this element's grid continued past the face by up to about
+ * one cell per layer), its P-projection if it is on DG, or on a sphere the outermost
+ * own cell (outflow), its no-incoming-Poynting state, or ext_fd of
+ * grffe_set_boundary_field (Dirichlet).  A DG face next to an FD element takes the
+ * neighbour's R-trace at the matched node.  The indicator, rollbacks, switches back
+ * and grffe_force_flags are those of the box grid.  These modes keep the host tables
+ * of the cells and faces (about 150 doubles per cell) on the device.
+ *
+ * Shells run in FP64: params->precision must be GRFFE_PRECISION_FP64
+ * (GRFFE_EUNSUPPORTED otherwise, and for FD modes with fd_order 4); the rotating
+ * conductor, the adjoint, batches and the matrix-core contraction are not available
+ * on shells.  grffe_init_from_fd, grffe_set_state / _get_state, grffe_rhs,
+ * grffe_step, grffe_step_logged, grffe_get_dt, grffe_get_counts and
+ * grffe_check_finite work as on the box grid. */
 int grffe_init_shell(const grffe_shell* shell, const grffe_params* params, const double* bg, void* stream,
                      grffe_domain** out);
 
@@ -195,9 +215,11 @@ int grffe_set_boundary_state(grffe_domain* dom, const double* state, void* strea
  * node's indices along the face's two tangential axes in increasing axis order;
  * ext_fd (device, [9][E][6][3][m^2]) the state at every FD ghost cell, layer
  * l = 0, 1, 2 counted outwards from face f, cell t1 + m t2.  Entries of faces that
- * are not Dirichlet faces are not read.  On a shell ext_fd may be NULL (every
- * element is DG) and this is the only way to set a Dirichlet sphere's states
- * (grffe_set_boundary_state returns GRFFE_EUNSUPPORTED there).  Both arrays are
+ * are not Dirichlet faces are not read.  On a shell ext_fd may be NULL when every
+ * element stays DG (GRFFE_HYBRID_DG_ONLY; GRFFE_EINVAL in the FD modes), and this is
+ * the only way to set a Dirichlet sphere's states (grffe_set_boundary_state returns
+ * GRFFE_EUNSUPPORTED there); there the ghost cells of layer l lie on the element's
+ * map continued past the sphere, at reference coordinate +-(1 + (2 l + 1) / m).  Both arrays are
  * copied into the domain (allocated at the first call) on `stream`; a later grffe_set_boundary_state
  * does not undo this.  Returns GRFFE_EINVAL for NULL pointers, GRFFE_ENOMEM,
  * GRFFE_EHIP. */

@@ -101,12 +101,14 @@ __device__ inline void volume_part(const double* X, const double* J, const Metri
 
 // Lift of the face of reference direction D on which the node lies (index id along
 // D, face node tt), if any.
-// NC components staged per face node (NV, or NW with the R-traces of FD neighbours);
-// sR[f] is the neighbour's representation (1: FD, whose staged J~ is taken as it is).
-template <int N, int D, int NC>
+// sR[f] is the neighbour's representation: an FD neighbour's J~ is its R-trace's
+// (read here from the trace buffer at the matched node of its face sFo[f]), not that
+// of the traced state.
+template <int N, int D, bool HYB>
 __device__ inline void face_part(const KArgs& a, int e, int id, int tt, const int* sO, const int* sR,
-                                 const double* sX, const double* X, const double* J, const Metric& M,
-                                 const double* ji, double* dU) {
+                                 const int* sFo, const double* sX, const double* X, const double* J,
+                                 const Metric& M, const double* ji, double* dU) {
+  constexpr int NC = NV;
   constexpr int nf = (N + 1) * (N + 1);
   if (id != 0 && id != N) return;
   const int s = (id == N) ? 1 : 0;
@@ -120,9 +122,14 @@ __device__ inline void face_part(const KArgs& a, int e, int id, int tt, const in
   if (o >= 0) {
 #pragma unroll
     for (int c = 0; c < NV; ++c) Ux[c] = sX[(f * NC + c) * nf + tt];
-    if (NC > NV && sR[f] == 1) {
+    if (HYB && sR[f] == 1) {
+      constexpr int n = N + 1;
+      const int pn = a.fnode[((size_t)e * 6 + f) * nf + tt];
+      const int fo = sFo[f], dd = fo >> 1;
+      const int ci[3] = {pn % n, (pn / n) % n, pn / (n * n)};
+      const int u = ci[dd == 0 ? 1 : 0] + n * ci[dd == 2 ? 1 : 2];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Jx[c] = sX[(f * NC + NV + c) * nf + tt];
+      for (int c = 0; c < 3; ++c) Jx[c] = a.trace[(((size_t)(NV + c) * a.E + o) * 6 + fo) * nf + u];
       have_j = true;
     }
   } else if (o < -1) {
@@ -178,7 +185,8 @@ __device__ inline void ref_derivative3(const double* sF3, const double* sD, int 
 //
 // HYB: elements may be on FD (hybrid modes).  Only the DG elements run; an FD
 // neighbour's face state is its R-trace (U and J~, written by the trace kernel),
-// read at the face node matched to ours; with the adaptive mode the troubled-cell
+// read at the face node matched to ours (U staged with the DG neighbours' states, J~
+// read where the face term needs it); with the adaptive mode the troubled-cell
 // indicator (Eq. persson tci) runs on the substep's result, and a troubled element
 // is appended to the substep's FD list and keeps its substep-start registers for the
 // FD redo, as on the box grid.
@@ -186,7 +194,7 @@ template <int N, bool CURVED, int MODE, bool HYB>
 __global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1)) void k_dg_mapped(KArgs a) {
   using Dm = Dims<N>;
   constexpr int n = Dm::n, nn = Dm::nn, nf = n * n, TPB = Dm::tpb;
-  constexpr int NC = HYB ? NW : NV;
+  constexpr int NC = NV;
   constexpr int ITEMS = 6 * NC * nf, PER = (ITEMS + TPB - 1) / TPB;
   // at N <= 5 the three flux components are staged together and differentiated in
   // one fully unrolled loop (three independent accumulator chains per component);
@@ -246,7 +254,7 @@ __global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1
         const int ci[3] = {pn % n, (pn / n) % n, pn / (n * n)};
         const int u1 = ci[dd == 0 ? 1 : 0], u2 = ci[dd == 2 ? 1 : 2];
         v[r] = a.trace[(((size_t)c * a.E + o) * 6 + fo) * nf + u1 + n * u2];
-      } else if (c < NV) {
+      } else {
         v[r] = src[((size_t)c * a.E + o) * nn + pn];
       }
     }
@@ -290,9 +298,9 @@ __global__ __launch_bounds__(Dims<N>::tpb, ((N <= 5 && MODE != MODE_RHS) ? 2 : 1
   }
   // face terms
   if (act) {
-    face_part<N, 0, NC>(a, e, i, j + n * k, sO, sR, sX, X, J, M, ji, dU);
-    face_part<N, 1, NC>(a, e, j, i + n * k, sO, sR, sX, X, J, M, ji, dU);
-    face_part<N, 2, NC>(a, e, k, i + n * j, sO, sR, sX, X, J, M, ji, dU);
+    face_part<N, 0, HYB>(a, e, i, j + n * k, sO, sR, sFo, sX, X, J, M, ji, dU);
+    face_part<N, 1, HYB>(a, e, j, i + n * k, sO, sR, sFo, sX, X, J, M, ji, dU);
+    face_part<N, 2, HYB>(a, e, k, i + n * j, sO, sR, sFo, sX, X, J, M, ji, dU);
   }
   const int idx[3] = {i, j, k};
   const int strideN[3] = {1, n, n * n};
