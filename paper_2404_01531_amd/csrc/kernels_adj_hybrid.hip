@@ -198,13 +198,18 @@ __global__ __launch_bounds__(256) void k_adj_project_un(KArgs a, const int32_t* 
   }
 }
 
-// dst = src on the live elements whose representation in rep is `want`.
+// dst = src on the live elements whose representation in rep is `want`: one
+// (component, element) row of P values per workgroup pass, rows of other elements
+// skipped whole (32-bit row arithmetic; the rows are contiguous in the [9][E][P]
+// layout).
 __global__ __launch_bounds__(256) void k_copy_rep(const KArgs a, const int32_t* rep, int want, int P,
                                                   const double* src, double* dst) {
-  const size_t total = (size_t)NV * a.E * P;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
-    const int e = (int)((i / P) % a.E);
-    if (a.live[e] && rep[e] == want) dst[i] = src[i];
+  const int rows = NV * a.E;
+  for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int e = r % a.E;
+    if (!a.live[e] || rep[e] != want) continue;  // the same for every thread of the block
+    const size_t base = (size_t)r * P;
+    for (int p = threadIdx.x; p < P; p += 256) dst[base + p] = src[base + p];
   }
 }
 
@@ -232,7 +237,8 @@ void launch_adj_project_un(const KArgs& a, int N, const int32_t* rep0, const int
 
 void launch_copy_rep(const KArgs& a, const int32_t* rep, int want, int P, const double* src, double* dst,
                      hipStream_t s) {
-  launch_kernel(k_copy_rep, dim3(1024), dim3(256), s, a, rep, want, P, src, dst);
+  const int rows = NV * a.E;
+  launch_kernel(k_copy_rep, dim3(rows < 4096 ? rows : 4096), dim3(256), s, a, rep, want, P, src, dst);
 }
 
 }  // namespace grffe
