@@ -52,12 +52,12 @@ TIMING_PERIOD = 10
 
 # HBM bytes per FD element per launch of k_fd_flux (FP64, flat): rocprofv3 FETCH_SIZE
 # and WRITE_SIZE runs on the current-sheet 8^3 workload (KiB per dispatch, 12
-# dispatches with 128 FD elements: fetch 14813.7, write 36200.4), each scaled by what
+# dispatches with 128 FD elements: fetch 14809.1, write 36205.0), each scaled by what
 # the same counter reads for a plain 512 MiB device copy (fetch x 2.0, write x 1.0).
 # Valid for the kernel source whose hash is FD_FLUX_TRAFFIC_SRC; reported as null for
 # any other source.
-FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 14813.7 + 1.0 * 36200.4) * 1024.0 / 128.0
-FD_FLUX_TRAFFIC_SRC = "c8e82d359ecf8627"
+FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 14809.1 + 1.0 * 36205.0) * 1024.0 / 128.0
+FD_FLUX_TRAFFIC_SRC = "242102cb6ed8addd"
 
 
 def parse():
@@ -1396,16 +1396,16 @@ def main():
 
 # HBM bytes per DG node per launch of the curved k_dg_substep (FP64) on the Kerr-Schild
 # 16^3 workload: rocprofv3 FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, 14
-# dispatches per substep with 4064-4088 DG elements; fetch 166910 / 216561 / 215282,
-# write 123751 / 123758 / 61892 for substeps 1 / 2 / 3), each scaled by what the same
+# dispatches per substep with 4064-4088 DG elements; fetch 166814 / 216046 / 215350,
+# write 123750 / 123760 / 61891 for substeps 1 / 2 / 3), each scaled by what the same
 # counter reads for a plain 512 MiB device copy (fetch x 2.0, write x 1.0), averaged
-# over the substeps and divided by 4072 x 216 nodes: 584.8 B against the 496 B of
-# algorithmic traffic.  Most of the excess (~89 B per node) is the neighbours' face
+# over the substeps and divided by 4072 x 216 nodes: 584.4 B against the 496 B of
+# algorithmic traffic.  Most of the excess (~88 B per node) is the neighbours' face
 # states the surface term reads (6 x 36 x 9 FP64 values per element, 72 B per node),
 # which the algorithmic figure leaves out.  Valid for the kernel source whose hash is
 # DG_TRAFFIC_SRC; reported as null for any other source.
-DG_TRAFFIC_PER_NODE = 584.8
-DG_TRAFFIC_SRC = "7b0001afb65883d0"
+DG_TRAFFIC_PER_NODE = 584.4
+DG_TRAFFIC_SRC = "60fc3d796b18ff1e"
 
 
 def dg_substep_traffic(rec):
