@@ -99,35 +99,39 @@ __device__ inline double div_weno(double n, double d) {
 // interpolants of point values; the normalisation is done with one quotient
 // (div_weno) per state after multiplying by b_0^2 b_1^2 b_2^2, b_k = beta_k + eps.
 __device__ inline void weno5z_cell(const double* v, double eps, double& left, double& right) {
+  // b_k here is 4 (beta_k + eps), and the candidates below carry their 1/8: both
+  // are power-of-two scalings, exact in floating point (the first cancels in the
+  // normalised combination), which save the separate scaling multiplications of
+  // the indicators and of the two states
   const double d0 = v[0] - 2.0 * v[1] + v[2], e0 = v[0] - 4.0 * v[1] + 3.0 * v[2];
   const double d1 = v[1] - 2.0 * v[2] + v[3], e1 = v[1] - v[3];
   const double d2 = v[2] - 2.0 * v[3] + v[4], e2 = 3.0 * v[2] - 4.0 * v[3] + v[4];
-  const double b0 = (13.0 / 12.0) * d0 * d0 + 0.25 * e0 * e0 + eps;
-  const double b1 = (13.0 / 12.0) * d1 * d1 + 0.25 * e1 * e1 + eps;
-  const double b2 = (13.0 / 12.0) * d2 * d2 + 0.25 * e2 * e2 + eps;
+  const double eps4 = 4.0 * eps;
+  const double b0 = (13.0 / 3.0) * d0 * d0 + e0 * e0 + eps4;
+  const double b1 = (13.0 / 3.0) * d1 * d1 + e1 * e1 + eps4;
+  const double b2 = (13.0 / 3.0) * d2 * d2 + e2 * e2 + eps4;
   const double tau = fabs(b0 - b2);
   const double t2 = tau * tau;
   const double s0 = b0 * b0, s1 = b1 * b1, s2 = b2 * b2;
   const double p01 = s0 * s1, p02 = s0 * s2, p12 = s1 * s2;
   const double a0 = (s0 + t2), a1 = (s1 + t2), a2 = (s2 + t2);
-  // the common factors 1/16 of the weights (which cancels in the normalisation) and
-  // 1/8 of the candidates (applied once to the result) are left out
+  // the common factor 1/16 of the weights cancels in the normalisation and is left out
   const double a1p = 10.0 * a1 * p02;
   {
     const double w0 = a0 * p12;
     const double w2 = 5.0 * a2 * p01;
-    const double q0 = 3.0 * v[0] - 10.0 * v[1] + 15.0 * v[2];
-    const double q1 = -v[1] + 6.0 * v[2] + 3.0 * v[3];
-    const double q2 = 3.0 * v[2] + 6.0 * v[3] - v[4];
-    left = 0.125 * div_weno(w0 * q0 + a1p * q1 + w2 * q2, w0 + a1p + w2);
+    const double q0 = 0.375 * v[0] - 1.25 * v[1] + 1.875 * v[2];
+    const double q1 = -0.125 * v[1] + 0.75 * v[2] + 0.375 * v[3];
+    const double q2 = 0.375 * v[2] + 0.75 * v[3] - 0.125 * v[4];
+    left = div_weno(w0 * q0 + a1p * q1 + w2 * q2, w0 + a1p + w2);
   }
   {
     const double w0 = a2 * p01;
     const double w2 = 5.0 * a0 * p12;
-    const double q0 = 3.0 * v[4] - 10.0 * v[3] + 15.0 * v[2];
-    const double q1 = -v[3] + 6.0 * v[2] + 3.0 * v[1];
-    const double q2 = 3.0 * v[2] + 6.0 * v[1] - v[0];
-    right = 0.125 * div_weno(w0 * q0 + a1p * q1 + w2 * q2, w0 + a1p + w2);
+    const double q0 = 0.375 * v[4] - 1.25 * v[3] + 1.875 * v[2];
+    const double q1 = -0.125 * v[3] + 0.75 * v[2] + 0.375 * v[1];
+    const double q2 = 0.375 * v[2] + 0.75 * v[1] - 0.125 * v[0];
+    right = div_weno(w0 * q0 + a1p * q1 + w2 * q2, w0 + a1p + w2);
   }
 }
 

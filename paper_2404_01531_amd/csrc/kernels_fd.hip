@@ -252,10 +252,15 @@ __global__ __launch_bounds__(flux_tpb<N>(), (flux_min_blocks<N, CURVED>())) void
   constexpr int F = m + 1;  // faces per pencil
   constexpr int NR = NV + 1;  // reconstructed components: U and J~^d
   constexpr int TPB = flux_tpb<N>();
+  constexpr int FP = m + 2;  // state slots per pencil: one per target cell -1 .. m
   static_assert(L % 2 == 1, "odd pencil count keeps the LDS tiles free of bank conflicts");
-  __shared__ double sW[NR * C * L];   // [k][extended cell][pencil]
-  __shared__ double sLf[NR * F * L];  // [k][face][pencil]
-  __shared__ double sRf[NR * F * L];
+  __shared__ double sW[NR * C * L];    // [k][extended cell][pencil]
+  // reconstructed states by target cell c (slot c + 1): the left state of face c + 1
+  // in sLf (face f at slot f), the right state of face c in sRf (face f at slot
+  // f + 1); the unused slots (left m + 1, right 0) take the two edge targets' other
+  // state, so that the reconstruction loop stores without conditions
+  __shared__ double sLf[NR * FP * L];  // [k][slot][pencil]
+  __shared__ double sRf[NR * FP * L];
   __shared__ double sM[CURVED ? NBGF * L * (m + 2) : 1];
   const int t = threadIdx.x;
   // work items: (listed FD element, direction, row of pencils).  Workgroups are
@@ -331,19 +336,20 @@ __global__ __launch_bounds__(flux_tpb<N>(), (flux_min_blocks<N, CURVED>())) void
   // phase 2: WENO5-Z of every component at every face of every pencil, and the
   // cell-centred fluxes of cells -1 .. m used by the corrector
   const double eps = a.weno_eps;
-  // target cells c = -1 .. m: left state of face c+1 and right state of face c
-  for (int q = t_weno; q < NR * L * (m + 2); q += TPB) {
-    const int t1 = q % L;
-    const int c = (q / L) % (m + 2) - 1;
-    const int k = q / (L * (m + 2));
-    const double* v = sW + (k * C + c + 1) * L + t1;  // cells c-2 .. c+2 (extended index c+1 .. c+5)
+  // target cells c = -1 .. m: left state of face c+1 and right state of face c.  The
+  // work index q = (k FP + c + 1) L + t1 is also the states' slot index, and the
+  // target's cells c-2 .. c+2 start at extended index c+1 of component k's tile:
+  // only the component is divided out
+  for (int q = t_weno; q < NR * L * FP; q += TPB) {
+    const int k = q / (L * FP);
+    const double* v = sW + q + k * (C - FP) * L;  // cells c-2 .. c+2
     double vl[5];
 #pragma unroll
     for (int z = 0; z < 5; ++z) vl[z] = v[z * L];
     double lft, rgt;
     weno5z_cell(vl, eps, lft, rgt);
-    if (c < m) sLf[(k * F + c + 1) * L + t1] = lft;
-    if (c >= 0) sRf[(k * F + c) * L + t1] = rgt;
+    sLf[q] = lft;
+    sRf[q] = rgt;
   }
   __syncthreads();
   // phase 3a: cell-centred fluxes of cells -1 .. m of every pencil (the corrector's
@@ -400,8 +406,8 @@ __global__ __launch_bounds__(flux_tpb<N>(), (flux_min_blocks<N, CURVED>())) void
     R WL[NR], WR[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      WL[k] = (R)sLf[(k * F + f3) * L + t13];
-      WR[k] = (R)sRf[(k * F + f3) * L + t13];
+      WL[k] = (R)sLf[(k * FP + f3) * L + t13];
+      WR[k] = (R)sRf[(k * FP + f3 + 1) * L + t13];
     }
     Metric Mf;
     load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nf, a.E, nf, e, tix, Mf);
