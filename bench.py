@@ -52,12 +52,12 @@ TIMING_PERIOD = 10
 
 # HBM bytes per FD element per launch of k_fd_flux (FP64, flat): rocprofv3 FETCH_SIZE
 # and WRITE_SIZE runs on the current-sheet 8^3 workload (KiB per dispatch, 12
-# dispatches with 128 FD elements: fetch 14809.1, write 36205.0), each scaled by what
+# dispatches with 128 FD elements: fetch 14825.0, write 36232.7), each scaled by what
 # the same counter reads for a plain 512 MiB device copy (fetch x 2.0, write x 1.0).
 # Valid for the kernel source whose hash is FD_FLUX_TRAFFIC_SRC; reported as null for
 # any other source.
-FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 14809.1 + 1.0 * 36205.0) * 1024.0 / 128.0
-FD_FLUX_TRAFFIC_SRC = "242102cb6ed8addd"
+FD_FLUX_TRAFFIC_PER_FD_ELEMENT = (2.0 * 14825.0 + 1.0 * 36232.7) * 1024.0 / 128.0
+FD_FLUX_TRAFFIC_SRC = "b4e40c45594c6e0f"
 
 
 def parse():
@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--contraction", choices=("valu", "mfma"), default="valu",
                     help="DG derivative contraction engine of the black-hole domains (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample-steps", type=int, default=12)
     ap.add_argument("--extras", choices=("core", "all", "none"), default="core",
                     help="also measure the batch, sheet, full-length black-hole and adjoint workloads (core), "
                          "and the paper's accuracy experiments (all); nested in the JSON line")
@@ -1405,7 +1405,7 @@ def main():
 # which the algorithmic figure leaves out.  Valid for the kernel source whose hash is
 # DG_TRAFFIC_SRC; reported as null for any other source.
 DG_TRAFFIC_PER_NODE = 584.4
-DG_TRAFFIC_SRC = "60fc3d796b18ff1e"
+DG_TRAFFIC_SRC = "b14332371343b5da"
 
 
 def dg_substep_traffic(rec):
@@ -1417,12 +1417,18 @@ def dg_substep_traffic(rec):
     return DG_TRAFFIC_PER_NODE * n_dg * 216
 
 
+# The library headers each counted kernel source includes (directly or through
+# another header).
+KERNEL_HEADERS = {"kernels_dg.hip": ("common.h", "physics.h", "grffe_internal.h"),
+                  "kernels_fd.hip": ("fd_common.h", "common.h", "physics.h", "grffe_internal.h")}
+
+
 def kernel_source_hash(main="kernels_fd.hip"):
     """SHA-256 (first 16 hex digits) of a kernel source and the headers it includes."""
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(ROOT, "paper_2404_01531_amd", "csrc")
-    for f in (main, "fd_common.h", "common.h", "physics.h", "grffe_internal.h"):
+    for f in (main,) + KERNEL_HEADERS[main]:
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -408,8 +408,12 @@ __global__ __launch_bounds__(flux_tpb<N>()) void k_fd_flux_mapped(KArgs a) {
   constexpr int TPB = flux_tpb<N>();
   constexpr int NA = (NW * C > 3 * NV * F) ? NW * C * L : 3 * NV * F * L;
   __shared__ double sA[NA];          // staged cells [k][cell][pencil], then F-hat [j][v][face][pencil]
-  __shared__ double sLf[NW * F * L];  // [k][face][pencil]
-  __shared__ double sRf[NW * F * L];
+  // reconstructed states by target cell c = -1 .. m (slot c + 1): the left state of
+  // face c + 1 in sLf (face f at slot f), the right state of face c in sRf (face f at
+  // slot f + 1); the unused slots take the edge targets' other state
+  constexpr int FP = m + 2;
+  __shared__ double sLf[NW * FP * L];  // [k][slot][pencil]
+  __shared__ double sRf[NW * FP * L];
   __shared__ int sNb[8];
   const int t = threadIdx.x;
   const int items = a.fd_count[a.sub] * 3 * m;
@@ -499,18 +503,18 @@ __global__ __launch_bounds__(flux_tpb<N>()) void k_fd_flux_mapped(KArgs a) {
     // phase 2: WENO5-Z of every component; target cells c = -1 .. m give the left
     // state of face c+1 and the right state of face c
     const double eps = a.weno_eps;
-    for (int q = t; q < NW * L * (m + 2); q += TPB) {
-      const int t1 = q % L;
-      const int c = (q / L) % (m + 2) - 1;
-      const int k = q / (L * (m + 2));
-      const double* v = sA + (k * C + c + 1) * L + t1;
+    // (the work index q = (k FP + c + 1) L + t1 is also the states' slot index, and
+    // the target's cells c-2 .. c+2 start at extended index c+1 of component k's tile)
+    for (int q = t; q < NW * L * FP; q += TPB) {
+      const int k = q / (L * FP);
+      const double* v = sA + q + k * (C - FP) * L;
       double vl[5];
 #pragma unroll
       for (int z = 0; z < 5; ++z) vl[z] = v[z * L];
       double lft, rgt;
       weno5z_cell(vl, eps, lft, rgt);
-      if (c < m) sLf[(k * F + c + 1) * L + t1] = lft;
-      if (c >= 0) sRf[(k * F + c) * L + t1] = rgt;
+      sLf[q] = lft;
+      sRf[q] = rgt;
     }
     __syncthreads();
     // phase 3: F-hat^j at every face of every pencil, into sA
@@ -530,8 +534,8 @@ __global__ __launch_bounds__(flux_tpb<N>()) void k_fd_flux_mapped(KArgs a) {
       double WL[NW], WR[NW];
 #pragma unroll
       for (int k = 0; k < NW; ++k) {
-        WL[k] = sLf[(k * F + f3) * L + t13];
-        WR[k] = sRf[(k * F + f3) * L + t13];
+        WL[k] = sLf[(k * FP + f3) * L + t13];
+        WR[k] = sRf[(k * FP + f3 + 1) * L + t13];
       }
       Metric Mf;
       load_metric<CURVED>(a.bg_face + (size_t)d * NBGF * a.E * nfc, a.E, nfc, e, tix, Mf);
